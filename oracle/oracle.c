@@ -1,0 +1,263 @@
+/*
+ * FP64 CPU oracle for the diffuse-scattering hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  The product path
+ * (the HIP library and its binding) never links, loads or calls it, and the two
+ * share no code.
+ *
+ * Everything here is the plain definition, written out as a direct summation
+ * over atoms in double precision, parallelised over output points with OpenMP:
+ *
+ *   orc_sf_nuclear   F_m(G) = sum_{R,mu} b_mu delta e^{2 pi i g.(R + r_mu + u)}
+ *                    (Sec. II, Eq. sf; Sec. III.A, Eq. total_sf), with g = G/n in
+ *                    reciprocal-lattice units (Eq. G_def).  exact mode evaluates
+ *                    e^{i G.u} directly; order-N mode replaces it by its Taylor
+ *                    polynomial sum_{k<=N} (i G.u)^k / k! (Sec. III.C, Eq.
+ *                    disp_expansion, with G.u = 2 pi sum_alpha g_alpha u^alpha,
+ *                    Eq. gdotu_1).
+ *   orc_sf_magnetic  vector F_m(G) = sum_{R,mu} b_mu delta M e^{2 pi i g.(R + r_mu)}
+ *                    (Sec. III.D, Eq. mag_sf and Eq. mag_ft with T = 1); the form
+ *                    factor, the perpendicular projection and the constant are
+ *                    applied by the Python side.
+ *   orc_pair_sum     (1/N) sum_{j,k} b_j b_k e^{i Q.(r_j - r_k)} with the
+ *                    nearest-image convention (Sec. II, Eq. intensity_dble_sum).
+ *   orc_lanczos      the windowed-sinc resampling of Sec. V.B (Eqs.
+ *                    intensity_convol_finite, windowed_sinc, weight_sinc, lanczos)
+ *                    summed directly over the (2m)^3 neighbourhood, NOT separably.
+ *
+ * The lattice-point part of every phase is reduced exactly in integers first:
+ * e^{2 pi i G_a R_a / n_a} = e^{2 pi i ((G_a R_a) mod n_a) / n_a}.  This is an
+ * identity, done only so that the double-precision argument stays small.
+ *
+ * Error behaviour: every entry point returns 0 on success and -1 on a bad
+ * argument; outputs are written only on success.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define TWO_PI 6.283185307179586476925286766559
+
+static long imodl(long a, long n) { long r = a % n; return r < 0 ? r + n : r; }
+
+static int bad_dims(const int32_t* n) { return n[0] < 1 || n[1] < 1 || n[2] < 1; }
+
+/* Structure factor of a nuclear model (see file header).
+ * n[3]        supercell
+ * S           number of species-sites
+ * frac[S][3]  average fractional positions r_mu (unit-cell coordinates)
+ * b[S]        scattering lengths
+ * M           number of configurations
+ * occ         [M][S][n1][n2][n3] occupancy or NULL (= 1)
+ * disp        [M][S][n1][n2][n3][3] fractional displacements or NULL (= 0)
+ * order       < 0: exact exponential; >= 0: Taylor polynomial of that order
+ * nG, G       [nG][3] integer supercell Bragg indices
+ * F           [M][nG][2] output (re, im)
+ */
+int orc_sf_nuclear(const int32_t* n, int32_t S, const double* frac, const double* b,
+                   int32_t M, const float* occ, const float* disp, int32_t order,
+                   int64_t nG, const int32_t* G, double* F)
+{
+    if (bad_dims(n) || S < 1 || M < 1 || nG < 0 || !frac || !b || !G || !F) return -1;
+    const long n1 = n[0], n2 = n[1], n3 = n[2];
+    const long ncell = n1 * n2 * n3;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t gi = 0; gi < nG; ++gi) {
+        const long G1 = G[3 * gi], G2 = G[3 * gi + 1], G3 = G[3 * gi + 2];
+        const double g[3] = {(double)G1 / n1, (double)G2 / n2, (double)G3 / n3};
+        for (int32_t m = 0; m < M; ++m) {
+            double fr = 0.0, fi = 0.0;
+            for (int32_t mu = 0; mu < S; ++mu) {
+                const double gr = g[0] * frac[3 * mu] + g[1] * frac[3 * mu + 1] + g[2] * frac[3 * mu + 2];
+                for (long R1 = 0; R1 < n1; ++R1)
+                for (long R2 = 0; R2 < n2; ++R2)
+                for (long R3 = 0; R3 < n3; ++R3) {
+                    const long cell = (R1 * n2 + R2) * n3 + R3;
+                    const long at = ((long)m * S + mu) * ncell + cell;
+                    const double delta = occ ? (double)occ[at] : 1.0;
+                    const double lat = (double)imodl(G1 * R1, n1) / n1 + (double)imodl(G2 * R2, n2) / n2
+                                     + (double)imodl(G3 * R3, n3) / n3;
+                    double gu = 0.0;
+                    if (disp) {
+                        const float* u = disp + 3 * at;
+                        gu = g[0] * u[0] + g[1] * u[1] + g[2] * u[2];
+                    }
+                    double er, ei;
+                    if (order < 0) {
+                        const double ph = TWO_PI * (lat + gr + gu);
+                        er = cos(ph); ei = sin(ph);
+                    } else {
+                        /* e^{2 pi i (lat + gr)} * sum_{k=0}^{order} (i x)^k / k!,  x = 2 pi g.u */
+                        const double ph = TWO_PI * (lat + gr);
+                        const double x = TWO_PI * gu;
+                        double sr = 0.0, si = 0.0, tr = 1.0, ti = 0.0;
+                        for (int k = 0; k <= order; ++k) {
+                            sr += tr; si += ti;
+                            /* t <- t * (i x) / (k + 1) */
+                            const double nr = -ti * x / (k + 1), ni = tr * x / (k + 1);
+                            tr = nr; ti = ni;
+                        }
+                        const double c = cos(ph), s = sin(ph);
+                        er = c * sr - s * si; ei = c * si + s * sr;
+                    }
+                    fr += b[mu] * delta * er;
+                    fi += b[mu] * delta * ei;
+                }
+            }
+            F[2 * ((int64_t)m * nG + gi)] = fr;
+            F[2 * ((int64_t)m * nG + gi) + 1] = fi;
+        }
+    }
+    return 0;
+}
+
+/* Vector structure factor of a magnetic model, per site, without form factor
+ * (see header).  The per-site split lets the caller apply a different form factor
+ * to each site before summing.
+ * spin [M][S][n1][n2][n3][3] Cartesian moments; occ optional as above.
+ * F    [M][nG][S][3][2] output:  sum_R b_mu delta M e^{2 pi i g.(R + r_mu)}. */
+int orc_sf_magnetic(const int32_t* n, int32_t S, const double* frac, const double* b,
+                    int32_t M, const float* occ, const float* spin,
+                    int64_t nG, const int32_t* G, double* F)
+{
+    if (bad_dims(n) || S < 1 || M < 1 || nG < 0 || !frac || !b || !spin || !G || !F) return -1;
+    const long n1 = n[0], n2 = n[1], n3 = n[2];
+    const long ncell = n1 * n2 * n3;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t gi = 0; gi < nG; ++gi) {
+        const long G1 = G[3 * gi], G2 = G[3 * gi + 1], G3 = G[3 * gi + 2];
+        const double g[3] = {(double)G1 / n1, (double)G2 / n2, (double)G3 / n3};
+        for (int32_t m = 0; m < M; ++m) {
+            for (int32_t mu = 0; mu < S; ++mu) {
+                double acc[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+                const double gr = g[0] * frac[3 * mu] + g[1] * frac[3 * mu + 1] + g[2] * frac[3 * mu + 2];
+                for (long R1 = 0; R1 < n1; ++R1)
+                for (long R2 = 0; R2 < n2; ++R2)
+                for (long R3 = 0; R3 < n3; ++R3) {
+                    const long cell = (R1 * n2 + R2) * n3 + R3;
+                    const long at = ((long)m * S + mu) * ncell + cell;
+                    const double delta = occ ? (double)occ[at] : 1.0;
+                    const double lat = (double)imodl(G1 * R1, n1) / n1 + (double)imodl(G2 * R2, n2) / n2
+                                     + (double)imodl(G3 * R3, n3) / n3;
+                    const double ph = TWO_PI * (lat + gr);
+                    const double c = cos(ph), s = sin(ph);
+                    for (int k = 0; k < 3; ++k) {
+                        const double w = b[mu] * delta * (double)spin[3 * at + k];
+                        acc[k][0] += w * c;
+                        acc[k][1] += w * s;
+                    }
+                }
+                double* o = F + 2 * 3 * (((int64_t)m * nG + gi) * S + mu);
+                for (int k = 0; k < 3; ++k) { o[2 * k] = acc[k][0]; o[2 * k + 1] = acc[k][1]; }
+            }
+        }
+    }
+    return 0;
+}
+
+/* Pair double sum for ONE configuration at integer supercell points G:
+ *   out(G) = (1/normN) sum_{j,k} b_j d_j b_k d_k e^{2 pi i g.(x_j - x_k)}
+ * where x = R + r_mu + u in unit-cell coordinates and each separation is mapped to
+ * its nearest image: (x_j - x_k)_a / n_a brought into [-1/2, 1/2) (Sec. II).
+ * out [nG][2]. */
+int orc_pair_sum(const int32_t* n, int32_t S, const double* frac, const double* b,
+                 const float* occ, const float* disp, double normN,
+                 int64_t nG, const int32_t* G, double* out)
+{
+    if (bad_dims(n) || S < 1 || nG < 0 || !frac || !b || !G || !out || !(normN > 0)) return -1;
+    const long n1 = n[0], n2 = n[1], n3 = n[2];
+    const long ncell = n1 * n2 * n3;
+    const long natom = ncell * S;
+    const double nd[3] = {(double)n1, (double)n2, (double)n3};
+    double* pos = (double*)malloc(sizeof(double) * 3 * natom);
+    double* w = (double*)malloc(sizeof(double) * natom);
+    if (!pos || !w) { free(pos); free(w); return -1; }
+    for (int32_t mu = 0; mu < S; ++mu)
+        for (long R1 = 0; R1 < n1; ++R1)
+        for (long R2 = 0; R2 < n2; ++R2)
+        for (long R3 = 0; R3 < n3; ++R3) {
+            const long cell = (R1 * n2 + R2) * n3 + R3;
+            const long at = (long)mu * ncell + cell;
+            const double R[3] = {(double)R1, (double)R2, (double)R3};
+            for (int a = 0; a < 3; ++a)
+                pos[3 * at + a] = R[a] + frac[3 * mu + a] + (disp ? (double)disp[3 * at + a] : 0.0);
+            w[at] = b[mu] * (occ ? (double)occ[at] : 1.0);
+        }
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t gi = 0; gi < nG; ++gi) {
+        const double Gv[3] = {(double)G[3 * gi], (double)G[3 * gi + 1], (double)G[3 * gi + 2]};
+        double sr = 0.0, si = 0.0;
+        for (long j = 0; j < natom; ++j) {
+            if (w[j] == 0.0) continue;
+            for (long k = 0; k < natom; ++k) {
+                if (w[k] == 0.0) continue;
+                double ph = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    double d = (pos[3 * j + a] - pos[3 * k + a]) / nd[a];   /* supercell fraction */
+                    d -= floor(d + 0.5);                                     /* nearest image */
+                    ph += Gv[a] * d;                                         /* g_a * d n_a = G_a d */
+                }
+                ph *= TWO_PI;
+                sr += w[j] * w[k] * cos(ph);
+                si += w[j] * w[k] * sin(ph);
+            }
+        }
+        out[2 * gi] = sr / normN;
+        out[2 * gi + 1] = si / normN;
+    }
+    free(pos); free(w);
+    return 0;
+}
+
+static double sinc(double x) { return x == 0.0 ? 1.0 : sin(x) / x; }
+
+/* One-axis factor of the windowed-sinc weight W = W_sinc * L:
+ * 2 r_cut sinc(2 pi r_cut d) * [ |d| < m ] sinc(pi d / m), with r_cut = (1 - 1/m)/2. */
+static double lanczos_axis(double d, int m)
+{
+    const double rcut = 0.5 * (1.0 - 1.0 / m);
+    if (!(fabs(d) < (double)m)) return 0.0;
+    return 2.0 * rcut * sinc(TWO_PI * rcut * d) * sinc(M_PI * d / m);
+}
+
+/* Windowed-sinc resampling, direct (2m)^3 sum.
+ * Input I(G) on the box [e0, e0 + ecount) (last axis fastest).
+ * Output I(Q) at Q_a = q0_a + i_a / s for i_a in [0, qcount_a) (last axis fastest):
+ *   I(Q) = sum_G I(G) W(Q - G) / sum_G W(Q - G),
+ *   G_a in [floor(Q_a) - m + 1, floor(Q_a) + m].
+ * Returns -1 if a needed G lies outside the input box. */
+int orc_lanczos(int32_t m, int32_t s, const int32_t* e0, const int32_t* ecount, const double* I,
+                const int32_t* q0, const int32_t* qcount, double* out)
+{
+    if (m < 2 || s < 1 || !e0 || !ecount || !I || !q0 || !qcount || !out) return -1;
+    /* range check over the whole output first */
+    for (int a = 0; a < 3; ++a) {
+        const long lo = (long)q0[a] - m + 1;
+        const long hi = (long)q0[a] + (qcount[a] - 1) / s + m;
+        if (lo < e0[a] || hi >= (long)e0[a] + ecount[a]) return -1;
+    }
+    const long total = (long)qcount[0] * qcount[1] * qcount[2];
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(|:bad)
+    for (long idx = 0; idx < total; ++idx) {
+        const long i3 = idx % qcount[2], i2 = (idx / qcount[2]) % qcount[1], i1 = idx / ((long)qcount[2] * qcount[1]);
+        const double Q[3] = {q0[0] + (double)i1 / s, q0[1] + (double)i2 / s, q0[2] + (double)i3 / s};
+        const long f[3] = {(long)floor(Q[0]), (long)floor(Q[1]), (long)floor(Q[2])};
+        double num = 0.0, den = 0.0;
+        for (long G1 = f[0] - m + 1; G1 <= f[0] + m; ++G1)
+        for (long G2 = f[1] - m + 1; G2 <= f[1] + m; ++G2)
+        for (long G3 = f[2] - m + 1; G3 <= f[2] + m; ++G3) {
+            const double W = lanczos_axis(Q[0] - G1, m) * lanczos_axis(Q[1] - G2, m) * lanczos_axis(Q[2] - G3, m);
+            const long j1 = G1 - e0[0], j2 = G2 - e0[1], j3 = G3 - e0[2];
+            if (j1 < 0 || j2 < 0 || j3 < 0 || j1 >= ecount[0] || j2 >= ecount[1] || j3 >= ecount[2]) { bad = 1; continue; }
+            num += W * I[(j1 * ecount[1] + j2) * ecount[2] + j3];
+            den += W;
+        }
+        out[idx] = num / den;
+    }
+    return bad ? -1 : 0;
+}
+
+int orc_version(void) { return 1; }

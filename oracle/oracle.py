@@ -1,0 +1,344 @@
+"""FP64 CPU oracle for the diffuse-scattering hot path.
+
+TEST INFRASTRUCTURE ONLY: imported by the test-suite, by the smoke check and by
+the CPU-baseline leg of the benchmark, never by the product path.  It shares no
+code with the HIP library (`paper_1809_07088_amd`), and neither imports the other.
+
+Two independent routes are provided:
+
+* the plain definition -- direct Fourier summation over every atom
+  (``oracle.c``: Sec. II Eqs. sf / intensity_sf, Sec. III.A Eq. total_sf,
+  Sec. III.D Eq. mag_sf), with the intensity, Bragg subtraction, magnetic form
+  factor and perpendicular projection applied here in NumPy;
+* the paper's FFT route for nuclear models, step by step in its own notation:
+  the per-site transforms U and A of the Taylor monomials (Sec. III.C,
+  Eqs. U_fft / A_fft, with the +i sign of Eq. fft) recombined by Eq.
+  total_sf_taylor.  It uses numpy's pocketfft as the transform.
+
+Readings of the paper taken here (each is listed with its reason in the design
+notes of the repository):
+
+* Fourier sign +i everywhere (Eq. sf, Eq. fft).
+* In the Taylor formulas G_alpha means g_alpha = G_alpha / n_alpha (reciprocal
+  lattice units) and u^alpha are fractional unit-cell components, so
+  G.u = 2 pi sum_alpha g_alpha u^alpha (Eq. gdotu_1).
+* The ordered index tuples alpha(n) of Eq. gu_expansion are regrouped into
+  multisets p + q + r = n with weight n!/(p! q! r!); the number of distinct
+  monomials of order n is then (n+1)(n+2)/2, as the paper states.
+* <F> is the empirical mean over the model's configurations, applied only at
+  G = 0 (mod n) on every axis (the delta_{G,H} of Eqs. bragg_sf /
+  bragg_sf_disp); odd Taylor orders are kept in that mean.
+* N in I = <|F|^2>/N is n1 n2 n3 times the number of distinct average atomic
+  positions (Sec. II), unless overridden.
+* Magnetic: T = 1, spins Cartesian, s = |Q|/(4 pi), the constant
+  C = 0.07265 barn of Eq. mag_intensity included, the Bragg subtraction applied to
+  F_perp, and I(G = 0) := 0 because the direction of G is undefined there.
+"""
+from __future__ import annotations
+
+import ctypes
+import itertools
+import math
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+NUCLEAR = 0
+MAGNETIC = 1
+MAG_CONSTANT_BARN = 0.07265      # C = (gamma_n r_0 / 2)^2, Sec. III.D
+
+_lib = None
+
+
+def build() -> str:
+    """Compile oracle.c into liboracle.so next to it (gcc, -O2, OpenMP, no fast-math)."""
+    tmp = LIB + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                           "-D_DEFAULT_SOURCE", "-o", tmp, SRC, "-lm"])
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+        L = ctypes.CDLL(LIB)
+        P = ctypes.c_void_p
+        i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        L.orc_sf_nuclear.argtypes = [P, i32, P, P, i32, P, P, i32, i64, P, P]
+        L.orc_sf_magnetic.argtypes = [P, i32, P, P, i32, P, P, i64, P, P]
+        L.orc_pair_sum.argtypes = [P, i32, P, P, P, P, f64, i64, P, P]
+        L.orc_lanczos.argtypes = [i32, i32, P, P, P, P, P, P]
+        for f in (L.orc_sf_nuclear, L.orc_sf_magnetic, L.orc_pair_sum, L.orc_lanczos):
+            f.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ----------------------------------------------------------------------------- geometry
+
+def cell_vectors(cell) -> np.ndarray:
+    """Rows a, b, c (Cartesian, Angstrom) of a cell given as (a, b, c, alpha, beta, gamma);
+    a along x, b in the xy plane."""
+    a, b, c, al, be, ga = [float(v) for v in cell]
+    al, be, ga = np.radians([al, be, ga])
+    ax = np.array([a, 0.0, 0.0])
+    bx = np.array([b * np.cos(ga), b * np.sin(ga), 0.0])
+    cx = c * np.cos(be)
+    cy = c * (np.cos(al) - np.cos(be) * np.cos(ga)) / np.sin(ga)
+    cz = np.sqrt(max(c * c - cx * cx - cy * cy, 0.0))
+    return np.array([ax, bx, [cx, cy, cz]])
+
+
+def reciprocal_basis(cell) -> np.ndarray:
+    """Rows a*, b*, c* with a* = 2 pi (b x c) / V (Sec. II)."""
+    A = cell_vectors(cell)
+    V = np.dot(A[0], np.cross(A[1], A[2]))
+    return 2.0 * np.pi * np.array([np.cross(A[1], A[2]), np.cross(A[2], A[0]),
+                                   np.cross(A[0], A[1])]) / V
+
+
+def norm_N(model) -> float:
+    """n1 n2 n3 x number of distinct average positions (or the model's override)."""
+    if getattr(model, "norm_N", 0.0):
+        return float(model.norm_N)
+    npos = model.n_sites if model.pos_id is None else len(np.unique(model.pos_id))
+    return float(np.prod(model.n)) * npos
+
+
+def grid_points(g0, count) -> np.ndarray:
+    """All integer G of the box [g0, g0 + count), last axis fastest, as int32 [nG][3]."""
+    axes = [np.arange(g0[a], g0[a] + count[a], dtype=np.int32) for a in range(3)]
+    return np.stack(np.meshgrid(*axes, indexing="ij"), axis=-1).reshape(-1, 3).astype(np.int32)
+
+
+def is_unit_cell_bragg(G, n) -> np.ndarray:
+    """True where G = 0 (mod n) on every axis (G = H, k = 0)."""
+    G = np.asarray(G)
+    return np.all(np.mod(G, np.asarray(n)) == 0, axis=-1)
+
+
+# ----------------------------------------------------------------------------- direct sums
+
+def structure_factor(model, G, order=None) -> np.ndarray:
+    """F_m(G) for every configuration m, complex128 [M][nG] (direct sum).
+    order=None: the model's Taylor order when it has displacements; order=-1: exact."""
+    assert model.kind == NUCLEAR
+    if order is None:
+        order = model.order if model.disp is not None else -1
+    G = np.ascontiguousarray(G, dtype=np.int32).reshape(-1, 3)
+    n = np.ascontiguousarray(model.n, dtype=np.int32)
+    frac = np.ascontiguousarray(model.frac, dtype=np.float64)
+    b = np.ascontiguousarray(model.b, dtype=np.float64)
+    occ = None if model.occ is None else np.ascontiguousarray(model.occ, dtype=np.float32)
+    disp = None if model.disp is None else np.ascontiguousarray(model.disp, dtype=np.float32)
+    M = model.n_configs
+    out = np.zeros((M, G.shape[0], 2), dtype=np.float64)
+    rc = lib().orc_sf_nuclear(_ptr(n), model.n_sites, _ptr(frac), _ptr(b), M, _ptr(occ),
+                              _ptr(disp), int(order), G.shape[0], _ptr(G), _ptr(out))
+    if rc != 0:
+        raise ValueError("orc_sf_nuclear rejected its arguments")
+    return out[..., 0] + 1j * out[..., 1]
+
+
+def structure_factor_magnetic_sites(model, G) -> np.ndarray:
+    """Per-site vector structure factor without form factor, complex128 [M][nG][S][3]."""
+    assert model.kind == MAGNETIC
+    G = np.ascontiguousarray(G, dtype=np.int32).reshape(-1, 3)
+    n = np.ascontiguousarray(model.n, dtype=np.int32)
+    frac = np.ascontiguousarray(model.frac, dtype=np.float64)
+    b = np.ascontiguousarray(model.b, dtype=np.float64)
+    occ = None if model.occ is None else np.ascontiguousarray(model.occ, dtype=np.float32)
+    spin = np.ascontiguousarray(model.spin, dtype=np.float32)
+    M, S = model.n_configs, model.n_sites
+    out = np.zeros((M, G.shape[0], S, 3, 2), dtype=np.float64)
+    rc = lib().orc_sf_magnetic(_ptr(n), S, _ptr(frac), _ptr(b), M, _ptr(occ), _ptr(spin),
+                               G.shape[0], _ptr(G), _ptr(out))
+    if rc != 0:
+        raise ValueError("orc_sf_magnetic rejected its arguments")
+    return out[..., 0] + 1j * out[..., 1]
+
+
+def magnetic_form_factor(ff, s) -> np.ndarray:
+    """f(s) = A e^{-a s^2} + B e^{-b s^2} + C e^{-c s^2} + D for ff = (A, a, B, b, C, c, D)."""
+    A, a, B, b, C, c, D = [float(v) for v in ff]
+    s2 = np.asarray(s, dtype=np.float64) ** 2
+    return A * np.exp(-a * s2) + B * np.exp(-b * s2) + C * np.exp(-c * s2) + D
+
+
+def q_cartesian(model, G) -> np.ndarray:
+    """Cartesian Q = g1 a* + g2 b* + g3 c* for g = G / n, [nG][3] (inverse Angstrom)."""
+    g = np.asarray(G, dtype=np.float64) / np.asarray(model.n, dtype=np.float64)
+    return g @ reciprocal_basis(model.cell)
+
+
+def bragg_diffuse(F, G, n, normN) -> np.ndarray:
+    """(1/N) [ (1/M) sum_m |F_m|^2 - [G = 0 mod n] |(1/M) sum_m F_m|^2 ]  (Eq. bragg_diffuse_sf).
+    F has shape [M][nG] or [M][nG][3] (vector: squared norms)."""
+    F = np.asarray(F)
+    if F.ndim == 2:
+        F = F[..., None]
+    mean_sq = np.mean(np.sum(np.abs(F) ** 2, axis=-1), axis=0)
+    sq_mean = np.sum(np.abs(np.mean(F, axis=0)) ** 2, axis=-1)
+    return (mean_sq - np.where(is_unit_cell_bragg(G, n), sq_mean, 0.0)) / normN
+
+
+def magnetic_perp(model, G, F_sites) -> np.ndarray:
+    """F_perp = F - Ghat (Ghat . F) of F = sum_mu f_mu(|Q|) F_mu; zero at G = 0. [M][nG][3]."""
+    Q = q_cartesian(model, G)
+    qn = np.linalg.norm(Q, axis=-1)
+    s = qn / (4.0 * np.pi)
+    f = np.stack([magnetic_form_factor(model.ff[mu], s) for mu in range(model.n_sites)], axis=-1)
+    F = np.einsum("gs,mgsc->mgc", f, F_sites)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        ghat = np.where(qn[:, None] > 0, Q / qn[:, None], 0.0)
+    proj = np.einsum("gc,mgc->mg", ghat, F)
+    Fp = F - ghat[None] * proj[..., None]
+    Fp[:, qn == 0.0, :] = 0.0
+    return Fp
+
+
+def intensity(model, G=None, order=None) -> np.ndarray:
+    """Bragg-subtracted diffuse intensity at the integer points G (default: the model box),
+    float64 [nG].  Nuclear: Eq. disp_diffuse_intensity; magnetic: Eq. mag_intensity with
+    the Bragg subtraction applied to F_perp."""
+    if G is None:
+        G = grid_points(model.g0, model.count)
+    G = np.asarray(G, dtype=np.int32).reshape(-1, 3)
+    N = norm_N(model)
+    if model.kind == NUCLEAR:
+        return bragg_diffuse(structure_factor(model, G, order), G, model.n, N)
+    Fp = magnetic_perp(model, G, structure_factor_magnetic_sites(model, G))
+    return MAG_CONSTANT_BARN * bragg_diffuse(Fp, G, model.n, N)
+
+
+def pair_sum(model, member, G) -> np.ndarray:
+    """(1/N) sum_{j,k} b_j b_k e^{i G.(r_j - r_k)} for one configuration, nearest-image
+    separations (Eq. intensity_dble_sum).  Complex [nG]; real up to rounding."""
+    assert model.kind == NUCLEAR
+    G = np.ascontiguousarray(G, dtype=np.int32).reshape(-1, 3)
+    n = np.ascontiguousarray(model.n, dtype=np.int32)
+    frac = np.ascontiguousarray(model.frac, dtype=np.float64)
+    b = np.ascontiguousarray(model.b, dtype=np.float64)
+    occ = None if model.occ is None else np.ascontiguousarray(model.occ[member], dtype=np.float32)
+    disp = None if model.disp is None else np.ascontiguousarray(model.disp[member], dtype=np.float32)
+    out = np.zeros((G.shape[0], 2))
+    rc = lib().orc_pair_sum(_ptr(n), model.n_sites, _ptr(frac), _ptr(b), _ptr(occ), _ptr(disp),
+                            norm_N(model), G.shape[0], _ptr(G), _ptr(out))
+    if rc != 0:
+        raise ValueError("orc_pair_sum rejected its arguments")
+    return out[:, 0] + 1j * out[:, 1]
+
+
+def lanczos(I_ext, e0, m, s, q0, qcount) -> np.ndarray:
+    """Windowed-sinc resampling by the direct (2m)^3 sum (Sec. V.B).
+    I_ext: float array [e1][e2][e3] on the box starting at e0; output on
+    Q_a = q0_a + i_a / s, i_a < qcount_a, float64 [q1][q2][q3]."""
+    I_ext = np.ascontiguousarray(I_ext, dtype=np.float64)
+    e0 = np.ascontiguousarray(e0, dtype=np.int32)
+    ec = np.ascontiguousarray(I_ext.shape, dtype=np.int32)
+    q0 = np.ascontiguousarray(q0, dtype=np.int32)
+    qc = np.ascontiguousarray(qcount, dtype=np.int32)
+    out = np.zeros(tuple(int(v) for v in qcount), dtype=np.float64)
+    rc = lib().orc_lanczos(int(m), int(s), _ptr(e0), _ptr(ec), _ptr(I_ext), _ptr(q0), _ptr(qc),
+                           _ptr(out))
+    if rc != 0:
+        raise ValueError("orc_lanczos: bad arguments or input box too small for the window")
+    return out
+
+
+def filtered_intensity(model, m, s=1, order=None) -> np.ndarray:
+    """The model box filtered with Lanczos parameter m: I(G) is summed directly on the
+    box grown by m on every side, then resampled by the direct (2m)^3 sum."""
+    e0 = [model.g0[a] - m for a in range(3)]
+    ec = [model.count[a] + 2 * m for a in range(3)]
+    I_ext = intensity(model, grid_points(e0, ec), order).reshape(ec)
+    qc = [s * model.count[a] for a in range(3)]
+    return lanczos(I_ext, e0, m, s, model.g0, qc)
+
+
+# ----------------------------------------------------------------------------- FFT route
+
+def monomials(order):
+    """Exponent triples (p, q, r), p + q + r <= order, grouped by total degree."""
+    out = []
+    for d in range(order + 1):
+        for p in range(d, -1, -1):
+            for q in range(d - p, -1, -1):
+                out.append((p, q, d - p - q))
+    return out
+
+
+def _plus_i_fft(x):
+    """X_k = sum_R x_R e^{+2 pi i k.R / n} over the last three axes (Eq. fft)."""
+    n = np.prod(x.shape[-3:])
+    return np.fft.ifftn(x, axes=(-3, -2, -1)) * n
+
+
+def fft_route_structure_factor(model, G, order=None) -> np.ndarray:
+    """F_m(G) by the paper's FFT route, complex128 [M][nG]: per site mu, the transforms
+    U^{pqr}_k and A^{pqr}_k of the monomials u1^p u2^q u3^r and a u1^p u2^q u3^r
+    (Eqs. U_fft, A_fft; a = (delta - c)/c, Eq. occ, c the ensemble-mean occupancy),
+    combined by Eq. total_sf_taylor at k = G mod n."""
+    assert model.kind == NUCLEAR
+    if order is None:
+        order = model.order if model.disp is not None else 0
+    G = np.asarray(G, dtype=np.int64).reshape(-1, 3)
+    n = np.asarray(model.n, dtype=np.int64)
+    g = G / n
+    k = np.mod(G, n)
+    M, S = model.n_configs, model.n_sites
+    F = np.zeros((M, G.shape[0]), dtype=np.complex128)
+    shp = (M,) + tuple(int(v) for v in n)
+    for mu in range(S):
+        delta = np.ones(shp) if model.occ is None else model.occ[:, mu].astype(np.float64)
+        c = delta.mean()
+        if c == 0.0:
+            continue
+        a = (delta - c) / c
+        u = np.zeros(shp + (3,)) if model.disp is None else model.disp[:, mu].astype(np.float64)
+        site_phase = np.exp(2j * np.pi * (g @ model.frac[mu]))
+        for (p, q, r) in monomials(order):
+            U = u[..., 0] ** p * u[..., 1] ** q * u[..., 2] ** r
+            Uk = _plus_i_fft(U)
+            Ak = _plus_i_fft(a * U)
+            d = p + q + r
+            coef = ((2j * np.pi) ** d * g[:, 0] ** p * g[:, 1] ** q * g[:, 2] ** r
+                    / (math.factorial(p) * math.factorial(q) * math.factorial(r)))
+            spec = (Uk + Ak)[:, k[:, 0], k[:, 1], k[:, 2]]
+            F += c * model.b[mu] * site_phase[None] * coef[None] * spec
+    return F
+
+
+def fft_route_intensity(model, G=None, order=None) -> np.ndarray:
+    if G is None:
+        G = grid_points(model.g0, model.count)
+    G = np.asarray(G, dtype=np.int32).reshape(-1, 3)
+    return bragg_diffuse(fft_route_structure_factor(model, G, order), G, model.n, norm_N(model))
+
+
+def ordered_tuple_weight_check(order, g) -> float:
+    """Largest |sum over ordered tuples alpha(n) of prod g_alpha u^alpha - regrouped multiset
+    sum| for a random u, used to pin the multiset regrouping (Eq. gu_expansion)."""
+    rng = np.random.default_rng(7)
+    u = rng.normal(size=3)
+    worst = 0.0
+    for d in range(order + 1):
+        tuples = sum(np.prod([g[a] * u[a] for a in t]) for t in itertools.product(range(3), repeat=d)) \
+            if d else 1.0
+        ms = sum(math.factorial(d) / (math.factorial(p) * math.factorial(q) * math.factorial(r))
+                 * (g[0] * u[0]) ** p * (g[1] * u[1]) ** q * (g[2] * u[2]) ** r
+                 for (p, q, r) in monomials(d) if p + q + r == d)
+        worst = max(worst, abs(tuples - ms))
+    return worst

@@ -1,0 +1,281 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: printed values,
+closed forms, exact invariances, the Taylor remainder bound, an independent
+brute-force formula (pair double sum), or an independent algorithm (the paper's
+FFT route against the direct sum).  All run on the CPU.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_values.txt")
+
+
+def golden():
+    vals = {}
+    with open(GOLDEN) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                key, val = line.split()[:2]
+                vals[key] = float(val)
+    return vals
+
+
+# --------------------------------------------------------------------------- printed values
+
+def test_printed_constants_and_counts():
+    g = golden()
+    assert O.MAG_CONSTANT_BARN == g["mag_constant_barn"]
+    for n in (0, 1, 2, 5):
+        assert sum(1 for t in O.monomials(n) if sum(t) == n) == g[f"ffts_per_order_{n}"]
+    # fully occupied sites: the constant monomial needs no transform
+    assert len(O.monomials(5)) - 1 == g["ffts_fifth_order_total"]
+
+
+def test_multiset_regrouping_of_ordered_tuples():
+    # Eq. gu_expansion sums over ordered tuples; the oracle's FFT route sums over
+    # multisets with multinomial weights. Same value for any g, u.
+    assert O.ordered_tuple_weight_check(6, np.array([0.7, -1.3, 2.1])) < 1e-12
+
+
+# --------------------------------------------------------------------------- P1 zero disorder
+
+@pytest.mark.parametrize("n", [4, 32])
+def test_zero_disorder_only_bragg_closed_form(n):
+    m = synth.displacive(n=n, order=0, hmax=1)
+    m.disp = None
+    H = np.array([[0, 0, 0], [1, 1, 1], [1, 0, 0], [0, 2, 0], [1, 1, 0], [2, -1, 1]])
+    off = np.array([[1, 0, 0], [3, 5, 7], [n - 1, 1, 2], [-5, 2, n + 3]])
+    G = np.concatenate([H * n, off])
+    F = O.structure_factor(m, G, order=-1)[0]
+    Itot = np.abs(F) ** 2 / O.norm_N(m)
+    # Eq. total_sf with u = 0, delta = 1: F(nH) = n^3 sum_mu b_mu e^{2 pi i H.r_mu}, 0 elsewhere
+    S = np.array([np.sum(m.b * np.exp(2j * np.pi * (m.frac @ h))) for h in H])
+    expect = (n ** 3 / m.n_sites) * np.abs(S) ** 2
+    assert np.allclose(Itot[:len(H)], expect, rtol=1e-10, atol=1e-9)
+    assert np.max(Itot[len(H):]) < 1e-18 * n ** 3
+    if n == 32:   # unmixed / mixed hkl of the fcc basis with b = 1, .7, .7, .7 (closed form)
+        assert abs(Itot[1] - 78725.12) < 1e-5 and abs(Itot[2] - 737.28) < 1e-6
+    Id = O.intensity(m, G, order=-1)
+    assert np.max(np.abs(Id)) < 1e-9
+
+
+# --------------------------------------------------------------------------- P2 Parseval
+
+def test_parseval_compositional_full_grid():
+    m = synth.compositional(n=12, M=1, hmax=2)
+    I = O.intensity(m).reshape(m.count)
+    cbar = float(m.occ.astype(np.float64).mean())
+    assert abs(I.mean() - cbar * (1 - cbar)) < 1e-12
+    # every 12^3 zone is identical (one site at the origin, no displacements)
+    z = I.reshape(4, 12, 4, 12, 4, 12)
+    assert np.allclose(z, z[:1, :, :1, :, :1, :], rtol=1e-10, atol=1e-12)
+
+
+# --------------------------------------------------------------------------- P3 Friedel
+
+@pytest.mark.parametrize("order", [-1, 0, 3, 6])
+def test_friedel_nuclear(order):
+    m = synth.random_model(3, n=(3, 4, 5), S=3, M=2, order=max(order, 0))
+    G = O.grid_points(m.g0, m.count)
+    sel = np.random.default_rng(0).choice(len(G), 300, replace=False)
+    I1 = O.intensity(m, G[sel], order)
+    I2 = O.intensity(m, -G[sel], order)
+    assert np.allclose(I1, I2, rtol=1e-10, atol=1e-12)
+
+
+def test_friedel_magnetic():
+    m = synth.random_model(4, n=(3, 3, 4), S=3, M=2, kind=synth.MAGNETIC,
+                           cell=[7.0, 8.0, 9.0, 80.0, 95.0, 100.0])
+    G = O.grid_points(m.g0, m.count)[::7]
+    assert np.allclose(O.intensity(m, G), O.intensity(m, -G), rtol=1e-10, atol=1e-14)
+
+
+# --------------------------------------------------------------------------- P4 invariances
+
+def test_invariance_shift_roll_permutation():
+    m = synth.random_model(5, n=(4, 3, 5), S=3, M=2, order=4)
+    G = O.grid_points(m.g0, m.count)[::5]
+    I0 = O.intensity(m, G)
+    # global shift of every average site position
+    m2 = synth.random_model(5, n=(4, 3, 5), S=3, M=2, order=4)
+    m2.frac = m2.frac + np.array([0.123, -0.31, 0.77])
+    assert np.allclose(O.intensity(m2, G), I0, rtol=1e-10, atol=1e-12)
+    # cyclic shift of lattice points in one configuration
+    m3 = synth.random_model(5, n=(4, 3, 5), S=3, M=2, order=4)
+    m3.occ[1] = np.roll(m3.occ[1], (1, 2, 3), axis=(1, 2, 3))
+    m3.disp[1] = np.roll(m3.disp[1], (1, 2, 3), axis=(1, 2, 3))
+    assert np.allclose(O.intensity(m3, G), I0, rtol=1e-10, atol=1e-12)
+    # permutation of the site order
+    m4 = synth.random_model(5, n=(4, 3, 5), S=3, M=2, order=4)
+    p = [2, 0, 1]
+    m4.frac, m4.b = m4.frac[p], m4.b[p]
+    m4.occ, m4.disp = m4.occ[:, p], m4.disp[:, p]
+    assert np.allclose(O.intensity(m4, G), I0, rtol=1e-10, atol=1e-12)
+
+
+def test_tiling_doubles_lattice():
+    m = synth.random_model(6, n=(2, 3, 2), S=2, M=2, order=3)
+    big = synth.random_model(6, n=(4, 6, 4), S=2, M=2, order=3)
+    big.frac, big.b = m.frac, m.b
+    big.occ = np.tile(m.occ, (1, 1, 2, 2, 2))
+    big.disp = np.tile(m.disp, (1, 1, 2, 2, 2, 1))
+    G = O.grid_points((-3, -4, -3), (7, 9, 7))
+    assert np.allclose(O.intensity(big, 2 * G), 8 * O.intensity(m, G), rtol=1e-10, atol=1e-12)
+    odd = 2 * G + np.array([1, 0, 0])
+    assert np.max(np.abs(O.intensity(big, odd[::3]))) < 1e-12
+
+
+# --------------------------------------------------------------------------- P5 Taylor
+
+def test_taylor_remainder_bound_and_convergence():
+    m = synth.random_model(7, n=(3, 3, 3), S=2, M=2, order=8, sigma=0.02)
+    G = O.grid_points(m.g0, m.count)[::3]
+    Fx = O.structure_factor(m, G, order=-1)
+    g = G / np.array(m.n)
+    # per-atom |2 pi g.u| and weights |b delta|
+    x = 2 * np.pi * np.einsum("ga,msijka->msijkg", g, m.disp.astype(np.float64))
+    w = np.abs(m.b[None, :, None, None, None] * m.occ.astype(np.float64))
+    errs = []
+    for N in range(0, 9):
+        FN = O.structure_factor(m, G, order=N)
+        bound = np.einsum("msijk,msijkg->mg", w, np.abs(x) ** (N + 1)) / math.factorial(N + 1)
+        assert np.all(np.abs(FN - Fx) <= bound * (1 + 1e-9) + 1e-12)
+        errs.append(np.max(np.abs(FN - Fx)))
+    assert all(errs[i + 1] < errs[i] for i in range(len(errs) - 1))
+    assert errs[-1] < 1e-4 * errs[0] and errs[-1] < 1e-5 * np.max(np.abs(Fx)) * 10
+
+
+# --------------------------------------------------------------------------- P7 magnetic
+
+def test_magnetic_form_factor_and_projection():
+    assert abs(O.magnetic_form_factor(synth.MAG_FF, 0.0) - 1.0) < 1e-15
+    m = synth.random_model(8, n=(3, 3, 3), S=2, M=1, kind=synth.MAGNETIC,
+                           cell=[5.0, 6.0, 7.0, 90.0, 100.0, 90.0])
+    G = O.grid_points(m.g0, m.count)[::4]
+    Fs = O.structure_factor_magnetic_sites(m, G)
+    Fp = O.magnetic_perp(m, G, Fs)
+    q = np.linalg.norm(O.q_cartesian(m, G), axis=-1)
+    f = np.stack([O.magnetic_form_factor(m.ff[mu], q / (4 * np.pi)) for mu in range(m.n_sites)], -1)
+    F = np.einsum("gs,mgsc->mgc", f, Fs)
+    assert np.all(np.sum(np.abs(Fp) ** 2, -1) <= np.sum(np.abs(F) ** 2, -1) * (1 + 1e-12) + 1e-15)
+    # F_perp is orthogonal to Q
+    Q = O.q_cartesian(m, G)
+    assert np.max(np.abs(np.einsum("gc,mgc->mg", Q, Fp))) < 1e-9
+
+
+def test_magnetic_ising_along_x_matches_scalar_route():
+    # moments +-x: |F_perp|^2 = (1 - Ghat_x^2) |F_x|^2, F_x the scalar sum with weights +-1
+    m = synth.random_model(9, n=(3, 4, 3), S=2, M=2, kind=synth.MAGNETIC,
+                           cell=[4.0, 4.5, 5.0, 90.0, 90.0, 90.0])
+    sgn = np.where(np.random.default_rng(3).random(m.spin.shape[:-1]) < 0.5, -1.0, 1.0)
+    m.occ = None
+    m.spin = np.zeros_like(m.spin)
+    m.spin[..., 0] = sgn
+    m.ff = np.tile(np.array([0, 0, 0, 0, 0, 0, 1.0]), (m.n_sites, 1))   # f = 1
+    G = O.grid_points(m.g0, m.count)[::3]
+    Imag = O.intensity(m, G)
+    nuc = synth.Model(cell=m.cell, n=m.n, frac=m.frac, b=m.b, occ=sgn.astype(np.float32))
+    Fx = O.structure_factor(nuc, G, order=-1)
+    Q = O.q_cartesian(m, G)
+    qn = np.linalg.norm(Q, axis=-1)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        gx2 = np.where(qn > 0, (Q[:, 0] / qn) ** 2, 1.0)
+    Fperp = np.sqrt(1 - gx2)[None] * Fx
+    expect = O.MAG_CONSTANT_BARN * O.bragg_diffuse(Fperp, G, m.n, O.norm_N(m))
+    assert np.allclose(Imag, expect, rtol=1e-10, atol=1e-14)
+
+
+def test_magnetic_collinear_z_zero_on_00l():
+    m = synth.random_model(10, n=(3, 3, 4), S=2, M=1, kind=synth.MAGNETIC)
+    m.spin = np.zeros_like(m.spin)
+    m.spin[..., 2] = np.where(np.random.default_rng(1).random(m.spin.shape[:-1]) < .5, -1, 1)
+    G = np.array([[0, 0, l] for l in range(-9, 10)])
+    assert np.max(np.abs(O.intensity(m, G))) < 1e-14
+
+
+# --------------------------------------------------------------------------- P8 Lanczos
+
+def _sep_lanczos(I_ext, e0, m, s, q0, qcount):
+    """Independent separable evaluation: three 1D normalised passes (Sec. V.B)."""
+    rcut = 0.5 * (1 - 1 / m)
+
+    def w(d):
+        d = np.asarray(d, float)
+        out = 2 * rcut * np.sinc(2 * rcut * d) * np.sinc(d / m)   # np.sinc(x) = sin(pi x)/(pi x)
+        return np.where(np.abs(d) < m, out, 0.0)
+
+    X = np.asarray(I_ext, float)
+    for ax in range(3):
+        Q = q0[ax] + np.arange(qcount[ax]) / s
+        fl = np.floor(Q).astype(int)
+        rows = []
+        for qi, Qv in enumerate(Q):
+            Gs = np.arange(fl[qi] - m + 1, fl[qi] + m + 1)
+            ww = w(Qv - Gs)
+            idx = Gs - e0[ax]
+            rows.append(np.tensordot(ww / ww.sum(), np.take(X, idx, axis=ax), axes=([0], [ax])))
+        X = np.moveaxis(np.stack(rows), 0, ax)
+    return X
+
+
+@pytest.mark.parametrize("m,s", [(2, 1), (4, 1), (2, 3), (3, 2)])
+def test_lanczos_direct_equals_separable_and_keeps_constants(m, s):
+    rng = np.random.default_rng(m * 10 + s)
+    e0 = np.array([-7, -5, -6])
+    I_ext = rng.random((17, 14, 15))
+    q0 = e0 + m
+    qc = [(17 - 2 * m) * s - s + 1, (14 - 2 * m) * s - s + 1, (15 - 2 * m) * s - s + 1]
+    qc = [max(1, (e - 2 * m - 1) * s) for e in (17, 14, 15)]
+    d = O.lanczos(I_ext, e0, m, s, q0, qc)
+    sep = _sep_lanczos(I_ext, e0, m, s, q0, qc)
+    assert np.allclose(d, sep, rtol=1e-12, atol=1e-13)
+    c = O.lanczos(np.full_like(I_ext, 3.25), e0, m, s, q0, qc)
+    assert np.allclose(c, 3.25, rtol=1e-13)
+
+
+def test_lanczos_m2_weights_closed_form():
+    # impulse response on the G grid: neighbours weighted by (2/pi)^2 per axis, normalised
+    e0 = np.array([-3, -3, -3])
+    I = np.zeros((7, 7, 7))
+    I[3, 3, 3] = 1.0
+    out = O.lanczos(I, e0, 2, 1, [-1, -1, -1], [3, 3, 3])
+    w1 = (2 / np.pi) ** 2
+    line = np.array([w1, 1.0, w1]) / (1 + 2 * w1)
+    assert np.allclose(out, np.einsum("i,j,k->ijk", line[::-1], line[::-1], line[::-1]), atol=1e-15)
+    assert abs(w1 - 0.405285) < 1e-6
+
+
+# --------------------------------------------------------------------------- P9 brute force
+
+@pytest.mark.parametrize("seed", [11, 12])
+def test_pair_double_sum_equals_single_sum(seed):
+    m = synth.random_model(seed, n=(2, 3, 3), S=3, M=1, order=0, sigma=0.1)
+    G = O.grid_points(m.g0, m.count)[::11]
+    P = O.pair_sum(m, 0, G)
+    F = O.structure_factor(m, G, order=-1)[0]
+    assert np.allclose(P.real, np.abs(F) ** 2 / O.norm_N(m), rtol=1e-11, atol=1e-12)
+    assert np.max(np.abs(P.imag)) < 1e-11
+
+
+# --------------------------------------------------------------------------- P10 FFT route
+
+@pytest.mark.parametrize("seed,order", [(13, 0), (14, 2), (15, 5)])
+def test_fft_route_equals_direct_sum(seed, order):
+    m = synth.random_model(seed, n=(3, 4, 5), S=2, M=3, order=order)
+    G = O.grid_points(m.g0, m.count)
+    Id = O.intensity(m, G, order)
+    If = O.fft_route_intensity(m, G, order)
+    assert np.linalg.norm(Id - If) <= 1e-12 * np.linalg.norm(Id)
+
+
+def test_fft_route_compositional_equals_direct():
+    m = synth.compositional(n=(4, 5, 6), M=2, hmax=1, frac=synth.FCC_BASIS[:3], b=synth.FCC_B[:3])
+    G = O.grid_points(m.g0, m.count)
+    assert np.allclose(O.intensity(m, G), O.fft_route_intensity(m, G), rtol=1e-11, atol=1e-13)
