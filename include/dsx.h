@@ -1,0 +1,186 @@
+/*
+ * dsx -- diffuse scattering from atomistic models on one MI355X (gfx950).
+ *
+ * C-ABI of the hot path of the FFT method of Paddison, "Ultrafast Calculation
+ * of Diffuse Scattering from Atomistic Models" (arXiv:1809.07088):
+ *
+ *   per-sublattice 3D FFTs of occupancy, spin and Taylor displacement-monomial
+ *   fields (Sec. III.B-D), recombined at the supercell Bragg points into the
+ *   Bragg-subtracted diffuse intensity I = <|F|^2> - |<F>|^2 (Sec. II Eq.
+ *   bragg_diffuse_sf; Sec. III Eqs. comp_diffuse_intensity,
+ *   disp_diffuse_intensity, mag_intensity), and the Lanczos windowed-sinc
+ *   noise filter (Sec. V.B).
+ *
+ * Conventions used by every call:
+ *   - Plain pointers and sizes only.  "Device" pointers are HIP device
+ *     allocations on the current device; "host" pointers are ordinary memory.
+ *   - Arrays are C order (last index fastest), float32 unless stated.
+ *   - Reciprocal-space points are integer supercell Bragg indices G (Eq. G_def):
+ *     G = (G1/n1) a* + (G2/n2) b* + (G3/n3) c*; g = G/n is the same point in
+ *     reciprocal-lattice units.  All transforms use the +i sign (Eqs. sf, fft).
+ *   - Every function returns DSX_OK (0) or a negative status.  Argument and
+ *     state errors return synchronously, enqueue nothing and leave the model
+ *     unchanged; dsx_last_error() then gives a message for the calling thread.
+ *   - A HIP failure inside a call returns DSX_ERR_DEVICE and marks the model
+ *     failed: every later call on it returns DSX_ERR_DEVICE.
+ *   - Distinct models may be used from different threads concurrently; one
+ *     model must not be used by two threads at once.
+ */
+#ifndef DSX_H
+#define DSX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dsx_model_s* dsx_model;   /* opaque, owned by the library */
+typedef int32_t dsx_status;
+
+enum {
+    DSX_OK = 0,
+    DSX_ERR_ARG = -1,          /* invalid argument                              */
+    DSX_ERR_STATE = -2,        /* call-order violation (e.g. sites not all set)  */
+    DSX_ERR_NOMEM = -3,        /* device or host allocation failed               */
+    DSX_ERR_DEVICE = -4,       /* HIP error; the model is now failed             */
+    DSX_ERR_UNSUPPORTED = -5,  /* valid but outside what this build implements   */
+    DSX_ERR_BUSY = -6          /* serving: admission refused and queue full      */
+};
+
+enum { DSX_NUCLEAR = 0, DSX_MAGNETIC = 1 };
+enum { DSX_HOST = 0, DSX_DEVICE = 1 };
+
+/* Largest supported values (DSX_ERR_UNSUPPORTED beyond them). */
+#define DSX_MAX_N        128   /* supercell edge n_alpha                         */
+#define DSX_MAX_SITES    64    /* species-sites per unit cell                    */
+#define DSX_MAX_ORDER    8     /* Taylor order of exp(i G.u)                     */
+
+/*
+ * Model description (Sec. II; Sec. III Eq. r_vec).  An atom of site mu at lattice
+ * point R sits at R + r_mu + u_{R,mu} (unit-cell coordinates) with occupancy
+ * delta_{R,mu}.  Only the pointers' contents are read, during dsx_create_model.
+ */
+typedef struct {
+    double  cell[6];        /* a, b, c [Angstrom]; alpha, beta, gamma [deg] (Sec. II: a* = 2 pi b x c / V) */
+    int32_t n[3];           /* supercell n1, n2, n3 (Eq. r_def), each in [1, DSX_MAX_N]                       */
+    int32_t n_sites;        /* species-sites (mu, i), in [1, DSX_MAX_SITES]; several may share a position     */
+    const double* frac;     /* [n_sites][3] average fractional positions r_mu (Eq. r_vec)                     */
+    const int32_t* pos_id;  /* [n_sites] position index used for the normalisation N, or NULL (= identity)   */
+    const double* b;        /* [n_sites] scattering length b_mu (nuclear) or moment scale (magnetic)         */
+    const double* ff;       /* [n_sites][7] magnetic form factor (A,a,B,b,C,c,D):                             */
+                            /*   f(s) = A e^{-a s^2} + B e^{-b s^2} + C e^{-c s^2} + D, s = |Q|/(4 pi);        */
+                            /*   NULL => f = 1.  Ignored for nuclear models.                                   */
+    int32_t kind;           /* DSX_NUCLEAR or DSX_MAGNETIC                                                    */
+    int32_t has_occ;        /* 0: delta == 1 everywhere (no occupancy array is read)                         */
+    int32_t taylor_order;   /* nuclear: order N of the expansion of exp(i G.u) (Sec. III.C, Eq.              */
+                            /*   disp_expansion), 0 = no displacements; magnetic: must be 0                  */
+    int32_t n_configs;      /* ensemble size M >= 1 (<.> is the mean over configurations)                    */
+    double  norm_N;         /* N of I = <|F|^2>/N (Eq. intensity_sf); 0 => n1 n2 n3 x distinct positions      */
+} dsx_model_desc;
+
+/*
+ * Host-only plan query: fills the sizes the model would use, without touching a
+ * GPU.  fields_per_site = number of real fields transformed per site and
+ * configuration: (N+1)(N+2)(N+3)/6 Taylor monomials (Sec. III.C: (n+1)(n+2)/2 per
+ * order n), minus the constant one when has_occ == 0; 3 spin components for
+ * magnetic models (Sec. III.D, Eq. mag_ft).  device_bytes = resident device
+ * memory of the model excluding output boxes.
+ */
+typedef struct {
+    int32_t fields_per_site;
+    int32_t total_fields;        /* n_configs x n_sites x fields_per_site          */
+    int32_t n_classes;           /* site groups sharing r_mu3 (and form factor)     */
+    int32_t reserved;
+    int64_t spectrum_bytes;      /* complex64 half spectra of all fields            */
+    int64_t device_bytes;
+} dsx_plan_info;
+
+dsx_status dsx_plan_query(const dsx_model_desc* d, dsx_plan_info* info);
+
+/*
+ * Create a model on the current HIP device and allocate its device state
+ * (inputs, spectra, FP64 sums).  *out receives the handle.  DSX_ERR_NOMEM when
+ * the device cannot hold it.
+ */
+dsx_status dsx_create_model(const dsx_model_desc* d, dsx_model* out);
+
+/*
+ * Set the variables of configuration `config` (0 <= config < n_configs).
+ *   occ  [n_sites][n1][n2][n3]     delta (read iff has_occ)
+ *   disp [n_sites][n1][n2][n3][3]  u in fractional unit-cell coordinates (read iff
+ *                                  nuclear and taylor_order > 0)
+ *   spin [n_sites][n1][n2][n3][3]  Cartesian moment M (read iff magnetic)
+ * Pointers not read may be NULL.  where = DSX_HOST or DSX_DEVICE for all three.
+ * The data are copied before return (the caller may free them at once).
+ */
+dsx_status dsx_set_sites(dsx_model m, int32_t config, const float* occ, const float* disp,
+                         const float* spin, int32_t where);
+
+/*
+ * Output box: the integer points G with g0[a] <= G_a < g0[a] + count[a], count >= 1.
+ */
+dsx_status dsx_set_grid(dsx_model m, const int32_t g0[3], const int32_t count[3]);
+
+/*
+ * I(G) on the box, float32 [count0][count1][count2]:
+ *   nuclear   I = (1/N) [ (1/M) sum_m |F_m|^2 - [G = 0 mod n] |(1/M) sum_m F_m|^2 ]
+ *             with F_m(G) = sum_{mu} b_mu e^{2 pi i g.r_mu} sum_{p+q+r<=N}
+ *             (2 pi i)^{p+q+r} g1^p g2^q g3^r / (p! q! r!) X^{pqr}_{m,mu}(k),
+ *             k = G mod n, X the +i FFT of delta u1^p u2^q u3^r (Sec. III.C, Eq.
+ *             total_sf_taylor, regrouped by monomial; Sec. III.B for N = 0);
+ *   magnetic  I = (C/N) [ (1/M) sum |F_perp|^2 - [G = 0 mod n] |(1/M) sum F_perp|^2 ],
+ *             F = sum_mu f_mu(|Q|) b_mu e^{2 pi i g.r_mu} M_{k,mu}, F_perp = F -
+ *             Ghat (Ghat . F), C = 0.07265 barn, I(0) = 0 (Sec. III.D).
+ * The points G = 0 (mod n) are evaluated in float64 from float64 lattice sums.
+ * out: device pointer (where = DSX_DEVICE; asynchronous on hip_stream, NULL = the
+ * null stream) or host pointer (where = DSX_HOST; synchronous).
+ * DSX_ERR_STATE unless every configuration's sites and the grid are set.
+ */
+dsx_status dsx_compute_intensity(dsx_model m, float* out, int32_t where, void* hip_stream);
+
+/*
+ * Lanczos resampling of I on the box (Sec. V.B, Eqs. intensity_convol_finite,
+ * windowed_sinc, lanczos): I(Q) = sum_G I(G) W(Q-G) / sum_G W(Q-G), W the product
+ * over axes of sinc(2 pi r_cut d) sinc(pi d/m) for |d| < m, r_cut = (1 - 1/m)/2,
+ * summed over floor(Q_a) - m + 1 <= G_a <= floor(Q_a) + m.  I(G) is computed
+ * internally on the box grown by the window (no clamping or wrapping).
+ * Output points Q_a = g0_a + i_a / s, i_a < s count_a; out float32
+ * [s count0][s count1][s count2], same `where` / stream rules as above.
+ * lanczos_m >= 2, oversample s >= 1.
+ */
+dsx_status dsx_noise_filter(dsx_model m, int32_t lanczos_m, int32_t oversample, float* out,
+                            int32_t where, void* hip_stream);
+
+/* Release a model and all its device memory (waits for its pending work). */
+dsx_status dsx_destroy_model(dsx_model m);
+
+/* Message for the last failed call on this thread ("" if none). Never NULL. */
+const char* dsx_last_error(void);
+
+/*
+ * Per-kernel timing (instrumentation; not part of the method).  While enabled,
+ * every kernel the library launches is bracketed by two HIP events recorded on
+ * the stream it runs on.  dsx_profile_read waits for the recorded events, folds
+ * them into per-kernel totals and copies at most `max` entries into `out`,
+ * returning the number of kernel kinds seen since the last reset.  Process-wide;
+ * safe to call from any thread.
+ */
+typedef struct {
+    char    name[32];      /* "sums", "fft_planes", "fft_axis1", "recombine", "bragg", "lanczos" */
+    int64_t launches;
+    double  total_ms;
+} dsx_kernel_stat;
+
+dsx_status dsx_profile_enable(int32_t on);
+int32_t    dsx_profile_read(dsx_kernel_stat* out, int32_t max);
+dsx_status dsx_profile_reset(void);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int32_t dsx_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DSX_H */

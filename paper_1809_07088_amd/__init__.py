@@ -1,0 +1,237 @@
+"""Python binding of the dsx C-ABI (include/dsx.h): argument marshalling only.
+
+Every step of the hot path runs in the gfx950 HIP library libdsx.so built in this
+package directory (``paper_1809_07088_amd.build.build()``).  There is no Python or
+CPU fallback: if the library is missing, loading it raises.
+
+Device memory and streams come from PyTorch: pass CUDA (HIP) tensors for
+device arrays and ``torch.cuda.current_stream()`` (the default) or any other
+stream; NumPy arrays are passed as host memory.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdsx.so")
+
+NUCLEAR, MAGNETIC = 0, 1
+HOST, DEVICE = 0, 1
+OK, ERR_ARG, ERR_STATE, ERR_NOMEM, ERR_DEVICE, ERR_UNSUPPORTED, ERR_BUSY = 0, -1, -2, -3, -4, -5, -6
+MAX_N, MAX_SITES, MAX_ORDER = 128, 64, 8
+
+
+class DsxError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"dsx status {status}: {message}")
+        self.status = status
+
+
+class ModelDesc(ctypes.Structure):
+    _fields_ = [("cell", ctypes.c_double * 6), ("n", ctypes.c_int32 * 3), ("n_sites", ctypes.c_int32),
+                ("frac", ctypes.c_void_p), ("pos_id", ctypes.c_void_p), ("b", ctypes.c_void_p),
+                ("ff", ctypes.c_void_p), ("kind", ctypes.c_int32), ("has_occ", ctypes.c_int32),
+                ("taylor_order", ctypes.c_int32), ("n_configs", ctypes.c_int32), ("norm_N", ctypes.c_double)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("fields_per_site", ctypes.c_int32), ("total_fields", ctypes.c_int32),
+                ("n_classes", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("spectrum_bytes", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
+
+
+EXPORTS = ("dsx_plan_query", "dsx_create_model", "dsx_set_sites", "dsx_set_grid",
+           "dsx_compute_intensity", "dsx_noise_filter", "dsx_destroy_model", "dsx_last_error",
+           "dsx_version", "dsx_profile_enable", "dsx_profile_read", "dsx_profile_reset")
+
+_lib = None
+
+
+def lib():
+    """Load libdsx.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_1809_07088_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32 = ctypes.c_void_p, ctypes.c_int32
+        L.dsx_plan_query.argtypes = [ctypes.POINTER(ModelDesc), ctypes.POINTER(PlanInfo)]
+        L.dsx_create_model.argtypes = [ctypes.POINTER(ModelDesc), ctypes.POINTER(P)]
+        L.dsx_set_sites.argtypes = [P, i32, P, P, P, i32]
+        L.dsx_set_grid.argtypes = [P, P, P]
+        L.dsx_compute_intensity.argtypes = [P, P, i32, P]
+        L.dsx_noise_filter.argtypes = [P, i32, i32, P, i32, P]
+        L.dsx_destroy_model.argtypes = [P]
+        L.dsx_last_error.argtypes = []
+        L.dsx_last_error.restype = ctypes.c_char_p
+        L.dsx_version.restype = i32
+        L.dsx_profile_enable.argtypes = [i32]
+        L.dsx_profile_enable.restype = i32
+        L.dsx_profile_read.argtypes = [P, i32]
+        L.dsx_profile_read.restype = i32
+        L.dsx_profile_reset.argtypes = []
+        L.dsx_profile_reset.restype = i32
+        for f in ("dsx_plan_query", "dsx_create_model", "dsx_set_sites", "dsx_set_grid",
+                  "dsx_compute_intensity", "dsx_noise_filter", "dsx_destroy_model"):
+            getattr(L, f).restype = i32
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().dsx_last_error().decode()
+
+
+def _check(status):
+    if status != OK:
+        raise DsxError(status, last_error())
+
+
+def _ptr_where(a):
+    """(pointer, where, keepalive) for a numpy array (host) or a torch tensor (device)."""
+    if a is None:
+        return None, None, None
+    if isinstance(a, np.ndarray):
+        a = np.ascontiguousarray(a, dtype=np.float32)
+        return a.ctypes.data, HOST, a
+    import torch
+    if isinstance(a, torch.Tensor):
+        if a.dtype != torch.float32 or not a.is_contiguous():
+            raise ValueError("device arrays must be contiguous float32 tensors")
+        return a.data_ptr(), (DEVICE if a.is_cuda else HOST), a
+    raise TypeError(f"unsupported array type {type(a)}")
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def make_desc(cell, n, frac, b, kind=NUCLEAR, taylor_order=0, n_configs=1, has_occ=False,
+              ff=None, pos_id=None, norm_N=0.0):
+    """A dsx_model_desc plus the arrays it points to (kept alive by the caller)."""
+    frac = np.ascontiguousarray(frac, dtype=np.float64).reshape(-1, 3)
+    b = np.ascontiguousarray(b, dtype=np.float64).reshape(-1)
+    ffa = None if ff is None else np.ascontiguousarray(ff, dtype=np.float64).reshape(-1, 7)
+    pid = None if pos_id is None else np.ascontiguousarray(pos_id, dtype=np.int32)
+    d = ModelDesc()
+    d.cell[:] = [float(v) for v in cell]
+    d.n[:] = [int(v) for v in n]
+    d.n_sites = frac.shape[0]
+    d.frac = frac.ctypes.data
+    d.b = b.ctypes.data
+    d.ff = None if ffa is None else ffa.ctypes.data
+    d.pos_id = None if pid is None else pid.ctypes.data
+    d.kind, d.has_occ, d.taylor_order = int(kind), int(bool(has_occ)), int(taylor_order)
+    d.n_configs, d.norm_N = int(n_configs), float(norm_N)
+    return d, (frac, b, ffa, pid)
+
+
+def plan_query(**kw) -> PlanInfo:
+    d, keep = make_desc(**kw)
+    info = PlanInfo()
+    _check(lib().dsx_plan_query(ctypes.byref(d), ctypes.byref(info)))
+    return info
+
+
+def create_model(**kw) -> int:
+    d, keep = make_desc(**kw)
+    h = ctypes.c_void_p()
+    _check(lib().dsx_create_model(ctypes.byref(d), ctypes.byref(h)))
+    return h.value
+
+
+def set_sites(model, config, occ=None, disp=None, spin=None):
+    ptrs = [_ptr_where(a) for a in (occ, disp, spin)]
+    wheres = {w for (_, w, _) in ptrs if w is not None}
+    if len(wheres) > 1:
+        raise ValueError("occ, disp and spin must all be host or all device arrays")
+    where = wheres.pop() if wheres else HOST
+    _check(lib().dsx_set_sites(model, int(config), ptrs[0][0], ptrs[1][0], ptrs[2][0], where))
+
+
+def set_grid(model, g0, count):
+    g = np.ascontiguousarray(g0, dtype=np.int32)
+    c = np.ascontiguousarray(count, dtype=np.int32)
+    _check(lib().dsx_set_grid(model, g.ctypes.data, c.ctypes.data))
+
+
+def compute_intensity(model, out, stream=None):
+    p, where, _ = _ptr_where(out)
+    st = _stream_handle(stream) if where == DEVICE else None
+    _check(lib().dsx_compute_intensity(model, p, where, st))
+    return out
+
+
+def noise_filter(model, lanczos_m, oversample, out, stream=None):
+    p, where, _ = _ptr_where(out)
+    st = _stream_handle(stream) if where == DEVICE else None
+    _check(lib().dsx_noise_filter(model, int(lanczos_m), int(oversample), p, where, st))
+    return out
+
+
+def destroy_model(model):
+    _check(lib().dsx_destroy_model(model))
+
+
+def version() -> int:
+    return int(lib().dsx_version())
+
+
+def profile_enable(on=True):
+    _check(lib().dsx_profile_enable(1 if on else 0))
+
+
+def profile_reset():
+    _check(lib().dsx_profile_reset())
+
+
+def profile_read() -> dict:
+    """{kernel name: (launches, total ms)} accumulated since the last reset."""
+    n = lib().dsx_profile_read(None, 0)
+    arr = (KernelStat * max(n, 1))()
+    n = lib().dsx_profile_read(ctypes.cast(arr, ctypes.c_void_p), n)
+    return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(n)}
+
+
+class Model:
+    """Convenience owner of one dsx model handle."""
+
+    def __init__(self, **kw):
+        self.desc_kw = dict(kw)
+        self.handle = create_model(**kw)
+
+    def set_sites(self, config, occ=None, disp=None, spin=None):
+        set_sites(self.handle, config, occ, disp, spin)
+
+    def set_grid(self, g0, count):
+        self.g0, self.count = tuple(int(v) for v in g0), tuple(int(v) for v in count)
+        set_grid(self.handle, g0, count)
+
+    def compute_intensity(self, out, stream=None):
+        return compute_intensity(self.handle, out, stream)
+
+    def noise_filter(self, lanczos_m, oversample, out, stream=None):
+        return noise_filter(self.handle, lanczos_m, oversample, out, stream)
+
+    def close(self):
+        if self.handle:
+            destroy_model(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,817 @@
+// Host runtime of the dsx C-ABI: model manager, planner and launch sequencing.
+//
+// A model owns its device state:
+//   inputs   occ [M][S][ncell], vec [M][S][ncell][3] (displacements or spins)
+//   sums     float64 lattice sums [M][S][T] (the k = 0 coefficients)
+//   spectra  complex64 k-major half spectra X [M][k1][k2][S*F][n3/2+1]
+//   tables   float64-generated phase tables for each output box in use
+// compute_intensity / noise_filter enqueue, on the caller's stream:
+//   sums -> plane FFTs (generation + axes 3, 2) -> axis-1 FFT    (when the sites changed)
+//   recombination over the box -> float64 Bragg points -> [Lanczos filter]
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "dsx.h"
+#include "dsx_internal.h"
+
+using namespace dsx;
+
+namespace {
+
+thread_local std::string g_err;
+
+void dfree(void* p) { if (p) (void)hipFree(p); }
+
+dsx_status fail(dsx_status s, const std::string& msg)
+{
+    g_err = msg;
+    return s;
+}
+
+// ---------------------------------------------------------------------------- instrumentation
+struct Prof {
+    std::mutex mu;
+    bool on = false;
+    struct Pending { std::string name; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    std::map<std::string, std::pair<long long, double>> stats;
+    hipEvent_t get() {
+        if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+};
+Prof g_prof;
+
+// Records an event before and after the launch `fn` on stream st when enabled.
+template <typename Fn>
+hipError_t timed(const char* name, hipStream_t st, Fn fn)
+{
+    if (!g_prof.on) return fn();
+    hipEvent_t a, b;
+    {
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        a = g_prof.get();
+        b = g_prof.get();
+    }
+    if (!a || !b) return fn();
+    hipError_t e = hipEventRecord(a, st);
+    if (e != hipSuccess) return e;
+    e = fn();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, st);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.pending.push_back({name, a, b});
+    return hipSuccess;
+}
+
+struct Box {
+    int g0[3];
+    int cnt[3];
+    bool operator<(const Box& o) const {
+        for (int a = 0; a < 3; ++a) {
+            if (g0[a] != o.g0[a]) return g0[a] < o.g0[a];
+            if (cnt[a] != o.cnt[a]) return cnt[a] < o.cnt[a];
+        }
+        return false;
+    }
+};
+
+long floordiv_l(long a, long b) { long q = a / b; if ((a % b) != 0 && a < 0) --q; return q; }
+long ceildiv_l(long a, long b) { return -floordiv_l(-a, b); }
+
+// H count of residue k on an axis (g0 <= k + n H < g0 + cnt)
+int hcount(int k, int n, int g0, int cnt)
+{
+    const long lo = ceildiv_l((long)g0 - k, n);
+    const long hi = floordiv_l((long)g0 + cnt - 1 - k, n);
+    return hi >= lo ? (int)(hi - lo + 1) : 0;
+}
+
+AxisPlan make_plan(int n)
+{
+    AxisPlan p{};
+    p.n = n;
+    int r = n;
+    while (r % 4 == 0) { p.rad[p.nrad++] = 4; r /= 4; }
+    while (r % 2 == 0) { p.rad[p.nrad++] = 2; r /= 2; }
+    for (int f : {3, 5}) while (r % f == 0) { p.rad[p.nrad++] = f; r /= f; }
+    for (int f = 7; r > 1; f += 2)
+        while (r % f == 0) { p.rad[p.nrad++] = f; r /= f; }
+    return p;
+}
+
+// Rows a*, b*, c* of the reciprocal basis (a* = 2 pi b x c / V), a along x and b in
+// the xy plane.  Returns false for an invalid cell.
+bool reciprocal_basis(const double cell[6], double out[9])
+{
+    const double d2r = M_PI / 180.0;
+    const double a = cell[0], b = cell[1], c = cell[2];
+    const double al = cell[3] * d2r, be = cell[4] * d2r, ga = cell[5] * d2r;
+    if (!(a > 0 && b > 0 && c > 0) || !(al > 0 && be > 0 && ga > 0 && al < M_PI && be < M_PI && ga < M_PI))
+        return false;
+    const double A[3] = {a, 0.0, 0.0};
+    const double B[3] = {b * std::cos(ga), b * std::sin(ga), 0.0};
+    const double cx = c * std::cos(be);
+    const double cy = c * (std::cos(al) - std::cos(be) * std::cos(ga)) / std::sin(ga);
+    const double cz2 = c * c - cx * cx - cy * cy;
+    if (!(cz2 > 0)) return false;
+    const double C[3] = {cx, cy, std::sqrt(cz2)};
+    auto cross = [](const double* u, const double* v, double* w) {
+        w[0] = u[1] * v[2] - u[2] * v[1];
+        w[1] = u[2] * v[0] - u[0] * v[2];
+        w[2] = u[0] * v[1] - u[1] * v[0];
+    };
+    double bc[3], ca[3], ab[3];
+    cross(B, C, bc); cross(C, A, ca); cross(A, B, ab);
+    const double V = A[0] * bc[0] + A[1] * bc[1] + A[2] * bc[2];
+    if (!(V > 0)) return false;
+    for (int i = 0; i < 3; ++i) {
+        out[i] = 2 * M_PI * bc[i] / V;
+        out[3 + i] = 2 * M_PI * ca[i] / V;
+        out[6 + i] = 2 * M_PI * ab[i] / V;
+    }
+    return true;
+}
+
+float2 cis(double x)   // e^{2 pi i x}, argument reduced mod 1 in float64 first
+{
+    x -= std::floor(x);
+    return make_float2((float)std::cos(2 * M_PI * x), (float)std::sin(2 * M_PI * x));
+}
+
+struct DeviceTables {
+    float2* tab1 = nullptr;
+    float2* tab2 = nullptr;
+    float2* tabK3 = nullptr;
+    float2* tabH3 = nullptr;
+    int H3min = 0, nH3span = 0;
+};
+
+struct LaunchPlan {
+    RecombParams rp;
+    int hc = 0, block = 0;
+    size_t lds = 0;
+    BraggParams bp;
+};
+
+}  // namespace
+
+struct dsx_model_s {
+    // description
+    double cell[6];
+    int n[3];
+    int S, kind, has_occ, order, M;
+    double normN;
+    std::vector<double> frac, b, ff;
+    bool has_ff = false;
+    double recip[9];
+    // plan
+    int F = 0, T = 0, first_mono = 0, nh = 0, SF = 0, ncell = 0, nclass = 0;
+    std::vector<int> site_of, class_of;     // class-sorted site order
+    std::vector<int> sc_start;              // site chunks for the recombination LDS budget
+    size_t chunk_lds = 0;
+    AxisPlan plan[3];
+    // device state
+    int device = 0;
+    float* d_occ = nullptr;
+    float* d_vec = nullptr;
+    double* d_partial = nullptr;
+    double* d_sums = nullptr;
+    double* d_site = nullptr;   // [S][11]: r_mu, b_mu, form factor
+    float2* d_X = nullptr;
+    float2* d_tw[3] = {nullptr, nullptr, nullptr};
+    float* d_ext = nullptr;   size_t ext_cap = 0;
+    float* d_stage = nullptr; size_t stage_cap = 0;
+    std::map<Box, DeviceTables> tables;
+    std::map<std::pair<int, int>, float*> lanczos_w;
+    int sum_chunks = 0;
+    // state
+    std::vector<char> set;
+    bool dirty = true;
+    bool failed = false;
+    bool grid_set = false;
+    Box box{};
+    hipStream_t last_stream = nullptr;
+};
+
+namespace {
+
+#define HIPCHK(m, expr)                                                                        \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) {                                                                \
+            if (m) (m)->failed = true;                                                         \
+            return fail(DSX_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));   \
+        }                                                                                      \
+    } while (0)
+
+dsx_status validate_desc(const dsx_model_desc* d)
+{
+    if (!d) return fail(DSX_ERR_ARG, "desc is NULL");
+    for (int a = 0; a < 3; ++a)
+        if (d->n[a] < 1) return fail(DSX_ERR_ARG, "n must be >= 1");
+    for (int a = 0; a < 3; ++a)
+        if (d->n[a] > DSX_MAX_N) return fail(DSX_ERR_UNSUPPORTED, "n exceeds DSX_MAX_N");
+    if (d->n_sites < 1) return fail(DSX_ERR_ARG, "n_sites must be >= 1");
+    if (d->n_sites > DSX_MAX_SITES) return fail(DSX_ERR_UNSUPPORTED, "n_sites exceeds DSX_MAX_SITES");
+    if (!d->frac || !d->b) return fail(DSX_ERR_ARG, "frac and b are required");
+    if (d->kind != DSX_NUCLEAR && d->kind != DSX_MAGNETIC) return fail(DSX_ERR_ARG, "bad kind");
+    if (d->taylor_order < 0) return fail(DSX_ERR_ARG, "taylor_order must be >= 0");
+    if (d->kind == DSX_MAGNETIC && d->taylor_order != 0)
+        return fail(DSX_ERR_UNSUPPORTED, "magnetic models take no Taylor order");
+    if (d->taylor_order > DSX_MAX_ORDER) return fail(DSX_ERR_UNSUPPORTED, "taylor_order exceeds DSX_MAX_ORDER");
+    if (d->n_configs < 1) return fail(DSX_ERR_ARG, "n_configs must be >= 1");
+    if (!(d->norm_N >= 0.0)) return fail(DSX_ERR_ARG, "norm_N must be >= 0");
+    if (d->kind == DSX_NUCLEAR && d->taylor_order == 0 && !d->has_occ)
+        return fail(DSX_ERR_ARG, "a nuclear model needs occupancies or displacements");
+    double rb[9];
+    if (!reciprocal_basis(d->cell, rb)) return fail(DSX_ERR_ARG, "invalid cell");
+    for (int i = 0; i < 3 * d->n_sites; ++i)
+        if (!std::isfinite(d->frac[i])) return fail(DSX_ERR_ARG, "non-finite site position");
+    return DSX_OK;
+}
+
+// Sizes shared by plan_query and create_model.
+struct Sizes {
+    int F, T, first_mono, nh, ncell, nclass;
+    long long spectrum_bytes, device_bytes;
+};
+
+int count_classes(const dsx_model_desc* d, std::vector<int>* site_of, std::vector<int>* class_of)
+{
+    // group sites sharing r_mu3 (and, for magnetic models, the form factor)
+    std::vector<int> cls(d->n_sites, -1);
+    int nc = 0;
+    for (int i = 0; i < d->n_sites; ++i) {
+        if (cls[i] >= 0) continue;
+        cls[i] = nc;
+        for (int j = i + 1; j < d->n_sites; ++j) {
+            if (cls[j] >= 0) continue;
+            bool same = d->frac[3 * i + 2] == d->frac[3 * j + 2];
+            if (same && d->kind == DSX_MAGNETIC && d->ff)
+                for (int k = 0; k < 7; ++k) same = same && d->ff[7 * i + k] == d->ff[7 * j + k];
+            if (same) cls[j] = nc;
+        }
+        ++nc;
+    }
+    if (site_of && class_of) {
+        site_of->clear(); class_of->clear();
+        for (int c = 0; c < nc; ++c)
+            for (int i = 0; i < d->n_sites; ++i)
+                if (cls[i] == c) { site_of->push_back(i); class_of->push_back(c); }
+    }
+    return nc;
+}
+
+Sizes sizes_of(const dsx_model_desc* d)
+{
+    Sizes z{};
+    z.ncell = d->n[0] * d->n[1] * d->n[2];
+    z.nh = d->n[2] / 2 + 1;
+    if (d->kind == DSX_MAGNETIC) { z.T = 3; z.F = 3; z.first_mono = 0; }
+    else {
+        z.T = n_monomials(d->taylor_order);
+        z.first_mono = d->has_occ ? 0 : 1;
+        z.F = z.T - z.first_mono;
+    }
+    z.nclass = count_classes(d, nullptr, nullptr);
+    const long long M = d->n_configs, S = d->n_sites;
+    z.spectrum_bytes = M * d->n[0] * d->n[1] * S * z.F * (long long)z.nh * 8;
+    long long in = 0;
+    if (d->has_occ) in += M * S * z.ncell * 4;
+    if (d->kind == DSX_MAGNETIC || d->taylor_order > 0) in += M * S * z.ncell * 12;
+    const long long chunks = (z.ncell + 255) / 256;
+    z.device_bytes = z.spectrum_bytes + in + M * S * z.T * 8 * (chunks + 1);
+    return z;
+}
+
+dsx_status check_model(dsx_model m)
+{
+    if (!m) return fail(DSX_ERR_ARG, "model is NULL");
+    if (m->failed) return fail(DSX_ERR_DEVICE, "model is in a failed state after a device error");
+    return DSX_OK;
+}
+
+void free_model(dsx_model m)
+{
+    dfree(m->d_occ); dfree(m->d_vec); dfree(m->d_partial); dfree(m->d_sums); dfree(m->d_X);
+    dfree(m->d_site);
+    for (auto& t : m->d_tw) dfree(t);
+    dfree(m->d_ext); dfree(m->d_stage);
+    for (auto& kv : m->tables) {
+        dfree(kv.second.tab1); dfree(kv.second.tab2); dfree(kv.second.tabK3); dfree(kv.second.tabH3);
+    }
+    for (auto& kv : m->lanczos_w) dfree(kv.second);
+}
+
+dsx_status tables_for(dsx_model m, const Box& bx, DeviceTables** out)
+{
+    auto it = m->tables.find(bx);
+    if (it != m->tables.end()) { *out = &it->second; return DSX_OK; }
+    if (m->tables.size() >= 8) {   // keep the cache small: drop every cached box
+        hipError_t se = hipStreamSynchronize(m->last_stream);
+        if (se != hipSuccess) { m->failed = true; return fail(DSX_ERR_DEVICE, hipGetErrorString(se)); }
+        for (auto& kv : m->tables) {
+            dfree(kv.second.tab1); dfree(kv.second.tab2); dfree(kv.second.tabK3); dfree(kv.second.tabH3);
+        }
+        m->tables.clear();
+    }
+    DeviceTables t;
+    const int S = m->S, n1 = m->n[0], n2 = m->n[1], n3 = m->n[2];
+    std::vector<float2> t1((size_t)S * bx.cnt[0]), t2((size_t)S * bx.cnt[1]), tk((size_t)S * n3);
+    for (int mu = 0; mu < S; ++mu) {
+        for (int i = 0; i < bx.cnt[1]; ++i)
+            t2[(size_t)mu * bx.cnt[1] + i] = cis((double)(bx.g0[1] + i) / n2 * m->frac[3 * mu + 1]);
+        for (int k = 0; k < n3; ++k)
+            tk[(size_t)mu * n3 + k] = cis((double)k / n3 * m->frac[3 * mu + 2]);
+    }
+    // b folded in tab1 must be computed in float64 before rounding
+    for (int mu = 0; mu < S; ++mu)
+        for (int i = 0; i < bx.cnt[0]; ++i) {
+            double x = (double)(bx.g0[0] + i) / n1 * m->frac[3 * mu];
+            x -= std::floor(x);
+            t1[(size_t)mu * bx.cnt[0] + i] = make_float2((float)(m->b[mu] * std::cos(2 * M_PI * x)),
+                                                         (float)(m->b[mu] * std::sin(2 * M_PI * x)));
+        }
+    t.H3min = (int)floordiv_l(bx.g0[2], n3);
+    const int H3max = (int)floordiv_l((long)bx.g0[2] + bx.cnt[2] - 1, n3);
+    t.nH3span = H3max - t.H3min + 1;
+    std::vector<float2> th((size_t)m->nclass * t.nH3span);
+    for (int c = 0; c < m->nclass; ++c) {
+        int mu = -1;
+        for (size_t i = 0; i < m->site_of.size(); ++i)
+            if (m->class_of[i] == c) { mu = m->site_of[i]; break; }
+        for (int h = 0; h < t.nH3span; ++h)
+            th[(size_t)c * t.nH3span + h] = cis((double)(t.H3min + h) * m->frac[3 * mu + 2]);
+    }
+    auto up = [&](float2** dst, const std::vector<float2>& src) -> hipError_t {
+        hipError_t e = hipMalloc(dst, sizeof(float2) * std::max<size_t>(1, src.size()));
+        if (e != hipSuccess) return e;
+        return hipMemcpy(*dst, src.data(), sizeof(float2) * src.size(), hipMemcpyHostToDevice);
+    };
+    hipError_t e;
+    if ((e = up(&t.tab1, t1)) != hipSuccess || (e = up(&t.tab2, t2)) != hipSuccess ||
+        (e = up(&t.tabK3, tk)) != hipSuccess || (e = up(&t.tabH3, th)) != hipSuccess) {
+        dfree(t.tab1); dfree(t.tab2); dfree(t.tabK3); dfree(t.tabH3);
+        if (e == hipErrorOutOfMemory) return fail(DSX_ERR_NOMEM, "out of device memory for phase tables");
+        m->failed = true;
+        return fail(DSX_ERR_DEVICE, std::string("phase tables: ") + hipGetErrorString(e));
+    }
+    auto ins = m->tables.emplace(bx, t);
+    *out = &ins.first->second;
+    return DSX_OK;
+}
+
+dsx_status plan_recombine(dsx_model m, const Box& bx, float* out, LaunchPlan& lp)
+{
+    DeviceTables* tb = nullptr;
+    dsx_status st = tables_for(m, bx, &tb);
+    if (st != DSX_OK) return st;
+    const int n1 = m->n[0], n2 = m->n[1], n3 = m->n[2];
+    const bool mag = m->kind == DSX_MAGNETIC;
+    RecombParams& p = lp.rp;
+    std::memset(&p, 0, sizeof(p));
+    p.X = m->d_X; p.out = out;
+    p.tab1 = tb->tab1; p.tab2 = tb->tab2; p.tabK3 = tb->tabK3; p.tabH3 = tb->tabH3;
+    p.n1 = n1; p.n2 = n2; p.n3 = n3; p.nh = m->nh; p.S = m->S; p.SF = m->SF; p.F = m->F; p.M = m->M;
+    p.first_mono = m->first_mono;
+    for (int a = 0; a < 3; ++a) { p.g0[a] = bx.g0[a]; p.cnt[a] = bx.cnt[a]; }
+    p.H3min = tb->H3min; p.nH3span = tb->nH3span;
+    int maxH1 = 0, maxH2 = 0, maxH3 = 0;
+    for (int k = 0; k < n1; ++k) maxH1 = std::max(maxH1, hcount(k, n1, bx.g0[0], bx.cnt[0]));
+    for (int k = 0; k < n2; ++k) maxH2 = std::max(maxH2, hcount(k, n2, bx.g0[1], bx.cnt[1]));
+    for (int k = 0; k < n3; ++k) maxH3 = std::max(maxH3, hcount(k, n3, bx.g0[2], bx.cnt[2]));
+    const int hcs_nuc[4] = {4, 8, 17, 32};
+    const int hcs_mag[3] = {4, 8, 17};
+    const int* hcs = mag ? hcs_mag : hcs_nuc;
+    const int nhcs = mag ? 3 : 4;
+    int hc = hcs[nhcs - 1];
+    for (int i = 0; i < nhcs; ++i) if (hcs[i] >= maxH3) { hc = hcs[i]; break; }
+    p.nchunk3 = (maxH3 + hc - 1) / hc;
+    const int maxT = recombine_max_threads(hc, mag);
+    const int per_h2 = n3 * p.nchunk3;
+    if (per_h2 > maxT) return fail(DSX_ERR_UNSUPPORTED, "output box too long along axis 3 for this supercell");
+    p.h2per = std::max(1, std::min(maxH2, maxT / per_h2));
+    p.nparts = (maxH2 + p.h2per - 1) / p.h2per;
+    p.maxH1 = maxH1;
+    const long long nb = (long long)n1 * n2 * maxH1 * p.nparts;
+    if (nb > (1LL << 30)) return fail(DSX_ERR_UNSUPPORTED, "output box too large");
+    p.nblocks = (int)nb;
+    p.nsc = (int)m->sc_start.size() - 1;
+    for (size_t i = 0; i < m->sc_start.size(); ++i) p.sc_start[i] = m->sc_start[i];
+    for (int i = 0; i < m->S; ++i) { p.site_of[i] = m->site_of[i]; p.class_of[i] = m->class_of[i]; }
+    const double C = mag ? 0.07265 : 1.0;
+    p.scale = (float)(C / (m->normN * m->M));
+    for (int i = 0; i < 9; ++i) p.recip[i] = (float)m->recip[i];
+    p.ff_uniform = 1;
+    for (int i = 0; i < m->S; ++i) {
+        const int mu = m->site_of[i];
+        for (int k = 0; k < 7; ++k) {
+            p.ff[i][k] = m->has_ff ? (float)m->ff[7 * mu + k] : (k == 6 ? 1.f : 0.f);
+            if (m->has_ff && m->ff[7 * mu + k] != m->ff[k]) p.ff_uniform = 0;
+        }
+    }
+    lp.hc = hc;
+    lp.block = ((std::min(maxT, p.h2per * per_h2) + 63) / 64) * 64;
+    lp.lds = m->chunk_lds;
+
+    BraggParams& q = lp.bp;
+    std::memset(&q, 0, sizeof(q));
+    q.sums = m->d_sums; q.out = out;
+    for (int a = 0; a < 3; ++a) {
+        q.g0[a] = bx.g0[a]; q.cnt[a] = bx.cnt[a]; q.n[a] = m->n[a];
+        q.Hlo[a] = (int)ceildiv_l(bx.g0[a], m->n[a]);
+        const int hi = (int)floordiv_l((long)bx.g0[a] + bx.cnt[a] - 1, m->n[a]);
+        q.nH[a] = std::max(0, hi - q.Hlo[a] + 1);
+    }
+    q.S = m->S; q.T = m->T; q.M = m->M; q.kind = m->kind;
+    q.scale = C / m->normN;
+    q.site = m->d_site;
+    for (int i = 0; i < 9; ++i) q.recip[i] = m->recip[i];
+    q.has_ff = m->has_ff ? 1 : 0;
+    return DSX_OK;
+}
+
+dsx_status ensure_spectra(dsx_model m, hipStream_t st)
+{
+    if (!m->dirty) return DSX_OK;
+    SumsParams sp{};
+    sp.occ = m->has_occ ? m->d_occ : nullptr;
+    sp.vec = m->d_vec;
+    sp.partial = m->d_partial; sp.sums = m->d_sums;
+    sp.M = m->M; sp.S = m->S; sp.ncell = m->ncell; sp.T = m->T; sp.kind = m->kind;
+    sp.chunk = 256; sp.nchunk = m->sum_chunks;
+    HIPCHK(m, timed("sums", st, [&] { return launch_sums(sp, m->order, st); }));
+
+    PlaneParams pp;
+    std::memset(&pp, 0, sizeof(pp));
+    pp.occ = sp.occ; pp.vec = m->d_vec; pp.sums = m->d_sums; pp.X = m->d_X;
+    pp.tw2 = m->d_tw[1]; pp.tw3 = m->d_tw[2];
+    pp.p2 = m->plan[1]; pp.p3 = m->plan[2];
+    pp.n1 = m->n[0]; pp.n2 = m->n[1]; pp.n3 = m->n[2]; pp.nh = m->nh;
+    pp.S = m->S; pp.F = m->F; pp.T = m->T; pp.M = m->M; pp.kind = m->kind; pp.first_mono = m->first_mono;
+    const long long planes = (long long)m->M * m->S * m->n[0];
+    pp.fchunk = (int)std::max<long long>(1, std::min<long long>(m->F, planes * m->F / 8192));
+    pp.nfchunk = (m->F + pp.fchunk - 1) / pp.fchunk;
+    const int npairs = (m->n[1] + 1) / 2;
+    pp.buf_elems = std::max(npairs * m->n[2], m->n[1] * m->nh);
+    if (m->kind == DSX_NUCLEAR) {
+        int t = 0;
+        for (int d = 0; d <= m->order; ++d)
+            for (int p = d; p >= 0; --p)
+                for (int q = d - p; q >= 0; --q) {
+                    pp.mono[3 * t] = (int8_t)p; pp.mono[3 * t + 1] = (int8_t)q; pp.mono[3 * t + 2] = (int8_t)(d - p - q);
+                    ++t;
+                }
+    }
+    HIPCHK(m, timed("fft_planes", st, [&] { return launch_fft_planes(pp, st); }));
+
+    Axis1Params ap{};
+    ap.X = m->d_X; ap.tw1 = m->d_tw[0]; ap.p1 = m->plan[0];
+    ap.n1 = m->n[0]; ap.n2 = m->n[1]; ap.cols = m->SF * m->nh; ap.M = m->M;
+    ap.tc = m->n[0] <= 64 ? 64 : 32;
+    ap.ncolblk = (ap.cols + ap.tc - 1) / ap.tc;
+    HIPCHK(m, timed("fft_axis1", st, [&] { return launch_fft_axis1(ap, st); }));
+    m->dirty = false;
+    return DSX_OK;
+}
+
+dsx_status run_box(dsx_model m, const Box& bx, float* dout, hipStream_t st)
+{
+    LaunchPlan lp;
+    dsx_status s = plan_recombine(m, bx, dout, lp);
+    if (s != DSX_OK) return s;
+    if (m->kind == DSX_MAGNETIC)
+        HIPCHK(m, timed("recombine", st, [&] { return launch_recombine_magnetic(lp.rp, lp.hc, lp.block, lp.lds, st); }));
+    else
+        HIPCHK(m, timed("recombine", st, [&] { return launch_recombine_nuclear(lp.rp, m->order, lp.hc, lp.block, lp.lds, st); }));
+    HIPCHK(m, timed("bragg", st, [&] { return launch_bragg(lp.bp, m->order, st); }));
+    return DSX_OK;
+}
+
+dsx_status ready(dsx_model m)
+{
+    for (int c = 0; c < m->M; ++c)
+        if (!m->set[c]) return fail(DSX_ERR_STATE, "configuration " + std::to_string(c) + " has no sites set");
+    if (!m->grid_set) return fail(DSX_ERR_STATE, "no output grid set");
+    return DSX_OK;
+}
+
+dsx_status stage(dsx_model m, size_t elems, float** p)
+{
+    if (m->stage_cap < elems) {
+        dfree(m->d_stage);
+        m->d_stage = nullptr; m->stage_cap = 0;
+        hipError_t e = hipMalloc(&m->d_stage, elems * sizeof(float));
+        if (e == hipErrorOutOfMemory) return fail(DSX_ERR_NOMEM, "out of device memory for the host output staging");
+        HIPCHK(m, e);
+        m->stage_cap = elems;
+    }
+    *p = m->d_stage;
+    return DSX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t dsx_version(void) { return 100; }
+
+dsx_status dsx_profile_enable(int32_t on)
+{
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.on = on != 0;
+    return DSX_OK;
+}
+
+int32_t dsx_profile_read(dsx_kernel_stat* out, int32_t max)
+{
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    for (auto& p : g_prof.pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            auto& s = g_prof.stats[p.name];
+            s.first += 1;
+            s.second += ms;
+        }
+        g_prof.pool.push_back(p.a);
+        g_prof.pool.push_back(p.b);
+    }
+    g_prof.pending.clear();
+    int32_t i = 0;
+    for (auto& kv : g_prof.stats) {
+        if (out && i < max) {
+            std::memset(out[i].name, 0, sizeof(out[i].name));
+            std::strncpy(out[i].name, kv.first.c_str(), sizeof(out[i].name) - 1);
+            out[i].launches = kv.second.first;
+            out[i].total_ms = kv.second.second;
+        }
+        ++i;
+    }
+    return i;
+}
+
+dsx_status dsx_profile_reset(void)
+{
+    dsx_profile_read(nullptr, 0);
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.stats.clear();
+    return DSX_OK;
+}
+
+const char* dsx_last_error(void) { return g_err.c_str(); }
+
+dsx_status dsx_plan_query(const dsx_model_desc* d, dsx_plan_info* info)
+{
+    dsx_status s = validate_desc(d);
+    if (s != DSX_OK) return s;
+    if (!info) return fail(DSX_ERR_ARG, "info is NULL");
+    const Sizes z = sizes_of(d);
+    info->fields_per_site = z.F;
+    info->total_fields = d->n_configs * d->n_sites * z.F;
+    info->n_classes = z.nclass;
+    info->reserved = 0;
+    info->spectrum_bytes = z.spectrum_bytes;
+    info->device_bytes = z.device_bytes;
+    return DSX_OK;
+}
+
+dsx_status dsx_create_model(const dsx_model_desc* d, dsx_model* out)
+{
+    dsx_status s = validate_desc(d);
+    if (s != DSX_OK) return s;
+    if (!out) return fail(DSX_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    dsx_model m = new (std::nothrow) dsx_model_s();
+    if (!m) return fail(DSX_ERR_NOMEM, "host allocation failed");
+    std::memcpy(m->cell, d->cell, sizeof(m->cell));
+    for (int a = 0; a < 3; ++a) m->n[a] = d->n[a];
+    m->S = d->n_sites; m->kind = d->kind; m->has_occ = d->has_occ ? 1 : 0;
+    m->order = d->kind == DSX_NUCLEAR ? d->taylor_order : 0;
+    m->M = d->n_configs;
+    m->frac.assign(d->frac, d->frac + 3 * m->S);
+    m->b.assign(d->b, d->b + m->S);
+    m->has_ff = d->kind == DSX_MAGNETIC && d->ff != nullptr;
+    if (m->has_ff) m->ff.assign(d->ff, d->ff + 7 * m->S);
+    reciprocal_basis(m->cell, m->recip);
+    int npos = m->S;
+    if (d->pos_id) {
+        std::vector<int> ids(d->pos_id, d->pos_id + m->S);
+        std::sort(ids.begin(), ids.end());
+        npos = (int)(std::unique(ids.begin(), ids.end()) - ids.begin());
+    }
+    const Sizes z = sizes_of(d);
+    m->ncell = z.ncell; m->nh = z.nh; m->F = z.F; m->T = z.T; m->first_mono = z.first_mono;
+    m->SF = m->S * m->F;
+    m->normN = d->norm_N > 0 ? d->norm_N : (double)m->ncell * npos;
+    m->nclass = count_classes(d, &m->site_of, &m->class_of);
+    // site chunks for the recombination's LDS budget
+    const size_t per_site = sizeof(float2) * (size_t)(m->kind == DSX_MAGNETIC ? 3 : n_pairs(m->order)) * m->n[2];
+    const size_t budget = 64 * 1024;
+    const int per_chunk = (int)std::max<size_t>(1, budget / per_site);
+    m->sc_start.clear();
+    for (int i = 0; i < m->S; i += per_chunk) m->sc_start.push_back(i);
+    m->sc_start.push_back(m->S);
+    m->chunk_lds = per_site * (size_t)std::min(per_chunk, m->S);
+    for (int a = 0; a < 3; ++a) m->plan[a] = make_plan(m->n[a]);
+    m->set.assign(m->M, 0);
+    (void)hipGetDevice(&m->device);
+
+    auto alloc = [&](void** p, size_t bytes) -> hipError_t { return hipMalloc(p, std::max<size_t>(bytes, 16)); };
+    const size_t M = m->M, S = m->S, nc = m->ncell;
+    m->sum_chunks = (m->ncell + 255) / 256;
+    hipError_t e = hipSuccess;
+    if (m->has_occ && e == hipSuccess) e = alloc((void**)&m->d_occ, M * S * nc * sizeof(float));
+    if ((m->kind == DSX_MAGNETIC || m->order > 0) && e == hipSuccess)
+        e = alloc((void**)&m->d_vec, M * S * nc * 3 * sizeof(float));
+    if (e == hipSuccess) e = alloc((void**)&m->d_partial, M * S * m->sum_chunks * m->T * sizeof(double));
+    if (e == hipSuccess) e = alloc((void**)&m->d_sums, M * S * m->T * sizeof(double));
+    if (e == hipSuccess) e = alloc((void**)&m->d_X, (size_t)z.spectrum_bytes);
+    if (e == hipSuccess) {
+        std::vector<double> site((size_t)m->S * 11, 0.0);
+        for (int mu = 0; mu < m->S; ++mu) {
+            for (int a = 0; a < 3; ++a) site[11 * mu + a] = m->frac[3 * mu + a];
+            site[11 * mu + 3] = m->b[mu];
+            for (int k = 0; k < 7; ++k) site[11 * mu + 4 + k] = m->has_ff ? m->ff[7 * mu + k] : 0.0;
+        }
+        e = alloc((void**)&m->d_site, site.size() * sizeof(double));
+        if (e == hipSuccess)
+            e = hipMemcpy(m->d_site, site.data(), site.size() * sizeof(double), hipMemcpyHostToDevice);
+    }
+    for (int a = 0; a < 3 && e == hipSuccess; ++a) {
+        const int n = m->n[a];
+        std::vector<float2> tw(n);
+        for (int t = 0; t < n; ++t) tw[t] = cis((double)t / n);
+        e = alloc((void**)&m->d_tw[a], sizeof(float2) * n);
+        if (e == hipSuccess) e = hipMemcpy(m->d_tw[a], tw.data(), sizeof(float2) * n, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        free_model(m);
+        delete m;
+        (void)hipGetLastError();
+        if (e == hipErrorOutOfMemory) return fail(DSX_ERR_NOMEM, "out of device memory for the model");
+        return fail(DSX_ERR_DEVICE, std::string("create_model: ") + hipGetErrorString(e));
+    }
+    *out = m;
+    return DSX_OK;
+}
+
+dsx_status dsx_set_sites(dsx_model m, int32_t config, const float* occ, const float* disp,
+                         const float* spin, int32_t where)
+{
+    dsx_status s = check_model(m);
+    if (s != DSX_OK) return s;
+    if (config < 0 || config >= m->M) return fail(DSX_ERR_ARG, "config out of range");
+    if (where != DSX_HOST && where != DSX_DEVICE) return fail(DSX_ERR_ARG, "bad 'where'");
+    if (m->has_occ && !occ) return fail(DSX_ERR_ARG, "occ is required (has_occ != 0)");
+    const float* vec = m->kind == DSX_MAGNETIC ? spin : disp;
+    const bool need_vec = m->kind == DSX_MAGNETIC || m->order > 0;
+    if (need_vec && !vec)
+        return fail(DSX_ERR_ARG, m->kind == DSX_MAGNETIC ? "spin is required" : "disp is required (taylor_order > 0)");
+    HIPCHK(m, hipStreamSynchronize(m->last_stream));   // no pending work still reads the inputs
+    const hipMemcpyKind kind = where == DSX_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    const size_t per = (size_t)m->S * m->ncell;
+    if (m->has_occ) HIPCHK(m, hipMemcpy(m->d_occ + per * config, occ, per * sizeof(float), kind));
+    if (need_vec) HIPCHK(m, hipMemcpy(m->d_vec + 3 * per * config, vec, 3 * per * sizeof(float), kind));
+    if (where == DSX_DEVICE) HIPCHK(m, hipStreamSynchronize(nullptr));
+    m->set[config] = 1;
+    m->dirty = true;
+    return DSX_OK;
+}
+
+dsx_status dsx_set_grid(dsx_model m, const int32_t g0[3], const int32_t count[3])
+{
+    dsx_status s = check_model(m);
+    if (s != DSX_OK) return s;
+    if (!g0 || !count) return fail(DSX_ERR_ARG, "g0 and count are required");
+    Box bx;
+    long long vox = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (count[a] < 1) return fail(DSX_ERR_ARG, "count must be >= 1 on every axis");
+        if (std::llabs((long long)g0[a]) > (1LL << 24) || count[a] > (1 << 24))
+            return fail(DSX_ERR_UNSUPPORTED, "box coordinates too large");
+        bx.g0[a] = g0[a]; bx.cnt[a] = count[a];
+        vox *= count[a];
+    }
+    if (vox > (1LL << 34)) return fail(DSX_ERR_UNSUPPORTED, "box too large");
+    m->box = bx;
+    m->grid_set = true;
+    return DSX_OK;
+}
+
+dsx_status dsx_compute_intensity(dsx_model m, float* out, int32_t where, void* hip_stream)
+{
+    dsx_status s = check_model(m);
+    if (s != DSX_OK) return s;
+    if (!out) return fail(DSX_ERR_ARG, "out is NULL");
+    if (where != DSX_HOST && where != DSX_DEVICE) return fail(DSX_ERR_ARG, "bad 'where'");
+    if ((s = ready(m)) != DSX_OK) return s;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const size_t vox = (size_t)m->box.cnt[0] * m->box.cnt[1] * m->box.cnt[2];
+    float* dout = out;
+    if (where == DSX_HOST && (s = stage(m, vox, &dout)) != DSX_OK) return s;
+    m->last_stream = st;
+    if ((s = ensure_spectra(m, st)) != DSX_OK) return s;
+    if ((s = run_box(m, m->box, dout, st)) != DSX_OK) return s;
+    if (where == DSX_HOST) {
+        HIPCHK(m, hipMemcpyAsync(out, dout, vox * sizeof(float), hipMemcpyDeviceToHost, st));
+        HIPCHK(m, hipStreamSynchronize(st));
+    }
+    return DSX_OK;
+}
+
+dsx_status dsx_noise_filter(dsx_model m, int32_t lanczos_m, int32_t oversample, float* out,
+                            int32_t where, void* hip_stream)
+{
+    dsx_status s = check_model(m);
+    if (s != DSX_OK) return s;
+    if (!out) return fail(DSX_ERR_ARG, "out is NULL");
+    if (where != DSX_HOST && where != DSX_DEVICE) return fail(DSX_ERR_ARG, "bad 'where'");
+    if (lanczos_m < 2) return fail(DSX_ERR_ARG, "lanczos_m must be >= 2");
+    if (oversample < 1) return fail(DSX_ERR_ARG, "oversample must be >= 1");
+    if (lanczos_m > 16 || oversample > 16) return fail(DSX_ERR_UNSUPPORTED, "lanczos_m and oversample are limited to 16");
+    if ((s = ready(m)) != DSX_OK) return s;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int mm = lanczos_m, sv = oversample;
+    Box ext;
+    size_t ext_vox = 1, out_vox = 1;
+    for (int a = 0; a < 3; ++a) {
+        ext.g0[a] = m->box.g0[a] - (mm - 1);
+        ext.cnt[a] = m->box.cnt[a] + 2 * mm - 1;
+        ext_vox *= ext.cnt[a];
+        out_vox *= (size_t)sv * m->box.cnt[a];
+    }
+    if (m->ext_cap < ext_vox) {
+        dfree(m->d_ext);
+        m->d_ext = nullptr; m->ext_cap = 0;
+        hipError_t e = hipMalloc(&m->d_ext, ext_vox * sizeof(float));
+        if (e == hipErrorOutOfMemory) return fail(DSX_ERR_NOMEM, "out of device memory for the grown box");
+        HIPCHK(m, e);
+        m->ext_cap = ext_vox;
+    }
+    // normalised weights [s][2m]
+    const auto key = std::make_pair(mm, sv);
+    if (!m->lanczos_w.count(key)) {
+        const double rcut = 0.5 * (1.0 - 1.0 / mm);
+        auto sinc = [](double x) { return x == 0.0 ? 1.0 : std::sin(x) / x; };
+        std::vector<float> w((size_t)sv * 2 * mm);
+        for (int j = 0; j < sv; ++j) {
+            std::vector<double> v(2 * mm);
+            double tot = 0.0;
+            for (int d = 0; d < 2 * mm; ++d) {
+                const double dl = (double)j / sv + mm - 1 - d;
+                v[d] = std::fabs(dl) < mm ? sinc(2 * M_PI * rcut * dl) * sinc(M_PI * dl / mm) : 0.0;
+                tot += v[d];
+            }
+            for (int d = 0; d < 2 * mm; ++d) w[(size_t)j * 2 * mm + d] = (float)(v[d] / tot);
+        }
+        float* dw = nullptr;
+        HIPCHK(m, hipMalloc(&dw, w.size() * sizeof(float)));
+        HIPCHK(m, hipMemcpy(dw, w.data(), w.size() * sizeof(float), hipMemcpyHostToDevice));
+        m->lanczos_w[key] = dw;
+    }
+    float* dout = out;
+    if (where == DSX_HOST && (s = stage(m, out_vox, &dout)) != DSX_OK) return s;
+    m->last_stream = st;
+    if ((s = ensure_spectra(m, st)) != DSX_OK) return s;
+    if ((s = run_box(m, ext, m->d_ext, st)) != DSX_OK) return s;
+
+    LanczosParams lp{};
+    lp.in = m->d_ext; lp.out = dout; lp.wn = m->lanczos_w[key];
+    for (int a = 0; a < 3; ++a) { lp.e[a] = ext.cnt[a]; lp.o[a] = sv * m->box.cnt[a]; }
+    lp.m = mm; lp.s = sv;
+    lp.t3 = 64; lp.t1 = 64;
+    lp.t2 = 32;
+    while (lp.t2 > 1 && lanczos_lds_bytes(lp) > 150 * 1024) lp.t2 /= 2;
+    while (lp.t3 > 8 && lanczos_lds_bytes(lp) > 150 * 1024) lp.t3 /= 2;
+    lp.nb1 = (lp.o[0] + lp.t1 - 1) / lp.t1;
+    lp.nb2 = (lp.o[1] + lp.t2 - 1) / lp.t2;
+    lp.nb3 = (lp.o[2] + lp.t3 - 1) / lp.t3;
+    HIPCHK(m, timed("lanczos", st, [&] { return launch_lanczos(lp, st); }));
+    if (where == DSX_HOST) {
+        HIPCHK(m, hipMemcpyAsync(out, dout, out_vox * sizeof(float), hipMemcpyDeviceToHost, st));
+        HIPCHK(m, hipStreamSynchronize(st));
+    }
+    return DSX_OK;
+}
+
+dsx_status dsx_destroy_model(dsx_model m)
+{
+    if (!m) return fail(DSX_ERR_ARG, "model is NULL");
+    (void)hipStreamSynchronize(m->last_stream);
+    free_model(m);
+    delete m;
+    return DSX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,140 @@
+// Internal parameter blocks and launchers shared by the host runtime (api.cpp)
+// and the gfx950 kernels (fft.hip, recombine.hip, lanczos.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dsx {
+
+constexpr int kMaxN = 128;        // supercell edge
+constexpr int kMaxSites = 64;
+constexpr int kMaxOrder = 8;
+constexpr int kMaxMono = 165;     // monomials of total degree <= 8: C(11, 3)
+constexpr int kMaxRadices = 16;
+
+// Mixed-radix factorisation of one FFT axis.
+struct AxisPlan {
+    int32_t n;
+    int32_t nrad;
+    int32_t rad[kMaxRadices];
+};
+
+// Number of monomials u1^p u2^q u3^r with p + q + r <= N.
+__host__ __device__ constexpr int n_monomials(int N) { return (N + 1) * (N + 2) * (N + 3) / 6; }
+// Number of (q, r) pairs with q + r <= N.
+__host__ __device__ constexpr int n_pairs(int N) { return (N + 1) * (N + 2) / 2; }
+// Index of monomial (p, q, r), ordered by degree d, then p descending, then q descending.
+__host__ __device__ constexpr int mono_index(int p, int q, int r) {
+    return (p + q + r) * (p + q + r + 1) * (p + q + r + 2) / 6
+         + (q + r) * (q + r + 1) / 2 + r;
+}
+// Index of the pair (q, r), ordered by e = q + r, then q descending.
+__host__ __device__ constexpr int pair_index(int q, int r) { return (q + r) * (q + r + 1) / 2 + r; }
+
+// ---------------------------------------------------------------------------- FP64 sums
+struct SumsParams {
+    const float* occ;     // [M][S][ncell] or null (delta = 1)
+    const float* vec;     // [M][S][ncell][3] displacements (nuclear) or spins (magnetic)
+    double* partial;      // [M*S][nchunk][T]
+    double* sums;         // [M*S][T]
+    int32_t M, S, ncell, T, kind, nchunk, chunk;
+};
+
+// ---------------------------------------------------------------------------- FFT
+struct PlaneParams {
+    const float* occ;     // [M][S][n1][n2][n3] or null
+    const float* vec;     // [M][S][n1][n2][n3][3] or null
+    const double* sums;   // [M*S][T] lattice sums (the field means are sums / ncell)
+    float2* X;            // [M][n1][n2][S*F][nh]; this pass writes the R1 index in place of k1
+    const float2* tw2;    // e^{+2 pi i t / n2}, t < n2
+    const float2* tw3;    // e^{+2 pi i t / n3}, t < n3
+    AxisPlan p2, p3;
+    int32_t n1, n2, n3, nh, S, F, T, M, kind, first_mono;
+    int32_t fchunk, nfchunk;
+    int32_t buf_elems;    // complex elements per LDS ping-pong buffer
+    int8_t mono[3 * kMaxMono];   // exponents (p, q, r) of monomial t
+};
+
+struct Axis1Params {
+    float2* X;            // [M][n1][n2][cols], transformed in place along n1
+    const float2* tw1;
+    AxisPlan p1;
+    int32_t n1, n2, cols, M, tc, ncolblk;
+};
+
+// ---------------------------------------------------------------------------- recombination
+// Phase tables are float32 values computed in float64 on the host:
+//   tab1[mu][i1]  = b_mu e^{2 pi i g1 r_mu1},  g1 = (g0_1 + i1)/n1
+//   tab2[mu][i2]  = e^{2 pi i g2 r_mu2}
+//   tabK3[mu][k3] = e^{2 pi i k3 r_mu3 / n3}
+//   tabH3[c][h]   = e^{2 pi i H3 r_c3},  H3 = H3min + h
+struct RecombParams {
+    const float2* X;
+    float* out;
+    const float2* tab1;
+    const float2* tab2;
+    const float2* tabK3;
+    const float2* tabH3;
+    int32_t n1, n2, n3, nh, S, SF, F, M, first_mono;
+    int32_t g0[3], cnt[3];
+    int32_t H3min, nH3span;
+    int32_t maxH1;          // largest number of H1 values over residues k1
+    int32_t h2per;          // H2 values per block part
+    int32_t nparts;         // parts per (k1, k2, H1)
+    int32_t nchunk3;        // H3 chunks per (H2, k3)
+    int32_t nblocks;        // logical blocks = n1 * n2 * maxH1 * nparts
+    int32_t nsc;            // site chunks (each fits the LDS budget)
+    int32_t sc_start[kMaxSites + 1];   // site chunk boundaries in the sorted site list
+    int32_t site_of[kMaxSites];        // sorted position -> site index
+    int32_t class_of[kMaxSites];       // sorted position -> class index
+    float scale;            // 1/(N M)  (magnetic: C/(N M))
+    // magnetic only
+    float recip[9];         // rows a*, b*, c* (inverse Angstrom)
+    int32_t ff_uniform;     // 1 when every site has the same form factor
+    float ff[kMaxSites][7];  // per sorted position
+};
+
+// ---------------------------------------------------------------------------- Bragg (k = 0)
+struct BraggParams {
+    const double* sums;     // [M*S][T]
+    float* out;             // output box
+    int32_t g0[3], cnt[3];
+    int32_t n[3];
+    int32_t Hlo[3], nH[3];  // H with n H inside the box
+    int32_t S, T, M, kind;
+    double scale;           // 1/N  (magnetic: C/N); the means over configurations are explicit
+    const double* site;     // [S][11]: r_mu (3), b_mu, form factor (7)
+    double recip[9];
+    int32_t has_ff;
+};
+
+// ---------------------------------------------------------------------------- Lanczos
+struct LanczosParams {
+    const float* in;        // I on the grown box [e1][e2][e3]
+    float* out;             // [o1][o2][o3]
+    const float* wn;        // [3][s][2m] normalised weights per axis
+    int32_t e[3], o[3];
+    int32_t m, s;
+    int32_t t1, t2, t3;     // tile extents (outputs)
+    int32_t nb1, nb2, nb3;
+};
+
+// ---------------------------------------------------------------------------- launchers
+hipError_t launch_sums(const SumsParams& p, int order, hipStream_t st);
+hipError_t launch_fft_planes(const PlaneParams& p, hipStream_t st);
+hipError_t launch_fft_axis1(const Axis1Params& p, hipStream_t st);
+hipError_t launch_recombine_nuclear(const RecombParams& p, int order, int hc, int block,
+                                    size_t lds, hipStream_t st);
+hipError_t launch_recombine_magnetic(const RecombParams& p, int hc, int block, size_t lds,
+                                     hipStream_t st);
+hipError_t launch_bragg(const BraggParams& p, int order, hipStream_t st);
+hipError_t launch_lanczos(const LanczosParams& p, hipStream_t st);
+
+// Block sizes / LDS limits the host planner must respect.
+int recombine_max_threads(int hc, int magnetic);
+size_t planes_lds_bytes(const PlaneParams& p);
+size_t axis1_lds_bytes(const Axis1Params& p);
+size_t lanczos_lds_bytes(const LanczosParams& p);
+
+}  // namespace dsx

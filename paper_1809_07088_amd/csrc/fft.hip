@@ -1,0 +1,388 @@
+// Field generation, float64 lattice sums and the batched 3D real-to-complex FFT
+// with the +i sign (X_k = sum_R x_R e^{+2 pi i k.R / n}), for gfx950.
+//
+//  k_sums        float64 sums S^{pqr}_{m,mu} = sum_R delta u1^p u2^q u3^r (nuclear) or
+//                sum_R delta M_c (magnetic): the k = 0 coefficient of every field,
+//                used for the Bragg points and to centre the float32 fields.
+//  k_fft_planes  generates the real fields of one lattice plane R1 (the Taylor
+//                monomials delta u1^p u2^q u3^r of Sec. III.C, the occupancy of Sec.
+//                III.B or the spin components of Sec. III.D), minus their mean, and
+//                transforms them along axes 3 (real-to-complex, two real rows packed
+//                in one complex line) and 2, entirely in LDS.
+//  k_fft_axis1   transforms along axis 1 in place, on LDS tiles of 64 contiguous
+//                columns.
+// The 1D transforms are Stockham auto-sort passes of radix 2, 3, 4, 5 and a direct
+// DFT for any other prime; twiddles come from a float64-generated table.
+#include "dsx_internal.h"
+
+namespace dsx {
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cmuli(float2 a) { return make_float2(-a.y, a.x); }   // i a
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+// One Stockham pass of radix R over `nlines` lines of length n held in LDS.
+// Element e of line l sits at base[l * lstride + e * estride].  Ns is the product
+// of the radices of the earlier passes.
+__device__ void stockham_pass(const float2* __restrict__ src, float2* __restrict__ dst,
+                              int nlines, int lstride, int estride, int n, int R, int Ns,
+                              const float2* __restrict__ tw)
+{
+    const int nb = n / R;
+    const int twstep = n / (Ns * R);
+    const int total = nlines * nb;
+    for (int it = threadIdx.x; it < total; it += blockDim.x) {
+        const int l = it / nb;
+        const int j = it - l * nb;
+        const float2* s = src + l * lstride;
+        float2* d = dst + l * lstride;
+        const int jm = j % Ns;
+        const int o = (j - jm) * R + jm;          // (j / Ns) * Ns * R + j mod Ns
+        const int te = jm * twstep;               // twiddle exponent step, r * te < n
+        if (R == 4) {
+            float2 v0 = s[j * estride];
+            float2 v1 = cmul(s[(j + nb) * estride], tw[te]);
+            float2 v2 = cmul(s[(j + 2 * nb) * estride], tw[2 * te]);
+            float2 v3 = cmul(s[(j + 3 * nb) * estride], tw[3 * te]);
+            float2 a0 = cadd(v0, v2), a1 = csub(v0, v2), a2 = cadd(v1, v3), a3 = cmuli(csub(v1, v3));
+            d[o * estride] = cadd(a0, a2);
+            d[(o + Ns) * estride] = cadd(a1, a3);
+            d[(o + 2 * Ns) * estride] = csub(a0, a2);
+            d[(o + 3 * Ns) * estride] = csub(a1, a3);
+        } else if (R == 2) {
+            float2 v0 = s[j * estride];
+            float2 v1 = cmul(s[(j + nb) * estride], tw[te]);
+            d[o * estride] = cadd(v0, v1);
+            d[(o + Ns) * estride] = csub(v0, v1);
+        } else if (R == 3) {
+            const float h = 0.86602540378443864676f;   // sin(2 pi / 3)
+            float2 v0 = s[j * estride];
+            float2 v1 = cmul(s[(j + nb) * estride], tw[te]);
+            float2 v2 = cmul(s[(j + 2 * nb) * estride], tw[2 * te]);
+            float2 sm = cadd(v1, v2);
+            float2 t = make_float2(v0.x - 0.5f * sm.x, v0.y - 0.5f * sm.y);
+            float2 u = cscale(cmuli(csub(v1, v2)), h);
+            d[o * estride] = cadd(v0, sm);
+            d[(o + Ns) * estride] = cadd(t, u);
+            d[(o + 2 * Ns) * estride] = csub(t, u);
+        } else if (R == 5) {
+            const float c1 = 0.30901699437494742410f, c2 = -0.80901699437494742410f;
+            const float s1 = 0.95105651629515357212f, s2 = 0.58778525229247312917f;
+            float2 v0 = s[j * estride];
+            float2 v1 = cmul(s[(j + nb) * estride], tw[te]);
+            float2 v2 = cmul(s[(j + 2 * nb) * estride], tw[2 * te]);
+            float2 v3 = cmul(s[(j + 3 * nb) * estride], tw[3 * te]);
+            float2 v4 = cmul(s[(j + 4 * nb) * estride], tw[4 * te]);
+            float2 b1 = cadd(v1, v4), b2 = cadd(v2, v3), d1 = csub(v1, v4), d2 = csub(v2, v3);
+            float2 ra = make_float2(v0.x + c1 * b1.x + c2 * b2.x, v0.y + c1 * b1.y + c2 * b2.y);
+            float2 rb = make_float2(v0.x + c2 * b1.x + c1 * b2.x, v0.y + c2 * b1.y + c1 * b2.y);
+            float2 ia = cmuli(make_float2(s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y));
+            float2 ib = cmuli(make_float2(s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y));
+            d[o * estride] = make_float2(v0.x + b1.x + b2.x, v0.y + b1.y + b2.y);
+            d[(o + Ns) * estride] = cadd(ra, ia);
+            d[(o + 4 * Ns) * estride] = csub(ra, ia);
+            d[(o + 2 * Ns) * estride] = cadd(rb, ib);
+            d[(o + 3 * Ns) * estride] = csub(rb, ib);
+        } else {
+            // direct DFT of prime length R: y_k = sum_r x_r e^{2 pi i r (jm/(Ns R) + k/R)}
+            const int step = n / R;
+            for (int k = 0; k < R; ++k) {
+                float2 acc = make_float2(0.f, 0.f);
+                for (int r = 0; r < R; ++r) {
+                    const int e = (r * te + ((r * k) % R) * step) % n;
+                    acc = cadd(acc, cmul(s[(j + r * nb) * estride], tw[e]));
+                }
+                d[(o + k * Ns) * estride] = acc;
+            }
+        }
+    }
+}
+
+// Full 1D transforms of all lines; ping-pongs between a and b and returns the
+// buffer holding the result.  Caller synchronises before (inputs visible).
+__device__ float2* lds_fft(float2* a, float2* b, int nlines, int lstride, int estride,
+                           const AxisPlan& P, const float2* tw)
+{
+    int Ns = 1;
+    for (int s = 0; s < P.nrad; ++s) {
+        stockham_pass(a, b, nlines, lstride, estride, P.n, P.rad[s], Ns, tw);
+        __syncthreads();
+        Ns *= P.rad[s];
+        float2* t = a; a = b; b = t;
+    }
+    return a;
+}
+
+// ---------------------------------------------------------------------------- sums
+// One lattice cell per thread (P.chunk == blockDim.x); every monomial is reduced
+// across the wave with shuffles and across the four waves through LDS, in a
+// fixed order, so the sums are reproducible run to run.
+template <int N>
+__global__ __launch_bounds__(256) void k_sums_nuclear(SumsParams P)
+{
+    constexpr int T = n_monomials(N);
+    __shared__ double red[4][T];
+    const int chunk = blockIdx.x % P.nchunk;
+    const int ms = blockIdx.x / P.nchunk;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c = chunk * P.chunk + threadIdx.x;
+    double d = 0.0;
+    double pw[3][N + 1];
+    if (c < P.ncell) {
+        const size_t at = (size_t)ms * P.ncell + c;
+        d = P.occ ? (double)P.occ[at] : 1.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            pw[a][0] = 1.0;
+            const double u = (N > 0 && P.vec) ? (double)P.vec[3 * at + a] : 0.0;
+#pragma unroll
+            for (int k = 1; k <= N; ++k) pw[a][k] = pw[a][k - 1] * u;
+        }
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int k = 0; k <= N; ++k) pw[a][k] = 0.0;
+    }
+#pragma unroll
+    for (int dg = 0; dg <= N; ++dg)
+#pragma unroll
+        for (int p = dg; p >= 0; --p)
+#pragma unroll
+            for (int q = dg - p; q >= 0; --q) {
+                const int r = dg - p - q;
+                double v = d * pw[0][p] * pw[1][q] * pw[2][r];
+                for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+                if (lane == 0) red[wave][mono_index(p, q, r)] = v;
+            }
+    __syncthreads();
+    for (int t = threadIdx.x; t < T; t += blockDim.x) {
+        double v = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) v += red[w][t];
+        P.partial[((size_t)ms * P.nchunk + chunk) * T + t] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sums_magnetic(SumsParams P)
+{
+    __shared__ double red[4][3];
+    const int chunk = blockIdx.x % P.nchunk;
+    const int ms = blockIdx.x / P.nchunk;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double acc[3] = {0.0, 0.0, 0.0};
+    const int c0 = chunk * P.chunk;
+    const int c1 = min(P.ncell, c0 + P.chunk);
+    for (int c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
+        const size_t at = (size_t)ms * P.ncell + c;
+        const double d = P.occ ? (double)P.occ[at] : 1.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) acc[a] += d * (double)P.vec[3 * at + a];
+    }
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        double v = acc[t];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        if (lane == 0) red[wave][t] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double v = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) v += red[w][threadIdx.x];
+        P.partial[((size_t)ms * P.nchunk + chunk) * 3 + threadIdx.x] = v;
+    }
+}
+
+__global__ void k_sums_reduce(SumsParams P)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= P.M * P.S * P.T) return;
+    const int ms = idx / P.T, t = idx - ms * P.T;
+    double v = 0.0;
+    for (int c = 0; c < P.nchunk; ++c) v += P.partial[((size_t)ms * P.nchunk + c) * P.T + t];
+    P.sums[idx] = v;
+}
+
+template <int N>
+static hipError_t launch_sums_t(const SumsParams& p, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sums_nuclear<N>, dim3(p.M * p.S * p.nchunk), dim3(256), 0, st, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_sums(const SumsParams& p, int order, hipStream_t st)
+{
+    hipError_t e = hipSuccess;
+    if (p.kind == 1) {
+        hipLaunchKernelGGL(k_sums_magnetic, dim3(p.M * p.S * p.nchunk), dim3(256), 0, st, p);
+        e = hipGetLastError();
+    } else {
+        switch (order) {
+            case 0: e = launch_sums_t<0>(p, st); break;
+            case 1: e = launch_sums_t<1>(p, st); break;
+            case 2: e = launch_sums_t<2>(p, st); break;
+            case 3: e = launch_sums_t<3>(p, st); break;
+            case 4: e = launch_sums_t<4>(p, st); break;
+            case 5: e = launch_sums_t<5>(p, st); break;
+            case 6: e = launch_sums_t<6>(p, st); break;
+            case 7: e = launch_sums_t<7>(p, st); break;
+            case 8: e = launch_sums_t<8>(p, st); break;
+            default: return hipErrorInvalidValue;
+        }
+    }
+    if (e != hipSuccess) return e;
+    const int tot = p.M * p.S * p.T;
+    hipLaunchKernelGGL(k_sums_reduce, dim3((tot + 255) / 256), dim3(256), 0, st, p);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------- plane FFT
+__global__ __launch_bounds__(256) void k_fft_planes(PlaneParams P)
+{
+    extern __shared__ float2 smem[];
+    float2* tw2 = smem;
+    float2* tw3 = tw2 + P.n2;
+    float2* A = tw3 + P.n3;
+    float2* B = A + P.buf_elems;
+
+    int b = blockIdx.x;
+    const int fc = b % P.nfchunk; b /= P.nfchunk;
+    const int R1 = b % P.n1; b /= P.n1;
+    const int mu = b % P.S;
+    const int m = b / P.S;
+    const int n2 = P.n2, n3 = P.n3, nh = P.nh;
+    const int ncell = P.n1 * n2 * n3;
+    const int SF = P.S * P.F;
+
+    for (int i = threadIdx.x; i < n2; i += blockDim.x) tw2[i] = P.tw2[i];
+    for (int i = threadIdx.x; i < n3; i += blockDim.x) tw3[i] = P.tw3[i];
+
+    const size_t plane0 = ((size_t)(m * P.S + mu)) * ncell + (size_t)R1 * n2 * n3;
+    const float* occ = P.occ ? P.occ + plane0 : nullptr;
+    const float* vec = P.vec ? P.vec + 3 * plane0 : nullptr;
+    const int npairs = (n2 + 1) / 2;
+    const int f_end = min(P.F, (fc + 1) * P.fchunk);
+
+    for (int f = fc * P.fchunk; f < f_end; ++f) {
+        const int t = f + P.first_mono;
+        const int ep = P.mono[3 * t], eq = P.mono[3 * t + 1], er = P.mono[3 * t + 2];
+        const float mean = (float)(P.sums[(size_t)(m * P.S + mu) * P.T + t] / (double)ncell);
+        __syncthreads();   // tables loaded / previous field finished with A and B
+        // generate two real rows per complex line: row 2j -> real, row 2j+1 -> imaginary
+        for (int idx = threadIdx.x; idx < npairs * n3; idx += blockDim.x) {
+            const int j = idx / n3, R3 = idx - j * n3;
+            float xv[2] = {0.f, 0.f};
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int R2 = 2 * j + h;
+                if (R2 < n2) {
+                    const int c = R2 * n3 + R3;
+                    float v;
+                    if (P.kind == 1) {
+                        v = vec[3 * c + t];
+                    } else {
+                        v = 1.f;
+                        if (ep | eq | er) {
+                            const float u0 = vec[3 * c], u1 = vec[3 * c + 1], u2 = vec[3 * c + 2];
+                            for (int k = 0; k < ep; ++k) v *= u0;
+                            for (int k = 0; k < eq; ++k) v *= u1;
+                            for (int k = 0; k < er; ++k) v *= u2;
+                        }
+                    }
+                    if (occ) v *= occ[c];
+                    xv[h] = v - mean;
+                }
+            }
+            A[j * n3 + R3] = make_float2(xv[0], xv[1]);
+        }
+        __syncthreads();
+        float2* Z = lds_fft(A, B, npairs, n3, 1, P.p3, tw3);
+        float2* C = (Z == A) ? B : A;
+        // unpack the packed real transforms: X_a = (Z_k + conj Z_-k)/2, X_b = -i (Z_k - conj Z_-k)/2
+        for (int idx = threadIdx.x; idx < npairs * nh; idx += blockDim.x) {
+            const int j = idx / nh, k = idx - j * nh;
+            const float2 zk = Z[j * n3 + k];
+            const int km = (k == 0) ? 0 : n3 - k;
+            const float2 zm = Z[j * n3 + km];
+            const float2 xa = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+            const float2 xb = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
+            C[(2 * j) * nh + k] = xa;
+            if (2 * j + 1 < n2) C[(2 * j + 1) * nh + k] = xb;
+        }
+        __syncthreads();
+        float2* D = (C == A) ? B : A;
+        float2* Y = lds_fft(C, D, nh, 1, nh, P.p2, tw2);
+        float2* out = P.X + ((size_t)(m * P.n1 + R1) * n2) * SF * nh + (size_t)(mu * P.F + f) * nh;
+        for (int idx = threadIdx.x; idx < n2 * nh; idx += blockDim.x) {
+            const int k2 = idx / nh, k3 = idx - k2 * nh;
+            out[(size_t)k2 * SF * nh + k3] = Y[k2 * nh + k3];
+        }
+    }
+}
+
+size_t planes_lds_bytes(const PlaneParams& p)
+{
+    return sizeof(float2) * (size_t)(p.n2 + p.n3 + 2 * p.buf_elems);
+}
+
+hipError_t launch_fft_planes(const PlaneParams& p, hipStream_t st)
+{
+    const size_t lds = planes_lds_bytes(p);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_fft_planes,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_fft_planes, dim3(p.M * p.S * p.n1 * p.nfchunk), dim3(256), lds, st, p);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------- axis-1 FFT
+__global__ __launch_bounds__(256) void k_fft_axis1(Axis1Params P)
+{
+    extern __shared__ float2 smem[];
+    float2* tw = smem;
+    float2* A = tw + P.n1;
+    float2* B = A + P.n1 * P.tc;
+    int b = blockIdx.x;
+    const int cb = b % P.ncolblk; b /= P.ncolblk;
+    const int k2 = b % P.n2;
+    const int m = b / P.n2;
+    const int tc = P.tc, n1 = P.n1;
+    const int c0 = cb * tc;
+    const size_t rowstride = (size_t)P.n2 * P.cols;
+    float2* base = P.X + ((size_t)m * n1 * P.n2 + k2) * P.cols + c0;
+    for (int i = threadIdx.x; i < n1; i += blockDim.x) tw[i] = P.tw1[i];
+    for (int idx = threadIdx.x; idx < n1 * tc; idx += blockDim.x) {
+        const int R1 = idx / tc, c = idx - R1 * tc;
+        A[idx] = (c0 + c < P.cols) ? base[R1 * rowstride + c] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    float2* Y = lds_fft(A, B, tc, 1, tc, P.p1, tw);
+    for (int idx = threadIdx.x; idx < n1 * tc; idx += blockDim.x) {
+        const int k1 = idx / tc, c = idx - k1 * tc;
+        if (c0 + c < P.cols) base[k1 * rowstride + c] = Y[idx];
+    }
+}
+
+size_t axis1_lds_bytes(const Axis1Params& p)
+{
+    return sizeof(float2) * (size_t)(p.n1 + 2 * p.n1 * p.tc);
+}
+
+hipError_t launch_fft_axis1(const Axis1Params& p, hipStream_t st)
+{
+    const size_t lds = axis1_lds_bytes(p);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_fft_axis1,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_fft_axis1, dim3(p.M * p.n2 * p.ncolblk), dim3(256), lds, st, p);
+    return hipGetLastError();
+}
+
+}  // namespace dsx

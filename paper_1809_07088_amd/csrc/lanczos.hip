@@ -1,0 +1,111 @@
+// Lanczos (windowed-sinc) resampling of I(G) for gfx950 (Sec. V.B, Eqs.
+// intensity_convol_finite, windowed_sinc, lanczos).
+//
+// The weight W(Q - G) is a product over the axes and the window takes the 2m
+// points floor(Q_a) - m + 1 <= G_a <= floor(Q_a) + m on every axis, so the
+// normalised sum  sum_G I(G) W / sum_G W  equals three normalised 1D passes, one
+// per axis, applied in sequence (the paper notes this separability).  The weights,
+// normalised per output phase i mod s, come from a float64 host table.
+//
+// One block owns an output tile T2 x T3 and a segment of T1 outputs along axis 1.
+// It streams the input planes e1 of that segment once: each plane is staged in
+// LDS (rows and halo), filtered along axis 3 then axis 2, and kept in a ring of
+// 2m filtered planes; an output plane is emitted as soon as its 2m input planes
+// are in the ring.  Every input value is read from HBM about once per block.
+#include "dsx_internal.h"
+
+namespace dsx {
+
+__global__ __launch_bounds__(256) void k_lanczos(LanczosParams P)
+{
+    extern __shared__ float sm[];
+    const int m2 = 2 * P.m, s = P.s;
+    int b = blockIdx.x;
+    const int b3 = b % P.nb3; b /= P.nb3;
+    const int b2 = b % P.nb2;
+    const int b1 = b / P.nb2;
+    const int o1 = b1 * P.t1, o2 = b2 * P.t2, o3 = b3 * P.t3;
+    const int T1 = min(P.t1, P.o[0] - o1), T2 = min(P.t2, P.o[1] - o2), T3 = min(P.t3, P.o[2] - o3);
+    const int E2lo = o2 / s, E2n = (o2 + T2 - 1) / s - E2lo + m2;
+    const int E3lo = o3 / s, E3n = (o3 + T3 - 1) / s - E3lo + m2;
+    const int L2max = (P.t2 - 1) / s + 1 + m2, L3max = (P.t3 - 1) / s + 1 + m2;
+
+    float* wn = sm;                                  // [s][2m]
+    float* stg = wn + ((s * m2 + 3) & ~3);           // [E2n][E3n]
+    float* mid = stg + L2max * L3max;                // [E2n][t3]
+    float* ring = mid + L2max * P.t3;                // [2m][t2][t3]
+    for (int i = threadIdx.x; i < s * m2; i += blockDim.x) wn[i] = P.wn[i];
+
+    const int tile = P.t2 * P.t3;
+    const int e1a = o1 / s, e1b = (o1 + T1 - 1) / s + m2 - 1;
+    for (int e1 = e1a; e1 <= e1b; ++e1) {
+        __syncthreads();
+        const float* src = P.in + ((size_t)e1 * P.e[1] + E2lo) * P.e[2] + E3lo;
+        for (int idx = threadIdx.x; idx < E2n * E3n; idx += blockDim.x) {
+            const int r = idx / E3n, c = idx - r * E3n;
+            stg[idx] = src[(size_t)r * P.e[2] + c];
+        }
+        __syncthreads();
+        // axis 3
+        for (int idx = threadIdx.x; idx < E2n * T3; idx += blockDim.x) {
+            const int r = idx / T3, j3 = idx - r * T3;
+            const int i3 = o3 + j3;
+            const float* w = wn + (i3 % s) * m2;
+            const float* x = stg + r * E3n + (i3 / s - E3lo);
+            float acc = 0.f;
+            for (int d = 0; d < m2; ++d) acc += w[d] * x[d];
+            mid[r * P.t3 + j3] = acc;
+        }
+        __syncthreads();
+        // axis 2 into the ring slot of plane e1
+        float* slot = ring + (e1 % m2) * tile;
+        for (int idx = threadIdx.x; idx < T2 * T3; idx += blockDim.x) {
+            const int j2 = idx / T3, j3 = idx - j2 * T3;
+            const int i2 = o2 + j2;
+            const float* w = wn + (i2 % s) * m2;
+            const float* x = mid + (i2 / s - E2lo) * P.t3 + j3;
+            float acc = 0.f;
+            for (int d = 0; d < m2; ++d) acc += w[d] * x[d * P.t3];
+            slot[j2 * P.t3 + j3] = acc;
+        }
+        __syncthreads();
+        // axis 1: outputs whose window ends at plane e1
+        const int fl = e1 - m2 + 1;
+        if (fl >= e1a) {
+            const int ia = max(o1, fl * s), ib = min(o1 + T1, fl * s + s);
+            for (int i1 = ia; i1 < ib; ++i1) {
+                const float* w = wn + (i1 % s) * m2;
+                float* orow = P.out + ((size_t)i1 * P.o[1] + o2) * P.o[2] + o3;
+                for (int idx = threadIdx.x; idx < T2 * T3; idx += blockDim.x) {
+                    const int j2 = idx / T3, j3 = idx - j2 * T3;
+                    float acc = 0.f;
+                    for (int d = 0; d < m2; ++d)
+                        acc += w[d] * ring[((fl + d) % m2) * tile + j2 * P.t3 + j3];
+                    orow[(size_t)j2 * P.o[2] + j3] = acc;
+                }
+            }
+        }
+    }
+}
+
+size_t lanczos_lds_bytes(const LanczosParams& p)
+{
+    const int m2 = 2 * p.m;
+    const int L2max = (p.t2 - 1) / p.s + 1 + m2, L3max = (p.t3 - 1) / p.s + 1 + m2;
+    return sizeof(float) * (size_t)(((p.s * m2 + 3) & ~3) + L2max * L3max + L2max * p.t3 +
+                                    m2 * p.t2 * p.t3);
+}
+
+hipError_t launch_lanczos(const LanczosParams& p, hipStream_t st)
+{
+    const size_t lds = lanczos_lds_bytes(p);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_lanczos,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_lanczos, dim3(p.nb1 * p.nb2 * p.nb3), dim3(256), lds, st, p);
+    return hipGetLastError();
+}
+
+}  // namespace dsx

@@ -1,0 +1,592 @@
+// Reciprocal-space recombination of the per-site spectra into the diffuse
+// intensity at every supercell Bragg point G of a box, for gfx950.
+//
+// For G = H + k (Sec. III, Eq. g_vec; k = G mod n) the structure factor of one
+// configuration is (Sec. III.C, Eq. total_sf_taylor, regrouped by monomial)
+//
+//   F(G) = sum_mu b_mu e^{2 pi i g.r_mu} sum_{p+q+r<=N}
+//          (i t1)^p/p! (i t2)^q/q! (i t3)^r/r! X^{pqr}_mu(k),   t_a = 2 pi g_a,
+//
+// with X the +i FFT of delta u1^p u2^q u3^r.  It is evaluated by sum factorisation
+// over the three axes:
+//   level A (per block: fixed k1, k2 and H1, i.e. fixed g1)
+//       B_mu^{qr}(k3) = b_mu e^{2 pi i g1 r_mu1} sum_p (i t1)^p/p! X^{pqr}_mu(k1,k2,k3)
+//       in LDS, read once per block from the k-major spectra;
+//   level B (per thread: fixed H2 and k3)
+//       D_c^r = sum_{mu in c} e^{2 pi i (g2 r_mu2 + k3 r_mu3/n3)} sum_q (i t2)^q/q! B_mu^{qr} / r!
+//       where the class c groups the sites that share r_mu3;
+//   level C (per voxel: the thread's H3 values)
+//       F = sum_c e^{2 pi i H3 r_c3} sum_r (i t3)^r D_c^r   (Horner in i t3),
+// then |F|^2 is accumulated over the configurations in registers and written
+// once, with consecutive lanes writing consecutive G3.  The magnetic kernel uses
+// the three spin-component spectra instead of the Taylor monomials, applies the
+// form factor and takes the component of F perpendicular to Q (Sec. III.D,
+// Eqs. mag_sf, mag_intensity, mag_projection).
+//
+// The points k = 0 (G = 0 mod n) are computed separately in float64 from the
+// float64 lattice sums (k_bragg_*), where the Bragg subtraction |<F>|^2 cancels
+// most of |F|^2 (Sec. II, Eq. bragg_diffuse_sf; Sec. III.A, Eq. bragg_sf); the
+// ensemble mean <F> is the mean over the model's configurations.
+#include "dsx_internal.h"
+
+namespace dsx {
+
+__device__ __forceinline__ float2 cmulf(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ int floordiv(int a, int b) {   // b > 0
+    int q = a / b;
+    if ((a % b) != 0 && (a < 0)) --q;
+    return q;
+}
+__device__ __forceinline__ int ceildiv(int a, int b) { return -floordiv(-a, b); }
+// H values of residue k on one axis: lo, count with g0 <= k + n H < g0 + cnt
+__device__ __forceinline__ void hrange(int k, int n, int g0, int cnt, int& lo, int& count) {
+    lo = ceildiv(g0 - k, n);
+    const int hi = floordiv(g0 + cnt - 1 - k, n);
+    count = hi >= lo ? hi - lo + 1 : 0;
+}
+
+__host__ __device__ constexpr float inv_factorial(int r) {
+    float f = 1.f;
+    for (int i = 2; i <= r; ++i) f *= (float)i;
+    return 1.f / f;
+}
+
+// Block decode shared by both kernels.  Returns false when the block has no work.
+struct BlockWork {
+    int k1, k2, G1, i1, h2a, h2b, H2lo;
+};
+
+__device__ __forceinline__ bool decode_block(const RecombParams& P, BlockWork& w)
+{
+    // Blocks are dealt round-robin to the 8 XCDs; remap so that each XCD walks a
+    // contiguous range of (k1, k2) columns and the H1 blocks of one column share
+    // its L2.
+    const int nb8 = (P.nblocks + 7) / 8;
+    const int logical = (int)(blockIdx.x % 8) * nb8 + (int)(blockIdx.x / 8);
+    if (logical >= P.nblocks) return false;
+    int t = logical;
+    const int part = t % P.nparts; t /= P.nparts;
+    const int j1 = t % P.maxH1; t /= P.maxH1;
+    w.k2 = t % P.n2;
+    w.k1 = t / P.n2;
+    int H1lo, nH1;
+    hrange(w.k1, P.n1, P.g0[0], P.cnt[0], H1lo, nH1);
+    if (j1 >= nH1) return false;
+    int nH2;
+    hrange(w.k2, P.n2, P.g0[1], P.cnt[1], w.H2lo, nH2);
+    w.h2a = part * P.h2per;
+    w.h2b = min(nH2, w.h2a + P.h2per);
+    if (w.h2a >= w.h2b) return false;
+    w.G1 = w.k1 + P.n1 * (H1lo + j1);
+    w.i1 = w.G1 - P.g0[0];
+    return true;
+}
+
+// ---------------------------------------------------------------------------- nuclear
+template <int N, int HC>
+__global__ __launch_bounds__(HC <= 17 ? 1024 : 512) void k_recombine_nuclear(RecombParams P)
+{
+    extern __shared__ float2 Bs[];
+    constexpr int QR = n_pairs(N);
+    BlockWork w;
+    if (!decode_block(P, w)) return;
+    const int n1 = P.n1, n2 = P.n2, n3 = P.n3, nh = P.nh;
+    const int SFnh = P.SF * nh;
+    const float tau1 = (float)(6.283185307179586 * (double)w.G1 / (double)n1);
+
+    // this thread's item: (H2, H3 chunk, k3) with k3 fastest
+    const int nitems = (w.h2b - w.h2a) * n3 * P.nchunk3;
+    const int item = threadIdx.x;
+    const bool active = item < nitems;
+    int k3 = 0, ch = 0, h2 = w.h2a;
+    if (active) {
+        k3 = item % n3;
+        const int r = item / n3;
+        ch = r % P.nchunk3;
+        h2 = w.h2a + r / P.nchunk3;
+    }
+    const int G2 = w.k2 + n2 * (w.H2lo + h2);
+    const int i2 = G2 - P.g0[1];
+    int H3lo, nH3;
+    hrange(k3, n3, P.g0[2], P.cnt[2], H3lo, nH3);
+    const int hbeg = ch * HC;
+    const int hcnt = active ? max(0, min(HC, nH3 - hbeg)) : 0;
+    const float tau2 = (float)(6.283185307179586 * (double)G2 / (double)n2);
+    const float c3 = (float)(6.283185307179586 / (double)n3);
+    float a2[N + 1];   // tau2^q / q!
+    a2[0] = 1.f;
+#pragma unroll
+    for (int q = 1; q <= N; ++q) a2[q] = a2[q - 1] * tau2 / (float)q;
+
+    float I[HC];
+#pragma unroll
+    for (int h = 0; h < HC; ++h) I[h] = 0.f;
+
+    const size_t col = ((size_t)w.k1 * n2 + w.k2) * SFnh;
+    const size_t colm = ((size_t)((n1 - w.k1) % n1) * n2 + (n2 - w.k2) % n2) * SFnh;
+
+    for (int m = 0; m < P.M; ++m) {
+        float2 F[HC];
+#pragma unroll
+        for (int h = 0; h < HC; ++h) F[h] = make_float2(0.f, 0.f);
+        const float2* Xm = P.X + (size_t)m * n1 * n2 * SFnh;
+        for (int sc = 0; sc < P.nsc; ++sc) {
+            const int s0 = P.sc_start[sc], s1 = P.sc_start[sc + 1];
+            const int ns = s1 - s0;
+            __syncthreads();
+            // level A
+            for (int idx = threadIdx.x; idx < ns * QR * n3; idx += blockDim.x) {
+                const int kk = idx % n3;
+                const int rj = idx / n3;
+                const int j = rj % QR;
+                const int sl = rj / QR;
+                const int mu = P.site_of[s0 + sl];
+                int e = 0;
+                while ((e + 1) * (e + 2) / 2 <= j) ++e;
+                const int rr = j - e * (e + 1) / 2;
+                const int q = e - rr;
+                const float2* src;
+                float sg;
+                if (kk < nh) { src = Xm + col + kk; sg = 1.f; }
+                else { src = Xm + colm + (n3 - kk); sg = -1.f; }     // X(k) = conj X(-k)
+                float2 wgt = P.tab1[(size_t)mu * P.cnt[0] + w.i1];
+                float2 acc = make_float2(0.f, 0.f);
+                for (int p = 0; p <= N - e; ++p) {
+                    const int f = mono_index(p, q, rr) - P.first_mono;
+                    if (f >= 0) {
+                        float2 x = src[(size_t)(mu * P.F + f) * nh];
+                        x.y *= sg;
+                        acc.x += wgt.x * x.x - wgt.y * x.y;
+                        acc.y += wgt.x * x.y + wgt.y * x.x;
+                    }
+                    // wgt <- wgt * (i tau1) / (p + 1)
+                    const float sc1 = tau1 / (float)(p + 1);
+                    wgt = make_float2(-wgt.y * sc1, wgt.x * sc1);
+                }
+                Bs[idx] = acc;
+            }
+            __syncthreads();
+            if (hcnt > 0) {
+                int sp = s0;
+                while (sp < s1) {
+                    const int c = P.class_of[sp];
+                    int se = sp + 1;
+                    while (se < s1 && P.class_of[se] == c) ++se;
+                    float2 D[N + 1];
+#pragma unroll
+                    for (int r = 0; r <= N; ++r) D[r] = make_float2(0.f, 0.f);
+                    for (int sl = sp - s0; sl < se - s0; ++sl) {
+                        const int mu = P.site_of[s0 + sl];
+                        const float2 ph = cmulf(P.tab2[(size_t)mu * P.cnt[1] + i2],
+                                                P.tabK3[(size_t)mu * n3 + k3]);
+                        const float2* Bp = Bs + (size_t)sl * QR * n3 + k3;
+#pragma unroll
+                        for (int r = 0; r <= N; ++r) {
+                            float2 C = make_float2(0.f, 0.f);
+#pragma unroll
+                            for (int q = 0; q + r <= N; ++q) {
+                                const float2 v = Bp[pair_index(q, r) * n3];
+                                const float a = a2[q];
+                                // C += i^q a v
+                                if ((q & 3) == 0) { C.x += a * v.x; C.y += a * v.y; }
+                                else if ((q & 3) == 1) { C.x -= a * v.y; C.y += a * v.x; }
+                                else if ((q & 3) == 2) { C.x -= a * v.x; C.y -= a * v.y; }
+                                else { C.x += a * v.y; C.y -= a * v.x; }
+                            }
+                            const float2 pc = cmulf(ph, C);
+                            D[r].x += pc.x * inv_factorial(r);
+                            D[r].y += pc.y * inv_factorial(r);
+                        }
+                    }
+                    const float2* tH = P.tabH3 + (size_t)c * P.nH3span - P.H3min;
+#pragma unroll
+                    for (int h = 0; h < HC; ++h) {
+                        if (h < hcnt) {
+                            const int H3 = H3lo + hbeg + h;
+                            const float t3 = (float)(k3 + n3 * H3) * c3;
+                            float2 acc = D[N];
+#pragma unroll
+                            for (int r = N - 1; r >= 0; --r)
+                                acc = make_float2(D[r].x - t3 * acc.y, D[r].y + t3 * acc.x);
+                            const float2 e3 = tH[H3];
+                            F[h].x += e3.x * acc.x - e3.y * acc.y;
+                            F[h].y += e3.x * acc.y + e3.y * acc.x;
+                        }
+                    }
+                    sp = se;
+                }
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < HC; ++h) I[h] += F[h].x * F[h].x + F[h].y * F[h].y;
+    }
+    if (hcnt > 0) {
+        float* orow = P.out + ((size_t)w.i1 * P.cnt[1] + i2) * P.cnt[2];
+#pragma unroll
+        for (int h = 0; h < HC; ++h) {
+            if (h < hcnt) {
+                const int G3 = k3 + n3 * (H3lo + hbeg + h);
+                orow[G3 - P.g0[2]] = I[h] * P.scale;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------- magnetic
+__device__ __forceinline__ float mag_ff(const float* f, float s2) {
+    return f[0] * expf(-f[1] * s2) + f[2] * expf(-f[3] * s2) + f[4] * expf(-f[5] * s2) + f[6];
+}
+
+template <int HC>
+__global__ __launch_bounds__(512) void k_recombine_magnetic(RecombParams P)
+{
+    extern __shared__ float2 Bs[];
+    BlockWork w;
+    if (!decode_block(P, w)) return;
+    const int n1 = P.n1, n2 = P.n2, n3 = P.n3, nh = P.nh;
+    const int SFnh = P.SF * nh;
+    const int nitems = (w.h2b - w.h2a) * n3 * P.nchunk3;
+    const int item = threadIdx.x;
+    const bool active = item < nitems;
+    int k3 = 0, ch = 0, h2 = w.h2a;
+    if (active) {
+        k3 = item % n3;
+        const int r = item / n3;
+        ch = r % P.nchunk3;
+        h2 = w.h2a + r / P.nchunk3;
+    }
+    const int G2 = w.k2 + n2 * (w.H2lo + h2);
+    const int i2 = G2 - P.g0[1];
+    int H3lo, nH3;
+    hrange(k3, n3, P.g0[2], P.cnt[2], H3lo, nH3);
+    const int hbeg = ch * HC;
+    const int hcnt = active ? max(0, min(HC, nH3 - hbeg)) : 0;
+    // Cartesian Q = g1 a* + g2 b* + g3 c*
+    const float g1 = (float)((double)w.G1 / (double)n1);
+    const float g2 = (float)((double)G2 / (double)n2);
+    const float q12x = g1 * P.recip[0] + g2 * P.recip[3];
+    const float q12y = g1 * P.recip[1] + g2 * P.recip[4];
+    const float q12z = g1 * P.recip[2] + g2 * P.recip[5];
+    const float inv16pi2 = 1.f / (16.f * 9.8696044010893586f);
+
+    float I[HC];
+#pragma unroll
+    for (int h = 0; h < HC; ++h) I[h] = 0.f;
+    const size_t col = ((size_t)w.k1 * n2 + w.k2) * SFnh;
+    const size_t colm = ((size_t)((n1 - w.k1) % n1) * n2 + (n2 - w.k2) % n2) * SFnh;
+
+    for (int m = 0; m < P.M; ++m) {
+        float2 F[HC][3];
+#pragma unroll
+        for (int h = 0; h < HC; ++h)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) F[h][c] = make_float2(0.f, 0.f);
+        const float2* Xm = P.X + (size_t)m * n1 * n2 * SFnh;
+        for (int sc = 0; sc < P.nsc; ++sc) {
+            const int s0 = P.sc_start[sc], s1 = P.sc_start[sc + 1];
+            const int ns = s1 - s0;
+            __syncthreads();
+            for (int idx = threadIdx.x; idx < ns * 3 * n3; idx += blockDim.x) {
+                const int kk = idx % n3;
+                const int rj = idx / n3;
+                const int comp = rj % 3;
+                const int sl = rj / 3;
+                const int mu = P.site_of[s0 + sl];
+                float2 x;
+                if (kk < nh) x = Xm[col + (size_t)(mu * 3 + comp) * nh + kk];
+                else { x = Xm[colm + (size_t)(mu * 3 + comp) * nh + (n3 - kk)]; x.y = -x.y; }
+                Bs[idx] = cmulf(P.tab1[(size_t)mu * P.cnt[0] + w.i1], x);
+            }
+            __syncthreads();
+            if (hcnt > 0) {
+                int sp = s0;
+                while (sp < s1) {
+                    const int c = P.class_of[sp];
+                    int se = sp + 1;
+                    while (se < s1 && P.class_of[se] == c) ++se;
+                    float2 D[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+                    for (int sl = sp - s0; sl < se - s0; ++sl) {
+                        const int mu = P.site_of[s0 + sl];
+                        const float2 ph = cmulf(P.tab2[(size_t)mu * P.cnt[1] + i2],
+                                                P.tabK3[(size_t)mu * n3 + k3]);
+                        const float2* Bp = Bs + (size_t)sl * 3 * n3 + k3;
+#pragma unroll
+                        for (int comp = 0; comp < 3; ++comp) {
+                            const float2 v = cmulf(ph, Bp[comp * n3]);
+                            D[comp].x += v.x;
+                            D[comp].y += v.y;
+                        }
+                    }
+                    const float2* tH = P.tabH3 + (size_t)c * P.nH3span - P.H3min;
+                    const float* ffc = P.ff[sp];
+#pragma unroll
+                    for (int h = 0; h < HC; ++h) {
+                        if (h < hcnt) {
+                            const int H3 = H3lo + hbeg + h;
+                            float2 e3 = tH[H3];
+                            if (!P.ff_uniform) {
+                                const float g3 = (float)(k3 + n3 * H3) / (float)n3;
+                                const float qx = q12x + g3 * P.recip[6], qy = q12y + g3 * P.recip[7],
+                                            qz = q12z + g3 * P.recip[8];
+                                const float f = mag_ff(ffc, (qx * qx + qy * qy + qz * qz) * inv16pi2);
+                                e3.x *= f; e3.y *= f;
+                            }
+#pragma unroll
+                            for (int comp = 0; comp < 3; ++comp) {
+                                F[h][comp].x += e3.x * D[comp].x - e3.y * D[comp].y;
+                                F[h][comp].y += e3.x * D[comp].y + e3.y * D[comp].x;
+                            }
+                        }
+                    }
+                    sp = se;
+                }
+            }
+        }
+        // perpendicular projection and |F_perp|^2
+#pragma unroll
+        for (int h = 0; h < HC; ++h) {
+            if (h < hcnt) {
+                const int H3 = H3lo + hbeg + h;
+                const float g3 = (float)(k3 + n3 * H3) / (float)n3;
+                const float qx = q12x + g3 * P.recip[6], qy = q12y + g3 * P.recip[7],
+                            qz = q12z + g3 * P.recip[8];
+                const float q2 = qx * qx + qy * qy + qz * qz;
+                if (q2 > 0.f) {
+                    const float iq = rsqrtf(q2);
+                    const float ex = qx * iq, ey = qy * iq, ez = qz * iq;
+                    const float px = ex * F[h][0].x + ey * F[h][1].x + ez * F[h][2].x;
+                    const float py = ex * F[h][0].y + ey * F[h][1].y + ez * F[h][2].y;
+                    float v = 0.f;
+#pragma unroll
+                    for (int comp = 0; comp < 3; ++comp)
+                        v += F[h][comp].x * F[h][comp].x + F[h][comp].y * F[h][comp].y;
+                    v -= px * px + py * py;
+                    if (P.ff_uniform) {
+                        const float f = mag_ff(P.ff[0], q2 * inv16pi2);
+                        v *= f * f;
+                    }
+                    I[h] += v;
+                }
+            }
+        }
+    }
+    if (hcnt > 0) {
+        float* orow = P.out + ((size_t)w.i1 * P.cnt[1] + i2) * P.cnt[2];
+#pragma unroll
+        for (int h = 0; h < HC; ++h) {
+            if (h < hcnt) {
+                const int G3 = k3 + n3 * (H3lo + hbeg + h);
+                orow[G3 - P.g0[2]] = I[h] * P.scale;
+            }
+        }
+    }
+}
+
+int recombine_max_threads(int hc, int magnetic)
+{
+    if (magnetic) return 512;
+    return hc <= 17 ? 1024 : 512;
+}
+
+template <int N, int HC>
+static hipError_t launch_nuc(const RecombParams& p, int block, size_t lds, hipStream_t st)
+{
+    const int grid = 8 * ((p.nblocks + 7) / 8);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_recombine_nuclear<N, HC>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_recombine_nuclear<N, HC>), dim3(grid), dim3(block), lds, st, p);
+    return hipGetLastError();
+}
+
+template <int N>
+static hipError_t launch_nuc_hc(const RecombParams& p, int hc, int block, size_t lds, hipStream_t st)
+{
+    switch (hc) {
+        case 4: return launch_nuc<N, 4>(p, block, lds, st);
+        case 8: return launch_nuc<N, 8>(p, block, lds, st);
+        case 17: return launch_nuc<N, 17>(p, block, lds, st);
+        case 32: return launch_nuc<N, 32>(p, block, lds, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_recombine_nuclear(const RecombParams& p, int order, int hc, int block,
+                                    size_t lds, hipStream_t st)
+{
+    switch (order) {
+        case 0: return launch_nuc_hc<0>(p, hc, block, lds, st);
+        case 1: return launch_nuc_hc<1>(p, hc, block, lds, st);
+        case 2: return launch_nuc_hc<2>(p, hc, block, lds, st);
+        case 3: return launch_nuc_hc<3>(p, hc, block, lds, st);
+        case 4: return launch_nuc_hc<4>(p, hc, block, lds, st);
+        case 5: return launch_nuc_hc<5>(p, hc, block, lds, st);
+        case 6: return launch_nuc_hc<6>(p, hc, block, lds, st);
+        case 7: return launch_nuc_hc<7>(p, hc, block, lds, st);
+        case 8: return launch_nuc_hc<8>(p, hc, block, lds, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_recombine_magnetic(const RecombParams& p, int hc, int block, size_t lds,
+                                     hipStream_t st)
+{
+    const int grid = 8 * ((p.nblocks + 7) / 8);
+    switch (hc) {
+        case 4: hipLaunchKernelGGL((k_recombine_magnetic<4>), dim3(grid), dim3(block), lds, st, p); break;
+        case 8: hipLaunchKernelGGL((k_recombine_magnetic<8>), dim3(grid), dim3(block), lds, st, p); break;
+        case 17: hipLaunchKernelGGL((k_recombine_magnetic<17>), dim3(grid), dim3(block), lds, st, p); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------- Bragg, float64
+template <int N>
+__global__ __launch_bounds__(256) void k_bragg_nuclear(BraggParams P)
+{
+    constexpr int T = n_monomials(N);
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int total = P.nH[0] * P.nH[1] * P.nH[2];
+    if (idx >= total) return;
+    const int j3 = idx % P.nH[2], j2 = (idx / P.nH[2]) % P.nH[1], j1 = idx / (P.nH[2] * P.nH[1]);
+    const int H[3] = {P.Hlo[0] + j1, P.Hlo[1] + j2, P.Hlo[2] + j3};
+    // (2 pi i H_a)^k / k! per axis
+    double Ar[3][N + 1], Ai[3][N + 1];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        Ar[a][0] = 1.0; Ai[a][0] = 0.0;
+        const double t = 6.283185307179586476925 * (double)H[a];
+#pragma unroll
+        for (int k = 1; k <= N; ++k) {
+            Ar[a][k] = -Ai[a][k - 1] * t / k;
+            Ai[a][k] = Ar[a][k - 1] * t / k;
+        }
+    }
+    double sq = 0.0, mr = 0.0, mi = 0.0;
+    for (int m = 0; m < P.M; ++m) {
+        double fr = 0.0, fi = 0.0;
+        for (int mu = 0; mu < P.S; ++mu) {
+            const double* Sm = P.sums + ((size_t)m * P.S + mu) * T;
+            double sr = 0.0, si = 0.0;
+#pragma unroll
+            for (int dg = 0; dg <= N; ++dg)
+#pragma unroll
+                for (int p = dg; p >= 0; --p)
+#pragma unroll
+                    for (int q = dg - p; q >= 0; --q) {
+                        const int r = dg - p - q;
+                        // coefficient A1[p] A2[q] A3[r]
+                        const double xr = Ar[0][p] * Ar[1][q] - Ai[0][p] * Ai[1][q];
+                        const double xi = Ar[0][p] * Ai[1][q] + Ai[0][p] * Ar[1][q];
+                        const double cr = xr * Ar[2][r] - xi * Ai[2][r];
+                        const double ci = xr * Ai[2][r] + xi * Ar[2][r];
+                        const double s = Sm[mono_index(p, q, r)];
+                        sr += cr * s;
+                        si += ci * s;
+                    }
+            const double* sd = P.site + 11 * mu;
+            double x = H[0] * sd[0] + H[1] * sd[1] + H[2] * sd[2];
+            x -= floor(x);
+            double sn, cs;
+            sincos(6.283185307179586476925 * x, &sn, &cs);
+            fr += sd[3] * (cs * sr - sn * si);
+            fi += sd[3] * (cs * si + sn * sr);
+        }
+        sq += fr * fr + fi * fi;
+        mr += fr; mi += fi;
+    }
+    mr /= P.M; mi /= P.M;
+    const double I = (sq / P.M - (mr * mr + mi * mi)) * P.scale;
+    const int G[3] = {P.n[0] * H[0], P.n[1] * H[1], P.n[2] * H[2]};
+    P.out[((size_t)(G[0] - P.g0[0]) * P.cnt[1] + (G[1] - P.g0[1])) * P.cnt[2] + (G[2] - P.g0[2])] = (float)I;
+}
+
+__device__ double mag_ff_d(const double* f, double s2) {
+    return f[0] * exp(-f[1] * s2) + f[2] * exp(-f[3] * s2) + f[4] * exp(-f[5] * s2) + f[6];
+}
+
+__global__ __launch_bounds__(256) void k_bragg_magnetic(BraggParams P)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int total = P.nH[0] * P.nH[1] * P.nH[2];
+    if (idx >= total) return;
+    const int j3 = idx % P.nH[2], j2 = (idx / P.nH[2]) % P.nH[1], j1 = idx / (P.nH[2] * P.nH[1]);
+    const int H[3] = {P.Hlo[0] + j1, P.Hlo[1] + j2, P.Hlo[2] + j3};
+    const int G[3] = {P.n[0] * H[0], P.n[1] * H[1], P.n[2] * H[2]};
+    float* o = P.out + ((size_t)(G[0] - P.g0[0]) * P.cnt[1] + (G[1] - P.g0[1])) * P.cnt[2] + (G[2] - P.g0[2]);
+    double Q[3];
+    for (int c = 0; c < 3; ++c) Q[c] = H[0] * P.recip[c] + H[1] * P.recip[3 + c] + H[2] * P.recip[6 + c];
+    const double q2 = Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2];
+    if (!(q2 > 0.0)) { *o = 0.f; return; }
+    const double iq = 1.0 / sqrt(q2);
+    const double e[3] = {Q[0] * iq, Q[1] * iq, Q[2] * iq};
+    const double s2 = q2 / (16.0 * 9.869604401089358618834);
+    double sq = 0.0, mr[3] = {0, 0, 0}, mi[3] = {0, 0, 0};
+    for (int m = 0; m < P.M; ++m) {
+        double fr[3] = {0, 0, 0}, fi[3] = {0, 0, 0};
+        for (int mu = 0; mu < P.S; ++mu) {
+            const double* sd = P.site + 11 * mu;
+            double x = H[0] * sd[0] + H[1] * sd[1] + H[2] * sd[2];
+            x -= floor(x);
+            double sn, cs;
+            sincos(6.283185307179586476925 * x, &sn, &cs);
+            const double f = P.has_ff ? mag_ff_d(sd + 4, s2) : 1.0;
+            const double* Sm = P.sums + ((size_t)m * P.S + mu) * 3;
+            for (int c = 0; c < 3; ++c) {
+                const double w = sd[3] * f * Sm[c];
+                fr[c] += w * cs;
+                fi[c] += w * sn;
+            }
+        }
+        const double pr = e[0] * fr[0] + e[1] * fr[1] + e[2] * fr[2];
+        const double pi = e[0] * fi[0] + e[1] * fi[1] + e[2] * fi[2];
+        for (int c = 0; c < 3; ++c) {
+            const double ar = fr[c] - e[c] * pr, ai = fi[c] - e[c] * pi;
+            sq += ar * ar + ai * ai;
+            mr[c] += ar; mi[c] += ai;
+        }
+    }
+    double mm = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        mr[c] /= P.M; mi[c] /= P.M;
+        mm += mr[c] * mr[c] + mi[c] * mi[c];
+    }
+    *o = (float)((sq / P.M - mm) * P.scale);
+}
+
+template <int N>
+static hipError_t launch_bragg_t(const BraggParams& p, int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bragg_nuclear<N>, dim3(grid), dim3(256), 0, st, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_bragg(const BraggParams& p, int order, hipStream_t st)
+{
+    const int total = p.nH[0] * p.nH[1] * p.nH[2];
+    if (total <= 0) return hipSuccess;
+    const int grid = (total + 255) / 256;
+    if (p.kind == 1) {
+        hipLaunchKernelGGL(k_bragg_magnetic, dim3(grid), dim3(256), 0, st, p);
+        return hipGetLastError();
+    }
+    switch (order) {
+        case 0: return launch_bragg_t<0>(p, grid, st);
+        case 1: return launch_bragg_t<1>(p, grid, st);
+        case 2: return launch_bragg_t<2>(p, grid, st);
+        case 3: return launch_bragg_t<3>(p, grid, st);
+        case 4: return launch_bragg_t<4>(p, grid, st);
+        case 5: return launch_bragg_t<5>(p, grid, st);
+        case 6: return launch_bragg_t<6>(p, grid, st);
+        case 7: return launch_bragg_t<7>(p, grid, st);
+        case 8: return launch_bragg_t<8>(p, grid, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace dsx

@@ -1,0 +1,61 @@
+"""Test glue: hand a synthetic model to the HIP library through the C-ABI binding."""
+import numpy as np
+
+import paper_1809_07088_amd as dsx
+
+
+def desc_kwargs(model):
+    return dict(cell=model.cell, n=model.n, frac=model.frac, b=model.b, kind=model.kind,
+                taylor_order=model.order if model.kind == dsx.NUCLEAR else 0,
+                n_configs=model.n_configs, has_occ=model.occ is not None, ff=model.ff,
+                pos_id=model.pos_id, norm_N=model.norm_N)
+
+
+def to_dsx(model, device=True):
+    """Create a dsx model and upload every configuration (torch device tensors or host)."""
+    import torch
+    h = dsx.Model(**desc_kwargs(model))
+    for m in range(model.n_configs):
+        arrs = []
+        for a in (model.occ, model.disp, model.spin):
+            if a is None:
+                arrs.append(None)
+            elif device:
+                arrs.append(torch.from_numpy(np.ascontiguousarray(a[m])).cuda())
+            else:
+                arrs.append(np.ascontiguousarray(a[m]))
+        h.set_sites(m, *arrs)
+    h.set_grid(model.g0, model.count)
+    return h
+
+
+def gpu_intensity(model, device=True):
+    import torch
+    h = to_dsx(model, device)
+    if device:
+        out = torch.empty(tuple(model.count), dtype=torch.float32, device="cuda")
+        h.compute_intensity(out)
+        torch.cuda.synchronize()
+        res = out.cpu().numpy()
+    else:
+        res = np.empty(tuple(model.count), dtype=np.float32)
+        h.compute_intensity(res)
+    h.close()
+    return res
+
+
+def gpu_filtered(model, m, s=1):
+    import torch
+    h = to_dsx(model)
+    out = torch.empty(tuple(s * c for c in model.count), dtype=torch.float32, device="cuda")
+    h.noise_filter(m, s, out)
+    torch.cuda.synchronize()
+    res = out.cpu().numpy()
+    h.close()
+    return res
+
+
+def rel_l2(a, ref):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    ref = np.asarray(ref, dtype=np.float64).ravel()
+    return float(np.linalg.norm(a - ref) / np.linalg.norm(ref))

@@ -1,0 +1,87 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared symbol, and its
+host-only planner counts fields and validates descriptions (no GPU calls)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1809_07088_amd as dsx
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    with open(os.path.join(ROOT, "include", "dsx.h")) as f:
+        src = f.read()
+    return sorted(set(re.findall(r"^\s*(?:dsx_status|const char\*|int32_t)\s+(dsx_\w+)\s*\(", src, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = dsx.lib()
+    syms = declared_symbols()
+    assert len(syms) >= 9
+    for s in syms:
+        assert hasattr(L, s), s
+    assert set(syms) == set(dsx.EXPORTS)
+    assert dsx.version() >= 100
+
+
+def golden(key):
+    with open(os.path.join(ROOT, "tests", "golden", "paper_values.txt")) as f:
+        for line in f:
+            if line.split() and line.split()[0] == key:
+                return float(line.split()[1])
+    raise KeyError(key)
+
+
+def test_field_counts_match_paper():
+    fcc = dict(cell=[1, 1, 1, 90, 90, 90], n=(8, 8, 8), frac=synth.FCC_BASIS, b=synth.FCC_B)
+    info = dsx.plan_query(**fcc, taylor_order=5)
+    assert info.fields_per_site == golden("ffts_fifth_order_total")        # 55
+    assert dsx.plan_query(**fcc, taylor_order=5, has_occ=True).fields_per_site == 56
+    for n in range(0, 9):
+        full = dsx.plan_query(**fcc, taylor_order=n, has_occ=True).fields_per_site
+        assert full == (n + 1) * (n + 2) * (n + 3) // 6
+    info = dsx.plan_query(**fcc, taylor_order=8, n_configs=3)
+    assert info.fields_per_site == 164 and info.total_fields == 3 * 4 * 164
+    assert info.n_classes == 2                       # r_mu3 in {0, 1/2}
+    assert info.spectrum_bytes == 3 * 8 * 8 * 4 * 164 * 5 * 8
+
+
+def test_magnetic_plan_and_classes():
+    pyro = synth.pyrochlore_sites()
+    info = dsx.plan_query(cell=[10, 10, 10, 90, 90, 90], n=(24, 24, 24), frac=pyro, b=np.ones(16),
+                          kind=dsx.MAGNETIC, ff=np.tile(synth.MAG_FF, (16, 1)))
+    assert info.fields_per_site == 3
+    assert info.n_classes == 4                       # r_mu3 in {0, 1/4, 1/2, 3/4}
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(n=(0, 4, 4)), dsx.ERR_ARG),
+    (dict(n=(4, 4, 129)), dsx.ERR_UNSUPPORTED),
+    (dict(taylor_order=9), dsx.ERR_UNSUPPORTED),
+    (dict(taylor_order=-1), dsx.ERR_ARG),
+    (dict(n_configs=0), dsx.ERR_ARG),
+    (dict(cell=[1, 1, 1, 90, 90, 200]), dsx.ERR_ARG),
+    (dict(cell=[0, 1, 1, 90, 90, 90]), dsx.ERR_ARG),
+    (dict(kind=dsx.MAGNETIC, taylor_order=2), dsx.ERR_UNSUPPORTED),
+    (dict(kind=7), dsx.ERR_ARG),
+    (dict(taylor_order=0, has_occ=False), dsx.ERR_ARG),
+    (dict(norm_N=-1.0), dsx.ERR_ARG),
+])
+def test_plan_query_rejects_bad_descriptions(kw, status):
+    base = dict(cell=[1, 1, 1, 90, 90, 90], n=(4, 4, 4), frac=[[0, 0, 0]], b=[1.0], taylor_order=2)
+    base.update(kw)
+    with pytest.raises(dsx.DsxError) as e:
+        dsx.plan_query(**base)
+    assert e.value.status == status
+    assert dsx.last_error() != ""
+
+
+def test_too_many_sites_unsupported():
+    with pytest.raises(dsx.DsxError) as e:
+        dsx.plan_query(cell=[1, 1, 1, 90, 90, 90], n=(4, 4, 4), frac=np.zeros((65, 3)), b=np.ones(65),
+                       taylor_order=1)
+    assert e.value.status == dsx.ERR_UNSUPPORTED

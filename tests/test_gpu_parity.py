@@ -1,0 +1,186 @@
+"""GPU parity: the HIP path through the C-ABI against the FP64 oracle.
+
+Tolerance: relative L2 <= 1e-5 over every compared voxel (float32 FFT and
+recombination, float64 Bragg points), the bar the path is built to.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import oracle as O
+from tests.helpers import desc_kwargs, gpu_filtered, gpu_intensity, rel_l2, to_dsx
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def say(msg):
+    print(f"[gpu case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_1809_07088_amd as dsx
+    dsx.lib()
+    yield
+
+
+# ------------------------------------------------------------------ compositional, full grid
+
+@pytest.mark.parametrize("M", [1, 4])
+def test_compositional_simple_cubic_full_grid(M):
+    m = synth.compositional(n=12, M=M, hmax=2)
+    say(f"compositional n=12 M={M} box={m.count}")
+    I = gpu_intensity(m)
+    ref = O.intensity(m).reshape(m.count)
+    err = rel_l2(I, ref)
+    print("rel L2", err)
+    assert err <= TOL
+    if M == 1:   # Parseval on the GPU output: mean = c (1 - c)
+        c = float(m.occ.astype(np.float64).mean())
+        assert abs(I.astype(np.float64).mean() - c * (1 - c)) < 1e-6
+
+
+# ------------------------------------------------------------------ displacive, every order
+
+@pytest.mark.parametrize("order", list(range(0, 9)))
+def test_random_model_every_order_full_box(order):
+    m = synth.random_model(100 + order, n=(6, 5, 8), S=3, M=2, order=order)
+    m.g0, m.count = (-7, -9, -10), (15, 13, 21)       # several zones, ragged on every axis
+    say(f"random model order={order} n={m.n} box={m.count}")
+    I = gpu_intensity(m)
+    ref = O.intensity(m, O.grid_points(m.g0, m.count), order).reshape(m.count)
+    err = rel_l2(I, ref)
+    print("rel L2", err)
+    assert err <= TOL
+
+
+@pytest.mark.parametrize("n", [(7, 11, 9), (1, 4, 3), (5, 3, 1), (16, 2, 10)])
+def test_odd_prime_and_degenerate_edges(n):
+    m = synth.random_model(200 + sum(n), n=n, S=2, M=1, order=3)
+    m.g0 = tuple(-v - 1 for v in n)
+    m.count = tuple(2 * v + 3 for v in n)
+    say(f"edge n={n} box={m.count}")
+    I = gpu_intensity(m)
+    ref = O.intensity(m, O.grid_points(m.g0, m.count), 3).reshape(m.count)
+    assert rel_l2(I, ref) <= TOL
+
+
+def test_box_smaller_than_supercell_without_bragg_points():
+    m = synth.random_model(300, n=(8, 8, 8), S=2, M=2, order=2)
+    m.g0, m.count = (3, 1, 2), (3, 4, 5)
+    say("small box, no k = 0 point")
+    I = gpu_intensity(m)
+    ref = O.intensity(m, O.grid_points(m.g0, m.count), 2).reshape(m.count)
+    assert rel_l2(I, ref) <= TOL
+
+
+def test_fcc_no_occupancy_shares_r3_classes():
+    m = synth.displacive(n=8, M=3, order=6, hmax=2)
+    say("fcc n=8 order 6 M=3")
+    I = gpu_intensity(m)
+    ref = O.intensity(m, O.grid_points(m.g0, m.count), 6).reshape(m.count)
+    assert rel_l2(I, ref) <= TOL
+    assert np.allclose(I, I[::-1, ::-1, ::-1], rtol=1e-4, atol=1e-6 * np.abs(I).max())
+
+
+# ------------------------------------------------------------------ magnetic
+
+def test_magnetic_random_noncubic_full_box():
+    m = synth.random_model(400, n=(4, 5, 6), S=3, M=2, kind=synth.MAGNETIC,
+                           cell=[7.0, 8.0, 9.0, 80.0, 95.0, 100.0])
+    m.g0, m.count = (-5, -6, -8), (11, 12, 17)
+    say("magnetic random non-cubic")
+    I = gpu_intensity(m)
+    ref = O.intensity(m, O.grid_points(m.g0, m.count)).reshape(m.count)
+    assert rel_l2(I, ref) <= TOL
+
+
+def test_magnetic_per_site_form_factors():
+    m = synth.random_model(401, n=(4, 4, 5), S=3, M=1, kind=synth.MAGNETIC,
+                           cell=[6.0, 6.0, 6.0, 90.0, 90.0, 90.0])
+    m.ff = np.array([[0.4, 20, 0.5, 7, 0.1, 2, 0.0], [0.3, 10, 0.6, 3, 0.1, 1, 0.0],
+                     [1.0, 5, 0, 0, 0, 0, 0.0]])
+    m.g0, m.count = (-6, -5, -7), (13, 11, 15)
+    say("magnetic per-site form factors")
+    I = gpu_intensity(m)
+    ref = O.intensity(m, O.grid_points(m.g0, m.count)).reshape(m.count)
+    assert rel_l2(I, ref) <= TOL
+
+
+# ------------------------------------------------------------------ Lanczos filter
+
+@pytest.mark.parametrize("lm,s", [(2, 1), (4, 1), (2, 2), (3, 3)])
+def test_lanczos_filter_matches_direct_window(lm, s):
+    m = synth.random_model(500 + lm, n=(5, 6, 4), S=2, M=2, order=2)
+    m.g0, m.count = (-4, -5, -3), (9, 11, 8)
+    say(f"lanczos m={lm} s={s}")
+    out = gpu_filtered(m, lm, s)
+    ref = O.filtered_intensity(m, lm, s, order=2)
+    assert out.shape == ref.shape
+    assert rel_l2(out, ref) <= TOL
+
+
+# ------------------------------------------------------------------ ABI behaviour on the GPU
+
+def test_host_and_device_outputs_identical_and_deterministic():
+    m = synth.random_model(600, n=(6, 6, 6), S=2, M=2, order=4)
+    say("host vs device output, determinism")
+    a = gpu_intensity(m, device=True)
+    b = gpu_intensity(m, device=False)
+    c = gpu_intensity(m, device=True)
+    assert np.array_equal(a, c)
+    assert np.array_equal(a, b)
+
+
+def test_state_errors():
+    import torch
+    import paper_1809_07088_amd as dsx
+    m = synth.random_model(601, n=(4, 4, 4), S=1, M=2, order=1)
+    say("state errors")
+    h = dsx.Model(**desc_kwargs(m))
+    out = torch.empty(tuple(m.count), device="cuda")
+    with pytest.raises(dsx.DsxError) as e:
+        h.compute_intensity(out)
+    assert e.value.status == dsx.ERR_STATE
+    h.set_sites(0, torch.from_numpy(m.occ[0]).cuda(), torch.from_numpy(m.disp[0]).cuda())
+    with pytest.raises(dsx.DsxError) as e:
+        h.set_sites(2, torch.from_numpy(m.occ[0]).cuda(), torch.from_numpy(m.disp[0]).cuda())
+    assert e.value.status == dsx.ERR_ARG
+    with pytest.raises(dsx.DsxError) as e:
+        h.set_sites(1, torch.from_numpy(m.occ[1]).cuda(), None)
+    assert e.value.status == dsx.ERR_ARG
+    h.set_sites(1, torch.from_numpy(m.occ[1]).cuda(), torch.from_numpy(m.disp[1]).cuda())
+    with pytest.raises(dsx.DsxError) as e:
+        h.compute_intensity(out)          # no grid yet
+    assert e.value.status == dsx.ERR_STATE
+    h.set_grid(m.g0, m.count)
+    with pytest.raises(dsx.DsxError) as e:
+        h.noise_filter(1, 1, out)
+    assert e.value.status == dsx.ERR_ARG
+    h.compute_intensity(out)
+    torch.cuda.synchronize()
+    ref = O.intensity(m).reshape(m.count)
+    assert rel_l2(out.cpu().numpy(), ref) <= TOL
+    h.close()
+
+
+def test_set_sites_marks_spectra_stale():
+    import torch
+    m = synth.random_model(602, n=(5, 4, 6), S=2, M=1, order=2)
+    m2 = synth.random_model(603, n=(5, 4, 6), S=2, M=1, order=2)
+    m2.frac, m2.b = m.frac, m.b
+    say("set_sites invalidates spectra")
+    h = to_dsx(m)
+    out = torch.empty(tuple(m.count), device="cuda")
+    h.compute_intensity(out)
+    h.set_sites(0, torch.from_numpy(m2.occ[0]).cuda(), torch.from_numpy(m2.disp[0]).cuda())
+    h.compute_intensity(out)
+    torch.cuda.synchronize()
+    assert rel_l2(out.cpu().numpy(), O.intensity(m2).reshape(m.count)) <= TOL
+    h.close()
