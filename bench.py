@@ -1,0 +1,227 @@
+#!/usr/bin/env python
+"""Throughput benchmark of the diffuse-scattering hot path on one MI355X.
+
+Workload (displacive disorder): fcc-type basis with 4 sites per cell and
+scattering lengths {1.0, 0.7, 0.7, 0.7}, a 32^3 supercell (131072 atoms),
+Gaussian displacements of sigma = 0.05 a smoothed by a periodic Gaussian of
+width 1.5 cells, Taylor order 8, every supercell Bragg point G with
+|h|,|k|,|l| <= 8 (513^3 voxels).  Synthetic, seeded inputs.
+
+One step is one pass of the whole hot path over the resident inputs:
+  set_sites (device copy) -> float64 lattice sums -> field generation + 3D FFTs
+  -> recombination on the box grown by the Lanczos window -> float64 Bragg
+  points -> Lanczos filter (m = 2) into the 513^3 output.
+value = output voxels x configurations per second.
+
+Besides the JSON line fields of the contract it reports:
+  roofline      the dominant kernel (recombination) measured with HIP events on
+                its own stream over the timed region, against its algorithmic
+                flops and bytes per launch;
+  cpu_baseline  the FP64 oracle (direct sum, OpenMP) on a bounded seeded voxel
+                sample of the same workload, scaled to voxels/s;
+  parity        relative L2 of the GPU I(G) against the oracle on that sample.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "diffuse-intensity voxels/s at ≤1e-5 rel L2 vs FP64; p50/p99 request latency"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_PEAK_TFLOPS = 157.3       # MI355X published FP32 vector peak
+
+
+def hcount(k, n, g0, cnt):
+    """Number of H with g0 <= k + n H < g0 + cnt."""
+    lo = -((k - g0) // n)
+    hi = (g0 + cnt - 1 - k) // n
+    return max(0, hi - lo + 1)
+
+
+def recombine_work(n, S, nclass3, N, M, g0, cnt, nh, F):
+    """Algorithmic flops and bytes of one recombination launch over the box (g0, cnt).
+
+    flops: the sum-factorised evaluation --
+      level C  per voxel and r3 class: Horner (4N) + class phase (8); |F|^2 (4)
+      level B  per (G1, G2, k3) and site: 4 QR (q sums) + 10 (N+1) + 6
+      level A  per (G1, k2) column, site and k3: 10 flops per Taylor term
+    bytes: float32 output written once + every half spectrum read once."""
+    QR = (N + 1) * (N + 2) // 2
+    T = (N + 1) * (N + 2) * (N + 3) // 6
+    V = int(np.prod(cnt))
+    rows12 = cnt[0] * cnt[1]
+    items = sum(1 for k3 in range(n[2]) if hcount(k3, n[2], g0[2], cnt[2]) > 0) * rows12
+    cols = cnt[0] * sum(1 for k2 in range(n[1]) if hcount(k2, n[1], g0[1], cnt[1]) > 0)
+    fl_c = V * (nclass3 * (4 * N + 8) + 4)
+    fl_b = items * S * (4 * QR + 10 * (N + 1) + 6)
+    fl_a = cols * S * n[2] * 10 * T
+    flops = M * (fl_a + fl_b + fl_c)
+    bytes_ = 4 * V + M * n[0] * n[1] * S * F * nh * 8
+    return flops, bytes_
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--order", type=int, default=8)
+    ap.add_argument("--lanczos-m", type=int, default=2)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sweep", action="store_true", help="also time compute_intensity for orders 1..8")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs the hot path on one GPU; --gpus must be 1 "
+              "(the multi-GPU sharding is a design note, not implemented)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1809_07088_amd as dsx
+    import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    N, lm = args.order, args.lanczos_m
+    model = synth.displacive(n=32, M=1, order=N, hmax=8)
+    n, S, M = model.n, model.n_sites, model.n_configs
+    count = tuple(model.count)
+    voxels = int(np.prod(count)) * M
+    disp_dev = torch.from_numpy(model.disp[0]).to(dev)
+    h = dsx.Model(cell=model.cell, n=n, frac=model.frac, b=model.b, taylor_order=N, n_configs=M)
+    h.set_grid(model.g0, count)
+    out = torch.empty(count, dtype=torch.float32, device=dev)
+    info = dsx.plan_query(cell=model.cell, n=n, frac=model.frac, b=model.b, taylor_order=N, n_configs=M)
+
+    def step():
+        h.set_sites(0, None, disp_dev)
+        h.noise_filter(lm, 1, out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    dsx.profile_reset()
+    dsx.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dsx.profile_enable(False)
+    kstats = dsx.profile_read()
+    sec = (t1 - t0) / args.steps
+    value = voxels / sec
+
+    # dominant kernel: recombination on the grown box
+    ext_g0 = tuple(g - (lm - 1) for g in model.g0)
+    ext_cnt = tuple(c + 2 * lm - 1 for c in count)
+    nclass3 = len(np.unique(model.frac[:, 2]))
+    flops, bytes_ = recombine_work(n, S, nclass3, N, M, ext_g0, ext_cnt, n[2] // 2 + 1,
+                                   info.fields_per_site)
+    launches, tot_ms = kstats.get("recombine", (0, float("nan")))
+    t_launch = tot_ms / max(launches, 1) / 1e3
+    tflops = flops / t_launch / 1e12
+    gbs = bytes_ / t_launch / 1e9
+    alu_bound = flops / (FP32_PEAK_TFLOPS * 1e12) > bytes_ / (HBM_PEAK_GBS * 1e9)
+    if alu_bound:
+        roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(tflops / FP32_PEAK_TFLOPS, 4), "traffic": None}
+    else:
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None}
+    roof.update({"kernel": "recombine", "launch_ms": round(t_launch * 1e3, 4),
+                 "algorithmic_flops_per_launch": int(flops), "algorithmic_bytes_per_launch": int(bytes_),
+                 "achieved_hbm_GBs": round(gbs, 1), "achieved_TFLOPs": round(tflops, 3)})
+    kernels = {k: {"launches": v[0], "avg_ms": round(v[1] / max(v[0], 1), 4)} for k, v in kstats.items()}
+
+    # unfiltered path (compute_intensity) for context
+    for _ in range(2):
+        h.set_sites(0, None, disp_dev)
+        h.compute_intensity(out)
+    torch.cuda.synchronize()
+    u0 = time.perf_counter()
+    for _ in range(args.steps):
+        h.set_sites(0, None, disp_dev)
+        h.compute_intensity(out)
+    torch.cuda.synchronize()
+    unfiltered = voxels / ((time.perf_counter() - u0) / args.steps)
+    I_gpu = out.cpu().numpy()
+
+    sweep = None
+    if args.sweep:
+        sweep = {}
+        for NN in range(1, 9):
+            hm = dsx.Model(cell=model.cell, n=n, frac=model.frac, b=model.b, taylor_order=NN, n_configs=M)
+            hm.set_grid(model.g0, count)
+            hm.set_sites(0, None, disp_dev)
+            for _ in range(2):
+                hm.set_sites(0, None, disp_dev)
+                hm.compute_intensity(out)
+            torch.cuda.synchronize()
+            s0 = time.perf_counter()
+            for _ in range(args.steps):
+                hm.set_sites(0, None, disp_dev)
+                hm.compute_intensity(out)
+            torch.cuda.synchronize()
+            sweep[str(NN)] = round(voxels / ((time.perf_counter() - s0) / args.steps), 1)
+            hm.close()
+
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        rng = np.random.default_rng([2, 0, 777])
+        G_all = lambda k: np.stack([rng.integers(model.g0[a], model.g0[a] + count[a], k)
+                                    for a in range(3)], -1).astype(np.int32)
+        threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+        Gs = G_all(64)
+        c0 = time.perf_counter()
+        O.intensity(model, Gs, N)
+        dt = time.perf_counter() - c0
+        k = int(min(65536, max(64, 64 * args.cpu_seconds / max(dt, 1e-3))))
+        Gs = G_all(k)
+        c0 = time.perf_counter()
+        I_or = O.intensity(model, Gs, N)
+        dt = time.perf_counter() - c0
+        cpu = {"value": round(len(Gs) / dt, 2), "unit": "voxels/s", "cores": threads, "kind": "oracle",
+               "sample": f"{len(Gs)} seeded random G of the 513^3 box, FP64 direct sum over all "
+                         f"131072 atoms, Taylor order {N}, {dt:.1f} s"}
+        idx = tuple((Gs[:, a] - model.g0[a]) for a in range(3))
+        g = I_gpu[idx].astype(np.float64)
+        parity = {"rel_l2_vs_fp64_order_N": float(np.linalg.norm(g - I_or) / np.linalg.norm(I_or)),
+                  "voxels": int(len(Gs))}
+        I_ex = O.intensity(model, Gs[:256], -1)
+        parity["rel_l2_vs_fp64_exact_256"] = float(np.linalg.norm(g[:256] - I_ex) / np.linalg.norm(I_ex))
+    h.close()
+
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "voxels/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"displacive fcc 4 sites/cell, 32^3 supercell, Taylor order {N}, "
+                               f"|h|,|k|,|l|<=8 step 1/32 ({count[0]}^3 voxels), Lanczos m={lm}",
+                   "voxels_per_step": voxels, "taylor_order": N, "lanczos_m": lm,
+                   "fft_fields": info.total_fields},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "parity": parity,
+        "unfiltered_voxels_per_s": round(unfiltered, 1),
+        "kernels": kernels,
+    }
+    if sweep is not None:
+        line["compute_intensity_voxels_per_s_by_order"] = sweep
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()
