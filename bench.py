@@ -45,14 +45,16 @@ def hcount(k, n, g0, cnt):
     return max(0, hi - lo + 1)
 
 
-def recombine_work(n, S, nclass3, N, M, g0, cnt, nh, F):
+def recombine_work(n, S, nclass3, N, M, g0, cnt, nh, F, friedel=False):
     """Algorithmic flops and bytes of one recombination launch over the box (g0, cnt).
 
     flops: the sum-factorised evaluation --
       level C  per voxel and r3 class: Horner (4N) + class phase (8); |F|^2 (4)
       level B  per (G1, G2, k3) and site: 4 QR (q sums) + 10 (N+1) + 6
       level A  per (G1, k2) column, site and k3: 10 flops per Taylor term
-    bytes: float32 output written once + every half spectrum read once."""
+    bytes: float32 output written once + every half spectrum read once.
+    On a box symmetric about G = 0 only half of the voxels are evaluated (the
+    other half is I(-G) = I(G)), so the flops are halved."""
     QR = (N + 1) * (N + 2) // 2
     T = (N + 1) * (N + 2) * (N + 3) // 6
     V = int(np.prod(cnt))
@@ -62,7 +64,7 @@ def recombine_work(n, S, nclass3, N, M, g0, cnt, nh, F):
     fl_c = V * (nclass3 * (4 * N + 8) + 4)
     fl_b = items * S * (4 * QR + 10 * (N + 1) + 6)
     fl_a = cols * S * n[2] * 10 * T
-    flops = M * (fl_a + fl_b + fl_c)
+    flops = M * (fl_a + fl_b + fl_c) * (0.5 if friedel else 1.0)
     bytes_ = 4 * V + M * n[0] * n[1] * S * F * nh * 8
     return flops, bytes_
 
@@ -122,11 +124,12 @@ def main():
     value = voxels / sec
 
     # dominant kernel: recombination on the grown box
-    ext_g0 = tuple(g - (lm - 1) for g in model.g0)
-    ext_cnt = tuple(c + 2 * lm - 1 for c in count)
+    ext_g0 = tuple(g - lm for g in model.g0)
+    ext_cnt = tuple(c + 2 * lm for c in count)
     nclass3 = len(np.unique(model.frac[:, 2]))
+    sym = all(c % 2 == 1 and g == -(c - 1) // 2 for g, c in zip(ext_g0, ext_cnt))
     flops, bytes_ = recombine_work(n, S, nclass3, N, M, ext_g0, ext_cnt, n[2] // 2 + 1,
-                                   info.fields_per_site)
+                                   info.fields_per_site, friedel=sym)
     launches, tot_ms = kstats.get("recombine", (0, float("nan")))
     t_launch = tot_ms / max(launches, 1) / 1e3
     tflops = flops / t_launch / 1e12

@@ -154,7 +154,9 @@ struct DeviceTables {
     float2* tab2 = nullptr;
     float2* tabK3 = nullptr;
     float2* tabH3 = nullptr;
+    int4* work = nullptr;
     int H3min = 0, nH3span = 0;
+    int nwork = 0, hc = 0, nchunk3 = 0, block = 0;
 };
 
 struct LaunchPlan {
@@ -180,6 +182,7 @@ struct dsx_model_s {
     std::vector<int> site_of, class_of;     // class-sorted site order
     std::vector<int> sc_start;              // site chunks for the recombination LDS budget
     size_t chunk_lds = 0;
+    int bs_elems = 0, xs_elems = 0;
     AxisPlan plan[3];
     // device state
     int device = 0;
@@ -310,6 +313,7 @@ void free_model(dsx_model m)
     dfree(m->d_ext); dfree(m->d_stage);
     for (auto& kv : m->tables) {
         dfree(kv.second.tab1); dfree(kv.second.tab2); dfree(kv.second.tabK3); dfree(kv.second.tabH3);
+        dfree(kv.second.work);
     }
     for (auto& kv : m->lanczos_w) dfree(kv.second);
 }
@@ -323,6 +327,7 @@ dsx_status tables_for(dsx_model m, const Box& bx, DeviceTables** out)
         if (se != hipSuccess) { m->failed = true; return fail(DSX_ERR_DEVICE, hipGetErrorString(se)); }
         for (auto& kv : m->tables) {
             dfree(kv.second.tab1); dfree(kv.second.tab2); dfree(kv.second.tabK3); dfree(kv.second.tabH3);
+            dfree(kv.second.work);
         }
         m->tables.clear();
     }
@@ -354,6 +359,75 @@ dsx_status tables_for(dsx_model m, const Box& bx, DeviceTables** out)
         for (int h = 0; h < t.nH3span; ++h)
             th[(size_t)c * t.nH3span + h] = cis((double)(t.H3min + h) * m->frac[3 * mu + 2]);
     }
+    // ---- work list of the recombination: (k1, k2, G1, H2 range), one block each
+    const bool mag = m->kind == DSX_MAGNETIC;
+    int maxH2 = 0, maxH3 = 0;
+    for (int k = 0; k < n2; ++k) maxH2 = std::max(maxH2, hcount(k, n2, bx.g0[1], bx.cnt[1]));
+    for (int k = 0; k < n3; ++k) maxH3 = std::max(maxH3, hcount(k, n3, bx.g0[2], bx.cnt[2]));
+    const int hcs_nuc[4] = {4, 8, 17, 32};
+    const int hcs_mag[3] = {4, 8, 17};
+    const int* hcs = mag ? hcs_mag : hcs_nuc;
+    const int nhcs = mag ? 3 : 4;
+    t.hc = hcs[nhcs - 1];
+    for (int i = 0; i < nhcs; ++i) if (hcs[i] >= maxH3) { t.hc = hcs[i]; break; }
+    t.nchunk3 = (maxH3 + t.hc - 1) / t.hc;
+    const int maxT = recombine_max_threads(t.hc, mag);
+    const int per_h2 = n3 * t.nchunk3;
+    if (per_h2 > maxT) return fail(DSX_ERR_UNSUPPORTED, "output box too long along axis 3 for this supercell");
+    if (maxH2 > 4095) return fail(DSX_ERR_UNSUPPORTED, "output box too long along axis 2 for this supercell");
+    if ((size_t)m->nclass * t.nH3span * sizeof(float2) > 32 * 1024)
+        return fail(DSX_ERR_UNSUPPORTED, "output box too long along axis 3 for this supercell");
+    const int h2per = std::max(1, maxT / per_h2);
+    bool friedel = true;
+    for (int a = 0; a < 3; ++a)
+        if (bx.cnt[a] % 2 == 0 || bx.g0[a] != -(bx.cnt[a] - 1) / 2) friedel = false;
+    std::vector<std::pair<long long, int4>> items;
+    int maxrows = 1;
+    for (int k1 = 0; k1 < n1; ++k1) {
+        const int nH1 = hcount(k1, n1, bx.g0[0], bx.cnt[0]);
+        const int H1lo = (int)ceildiv_l((long)bx.g0[0] - k1, n1);
+        for (int k2 = 0; k2 < n2; ++k2) {
+            const int nH2 = hcount(k2, n2, bx.g0[1], bx.cnt[1]);
+            if (nH2 == 0) continue;
+            const int km1 = (n1 - k1) % n1, km2 = (n2 - k2) % n2;
+            // order key: a column and its mirror are adjacent
+            const long long c0 = (long long)k1 * n2 + k2, c1 = (long long)km1 * n2 + km2;
+            const long long key = std::min(c0, c1) * 2 + (c0 > c1 ? 1 : 0);
+            const int np = (nH2 + h2per - 1) / h2per;
+            const int rpp = (nH2 + np - 1) / np;
+            for (int j1 = 0; j1 < nH1; ++j1) {
+                const int G1 = k1 + n1 * (H1lo + j1);
+                int mirror = 0;
+                if (friedel) {
+                    if (G1 > 0) continue;
+                    if (G1 == 0) {
+                        if (k2 > km2) continue;
+                        mirror = k2 < km2 ? 1 : 0;
+                    } else {
+                        mirror = 1;
+                    }
+                }
+                for (int part = 0; part < np; ++part) {
+                    const int h2a = part * rpp, h2b = std::min(nH2, h2a + rpp);
+                    if (h2a >= h2b) continue;
+                    maxrows = std::max(maxrows, h2b - h2a);
+                    items.push_back({key * 4096 + j1, make_int4(k1, k2, G1, h2a | (h2b << 12) | (mirror << 24))});
+                }
+            }
+        }
+    }
+    std::stable_sort(items.begin(), items.end(),
+                     [](const std::pair<long long, int4>& x, const std::pair<long long, int4>& y) { return x.first < y.first; });
+    // blocks are dealt round-robin to the 8 XCDs: XCD x runs the x-th contiguous eighth
+    const size_t per = (items.size() + 7) / 8;
+    std::vector<int4> work(8 * per, make_int4(-1, 0, 0, 0));
+    for (size_t b = 0; b < work.size(); ++b) {
+        const size_t L = (b % 8) * per + b / 8;
+        if (L < items.size()) work[b] = items[L].second;
+    }
+    t.nwork = (int)work.size();
+    t.block = ((std::min(maxT, maxrows * per_h2) + 63) / 64) * 64;
+
     auto up = [&](float2** dst, const std::vector<float2>& src) -> hipError_t {
         hipError_t e = hipMalloc(dst, sizeof(float2) * std::max<size_t>(1, src.size()));
         if (e != hipSuccess) return e;
@@ -361,8 +435,10 @@ dsx_status tables_for(dsx_model m, const Box& bx, DeviceTables** out)
     };
     hipError_t e;
     if ((e = up(&t.tab1, t1)) != hipSuccess || (e = up(&t.tab2, t2)) != hipSuccess ||
-        (e = up(&t.tabK3, tk)) != hipSuccess || (e = up(&t.tabH3, th)) != hipSuccess) {
-        dfree(t.tab1); dfree(t.tab2); dfree(t.tabK3); dfree(t.tabH3);
+        (e = up(&t.tabK3, tk)) != hipSuccess || (e = up(&t.tabH3, th)) != hipSuccess ||
+        (e = hipMalloc(&t.work, sizeof(int4) * std::max<size_t>(1, work.size()))) != hipSuccess ||
+        (e = hipMemcpy(t.work, work.data(), sizeof(int4) * work.size(), hipMemcpyHostToDevice)) != hipSuccess) {
+        dfree(t.tab1); dfree(t.tab2); dfree(t.tabK3); dfree(t.tabH3); dfree(t.work);
         if (e == hipErrorOutOfMemory) return fail(DSX_ERR_NOMEM, "out of device memory for phase tables");
         m->failed = true;
         return fail(DSX_ERR_DEVICE, std::string("phase tables: ") + hipGetErrorString(e));
@@ -387,29 +463,14 @@ dsx_status plan_recombine(dsx_model m, const Box& bx, float* out, LaunchPlan& lp
     p.first_mono = m->first_mono;
     for (int a = 0; a < 3; ++a) { p.g0[a] = bx.g0[a]; p.cnt[a] = bx.cnt[a]; }
     p.H3min = tb->H3min; p.nH3span = tb->nH3span;
-    int maxH1 = 0, maxH2 = 0, maxH3 = 0;
-    for (int k = 0; k < n1; ++k) maxH1 = std::max(maxH1, hcount(k, n1, bx.g0[0], bx.cnt[0]));
-    for (int k = 0; k < n2; ++k) maxH2 = std::max(maxH2, hcount(k, n2, bx.g0[1], bx.cnt[1]));
-    for (int k = 0; k < n3; ++k) maxH3 = std::max(maxH3, hcount(k, n3, bx.g0[2], bx.cnt[2]));
-    const int hcs_nuc[4] = {4, 8, 17, 32};
-    const int hcs_mag[3] = {4, 8, 17};
-    const int* hcs = mag ? hcs_mag : hcs_nuc;
-    const int nhcs = mag ? 3 : 4;
-    int hc = hcs[nhcs - 1];
-    for (int i = 0; i < nhcs; ++i) if (hcs[i] >= maxH3) { hc = hcs[i]; break; }
-    p.nchunk3 = (maxH3 + hc - 1) / hc;
-    const int maxT = recombine_max_threads(hc, mag);
-    const int per_h2 = n3 * p.nchunk3;
-    if (per_h2 > maxT) return fail(DSX_ERR_UNSUPPORTED, "output box too long along axis 3 for this supercell");
-    p.h2per = std::max(1, std::min(maxH2, maxT / per_h2));
-    p.nparts = (maxH2 + p.h2per - 1) / p.h2per;
-    p.maxH1 = maxH1;
-    const long long nb = (long long)n1 * n2 * maxH1 * p.nparts;
-    if (nb > (1LL << 30)) return fail(DSX_ERR_UNSUPPORTED, "output box too large");
-    p.nblocks = (int)nb;
+    p.nclass = m->nclass;
+    p.work = tb->work; p.nwork = tb->nwork;
+    p.nchunk3 = tb->nchunk3;
     p.nsc = (int)m->sc_start.size() - 1;
     for (size_t i = 0; i < m->sc_start.size(); ++i) p.sc_start[i] = m->sc_start[i];
     for (int i = 0; i < m->S; ++i) { p.site_of[i] = m->site_of[i]; p.class_of[i] = m->class_of[i]; }
+    p.bs_elems = m->bs_elems;
+    p.xs_elems = m->xs_elems;
     const double C = mag ? 0.07265 : 1.0;
     p.scale = (float)(C / (m->normN * m->M));
     for (int i = 0; i < 9; ++i) p.recip[i] = (float)m->recip[i];
@@ -421,9 +482,10 @@ dsx_status plan_recombine(dsx_model m, const Box& bx, float* out, LaunchPlan& lp
             if (m->has_ff && m->ff[7 * mu + k] != m->ff[k]) p.ff_uniform = 0;
         }
     }
-    lp.hc = hc;
-    lp.block = ((std::min(maxT, p.h2per * per_h2) + 63) / 64) * 64;
-    lp.lds = m->chunk_lds;
+    lp.hc = tb->hc;
+    lp.block = tb->block;
+    lp.lds = m->chunk_lds + sizeof(float2) * (size_t)m->nclass * tb->nH3span;
+    if (lp.lds > 160 * 1024) return fail(DSX_ERR_UNSUPPORTED, "recombination does not fit the LDS for this box");
 
     BraggParams& q = lp.bp;
     std::memset(&q, 0, sizeof(q));
@@ -437,6 +499,15 @@ dsx_status plan_recombine(dsx_model m, const Box& bx, float* out, LaunchPlan& lp
     q.S = m->S; q.T = m->T; q.M = m->M; q.kind = m->kind;
     q.scale = C / m->normN;
     q.site = m->d_site;
+    if (m->kind == DSX_NUCLEAR) {
+        int t = 0;
+        for (int d = 0; d <= m->order; ++d)
+            for (int pp = d; pp >= 0; --pp)
+                for (int qq = d - pp; qq >= 0; --qq) {
+                    q.mono[3 * t] = (int8_t)pp; q.mono[3 * t + 1] = (int8_t)qq; q.mono[3 * t + 2] = (int8_t)(d - pp - qq);
+                    ++t;
+                }
+    }
     for (int i = 0; i < 9; ++i) q.recip[i] = m->recip[i];
     q.has_ff = m->has_ff ? 1 : 0;
     return DSX_OK;
@@ -466,12 +537,14 @@ dsx_status ensure_spectra(dsx_model m, hipStream_t st)
     const int npairs = (m->n[1] + 1) / 2;
     pp.buf_elems = std::max(npairs * m->n[2], m->n[1] * m->nh);
     if (m->kind == DSX_NUCLEAR) {
-        int t = 0;
-        for (int d = 0; d <= m->order; ++d)
-            for (int p = d; p >= 0; --p)
-                for (int q = d - p; q >= 0; --q) {
-                    pp.mono[3 * t] = (int8_t)p; pp.mono[3 * t + 1] = (int8_t)q; pp.mono[3 * t + 2] = (int8_t)(d - p - q);
-                    ++t;
+        // spectra order: pairs (q, r) by e = q + r, q descending; p ascending within
+        int f = 0;
+        for (int e = 0; e <= m->order; ++e)
+            for (int q = e; q >= 0; --q)
+                for (int p = 0; p <= m->order - e; ++p) {
+                    if (p == 0 && e == 0 && m->first_mono == 1) continue;
+                    pp.mono[3 * f] = (int8_t)p; pp.mono[3 * f + 1] = (int8_t)q; pp.mono[3 * f + 2] = (int8_t)(e - q);
+                    ++f;
                 }
     }
     HIPCHK(m, timed("fft_planes", st, [&] { return launch_fft_planes(pp, st); }));
@@ -615,14 +688,23 @@ dsx_status dsx_create_model(const dsx_model_desc* d, dsx_model* out)
     m->SF = m->S * m->F;
     m->normN = d->norm_N > 0 ? d->norm_N : (double)m->ncell * npos;
     m->nclass = count_classes(d, &m->site_of, &m->class_of);
-    // site chunks for the recombination's LDS budget
-    const size_t per_site = sizeof(float2) * (size_t)(m->kind == DSX_MAGNETIC ? 3 : n_pairs(m->order)) * m->n[2];
-    const size_t budget = 64 * 1024;
-    const int per_chunk = (int)std::max<size_t>(1, budget / per_site);
+    // site chunks for the recombination's LDS budget: level-A buffer of the chunk's
+    // sites plus the staging area of one site (nuclear) or of the chunk (magnetic);
+    // 72 KB keeps two 512-thread blocks per CU, larger plans take up to 150 KB.
+    const bool mag = m->kind == DSX_MAGNETIC;
+    const size_t per_site = sizeof(float2) * (size_t)(mag ? 3 : n_pairs(m->order)) * m->n[2];
+    const size_t stage_fixed = mag ? 0 : sizeof(float2) * (size_t)m->F * m->nh;
+    const size_t stage_site = mag ? sizeof(float2) * 6 * (size_t)m->nh : 0;
+    size_t budget = 72 * 1024;
+    if (stage_fixed + per_site + stage_site > budget) budget = 150 * 1024;
+    const int per_chunk = (int)std::max<size_t>(1, (budget - stage_fixed) / (per_site + stage_site));
     m->sc_start.clear();
     for (int i = 0; i < m->S; i += per_chunk) m->sc_start.push_back(i);
     m->sc_start.push_back(m->S);
-    m->chunk_lds = per_site * (size_t)std::min(per_chunk, m->S);
+    const int chunk_sites = std::min(per_chunk, m->S);
+    m->bs_elems = (int)(per_site / sizeof(float2)) * chunk_sites;
+    m->xs_elems = (int)((stage_fixed + stage_site * chunk_sites) / sizeof(float2));
+    m->chunk_lds = per_site * chunk_sites + stage_fixed + stage_site * chunk_sites;
     for (int a = 0; a < 3; ++a) m->plan[a] = make_plan(m->n[a]);
     m->set.assign(m->M, 0);
     (void)hipGetDevice(&m->device);
@@ -745,9 +827,12 @@ dsx_status dsx_noise_filter(dsx_model m, int32_t lanczos_m, int32_t oversample, 
     const int mm = lanczos_m, sv = oversample;
     Box ext;
     size_t ext_vox = 1, out_vox = 1;
+    // grown box [g0 - m, g0 + count + m): the window of output Q_a = g0_a + i/s spans
+    // G_a in [floor(Q_a) - m + 1, floor(Q_a) + m]; growing by m on both sides (one
+    // unused plane below) keeps a box symmetric about 0 symmetric.
     for (int a = 0; a < 3; ++a) {
-        ext.g0[a] = m->box.g0[a] - (mm - 1);
-        ext.cnt[a] = m->box.cnt[a] + 2 * mm - 1;
+        ext.g0[a] = m->box.g0[a] - mm;
+        ext.cnt[a] = m->box.cnt[a] + 2 * mm;
         ext_vox *= ext.cnt[a];
         out_vox *= (size_t)sv * m->box.cnt[a];
     }
@@ -790,6 +875,7 @@ dsx_status dsx_noise_filter(dsx_model m, int32_t lanczos_m, int32_t oversample, 
     lp.in = m->d_ext; lp.out = dout; lp.wn = m->lanczos_w[key];
     for (int a = 0; a < 3; ++a) { lp.e[a] = ext.cnt[a]; lp.o[a] = sv * m->box.cnt[a]; }
     lp.m = mm; lp.s = sv;
+    lp.eoff = 1;
     lp.t3 = 64; lp.t1 = 64;
     lp.t2 = 32;
     while (lp.t2 > 1 && lanczos_lds_bytes(lp) > 150 * 1024) lp.t2 /= 2;

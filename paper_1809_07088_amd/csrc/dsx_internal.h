@@ -46,14 +46,16 @@ struct PlaneParams {
     const float* occ;     // [M][S][n1][n2][n3] or null
     const float* vec;     // [M][S][n1][n2][n3][3] or null
     const double* sums;   // [M*S][T] lattice sums (the field means are sums / ncell)
-    float2* X;            // [M][n1][n2][S*F][nh]; this pass writes the R1 index in place of k1
+    float2* X;            // [M][n1][n2][S*F][nh]; this pass writes the R1 index in place of k1.
+                          // Fields of a site are ordered by the pair (q, r) (e = q + r ascending,
+                          // q descending), then p ascending, so that each p-run is contiguous.
     const float2* tw2;    // e^{+2 pi i t / n2}, t < n2
     const float2* tw3;    // e^{+2 pi i t / n3}, t < n3
     AxisPlan p2, p3;
     int32_t n1, n2, n3, nh, S, F, T, M, kind, first_mono;
     int32_t fchunk, nfchunk;
     int32_t buf_elems;    // complex elements per LDS ping-pong buffer
-    int8_t mono[3 * kMaxMono];   // exponents (p, q, r) of monomial t
+    int8_t mono[3 * kMaxMono];   // exponents (p, q, r) of field f (spectra order)
 };
 
 struct Axis1Params {
@@ -79,12 +81,13 @@ struct RecombParams {
     int32_t n1, n2, n3, nh, S, SF, F, M, first_mono;
     int32_t g0[3], cnt[3];
     int32_t H3min, nH3span;
-    int32_t maxH1;          // largest number of H1 values over residues k1
-    int32_t h2per;          // H2 values per block part
-    int32_t nparts;         // parts per (k1, k2, H1)
+    int32_t nclass;         // r3 classes (rows of tabH3)
+    const int4* work;       // [nwork] (k1, k2, G1, h2a | h2b << 12 | mirror << 24), or k1 < 0
+    int32_t nwork;
     int32_t nchunk3;        // H3 chunks per (H2, k3)
-    int32_t nblocks;        // logical blocks = n1 * n2 * maxH1 * nparts
     int32_t nsc;            // site chunks (each fits the LDS budget)
+    int32_t bs_elems;       // float2 elements of the level-A buffer (the staging area follows)
+    int32_t xs_elems;       // float2 elements of the staging area (the class phases follow)
     int32_t sc_start[kMaxSites + 1];   // site chunk boundaries in the sorted site list
     int32_t site_of[kMaxSites];        // sorted position -> site index
     int32_t class_of[kMaxSites];       // sorted position -> class index
@@ -107,15 +110,17 @@ struct BraggParams {
     const double* site;     // [S][11]: r_mu (3), b_mu, form factor (7)
     double recip[9];
     int32_t has_ff;
+    int8_t mono[3 * kMaxMono];   // exponents (p, q, r) of monomial t
 };
 
 // ---------------------------------------------------------------------------- Lanczos
 struct LanczosParams {
     const float* in;        // I on the grown box [e1][e2][e3]
     float* out;             // [o1][o2][o3]
-    const float* wn;        // [3][s][2m] normalised weights per axis
+    const float* wn;        // [s][2m] normalised weights (the same on every axis)
     int32_t e[3], o[3];
     int32_t m, s;
+    int32_t eoff;           // input index of the first window point of output 0
     int32_t t1, t2, t3;     // tile extents (outputs)
     int32_t nb1, nb2, nb3;
 };

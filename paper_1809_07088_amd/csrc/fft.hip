@@ -196,14 +196,18 @@ __global__ __launch_bounds__(256) void k_sums_magnetic(SumsParams P)
     }
 }
 
-__global__ void k_sums_reduce(SumsParams P)
+// One wave per output sum: lanes read the chunk partials, then a fixed-order
+// shuffle reduction (reproducible).
+__global__ __launch_bounds__(256) void k_sums_reduce(SumsParams P)
 {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int idx = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (idx >= P.M * P.S * P.T) return;
     const int ms = idx / P.T, t = idx - ms * P.T;
     double v = 0.0;
-    for (int c = 0; c < P.nchunk; ++c) v += P.partial[((size_t)ms * P.nchunk + c) * P.T + t];
-    P.sums[idx] = v;
+    for (int c = lane; c < P.nchunk; c += 64) v += P.partial[((size_t)ms * P.nchunk + c) * P.T + t];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) P.sums[idx] = v;
 }
 
 template <int N>
@@ -235,7 +239,7 @@ hipError_t launch_sums(const SumsParams& p, int order, hipStream_t st)
     }
     if (e != hipSuccess) return e;
     const int tot = p.M * p.S * p.T;
-    hipLaunchKernelGGL(k_sums_reduce, dim3((tot + 255) / 256), dim3(256), 0, st, p);
+    hipLaunchKernelGGL(k_sums_reduce, dim3((tot + 3) / 4), dim3(256), 0, st, p);
     return hipGetLastError();
 }
 
@@ -267,8 +271,8 @@ __global__ __launch_bounds__(256) void k_fft_planes(PlaneParams P)
     const int f_end = min(P.F, (fc + 1) * P.fchunk);
 
     for (int f = fc * P.fchunk; f < f_end; ++f) {
-        const int t = f + P.first_mono;
-        const int ep = P.mono[3 * t], eq = P.mono[3 * t + 1], er = P.mono[3 * t + 2];
+        const int ep = P.mono[3 * f], eq = P.mono[3 * f + 1], er = P.mono[3 * f + 2];
+        const int t = P.kind == 1 ? f : mono_index(ep, eq, er);    // index of the field's lattice sum
         const float mean = (float)(P.sums[(size_t)(m * P.S + mu) * P.T + t] / (double)ncell);
         __syncthreads();   // tables loaded / previous field finished with A and B
         // generate two real rows per complex line: row 2j -> real, row 2j+1 -> imaginary

@@ -26,8 +26,9 @@ __global__ __launch_bounds__(256) void k_lanczos(LanczosParams P)
     const int b1 = b / P.nb2;
     const int o1 = b1 * P.t1, o2 = b2 * P.t2, o3 = b3 * P.t3;
     const int T1 = min(P.t1, P.o[0] - o1), T2 = min(P.t2, P.o[1] - o2), T3 = min(P.t3, P.o[2] - o3);
-    const int E2lo = o2 / s, E2n = (o2 + T2 - 1) / s - E2lo + m2;
-    const int E3lo = o3 / s, E3n = (o3 + T3 - 1) / s - E3lo + m2;
+    const int eo = P.eoff;
+    const int E2lo = o2 / s + eo, E2n = (o2 + T2 - 1) / s + eo - E2lo + m2;
+    const int E3lo = o3 / s + eo, E3n = (o3 + T3 - 1) / s + eo - E3lo + m2;
     const int L2max = (P.t2 - 1) / s + 1 + m2, L3max = (P.t3 - 1) / s + 1 + m2;
 
     float* wn = sm;                                  // [s][2m]
@@ -37,7 +38,7 @@ __global__ __launch_bounds__(256) void k_lanczos(LanczosParams P)
     for (int i = threadIdx.x; i < s * m2; i += blockDim.x) wn[i] = P.wn[i];
 
     const int tile = P.t2 * P.t3;
-    const int e1a = o1 / s, e1b = (o1 + T1 - 1) / s + m2 - 1;
+    const int e1a = o1 / s + eo, e1b = (o1 + T1 - 1) / s + eo + m2 - 1;
     for (int e1 = e1a; e1 <= e1b; ++e1) {
         __syncthreads();
         const float* src = P.in + ((size_t)e1 * P.e[1] + E2lo) * P.e[2] + E3lo;
@@ -51,7 +52,7 @@ __global__ __launch_bounds__(256) void k_lanczos(LanczosParams P)
             const int r = idx / T3, j3 = idx - r * T3;
             const int i3 = o3 + j3;
             const float* w = wn + (i3 % s) * m2;
-            const float* x = stg + r * E3n + (i3 / s - E3lo);
+            const float* x = stg + r * E3n + (i3 / s + eo - E3lo);
             float acc = 0.f;
             for (int d = 0; d < m2; ++d) acc += w[d] * x[d];
             mid[r * P.t3 + j3] = acc;
@@ -63,16 +64,16 @@ __global__ __launch_bounds__(256) void k_lanczos(LanczosParams P)
             const int j2 = idx / T3, j3 = idx - j2 * T3;
             const int i2 = o2 + j2;
             const float* w = wn + (i2 % s) * m2;
-            const float* x = mid + (i2 / s - E2lo) * P.t3 + j3;
+            const float* x = mid + (i2 / s + eo - E2lo) * P.t3 + j3;
             float acc = 0.f;
             for (int d = 0; d < m2; ++d) acc += w[d] * x[d * P.t3];
             slot[j2 * P.t3 + j3] = acc;
         }
         __syncthreads();
         // axis 1: outputs whose window ends at plane e1
-        const int fl = e1 - m2 + 1;
+        const int fl = e1 - m2 + 1;       // first input plane of the window
         if (fl >= e1a) {
-            const int ia = max(o1, fl * s), ib = min(o1 + T1, fl * s + s);
+            const int ia = max(o1, (fl - eo) * s), ib = min(o1 + T1, (fl - eo) * s + s);
             for (int i1 = ia; i1 < ib; ++i1) {
                 const float* w = wn + (i1 % s) * m2;
                 float* orow = P.out + ((size_t)i1 * P.o[1] + o2) * P.o[2] + o3;
@@ -88,6 +89,120 @@ __global__ __launch_bounds__(256) void k_lanczos(LanczosParams P)
     }
 }
 
+// Register-ring variant for m = M2/2 in {2, 3, 4} and a 32 x 64 output tile:
+// each thread owns 8 fixed output positions of the tile, keeps the last 2m
+// axis-2-filtered values of each in registers, and prefetches the next input plane
+// into registers while the current one is filtered.  Two block barriers per plane.
+constexpr int kRT2 = 32, kRT3 = 64, kRPPT = kRT2 * kRT3 / 256;
+
+template <int M2>
+__global__ __launch_bounds__(256) void k_lanczos_ring(LanczosParams P)
+{
+    constexpr int L2 = kRT2 + M2, L3 = kRT3 + M2;          // staging extent for s = 1
+    constexpr int NSTG = (L2 * L3 + 255) / 256;
+    __shared__ float wn_s[16 * M2];
+    __shared__ float stg[L2 * L3];
+    __shared__ float mid[L2 * kRT3];
+    const int s = P.s;
+    int b = blockIdx.x;
+    const int b3 = b % P.nb3; b /= P.nb3;
+    const int b2 = b % P.nb2;
+    const int b1 = b / P.nb2;
+    const int o1 = b1 * P.t1, o2 = b2 * kRT2, o3 = b3 * kRT3;
+    const int T1 = min(P.t1, P.o[0] - o1), T2 = min(kRT2, P.o[1] - o2), T3 = min(kRT3, P.o[2] - o3);
+    const int eo = P.eoff;
+    const int E2lo = o2 / s + eo, E2n = (o2 + T2 - 1) / s + eo - E2lo + M2;
+    const int E3lo = o3 / s + eo, E3n = (o3 + T3 - 1) / s + eo - E3lo + M2;
+    for (int i = threadIdx.x; i < s * M2; i += blockDim.x) wn_s[i] = P.wn[i];
+
+    // prefetch addresses: this thread's staging elements
+    int soff[NSTG];
+#pragma unroll
+    for (int k = 0; k < NSTG; ++k) {
+        const int idx = threadIdx.x + 256 * k;
+        soff[k] = -1;
+        if (idx < E2n * E3n) {
+            const int r = idx / E3n, c = idx - r * E3n;
+            soff[k] = (E2lo + r) * P.e[2] + E3lo + c;
+        }
+    }
+    const size_t plane = (size_t)P.e[1] * P.e[2];
+    const int e1a = o1 / s + eo, e1b = (o1 + T1 - 1) / s + eo + M2 - 1;
+    float pf[NSTG];
+#pragma unroll
+    for (int k = 0; k < NSTG; ++k) pf[k] = soff[k] >= 0 ? P.in[(size_t)e1a * plane + soff[k]] : 0.f;
+
+    float ring[M2][kRPPT];
+#pragma unroll
+    for (int d = 0; d < M2; ++d)
+#pragma unroll
+        for (int k = 0; k < kRPPT; ++k) ring[d][k] = 0.f;
+    const int j3 = threadIdx.x & 63;
+    const int j2b = threadIdx.x >> 6;       // rows j2b + 4 k
+
+    for (int e1 = e1a; e1 <= e1b; ++e1) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NSTG; ++k)
+            if (soff[k] >= 0) stg[threadIdx.x + 256 * k] = pf[k];
+        if (e1 < e1b) {
+#pragma unroll
+            for (int k = 0; k < NSTG; ++k)
+                if (soff[k] >= 0) pf[k] = P.in[(size_t)(e1 + 1) * plane + soff[k]];
+        }
+        __syncthreads();
+        // axis 3: mid[r][j3] for every staged row
+        for (int idx = threadIdx.x; idx < E2n * kRT3; idx += 256) {
+            const int r = idx >> 6, jj = idx & 63;
+            if (jj < T3) {
+                const int i3 = o3 + jj;
+                const float* w = wn_s + (i3 % s) * M2;
+                const float* x = stg + r * E3n + (i3 / s + eo - E3lo);
+                float acc = 0.f;
+#pragma unroll
+                for (int d = 0; d < M2; ++d) acc += w[d] * x[d];
+                mid[idx] = acc;
+            }
+        }
+        __syncthreads();
+        // axis 2 into the register ring (shift by one plane)
+#pragma unroll
+        for (int k = 0; k < kRPPT; ++k) {
+            const int j2 = j2b + 4 * k;
+            float v = 0.f;
+            if (j2 < T2 && j3 < T3) {
+                const int i2 = o2 + j2;
+                const float* w = wn_s + (i2 % s) * M2;
+                const float* x = mid + (i2 / s + eo - E2lo) * kRT3 + j3;
+#pragma unroll
+                for (int d = 0; d < M2; ++d) v += w[d] * x[d * kRT3];
+            }
+#pragma unroll
+            for (int d = 0; d < M2 - 1; ++d) ring[d][k] = ring[d + 1][k];
+            ring[M2 - 1][k] = v;
+        }
+        // axis 1: outputs whose window ends at plane e1
+        const int fl = e1 - M2 + 1;       // first input plane of the window
+        if (fl >= e1a) {
+            const int ia = max(o1, (fl - eo) * s), ib = min(o1 + T1, (fl - eo) * s + s);
+            for (int i1 = ia; i1 < ib; ++i1) {
+                const float* w = wn_s + (i1 % s) * M2;
+                float* orow = P.out + ((size_t)i1 * P.o[1] + o2) * P.o[2] + o3;
+#pragma unroll
+                for (int k = 0; k < kRPPT; ++k) {
+                    const int j2 = j2b + 4 * k;
+                    if (j2 < T2 && j3 < T3) {
+                        float acc = 0.f;
+#pragma unroll
+                        for (int d = 0; d < M2; ++d) acc += w[d] * ring[d][k];
+                        orow[(size_t)j2 * P.o[2] + j3] = acc;
+                    }
+                }
+            }
+        }
+    }
+}
+
 size_t lanczos_lds_bytes(const LanczosParams& p)
 {
     const int m2 = 2 * p.m;
@@ -96,8 +211,24 @@ size_t lanczos_lds_bytes(const LanczosParams& p)
                                     m2 * p.t2 * p.t3);
 }
 
+bool lanczos_ring_supported(const LanczosParams& p)
+{
+    return p.s <= 16 && (p.m == 2 || p.m == 3 || p.m == 4);
+}
+
 hipError_t launch_lanczos(const LanczosParams& p, hipStream_t st)
 {
+    if (lanczos_ring_supported(p)) {
+        LanczosParams q = p;
+        q.t2 = kRT2; q.t3 = kRT3;
+        q.nb2 = (p.o[1] + kRT2 - 1) / kRT2;
+        q.nb3 = (p.o[2] + kRT3 - 1) / kRT3;
+        const dim3 grid(q.nb1 * q.nb2 * q.nb3);
+        if (p.m == 2) hipLaunchKernelGGL(k_lanczos_ring<4>, grid, dim3(256), 0, st, q);
+        else if (p.m == 3) hipLaunchKernelGGL(k_lanczos_ring<6>, grid, dim3(256), 0, st, q);
+        else hipLaunchKernelGGL(k_lanczos_ring<8>, grid, dim3(256), 0, st, q);
+        return hipGetLastError();
+    }
     const size_t lds = lanczos_lds_bytes(p);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)k_lanczos,

@@ -11,7 +11,9 @@
 // over the three axes:
 //   level A (per block: fixed k1, k2 and H1, i.e. fixed g1)
 //       B_mu^{qr}(k3) = b_mu e^{2 pi i g1 r_mu1} sum_p (i t1)^p/p! X^{pqr}_mu(k1,k2,k3)
-//       in LDS, read once per block from the k-major spectra;
+//       in LDS; the spectra of one site of column (k1, k2), then of the mirrored
+//       column (-k1, -k2) that supplies k3 > n3/2 through X(k) = conj X(-k), are
+//       staged in LDS with independent coalesced loads;
 //   level B (per thread: fixed H2 and k3)
 //       D_c^r = sum_{mu in c} e^{2 pi i (g2 r_mu2 + k3 r_mu3/n3)} sum_q (i t2)^q/q! B_mu^{qr} / r!
 //       where the class c groups the sites that share r_mu3;
@@ -22,6 +24,12 @@
 // the three spin-component spectra instead of the Taylor monomials, applies the
 // form factor and takes the component of F perpendicular to Q (Sec. III.D,
 // Eqs. mag_sf, mag_intensity, mag_projection).
+//
+// Blocks walk a host-built work list of (k1, k2, G1, H2 range) items, already in
+// the order that keeps the blocks of one column (and of its mirror) on one XCD.
+// On a box symmetric about G = 0 the list holds only half of the G1 planes and the
+// blocks also write I(-G) = I(G) (Friedel symmetry, exact for real fields and for
+// the truncated Taylor series).
 //
 // The points k = 0 (G = 0 mod n) are computed separately in float64 from the
 // float64 lattice sums (k_bragg_*), where the Bragg subtraction |<F>|^2 cancels
@@ -53,48 +61,81 @@ __host__ __device__ constexpr float inv_factorial(int r) {
     return 1.f / f;
 }
 
-// Block decode shared by both kernels.  Returns false when the block has no work.
+// Cooperative global -> LDS copy with up to eight independent loads in flight per
+// thread before any of them is stored.
+__device__ __forceinline__ void stage_copy(float2* __restrict__ dst, const float2* __restrict__ src,
+                                           int total)
+{
+    for (int base = threadIdx.x; base < total; base += 8 * blockDim.x) {
+        float2 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = base + u * blockDim.x;
+            if (i < total) v[u] = src[i];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = base + u * blockDim.x;
+            if (i < total) dst[i] = v[u];
+        }
+    }
+}
+
 struct BlockWork {
     int k1, k2, G1, i1, h2a, h2b, H2lo;
+    bool mirror;
 };
 
 __device__ __forceinline__ bool decode_block(const RecombParams& P, BlockWork& w)
 {
-    // Blocks are dealt round-robin to the 8 XCDs; remap so that each XCD walks a
-    // contiguous range of (k1, k2) columns and the H1 blocks of one column share
-    // its L2.
-    const int nb8 = (P.nblocks + 7) / 8;
-    const int logical = (int)(blockIdx.x % 8) * nb8 + (int)(blockIdx.x / 8);
-    if (logical >= P.nblocks) return false;
-    int t = logical;
-    const int part = t % P.nparts; t /= P.nparts;
-    const int j1 = t % P.maxH1; t /= P.maxH1;
-    w.k2 = t % P.n2;
-    w.k1 = t / P.n2;
-    int H1lo, nH1;
-    hrange(w.k1, P.n1, P.g0[0], P.cnt[0], H1lo, nH1);
-    if (j1 >= nH1) return false;
+    const int4 it = P.work[blockIdx.x];
+    if (it.x < 0) return false;
+    w.k1 = it.x;
+    w.k2 = it.y;
+    w.G1 = it.z;
+    w.h2a = it.w & 0xfff;
+    w.h2b = (it.w >> 12) & 0xfff;
+    w.mirror = (it.w >> 24) & 1;
     int nH2;
     hrange(w.k2, P.n2, P.g0[1], P.cnt[1], w.H2lo, nH2);
-    w.h2a = part * P.h2per;
-    w.h2b = min(nH2, w.h2a + P.h2per);
-    if (w.h2a >= w.h2b) return false;
-    w.G1 = w.k1 + P.n1 * (H1lo + j1);
     w.i1 = w.G1 - P.g0[0];
     return true;
 }
 
+// Copy the class phase table e^{2 pi i H3 r_c3} into LDS; returns the pointer to
+// index with an absolute H3.
+__device__ __forceinline__ const float2* stage_class_phases(const RecombParams& P, float2* dst)
+{
+    const int tot = P.nclass * P.nH3span;
+    for (int i = threadIdx.x; i < tot; i += blockDim.x) dst[i] = P.tabH3[i];
+    return dst - P.H3min;
+}
+
 // ---------------------------------------------------------------------------- nuclear
 template <int N, int HC>
-__global__ __launch_bounds__(HC <= 17 ? 1024 : 512) void k_recombine_nuclear(RecombParams P)
+__global__ __launch_bounds__(512) void k_recombine_nuclear(RecombParams P)
 {
-    extern __shared__ float2 Bs[];
+    extern __shared__ float2 smem[];
     constexpr int QR = n_pairs(N);
     BlockWork w;
     if (!decode_block(P, w)) return;
+    float2* Bs = smem;                                  // [sites of the chunk][QR][n3]
+    float2* Xs = smem + P.bs_elems;                     // [F][nh] staging
+    float2* tHs = Xs + P.xs_elems;                      // [nclass][nH3span]
+    __shared__ int jtab[2][QR];                         // e = q + r and first field of pair j
     const int n1 = P.n1, n2 = P.n2, n3 = P.n3, nh = P.nh;
     const int SFnh = P.SF * nh;
     const float tau1 = (float)(6.283185307179586 * (double)w.G1 / (double)n1);
+    for (int j = threadIdx.x; j < QR; j += blockDim.x) {
+        int e = 0;
+        while ((e + 1) * (e + 2) / 2 <= j) ++e;
+        int cum = 0;
+        for (int ee = 0; ee < e; ++ee) cum += (ee + 1) * (N - ee + 1);
+        cum += (j - e * (e + 1) / 2) * (N - e + 1);
+        jtab[0][j] = e;
+        jtab[1][j] = cum - P.first_mono;
+    }
+    const float2* tH0 = stage_class_phases(P, tHs);
 
     // this thread's item: (H2, H3 chunk, k3) with k3 fastest
     const int nitems = (w.h2b - w.h2a) * n3 * P.nchunk3;
@@ -135,37 +176,43 @@ __global__ __launch_bounds__(HC <= 17 ? 1024 : 512) void k_recombine_nuclear(Rec
         for (int sc = 0; sc < P.nsc; ++sc) {
             const int s0 = P.sc_start[sc], s1 = P.sc_start[sc + 1];
             const int ns = s1 - s0;
-            __syncthreads();
             // level A
-            for (int idx = threadIdx.x; idx < ns * QR * n3; idx += blockDim.x) {
-                const int kk = idx % n3;
-                const int rj = idx / n3;
-                const int j = rj % QR;
-                const int sl = rj / QR;
+            for (int sl = 0; sl < ns; ++sl) {
                 const int mu = P.site_of[s0 + sl];
-                int e = 0;
-                while ((e + 1) * (e + 2) / 2 <= j) ++e;
-                const int rr = j - e * (e + 1) / 2;
-                const int q = e - rr;
-                const float2* src;
-                float sg;
-                if (kk < nh) { src = Xm + col + kk; sg = 1.f; }
-                else { src = Xm + colm + (n3 - kk); sg = -1.f; }     // X(k) = conj X(-k)
-                float2 wgt = P.tab1[(size_t)mu * P.cnt[0] + w.i1];
-                float2 acc = make_float2(0.f, 0.f);
-                for (int p = 0; p <= N - e; ++p) {
-                    const int f = mono_index(p, q, rr) - P.first_mono;
-                    if (f >= 0) {
-                        float2 x = src[(size_t)(mu * P.F + f) * nh];
-                        x.y *= sg;
-                        acc.x += wgt.x * x.x - wgt.y * x.y;
-                        acc.y += wgt.x * x.y + wgt.y * x.x;
+                const float2 wbase = P.tab1[(size_t)mu * P.cnt[0] + w.i1];
+                for (int half = 0; half < 2; ++half) {
+                    const int k3lo = half ? nh : 0;
+                    const int nk = half ? n3 - nh : nh;
+                    if (nk <= 0) continue;
+                    __syncthreads();
+                    stage_copy(Xs, Xm + (half ? colm : col) + (size_t)mu * P.F * nh, P.F * nh);
+                    __syncthreads();
+                    const float sg = half ? -1.f : 1.f;
+                    for (int idx = threadIdx.x; idx < QR * nk; idx += blockDim.x) {
+                        const int j = idx / nk;
+                        const int kk = k3lo + (idx - j * nk);
+                        const int e = jtab[0][j];
+                        const int f0 = jtab[1][j];           // field of p = 0 (may be -1)
+                        const float2* xs = Xs + f0 * nh + (half ? n3 - kk : kk);
+                        float2 wgt = wbase;
+                        float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+                        for (int p = 0; p <= N; ++p) {
+                            if (p <= N - e) {
+                                if (f0 + p >= 0) {
+                                    float2 x = xs[p * nh];
+                                    x.y *= sg;
+                                    acc.x += wgt.x * x.x - wgt.y * x.y;
+                                    acc.y += wgt.x * x.y + wgt.y * x.x;
+                                }
+                                // wgt <- wgt * (i tau1) / (p + 1)
+                                const float sc1 = tau1 * inv_factorial(p + 1) / inv_factorial(p);
+                                wgt = make_float2(-wgt.y * sc1, wgt.x * sc1);
+                            }
+                        }
+                        Bs[((size_t)sl * QR + j) * n3 + kk] = acc;
                     }
-                    // wgt <- wgt * (i tau1) / (p + 1)
-                    const float sc1 = tau1 / (float)(p + 1);
-                    wgt = make_float2(-wgt.y * sc1, wgt.x * sc1);
                 }
-                Bs[idx] = acc;
             }
             __syncthreads();
             if (hcnt > 0) {
@@ -200,7 +247,7 @@ __global__ __launch_bounds__(HC <= 17 ? 1024 : 512) void k_recombine_nuclear(Rec
                             D[r].y += pc.y * inv_factorial(r);
                         }
                     }
-                    const float2* tH = P.tabH3 + (size_t)c * P.nH3span - P.H3min;
+                    const float2* tH = tH0 + (size_t)c * P.nH3span;
 #pragma unroll
                     for (int h = 0; h < HC; ++h) {
                         if (h < hcnt) {
@@ -224,11 +271,14 @@ __global__ __launch_bounds__(HC <= 17 ? 1024 : 512) void k_recombine_nuclear(Rec
     }
     if (hcnt > 0) {
         float* orow = P.out + ((size_t)w.i1 * P.cnt[1] + i2) * P.cnt[2];
+        float* mrow = P.out + ((size_t)(P.cnt[0] - 1 - w.i1) * P.cnt[1] + (P.cnt[1] - 1 - i2)) * P.cnt[2];
 #pragma unroll
         for (int h = 0; h < HC; ++h) {
             if (h < hcnt) {
-                const int G3 = k3 + n3 * (H3lo + hbeg + h);
-                orow[G3 - P.g0[2]] = I[h] * P.scale;
+                const int i3 = k3 + n3 * (H3lo + hbeg + h) - P.g0[2];
+                const float v = I[h] * P.scale;
+                orow[i3] = v;
+                if (w.mirror) mrow[P.cnt[2] - 1 - i3] = v;
             }
         }
     }
@@ -242,9 +292,13 @@ __device__ __forceinline__ float mag_ff(const float* f, float s2) {
 template <int HC>
 __global__ __launch_bounds__(512) void k_recombine_magnetic(RecombParams P)
 {
-    extern __shared__ float2 Bs[];
+    extern __shared__ float2 smem[];
     BlockWork w;
     if (!decode_block(P, w)) return;
+    float2* Bs = smem;                    // [sites of the chunk][3][n3]
+    float2* Xs = smem + P.bs_elems;       // [2][sites of the chunk][3][nh] staging
+    float2* tHs = Xs + P.xs_elems;        // [nclass][nH3span]
+    const float2* tH0 = stage_class_phases(P, tHs);
     const int n1 = P.n1, n2 = P.n2, n3 = P.n3, nh = P.nh;
     const int SFnh = P.SF * nh;
     const int nitems = (w.h2b - w.h2a) * n3 * P.nchunk3;
@@ -287,6 +341,14 @@ __global__ __launch_bounds__(512) void k_recombine_magnetic(RecombParams P)
         for (int sc = 0; sc < P.nsc; ++sc) {
             const int s0 = P.sc_start[sc], s1 = P.sc_start[sc + 1];
             const int ns = s1 - s0;
+            // level A: stage the chunk's spin spectra of column (k1, k2) and of the
+            // mirrored column, then apply b_mu e^{2 pi i g1 r_mu1}
+            __syncthreads();
+            for (int sl = 0; sl < ns; ++sl) {
+                const int mu = P.site_of[s0 + sl];
+                stage_copy(Xs + sl * 3 * nh, Xm + col + (size_t)mu * 3 * nh, 3 * nh);
+                stage_copy(Xs + (ns + sl) * 3 * nh, Xm + colm + (size_t)mu * 3 * nh, 3 * nh);
+            }
             __syncthreads();
             for (int idx = threadIdx.x; idx < ns * 3 * n3; idx += blockDim.x) {
                 const int kk = idx % n3;
@@ -295,8 +357,8 @@ __global__ __launch_bounds__(512) void k_recombine_magnetic(RecombParams P)
                 const int sl = rj / 3;
                 const int mu = P.site_of[s0 + sl];
                 float2 x;
-                if (kk < nh) x = Xm[col + (size_t)(mu * 3 + comp) * nh + kk];
-                else { x = Xm[colm + (size_t)(mu * 3 + comp) * nh + (n3 - kk)]; x.y = -x.y; }
+                if (kk < nh) x = Xs[(sl * 3 + comp) * nh + kk];
+                else { x = Xs[ns * 3 * nh + (sl * 3 + comp) * nh + (n3 - kk)]; x.y = -x.y; }
                 Bs[idx] = cmulf(P.tab1[(size_t)mu * P.cnt[0] + w.i1], x);
             }
             __syncthreads();
@@ -319,7 +381,7 @@ __global__ __launch_bounds__(512) void k_recombine_magnetic(RecombParams P)
                             D[comp].y += v.y;
                         }
                     }
-                    const float2* tH = P.tabH3 + (size_t)c * P.nH3span - P.H3min;
+                    const float2* tH = tH0 + (size_t)c * P.nH3span;
                     const float* ffc = P.ff[sp];
 #pragma unroll
                     for (int h = 0; h < HC; ++h) {
@@ -374,11 +436,14 @@ __global__ __launch_bounds__(512) void k_recombine_magnetic(RecombParams P)
     }
     if (hcnt > 0) {
         float* orow = P.out + ((size_t)w.i1 * P.cnt[1] + i2) * P.cnt[2];
+        float* mrow = P.out + ((size_t)(P.cnt[0] - 1 - w.i1) * P.cnt[1] + (P.cnt[1] - 1 - i2)) * P.cnt[2];
 #pragma unroll
         for (int h = 0; h < HC; ++h) {
             if (h < hcnt) {
-                const int G3 = k3 + n3 * (H3lo + hbeg + h);
-                orow[G3 - P.g0[2]] = I[h] * P.scale;
+                const int i3 = k3 + n3 * (H3lo + hbeg + h) - P.g0[2];
+                const float v = I[h] * P.scale;
+                orow[i3] = v;
+                if (w.mirror) mrow[P.cnt[2] - 1 - i3] = v;
             }
         }
     }
@@ -386,20 +451,23 @@ __global__ __launch_bounds__(512) void k_recombine_magnetic(RecombParams P)
 
 int recombine_max_threads(int hc, int magnetic)
 {
-    if (magnetic) return 512;
-    return hc <= 17 ? 1024 : 512;
+    (void)hc; (void)magnetic;
+    return 512;
+}
+
+template <typename K>
+static hipError_t set_lds(K kernel, size_t lds)
+{
+    if (lds <= 65536) return hipSuccess;
+    return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 template <int N, int HC>
 static hipError_t launch_nuc(const RecombParams& p, int block, size_t lds, hipStream_t st)
 {
-    const int grid = 8 * ((p.nblocks + 7) / 8);
-    if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_recombine_nuclear<N, HC>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL((k_recombine_nuclear<N, HC>), dim3(grid), dim3(block), lds, st, p);
+    hipError_t e = set_lds(k_recombine_nuclear<N, HC>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_recombine_nuclear<N, HC>), dim3(p.nwork), dim3(block), lds, st, p);
     return hipGetLastError();
 }
 
@@ -418,6 +486,7 @@ static hipError_t launch_nuc_hc(const RecombParams& p, int hc, int block, size_t
 hipError_t launch_recombine_nuclear(const RecombParams& p, int order, int hc, int block,
                                     size_t lds, hipStream_t st)
 {
+    if (p.nwork <= 0) return hipSuccess;
     switch (order) {
         case 0: return launch_nuc_hc<0>(p, hc, block, lds, st);
         case 1: return launch_nuc_hc<1>(p, hc, block, lds, st);
@@ -432,78 +501,103 @@ hipError_t launch_recombine_nuclear(const RecombParams& p, int order, int hc, in
     }
 }
 
-hipError_t launch_recombine_magnetic(const RecombParams& p, int hc, int block, size_t lds,
-                                     hipStream_t st)
+template <int HC>
+static hipError_t launch_mag(const RecombParams& p, int block, size_t lds, hipStream_t st)
 {
-    const int grid = 8 * ((p.nblocks + 7) / 8);
-    switch (hc) {
-        case 4: hipLaunchKernelGGL((k_recombine_magnetic<4>), dim3(grid), dim3(block), lds, st, p); break;
-        case 8: hipLaunchKernelGGL((k_recombine_magnetic<8>), dim3(grid), dim3(block), lds, st, p); break;
-        case 17: hipLaunchKernelGGL((k_recombine_magnetic<17>), dim3(grid), dim3(block), lds, st, p); break;
-        default: return hipErrorInvalidValue;
-    }
+    hipError_t e = set_lds(k_recombine_magnetic<HC>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_recombine_magnetic<HC>), dim3(p.nwork), dim3(block), lds, st, p);
     return hipGetLastError();
 }
 
+hipError_t launch_recombine_magnetic(const RecombParams& p, int hc, int block, size_t lds,
+                                     hipStream_t st)
+{
+    if (p.nwork <= 0) return hipSuccess;
+    switch (hc) {
+        case 4: return launch_mag<4>(p, block, lds, st);
+        case 8: return launch_mag<8>(p, block, lds, st);
+        case 17: return launch_mag<17>(p, block, lds, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 // ---------------------------------------------------------------------------- Bragg, float64
+// One 64-lane wave per unit-cell Bragg point H: lanes split the monomials of each
+// site, the partial sums are reduced across the wave in a fixed order, and lane 0
+// forms F_m(H), the ensemble moments and I(H), all in float64.
 template <int N>
-__global__ __launch_bounds__(256) void k_bragg_nuclear(BraggParams P)
+__global__ __launch_bounds__(64) void k_bragg_nuclear(BraggParams P)
 {
     constexpr int T = n_monomials(N);
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double Ar[3][N + 1], Ai[3][N + 1];
     const int total = P.nH[0] * P.nH[1] * P.nH[2];
+    const int idx = blockIdx.x;
     if (idx >= total) return;
+    const int lane = threadIdx.x;
     const int j3 = idx % P.nH[2], j2 = (idx / P.nH[2]) % P.nH[1], j1 = idx / (P.nH[2] * P.nH[1]);
     const int H[3] = {P.Hlo[0] + j1, P.Hlo[1] + j2, P.Hlo[2] + j3};
-    // (2 pi i H_a)^k / k! per axis
-    double Ar[3][N + 1], Ai[3][N + 1];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        Ar[a][0] = 1.0; Ai[a][0] = 0.0;
+    // (2 pi i H_a)^k / k! per axis, in closed form
+    if (lane < 3 * (N + 1)) {
+        const int a = lane / (N + 1), k = lane % (N + 1);
+        double mag = 1.0;
         const double t = 6.283185307179586476925 * (double)H[a];
-#pragma unroll
-        for (int k = 1; k <= N; ++k) {
-            Ar[a][k] = -Ai[a][k - 1] * t / k;
-            Ai[a][k] = Ar[a][k - 1] * t / k;
-        }
+        for (int i = 1; i <= k; ++i) mag *= t / i;
+        const int ph = k & 3;    // i^k
+        Ar[a][k] = ph == 0 ? mag : (ph == 2 ? -mag : 0.0);
+        Ai[a][k] = ph == 1 ? mag : (ph == 3 ? -mag : 0.0);
     }
-    double sq = 0.0, mr = 0.0, mi = 0.0;
+    __syncthreads();
+    // this lane's monomials
+    int mp[(T + 63) / 64], mq[(T + 63) / 64], mr[(T + 63) / 64];
+#pragma unroll
+    for (int u = 0; u < (T + 63) / 64; ++u) {
+        const int t = lane + 64 * u;
+        mp[u] = mq[u] = mr[u] = -1;
+        if (t < T) { mp[u] = P.mono[3 * t]; mq[u] = P.mono[3 * t + 1]; mr[u] = P.mono[3 * t + 2]; }
+    }
+    double sq = 0.0, mre = 0.0, mim = 0.0;
     for (int m = 0; m < P.M; ++m) {
         double fr = 0.0, fi = 0.0;
         for (int mu = 0; mu < P.S; ++mu) {
             const double* Sm = P.sums + ((size_t)m * P.S + mu) * T;
             double sr = 0.0, si = 0.0;
 #pragma unroll
-            for (int dg = 0; dg <= N; ++dg)
-#pragma unroll
-                for (int p = dg; p >= 0; --p)
-#pragma unroll
-                    for (int q = dg - p; q >= 0; --q) {
-                        const int r = dg - p - q;
-                        // coefficient A1[p] A2[q] A3[r]
-                        const double xr = Ar[0][p] * Ar[1][q] - Ai[0][p] * Ai[1][q];
-                        const double xi = Ar[0][p] * Ai[1][q] + Ai[0][p] * Ar[1][q];
-                        const double cr = xr * Ar[2][r] - xi * Ai[2][r];
-                        const double ci = xr * Ai[2][r] + xi * Ar[2][r];
-                        const double s = Sm[mono_index(p, q, r)];
-                        sr += cr * s;
-                        si += ci * s;
-                    }
-            const double* sd = P.site + 11 * mu;
-            double x = H[0] * sd[0] + H[1] * sd[1] + H[2] * sd[2];
-            x -= floor(x);
-            double sn, cs;
-            sincos(6.283185307179586476925 * x, &sn, &cs);
-            fr += sd[3] * (cs * sr - sn * si);
-            fi += sd[3] * (cs * si + sn * sr);
+            for (int u = 0; u < (T + 63) / 64; ++u) {
+                if (mp[u] >= 0) {
+                    const int p = mp[u], q = mq[u], r = mr[u];
+                    const double xr = Ar[0][p] * Ar[1][q] - Ai[0][p] * Ai[1][q];
+                    const double xi = Ar[0][p] * Ai[1][q] + Ai[0][p] * Ar[1][q];
+                    const double cr = xr * Ar[2][r] - xi * Ai[2][r];
+                    const double ci = xr * Ai[2][r] + xi * Ar[2][r];
+                    const double sv = Sm[lane + 64 * u];
+                    sr += cr * sv;
+                    si += ci * sv;
+                }
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                sr += __shfl_down(sr, off, 64);
+                si += __shfl_down(si, off, 64);
+            }
+            if (lane == 0) {
+                const double* sd = P.site + 11 * mu;
+                double x = H[0] * sd[0] + H[1] * sd[1] + H[2] * sd[2];
+                x -= floor(x);
+                double sn, cs;
+                sincos(6.283185307179586476925 * x, &sn, &cs);
+                fr += sd[3] * (cs * sr - sn * si);
+                fi += sd[3] * (cs * si + sn * sr);
+            }
         }
         sq += fr * fr + fi * fi;
-        mr += fr; mi += fi;
+        mre += fr; mim += fi;
     }
-    mr /= P.M; mi /= P.M;
-    const double I = (sq / P.M - (mr * mr + mi * mi)) * P.scale;
-    const int G[3] = {P.n[0] * H[0], P.n[1] * H[1], P.n[2] * H[2]};
-    P.out[((size_t)(G[0] - P.g0[0]) * P.cnt[1] + (G[1] - P.g0[1])) * P.cnt[2] + (G[2] - P.g0[2])] = (float)I;
+    if (lane == 0) {
+        mre /= P.M; mim /= P.M;
+        const double I = (sq / P.M - (mre * mre + mim * mim)) * P.scale;
+        const int G[3] = {P.n[0] * H[0], P.n[1] * H[1], P.n[2] * H[2]};
+        P.out[((size_t)(G[0] - P.g0[0]) * P.cnt[1] + (G[1] - P.g0[1])) * P.cnt[2] + (G[2] - P.g0[2])] = (float)I;
+    }
 }
 
 __device__ double mag_ff_d(const double* f, double s2) {
@@ -562,7 +656,8 @@ __global__ __launch_bounds__(256) void k_bragg_magnetic(BraggParams P)
 template <int N>
 static hipError_t launch_bragg_t(const BraggParams& p, int grid, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_bragg_nuclear<N>, dim3(grid), dim3(256), 0, st, p);
+    (void)grid;
+    hipLaunchKernelGGL(k_bragg_nuclear<N>, dim3(p.nH[0] * p.nH[1] * p.nH[2]), dim3(64), 0, st, p);
     return hipGetLastError();
 }
 
