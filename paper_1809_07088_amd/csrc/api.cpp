@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -466,11 +467,23 @@ dsx_status plan_recombine(dsx_model m, const Box& bx, float* out, LaunchPlan& lp
     p.nclass = m->nclass;
     p.work = tb->work; p.nwork = tb->nwork;
     p.nchunk3 = tb->nchunk3;
+    {
+        static const int forced = [] { const char* v = std::getenv("DSX_RECOMBINE_VARIANT"); return v ? std::atoi(v) : 0; }();
+        p.variant = forced;
+    }
     p.nsc = (int)m->sc_start.size() - 1;
     for (size_t i = 0; i < m->sc_start.size(); ++i) p.sc_start[i] = m->sc_start[i];
     for (int i = 0; i < m->S; ++i) { p.site_of[i] = m->site_of[i]; p.class_of[i] = m->class_of[i]; }
     p.bs_elems = m->bs_elems;
     p.xs_elems = m->xs_elems;
+    // parity form: every r_mu3 a multiple of 1/2 (exactly, as given)
+    p.parity = m->kind == DSX_NUCLEAR ? 1 : 0;
+    for (int i = 0; i < m->S; ++i) {
+        const double t2 = 2.0 * m->frac[3 * m->site_of[i] + 2];
+        if (t2 != std::floor(t2)) p.parity = 0;
+        const long a2 = (long)std::floor(t2);
+        p.class_sign[m->class_of[i]] = (a2 % 2 == 0) ? 1 : -1;
+    }
     const double C = mag ? 0.07265 : 1.0;
     p.scale = (float)(C / (m->normN * m->M));
     for (int i = 0; i < 9; ++i) p.recip[i] = (float)m->recip[i];
@@ -531,11 +544,16 @@ dsx_status ensure_spectra(dsx_model m, hipStream_t st)
     pp.p2 = m->plan[1]; pp.p3 = m->plan[2];
     pp.n1 = m->n[0]; pp.n2 = m->n[1]; pp.n3 = m->n[2]; pp.nh = m->nh;
     pp.S = m->S; pp.F = m->F; pp.T = m->T; pp.M = m->M; pp.kind = m->kind; pp.first_mono = m->first_mono;
-    const long long planes = (long long)m->M * m->S * m->n[0];
-    pp.fchunk = (int)std::max<long long>(1, std::min<long long>(m->F, planes * m->F / 8192));
-    pp.nfchunk = (m->F + pp.fchunk - 1) / pp.fchunk;
     const int npairs = (m->n[1] + 1) / 2;
     pp.buf_elems = std::max(npairs * m->n[2], m->n[1] * m->nh);
+    // fields batched per block: more butterflies per pass, LDS <= 24 KB, and
+    // at least ~2048 blocks when the problem allows it
+    const long long planes = (long long)m->M * m->S * m->n[0];
+    int fb = (int)std::max<size_t>(1, (24 * 1024 / sizeof(float2) - m->n[1] - m->n[2]) / (2 * (size_t)pp.buf_elems));
+    fb = std::min(fb, 4);
+    while (fb > 1 && planes * ((m->F + fb - 1) / fb) < 2048) --fb;
+    pp.fchunk = std::min(fb, m->F);
+    pp.nfchunk = (m->F + pp.fchunk - 1) / pp.fchunk;
     if (m->kind == DSX_NUCLEAR) {
         // spectra order: pairs (q, r) by e = q + r, q descending; p ascending within
         int f = 0;
@@ -876,7 +894,7 @@ dsx_status dsx_noise_filter(dsx_model m, int32_t lanczos_m, int32_t oversample, 
     for (int a = 0; a < 3; ++a) { lp.e[a] = ext.cnt[a]; lp.o[a] = sv * m->box.cnt[a]; }
     lp.m = mm; lp.s = sv;
     lp.eoff = 1;
-    lp.t3 = 64; lp.t1 = 64;
+    lp.t3 = 64; lp.t1 = 32;
     lp.t2 = 32;
     while (lp.t2 > 1 && lanczos_lds_bytes(lp) > 150 * 1024) lp.t2 /= 2;
     while (lp.t3 > 8 && lanczos_lds_bytes(lp) > 150 * 1024) lp.t3 /= 2;

@@ -85,6 +85,10 @@ struct RecombParams {
     const int4* work;       // [nwork] (k1, k2, G1, h2a | h2b << 12 | mirror << 24), or k1 < 0
     int32_t nwork;
     int32_t nchunk3;        // H3 chunks per (H2, k3)
+    int32_t variant;        // kernel variant (0: default for the problem, 1: multi-configuration
+                            // form, 2: class form even when the parity form applies)
+    int32_t parity;         // every r_mu3 is a multiple of 1/2 (the parity form applies)
+    int32_t class_sign[kMaxSites];   // per class: e^{2 pi i r_c3} = +-1 in the parity form
     int32_t nsc;            // site chunks (each fits the LDS budget)
     int32_t bs_elems;       // float2 elements of the level-A buffer (the staging area follows)
     int32_t xs_elems;       // float2 elements of the staging area (the class phases follow)

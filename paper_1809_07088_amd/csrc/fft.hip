@@ -25,21 +25,22 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 __device__ __forceinline__ float2 cmuli(float2 a) { return make_float2(-a.y, a.x); }   // i a
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 
-// One Stockham pass of radix R over `nlines` lines of length n held in LDS.
-// Element e of line l sits at base[l * lstride + e * estride].  Ns is the product
-// of the radices of the earlier passes.
+// One Stockham pass of radix R over nf x nlines lines of length n held in LDS.
+// Element e of line l of batch b sits at base[b * fstride + l * lstride + e * estride].
+// Ns is the product of the radices of the earlier passes.
 __device__ void stockham_pass(const float2* __restrict__ src, float2* __restrict__ dst,
-                              int nlines, int lstride, int estride, int n, int R, int Ns,
-                              const float2* __restrict__ tw)
+                              int nlines, int lstride, int estride, int nf, int fstride,
+                              int n, int R, int Ns, const float2* __restrict__ tw)
 {
     const int nb = n / R;
     const int twstep = n / (Ns * R);
-    const int total = nlines * nb;
+    const int total = nf * nlines * nb;
     for (int it = threadIdx.x; it < total; it += blockDim.x) {
-        const int l = it / nb;
-        const int j = it - l * nb;
-        const float2* s = src + l * lstride;
-        float2* d = dst + l * lstride;
+        const int L = it / nb;
+        const int j = it - L * nb;
+        const int fb = L / nlines, l = L - fb * nlines;
+        const float2* s = src + fb * fstride + l * lstride;
+        float2* d = dst + fb * fstride + l * lstride;
         const int jm = j % Ns;
         const int o = (j - jm) * R + jm;          // (j / Ns) * Ns * R + j mod Ns
         const int te = jm * twstep;               // twiddle exponent step, r * te < n
@@ -105,11 +106,11 @@ __device__ void stockham_pass(const float2* __restrict__ src, float2* __restrict
 // Full 1D transforms of all lines; ping-pongs between a and b and returns the
 // buffer holding the result.  Caller synchronises before (inputs visible).
 __device__ float2* lds_fft(float2* a, float2* b, int nlines, int lstride, int estride,
-                           const AxisPlan& P, const float2* tw)
+                           const AxisPlan& P, const float2* tw, int nf = 1, int fstride = 0)
 {
     int Ns = 1;
     for (int s = 0; s < P.nrad; ++s) {
-        stockham_pass(a, b, nlines, lstride, estride, P.n, P.rad[s], Ns, tw);
+        stockham_pass(a, b, nlines, lstride, estride, nf, fstride, P.n, P.rad[s], Ns, tw);
         __syncthreads();
         Ns *= P.rad[s];
         float2* t = a; a = b; b = t;
@@ -250,7 +251,7 @@ __global__ __launch_bounds__(256) void k_fft_planes(PlaneParams P)
     float2* tw2 = smem;
     float2* tw3 = tw2 + P.n2;
     float2* A = tw3 + P.n3;
-    float2* B = A + P.buf_elems;
+    float2* B = A + P.fchunk * P.buf_elems;
 
     int b = blockIdx.x;
     const int fc = b % P.nfchunk; b /= P.nfchunk;
@@ -268,68 +269,76 @@ __global__ __launch_bounds__(256) void k_fft_planes(PlaneParams P)
     const float* occ = P.occ ? P.occ + plane0 : nullptr;
     const float* vec = P.vec ? P.vec + 3 * plane0 : nullptr;
     const int npairs = (n2 + 1) / 2;
-    const int f_end = min(P.F, (fc + 1) * P.fchunk);
+    const int fa = fc * P.fchunk;
+    const int nfb = min(P.F, fa + P.fchunk) - fa;     // fields of this block, batched
+    const int BE = P.buf_elems;
 
-    for (int f = fc * P.fchunk; f < f_end; ++f) {
+    // generate two real rows per complex line: row 2j -> real, row 2j+1 -> imaginary
+    __syncthreads();   // twiddles visible
+    for (int idx = threadIdx.x; idx < nfb * npairs * n3; idx += blockDim.x) {
+        const int fb = idx / (npairs * n3);
+        const int rem = idx - fb * npairs * n3;
+        const int j = rem / n3, R3 = rem - j * n3;
+        const int f = fa + fb;
         const int ep = P.mono[3 * f], eq = P.mono[3 * f + 1], er = P.mono[3 * f + 2];
         const int t = P.kind == 1 ? f : mono_index(ep, eq, er);    // index of the field's lattice sum
         const float mean = (float)(P.sums[(size_t)(m * P.S + mu) * P.T + t] / (double)ncell);
-        __syncthreads();   // tables loaded / previous field finished with A and B
-        // generate two real rows per complex line: row 2j -> real, row 2j+1 -> imaginary
-        for (int idx = threadIdx.x; idx < npairs * n3; idx += blockDim.x) {
-            const int j = idx / n3, R3 = idx - j * n3;
-            float xv[2] = {0.f, 0.f};
+        float xv[2] = {0.f, 0.f};
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int R2 = 2 * j + h;
-                if (R2 < n2) {
-                    const int c = R2 * n3 + R3;
-                    float v;
-                    if (P.kind == 1) {
-                        v = vec[3 * c + t];
-                    } else {
-                        v = 1.f;
-                        if (ep | eq | er) {
-                            const float u0 = vec[3 * c], u1 = vec[3 * c + 1], u2 = vec[3 * c + 2];
-                            for (int k = 0; k < ep; ++k) v *= u0;
-                            for (int k = 0; k < eq; ++k) v *= u1;
-                            for (int k = 0; k < er; ++k) v *= u2;
-                        }
+        for (int h = 0; h < 2; ++h) {
+            const int R2 = 2 * j + h;
+            if (R2 < n2) {
+                const int c = R2 * n3 + R3;
+                float v;
+                if (P.kind == 1) {
+                    v = vec[3 * c + t];
+                } else {
+                    v = 1.f;
+                    if (ep | eq | er) {
+                        const float u0 = vec[3 * c], u1 = vec[3 * c + 1], u2 = vec[3 * c + 2];
+                        for (int k = 0; k < ep; ++k) v *= u0;
+                        for (int k = 0; k < eq; ++k) v *= u1;
+                        for (int k = 0; k < er; ++k) v *= u2;
                     }
-                    if (occ) v *= occ[c];
-                    xv[h] = v - mean;
                 }
+                if (occ) v *= occ[c];
+                xv[h] = v - mean;
             }
-            A[j * n3 + R3] = make_float2(xv[0], xv[1]);
         }
-        __syncthreads();
-        float2* Z = lds_fft(A, B, npairs, n3, 1, P.p3, tw3);
-        float2* C = (Z == A) ? B : A;
-        // unpack the packed real transforms: X_a = (Z_k + conj Z_-k)/2, X_b = -i (Z_k - conj Z_-k)/2
-        for (int idx = threadIdx.x; idx < npairs * nh; idx += blockDim.x) {
-            const int j = idx / nh, k = idx - j * nh;
-            const float2 zk = Z[j * n3 + k];
-            const int km = (k == 0) ? 0 : n3 - k;
-            const float2 zm = Z[j * n3 + km];
-            const float2 xa = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
-            const float2 xb = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
-            C[(2 * j) * nh + k] = xa;
-            if (2 * j + 1 < n2) C[(2 * j + 1) * nh + k] = xb;
-        }
-        __syncthreads();
-        float2* D = (C == A) ? B : A;
-        float2* Y = lds_fft(C, D, nh, 1, nh, P.p2, tw2);
-        float2* out = P.X + ((size_t)(m * P.n1 + R1) * n2) * SF * nh + (size_t)(mu * P.F + f) * nh;
-        for (int idx = threadIdx.x; idx < n2 * nh; idx += blockDim.x) {
-            const int k2 = idx / nh, k3 = idx - k2 * nh;
-            out[(size_t)k2 * SF * nh + k3] = Y[k2 * nh + k3];
-        }
+        A[fb * BE + j * n3 + R3] = make_float2(xv[0], xv[1]);
+    }
+    __syncthreads();
+    float2* Z = lds_fft(A, B, npairs, n3, 1, P.p3, tw3, nfb, BE);
+    float2* C = (Z == A) ? B : A;
+    // unpack the packed real transforms: X_a = (Z_k + conj Z_-k)/2, X_b = -i (Z_k - conj Z_-k)/2
+    for (int idx = threadIdx.x; idx < nfb * npairs * nh; idx += blockDim.x) {
+        const int fb = idx / (npairs * nh);
+        const int rem = idx - fb * npairs * nh;
+        const int j = rem / nh, k = rem - j * nh;
+        const float2 zk = Z[fb * BE + j * n3 + k];
+        const int km = (k == 0) ? 0 : n3 - k;
+        const float2 zm = Z[fb * BE + j * n3 + km];
+        const float2 xa = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+        const float2 xb = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
+        C[fb * BE + (2 * j) * nh + k] = xa;
+        if (2 * j + 1 < n2) C[fb * BE + (2 * j + 1) * nh + k] = xb;
+    }
+    __syncthreads();
+    float2* D = (C == A) ? B : A;
+    float2* Y = lds_fft(C, D, nh, 1, nh, P.p2, tw2, nfb, BE);
+    // write: for each k2, the block's fields are contiguous runs of nh complex
+    float2* out = P.X + ((size_t)(m * P.n1 + R1) * n2) * SF * nh + (size_t)(mu * P.F + fa) * nh;
+    for (int idx = threadIdx.x; idx < n2 * nfb * nh; idx += blockDim.x) {
+        const int k2 = idx / (nfb * nh);
+        const int rem = idx - k2 * nfb * nh;
+        const int fb = rem / nh, k3 = rem - fb * nh;
+        out[(size_t)k2 * SF * nh + rem] = Y[fb * BE + k2 * nh + k3];
     }
 }
 
 size_t planes_lds_bytes(const PlaneParams& p)
 {
-    return sizeof(float2) * (size_t)(p.n2 + p.n3 + 2 * p.buf_elems);
+    return sizeof(float2) * (size_t)(p.n2 + p.n3 + 2 * p.fchunk * p.buf_elems);
 }
 
 hipError_t launch_fft_planes(const PlaneParams& p, hipStream_t st)
@@ -360,9 +369,19 @@ __global__ __launch_bounds__(256) void k_fft_axis1(Axis1Params P)
     const size_t rowstride = (size_t)P.n2 * P.cols;
     float2* base = P.X + ((size_t)m * n1 * P.n2 + k2) * P.cols + c0;
     for (int i = threadIdx.x; i < n1; i += blockDim.x) tw[i] = P.tw1[i];
-    for (int idx = threadIdx.x; idx < n1 * tc; idx += blockDim.x) {
-        const int R1 = idx / tc, c = idx - R1 * tc;
-        A[idx] = (c0 + c < P.cols) ? base[R1 * rowstride + c] : make_float2(0.f, 0.f);
+    for (int b0 = threadIdx.x; b0 < n1 * tc; b0 += 8 * blockDim.x) {
+        float2 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = b0 + u * blockDim.x;
+            const int R1 = idx / tc, c = idx - R1 * tc;
+            v[u] = (idx < n1 * tc && c0 + c < P.cols) ? base[R1 * rowstride + c] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = b0 + u * blockDim.x;
+            if (idx < n1 * tc) A[idx] = v[u];
+        }
     }
     __syncthreads();
     float2* Y = lds_fft(A, B, tc, 1, tc, P.p1, tw);

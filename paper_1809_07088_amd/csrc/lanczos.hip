@@ -93,13 +93,13 @@ __global__ __launch_bounds__(256) void k_lanczos(LanczosParams P)
 // each thread owns 8 fixed output positions of the tile, keeps the last 2m
 // axis-2-filtered values of each in registers, and prefetches the next input plane
 // into registers while the current one is filtered.  Two block barriers per plane.
-constexpr int kRT2 = 32, kRT3 = 64, kRPPT = kRT2 * kRT3 / 256;
+constexpr int kRT2 = 32, kRT3 = 64, kRThreads = 512, kRPPT = kRT2 * kRT3 / kRThreads;
 
 template <int M2>
-__global__ __launch_bounds__(256) void k_lanczos_ring(LanczosParams P)
+__global__ __launch_bounds__(512, 2) void k_lanczos_ring(LanczosParams P)
 {
     constexpr int L2 = kRT2 + M2, L3 = kRT3 + M2;          // staging extent for s = 1
-    constexpr int NSTG = (L2 * L3 + 255) / 256;
+    constexpr int NSTG = (L2 * L3 + kRThreads - 1) / kRThreads;
     __shared__ float wn_s[16 * M2];
     __shared__ float stg[L2 * L3];
     __shared__ float mid[L2 * kRT3];
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(256) void k_lanczos_ring(LanczosParams P)
     int soff[NSTG];
 #pragma unroll
     for (int k = 0; k < NSTG; ++k) {
-        const int idx = threadIdx.x + 256 * k;
+        const int idx = threadIdx.x + kRThreads * k;
         soff[k] = -1;
         if (idx < E2n * E3n) {
             const int r = idx / E3n, c = idx - r * E3n;
@@ -128,9 +128,13 @@ __global__ __launch_bounds__(256) void k_lanczos_ring(LanczosParams P)
     }
     const size_t plane = (size_t)P.e[1] * P.e[2];
     const int e1a = o1 / s + eo, e1b = (o1 + T1 - 1) / s + eo + M2 - 1;
-    float pf[NSTG];
+    constexpr bool DEEP = true;           // two planes in flight
+    float pf[NSTG], pf2[NSTG];
 #pragma unroll
-    for (int k = 0; k < NSTG; ++k) pf[k] = soff[k] >= 0 ? P.in[(size_t)e1a * plane + soff[k]] : 0.f;
+    for (int k = 0; k < NSTG; ++k) {
+        pf[k] = soff[k] >= 0 ? P.in[(size_t)e1a * plane + soff[k]] : 0.f;
+        if (DEEP) pf2[k] = (soff[k] >= 0 && e1a + 1 <= e1b) ? P.in[(size_t)(e1a + 1) * plane + soff[k]] : 0.f;
+    }
 
     float ring[M2][kRPPT];
 #pragma unroll
@@ -138,21 +142,29 @@ __global__ __launch_bounds__(256) void k_lanczos_ring(LanczosParams P)
 #pragma unroll
         for (int k = 0; k < kRPPT; ++k) ring[d][k] = 0.f;
     const int j3 = threadIdx.x & 63;
-    const int j2b = threadIdx.x >> 6;       // rows j2b + 4 k
+    const int j2b = threadIdx.x >> 6;       // rows j2b + 8 k
 
     for (int e1 = e1a; e1 <= e1b; ++e1) {
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < NSTG; ++k)
-            if (soff[k] >= 0) stg[threadIdx.x + 256 * k] = pf[k];
-        if (e1 < e1b) {
+        for (int k = 0; k < NSTG; ++k) {
+            if (soff[k] >= 0) stg[threadIdx.x + kRThreads * k] = pf[k];
+            if (DEEP) pf[k] = pf2[k];
+        }
+        if (DEEP) {
+            if (e1 + 2 <= e1b) {
+#pragma unroll
+                for (int k = 0; k < NSTG; ++k)
+                    if (soff[k] >= 0) pf2[k] = P.in[(size_t)(e1 + 2) * plane + soff[k]];
+            }
+        } else if (e1 < e1b) {
 #pragma unroll
             for (int k = 0; k < NSTG; ++k)
                 if (soff[k] >= 0) pf[k] = P.in[(size_t)(e1 + 1) * plane + soff[k]];
         }
         __syncthreads();
         // axis 3: mid[r][j3] for every staged row
-        for (int idx = threadIdx.x; idx < E2n * kRT3; idx += 256) {
+        for (int idx = threadIdx.x; idx < E2n * kRT3; idx += kRThreads) {
             const int r = idx >> 6, jj = idx & 63;
             if (jj < T3) {
                 const int i3 = o3 + jj;
@@ -168,7 +180,7 @@ __global__ __launch_bounds__(256) void k_lanczos_ring(LanczosParams P)
         // axis 2 into the register ring (shift by one plane)
 #pragma unroll
         for (int k = 0; k < kRPPT; ++k) {
-            const int j2 = j2b + 4 * k;
+            const int j2 = j2b + 8 * k;
             float v = 0.f;
             if (j2 < T2 && j3 < T3) {
                 const int i2 = o2 + j2;
@@ -190,7 +202,7 @@ __global__ __launch_bounds__(256) void k_lanczos_ring(LanczosParams P)
                 float* orow = P.out + ((size_t)i1 * P.o[1] + o2) * P.o[2] + o3;
 #pragma unroll
                 for (int k = 0; k < kRPPT; ++k) {
-                    const int j2 = j2b + 4 * k;
+                    const int j2 = j2b + 8 * k;
                     if (j2 < T2 && j3 < T3) {
                         float acc = 0.f;
 #pragma unroll
@@ -224,9 +236,9 @@ hipError_t launch_lanczos(const LanczosParams& p, hipStream_t st)
         q.nb2 = (p.o[1] + kRT2 - 1) / kRT2;
         q.nb3 = (p.o[2] + kRT3 - 1) / kRT3;
         const dim3 grid(q.nb1 * q.nb2 * q.nb3);
-        if (p.m == 2) hipLaunchKernelGGL(k_lanczos_ring<4>, grid, dim3(256), 0, st, q);
-        else if (p.m == 3) hipLaunchKernelGGL(k_lanczos_ring<6>, grid, dim3(256), 0, st, q);
-        else hipLaunchKernelGGL(k_lanczos_ring<8>, grid, dim3(256), 0, st, q);
+        if (p.m == 2) hipLaunchKernelGGL(k_lanczos_ring<4>, grid, dim3(kRThreads), 0, st, q);
+        else if (p.m == 3) hipLaunchKernelGGL(k_lanczos_ring<6>, grid, dim3(kRThreads), 0, st, q);
+        else hipLaunchKernelGGL(k_lanczos_ring<8>, grid, dim3(kRThreads), 0, st, q);
         return hipGetLastError();
     }
     const size_t lds = lanczos_lds_bytes(p);

@@ -112,14 +112,60 @@ __device__ __forceinline__ const float2* stage_class_phases(const RecombParams& 
 }
 
 // ---------------------------------------------------------------------------- nuclear
-template <int N, int HC>
-__global__ __launch_bounds__(512) void k_recombine_nuclear(RecombParams P)
+__device__ __forceinline__ int wave_min_uniform(int v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+// Level C in the parity form: |sum_r (i t3)^r S_r|^2 for the thread's H3 values,
+// S = DE for even and DO for odd H3 (h0 = H3 of h = 0), handed to emit(h, value).
+template <int N, int HC, typename Emit>
+__device__ __forceinline__ void parity_level_c(float2 (&DE)[N + 1], float2 (&DO)[N + 1], int h0, int hmin,
+                                               int hcnt, float t3base, float dt3, Emit emit)
+{
+    // the set for even h becomes DE, the set for odd h DO (swap in place)
+    const bool odd0 = (h0 & 1) != 0;
+#pragma unroll
+    for (int r = 0; r <= N; ++r) {
+        const float2 t = DE[r];
+        DE[r] = odd0 ? DO[r] : DE[r];
+        DO[r] = odd0 ? t : DO[r];
+    }
+#pragma unroll
+    for (int h = 0; h < HC; ++h) {
+        if (h < hmin || h < hcnt) {
+            const float t3 = t3base + (float)h * dt3;
+            float2 acc;
+            if ((h & 1) == 0) {
+                acc = DE[N];
+#pragma unroll
+                for (int r = N - 1; r >= 0; --r)
+                    acc = make_float2(DE[r].x - t3 * acc.y, DE[r].y + t3 * acc.x);
+            } else {
+                acc = DO[N];
+#pragma unroll
+                for (int r = N - 1; r >= 0; --r)
+                    acc = make_float2(DO[r].x - t3 * acc.y, DO[r].y + t3 * acc.x);
+            }
+            emit(h, acc.x * acc.x + acc.y * acc.y);
+        }
+    }
+}
+
+// MULTI: more than one configuration; a single configuration needs no separate
+// |F|^2 accumulator, and the registers it frees hold the level-A prefetch.
+// PAR: every r_mu3 is a multiple of 1/2, so e^{2 pi i H3 r_c3} = +-1 by the parity
+// of H3: level B folds the classes into two coefficient sets, one for even and one
+// for odd H3, and level C evaluates a single polynomial per voxel.
+template <int N, int HC, bool MULTI, bool PAR>
+__global__ __launch_bounds__(512, 4) void k_recombine_nuclear(RecombParams P)
 {
     extern __shared__ float2 smem[];
     constexpr int QR = n_pairs(N);
     BlockWork w;
     if (!decode_block(P, w)) return;
-    float2* Bs = smem;                                  // [sites of the chunk][QR][n3]
+    float2* Bs = smem;                                  // [sites of the chunk][n3][QR]
     float2* Xs = smem + P.bs_elems;                     // [F][nh] staging
     float2* tHs = Xs + P.xs_elems;                      // [nclass][nH3span]
     __shared__ int jtab[2][QR];                         // e = q + r and first field of pair j
@@ -135,7 +181,7 @@ __global__ __launch_bounds__(512) void k_recombine_nuclear(RecombParams P)
         jtab[0][j] = e;
         jtab[1][j] = cum - P.first_mono;
     }
-    const float2* tH0 = stage_class_phases(P, tHs);
+    const float2* tH0 = PAR ? nullptr : stage_class_phases(P, tHs);
 
     // this thread's item: (H2, H3 chunk, k3) with k3 fastest
     const int nitems = (w.h2b - w.h2a) * n3 * P.nchunk3;
@@ -154,87 +200,121 @@ __global__ __launch_bounds__(512) void k_recombine_nuclear(RecombParams P)
     hrange(k3, n3, P.g0[2], P.cnt[2], H3lo, nH3);
     const int hbeg = ch * HC;
     const int hcnt = active ? max(0, min(HC, nH3 - hbeg)) : 0;
+    const int hmin = wave_min_uniform(active ? hcnt : HC);   // iterations every lane needs
     const float tau2 = (float)(6.283185307179586 * (double)G2 / (double)n2);
     const float c3 = (float)(6.283185307179586 / (double)n3);
+    const float t3base = (float)(k3 + n3 * (H3lo + hbeg)) * c3;   // tau3 of h = 0
+    const float dt3 = 6.283185307179586f;                          // tau3 step per H3
     float a2[N + 1];   // tau2^q / q!
     a2[0] = 1.f;
 #pragma unroll
     for (int q = 1; q <= N; ++q) a2[q] = a2[q - 1] * tau2 / (float)q;
 
-    float I[HC];
+    float I[MULTI ? HC : 1];
 #pragma unroll
-    for (int h = 0; h < HC; ++h) I[h] = 0.f;
+    for (int h = 0; h < (MULTI ? HC : 1); ++h) I[h] = 0.f;
 
     const size_t col = ((size_t)w.k1 * n2 + w.k2) * SFnh;
     const size_t colm = ((size_t)((n1 - w.k1) % n1) * n2 + (n2 - w.k2) % n2) * SFnh;
 
+    constexpr int NF = PAR ? 1 : HC;
+    float2 F[NF];           // class mode: F(H3) accumulated over the classes
+    float2 DE[N + 1], DO[N + 1];   // parity mode: coefficient sets of even / odd H3
     for (int m = 0; m < P.M; ++m) {
-        float2 F[HC];
 #pragma unroll
-        for (int h = 0; h < HC; ++h) F[h] = make_float2(0.f, 0.f);
+        for (int h = 0; h < NF; ++h) F[h] = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int r = 0; r <= N; ++r) { DE[r] = make_float2(0.f, 0.f); DO[r] = make_float2(0.f, 0.f); }
         const float2* Xm = P.X + (size_t)m * n1 * n2 * SFnh;
         for (int sc = 0; sc < P.nsc; ++sc) {
             const int s0 = P.sc_start[sc], s1 = P.sc_start[sc + 1];
             const int ns = s1 - s0;
-            // level A
-            for (int sl = 0; sl < ns; ++sl) {
+            // level A: stages (site, half); the next stage's spectra are loaded into
+            // registers while the current stage is contracted from LDS
+            const int nhalf = (n3 - nh > 0) ? 2 : 1;
+            const int nst = ns * nhalf;
+            const int stot = P.F * nh;
+            constexpr int PF = (MULTI || (PAR && N >= 6)) ? 1 : 6;
+            float2 pf[PF];
+            auto stage_src = [&](int st) {
+                const int mu = P.site_of[s0 + st / nhalf];
+                return Xm + ((st % nhalf) ? colm : col) + (size_t)mu * P.F * nh;
+            };
+            auto prefetch = [&](const float2* src) {
+#pragma unroll
+                for (int u = 0; u < PF; ++u) {
+                    const int i = threadIdx.x + u * blockDim.x;
+                    if (i < stot) pf[u] = src[i];
+                }
+            };
+            prefetch(stage_src(0));
+            for (int st = 0; st < nst; ++st) {
+                const int sl = st / nhalf, half = st % nhalf;
                 const int mu = P.site_of[s0 + sl];
                 const float2 wbase = P.tab1[(size_t)mu * P.cnt[0] + w.i1];
-                for (int half = 0; half < 2; ++half) {
-                    const int k3lo = half ? nh : 0;
-                    const int nk = half ? n3 - nh : nh;
-                    if (nk <= 0) continue;
-                    __syncthreads();
-                    stage_copy(Xs, Xm + (half ? colm : col) + (size_t)mu * P.F * nh, P.F * nh);
-                    __syncthreads();
-                    const float sg = half ? -1.f : 1.f;
-                    for (int idx = threadIdx.x; idx < QR * nk; idx += blockDim.x) {
-                        const int j = idx / nk;
-                        const int kk = k3lo + (idx - j * nk);
-                        const int e = jtab[0][j];
-                        const int f0 = jtab[1][j];           // field of p = 0 (may be -1)
-                        const float2* xs = Xs + f0 * nh + (half ? n3 - kk : kk);
-                        float2 wgt = wbase;
-                        float2 acc = make_float2(0.f, 0.f);
+                const int k3lo = half ? nh : 0;
+                const int nk = half ? n3 - nh : nh;
+                __syncthreads();
 #pragma unroll
-                        for (int p = 0; p <= N; ++p) {
-                            if (p <= N - e) {
-                                if (f0 + p >= 0) {
-                                    float2 x = xs[p * nh];
-                                    x.y *= sg;
-                                    acc.x += wgt.x * x.x - wgt.y * x.y;
-                                    acc.y += wgt.x * x.y + wgt.y * x.x;
-                                }
-                                // wgt <- wgt * (i tau1) / (p + 1)
-                                const float sc1 = tau1 * inv_factorial(p + 1) / inv_factorial(p);
-                                wgt = make_float2(-wgt.y * sc1, wgt.x * sc1);
+                for (int u = 0; u < PF; ++u) {
+                    const int i = threadIdx.x + u * blockDim.x;
+                    if (i < stot) Xs[i] = pf[u];
+                }
+                if (stot > PF * (int)blockDim.x)       // large spectra: the rest in batches
+                    stage_copy(Xs + PF * blockDim.x, stage_src(st) + PF * blockDim.x, stot - PF * blockDim.x);
+                if (st + 1 < nst) prefetch(stage_src(st + 1));
+                __syncthreads();
+                const float sg = half ? -1.f : 1.f;
+                for (int idx = threadIdx.x; idx < QR * nk; idx += blockDim.x) {
+                    const int j = idx / nk;
+                    const int kk = k3lo + (idx - j * nk);
+                    const int e = jtab[0][j];
+                    const int f0 = jtab[1][j];           // field of p = 0 (may be -1)
+                    const float2* xs = Xs + f0 * nh + (half ? n3 - kk : kk);
+                    float2 wgt = wbase;
+                    float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+                    for (int p = 0; p <= N; ++p) {
+                        if (p <= N - e) {
+                            if (f0 + p >= 0) {
+                                float2 x = xs[p * nh];
+                                x.y *= sg;
+                                acc.x += wgt.x * x.x - wgt.y * x.y;
+                                acc.y += wgt.x * x.y + wgt.y * x.x;
                             }
+                            // wgt <- wgt * (i tau1) / (p + 1)
+                            const float sc1 = tau1 * (1.f / (float)(p + 1));
+                            wgt = make_float2(-wgt.y * sc1, wgt.x * sc1);
                         }
-                        Bs[((size_t)sl * QR + j) * n3 + kk] = acc;
                     }
+                    Bs[((size_t)sl * n3 + kk) * QR + j] = acc;
                 }
             }
             __syncthreads();
-            if (hcnt > 0) {
+            // level B (+ level C in class mode)
+            if (active) {
                 int sp = s0;
                 while (sp < s1) {
                     const int c = P.class_of[sp];
                     int se = sp + 1;
                     while (se < s1 && P.class_of[se] == c) ++se;
-                    float2 D[N + 1];
+                    float2 D[PAR ? 1 : N + 1];
+                    if constexpr (!PAR) {
 #pragma unroll
-                    for (int r = 0; r <= N; ++r) D[r] = make_float2(0.f, 0.f);
+                        for (int r = 0; r <= N; ++r) D[r] = make_float2(0.f, 0.f);
+                    }
+                    const float sgn_odd = PAR ? (float)P.class_sign[c] : 1.f;
                     for (int sl = sp - s0; sl < se - s0; ++sl) {
                         const int mu = P.site_of[s0 + sl];
                         const float2 ph = cmulf(P.tab2[(size_t)mu * P.cnt[1] + i2],
                                                 P.tabK3[(size_t)mu * n3 + k3]);
-                        const float2* Bp = Bs + (size_t)sl * QR * n3 + k3;
+                        const float2* Bp = Bs + ((size_t)sl * n3 + k3) * QR;
 #pragma unroll
                         for (int r = 0; r <= N; ++r) {
                             float2 C = make_float2(0.f, 0.f);
 #pragma unroll
                             for (int q = 0; q + r <= N; ++q) {
-                                const float2 v = Bp[pair_index(q, r) * n3];
+                                const float2 v = Bp[pair_index(q, r)];
                                 const float a = a2[q];
                                 // C += i^q a v
                                 if ((q & 3) == 0) { C.x += a * v.x; C.y += a * v.y; }
@@ -243,43 +323,69 @@ __global__ __launch_bounds__(512) void k_recombine_nuclear(RecombParams P)
                                 else { C.x += a * v.y; C.y -= a * v.x; }
                             }
                             const float2 pc = cmulf(ph, C);
-                            D[r].x += pc.x * inv_factorial(r);
-                            D[r].y += pc.y * inv_factorial(r);
+                            if constexpr (PAR) {
+                                DE[r].x += pc.x * inv_factorial(r);
+                                DE[r].y += pc.y * inv_factorial(r);
+                                DO[r].x += sgn_odd * pc.x * inv_factorial(r);
+                                DO[r].y += sgn_odd * pc.y * inv_factorial(r);
+                            } else {
+                                D[r].x += pc.x * inv_factorial(r);
+                                D[r].y += pc.y * inv_factorial(r);
+                            }
+                            // keep the coefficient loads of one r at a time in registers
+                            __builtin_amdgcn_sched_barrier(0);
                         }
                     }
-                    const float2* tH = tH0 + (size_t)c * P.nH3span;
+                    if constexpr (!PAR) {
+                        const float2* tH = tH0 + (size_t)c * P.nH3span + H3lo + hbeg;
 #pragma unroll
-                    for (int h = 0; h < HC; ++h) {
-                        if (h < hcnt) {
-                            const int H3 = H3lo + hbeg + h;
-                            const float t3 = (float)(k3 + n3 * H3) * c3;
-                            float2 acc = D[N];
+                        for (int h = 0; h < HC; ++h) {
+                            if (h < hmin || h < hcnt) {
+                                const float t3 = t3base + (float)h * dt3;
+                                float2 acc = D[N];
 #pragma unroll
-                            for (int r = N - 1; r >= 0; --r)
-                                acc = make_float2(D[r].x - t3 * acc.y, D[r].y + t3 * acc.x);
-                            const float2 e3 = tH[H3];
-                            F[h].x += e3.x * acc.x - e3.y * acc.y;
-                            F[h].y += e3.x * acc.y + e3.y * acc.x;
+                                for (int r = N - 1; r >= 0; --r)
+                                    acc = make_float2(D[r].x - t3 * acc.y, D[r].y + t3 * acc.x);
+                                const float2 e3 = tH[h];
+                                F[h].x += e3.x * acc.x - e3.y * acc.y;
+                                F[h].y += e3.x * acc.y + e3.y * acc.x;
+                            }
                         }
                     }
                     sp = se;
                 }
             }
         }
+        if constexpr (PAR && MULTI) {
+            parity_level_c<N, HC>(DE, DO, H3lo + hbeg, hmin, hcnt, t3base, dt3, [&](int h, float v) { I[h] += v; });
+        } else if constexpr (MULTI) {
 #pragma unroll
-        for (int h = 0; h < HC; ++h) I[h] += F[h].x * F[h].x + F[h].y * F[h].y;
+            for (int h = 0; h < HC; ++h) I[h] += F[h].x * F[h].x + F[h].y * F[h].y;
+        }
     }
-    if (hcnt > 0) {
-        float* orow = P.out + ((size_t)w.i1 * P.cnt[1] + i2) * P.cnt[2];
-        float* mrow = P.out + ((size_t)(P.cnt[0] - 1 - w.i1) * P.cnt[1] + (P.cnt[1] - 1 - i2)) * P.cnt[2];
-#pragma unroll
-        for (int h = 0; h < HC; ++h) {
-            if (h < hcnt) {
-                const int i3 = k3 + n3 * (H3lo + hbeg + h) - P.g0[2];
-                const float v = I[h] * P.scale;
-                orow[i3] = v;
-                if (w.mirror) mrow[P.cnt[2] - 1 - i3] = v;
+    const int i3b = k3 + n3 * (H3lo + hbeg) - P.g0[2];       // output index of h = 0
+    float* orow = P.out + ((size_t)w.i1 * P.cnt[1] + i2) * P.cnt[2] + i3b;
+    float* mrow = P.out + ((size_t)(P.cnt[0] - 1 - w.i1) * P.cnt[1] + (P.cnt[1] - 1 - i2)) * P.cnt[2]
+                + (P.cnt[2] - 1 - i3b);
+    if constexpr (PAR && !MULTI) {
+        // single configuration: evaluate and write
+        parity_level_c<N, HC>(DE, DO, H3lo + hbeg, hmin, hcnt, t3base, dt3, [&](int h, float v) {
+            if (active) {
+                orow[n3 * h] = v * P.scale;
+                if (w.mirror) mrow[-n3 * h] = v * P.scale;
             }
+        });
+        return;
+    }
+    if (!active) return;
+#pragma unroll
+    for (int h = 0; h < HC; ++h) {
+        if (h < hmin || h < hcnt) {
+            float v;
+            if constexpr (MULTI) v = I[h] * P.scale;
+            else v = (F[h].x * F[h].x + F[h].y * F[h].y) * P.scale;
+            orow[n3 * h] = v;
+            if (w.mirror) mrow[-n3 * h] = v;
         }
     }
 }
@@ -462,13 +568,24 @@ static hipError_t set_lds(K kernel, size_t lds)
     return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
+template <int N, int HC, bool MULTI, bool PAR>
+static hipError_t launch_nuc_v(const RecombParams& p, int block, size_t lds, hipStream_t st)
+{
+    hipError_t e = set_lds(k_recombine_nuclear<N, HC, MULTI, PAR>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_recombine_nuclear<N, HC, MULTI, PAR>), dim3(p.nwork), dim3(block), lds, st, p);
+    return hipGetLastError();
+}
+
 template <int N, int HC>
 static hipError_t launch_nuc(const RecombParams& p, int block, size_t lds, hipStream_t st)
 {
-    hipError_t e = set_lds(k_recombine_nuclear<N, HC>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_recombine_nuclear<N, HC>), dim3(p.nwork), dim3(block), lds, st, p);
-    return hipGetLastError();
+    const bool multi = p.M > 1 || p.variant == 1;
+    const bool par = p.parity != 0 && p.variant != 2;
+    if (multi) return par ? launch_nuc_v<N, HC, true, true>(p, block, lds, st)
+                          : launch_nuc_v<N, HC, true, false>(p, block, lds, st);
+    return par ? launch_nuc_v<N, HC, false, true>(p, block, lds, st)
+               : launch_nuc_v<N, HC, false, false>(p, block, lds, st);
 }
 
 template <int N>
