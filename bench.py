@@ -22,9 +22,12 @@ Besides the JSON line fields of the contract it reports:
   parity        relative L2 of the GPU I(G) against the oracle on that sample.
 """
 import argparse
+import csv
+import glob
+import hashlib
 import json
-import math
 import os
+import re
 import sys
 import time
 
@@ -34,6 +37,68 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "diffuse-intensity voxels/s at ≤1e-5 rel L2 vs FP64; p50/p99 request latency"
+TRAFFIC_MD = os.path.join(ROOT, "profiles", "recombine_displacive32_order8_traffic.md")
+COPY_PROBE_BYTES = 256 << 20     # plain device copy of known size, read + write
+
+
+def kernel_source_hash():
+    """Hash of the recombination source: stored traffic is only used while it matches."""
+    with open(os.path.join(ROOT, "paper_1809_07088_amd", "csrc", "recombine.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def summarize_pmc(fetch_dir, write_dir, out_md, command):
+    """Turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) into the
+    traffic summary: per-launch HBM bytes of the recombination, scaled by the ratio of
+    the known size of the plain copy probe to what the same counter reads for it."""
+    def per_kernel(d, counter):
+        vals = {}
+        for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(path)):
+                if r["Counter_Name"] == counter:
+                    vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
+        return vals
+    fetch, write = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
+
+    def probe(vals):
+        cands = [max(v) for k, v in vals.items() if "copyBuffer" in k]
+        return max(cands) if cands else None
+    pf, pw = probe(fetch), probe(write)
+    kf = [v for k, v in fetch.items() if "k_recombine" in k]
+    kw = [v for k, v in write.items() if "k_recombine" in k]
+    if not kf or not kw or not pf or not pw:
+        raise SystemExit("summarize: recombination or copy probe missing in the counter files")
+    sf, sw = COPY_PROBE_BYTES / pf, COPY_PROBE_BYTES / pw
+    f_avg = sum(kf[0]) / len(kf[0]) * sf
+    w_avg = sum(kw[0]) / len(kw[0]) * sw
+    rec = {"kernel": "recombine", "source_hash": kernel_source_hash(), "fetch_bytes": f_avg,
+           "write_bytes": w_avg, "traffic_bytes": f_avg + w_avg, "copy_probe_bytes": COPY_PROBE_BYTES,
+           "fetch_scale": sf, "write_scale": sw}
+    with open(out_md, "w") as f:
+        f.write("# HBM traffic of the recombination kernel (displacive 32^3, Taylor order 8, "
+                "513^3 box grown by the Lanczos window)\n\n")
+        f.write("Two rocprofv3 PMC runs of the benchmark (`FETCH_SIZE`, then `WRITE_SIZE`, KiB per "
+                "dispatch), each scaled by copy-probe bytes / counter reading of the plain device "
+                "copy of %d MiB issued by the benchmark (fetch scale %.4f, write scale %.4f).\n\n"
+                % (COPY_PROBE_BYTES >> 20, sf, sw))
+        f.write("Command:\n\n```\n%s\n```\n\n" % command)
+        f.write("| counter | raw per launch (bytes) | scaled (bytes) |\n|---|---|---|\n")
+        f.write("| FETCH_SIZE | %.0f | %.0f |\n" % (sum(kf[0]) / len(kf[0]), f_avg))
+        f.write("| WRITE_SIZE | %.0f | %.0f |\n\n" % (sum(kw[0]) / len(kw[0]), w_avg))
+        f.write("```json\n%s\n```\n" % json.dumps(rec))
+    return rec
+
+
+def stored_traffic():
+    try:
+        txt = open(TRAFFIC_MD).read()
+    except OSError:
+        return None
+    m = re.search(r"```json\n(.*?)\n```", txt, re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    return rec if rec.get("source_hash") == kernel_source_hash() else None
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP32_PEAK_TFLOPS = 157.3       # MI355X published FP32 vector peak
 
@@ -79,7 +144,16 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep", action="store_true", help="also time compute_intensity for orders 1..8")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="issue one plain device copy of known size (reference for PMC byte counters)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the traffic summary from two rocprofv3 --pmc output folders and exit")
+    ap.add_argument("--pmc-command", default="", help="command line recorded in the traffic summary")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        print(json.dumps(summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], TRAFFIC_MD,
+                                       args.pmc_command)))
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build runs the hot path on one GPU; --gpus must be 1 "
@@ -106,6 +180,13 @@ def main():
     def step():
         h.set_sites(0, None, disp_dev)
         h.noise_filter(lm, 1, out)
+
+    if args.copy_probe:
+        src = torch.empty(COPY_PROBE_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for _ in range(args.warmup):
         step()
@@ -141,6 +222,9 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None}
+    tr = stored_traffic()
+    if tr is not None:
+        roof["traffic"] = int(tr["traffic_bytes"])
     roof.update({"kernel": "recombine", "launch_ms": round(t_launch * 1e3, 4),
                  "algorithmic_flops_per_launch": int(flops), "algorithmic_bytes_per_launch": int(bytes_),
                  "achieved_hbm_GBs": round(gbs, 1), "achieved_TFLOPs": round(tflops, 3)})

@@ -25,6 +25,17 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 __device__ __forceinline__ float2 cmuli(float2 a) { return make_float2(-a.y, a.x); }   // i a
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 
+// Quotient a / b for 0 <= a < 2^22 and 0 < b < 2^22, with rb ~= 1/b (float): the
+// float estimate is off by at most one and is corrected with one remainder check.
+__device__ __forceinline__ int qdiv(int a, int b, float rb)
+{
+    int q = (int)((float)a * rb);
+    const int r = a - q * b;
+    q += (r >= b) ? 1 : 0;
+    q -= (r < 0) ? 1 : 0;
+    return q;
+}
+
 // One Stockham pass of radix R over nf x nlines lines of length n held in LDS.
 // Element e of line l of batch b sits at base[b * fstride + l * lstride + e * estride].
 // Ns is the product of the radices of the earlier passes.
@@ -35,13 +46,14 @@ __device__ void stockham_pass(const float2* __restrict__ src, float2* __restrict
     const int nb = n / R;
     const int twstep = n / (Ns * R);
     const int total = nf * nlines * nb;
+    const float rnb = 1.f / (float)nb, rnl = 1.f / (float)nlines, rns = 1.f / (float)Ns;
     for (int it = threadIdx.x; it < total; it += blockDim.x) {
-        const int L = it / nb;
+        const int L = qdiv(it, nb, rnb);
         const int j = it - L * nb;
-        const int fb = L / nlines, l = L - fb * nlines;
+        const int fb = qdiv(L, nlines, rnl), l = L - fb * nlines;
         const float2* s = src + fb * fstride + l * lstride;
         float2* d = dst + fb * fstride + l * lstride;
-        const int jm = j % Ns;
+        const int jm = j - qdiv(j, Ns, rns) * Ns;
         const int o = (j - jm) * R + jm;          // (j / Ns) * Ns * R + j mod Ns
         const int te = jm * twstep;               // twiddle exponent step, r * te < n
         if (R == 4) {
@@ -275,10 +287,12 @@ __global__ __launch_bounds__(256) void k_fft_planes(PlaneParams P)
 
     // generate two real rows per complex line: row 2j -> real, row 2j+1 -> imaginary
     __syncthreads();   // twiddles visible
+    const float rpn3 = 1.f / (float)(npairs * n3), rn3 = 1.f / (float)n3, rnh = 1.f / (float)nh;
+    const float rpnh = 1.f / (float)(npairs * nh), rfnh = 1.f / (float)(nfb * nh);
     for (int idx = threadIdx.x; idx < nfb * npairs * n3; idx += blockDim.x) {
-        const int fb = idx / (npairs * n3);
+        const int fb = qdiv(idx, npairs * n3, rpn3);
         const int rem = idx - fb * npairs * n3;
-        const int j = rem / n3, R3 = rem - j * n3;
+        const int j = qdiv(rem, n3, rn3), R3 = rem - j * n3;
         const int f = fa + fb;
         const int ep = P.mono[3 * f], eq = P.mono[3 * f + 1], er = P.mono[3 * f + 2];
         const int t = P.kind == 1 ? f : mono_index(ep, eq, er);    // index of the field's lattice sum
@@ -312,9 +326,9 @@ __global__ __launch_bounds__(256) void k_fft_planes(PlaneParams P)
     float2* C = (Z == A) ? B : A;
     // unpack the packed real transforms: X_a = (Z_k + conj Z_-k)/2, X_b = -i (Z_k - conj Z_-k)/2
     for (int idx = threadIdx.x; idx < nfb * npairs * nh; idx += blockDim.x) {
-        const int fb = idx / (npairs * nh);
+        const int fb = qdiv(idx, npairs * nh, rpnh);
         const int rem = idx - fb * npairs * nh;
-        const int j = rem / nh, k = rem - j * nh;
+        const int j = qdiv(rem, nh, rnh), k = rem - j * nh;
         const float2 zk = Z[fb * BE + j * n3 + k];
         const int km = (k == 0) ? 0 : n3 - k;
         const float2 zm = Z[fb * BE + j * n3 + km];
@@ -329,9 +343,9 @@ __global__ __launch_bounds__(256) void k_fft_planes(PlaneParams P)
     // write: for each k2, the block's fields are contiguous runs of nh complex
     float2* out = P.X + ((size_t)(m * P.n1 + R1) * n2) * SF * nh + (size_t)(mu * P.F + fa) * nh;
     for (int idx = threadIdx.x; idx < n2 * nfb * nh; idx += blockDim.x) {
-        const int k2 = idx / (nfb * nh);
+        const int k2 = qdiv(idx, nfb * nh, rfnh);
         const int rem = idx - k2 * nfb * nh;
-        const int fb = rem / nh, k3 = rem - fb * nh;
+        const int fb = qdiv(rem, nh, rnh), k3 = rem - fb * nh;
         out[(size_t)k2 * SF * nh + rem] = Y[fb * BE + k2 * nh + k3];
     }
 }

@@ -95,7 +95,7 @@ __global__ __launch_bounds__(256) void k_lanczos(LanczosParams P)
 // into registers while the current one is filtered.  Two block barriers per plane.
 constexpr int kRT2 = 32, kRT3 = 64, kRThreads = 512, kRPPT = kRT2 * kRT3 / kRThreads;
 
-template <int M2>
+template <int M2, bool S1>
 __global__ __launch_bounds__(512, 2) void k_lanczos_ring(LanczosParams P)
 {
     constexpr int L2 = kRT2 + M2, L3 = kRT3 + M2;          // staging extent for s = 1
@@ -103,7 +103,7 @@ __global__ __launch_bounds__(512, 2) void k_lanczos_ring(LanczosParams P)
     __shared__ float wn_s[16 * M2];
     __shared__ float stg[L2 * L3];
     __shared__ float mid[L2 * kRT3];
-    const int s = P.s;
+    const int s = S1 ? 1 : P.s;              // S1: no oversampling, divisions by s vanish
     int b = blockIdx.x;
     const int b3 = b % P.nb3; b /= P.nb3;
     const int b2 = b % P.nb2;
@@ -128,12 +128,13 @@ __global__ __launch_bounds__(512, 2) void k_lanczos_ring(LanczosParams P)
     }
     const size_t plane = (size_t)P.e[1] * P.e[2];
     const int e1a = o1 / s + eo, e1b = (o1 + T1 - 1) / s + eo + M2 - 1;
-    constexpr bool DEEP = true;           // two planes in flight
-    float pf[NSTG], pf2[NSTG];
+    // two register buffers alternate: the load of plane e1 + 2 is issued right
+    // after plane e1 is staged, so every load has two plane iterations to land
+    float pa[NSTG], pb[NSTG];
 #pragma unroll
     for (int k = 0; k < NSTG; ++k) {
-        pf[k] = soff[k] >= 0 ? P.in[(size_t)e1a * plane + soff[k]] : 0.f;
-        if (DEEP) pf2[k] = (soff[k] >= 0 && e1a + 1 <= e1b) ? P.in[(size_t)(e1a + 1) * plane + soff[k]] : 0.f;
+        pa[k] = soff[k] >= 0 ? P.in[(size_t)e1a * plane + soff[k]] : 0.f;
+        pb[k] = (soff[k] >= 0 && e1a + 1 <= e1b) ? P.in[(size_t)(e1a + 1) * plane + soff[k]] : 0.f;
     }
 
     float ring[M2][kRPPT];
@@ -144,23 +145,15 @@ __global__ __launch_bounds__(512, 2) void k_lanczos_ring(LanczosParams P)
     const int j3 = threadIdx.x & 63;
     const int j2b = threadIdx.x >> 6;       // rows j2b + 8 k
 
-    for (int e1 = e1a; e1 <= e1b; ++e1) {
+    auto plane_step = [&](int e1, float (&buf)[NSTG]) {
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < NSTG; ++k) {
-            if (soff[k] >= 0) stg[threadIdx.x + kRThreads * k] = pf[k];
-            if (DEEP) pf[k] = pf2[k];
-        }
-        if (DEEP) {
-            if (e1 + 2 <= e1b) {
-#pragma unroll
-                for (int k = 0; k < NSTG; ++k)
-                    if (soff[k] >= 0) pf2[k] = P.in[(size_t)(e1 + 2) * plane + soff[k]];
-            }
-        } else if (e1 < e1b) {
+        for (int k = 0; k < NSTG; ++k)
+            if (soff[k] >= 0) stg[threadIdx.x + kRThreads * k] = buf[k];
+        if (e1 + 2 <= e1b) {
 #pragma unroll
             for (int k = 0; k < NSTG; ++k)
-                if (soff[k] >= 0) pf[k] = P.in[(size_t)(e1 + 1) * plane + soff[k]];
+                if (soff[k] >= 0) buf[k] = P.in[(size_t)(e1 + 2) * plane + soff[k]];
         }
         __syncthreads();
         // axis 3: mid[r][j3] for every staged row
@@ -168,8 +161,8 @@ __global__ __launch_bounds__(512, 2) void k_lanczos_ring(LanczosParams P)
             const int r = idx >> 6, jj = idx & 63;
             if (jj < T3) {
                 const int i3 = o3 + jj;
-                const float* w = wn_s + (i3 % s) * M2;
-                const float* x = stg + r * E3n + (i3 / s + eo - E3lo);
+                const float* w = wn_s + (S1 ? 0 : (i3 % s) * M2);
+                const float* x = stg + r * E3n + ((S1 ? i3 : i3 / s) + eo - E3lo);
                 float acc = 0.f;
 #pragma unroll
                 for (int d = 0; d < M2; ++d) acc += w[d] * x[d];
@@ -184,8 +177,8 @@ __global__ __launch_bounds__(512, 2) void k_lanczos_ring(LanczosParams P)
             float v = 0.f;
             if (j2 < T2 && j3 < T3) {
                 const int i2 = o2 + j2;
-                const float* w = wn_s + (i2 % s) * M2;
-                const float* x = mid + (i2 / s + eo - E2lo) * kRT3 + j3;
+                const float* w = wn_s + (S1 ? 0 : (i2 % s) * M2);
+                const float* x = mid + ((S1 ? i2 : i2 / s) + eo - E2lo) * kRT3 + j3;
 #pragma unroll
                 for (int d = 0; d < M2; ++d) v += w[d] * x[d * kRT3];
             }
@@ -212,6 +205,10 @@ __global__ __launch_bounds__(512, 2) void k_lanczos_ring(LanczosParams P)
                 }
             }
         }
+    };
+    for (int e1 = e1a; e1 <= e1b; e1 += 2) {
+        plane_step(e1, pa);
+        if (e1 + 1 <= e1b) plane_step(e1 + 1, pb);
     }
 }
 
@@ -236,9 +233,17 @@ hipError_t launch_lanczos(const LanczosParams& p, hipStream_t st)
         q.nb2 = (p.o[1] + kRT2 - 1) / kRT2;
         q.nb3 = (p.o[2] + kRT3 - 1) / kRT3;
         const dim3 grid(q.nb1 * q.nb2 * q.nb3);
-        if (p.m == 2) hipLaunchKernelGGL(k_lanczos_ring<4>, grid, dim3(kRThreads), 0, st, q);
-        else if (p.m == 3) hipLaunchKernelGGL(k_lanczos_ring<6>, grid, dim3(kRThreads), 0, st, q);
-        else hipLaunchKernelGGL(k_lanczos_ring<8>, grid, dim3(kRThreads), 0, st, q);
+        const bool s1 = p.s == 1;
+        if (p.m == 2) {
+            if (s1) hipLaunchKernelGGL((k_lanczos_ring<4, true>), grid, dim3(kRThreads), 0, st, q);
+            else hipLaunchKernelGGL((k_lanczos_ring<4, false>), grid, dim3(kRThreads), 0, st, q);
+        } else if (p.m == 3) {
+            if (s1) hipLaunchKernelGGL((k_lanczos_ring<6, true>), grid, dim3(kRThreads), 0, st, q);
+            else hipLaunchKernelGGL((k_lanczos_ring<6, false>), grid, dim3(kRThreads), 0, st, q);
+        } else {
+            if (s1) hipLaunchKernelGGL((k_lanczos_ring<8, true>), grid, dim3(kRThreads), 0, st, q);
+            else hipLaunchKernelGGL((k_lanczos_ring<8, false>), grid, dim3(kRThreads), 0, st, q);
+        }
         return hipGetLastError();
     }
     const size_t lds = lanczos_lds_bytes(p);
