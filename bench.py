@@ -134,6 +134,78 @@ def recombine_work(n, S, nclass3, N, M, g0, cnt, nh, F, friedel=False):
     return flops, bytes_
 
 
+def bench_ensemble(dsx, torch, dev, steps, warmup, lm=2):
+    """Batched ensemble (8 models x 8 configurations, edges from {16,20,24,32,40}, 1-4
+    sites, Taylor order 6, |h|,|k|,|l| <= 4, Lanczos filter): one graph replay against the
+    plain path that calls noise_filter model by model.  Both steps first upload every
+    configuration again (device-to-device set_sites), so both recompute all spectra."""
+    import synth
+    models = synth.ensemble()
+    hs, outs, sites = [], [], []
+    for m in models:
+        h = dsx.Model(cell=m.cell, n=m.n, frac=m.frac, b=m.b, taylor_order=m.order,
+                      n_configs=m.n_configs, has_occ=m.occ is not None)
+        h.set_grid(m.g0, m.count)
+        st = []
+        for c in range(m.n_configs):
+            occ = None if m.occ is None else torch.from_numpy(m.occ[c]).to(dev)
+            disp = None if m.disp is None else torch.from_numpy(m.disp[c]).to(dev)
+            st.append((occ, disp))
+            h.set_sites(c, occ, disp)
+        hs.append(h)
+        sites.append(st)
+        outs.append(torch.empty(tuple(m.count), dtype=torch.float32, device=dev))
+    voxels = sum(int(np.prod(m.count)) * m.n_configs for m in models)
+
+    def upload():
+        for h, st in zip(hs, sites):
+            for c, (occ, disp) in enumerate(st):
+                h.set_sites(c, occ, disp)
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    def plain():
+        upload()
+        for h, o in zip(hs, outs):
+            h.noise_filter(lm, 1, o)
+
+    t_upload = timed(upload)
+    t_plain = timed(plain)
+    ref = [o.clone() for o in outs]
+    c0 = time.perf_counter()
+    batch = dsx.Batch(hs, outs, lanczos_m=lm)
+    t_create = time.perf_counter() - c0
+
+    def batched():
+        upload()
+        batch.run()
+
+    t_batch = timed(batched)
+    same = all(torch.equal(a, b) for a, b in zip(ref, outs))
+    batch.close()
+    for h in hs:
+        h.close()
+    return {"workload": "8 models x 8 configurations, edges {16,20,24,32,40}, 1-4 fcc-prefix sites, "
+                        "displacive (Taylor order 6) or compositional, |h|,|k|,|l|<=4, Lanczos m=2",
+            "voxels_per_step": voxels,
+            "batched_voxels_per_s": round(voxels / t_batch, 1),
+            "plain_voxels_per_s": round(voxels / t_plain, 1),
+            "batched_ms": round(t_batch * 1e3, 3), "plain_ms": round(t_plain * 1e3, 3),
+            "upload_ms": round(t_upload * 1e3, 3),
+            "batched_compute_ms": round((t_batch - t_upload) * 1e3, 3),
+            "plain_compute_ms": round((t_plain - t_upload) * 1e3, 3),
+            "create_and_tune_s": round(t_create, 2),
+            "batched_equals_plain": bool(same)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,6 +221,9 @@ def main():
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the traffic summary from two rocprofv3 --pmc output folders and exit")
     ap.add_argument("--pmc-command", default="", help="command line recorded in the traffic summary")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble comparison")
+    ap.add_argument("--ensemble-only", action="store_true",
+                    help="time only the batched ensemble (for kernel traces of the graph path)")
     args = ap.parse_args()
     if args.summarize_pmc:
         print(json.dumps(summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], TRAFFIC_MD,
@@ -166,6 +241,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.ensemble_only:
+        print(json.dumps({"ensemble": bench_ensemble(dsx, torch, dev, args.steps, args.warmup)}))
+        return
     N, lm = args.order, args.lanczos_m
     model = synth.displacive(n=32, M=1, order=N, hmax=8)
     n, S, M = model.n, model.n_sites, model.n_configs
@@ -290,6 +368,8 @@ def main():
         parity["rel_l2_vs_fp64_exact_256"] = float(np.linalg.norm(g[:256] - I_ex) / np.linalg.norm(I_ex))
     h.close()
 
+    ensemble = None if args.no_ensemble else bench_ensemble(dsx, torch, dev, max(3, args.steps // 4), 2)
+
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "voxels/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 4),
@@ -307,6 +387,8 @@ def main():
     }
     if sweep is not None:
         line["compute_intensity_voxels_per_s_by_order"] = sweep
+    if ensemble is not None:
+        line["ensemble"] = ensemble
     print(json.dumps(line))
 
 

@@ -45,7 +45,8 @@ enum {
     DSX_ERR_NOMEM = -3,        /* device or host allocation failed               */
     DSX_ERR_DEVICE = -4,       /* HIP error; the model is now failed             */
     DSX_ERR_UNSUPPORTED = -5,  /* valid but outside what this build implements   */
-    DSX_ERR_BUSY = -6          /* serving: admission refused and queue full      */
+    DSX_ERR_BUSY = -6          /* resource held: model recorded in a batch, or a
+                                  server's request queue is full                 */
 };
 
 enum { DSX_NUCLEAR = 0, DSX_MAGNETIC = 1 };
@@ -152,7 +153,47 @@ dsx_status dsx_compute_intensity(dsx_model m, float* out, int32_t where, void* h
 dsx_status dsx_noise_filter(dsx_model m, int32_t lanczos_m, int32_t oversample, float* out,
                             int32_t where, void* hip_stream);
 
-/* Release a model and all its device memory (waits for its pending work). */
+/*
+ * Batched execution (an execution pattern; the arithmetic is that of
+ * dsx_compute_intensity / dsx_noise_filter).  The paper prefers many small
+ * supercells averaged as an ensemble (Sec. III.B) and notes that their intensity
+ * calculations can run in parallel (Sec. VI).  A batch fixes a set of ready models
+ * (sites and grid set), one device output per model and the filter parameters.
+ * dsx_batch_create tunes and plans every model (dsx_autotune), then records the
+ * whole launch sequence -- per model its lattice sums, FFTs, recombination, Bragg
+ * points and, when lanczos_m >= 2, the filter; each model on its own forked stream
+ * -- into one hipGraph.  dsx_batch_run replays it on hip_stream: one graph launch
+ * recomputes every model from its current sites (dsx_set_sites between runs is
+ * allowed; grids and outputs are fixed).
+ *   models[n]  distinct models; n >= 1
+ *   lanczos_m  0 = unfiltered I(G) (outs[i]: [count0][count1][count2] of model i),
+ *              >= 2 = filtered with oversample s (outs[i]: [s count0][s count1][s count2])
+ *   outs[n]    device pointers, owned by the caller, alive while the batch is used
+ * While a batch exists its models keep the buffers it recorded: dsx_set_grid,
+ * dsx_destroy_model and a dsx_noise_filter whose grown box would need a larger
+ * buffer return DSX_ERR_BUSY.  Other calls on the models stay allowed; every call
+ * on a model, batch replays included, is ordered after the model's previous work
+ * whatever stream it was on.
+ */
+typedef struct dsx_batch_s* dsx_batch;
+
+dsx_status dsx_batch_create(const dsx_model* models, int32_t n, int32_t lanczos_m, int32_t oversample,
+                            float* const* outs, dsx_batch* out);
+dsx_status dsx_batch_run(dsx_batch b, void* hip_stream);
+dsx_status dsx_batch_destroy(dsx_batch b);
+
+/*
+ * Autotuner: times the kernel variants of a ready model for its key (kind, n,
+ * sites, order, configurations, box, filter) -- the recombination form, the number
+ * of fields per FFT plane block and the filter's plane segment -- and keeps the
+ * fastest.  With DSX_TUNE_CACHE naming a file, choices are read from / appended to
+ * it (one line per key), so a key is tuned once and then always gets the same plan.
+ * Runs kernels on hip_stream and waits for them.
+ */
+dsx_status dsx_autotune(dsx_model m, int32_t lanczos_m, void* hip_stream);
+
+/* Release a model and all its device memory (waits for its pending work).
+ * DSX_ERR_BUSY while a batch still holds the model. */
 dsx_status dsx_destroy_model(dsx_model m);
 
 /* Message for the last failed call on this thread ("" if none). Never NULL. */

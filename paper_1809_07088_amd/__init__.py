@@ -49,7 +49,8 @@ class KernelStat(ctypes.Structure):
 
 EXPORTS = ("dsx_plan_query", "dsx_create_model", "dsx_set_sites", "dsx_set_grid",
            "dsx_compute_intensity", "dsx_noise_filter", "dsx_destroy_model", "dsx_last_error",
-           "dsx_version", "dsx_profile_enable", "dsx_profile_read", "dsx_profile_reset")
+           "dsx_version", "dsx_profile_enable", "dsx_profile_read", "dsx_profile_reset",
+           "dsx_batch_create", "dsx_batch_run", "dsx_batch_destroy", "dsx_autotune")
 
 _lib = None
 
@@ -78,6 +79,12 @@ def lib():
         L.dsx_profile_read.restype = i32
         L.dsx_profile_reset.argtypes = []
         L.dsx_profile_reset.restype = i32
+        L.dsx_batch_create.argtypes = [P, i32, i32, i32, P, ctypes.POINTER(P)]
+        L.dsx_batch_run.argtypes = [P, P]
+        L.dsx_batch_destroy.argtypes = [P]
+        L.dsx_autotune.argtypes = [P, i32, P]
+        for f in ("dsx_batch_create", "dsx_batch_run", "dsx_batch_destroy", "dsx_autotune"):
+            getattr(L, f).restype = i32
         for f in ("dsx_plan_query", "dsx_create_model", "dsx_set_sites", "dsx_set_grid",
                   "dsx_compute_intensity", "dsx_noise_filter", "dsx_destroy_model"):
             getattr(L, f).restype = i32
@@ -205,6 +212,40 @@ def profile_read() -> dict:
     return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(n)}
 
 
+def autotune(model, lanczos_m=0, stream=None):
+    _check(lib().dsx_autotune(model, int(lanczos_m), _stream_handle(stream)))
+
+
+class Batch:
+    """A recorded launch sequence over several models (dsx_batch_*): run() replays it."""
+
+    def __init__(self, models, outs, lanczos_m=0, oversample=1):
+        handles = [m.handle if isinstance(m, Model) else m for m in models]
+        if len(handles) != len(outs) or not handles:
+            raise ValueError("one output per model, at least one model")
+        self._keep = (list(models), list(outs))
+        arr_m = (ctypes.c_void_p * len(handles))(*handles)
+        arr_o = (ctypes.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
+        h = ctypes.c_void_p()
+        _check(lib().dsx_batch_create(ctypes.cast(arr_m, ctypes.c_void_p), len(handles), int(lanczos_m),
+                                      int(oversample), ctypes.cast(arr_o, ctypes.c_void_p), ctypes.byref(h)))
+        self.handle = h.value
+
+    def run(self, stream=None):
+        _check(lib().dsx_batch_run(self.handle, _stream_handle(stream)))
+
+    def close(self):
+        if self.handle:
+            _check(lib().dsx_batch_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Model:
     """Convenience owner of one dsx model handle."""
 
@@ -224,6 +265,9 @@ class Model:
 
     def noise_filter(self, lanczos_m, oversample, out, stream=None):
         return noise_filter(self.handle, lanczos_m, oversample, out, stream)
+
+    def autotune(self, lanczos_m=0, stream=None):
+        autotune(self.handle, lanczos_m, stream)
 
     def close(self):
         if self.handle:

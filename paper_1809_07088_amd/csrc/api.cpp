@@ -13,6 +13,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <map>
 #include <mutex>
 #include <string>
@@ -199,13 +201,20 @@ struct dsx_model_s {
     std::map<Box, DeviceTables> tables;
     std::map<std::pair<int, int>, float*> lanczos_w;
     int sum_chunks = 0;
+    // plan knobs (defaults, or chosen by the autotuner for this model's key)
+    int tune_recomb_variant = 0;   // 0 default form, 2 class form
+    int tune_fchunk = 0;           // fields per FFT plane block (0 = heuristic)
+    int tune_lanczos_t1 = 32;      // planes per filter block
+    bool tuned = false;
     // state
     std::vector<char> set;
     bool dirty = true;
     bool failed = false;
     bool grid_set = false;
     Box box{};
-    hipStream_t last_stream = nullptr;
+    hipStream_t last_stream = nullptr;   // stream of the last enqueued work
+    hipEvent_t order_ev = nullptr;       // orders work across the caller's streams
+    int pins = 0;                        // batches that recorded this model's buffers
 };
 
 namespace {
@@ -317,13 +326,27 @@ void free_model(dsx_model m)
         dfree(kv.second.work);
     }
     for (auto& kv : m->lanczos_w) dfree(kv.second);
+    if (m->order_ev) (void)hipEventDestroy(m->order_ev);
+}
+
+// Calls on one model are serialised: work enqueued on st starts after everything the
+// model enqueued before, on whichever stream that was.
+dsx_status follow(dsx_model m, hipStream_t st)
+{
+    if (m->last_stream != st) {
+        HIPCHK(m, hipEventRecord(m->order_ev, m->last_stream));
+        HIPCHK(m, hipStreamWaitEvent(st, m->order_ev, 0));
+    }
+    m->last_stream = st;
+    return DSX_OK;
 }
 
 dsx_status tables_for(dsx_model m, const Box& bx, DeviceTables** out)
 {
     auto it = m->tables.find(bx);
     if (it != m->tables.end()) { *out = &it->second; return DSX_OK; }
-    if (m->tables.size() >= 8) {   // keep the cache small: drop every cached box
+    if (m->tables.size() >= 8 && m->pins == 0) {   // keep the cache small: drop every cached box
+        // (never while a recorded batch still points at a cached table)
         hipError_t se = hipStreamSynchronize(m->last_stream);
         if (se != hipSuccess) { m->failed = true; return fail(DSX_ERR_DEVICE, hipGetErrorString(se)); }
         for (auto& kv : m->tables) {
@@ -468,8 +491,8 @@ dsx_status plan_recombine(dsx_model m, const Box& bx, float* out, LaunchPlan& lp
     p.work = tb->work; p.nwork = tb->nwork;
     p.nchunk3 = tb->nchunk3;
     {
-        static const int forced = [] { const char* v = std::getenv("DSX_RECOMBINE_VARIANT"); return v ? std::atoi(v) : 0; }();
-        p.variant = forced;
+        static const int forced = [] { const char* v = std::getenv("DSX_RECOMBINE_VARIANT"); return v ? std::atoi(v) : -1; }();
+        p.variant = forced >= 0 ? forced : m->tune_recomb_variant;
     }
     p.nsc = (int)m->sc_start.size() - 1;
     for (size_t i = 0; i < m->sc_start.size(); ++i) p.sc_start[i] = m->sc_start[i];
@@ -526,9 +549,9 @@ dsx_status plan_recombine(dsx_model m, const Box& bx, float* out, LaunchPlan& lp
     return DSX_OK;
 }
 
-dsx_status ensure_spectra(dsx_model m, hipStream_t st)
+dsx_status ensure_spectra(dsx_model m, hipStream_t st, bool force = false)
 {
-    if (!m->dirty) return DSX_OK;
+    if (!m->dirty && !force) return DSX_OK;
     SumsParams sp{};
     sp.occ = m->has_occ ? m->d_occ : nullptr;
     sp.vec = m->d_vec;
@@ -552,6 +575,7 @@ dsx_status ensure_spectra(dsx_model m, hipStream_t st)
     int fb = (int)std::max<size_t>(1, (24 * 1024 / sizeof(float2) - m->n[1] - m->n[2]) / (2 * (size_t)pp.buf_elems));
     fb = std::min(fb, 4);
     while (fb > 1 && planes * ((m->F + fb - 1) / fb) < 2048) --fb;
+    if (m->tune_fchunk > 0) fb = m->tune_fchunk;
     pp.fchunk = std::min(fb, m->F);
     pp.nfchunk = (m->F + pp.fchunk - 1) / pp.fchunk;
     if (m->kind == DSX_NUCLEAR) {
@@ -612,6 +636,11 @@ dsx_status stage(dsx_model m, size_t elems, float** p)
     return DSX_OK;
 }
 
+}  // namespace
+
+namespace {
+dsx_status prepare_intensity(dsx_model m);
+dsx_status enqueue_intensity(dsx_model m, float* dout, hipStream_t st, bool force);
 }  // namespace
 
 extern "C" {
@@ -737,6 +766,7 @@ dsx_status dsx_create_model(const dsx_model_desc* d, dsx_model* out)
     if (e == hipSuccess) e = alloc((void**)&m->d_partial, M * S * m->sum_chunks * m->T * sizeof(double));
     if (e == hipSuccess) e = alloc((void**)&m->d_sums, M * S * m->T * sizeof(double));
     if (e == hipSuccess) e = alloc((void**)&m->d_X, (size_t)z.spectrum_bytes);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&m->order_ev, hipEventDisableTiming);
     if (e == hipSuccess) {
         std::vector<double> site((size_t)m->S * 11, 0.0);
         for (int mu = 0; mu < m->S; ++mu) {
@@ -794,6 +824,7 @@ dsx_status dsx_set_grid(dsx_model m, const int32_t g0[3], const int32_t count[3]
     dsx_status s = check_model(m);
     if (s != DSX_OK) return s;
     if (!g0 || !count) return fail(DSX_ERR_ARG, "g0 and count are required");
+    if (m->pins) return fail(DSX_ERR_BUSY, "the model is recorded in a batch; destroy the batch first");
     Box bx;
     long long vox = 1;
     for (int a = 0; a < 3; ++a) {
@@ -820,9 +851,9 @@ dsx_status dsx_compute_intensity(dsx_model m, float* out, int32_t where, void* h
     const size_t vox = (size_t)m->box.cnt[0] * m->box.cnt[1] * m->box.cnt[2];
     float* dout = out;
     if (where == DSX_HOST && (s = stage(m, vox, &dout)) != DSX_OK) return s;
-    m->last_stream = st;
-    if ((s = ensure_spectra(m, st)) != DSX_OK) return s;
-    if ((s = run_box(m, m->box, dout, st)) != DSX_OK) return s;
+    if ((s = prepare_intensity(m)) != DSX_OK) return s;
+    if ((s = follow(m, st)) != DSX_OK) return s;
+    if ((s = enqueue_intensity(m, dout, st, false)) != DSX_OK) return s;
     if (where == DSX_HOST) {
         HIPCHK(m, hipMemcpyAsync(out, dout, vox * sizeof(float), hipMemcpyDeviceToHost, st));
         HIPCHK(m, hipStreamSynchronize(st));
@@ -830,31 +861,30 @@ dsx_status dsx_compute_intensity(dsx_model m, float* out, int32_t where, void* h
     return DSX_OK;
 }
 
-dsx_status dsx_noise_filter(dsx_model m, int32_t lanczos_m, int32_t oversample, float* out,
-                            int32_t where, void* hip_stream)
+}  // extern "C"
+
+namespace {
+
+Box grown_box(const Box& b, int mm)
 {
-    dsx_status s = check_model(m);
-    if (s != DSX_OK) return s;
-    if (!out) return fail(DSX_ERR_ARG, "out is NULL");
-    if (where != DSX_HOST && where != DSX_DEVICE) return fail(DSX_ERR_ARG, "bad 'where'");
-    if (lanczos_m < 2) return fail(DSX_ERR_ARG, "lanczos_m must be >= 2");
-    if (oversample < 1) return fail(DSX_ERR_ARG, "oversample must be >= 1");
-    if (lanczos_m > 16 || oversample > 16) return fail(DSX_ERR_UNSUPPORTED, "lanczos_m and oversample are limited to 16");
-    if ((s = ready(m)) != DSX_OK) return s;
-    hipStream_t st = (hipStream_t)hip_stream;
-    const int mm = lanczos_m, sv = oversample;
-    Box ext;
-    size_t ext_vox = 1, out_vox = 1;
     // grown box [g0 - m, g0 + count + m): the window of output Q_a = g0_a + i/s spans
     // G_a in [floor(Q_a) - m + 1, floor(Q_a) + m]; growing by m on both sides (one
     // unused plane below) keeps a box symmetric about 0 symmetric.
+    Box ext;
     for (int a = 0; a < 3; ++a) {
-        ext.g0[a] = m->box.g0[a] - mm;
-        ext.cnt[a] = m->box.cnt[a] + 2 * mm;
-        ext_vox *= ext.cnt[a];
-        out_vox *= (size_t)sv * m->box.cnt[a];
+        ext.g0[a] = b.g0[a] - mm;
+        ext.cnt[a] = b.cnt[a] + 2 * mm;
     }
+    return ext;
+}
+
+// Everything the filter needs that allocates or uploads (never inside a capture).
+dsx_status prepare_filter(dsx_model m, int mm, int sv)
+{
+    const Box ext = grown_box(m->box, mm);
+    const size_t ext_vox = (size_t)ext.cnt[0] * ext.cnt[1] * ext.cnt[2];
     if (m->ext_cap < ext_vox) {
+        if (m->pins) return fail(DSX_ERR_BUSY, "the grown box would outgrow a buffer a batch has recorded");
         dfree(m->d_ext);
         m->d_ext = nullptr; m->ext_cap = 0;
         hipError_t e = hipMalloc(&m->d_ext, ext_vox * sizeof(float));
@@ -883,18 +913,30 @@ dsx_status dsx_noise_filter(dsx_model m, int32_t lanczos_m, int32_t oversample, 
         HIPCHK(m, hipMemcpy(dw, w.data(), w.size() * sizeof(float), hipMemcpyHostToDevice));
         m->lanczos_w[key] = dw;
     }
-    float* dout = out;
-    if (where == DSX_HOST && (s = stage(m, out_vox, &dout)) != DSX_OK) return s;
-    m->last_stream = st;
-    if ((s = ensure_spectra(m, st)) != DSX_OK) return s;
-    if ((s = run_box(m, ext, m->d_ext, st)) != DSX_OK) return s;
+    DeviceTables* tb = nullptr;
+    return tables_for(m, ext, &tb);
+}
 
+dsx_status prepare_intensity(dsx_model m)
+{
+    DeviceTables* tb = nullptr;
+    return tables_for(m, m->box, &tb);
+}
+
+// Stream-ordered launches only: spectra (when stale or forced), recombination on
+// the grown box, Bragg points, filter.
+dsx_status enqueue_filter(dsx_model m, int mm, int sv, float* dout, hipStream_t st, bool force)
+{
+    dsx_status s;
+    const Box ext = grown_box(m->box, mm);
+    if ((s = ensure_spectra(m, st, force)) != DSX_OK) return s;
+    if ((s = run_box(m, ext, m->d_ext, st)) != DSX_OK) return s;
     LanczosParams lp{};
-    lp.in = m->d_ext; lp.out = dout; lp.wn = m->lanczos_w[key];
+    lp.in = m->d_ext; lp.out = dout; lp.wn = m->lanczos_w[std::make_pair(mm, sv)];
     for (int a = 0; a < 3; ++a) { lp.e[a] = ext.cnt[a]; lp.o[a] = sv * m->box.cnt[a]; }
     lp.m = mm; lp.s = sv;
     lp.eoff = 1;
-    lp.t3 = 64; lp.t1 = 32;
+    lp.t3 = 64; lp.t1 = m->tune_lanczos_t1;
     lp.t2 = 32;
     while (lp.t2 > 1 && lanczos_lds_bytes(lp) > 150 * 1024) lp.t2 /= 2;
     while (lp.t3 > 8 && lanczos_lds_bytes(lp) > 150 * 1024) lp.t3 /= 2;
@@ -902,6 +944,45 @@ dsx_status dsx_noise_filter(dsx_model m, int32_t lanczos_m, int32_t oversample, 
     lp.nb2 = (lp.o[1] + lp.t2 - 1) / lp.t2;
     lp.nb3 = (lp.o[2] + lp.t3 - 1) / lp.t3;
     HIPCHK(m, timed("lanczos", st, [&] { return launch_lanczos(lp, st); }));
+    return DSX_OK;
+}
+
+dsx_status enqueue_intensity(dsx_model m, float* dout, hipStream_t st, bool force)
+{
+    dsx_status s;
+    if ((s = ensure_spectra(m, st, force)) != DSX_OK) return s;
+    return run_box(m, m->box, dout, st);
+}
+
+dsx_status check_filter_args(int32_t lanczos_m, int32_t oversample)
+{
+    if (lanczos_m < 2) return fail(DSX_ERR_ARG, "lanczos_m must be >= 2");
+    if (oversample < 1) return fail(DSX_ERR_ARG, "oversample must be >= 1");
+    if (lanczos_m > 16 || oversample > 16) return fail(DSX_ERR_UNSUPPORTED, "lanczos_m and oversample are limited to 16");
+    return DSX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dsx_status dsx_noise_filter(dsx_model m, int32_t lanczos_m, int32_t oversample, float* out,
+                            int32_t where, void* hip_stream)
+{
+    dsx_status s = check_model(m);
+    if (s != DSX_OK) return s;
+    if (!out) return fail(DSX_ERR_ARG, "out is NULL");
+    if (where != DSX_HOST && where != DSX_DEVICE) return fail(DSX_ERR_ARG, "bad 'where'");
+    if ((s = check_filter_args(lanczos_m, oversample)) != DSX_OK) return s;
+    if ((s = ready(m)) != DSX_OK) return s;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const size_t out_vox = (size_t)oversample * m->box.cnt[0] * oversample * m->box.cnt[1] *
+                           oversample * m->box.cnt[2];
+    if ((s = prepare_filter(m, lanczos_m, oversample)) != DSX_OK) return s;
+    float* dout = out;
+    if (where == DSX_HOST && (s = stage(m, out_vox, &dout)) != DSX_OK) return s;
+    if ((s = follow(m, st)) != DSX_OK) return s;
+    if ((s = enqueue_filter(m, lanczos_m, oversample, dout, st, false)) != DSX_OK) return s;
     if (where == DSX_HOST) {
         HIPCHK(m, hipMemcpyAsync(out, dout, out_vox * sizeof(float), hipMemcpyDeviceToHost, st));
         HIPCHK(m, hipStreamSynchronize(st));
@@ -909,9 +990,275 @@ dsx_status dsx_noise_filter(dsx_model m, int32_t lanczos_m, int32_t oversample, 
     return DSX_OK;
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------- autotuner
+namespace {
+
+std::string tune_key(dsx_model m, int lm)
+{
+    std::ostringstream k;
+    k << "gfx950|" << m->kind << "|" << m->n[0] << "," << m->n[1] << "," << m->n[2] << "|S" << m->S
+      << "|N" << m->order << "|M" << m->M << "|occ" << m->has_occ << "|box" << m->box.g0[0] << ","
+      << m->box.g0[1] << "," << m->box.g0[2] << "," << m->box.cnt[0] << "," << m->box.cnt[1] << ","
+      << m->box.cnt[2] << "|m" << lm;
+    return k.str();
+}
+
+std::mutex g_tune_mu;
+
+bool tune_lookup(const std::string& key, int* v, int* fc, int* t1)
+{
+    const char* path = std::getenv("DSX_TUNE_CACHE");
+    if (!path || !*path) return false;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    std::ifstream f(path);
+    std::string line;
+    bool found = false;
+    while (std::getline(f, line)) {
+        const size_t tab = line.find('\t');
+        if (tab == std::string::npos || line.substr(0, tab) != key) continue;
+        std::istringstream in(line.substr(tab + 1));
+        int a, b, c;
+        if (in >> a >> b >> c) { *v = a; *fc = b; *t1 = c; found = true; }
+    }
+    return found;
+}
+
+void tune_store(const std::string& key, int v, int fc, int t1)
+{
+    const char* path = std::getenv("DSX_TUNE_CACHE");
+    if (!path || !*path) return;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    std::ofstream f(path, std::ios::app);
+    f << key << "\t" << v << " " << fc << " " << t1 << "\n";
+}
+
+// Minimum over `reps` timed runs of fn() on stream st (milliseconds), or < 0 on error.
+template <typename Fn>
+float time_min(hipStream_t st, int reps, Fn fn)
+{
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return -1.f;
+    if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return -1.f; }
+    float best = -1.f;
+    for (int r = 0; r < reps; ++r) {
+        if (hipEventRecord(a, st) != hipSuccess) break;
+        if (fn() != DSX_OK) { best = -1.f; break; }
+        if (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess) break;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, a, b) != hipSuccess) break;
+        if (best < 0.f || ms < best) best = ms;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return best;
+}
+
+}  // namespace
+
+extern "C" {
+
+dsx_status dsx_autotune(dsx_model m, int32_t lanczos_m, void* hip_stream)
+{
+    dsx_status s = check_model(m);
+    if (s != DSX_OK) return s;
+    if ((s = ready(m)) != DSX_OK) return s;
+    const bool filt = lanczos_m >= 2;
+    if (lanczos_m != 0 && (s = check_filter_args(lanczos_m, 1)) != DSX_OK) return s;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const std::string key = tune_key(m, lanczos_m);
+    int v = 0, fc = 0, t1 = 32;
+    if (tune_lookup(key, &v, &fc, &t1)) {
+        m->tune_recomb_variant = v; m->tune_fchunk = fc; m->tune_lanczos_t1 = t1;
+        m->tuned = true;
+        return DSX_OK;
+    }
+    if ((s = prepare_intensity(m)) != DSX_OK) return s;
+    if (filt && (s = prepare_filter(m, lanczos_m, 1)) != DSX_OK) return s;
+    float* scratch = nullptr;
+    const size_t vox = (size_t)m->box.cnt[0] * m->box.cnt[1] * m->box.cnt[2];
+    if ((s = stage(m, vox, &scratch)) != DSX_OK) return s;
+    if ((s = follow(m, st)) != DSX_OK) return s;
+    const bool prof = g_prof.on;
+    g_prof.on = false;
+    // FFT: fields per plane block
+    float best = -1.f;
+    int best_fc = 0;
+    for (int cand : {0, 1, 2, 4}) {
+        m->tune_fchunk = cand;
+        const float t = time_min(st, 3, [&] { return ensure_spectra(m, st, true); });
+        if (t >= 0.f && (best < 0.f || t < best)) { best = t; best_fc = cand; }
+    }
+    m->tune_fchunk = best_fc;
+    // recombination form (the parity form only exists for nuclear models whose r3 are halves)
+    best = -1.f;
+    int best_v = 0;
+    const Box b = filt ? grown_box(m->box, lanczos_m) : m->box;
+    float* dst = filt ? m->d_ext : scratch;
+    for (int cand : {0, 2}) {
+        if (cand == 2 && m->kind != DSX_NUCLEAR) continue;
+        m->tune_recomb_variant = cand;
+        const float t = time_min(st, 3, [&] { return run_box(m, b, dst, st); });
+        if (t >= 0.f && (best < 0.f || t < best)) { best = t; best_v = cand; }
+    }
+    m->tune_recomb_variant = best_v;
+    // filter: planes per block
+    int best_t1 = 32;
+    if (filt) {
+        best = -1.f;
+        for (int cand : {16, 32, 64}) {
+            m->tune_lanczos_t1 = cand;
+            const float t = time_min(st, 3, [&] { return enqueue_filter(m, lanczos_m, 1, scratch, st, false); });
+            if (t >= 0.f && (best < 0.f || t < best)) { best = t; best_t1 = cand; }
+        }
+        m->tune_lanczos_t1 = best_t1;
+    }
+    g_prof.on = prof;
+    if (m->failed) return fail(DSX_ERR_DEVICE, "device error during tuning");
+    m->tuned = true;
+    tune_store(key, best_v, best_fc, best_t1);
+    return DSX_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------- batches
+struct dsx_batch_s {
+    std::vector<dsx_model> models;
+    std::vector<float*> outs;
+    int lanczos_m = 0, oversample = 1;
+    hipStream_t cap = nullptr;
+    std::vector<hipStream_t> streams;
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> joins;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void free_batch(dsx_batch b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (auto e : b->joins) if (e) (void)hipEventDestroy(e);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    for (auto st : b->streams) if (st) (void)hipStreamDestroy(st);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+}
+
+}  // namespace
+
+extern "C" {
+
+dsx_status dsx_batch_create(const dsx_model* models, int32_t n, int32_t lanczos_m, int32_t oversample,
+                            float* const* outs, dsx_batch* out)
+{
+    if (!models || !outs || !out || n < 1) return fail(DSX_ERR_ARG, "models, outs and out are required, n >= 1");
+    *out = nullptr;
+    dsx_status s;
+    if (lanczos_m != 0 && (s = check_filter_args(lanczos_m, oversample)) != DSX_OK) return s;
+    for (int i = 0; i < n; ++i) {
+        if ((s = check_model(models[i])) != DSX_OK) return s;
+        if ((s = ready(models[i])) != DSX_OK) return s;
+        if (!outs[i]) return fail(DSX_ERR_ARG, "outs[" + std::to_string(i) + "] is NULL");
+        for (int j = 0; j < i; ++j)
+            if (models[j] == models[i]) return fail(DSX_ERR_ARG, "a model appears twice in the batch");
+    }
+    dsx_batch b = new (std::nothrow) dsx_batch_s();
+    if (!b) return fail(DSX_ERR_NOMEM, "host allocation failed");
+    b->models.assign(models, models + n);
+    b->outs.assign(outs, outs + n);
+    b->lanczos_m = lanczos_m;
+    b->oversample = lanczos_m ? oversample : 1;
+    auto bail = [&](dsx_status st) { free_batch(b); delete b; return st; };
+    hipError_t e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return bail(fail(DSX_ERR_DEVICE, hipGetErrorString(e)));
+    // plan and tune (allocations and uploads happen here, never during capture)
+    for (int i = 0; i < n; ++i) {
+        dsx_model m = b->models[i];
+        if (!m->tuned && (s = dsx_autotune(m, lanczos_m, b->cap)) != DSX_OK) return bail(s);
+        if ((s = prepare_intensity(m)) != DSX_OK) return bail(s);
+        if (lanczos_m && (s = prepare_filter(m, lanczos_m, b->oversample)) != DSX_OK) return bail(s);
+    }
+    if ((e = hipStreamSynchronize(b->cap)) != hipSuccess) return bail(fail(DSX_ERR_DEVICE, hipGetErrorString(e)));
+    b->streams.assign(n, nullptr);
+    b->joins.assign(n, nullptr);
+    if ((e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming)) != hipSuccess)
+        return bail(fail(DSX_ERR_DEVICE, hipGetErrorString(e)));
+    for (int i = 0; i < n; ++i) {
+        if ((e = hipStreamCreateWithFlags(&b->streams[i], hipStreamNonBlocking)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&b->joins[i], hipEventDisableTiming)) != hipSuccess)
+            return bail(fail(DSX_ERR_DEVICE, hipGetErrorString(e)));
+    }
+    // record every model's launch sequence into one graph
+    const bool prof = g_prof.on;
+    g_prof.on = false;
+    dsx_status cs = DSX_OK;
+    if ((e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed)) != hipSuccess) {
+        g_prof.on = prof;
+        return bail(fail(DSX_ERR_DEVICE, hipGetErrorString(e)));
+    }
+    e = hipEventRecord(b->fork, b->cap);
+    for (int i = 0; i < n && e == hipSuccess && cs == DSX_OK; ++i) {
+        dsx_model m = b->models[i];
+        hipStream_t si = b->streams[i];
+        if ((e = hipStreamWaitEvent(si, b->fork, 0)) != hipSuccess) break;
+        cs = lanczos_m ? enqueue_filter(m, lanczos_m, b->oversample, b->outs[i], si, true)
+                       : enqueue_intensity(m, b->outs[i], si, true);
+        if (cs != DSX_OK) break;
+        if ((e = hipEventRecord(b->joins[i], si)) != hipSuccess) break;
+        e = hipStreamWaitEvent(b->cap, b->joins[i], 0);
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t ee = hipStreamEndCapture(b->cap, &g);
+    g_prof.on = prof;
+    b->graph = g;
+    if (cs != DSX_OK) return bail(cs);
+    if (e != hipSuccess || ee != hipSuccess)
+        return bail(fail(DSX_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : ee)));
+    if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess)
+        return bail(fail(DSX_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e)));
+    for (dsx_model m : b->models) ++m->pins;
+    *out = b;
+    return DSX_OK;
+}
+
+dsx_status dsx_batch_run(dsx_batch b, void* hip_stream)
+{
+    if (!b) return fail(DSX_ERR_ARG, "batch is NULL");
+    for (dsx_model m : b->models) {
+        dsx_status s = check_model(m);
+        if (s != DSX_OK) return s;
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    for (dsx_model m : b->models) {
+        dsx_status s = follow(m, st);
+        if (s != DSX_OK) return s;
+    }
+    const hipError_t e = hipGraphLaunch(b->exec, st);
+    if (e != hipSuccess) {
+        for (dsx_model m : b->models) m->failed = true;
+        return fail(DSX_ERR_DEVICE, std::string("graph launch: ") + hipGetErrorString(e));
+    }
+    for (dsx_model m : b->models) m->dirty = false;
+    return DSX_OK;
+}
+
+dsx_status dsx_batch_destroy(dsx_batch b)
+{
+    if (!b) return fail(DSX_ERR_ARG, "batch is NULL");
+    for (dsx_model m : b->models) { (void)hipStreamSynchronize(m->last_stream); --m->pins; }
+    free_batch(b);
+    delete b;
+    return DSX_OK;
+}
+
 dsx_status dsx_destroy_model(dsx_model m)
 {
     if (!m) return fail(DSX_ERR_ARG, "model is NULL");
+    if (m->pins) return fail(DSX_ERR_BUSY, "the model is recorded in a batch; destroy the batch first");
     (void)hipStreamSynchronize(m->last_stream);
     free_model(m);
     delete m;

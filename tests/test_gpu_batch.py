@@ -1,0 +1,115 @@
+"""GPU tests of batched execution (one hipGraph over several models) and the
+autotuner: a batch must reproduce, bit for bit, what each model computes alone,
+and match the FP64 oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import oracle as O
+from tests.helpers import rel_l2, to_dsx
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def say(msg):
+    print(f"[gpu case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def small_ensemble():
+    # uneven sizes, both disorder types, several configurations each
+    ms = [synth.displacive(workload=40, model=0, n=8, M=3, order=6, hmax=2, n_sites=3),
+          synth.compositional(workload=40, model=1, n=10, M=4, hmax=2, closed=True,
+                              frac=synth.FCC_BASIS[:2], b=synth.FCC_B[:2]),
+          synth.displacive(workload=40, model=2, n=12, M=2, order=4, hmax=1, n_sites=1),
+          synth.random_model(41, n=(6, 5, 7), S=2, M=2, order=3)]
+    ms[3].g0, ms[3].count = (-6, -5, -7), (13, 11, 15)
+    return ms
+
+
+@pytest.mark.parametrize("lm", [0, 2])
+def test_batch_equals_individual_and_oracle(lm):
+    import torch
+    import paper_1809_07088_amd as dsx
+    models = small_ensemble()
+    say(f"batch of {len(models)} models, lanczos_m={lm}")
+    hs = [to_dsx(m) for m in models]
+    outs = [torch.full(tuple(m.count), -1.0, device="cuda") for m in models]
+    batch = dsx.Batch(hs, outs, lanczos_m=lm)
+    batch.run()
+    torch.cuda.synchronize()
+    got = [o.cpu().numpy() for o in outs]
+    for m, h, g in zip(models, hs, got):
+        alone = torch.empty(tuple(m.count), device="cuda")
+        if lm:
+            h.noise_filter(lm, 1, alone)
+        else:
+            h.compute_intensity(alone)
+        torch.cuda.synchronize()
+        assert np.array_equal(alone.cpu().numpy(), g)
+        ref = O.filtered_intensity(m, lm, 1) if lm else O.intensity(m).reshape(m.count)
+        assert rel_l2(g, ref) <= TOL
+    # replay after new sites: the graph recomputes the spectra
+    m0, h0 = models[0], hs[0]
+    new = synth.displacive(workload=40, model=9, n=8, M=3, order=6, hmax=2, n_sites=3)
+    for c in range(m0.n_configs):
+        h0.set_sites(c, None, torch.from_numpy(new.disp[c]).cuda())
+    batch.run()
+    torch.cuda.synchronize()
+    ref = O.filtered_intensity(new, lm, 1) if lm else O.intensity(new).reshape(new.count)
+    assert rel_l2(outs[0].cpu().numpy(), ref) <= TOL
+    # the batch holds its models' recorded buffers
+    with pytest.raises(dsx.DsxError) as e:
+        h0.set_grid(m0.g0, m0.count)
+    assert e.value.status == dsx.ERR_BUSY
+    with pytest.raises(dsx.DsxError) as e:
+        dsx.destroy_model(h0.handle)
+    assert e.value.status == dsx.ERR_BUSY
+    batch.close()
+    h0.set_grid(m0.g0, m0.count)
+    for h in hs:
+        h.close()
+
+
+def test_autotune_cache_is_deterministic(tmp_path, monkeypatch):
+    import torch
+    import paper_1809_07088_amd as dsx
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("DSX_TUNE_CACHE", str(cache))
+    m = synth.displacive(workload=42, n=8, M=1, order=5, hmax=2)
+    say("autotune with a cache file")
+    h = to_dsx(m)
+    h.autotune(2)
+    lines = cache.read_text().strip().splitlines()
+    assert len(lines) == 1 and "\t" in lines[0]
+    h2 = to_dsx(m)
+    h2.autotune(2)                        # read back, no second entry
+    assert cache.read_text().strip().splitlines() == lines
+    a = torch.empty(tuple(m.count), device="cuda")
+    b = torch.empty(tuple(m.count), device="cuda")
+    h.compute_intensity(a)
+    h2.compute_intensity(b)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert rel_l2(a.cpu().numpy(), O.intensity(m).reshape(m.count)) <= TOL
+    h.close()
+    h2.close()
+
+
+def test_batch_rejects_bad_arguments():
+    import torch
+    import paper_1809_07088_amd as dsx
+    m = synth.random_model(43, n=(4, 4, 4), S=1, M=1, order=1)
+    say("batch argument errors")
+    h = to_dsx(m)
+    out = torch.empty(tuple(m.count), device="cuda")
+    with pytest.raises(dsx.DsxError) as e:
+        dsx.Batch([h, h], [out, out])
+    assert e.value.status == dsx.ERR_ARG
+    with pytest.raises(dsx.DsxError) as e:
+        dsx.Batch([h], [out], lanczos_m=1)
+    assert e.value.status == dsx.ERR_ARG
+    h.close()
