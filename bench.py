@@ -206,6 +206,131 @@ def bench_ensemble(dsx, torch, dev, steps, warmup, lm=2):
             "batched_equals_plain": bool(same)}
 
 
+def serving_pool(n_models=32, variants=2):
+    """Resident models of the serving workload and, per model, device-ready site variants."""
+    import synth
+    pool = [synth.serving_request_model(workload=5, model=i) for i in range(n_models)]
+    sites = []
+    for i, m in enumerate(pool):
+        vs = [(None if m.occ is None else m.occ[0], None if m.disp is None else m.disp[0],
+               None if m.spin is None else m.spin[0])]
+        r = np.random.default_rng([5, i, 40_000])
+        for _ in range(variants - 1):
+            S, nn = m.n_sites, tuple(m.n)
+            if m.occ is not None:
+                vs.append(((r.random((S,) + nn) < 0.5).astype(np.float32), None, None))
+            elif m.disp is not None:
+                vs.append((None, synth.correlated_displacements(r, 1, S, nn)[0], None))
+            else:
+                v = r.normal(size=(S,) + nn + (3,))
+                vs.append((None, None, (v / np.linalg.norm(v, axis=-1, keepdims=True)).astype(np.float32)))
+        sites.append(vs)
+    return pool, sites
+
+
+def bench_serving(dsx, torch, dev, seconds, slots=4):
+    """Open-loop Poisson requests (200/s) over 32 resident models of the serving workload
+    (edge 8..64, 1-16 random sites, compositional / displacive order 6 / magnetic,
+    |h|,|k|,|l| <= 2): the server (continuous batching over `slots` streams, arena
+    admission) against the plain path serving the same trace first come first served
+    with one synchronous call at a time.  A burst of every request at once gives the
+    saturated throughput of both."""
+    import synth
+    pool, sites = serving_pool()
+    arrivals = synth.poisson_arrivals(rate=200.0, duration=seconds)
+    pick = np.random.default_rng([5, 0, 50_000])
+    reqs = [(int(pick.integers(0, len(pool))), int(pick.integers(0, 2))) for _ in arrivals]
+    dsites = [[tuple(None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in v)
+               for v in vs] for vs in sites]
+    outs = [torch.empty(tuple(m.count), dtype=torch.float32, device=dev) for m in pool]
+    vox = [int(np.prod(m.count)) for m in pool]
+
+    def desc(m):
+        return dict(cell=m.cell, n=m.n, frac=m.frac, b=m.b, kind=m.kind,
+                    taylor_order=m.order if m.kind == 0 else 0, n_configs=1,
+                    has_occ=m.occ is not None, ff=m.ff)
+
+    # ---- server
+    srv = dsx.Server(slots=slots, queue_capacity=4096, arena_bytes=24 << 30)
+    hs = []
+    for m, v in zip(pool, dsites):
+        h = srv.add_model(**desc(m))
+        h.set_grid(m.g0, m.count)
+        h.set_sites(0, *v[0])
+        hs.append(h)
+    for i in range(len(pool)):          # warm: tables, first launches
+        srv.wait(srv.submit(hs[i], outs[i], 0, *dsites[i][0]))
+    srv.stats(reset=True)
+    lag = 0.0
+    t0 = time.perf_counter()
+    tickets = []
+    for ta, (i, v) in zip(arrivals, reqs):
+        while True:
+            dt = t0 + ta - time.perf_counter()
+            if dt <= 0:
+                break
+            time.sleep(dt if dt > 2e-3 else 0)
+        lag = max(lag, time.perf_counter() - (t0 + ta))
+        tickets.append(srv.submit(hs[i], outs[i], 0, *dsites[i][v]))
+    for t in tickets:
+        srv.wait(t)
+    open_srv = srv.stats(reset=True)
+    tb = time.perf_counter()
+    tickets = [srv.submit(hs[i], outs[i], 0, *dsites[i][v]) for (i, v) in reqs]
+    for t in tickets:
+        srv.wait(t)
+    burst_srv = time.perf_counter() - tb
+    burst_stats = srv.stats(reset=True)
+    srv.close()
+
+    # ---- plain path: one synchronous call at a time, same trace
+    plain = []
+    for m, v in zip(pool, dsites):
+        h = dsx.Model(**desc(m))
+        h.set_grid(m.g0, m.count)
+        h.set_sites(0, *v[0])
+        h.compute_intensity(outs[len(plain)])
+        plain.append(h)
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for ta, (i, v) in zip(arrivals, reqs):
+        while time.perf_counter() < t0 + ta:
+            dt = t0 + ta - time.perf_counter()
+            time.sleep(dt if dt > 2e-3 else 0)
+        plain[i].set_sites(0, *dsites[i][v])
+        plain[i].compute_intensity(outs[i])
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - (t0 + ta)) * 1e3)
+    span_plain = time.perf_counter() - t0
+    tb = time.perf_counter()
+    for (i, v) in reqs:
+        plain[i].set_sites(0, *dsites[i][v])
+        plain[i].compute_intensity(outs[i])
+    torch.cuda.synchronize()
+    burst_plain = time.perf_counter() - tb
+    for h in plain:
+        h.close()
+    total_vox = sum(vox[i] for (i, _) in reqs)
+    lat = np.sort(np.array(lat))
+    pct = lambda p: float(lat[max(0, int(np.ceil(p * len(lat))) - 1)])
+    return {"workload": f"Poisson 200 req/s for {seconds:g} s ({len(reqs)} requests) over 32 resident "
+                        "models: edge U{8..64}, 1-16 sites, compositional / displacive (order 6) / "
+                        "magnetic, |h|,|k|,|l|<=2, new sites per request",
+            "server": {"slots": slots, "voxels_per_s": round(open_srv["voxels"] / max(open_srv["span_s"], 1e-9), 1),
+                       "p50_ms": round(open_srv["p50_ms"], 3), "p99_ms": round(open_srv["p99_ms"], 3),
+                       "max_ms": round(open_srv["max_ms"], 3), "completed": open_srv["completed"],
+                       "peak_in_flight": open_srv["peak_in_flight"],
+                       "arena_peak_GB": round(open_srv["arena_peak_bytes"] / 1e9, 3),
+                       "max_submit_lag_ms": round(lag * 1e3, 3),
+                       "saturated_voxels_per_s": round(total_vox / burst_srv, 1),
+                       "saturated_p99_ms": round(burst_stats["p99_ms"], 3)},
+            "plain": {"voxels_per_s": round(total_vox / span_plain, 1), "p50_ms": round(pct(0.5), 3),
+                      "p99_ms": round(pct(0.99), 3), "max_ms": round(float(lat[-1]), 3),
+                      "saturated_voxels_per_s": round(total_vox / burst_plain, 1)},
+            "offered_voxels_per_s": round(total_vox / seconds, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -224,6 +349,9 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble comparison")
     ap.add_argument("--ensemble-only", action="store_true",
                     help="time only the batched ensemble (for kernel traces of the graph path)")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="length of the Poisson request trace of the serving comparison (0: skip)")
+    ap.add_argument("--serving-only", action="store_true", help="run only the serving comparison")
     args = ap.parse_args()
     if args.summarize_pmc:
         print(json.dumps(summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], TRAFFIC_MD,
@@ -243,6 +371,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.ensemble_only:
         print(json.dumps({"ensemble": bench_ensemble(dsx, torch, dev, args.steps, args.warmup)}))
+        return
+    if args.serving_only:
+        print(json.dumps({"serving": bench_serving(dsx, torch, dev, args.serve_seconds)}))
         return
     N, lm = args.order, args.lanczos_m
     model = synth.displacive(n=32, M=1, order=N, hmax=8)
@@ -369,6 +500,7 @@ def main():
     h.close()
 
     ensemble = None if args.no_ensemble else bench_ensemble(dsx, torch, dev, max(3, args.steps // 4), 2)
+    serving = bench_serving(dsx, torch, dev, args.serve_seconds) if args.serve_seconds > 0 else None
 
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "voxels/s", "n_gpus": 1,
@@ -389,6 +521,8 @@ def main():
         line["compute_intensity_voxels_per_s_by_order"] = sweep
     if ensemble is not None:
         line["ensemble"] = ensemble
+    if serving is not None:
+        line["serving"] = serving
     print(json.dumps(line))
 
 

@@ -192,6 +192,85 @@ dsx_status dsx_batch_destroy(dsx_batch b);
  */
 dsx_status dsx_autotune(dsx_model m, int32_t lanczos_m, void* hip_stream);
 
+/*
+ * Serving (an execution pattern; the arithmetic is that of dsx_compute_intensity /
+ * dsx_noise_filter).  Refinement recomputes the intensity of a model again and
+ * again as its variables change (Sec. I; Sec. VI), so a server keeps models
+ * resident on the device -- plan, site variables, lattice sums and phase tables --
+ * and runs requests with continuous batching: up to `slots` requests are on the
+ * device at once, each on its own stream, and a request that arrives while others
+ * run starts as soon as a slot and workspace are free.  A request's workspace --
+ * the model's spectra, its partial lattice sums and, when filtered, the grown box
+ * -- is taken from one device arena allocated at dsx_server_create; a request is
+ * admitted only when its workspace fits in the free part of the arena (admission
+ * by HBM footprint), and requests of one model run one after another in
+ * submission order.  Waiting requests are served first come first served, except
+ * that a request that fits may start before an earlier one that does not yet fit
+ * (at most 64 times for one waiting request).
+ *   slots           1..16 requests on the device at once
+ *   queue_capacity  >= 1 requests waiting for admission; beyond it submit returns
+ *                   DSX_ERR_BUSY
+ *   arena_bytes     device workspace shared by requests on the device
+ */
+typedef struct dsx_server_s* dsx_server;
+
+typedef struct {
+    int32_t slots;
+    int32_t queue_capacity;
+    int64_t arena_bytes;
+} dsx_server_config;
+
+/*
+ * One request: replace the site variables of `config` (when config >= 0; the
+ * pointers follow dsx_set_sites and must stay valid until the request finishes),
+ * then compute I(G) on the model's grid (lanczos_m = 0) or the filtered intensity
+ * (lanczos_m >= 2, oversample s >= 1) into the device array `out`
+ * ([count0][count1][count2], or s times that per axis), owned by the caller.
+ */
+typedef struct {
+    dsx_model model;
+    int32_t config;
+    const float* occ;
+    const float* disp;
+    const float* spin;
+    int32_t where;
+    int32_t lanczos_m;
+    int32_t oversample;
+    float* out;
+} dsx_request;
+
+/* Latencies are completion minus submission, over requests finished since the
+ * last reset; voxels counts their output voxels. */
+typedef struct {
+    int64_t submitted, completed, failed, rejected;
+    int64_t voxels;
+    double p50_ms, p99_ms, mean_ms, max_ms;
+    double span_s;             /* first submission to last completion */
+    int64_t arena_bytes, arena_peak_bytes;
+    int32_t slots, peak_in_flight;
+} dsx_server_stats;
+
+dsx_status dsx_server_create(const dsx_server_config* c, dsx_server* out);
+
+/* A resident model owned by the server (dsx_create_model otherwise): set its grid
+ * and sites with dsx_set_grid / dsx_set_sites (DSX_ERR_BUSY while it has requests
+ * queued); direct compute calls on it return DSX_ERR_STATE. */
+dsx_status dsx_server_add_model(dsx_server s, const dsx_model_desc* d, dsx_model* out);
+
+/* Queue a request; *ticket identifies it.  DSX_ERR_BUSY: queue full.
+ * DSX_ERR_NOMEM: the request's workspace exceeds the whole arena. */
+dsx_status dsx_server_submit(dsx_server s, const dsx_request* r, int64_t* ticket);
+
+/* Wait up to timeout_ms (< 0: no limit) for a request.  Returns DSX_OK once it
+ * has finished, with its own status in *result (the ticket is then retired), or
+ * DSX_ERR_BUSY if it is still queued or running.  Any thread may wait. */
+dsx_status dsx_server_wait(dsx_server s, int64_t ticket, int32_t timeout_ms, dsx_status* result);
+
+dsx_status dsx_server_stats_read(dsx_server s, int32_t reset, dsx_server_stats* out);
+
+/* Finish every queued request, then release the server and its models. */
+dsx_status dsx_server_destroy(dsx_server s);
+
 /* Release a model and all its device memory (waits for its pending work).
  * DSX_ERR_BUSY while a batch still holds the model. */
 dsx_status dsx_destroy_model(dsx_model m);

@@ -50,7 +50,28 @@ class KernelStat(ctypes.Structure):
 EXPORTS = ("dsx_plan_query", "dsx_create_model", "dsx_set_sites", "dsx_set_grid",
            "dsx_compute_intensity", "dsx_noise_filter", "dsx_destroy_model", "dsx_last_error",
            "dsx_version", "dsx_profile_enable", "dsx_profile_read", "dsx_profile_reset",
-           "dsx_batch_create", "dsx_batch_run", "dsx_batch_destroy", "dsx_autotune")
+           "dsx_batch_create", "dsx_batch_run", "dsx_batch_destroy", "dsx_autotune",
+           "dsx_server_create", "dsx_server_add_model", "dsx_server_submit", "dsx_server_wait",
+           "dsx_server_stats_read", "dsx_server_destroy")
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("queue_capacity", ctypes.c_int32), ("arena_bytes", ctypes.c_int64)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_void_p), ("config", ctypes.c_int32), ("occ", ctypes.c_void_p),
+                ("disp", ctypes.c_void_p), ("spin", ctypes.c_void_p), ("where", ctypes.c_int32),
+                ("lanczos_m", ctypes.c_int32), ("oversample", ctypes.c_int32), ("out", ctypes.c_void_p)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("rejected", ctypes.c_int64), ("voxels", ctypes.c_int64), ("p50_ms", ctypes.c_double),
+                ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
+                ("span_s", ctypes.c_double), ("arena_bytes", ctypes.c_int64),
+                ("arena_peak_bytes", ctypes.c_int64), ("slots", ctypes.c_int32),
+                ("peak_in_flight", ctypes.c_int32)]
+
 
 _lib = None
 
@@ -83,7 +104,15 @@ def lib():
         L.dsx_batch_run.argtypes = [P, P]
         L.dsx_batch_destroy.argtypes = [P]
         L.dsx_autotune.argtypes = [P, i32, P]
-        for f in ("dsx_batch_create", "dsx_batch_run", "dsx_batch_destroy", "dsx_autotune"):
+        L.dsx_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(P)]
+        L.dsx_server_add_model.argtypes = [P, ctypes.POINTER(ModelDesc), ctypes.POINTER(P)]
+        L.dsx_server_submit.argtypes = [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_int64)]
+        L.dsx_server_wait.argtypes = [P, ctypes.c_int64, i32, ctypes.POINTER(i32)]
+        L.dsx_server_stats_read.argtypes = [P, i32, ctypes.POINTER(ServerStats)]
+        L.dsx_server_destroy.argtypes = [P]
+        for f in ("dsx_batch_create", "dsx_batch_run", "dsx_batch_destroy", "dsx_autotune",
+                  "dsx_server_create", "dsx_server_add_model", "dsx_server_submit", "dsx_server_wait",
+                  "dsx_server_stats_read", "dsx_server_destroy"):
             getattr(L, f).restype = i32
         for f in ("dsx_plan_query", "dsx_create_model", "dsx_set_sites", "dsx_set_grid",
                   "dsx_compute_intensity", "dsx_noise_filter", "dsx_destroy_model"):
@@ -273,6 +302,80 @@ class Model:
         if self.handle:
             destroy_model(self.handle)
             self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class ServedModel(Model):
+    """A resident model owned by a Server (released with it)."""
+
+    def __init__(self, server, **kw):
+        self.desc_kw = dict(kw)
+        d, keep = make_desc(**kw)
+        h = ctypes.c_void_p()
+        _check(lib().dsx_server_add_model(server.handle, ctypes.byref(d), ctypes.byref(h)))
+        self.handle = h.value
+        self.server = server
+
+    def close(self):
+        self.handle = None
+
+
+class Server:
+    """Continuous-batching request server over resident models (dsx_server_*)."""
+
+    def __init__(self, slots=4, queue_capacity=1024, arena_bytes=8 << 30):
+        c = ServerConfig(int(slots), int(queue_capacity), int(arena_bytes))
+        h = ctypes.c_void_p()
+        _check(lib().dsx_server_create(ctypes.byref(c), ctypes.byref(h)))
+        self.handle = h.value
+        self._keep = {}
+
+    def add_model(self, **kw) -> ServedModel:
+        return ServedModel(self, **kw)
+
+    def submit(self, model, out, config=-1, occ=None, disp=None, spin=None, lanczos_m=0, oversample=1):
+        """Queue a request; returns its ticket (DsxError ERR_BUSY when the queue is full)."""
+        ptrs = [_ptr_where(a) for a in (occ, disp, spin)]
+        wheres = {w for (_, w, _) in ptrs if w is not None}
+        if len(wheres) > 1:
+            raise ValueError("occ, disp and spin must all be host or all device arrays")
+        p_out, w_out, _ = _ptr_where(out)
+        if w_out != DEVICE:
+            raise ValueError("out must be a device tensor")
+        r = Request(model.handle, int(config), ptrs[0][0], ptrs[1][0], ptrs[2][0],
+                    wheres.pop() if wheres else DEVICE, int(lanczos_m), int(oversample), p_out)
+        t = ctypes.c_int64()
+        _check(lib().dsx_server_submit(self.handle, ctypes.byref(r), ctypes.byref(t)))
+        self._keep[t.value] = (out, [k for (_, _, k) in ptrs])
+        return t.value
+
+    def wait(self, ticket, timeout_ms=-1):
+        """True once the request finished (raises DsxError if it failed); False on timeout."""
+        res = ctypes.c_int32()
+        st = lib().dsx_server_wait(self.handle, int(ticket), int(timeout_ms), ctypes.byref(res))
+        if st == ERR_BUSY:
+            return False
+        _check(st)
+        self._keep.pop(ticket, None)
+        if res.value != OK:
+            raise DsxError(res.value, last_error())
+        return True
+
+    def stats(self, reset=False) -> dict:
+        z = ServerStats()
+        _check(lib().dsx_server_stats_read(self.handle, 1 if reset else 0, ctypes.byref(z)))
+        return {f: getattr(z, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if self.handle:
+            _check(lib().dsx_server_destroy(self.handle))
+            self.handle = None
+            self._keep.clear()
 
     def __del__(self):
         try:

@@ -9,7 +9,11 @@
 //   sums -> plane FFTs (generation + axes 3, 2) -> axis-1 FFT    (when the sites changed)
 //   recombination over the box -> float64 Bragg points -> [Lanczos filter]
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
+#include <deque>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -17,7 +21,9 @@
 #include <sstream>
 #include <map>
 #include <mutex>
+#include <set>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "dsx.h"
@@ -215,6 +221,11 @@ struct dsx_model_s {
     hipStream_t last_stream = nullptr;   // stream of the last enqueued work
     hipEvent_t order_ev = nullptr;       // orders work across the caller's streams
     int pins = 0;                        // batches that recorded this model's buffers
+    // served models: spectra, partial sums and the grown box live in the server's
+    // arena for the duration of one request; everything else stays resident
+    dsx_server_s* server = nullptr;
+    std::atomic<int> queued{0};          // requests submitted and not yet finished
+    size_t spectrum_bytes = 0, partial_bytes = 0;
 };
 
 namespace {
@@ -706,7 +717,12 @@ dsx_status dsx_plan_query(const dsx_model_desc* d, dsx_plan_info* info)
     return DSX_OK;
 }
 
-dsx_status dsx_create_model(const dsx_model_desc* d, dsx_model* out)
+}  // extern "C"
+
+namespace {
+
+// Builds a model; `transient` leaves the spectra and partial-sum buffers to a server.
+dsx_status create_model_impl(const dsx_model_desc* d, bool transient, dsx_model* out)
 {
     dsx_status s = validate_desc(d);
     if (s != DSX_OK) return s;
@@ -763,9 +779,11 @@ dsx_status dsx_create_model(const dsx_model_desc* d, dsx_model* out)
     if (m->has_occ && e == hipSuccess) e = alloc((void**)&m->d_occ, M * S * nc * sizeof(float));
     if ((m->kind == DSX_MAGNETIC || m->order > 0) && e == hipSuccess)
         e = alloc((void**)&m->d_vec, M * S * nc * 3 * sizeof(float));
-    if (e == hipSuccess) e = alloc((void**)&m->d_partial, M * S * m->sum_chunks * m->T * sizeof(double));
+    m->spectrum_bytes = (size_t)z.spectrum_bytes;
+    m->partial_bytes = M * S * m->sum_chunks * m->T * sizeof(double);
+    if (e == hipSuccess && !transient) e = alloc((void**)&m->d_partial, m->partial_bytes);
     if (e == hipSuccess) e = alloc((void**)&m->d_sums, M * S * m->T * sizeof(double));
-    if (e == hipSuccess) e = alloc((void**)&m->d_X, (size_t)z.spectrum_bytes);
+    if (e == hipSuccess && !transient) e = alloc((void**)&m->d_X, (size_t)z.spectrum_bytes);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&m->order_ev, hipEventDisableTiming);
     if (e == hipSuccess) {
         std::vector<double> site((size_t)m->S * 11, 0.0);
@@ -796,6 +814,24 @@ dsx_status dsx_create_model(const dsx_model_desc* d, dsx_model* out)
     return DSX_OK;
 }
 
+// Direct compute calls own their buffers; a served model computes only through its server.
+dsx_status check_direct(dsx_model m)
+{
+    dsx_status s = check_model(m);
+    if (s != DSX_OK) return s;
+    if (m->server) return fail(DSX_ERR_STATE, "the model belongs to a server: submit requests to it");
+    return DSX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dsx_status dsx_create_model(const dsx_model_desc* d, dsx_model* out)
+{
+    return create_model_impl(d, false, out);
+}
+
 dsx_status dsx_set_sites(dsx_model m, int32_t config, const float* occ, const float* disp,
                          const float* spin, int32_t where)
 {
@@ -808,6 +844,7 @@ dsx_status dsx_set_sites(dsx_model m, int32_t config, const float* occ, const fl
     const bool need_vec = m->kind == DSX_MAGNETIC || m->order > 0;
     if (need_vec && !vec)
         return fail(DSX_ERR_ARG, m->kind == DSX_MAGNETIC ? "spin is required" : "disp is required (taylor_order > 0)");
+    if (m->queued.load() > 0) return fail(DSX_ERR_BUSY, "the model has requests queued at its server");
     HIPCHK(m, hipStreamSynchronize(m->last_stream));   // no pending work still reads the inputs
     const hipMemcpyKind kind = where == DSX_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
     const size_t per = (size_t)m->S * m->ncell;
@@ -825,6 +862,7 @@ dsx_status dsx_set_grid(dsx_model m, const int32_t g0[3], const int32_t count[3]
     if (s != DSX_OK) return s;
     if (!g0 || !count) return fail(DSX_ERR_ARG, "g0 and count are required");
     if (m->pins) return fail(DSX_ERR_BUSY, "the model is recorded in a batch; destroy the batch first");
+    if (m->queued.load() > 0) return fail(DSX_ERR_BUSY, "the model has requests queued at its server");
     Box bx;
     long long vox = 1;
     for (int a = 0; a < 3; ++a) {
@@ -842,7 +880,7 @@ dsx_status dsx_set_grid(dsx_model m, const int32_t g0[3], const int32_t count[3]
 
 dsx_status dsx_compute_intensity(dsx_model m, float* out, int32_t where, void* hip_stream)
 {
-    dsx_status s = check_model(m);
+    dsx_status s = check_direct(m);
     if (s != DSX_OK) return s;
     if (!out) return fail(DSX_ERR_ARG, "out is NULL");
     if (where != DSX_HOST && where != DSX_DEVICE) return fail(DSX_ERR_ARG, "bad 'where'");
@@ -969,7 +1007,7 @@ extern "C" {
 dsx_status dsx_noise_filter(dsx_model m, int32_t lanczos_m, int32_t oversample, float* out,
                             int32_t where, void* hip_stream)
 {
-    dsx_status s = check_model(m);
+    dsx_status s = check_direct(m);
     if (s != DSX_OK) return s;
     if (!out) return fail(DSX_ERR_ARG, "out is NULL");
     if (where != DSX_HOST && where != DSX_DEVICE) return fail(DSX_ERR_ARG, "bad 'where'");
@@ -1061,7 +1099,7 @@ extern "C" {
 
 dsx_status dsx_autotune(dsx_model m, int32_t lanczos_m, void* hip_stream)
 {
-    dsx_status s = check_model(m);
+    dsx_status s = check_direct(m);
     if (s != DSX_OK) return s;
     if ((s = ready(m)) != DSX_OK) return s;
     const bool filt = lanczos_m >= 2;
@@ -1160,7 +1198,7 @@ dsx_status dsx_batch_create(const dsx_model* models, int32_t n, int32_t lanczos_
     dsx_status s;
     if (lanczos_m != 0 && (s = check_filter_args(lanczos_m, oversample)) != DSX_OK) return s;
     for (int i = 0; i < n; ++i) {
-        if ((s = check_model(models[i])) != DSX_OK) return s;
+        if ((s = check_direct(models[i])) != DSX_OK) return s;
         if ((s = ready(models[i])) != DSX_OK) return s;
         if (!outs[i]) return fail(DSX_ERR_ARG, "outs[" + std::to_string(i) + "] is NULL");
         for (int j = 0; j < i; ++j)
@@ -1258,10 +1296,427 @@ dsx_status dsx_batch_destroy(dsx_batch b)
 dsx_status dsx_destroy_model(dsx_model m)
 {
     if (!m) return fail(DSX_ERR_ARG, "model is NULL");
+    if (m->server) return fail(DSX_ERR_ARG, "the model belongs to a server: dsx_server_destroy releases it");
     if (m->pins) return fail(DSX_ERR_BUSY, "the model is recorded in a batch; destroy the batch first");
     (void)hipStreamSynchronize(m->last_stream);
     free_model(m);
     delete m;
+    return DSX_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------- serving
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+// First-fit sub-allocator over the server's device arena, in 256-byte granules.
+class Arena {
+public:
+    static size_t round(size_t n) { return (n + 255) & ~size_t(255); }
+    void init(size_t n) { size_ = n; used_ = peak_ = 0; free_.clear(); free_[0] = n; }
+    bool alloc(size_t n, size_t* off)
+    {
+        n = round(n);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < n) continue;
+            *off = it->first;
+            const size_t rest = it->second - n, next = it->first + n;
+            free_.erase(it);
+            if (rest) free_[next] = rest;
+            used_ += n;
+            peak_ = std::max(peak_, used_);
+            return true;
+        }
+        return false;
+    }
+    void release(size_t off, size_t n)
+    {
+        n = round(n);
+        used_ -= n;
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t size() const { return size_; }
+    size_t peak() const { return peak_; }
+    void reset_peak() { peak_ = used_; }
+
+private:
+    size_t size_ = 0, used_ = 0, peak_ = 0;
+    std::map<size_t, size_t> free_;   // offset -> length of each free range
+};
+
+struct Request {
+    int64_t ticket = 0;
+    dsx_request r{};
+    size_t ws = 0, off = 0;     // workspace bytes and its arena offset
+    size_t x_bytes = 0;         // spectra part of the workspace
+    int64_t voxels = 0;
+    Clock::time_point t_submit;
+    int bypassed = 0;           // later requests admitted before this one
+};
+
+struct Finished {
+    dsx_status status;
+    std::string msg;
+};
+
+constexpr int kMaxBypass = 64;
+
+}  // namespace
+
+struct dsx_server_s {
+    int device = 0;
+    int nslots = 0, capacity = 0;
+    char* arena_mem = nullptr;
+    Arena arena;
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> events;
+    std::vector<char> busy;
+    std::vector<Request> running;      // per slot
+    std::deque<Request> queue;
+    std::vector<dsx_model> models;
+    std::set<dsx_model> active;        // models with a request on the device
+    std::map<int64_t, Finished> finished;
+    std::set<int64_t> pending;         // queued or running tickets
+    int64_t next_ticket = 1;
+    bool stop = false;
+    std::mutex mu;
+    std::condition_variable wake;      // the dispatcher: new request or stop
+    std::condition_variable done;      // waiters: a request finished
+    std::thread worker;
+    // statistics since the last reset
+    int64_t submitted = 0, completed = 0, failed = 0, rejected = 0, voxels = 0;
+    std::vector<double> lat_ms;
+    bool have_first = false;
+    Clock::time_point first_submit, last_done;
+    int in_flight = 0, peak_in_flight = 0;
+};
+
+namespace {
+
+size_t box_voxels(const Box& b) { return (size_t)b.cnt[0] * b.cnt[1] * b.cnt[2]; }
+
+// Workspace of one request: spectra, partial lattice sums and, filtered, the grown box.
+size_t request_workspace(dsx_model m, int lm, size_t* x_bytes)
+{
+    *x_bytes = Arena::round(m->spectrum_bytes);
+    size_t ws = *x_bytes + Arena::round(m->partial_bytes);
+    if (lm >= 2) ws += Arena::round(box_voxels(grown_box(m->box, lm)) * sizeof(float));
+    return ws;
+}
+
+// Enqueues an admitted request on stream st and records ev after it (dispatcher thread).
+dsx_status launch_request(dsx_server s, const Request& q, hipStream_t st, hipEvent_t ev)
+{
+    dsx_model m = q.r.model;
+    dsx_status rs = check_model(m);
+    if (rs != DSX_OK) return rs;
+    const int lm = q.r.lanczos_m, sv = lm >= 2 ? q.r.oversample : 1;
+    char* base = s->arena_mem + q.off;
+    m->d_X = reinterpret_cast<float2*>(base);
+    m->d_partial = reinterpret_cast<double*>(base + q.x_bytes);
+    if (lm >= 2) {
+        m->d_ext = reinterpret_cast<float*>(base + q.x_bytes + Arena::round(m->partial_bytes));
+        m->ext_cap = box_voxels(grown_box(m->box, lm));
+    }
+    rs = follow(m, st);
+    if (rs == DSX_OK && q.r.config >= 0) {
+        const hipMemcpyKind kind = q.r.where == DSX_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+        const size_t per = (size_t)m->S * m->ncell;
+        const float* vec = m->kind == DSX_MAGNETIC ? q.r.spin : q.r.disp;
+        hipError_t e = hipSuccess;
+        if (m->has_occ) e = hipMemcpyAsync(m->d_occ + per * q.r.config, q.r.occ, per * sizeof(float), kind, st);
+        if (e == hipSuccess && vec)
+            e = hipMemcpyAsync(m->d_vec + 3 * per * q.r.config, vec, 3 * per * sizeof(float), kind, st);
+        if (e != hipSuccess) { m->failed = true; rs = fail(DSX_ERR_DEVICE, std::string("site upload: ") + hipGetErrorString(e)); }
+        else m->set[q.r.config] = 1;
+    }
+    if (rs == DSX_OK) rs = ready(m);
+    if (rs == DSX_OK) rs = lm >= 2 ? prepare_filter(m, lm, sv) : prepare_intensity(m);
+    if (rs == DSX_OK)
+        rs = lm >= 2 ? enqueue_filter(m, lm, sv, q.r.out, st, true) : enqueue_intensity(m, q.r.out, st, true);
+    // the arena range belongs to the request, not the model
+    m->d_X = nullptr; m->d_partial = nullptr; m->d_ext = nullptr; m->ext_cap = 0;
+    m->dirty = true;
+    if (rs == DSX_OK) {
+        const hipError_t e = hipEventRecord(ev, st);
+        if (e != hipSuccess) { m->failed = true; rs = fail(DSX_ERR_DEVICE, hipGetErrorString(e)); }
+    }
+    if (rs != DSX_OK) (void)hipStreamSynchronize(st);   // nothing may still use the range
+    return rs;
+}
+
+// Bookkeeping of a request that left the device (lock held).
+void finish_request(dsx_server s, const Request& q, dsx_status st, const std::string& msg)
+{
+    s->arena.release(q.off, q.ws);
+    s->active.erase(q.r.model);
+    --q.r.model->queued;
+    s->pending.erase(q.ticket);
+    s->finished[q.ticket] = Finished{st, msg};
+    if (st == DSX_OK) {
+        const Clock::time_point now = Clock::now();
+        ++s->completed;
+        s->voxels += q.voxels;
+        s->lat_ms.push_back(std::chrono::duration<double, std::milli>(now - q.t_submit).count());
+        s->last_done = now;
+    } else {
+        ++s->failed;
+    }
+}
+
+void serve(dsx_server s)
+{
+    (void)hipSetDevice(s->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        bool changed = false;
+        for (int i = 0; i < s->nslots; ++i) {
+            if (!s->busy[i]) continue;
+            const hipError_t e = hipEventQuery(s->events[i]);
+            if (e == hipErrorNotReady) continue;
+            dsx_status st = DSX_OK;
+            std::string msg;
+            if (e != hipSuccess) {
+                st = DSX_ERR_DEVICE;
+                msg = hipGetErrorString(e);
+                s->running[i].r.model->failed = true;
+            }
+            finish_request(s, s->running[i], st, msg);
+            s->busy[i] = 0;
+            --s->in_flight;
+            changed = true;
+        }
+        // admission: first come first served among requests whose workspace fits and
+        // whose model is idle; a request that fits may pass one that does not yet
+        for (;;) {
+            int slot = -1;
+            for (int i = 0; i < s->nslots && slot < 0; ++i)
+                if (!s->busy[i]) slot = i;
+            if (slot < 0 || s->queue.empty()) break;
+            std::set<dsx_model> waiting;   // models with an earlier request still queued
+            auto pick = s->queue.end();
+            for (auto it = s->queue.begin(); it != s->queue.end(); ++it) {
+                if (it != s->queue.begin() && s->queue.front().bypassed >= kMaxBypass) break;
+                dsx_model m = it->r.model;
+                if (s->active.count(m) || waiting.count(m)) { waiting.insert(m); continue; }
+                size_t off = 0;
+                if (!s->arena.alloc(it->ws, &off)) { waiting.insert(m); continue; }
+                it->off = off;
+                pick = it;
+                break;
+            }
+            if (pick == s->queue.end()) break;
+            for (auto it = s->queue.begin(); it != pick; ++it) ++it->bypassed;
+            s->running[slot] = std::move(*pick);
+            s->queue.erase(pick);
+            s->busy[slot] = 1;
+            s->active.insert(s->running[slot].r.model);
+            s->peak_in_flight = std::max(s->peak_in_flight, ++s->in_flight);
+            lk.unlock();
+            const dsx_status st = launch_request(s, s->running[slot], s->streams[slot], s->events[slot]);
+            const std::string msg = st == DSX_OK ? std::string() : std::string(dsx_last_error());
+            lk.lock();
+            if (st != DSX_OK) {
+                finish_request(s, s->running[slot], st, msg);
+                s->busy[slot] = 0;
+                --s->in_flight;
+            }
+            changed = true;
+        }
+        if (changed) s->done.notify_all();
+        if (s->stop && s->queue.empty() && s->in_flight == 0) break;
+        if (s->in_flight == 0)
+            s->wake.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+        else
+            s->wake.wait_for(lk, std::chrono::microseconds(50));
+    }
+    s->done.notify_all();
+}
+
+void free_server(dsx_server s)
+{
+    for (dsx_model m : s->models) { free_model(m); delete m; }
+    for (auto e : s->events) if (e) (void)hipEventDestroy(e);
+    for (auto st : s->streams) if (st) (void)hipStreamDestroy(st);
+    dfree(s->arena_mem);
+}
+
+}  // namespace
+
+extern "C" {
+
+dsx_status dsx_server_create(const dsx_server_config* c, dsx_server* out)
+{
+    if (!c || !out) return fail(DSX_ERR_ARG, "config and out are required");
+    *out = nullptr;
+    if (c->slots < 1 || c->slots > 16) return fail(DSX_ERR_ARG, "slots must be in 1..16");
+    if (c->queue_capacity < 1) return fail(DSX_ERR_ARG, "queue_capacity must be >= 1");
+    if (c->arena_bytes < 1) return fail(DSX_ERR_ARG, "arena_bytes must be >= 1");
+    dsx_server s = new (std::nothrow) dsx_server_s();
+    if (!s) return fail(DSX_ERR_NOMEM, "host allocation failed");
+    auto bail = [&](dsx_status st) { free_server(s); delete s; return st; };
+    (void)hipGetDevice(&s->device);
+    s->nslots = c->slots;
+    s->capacity = c->queue_capacity;
+    const size_t bytes = Arena::round((size_t)c->arena_bytes);
+    hipError_t e = hipMalloc(&s->arena_mem, bytes);
+    if (e == hipErrorOutOfMemory) { (void)hipGetLastError(); return bail(fail(DSX_ERR_NOMEM, "out of device memory for the arena")); }
+    if (e != hipSuccess) return bail(fail(DSX_ERR_DEVICE, hipGetErrorString(e)));
+    s->arena.init(bytes);
+    s->streams.assign(s->nslots, nullptr);
+    s->events.assign(s->nslots, nullptr);
+    s->busy.assign(s->nslots, 0);
+    s->running.resize(s->nslots);
+    for (int i = 0; i < s->nslots; ++i) {
+        if ((e = hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&s->events[i], hipEventDisableTiming)) != hipSuccess)
+            return bail(fail(DSX_ERR_DEVICE, hipGetErrorString(e)));
+    }
+    try {
+        s->worker = std::thread(serve, s);
+    } catch (...) {
+        return bail(fail(DSX_ERR_NOMEM, "cannot start the dispatcher thread"));
+    }
+    *out = s;
+    return DSX_OK;
+}
+
+dsx_status dsx_server_add_model(dsx_server s, const dsx_model_desc* d, dsx_model* out)
+{
+    if (!s) return fail(DSX_ERR_ARG, "server is NULL");
+    dsx_status st = create_model_impl(d, true, out);
+    if (st != DSX_OK) return st;
+    (*out)->server = s;
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->models.push_back(*out);
+    return DSX_OK;
+}
+
+dsx_status dsx_server_submit(dsx_server s, const dsx_request* r, int64_t* ticket)
+{
+    if (!s || !r || !ticket) return fail(DSX_ERR_ARG, "server, request and ticket are required");
+    dsx_model m = r->model;
+    dsx_status st = check_model(m);
+    if (st != DSX_OK) return st;
+    if (m->server != s) return fail(DSX_ERR_ARG, "the model does not belong to this server");
+    if (!r->out) return fail(DSX_ERR_ARG, "out is NULL");
+    if (r->lanczos_m != 0 && (st = check_filter_args(r->lanczos_m, r->oversample)) != DSX_OK) return st;
+    if (!m->grid_set) return fail(DSX_ERR_STATE, "no output grid set");
+    if (r->config >= m->M || r->config < -1) return fail(DSX_ERR_ARG, "config out of range");
+    if (r->config >= 0) {
+        if (r->where != DSX_HOST && r->where != DSX_DEVICE) return fail(DSX_ERR_ARG, "bad 'where'");
+        if (m->has_occ && !r->occ) return fail(DSX_ERR_ARG, "occ is required (has_occ != 0)");
+        const bool need_vec = m->kind == DSX_MAGNETIC || m->order > 0;
+        if (need_vec && !(m->kind == DSX_MAGNETIC ? r->spin : r->disp))
+            return fail(DSX_ERR_ARG, m->kind == DSX_MAGNETIC ? "spin is required" : "disp is required");
+    }
+    Request q;
+    q.r = *r;
+    q.ws = request_workspace(m, r->lanczos_m, &q.x_bytes);
+    if (q.ws > s->arena.size())
+        return fail(DSX_ERR_NOMEM, "the request's workspace (" + std::to_string(q.ws) +
+                                   " bytes) exceeds the server's arena");
+    const int64_t sv = r->lanczos_m >= 2 ? r->oversample : 1;
+    q.voxels = sv * m->box.cnt[0] * sv * m->box.cnt[1] * sv * (int64_t)m->box.cnt[2];
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) return fail(DSX_ERR_STATE, "the server is shutting down");
+    if ((int)s->queue.size() >= s->capacity) {
+        ++s->rejected;
+        return fail(DSX_ERR_BUSY, "request queue full");
+    }
+    q.ticket = s->next_ticket++;
+    q.t_submit = Clock::now();
+    if (!s->have_first) { s->first_submit = q.t_submit; s->have_first = true; }
+    ++m->queued;
+    ++s->submitted;
+    s->pending.insert(q.ticket);
+    *ticket = q.ticket;
+    s->queue.push_back(std::move(q));
+    s->wake.notify_one();
+    return DSX_OK;
+}
+
+dsx_status dsx_server_wait(dsx_server s, int64_t ticket, int32_t timeout_ms, dsx_status* result)
+{
+    if (!s || !result) return fail(DSX_ERR_ARG, "server and result are required");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto ready_ = [&] { return s->finished.count(ticket) > 0 || !s->pending.count(ticket); };
+    if (timeout_ms < 0) s->done.wait(lk, ready_);
+    else s->done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready_);
+    auto it = s->finished.find(ticket);
+    if (it == s->finished.end()) {
+        if (!s->pending.count(ticket)) return fail(DSX_ERR_ARG, "unknown or already retired ticket");
+        return fail(DSX_ERR_BUSY, "the request has not finished");
+    }
+    *result = it->second.status;
+    g_err = it->second.msg;
+    s->finished.erase(it);
+    return DSX_OK;
+}
+
+dsx_status dsx_server_stats_read(dsx_server s, int32_t reset, dsx_server_stats* out)
+{
+    if (!s || !out) return fail(DSX_ERR_ARG, "server and out are required");
+    std::lock_guard<std::mutex> lk(s->mu);
+    dsx_server_stats z{};
+    z.submitted = s->submitted; z.completed = s->completed; z.failed = s->failed; z.rejected = s->rejected;
+    z.voxels = s->voxels;
+    std::vector<double> l = s->lat_ms;
+    if (!l.empty()) {
+        std::sort(l.begin(), l.end());
+        auto q = [&](double p) {   // nearest-rank percentile
+            size_t k = (size_t)std::ceil(p * l.size());
+            return l[std::min(l.size(), std::max<size_t>(k, 1)) - 1];
+        };
+        z.p50_ms = q(0.50);
+        z.p99_ms = q(0.99);
+        double t = 0;
+        for (double v : l) t += v;
+        z.mean_ms = t / l.size();
+        z.max_ms = l.back();
+        z.span_s = std::chrono::duration<double>(s->last_done - s->first_submit).count();
+    }
+    z.arena_bytes = (int64_t)s->arena.size();
+    z.arena_peak_bytes = (int64_t)s->arena.peak();
+    z.slots = s->nslots;
+    z.peak_in_flight = s->peak_in_flight;
+    *out = z;
+    if (reset) {
+        s->submitted = s->completed = s->failed = s->rejected = s->voxels = 0;
+        s->lat_ms.clear();
+        s->have_first = false;
+        s->peak_in_flight = s->in_flight;
+        s->arena.reset_peak();
+    }
+    return DSX_OK;
+}
+
+dsx_status dsx_server_destroy(dsx_server s)
+{
+    if (!s) return fail(DSX_ERR_ARG, "server is NULL");
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->wake.notify_all();
+    if (s->worker.joinable()) s->worker.join();
+    for (auto st : s->streams) if (st) (void)hipStreamSynchronize(st);
+    free_server(s);
+    delete s;
     return DSX_OK;
 }
 

@@ -85,3 +85,33 @@ def test_too_many_sites_unsupported():
         dsx.plan_query(cell=[1, 1, 1, 90, 90, 90], n=(4, 4, 4), frac=np.zeros((65, 3)), b=np.ones(65),
                        taylor_order=1)
     assert e.value.status == dsx.ERR_UNSUPPORTED
+
+
+def _header_structs():
+    """Field names, in order, of every `typedef struct { ... } name;` in include/dsx.h."""
+    import re
+    text = open(os.path.join(ROOT, "include", "dsx.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    out = {}
+    for body, name in re.findall(r"typedef struct\s*\{(.*?)\}\s*(\w+)\s*;", text, flags=re.S):
+        fields = []
+        for decl in body.split(";"):
+            decl = decl.strip()
+            if not decl:
+                continue
+            decl = re.sub(r"^(const\s+)?[\w]+\s*\**\s*", "", decl, count=1)
+            for part in decl.split(","):
+                fields.append(re.sub(r"[\s\*]|\[.*?\]", "", part))
+        out[name] = fields
+    return out
+
+
+def test_binding_structs_match_header_layout():
+    import paper_1809_07088_amd as dsx
+    hs = _header_structs()
+    pairs = {"dsx_model_desc": dsx.ModelDesc, "dsx_plan_info": dsx.PlanInfo,
+             "dsx_kernel_stat": dsx.KernelStat, "dsx_server_config": dsx.ServerConfig,
+             "dsx_request": dsx.Request, "dsx_server_stats": dsx.ServerStats}
+    assert set(pairs) <= set(hs)
+    for cname, py in pairs.items():
+        assert [f for f, _ in py._fields_] == hs[cname], cname
