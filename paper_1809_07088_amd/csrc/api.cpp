@@ -111,11 +111,14 @@ AxisPlan make_plan(int n)
     AxisPlan p{};
     p.n = n;
     int r = n;
+    // primes above 5 first: the first pass of a Stockham transform needs no twiddles
+    for (int f = 7; f <= r; f += 2) {
+        if (f % 3 == 0 || f % 5 == 0) continue;
+        while (r % f == 0) { p.rad[p.nrad++] = f; r /= f; }
+    }
     while (r % 4 == 0) { p.rad[p.nrad++] = 4; r /= 4; }
     while (r % 2 == 0) { p.rad[p.nrad++] = 2; r /= 2; }
     for (int f : {3, 5}) while (r % f == 0) { p.rad[p.nrad++] = f; r /= f; }
-    for (int f = 7; r > 1; f += 2)
-        while (r % f == 0) { p.rad[p.nrad++] = f; r /= f; }
     return p;
 }
 
@@ -206,7 +209,7 @@ struct dsx_model_s {
     float* d_stage = nullptr; size_t stage_cap = 0;
     std::map<Box, DeviceTables> tables;
     std::map<std::pair<int, int>, float*> lanczos_w;
-    int sum_chunks = 0;
+    int sum_chunk = 256, sum_chunks = 0;   // cells per sums block, blocks per (config, site)
     // plan knobs (defaults, or chosen by the autotuner for this model's key)
     int tune_recomb_variant = 0;   // 0 default form, 2 class form
     int tune_fchunk = 0;           // fields per FFT plane block (0 = heuristic)
@@ -314,7 +317,8 @@ Sizes sizes_of(const dsx_model_desc* d)
     long long in = 0;
     if (d->has_occ) in += M * S * z.ncell * 4;
     if (d->kind == DSX_MAGNETIC || d->taylor_order > 0) in += M * S * z.ncell * 12;
-    const long long chunks = (z.ncell + 255) / 256;
+    const long long sc = sums_chunk(z.ncell, M * S);
+    const long long chunks = (z.ncell + sc - 1) / sc;
     z.device_bytes = z.spectrum_bytes + in + M * S * z.T * 8 * (chunks + 1);
     return z;
 }
@@ -568,7 +572,7 @@ dsx_status ensure_spectra(dsx_model m, hipStream_t st, bool force = false)
     sp.vec = m->d_vec;
     sp.partial = m->d_partial; sp.sums = m->d_sums;
     sp.M = m->M; sp.S = m->S; sp.ncell = m->ncell; sp.T = m->T; sp.kind = m->kind;
-    sp.chunk = 256; sp.nchunk = m->sum_chunks;
+    sp.chunk = m->sum_chunk; sp.nchunk = m->sum_chunks;
     HIPCHK(m, timed("sums", st, [&] { return launch_sums(sp, m->order, st); }));
 
     PlaneParams pp;
@@ -774,7 +778,8 @@ dsx_status create_model_impl(const dsx_model_desc* d, bool transient, dsx_model*
 
     auto alloc = [&](void** p, size_t bytes) -> hipError_t { return hipMalloc(p, std::max<size_t>(bytes, 16)); };
     const size_t M = m->M, S = m->S, nc = m->ncell;
-    m->sum_chunks = (m->ncell + 255) / 256;
+    m->sum_chunk = sums_chunk(m->ncell, (long long)m->M * m->S);
+    m->sum_chunks = (m->ncell + m->sum_chunk - 1) / m->sum_chunk;
     hipError_t e = hipSuccess;
     if (m->has_occ && e == hipSuccess) e = alloc((void**)&m->d_occ, M * S * nc * sizeof(float));
     if ((m->kind == DSX_MAGNETIC || m->order > 0) && e == hipSuccess)

@@ -33,6 +33,14 @@ __host__ __device__ constexpr int mono_index(int p, int q, int r) {
 __host__ __device__ constexpr int pair_index(int q, int r) { return (q + r) * (q + r + 1) / 2 + r; }
 
 // ---------------------------------------------------------------------------- FP64 sums
+// Lattice cells per block of the sums kernels (a multiple of 256, the block size):
+// enough blocks to fill the chip, at most 8 cells per thread.
+inline int sums_chunk(long long ncell, long long ms)
+{
+    long long per = (ncell * ms) / (256LL * 2048);
+    per = per < 1 ? 1 : (per > 8 ? 8 : per);
+    return (int)(256 * per);
+}
 struct SumsParams {
     const float* occ;     // [M][S][ncell] or null (delta = 1)
     const float* vec;     // [M][S][ncell][3] displacements (nuclear) or spins (magnetic)

@@ -12,7 +12,8 @@
 //  k_fft_axis1   transforms along axis 1 in place, on LDS tiles of 64 contiguous
 //                columns.
 // The 1D transforms are Stockham auto-sort passes of radix 2, 3, 4, 5 and a direct
-// DFT for any other prime; twiddles come from a float64-generated table.
+// DFT, one output per thread, for any other prime (planned first, where it needs no
+// twiddles); twiddles come from a float64-generated table.
 #include "dsx_internal.h"
 
 namespace dsx {
@@ -47,6 +48,44 @@ __device__ void stockham_pass(const float2* __restrict__ src, float2* __restrict
     const int twstep = n / (Ns * R);
     const int total = nf * nlines * nb;
     const float rnb = 1.f / (float)nb, rnl = 1.f / (float)nlines, rns = 1.f / (float)Ns;
+    if (R > 5) {
+        // odd prime R: one output per work item, so a pass keeps every thread busy.
+        // y_k = x'_0 + sum_{r=1}^{(R-1)/2} [(x'_r + x'_{R-r}) cos(2 pi r k / R)
+        //                                   + i (x'_r - x'_{R-r}) sin(2 pi r k / R)],
+        // x'_r = x_r e^{2 pi i r te / n} (te = 0 in the first pass).  r te <= R te < n
+        // and r k mod R is stepped, so no index needs a division.
+        const int step = n / R, h = (R - 1) / 2;
+        const float rR = 1.f / (float)R;
+        for (int it = threadIdx.x; it < total * R; it += blockDim.x) {
+            const int B = qdiv(it, R, rR);
+            const int k = it - B * R;
+            const int L = qdiv(B, nb, rnb);
+            const int j = B - L * nb;
+            const int fb = qdiv(L, nlines, rnl), l = L - fb * nlines;
+            const float2* x = src + fb * fstride + l * lstride + j * estride;
+            const int jm = j - qdiv(j, Ns, rns) * Ns;
+            const int o = (j - jm) * R + jm;
+            const int te = jm * twstep;
+            const int xs = nb * estride;
+            float2 y = x[0];
+            int b = 0;
+            for (int r = 1; r <= h; ++r) {
+                b += k;
+                b -= (b >= R) ? R : 0;
+                float2 xr = x[r * xs], xq = x[(R - r) * xs];
+                if (Ns > 1) {
+                    xr = cmul(xr, tw[r * te]);
+                    xq = cmul(xq, tw[(R - r) * te]);
+                }
+                const float2 w = tw[b * step];
+                const float2 sm = cadd(xr, xq), df = csub(xr, xq);
+                y.x += sm.x * w.x - df.y * w.y;
+                y.y += sm.y * w.x + df.x * w.y;
+            }
+            dst[fb * fstride + l * lstride + (o + k * Ns) * estride] = y;
+        }
+        return;
+    }
     for (int it = threadIdx.x; it < total; it += blockDim.x) {
         const int L = qdiv(it, nb, rnb);
         const int j = it - L * nb;
@@ -82,7 +121,7 @@ __device__ void stockham_pass(const float2* __restrict__ src, float2* __restrict
             d[o * estride] = cadd(v0, sm);
             d[(o + Ns) * estride] = cadd(t, u);
             d[(o + 2 * Ns) * estride] = csub(t, u);
-        } else if (R == 5) {
+        } else {   // R == 5
             const float c1 = 0.30901699437494742410f, c2 = -0.80901699437494742410f;
             const float s1 = 0.95105651629515357212f, s2 = 0.58778525229247312917f;
             float2 v0 = s[j * estride];
@@ -100,17 +139,6 @@ __device__ void stockham_pass(const float2* __restrict__ src, float2* __restrict
             d[(o + 4 * Ns) * estride] = csub(ra, ia);
             d[(o + 2 * Ns) * estride] = cadd(rb, ib);
             d[(o + 3 * Ns) * estride] = csub(rb, ib);
-        } else {
-            // direct DFT of prime length R: y_k = sum_r x_r e^{2 pi i r (jm/(Ns R) + k/R)}
-            const int step = n / R;
-            for (int k = 0; k < R; ++k) {
-                float2 acc = make_float2(0.f, 0.f);
-                for (int r = 0; r < R; ++r) {
-                    const int e = (r * te + ((r * k) % R) * step) % n;
-                    acc = cadd(acc, cmul(s[(j + r * nb) * estride], tw[e]));
-                }
-                d[(o + k * Ns) * estride] = acc;
-            }
         }
     }
 }
@@ -131,52 +159,103 @@ __device__ float2* lds_fft(float2* a, float2* b, int nlines, int lstride, int es
 }
 
 // ---------------------------------------------------------------------------- sums
-// One lattice cell per thread (P.chunk == blockDim.x); every monomial is reduced
-// across the wave with shuffles and across the four waves through LDS, in a
-// fixed order, so the sums are reproducible run to run.
+// Each thread walks P.chunk / 256 lattice cells and accumulates the monomials in
+// groups of kSumsGroup float64 accumulators.  A group is reduced across the wave
+// by recursive halving (each exchange moves half of the remaining values, so 32
+// values need 32 exchanges instead of 32 x 6), then across the four waves through
+// LDS.  The order of every addition is fixed: the sums are reproducible.
+constexpr int kSumsGroup = 32;
+
+template <int N>
+struct MonoTable {
+    int p[n_monomials(N)], q[n_monomials(N)], r[n_monomials(N)];
+};
+
+// (p, q, r) of every monomial index, in mono_index order
+template <int N>
+__host__ __device__ constexpr MonoTable<N> mono_table()
+{
+    MonoTable<N> m{};
+    for (int dg = 0; dg <= N; ++dg)
+        for (int p = dg; p >= 0; --p)
+            for (int q = dg - p; q >= 0; --q) {
+                const int t = mono_index(p, q, dg - p - q);
+                m.p[t] = p; m.q[t] = q; m.r[t] = dg - p - q;
+            }
+    return m;
+}
+
+// One halving step: lanes with bit MASK set keep the upper HALF values, the others
+// the lower HALF, each adding the partner's copy of the values it keeps.
+template <int HALF, int MASK>
+__device__ __forceinline__ void halve(double (&acc)[kSumsGroup], int lane)
+{
+    const bool hi = (lane & MASK) != 0;
+#pragma unroll
+    for (int k = 0; k < HALF; ++k) {
+        const double send = hi ? acc[k] : acc[k + HALF];
+        const double keep = hi ? acc[k + HALF] : acc[k];
+        acc[k] = keep + __shfl_xor(send, MASK, 64);
+    }
+}
+
+// Sum over the 64 lanes of acc[t] for every t; lane l (even) returns the total of
+// acc[l >> 1].
+__device__ __forceinline__ double wave_transpose_sum(double (&acc)[kSumsGroup], int lane)
+{
+    static_assert(kSumsGroup == 32, "five halving steps");
+    halve<16, 32>(acc, lane);
+    halve<8, 16>(acc, lane);
+    halve<4, 8>(acc, lane);
+    halve<2, 4>(acc, lane);
+    halve<1, 2>(acc, lane);
+    return acc[0] + __shfl_xor(acc[0], 1, 64);
+}
+
 template <int N>
 __global__ __launch_bounds__(256) void k_sums_nuclear(SumsParams P)
 {
     constexpr int T = n_monomials(N);
-    __shared__ double red[4][T];
+    constexpr MonoTable<N> mt = mono_table<N>();
+    __shared__ double red[4][kSumsGroup];
     const int chunk = blockIdx.x % P.nchunk;
     const int ms = blockIdx.x / P.nchunk;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int c = chunk * P.chunk + threadIdx.x;
-    double d = 0.0;
-    double pw[3][N + 1];
-    if (c < P.ncell) {
-        const size_t at = (size_t)ms * P.ncell + c;
-        d = P.occ ? (double)P.occ[at] : 1.0;
+    const int c0 = chunk * P.chunk + threadIdx.x;
+    const int c1 = min(P.ncell, (chunk + 1) * P.chunk);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            pw[a][0] = 1.0;
-            const double u = (N > 0 && P.vec) ? (double)P.vec[3 * at + a] : 0.0;
+    for (int g0 = 0; g0 < T; g0 += kSumsGroup) {
+        double acc[kSumsGroup];
 #pragma unroll
-            for (int k = 1; k <= N; ++k) pw[a][k] = pw[a][k - 1] * u;
-        }
-    } else {
+        for (int t = 0; t < kSumsGroup; ++t) acc[t] = 0.0;
+        // the cells are re-read (from cache) for every group: one group's
+        // accumulators at a time stay in registers
+#pragma unroll 1
+        for (int c = c0; c < c1; c += 256) {
+            const size_t at = (size_t)ms * P.ncell + c;
+            const double d = P.occ ? (double)P.occ[at] : 1.0;
+            double pw[3][N + 1];
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
+            for (int a = 0; a < 3; ++a) {
+                pw[a][0] = 1.0;
+                const double u = (N > 0 && P.vec) ? (double)P.vec[3 * at + a] : 0.0;
 #pragma unroll
-            for (int k = 0; k <= N; ++k) pw[a][k] = 0.0;
-    }
-#pragma unroll
-    for (int dg = 0; dg <= N; ++dg)
-#pragma unroll
-        for (int p = dg; p >= 0; --p)
-#pragma unroll
-            for (int q = dg - p; q >= 0; --q) {
-                const int r = dg - p - q;
-                double v = d * pw[0][p] * pw[1][q] * pw[2][r];
-                for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-                if (lane == 0) red[wave][mono_index(p, q, r)] = v;
+                for (int k = 1; k <= N; ++k) pw[a][k] = pw[a][k - 1] * u;
             }
-    __syncthreads();
-    for (int t = threadIdx.x; t < T; t += blockDim.x) {
-        double v = 0.0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) v += red[w][t];
-        P.partial[((size_t)ms * P.nchunk + chunk) * T + t] = v;
+#pragma unroll
+            for (int t = 0; t < kSumsGroup; ++t)
+                if (g0 + t < T)
+                    acc[t] += d * pw[0][mt.p[g0 + t]] * pw[1][mt.q[g0 + t]] * pw[2][mt.r[g0 + t]];
+        }
+        const double v = wave_transpose_sum(acc, lane);
+        if ((lane & 1) == 0) red[wave][lane >> 1] = v;
+        __syncthreads();
+        if (threadIdx.x < kSumsGroup && g0 + (int)threadIdx.x < T) {
+            const int t = threadIdx.x;
+            P.partial[((size_t)ms * P.nchunk + chunk) * T + g0 + t] =
+                (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
+        }
+        __syncthreads();
     }
 }
 

@@ -60,7 +60,8 @@ def test_random_model_every_order_full_box(order):
     assert err <= TOL
 
 
-@pytest.mark.parametrize("n", [(7, 11, 9), (1, 4, 3), (5, 3, 1), (16, 2, 10)])
+@pytest.mark.parametrize("n", [(7, 11, 9), (1, 4, 3), (5, 3, 1), (16, 2, 10),
+                               (13, 26, 7), (49, 2, 7), (53, 1, 3), (2, 58, 3)])
 def test_odd_prime_and_degenerate_edges(n):
     m = synth.random_model(200 + sum(n), n=n, S=2, M=1, order=3)
     m.g0 = tuple(-v - 1 for v in n)
