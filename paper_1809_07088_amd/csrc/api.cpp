@@ -164,11 +164,13 @@ float2 cis(double x)   // e^{2 pi i x}, argument reduced mod 1 in float64 first
 struct DeviceTables {
     float2* tab1 = nullptr;
     float2* tab2 = nullptr;
+    float2* tabK2 = nullptr;
     float2* tabK3 = nullptr;
     float2* tabH3 = nullptr;
     int4* work = nullptr;
+    int4* work2 = nullptr;     // the same blocks with two G1 planes of one column each
     int H3min = 0, nH3span = 0;
-    int nwork = 0, hc = 0, nchunk3 = 0, block = 0;
+    int nwork = 0, nwork2 = 0, hc = 0, nchunk3 = 0, block = 0;
 };
 
 struct LaunchPlan {
@@ -366,14 +368,17 @@ dsx_status tables_for(dsx_model m, const Box& bx, DeviceTables** out)
         if (se != hipSuccess) { m->failed = true; return fail(DSX_ERR_DEVICE, hipGetErrorString(se)); }
         for (auto& kv : m->tables) {
             dfree(kv.second.tab1); dfree(kv.second.tab2); dfree(kv.second.tabK3); dfree(kv.second.tabH3);
-            dfree(kv.second.work);
+            dfree(kv.second.tabK2); dfree(kv.second.work); dfree(kv.second.work2);
         }
         m->tables.clear();
     }
     DeviceTables t;
     const int S = m->S, n1 = m->n[0], n2 = m->n[1], n3 = m->n[2];
     std::vector<float2> t1((size_t)S * bx.cnt[0]), t2((size_t)S * bx.cnt[1]), tk((size_t)S * n3);
+    std::vector<float2> tk2((size_t)S * n2);
     for (int mu = 0; mu < S; ++mu) {
+        for (int k = 0; k < n2; ++k)
+            tk2[(size_t)mu * n2 + k] = cis((double)k / n2 * m->frac[3 * mu + 1]);
         for (int i = 0; i < bx.cnt[1]; ++i)
             t2[(size_t)mu * bx.cnt[1] + i] = cis((double)(bx.g0[1] + i) / n2 * m->frac[3 * mu + 1]);
         for (int k = 0; k < n3; ++k)
@@ -420,7 +425,7 @@ dsx_status tables_for(dsx_model m, const Box& bx, DeviceTables** out)
     bool friedel = true;
     for (int a = 0; a < 3; ++a)
         if (bx.cnt[a] % 2 == 0 || bx.g0[a] != -(bx.cnt[a] - 1) / 2) friedel = false;
-    std::vector<std::pair<long long, int4>> items;
+    std::vector<std::pair<long long, int4>> items, items2;
     int maxrows = 1;
     for (int k1 = 0; k1 < n1; ++k1) {
         const int nH1 = hcount(k1, n1, bx.g0[0], bx.cnt[0]);
@@ -434,6 +439,7 @@ dsx_status tables_for(dsx_model m, const Box& bx, DeviceTables** out)
             const long long key = std::min(c0, c1) * 2 + (c0 > c1 ? 1 : 0);
             const int np = (nH2 + h2per - 1) / h2per;
             const int rpp = (nH2 + np - 1) / np;
+            std::vector<std::pair<int, int>> planes;   // (j1, mirror) of the G1 planes computed
             for (int j1 = 0; j1 < nH1; ++j1) {
                 const int G1 = k1 + n1 * (H1lo + j1);
                 int mirror = 0;
@@ -446,25 +452,45 @@ dsx_status tables_for(dsx_model m, const Box& bx, DeviceTables** out)
                         mirror = 1;
                     }
                 }
-                for (int part = 0; part < np; ++part) {
-                    const int h2a = part * rpp, h2b = std::min(nH2, h2a + rpp);
-                    if (h2a >= h2b) continue;
-                    maxrows = std::max(maxrows, h2b - h2a);
-                    items.push_back({key * 4096 + j1, make_int4(k1, k2, G1, h2a | (h2b << 12) | (mirror << 24))});
+                planes.push_back({j1, mirror});
+            }
+            for (int part = 0; part < np; ++part) {
+                const int h2a = part * rpp, h2b = std::min(nH2, h2a + rpp);
+                if (h2a >= h2b) continue;
+                maxrows = std::max(maxrows, h2b - h2a);
+                for (size_t i = 0; i < planes.size(); ++i) {
+                    const int j1 = planes[i].first;
+                    const int G1 = k1 + n1 * (H1lo + j1);
+                    items.push_back({key * 4096 + j1, make_int4(k1, k2, G1, h2a | (h2b << 12) | (planes[i].second << 24))});
+                }
+                // planes are consecutive in H1 (the skipped ones are all at the end)
+                for (size_t i = 0; i < planes.size(); i += 2) {
+                    const int j1 = planes[i].first;
+                    const int G1 = k1 + n1 * (H1lo + j1);
+                    const int hasb = i + 1 < planes.size() ? 1 : 0;
+                    const int mb = hasb ? planes[i + 1].second : 0;
+                    items2.push_back({key * 4096 + j1, make_int4(k1, k2, G1, h2a | (h2b << 12) | (planes[i].second << 24) |
+                                                                          (hasb << 25) | (mb << 26))});
                 }
             }
         }
     }
-    std::stable_sort(items.begin(), items.end(),
-                     [](const std::pair<long long, int4>& x, const std::pair<long long, int4>& y) { return x.first < y.first; });
     // blocks are dealt round-robin to the 8 XCDs: XCD x runs the x-th contiguous eighth
-    const size_t per = (items.size() + 7) / 8;
-    std::vector<int4> work(8 * per, make_int4(-1, 0, 0, 0));
-    for (size_t b = 0; b < work.size(); ++b) {
-        const size_t L = (b % 8) * per + b / 8;
-        if (L < items.size()) work[b] = items[L].second;
-    }
+    // of the list, in which the blocks of a column and of its mirror are adjacent
+    auto xcd_order = [](std::vector<std::pair<long long, int4>>& its) {
+        std::stable_sort(its.begin(), its.end(),
+                         [](const std::pair<long long, int4>& x, const std::pair<long long, int4>& y) { return x.first < y.first; });
+        const size_t per = (its.size() + 7) / 8;
+        std::vector<int4> wl(8 * per, make_int4(-1, 0, 0, 0));
+        for (size_t b = 0; b < wl.size(); ++b) {
+            const size_t L = (b % 8) * per + b / 8;
+            if (L < its.size()) wl[b] = its[L].second;
+        }
+        return wl;
+    };
+    const std::vector<int4> work = xcd_order(items), work2 = xcd_order(items2);
     t.nwork = (int)work.size();
+    t.nwork2 = (int)work2.size();
     t.block = ((std::min(maxT, maxrows * per_h2) + 63) / 64) * 64;
 
     auto up = [&](float2** dst, const std::vector<float2>& src) -> hipError_t {
@@ -474,10 +500,13 @@ dsx_status tables_for(dsx_model m, const Box& bx, DeviceTables** out)
     };
     hipError_t e;
     if ((e = up(&t.tab1, t1)) != hipSuccess || (e = up(&t.tab2, t2)) != hipSuccess ||
+        (e = up(&t.tabK2, tk2)) != hipSuccess ||
         (e = up(&t.tabK3, tk)) != hipSuccess || (e = up(&t.tabH3, th)) != hipSuccess ||
         (e = hipMalloc(&t.work, sizeof(int4) * std::max<size_t>(1, work.size()))) != hipSuccess ||
-        (e = hipMemcpy(t.work, work.data(), sizeof(int4) * work.size(), hipMemcpyHostToDevice)) != hipSuccess) {
-        dfree(t.tab1); dfree(t.tab2); dfree(t.tabK3); dfree(t.tabH3); dfree(t.work);
+        (e = hipMemcpy(t.work, work.data(), sizeof(int4) * work.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMalloc(&t.work2, sizeof(int4) * std::max<size_t>(1, work2.size()))) != hipSuccess ||
+        (e = hipMemcpy(t.work2, work2.data(), sizeof(int4) * work2.size(), hipMemcpyHostToDevice)) != hipSuccess) {
+        dfree(t.tab1); dfree(t.tab2); dfree(t.tabK3); dfree(t.tabH3); dfree(t.tabK2); dfree(t.work); dfree(t.work2);
         if (e == hipErrorOutOfMemory) return fail(DSX_ERR_NOMEM, "out of device memory for phase tables");
         m->failed = true;
         return fail(DSX_ERR_DEVICE, std::string("phase tables: ") + hipGetErrorString(e));
@@ -494,10 +523,12 @@ dsx_status plan_recombine(dsx_model m, const Box& bx, float* out, LaunchPlan& lp
     if (st != DSX_OK) return st;
     const int n1 = m->n[0], n2 = m->n[1], n3 = m->n[2];
     const bool mag = m->kind == DSX_MAGNETIC;
+    if ((unsigned long long)bx.cnt[1] * bx.cnt[2] * sizeof(float) >= (1ULL << 32))
+        return fail(DSX_ERR_UNSUPPORTED, "one plane of the output box must stay below 4 GiB");
     RecombParams& p = lp.rp;
     std::memset(&p, 0, sizeof(p));
     p.X = m->d_X; p.out = out;
-    p.tab1 = tb->tab1; p.tab2 = tb->tab2; p.tabK3 = tb->tabK3; p.tabH3 = tb->tabH3;
+    p.tab1 = tb->tab1; p.tab2 = tb->tab2; p.tabK3 = tb->tabK3; p.tabH3 = tb->tabH3; p.tabK2 = tb->tabK2;
     p.n1 = n1; p.n2 = n2; p.n3 = n3; p.nh = m->nh; p.S = m->S; p.SF = m->SF; p.F = m->F; p.M = m->M;
     p.first_mono = m->first_mono;
     for (int a = 0; a < 3; ++a) { p.g0[a] = bx.g0[a]; p.cnt[a] = bx.cnt[a]; }
@@ -506,8 +537,9 @@ dsx_status plan_recombine(dsx_model m, const Box& bx, float* out, LaunchPlan& lp
     p.work = tb->work; p.nwork = tb->nwork;
     p.nchunk3 = tb->nchunk3;
     {
-        static const int forced = [] { const char* v = std::getenv("DSX_RECOMBINE_VARIANT"); return v ? std::atoi(v) : -1; }();
-        p.variant = forced >= 0 ? forced : m->tune_recomb_variant;
+        // DSX_RECOMBINE_VARIANT forces a kernel form (diagnostics and tests)
+        const char* v = std::getenv("DSX_RECOMBINE_VARIANT");
+        p.variant = (v && *v) ? std::atoi(v) : m->tune_recomb_variant;
     }
     p.nsc = (int)m->sc_start.size() - 1;
     for (size_t i = 0; i < m->sc_start.size(); ++i) p.sc_start[i] = m->sc_start[i];
@@ -537,6 +569,33 @@ dsx_status plan_recombine(dsx_model m, const Box& bx, float* out, LaunchPlan& lp
     lp.block = tb->block;
     lp.lds = m->chunk_lds + sizeof(float2) * (size_t)m->nclass * tb->nH3span;
     if (lp.lds > 160 * 1024) return fail(DSX_ERR_UNSUPPORTED, "recombination does not fit the LDS for this box");
+    // folded form: every r_mu2 a multiple of 1/2 (exactly, as given), fewer r3 classes
+    // than sites, and the class buffers fit the LDS
+    if (!mag && p.variant != 3 && m->nclass < m->S) {
+        bool halves = true, whole = true;
+        for (int i = 0; i < m->S; ++i) {
+            const double r2 = m->frac[3 * m->site_of[i] + 1];
+            const double t2 = 2.0 * r2;
+            if (t2 != std::floor(t2)) halves = false;
+            if (r2 != std::floor(r2)) whole = false;
+            p.sgn2[i] = ((long long)std::floor(t2) % 2 == 0) ? 1 : -1;
+        }
+        const int L2 = whole ? 1 : 2;
+        const size_t bs = (size_t)m->nclass * L2 * n3 * n_pairs(m->order);
+        // two planes per block: level A buffers of both, then the class phases
+        const bool par = p.parity && p.variant != 2;
+        const size_t lds = sizeof(float2) * (2 * bs + (par ? 0 : (size_t)m->nclass * tb->nH3span));
+        if (halves && lds <= 140 * 1024) {
+            p.fold = 1;
+            p.fold_l2 = L2;
+            p.bs_elems = (int)bs;
+            p.xs_elems = 0;
+            p.work = tb->work2;
+            p.nwork = tb->nwork2;
+            lp.block = 2 * tb->block;
+            lp.lds = lds;
+        }
+    }
 
     BraggParams& q = lp.bp;
     std::memset(&q, 0, sizeof(q));
@@ -1139,8 +1198,8 @@ dsx_status dsx_autotune(dsx_model m, int32_t lanczos_m, void* hip_stream)
     int best_v = 0;
     const Box b = filt ? grown_box(m->box, lanczos_m) : m->box;
     float* dst = filt ? m->d_ext : scratch;
-    for (int cand : {0, 2}) {
-        if (cand == 2 && m->kind != DSX_NUCLEAR) continue;
+    for (int cand : {0, 2, 3}) {
+        if (cand != 0 && m->kind != DSX_NUCLEAR) continue;
         m->tune_recomb_variant = cand;
         const float t = time_min(st, 3, [&] { return run_box(m, b, dst, st); });
         if (t >= 0.f && (best < 0.f || t < best)) { best = t; best_v = cand; }

@@ -79,6 +79,7 @@ struct Axis1Params {
 //   tab2[mu][i2]  = e^{2 pi i g2 r_mu2}
 //   tabK3[mu][k3] = e^{2 pi i k3 r_mu3 / n3}
 //   tabH3[c][h]   = e^{2 pi i H3 r_c3},  H3 = H3min + h
+//   tabK2[mu][k2] = e^{2 pi i k2 r_mu2 / n2}          (the folded form)
 struct RecombParams {
     const float2* X;
     float* out;
@@ -86,6 +87,7 @@ struct RecombParams {
     const float2* tab2;
     const float2* tabK3;
     const float2* tabH3;
+    const float2* tabK2;
     int32_t n1, n2, n3, nh, S, SF, F, M, first_mono;
     int32_t g0[3], cnt[3];
     int32_t H3min, nH3span;
@@ -94,7 +96,13 @@ struct RecombParams {
     int32_t nwork;
     int32_t nchunk3;        // H3 chunks per (H2, k3)
     int32_t variant;        // kernel variant (0: default for the problem, 1: multi-configuration
-                            // form, 2: class form even when the parity form applies)
+                            // form, 2: class form even when the parity form applies,
+                            // 3: unfolded even when the folded form applies)
+    int32_t fold;           // folded form: every r_mu2 is a multiple of 1/2, so the g2 phase of a
+                            // site is e^{2 pi i k2 r_mu2 / n2} times +-1 by the parity of H2, and
+                            // level A sums the sites of each r3 class (per H2 residue)
+    int32_t fold_l2;        // H2 residues of the folded form: 1 (every r_mu2 whole) or 2
+    int32_t sgn2[kMaxSites];         // per sorted position: e^{2 pi i r_mu2} = +-1
     int32_t parity;         // every r_mu3 is a multiple of 1/2 (the parity form applies)
     int32_t class_sign[kMaxSites];   // per class: e^{2 pi i r_c3} = +-1 in the parity form
     int32_t nsc;            // site chunks (each fits the LDS budget)

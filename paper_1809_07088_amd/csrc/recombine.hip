@@ -25,6 +25,12 @@
 // form factor and takes the component of F perpendicular to Q (Sec. III.D,
 // Eqs. mag_sf, mag_intensity, mag_projection).
 //
+// Folded form: when every r_mu2 is a multiple of 1/2, e^{2 pi i g2 r_mu2} =
+// e^{2 pi i k2 r_mu2 / n2} (+-1)^{H2}, so the g2 phase splits into a block-uniform
+// factor and a sign fixed by the parity of H2.  Level A then applies the site's whole
+// phase but that sign (and 1/r!), and sums the sites of each r3 class into one buffer
+// per H2 parity; level B contracts q once per class instead of once per site.
+//
 // Blocks walk a host-built work list of (k1, k2, G1, H2 range) items, already in
 // the order that keeps the blocks of one column (and of its mirror) on one XCD.
 // On a box symmetric about G = 0 the list holds only half of the G1 planes and the
@@ -59,6 +65,26 @@ __host__ __device__ constexpr float inv_factorial(int r) {
     float f = 1.f;
     for (int i = 2; i <= r; ++i) f *= (float)i;
     return 1.f / f;
+}
+
+// 1/r! for a run-time r <= 8.
+__device__ __forceinline__ float inv_factorial_rt(int r)
+{
+    float v = 1.f;
+#pragma unroll
+    for (int i = 2; i <= 8; ++i) v = (r == i) ? inv_factorial(i) : v;
+    return v;
+}
+
+// Quotient a / b for 0 <= a < 2^22 and 0 < b < 2^22, with rb ~= 1/b (float): the
+// float estimate is off by at most one and is corrected with one remainder check.
+__device__ __forceinline__ int qdiv_r(int a, int b, float rb)
+{
+    int q = (int)((float)a * rb);
+    const int r = a - q * b;
+    q += (r >= b) ? 1 : 0;
+    q -= (r < 0) ? 1 : 0;
+    return q;
 }
 
 // Cooperative global -> LDS copy with up to eight independent loads in flight per
@@ -118,13 +144,58 @@ __device__ __forceinline__ int wave_min_uniform(int v)
     return __builtin_amdgcn_readfirstlane(v);
 }
 
-// Level C in the parity form: |sum_r (i t3)^r S_r|^2 for the thread's H3 values,
-// S = DE for even and DO for odd H3 (h0 = H3 of h = 0), handed to emit(h, value).
-template <int N, int HC, typename Emit>
-__device__ __forceinline__ void parity_level_c(float2 (&DE)[N + 1], float2 (&DO)[N + 1], int h0, int hmin,
-                                               int hcnt, float t3base, float dt3, Emit emit)
+// The thread's output voxels G3 = G3(h = 0) + n3 h of row (G1, G2) and, on symmetric
+// boxes, their mirrors -G: byte offsets from block-uniform plane bases (a plane of
+// the box is below 4 GiB), so each store is one 32-bit add and a global store.
+struct RowOut {
+    char* oplane;
+    char* mplane;
+    uint32_t o0, m0, step;
+    __device__ __forceinline__ void put(int h, float v) const {
+        *reinterpret_cast<float*>(oplane + (o0 + step * (uint32_t)h)) = v;
+    }
+    __device__ __forceinline__ void put_mirror(int h, float v) const {
+        *reinterpret_cast<float*>(mplane + (m0 - step * (uint32_t)h)) = v;
+    }
+};
+
+__device__ __forceinline__ RowOut row_out(const RecombParams& P, const BlockWork& w, int i2, int i3b)
 {
-    // the set for even h becomes DE, the set for odd h DO (swap in place)
+    RowOut r;
+    const size_t plane = (size_t)P.cnt[1] * P.cnt[2];
+    r.oplane = reinterpret_cast<char*>(P.out + (size_t)w.i1 * plane);
+    r.mplane = reinterpret_cast<char*>(P.out + (size_t)(P.cnt[0] - 1 - w.i1) * plane);
+    r.o0 = 4u * (uint32_t)(i2 * P.cnt[2] + i3b);
+    r.m0 = 4u * (uint32_t)((P.cnt[1] - 1 - i2) * P.cnt[2] + (P.cnt[2] - 1 - i3b));
+    r.step = 4u * (uint32_t)P.n3;
+    return r;
+}
+
+// Writes v(h) for the thread's H3 values: unconditionally while every lane of the
+// wave has it (h < hmin and the whole wave active), with a per-lane test otherwise.
+template <int HC, bool MIRROR, typename Val>
+__device__ __forceinline__ void write_row(const RowOut& ro, bool full, bool active, int hmin, int hcnt,
+                                          float scale, Val val)
+{
+#pragma unroll
+    for (int h = 0; h < HC; ++h) {
+        if (h < hmin && full) {
+            const float v = val(h) * scale;
+            ro.put(h, v);
+            if (MIRROR) ro.put_mirror(h, v);
+        } else if (active && h < hcnt) {
+            const float v = val(h) * scale;
+            ro.put(h, v);
+            if (MIRROR) ro.put_mirror(h, v);
+        }
+    }
+}
+
+// Level C in the parity form: the coefficient set of even H3 goes to DE and that of
+// odd H3 to DO (h0 = H3 of h = 0) ...
+template <int N>
+__device__ __forceinline__ void parity_order(float2 (&DE)[N + 1], float2 (&DO)[N + 1], int h0)
+{
     const bool odd0 = (h0 & 1) != 0;
 #pragma unroll
     for (int r = 0; r <= N; ++r) {
@@ -132,25 +203,17 @@ __device__ __forceinline__ void parity_level_c(float2 (&DE)[N + 1], float2 (&DO)
         DE[r] = odd0 ? DO[r] : DE[r];
         DO[r] = odd0 ? t : DO[r];
     }
+}
+
+// ... and |sum_r (i t3)^r S_r|^2 at the thread's h (Horner in i t3).
+template <int N>
+__device__ __forceinline__ float parity_eval(const float2 (&S)[N + 1], float t3)
+{
+    float2 acc = S[N];
 #pragma unroll
-    for (int h = 0; h < HC; ++h) {
-        if (h < hmin || h < hcnt) {
-            const float t3 = t3base + (float)h * dt3;
-            float2 acc;
-            if ((h & 1) == 0) {
-                acc = DE[N];
-#pragma unroll
-                for (int r = N - 1; r >= 0; --r)
-                    acc = make_float2(DE[r].x - t3 * acc.y, DE[r].y + t3 * acc.x);
-            } else {
-                acc = DO[N];
-#pragma unroll
-                for (int r = N - 1; r >= 0; --r)
-                    acc = make_float2(DO[r].x - t3 * acc.y, DO[r].y + t3 * acc.x);
-            }
-            emit(h, acc.x * acc.x + acc.y * acc.y);
-        }
-    }
+    for (int r = N - 1; r >= 0; --r)
+        acc = make_float2(S[r].x - t3 * acc.y, S[r].y + t3 * acc.x);
+    return acc.x * acc.x + acc.y * acc.y;
 }
 
 // MULTI: more than one configuration; a single configuration needs no separate
@@ -357,37 +420,310 @@ __global__ __launch_bounds__(512, 4) void k_recombine_nuclear(RecombParams P)
             }
         }
         if constexpr (PAR && MULTI) {
-            parity_level_c<N, HC>(DE, DO, H3lo + hbeg, hmin, hcnt, t3base, dt3, [&](int h, float v) { I[h] += v; });
+            parity_order<N>(DE, DO, H3lo + hbeg);
+#pragma unroll
+            for (int h = 0; h < HC; ++h)
+                if (h < hmin || h < hcnt) I[h] += parity_eval<N>((h & 1) ? DO : DE, t3base + (float)h * dt3);
         } else if constexpr (MULTI) {
 #pragma unroll
             for (int h = 0; h < HC; ++h) I[h] += F[h].x * F[h].x + F[h].y * F[h].y;
         }
     }
     const int i3b = k3 + n3 * (H3lo + hbeg) - P.g0[2];       // output index of h = 0
-    float* orow = P.out + ((size_t)w.i1 * P.cnt[1] + i2) * P.cnt[2] + i3b;
-    float* mrow = P.out + ((size_t)(P.cnt[0] - 1 - w.i1) * P.cnt[1] + (P.cnt[1] - 1 - i2)) * P.cnt[2]
-                + (P.cnt[2] - 1 - i3b);
-    if constexpr (PAR && !MULTI) {
-        // single configuration: evaluate and write
-        parity_level_c<N, HC>(DE, DO, H3lo + hbeg, hmin, hcnt, t3base, dt3, [&](int h, float v) {
-            if (active) {
-                orow[n3 * h] = v * P.scale;
-                if (w.mirror) mrow[-n3 * h] = v * P.scale;
-            }
-        });
-        return;
+    const RowOut ro = row_out(P, w, i2, i3b);
+    const bool full = wave_min_uniform(active ? 1 : 0) != 0;
+    if constexpr (PAR && !MULTI) parity_order<N>(DE, DO, H3lo + hbeg);
+    auto val = [&](int h) -> float {
+        if constexpr (MULTI) return I[h];
+        else if constexpr (PAR) return parity_eval<N>((h & 1) ? DO : DE, t3base + (float)h * dt3);
+        else return F[h].x * F[h].x + F[h].y * F[h].y;
+    };
+    if (w.mirror) write_row<HC, true>(ro, full, active, hmin, hcnt, P.scale, val);
+    else write_row<HC, false>(ro, full, active, hmin, hcnt, P.scale, val);
+}
+
+// Folded form (every r_mu2 a multiple of 1/2; see the top of the file).  A block
+// takes two planes G1 and G1 + n1 of one spectra column (the second may be absent):
+// level A reads every spectrum once for both, and each half of the block then runs
+// levels B and C of one plane.  LDS:
+//   Bs   [2][nclass][L2][n3][QR]  level A summed over the sites of each r3 class,
+//                                 with the site phase (but the H2-parity sign) and 1/r!
+//   tHs  [nclass][nH3span]        class phases e^{2 pi i H3 r_c3} (class form only)
+// Level A reads the spectra straight from the (L2-resident) column: every thread
+// owns (pair, k3) items and accumulates the sites of a class in registers, with the
+// loads of the next site in flight, so the level needs no staging and no barrier.
+template <int N, int HC, bool MULTI, bool PAR>
+__global__ __launch_bounds__(1024) void k_recombine_folded(RecombParams P)
+{
+    extern __shared__ float2 smem[];
+    constexpr int QR = n_pairs(N);
+    const int4 wi = P.work[blockIdx.x];
+    if (wi.x < 0) return;
+    const bool hasb = (wi.w >> 25) & 1;
+    const int bh = blockDim.x >> 1;                 // threads per plane
+    const int sel = (int)threadIdx.x >= bh ? 1 : 0; // the plane of this thread's B / C item
+    BlockWork w;
+    w.k1 = wi.x;
+    w.k2 = wi.y;
+    w.G1 = wi.z + (sel && hasb ? P.n1 : 0);
+    w.h2a = wi.w & 0xfff;
+    w.h2b = (wi.w >> 12) & 0xfff;
+    w.mirror = ((wi.w >> (sel ? 26 : 24)) & 1) != 0;
+    {
+        int nH2;
+        hrange(w.k2, P.n2, P.g0[1], P.cnt[1], w.H2lo, nH2);
     }
-    if (!active) return;
+    w.i1 = w.G1 - P.g0[0];
+    const int L2 = P.fold_l2;
+    float2* Bs = smem + (size_t)sel * P.bs_elems;
+    float2* tHs = smem + 2 * (size_t)P.bs_elems;
+    __shared__ int jtab[2][QR];              // terms N - e + 1, field of p = 0 of pair j
+    __shared__ float jfr[QR];                // 1/r! of pair j
+    // per plane and site: b e^{2 pi i (g1 r1 + k2 r2 / n2)} (i tau1)^p / p!
+    __shared__ float2 wtab[2][kMaxSites][N + 1];
+    const int n1 = P.n1, n2 = P.n2, n3 = P.n3, nh = P.nh;
+    const int SFnh = P.SF * nh;
+    for (int j = threadIdx.x; j < QR; j += blockDim.x) {
+        int e = 0;
+        while ((e + 1) * (e + 2) / 2 <= j) ++e;
+        int cum = 0;
+        for (int ee = 0; ee < e; ++ee) cum += (ee + 1) * (N - ee + 1);
+        const int r = j - e * (e + 1) / 2;   // pair_index(q, r) = e (e + 1) / 2 + r
+        cum += r * (N - e + 1);
+        jtab[0][j] = N - e + 1;
+        jtab[1][j] = cum - P.first_mono;
+        jfr[j] = inv_factorial_rt(r);
+    }
+    for (int t = threadIdx.x; t < 2 * P.S * (N + 1); t += blockDim.x) {
+        const int pl = t / (P.S * (N + 1));
+        const int u = t - pl * P.S * (N + 1);
+        const int sl = u / (N + 1), p = u - sl * (N + 1);
+        const int mu = P.site_of[sl];
+        const int G1 = wi.z + (pl && hasb ? n1 : 0);      // (an absent plane repeats the first)
+        const float tau1 = (float)(6.283185307179586 * (double)G1 / (double)n1);
+        const float2 wb = cmulf(P.tab1[(size_t)mu * P.cnt[0] + (G1 - P.g0[0])], P.tabK2[(size_t)mu * n2 + w.k2]);
+        float mag = 1.f;
+        for (int v = 1; v <= p; ++v) mag *= tau1 / (float)v;
+        const int p4 = p & 3;
+        const float2 ip = p4 == 0 ? make_float2(mag, 0.f) : p4 == 1 ? make_float2(0.f, mag)
+                        : p4 == 2 ? make_float2(-mag, 0.f) : make_float2(0.f, -mag);
+        wtab[pl][sl][p] = cmulf(wb, ip);
+    }
+    const float2* tH0 = PAR ? nullptr : stage_class_phases(P, tHs);
+
+    // this thread's item: (H2, H3 chunk, k3) with k3 fastest, in its plane
+    const int nitems = (w.h2b - w.h2a) * n3 * P.nchunk3;
+    const int item = threadIdx.x - sel * bh;
+    const bool active = item < nitems && (sel == 0 || hasb);
+    int k3 = 0, ch = 0, h2 = w.h2a;
+    if (active) {
+        k3 = item % n3;
+        const int r = item / n3;
+        ch = r % P.nchunk3;
+        h2 = w.h2a + r / P.nchunk3;
+    }
+    const int H2 = w.H2lo + h2;
+    const int rho = (L2 == 2) ? (H2 & 1) : 0;
+    const int G2 = w.k2 + n2 * H2;
+    const int i2 = G2 - P.g0[1];
+    int H3lo, nH3;
+    hrange(k3, n3, P.g0[2], P.cnt[2], H3lo, nH3);
+    const int hbeg = ch * HC;
+    const int hcnt = active ? max(0, min(HC, nH3 - hbeg)) : 0;
+    const int hmin = wave_min_uniform(active ? hcnt : HC);   // iterations every lane needs
+    const float tau2 = (float)(6.283185307179586 * (double)G2 / (double)n2);
+    const float c3 = (float)(6.283185307179586 / (double)n3);
+    const float t3base = (float)(k3 + n3 * (H3lo + hbeg)) * c3;   // tau3 of h = 0
+    const float dt3 = 6.283185307179586f;                          // tau3 step per H3
+    float I[MULTI ? HC : 1];
 #pragma unroll
-    for (int h = 0; h < HC; ++h) {
-        if (h < hmin || h < hcnt) {
-            float v;
-            if constexpr (MULTI) v = I[h] * P.scale;
-            else v = (F[h].x * F[h].x + F[h].y * F[h].y) * P.scale;
-            orow[n3 * h] = v;
-            if (w.mirror) mrow[-n3 * h] = v;
+    for (int h = 0; h < (MULTI ? HC : 1); ++h) I[h] = 0.f;
+
+    const size_t col = ((size_t)w.k1 * n2 + w.k2) * SFnh;
+    const size_t colm = ((size_t)((n1 - w.k1) % n1) * n2 + (n2 - w.k2) % n2) * SFnh;
+    const int nitemA = QR * n3;
+    const float rn3 = 1.f / (float)n3;
+    const size_t fstride = (size_t)P.F * nh;   // between the sites of a column
+
+    constexpr int NF = PAR ? 1 : HC;
+    float2 F[NF];
+    float2 DE[N + 1], DO[N + 1];
+    __syncthreads();
+    for (int m = 0; m < P.M; ++m) {
+        const float2* Xm = P.X + (size_t)m * n1 * n2 * SFnh;
+        // level A: items (pair j, k3) with k3 fastest; pairs run in order of e = q + r,
+        // so the number of p terms N - e + 1 only falls along a wave: its first and
+        // last lanes give the wave-uniform bounds
+        for (int base = 0; base < nitemA; base += blockDim.x) {
+            const int gw0 = __builtin_amdgcn_readfirstlane(base + (int)(threadIdx.x & ~63u));
+            if (gw0 >= nitemA) continue;
+            const int gw1 = min(gw0 + 63, nitemA - 1);
+            const int pmax = __builtin_amdgcn_readfirstlane(jtab[0][qdiv_r(gw0, n3, rn3)]);
+            const int pmin = __builtin_amdgcn_readfirstlane(jtab[0][qdiv_r(gw1, n3, rn3)]);
+            const int g = base + threadIdx.x;
+            const bool ok = g < nitemA;
+            const int gg = ok ? g : nitemA - 1;
+            const int j = qdiv_r(gg, n3, rn3);
+            const int kk = gg - j * n3;
+            const int pc = jtab[0][j], f0 = jtab[1][j];
+            const float fr = jfr[j];
+            const bool half = kk >= nh;                   // conj X(-k) from the mirrored column
+            const float2* xl = Xm + (half ? colm : col) + (half ? n3 - kk : kk);
+            const unsigned cj = half ? 0x80000000u : 0u;
+            // the p terms of site sl: loads (clamped in-bounds, masked later) ...
+            auto load = [&](int sl, float2 (&x)[N + 1]) {
+                const float2* xb = xl + (size_t)P.site_of[sl] * fstride;
+#pragma unroll
+                for (int p = 0; p <= N; ++p) {
+                    if (p < pmax) {
+                        const int f = f0 + p;
+                        if (p < pmin) x[p] = xb[(size_t)(p == 0 ? max(f, 0) : f) * nh];
+                        else x[p] = xb[(size_t)min(f, P.F - 1) * nh];
+                    }
+                }
+            };
+            // ... and sum_p w_p X (X = x, or conj x on the mirrored half) for both planes
+            auto contract = [&](int sl, const float2 (&x)[N + 1], float2& acc0, float2& acc1) {
+                const float2* w0 = wtab[0][sl];
+                const float2* w1 = wtab[1][sl];
+                acc0 = make_float2(0.f, 0.f);
+                acc1 = make_float2(0.f, 0.f);
+#pragma unroll
+                for (int p = 0; p <= N; ++p) {
+                    if (p < pmax) {
+                        float2 v = x[p];
+                        if (p == 0) v = f0 >= 0 ? v : make_float2(0.f, 0.f);   // absent constant monomial
+                        if (p >= pmin) v = p < pc ? v : make_float2(0.f, 0.f);
+                        v.y = __uint_as_float(__float_as_uint(v.y) ^ cj);
+                        const float2 wp = w0[p], wq = w1[p];
+                        acc0.x += wp.x * v.x - wp.y * v.y;
+                        acc0.y += wp.x * v.y + wp.y * v.x;
+                        acc1.x += wq.x * v.x - wq.y * v.y;
+                        acc1.y += wq.x * v.y + wq.y * v.x;
+                    }
+                }
+            };
+            // sites in class order; the loads of the next site are in flight while the
+            // current one is contracted
+            float2 xa[N + 1], xb2[N + 1];
+            float2 aE0 = make_float2(0.f, 0.f), aO0 = aE0, aE1 = aE0, aO1 = aE0;
+            auto finish = [&](int sl, const float2& acc0, const float2& acc1) {
+                const int mu = P.site_of[sl];
+                const float2 k3p = P.tabK3[(size_t)mu * n3 + kk];
+                const float2 kf = make_float2(k3p.x * fr, k3p.y * fr);
+                const float2 v0 = cmulf(kf, acc0), v1 = cmulf(kf, acc1);
+                const float s2 = (float)P.sgn2[sl];
+                aE0.x += v0.x; aE0.y += v0.y;
+                aO0.x += s2 * v0.x; aO0.y += s2 * v0.y;
+                aE1.x += v1.x; aE1.y += v1.y;
+                aO1.x += s2 * v1.x; aO1.y += s2 * v1.y;
+                const int c = P.class_of[sl];
+                if (sl + 1 == P.S || P.class_of[sl + 1] != c) {   // last site of class c
+                    if (ok) {
+                        float2* b0 = smem + ((size_t)(c * L2) * n3 + kk) * QR + j;
+                        float2* b1 = b0 + P.bs_elems;
+                        b0[0] = aE0;
+                        b1[0] = aE1;
+                        if (L2 == 2) {
+                            b0[(size_t)n3 * QR] = aO0;
+                            b1[(size_t)n3 * QR] = aO1;
+                        }
+                    }
+                    aE0 = aO0 = aE1 = aO1 = make_float2(0.f, 0.f);
+                }
+            };
+            float2 c0, c1;
+            load(0, xa);
+            for (int sl = 0; sl < P.S; sl += 2) {
+                if (sl + 1 < P.S) load(sl + 1, xb2);
+                contract(sl, xa, c0, c1);
+                finish(sl, c0, c1);
+                if (sl + 1 < P.S) {
+                    if (sl + 2 < P.S) load(sl + 2, xa);
+                    contract(sl + 1, xb2, c0, c1);
+                    finish(sl + 1, c0, c1);
+                }
+            }
+        }
+        __syncthreads();
+        // level B: contract q once per class; the parity form folds the classes into
+        // DE / DO, the class form evaluates level C per class
+        float a2[N + 1];   // tau2^q / q!
+        a2[0] = 1.f;
+#pragma unroll
+        for (int q = 1; q <= N; ++q) a2[q] = a2[q - 1] * tau2 / (float)q;
+#pragma unroll
+        for (int h = 0; h < NF; ++h) F[h] = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int r = 0; r <= N; ++r) { DE[r] = make_float2(0.f, 0.f); DO[r] = make_float2(0.f, 0.f); }
+        if (active) {
+            for (int c = 0; c < P.nclass; ++c) {
+                const float2* Bp = Bs + ((size_t)(c * L2 + rho) * n3 + k3) * QR;
+                const float sgn = PAR ? (float)P.class_sign[c] : 1.f;
+                float2 D[PAR ? 1 : N + 1];
+#pragma unroll
+                for (int r = 0; r <= N; ++r) {
+                    float2 C = make_float2(0.f, 0.f);
+#pragma unroll
+                    for (int q = 0; q + r <= N; ++q) {
+                        const float2 v = Bp[pair_index(q, r)];
+                        const float a = a2[q];
+                        // C += i^q a v
+                        if ((q & 3) == 0) { C.x += a * v.x; C.y += a * v.y; }
+                        else if ((q & 3) == 1) { C.x -= a * v.y; C.y += a * v.x; }
+                        else if ((q & 3) == 2) { C.x -= a * v.x; C.y -= a * v.y; }
+                        else { C.x += a * v.y; C.y -= a * v.x; }
+                    }
+                    if constexpr (PAR) {
+                        DE[r].x += C.x; DE[r].y += C.y;
+                        DO[r].x += sgn * C.x; DO[r].y += sgn * C.y;
+                    } else {
+                        D[r] = C;
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                if constexpr (!PAR) {
+                    const float2* tH = tH0 + (size_t)c * P.nH3span + H3lo + hbeg;
+#pragma unroll
+                    for (int h = 0; h < HC; ++h) {
+                        if (h < hmin || h < hcnt) {
+                            const float t3 = t3base + (float)h * dt3;
+                            float2 acc = D[N];
+#pragma unroll
+                            for (int r = N - 1; r >= 0; --r)
+                                acc = make_float2(D[r].x - t3 * acc.y, D[r].y + t3 * acc.x);
+                            const float2 e3 = tH[h];
+                            F[h].x += e3.x * acc.x - e3.y * acc.y;
+                            F[h].y += e3.x * acc.y + e3.y * acc.x;
+                        }
+                    }
+                }
+            }
+        }
+        if constexpr (MULTI) {
+            if constexpr (PAR) {
+                parity_order<N>(DE, DO, H3lo + hbeg);
+#pragma unroll
+                for (int h = 0; h < HC; ++h)
+                    if (h < hmin || h < hcnt) I[h] += parity_eval<N>((h & 1) ? DO : DE, t3base + (float)h * dt3);
+            } else {
+#pragma unroll
+                for (int h = 0; h < HC; ++h) I[h] += F[h].x * F[h].x + F[h].y * F[h].y;
+            }
+            __syncthreads();                 // every thread has read Bs before it is cleared
         }
     }
+    const int i3b = k3 + n3 * (H3lo + hbeg) - P.g0[2];       // output index of h = 0
+    const RowOut ro = row_out(P, w, i2, i3b);
+    const bool full = wave_min_uniform(active ? 1 : 0) != 0;
+    if constexpr (PAR && !MULTI) parity_order<N>(DE, DO, H3lo + hbeg);
+    auto val = [&](int h) -> float {
+        if constexpr (MULTI) return I[h];
+        else if constexpr (PAR) return parity_eval<N>((h & 1) ? DO : DE, t3base + (float)h * dt3);
+        else return F[h].x * F[h].x + F[h].y * F[h].y;
+    };
+    if (w.mirror) write_row<HC, true>(ro, full, active, hmin, hcnt, P.scale, val);
+    else write_row<HC, false>(ro, full, active, hmin, hcnt, P.scale, val);
 }
 
 // ---------------------------------------------------------------------------- magnetic
@@ -577,11 +913,26 @@ static hipError_t launch_nuc_v(const RecombParams& p, int block, size_t lds, hip
     return hipGetLastError();
 }
 
+template <int N, int HC, bool MULTI, bool PAR>
+static hipError_t launch_fold_v(const RecombParams& p, int block, size_t lds, hipStream_t st)
+{
+    hipError_t e = set_lds(k_recombine_folded<N, HC, MULTI, PAR>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_recombine_folded<N, HC, MULTI, PAR>), dim3(p.nwork), dim3(block), lds, st, p);
+    return hipGetLastError();
+}
+
 template <int N, int HC>
 static hipError_t launch_nuc(const RecombParams& p, int block, size_t lds, hipStream_t st)
 {
     const bool multi = p.M > 1 || p.variant == 1;
     const bool par = p.parity != 0 && p.variant != 2;
+    if (p.fold) {
+        if (multi) return par ? launch_fold_v<N, HC, true, true>(p, block, lds, st)
+                              : launch_fold_v<N, HC, true, false>(p, block, lds, st);
+        return par ? launch_fold_v<N, HC, false, true>(p, block, lds, st)
+                   : launch_fold_v<N, HC, false, false>(p, block, lds, st);
+    }
     if (multi) return par ? launch_nuc_v<N, HC, true, true>(p, block, lds, st)
                           : launch_nuc_v<N, HC, true, false>(p, block, lds, st);
     return par ? launch_nuc_v<N, HC, false, true>(p, block, lds, st)

@@ -185,3 +185,29 @@ def test_set_sites_marks_spectra_stale():
     torch.cuda.synchronize()
     assert rel_l2(out.cpu().numpy(), O.intensity(m2).reshape(m.count)) <= TOL
     h.close()
+
+
+# ------------------------------------------------------------------ recombination forms
+
+def _half_r2_model(seed, order, M, parity):
+    """Four sites whose r2 are multiples of 1/2 and which share two r3 classes (the
+    folded form applies); r3 are halves too when `parity`."""
+    m = synth.random_model(seed, n=(6, 4, 6), S=4, M=M, order=order)
+    r3 = (0.0, 0.5) if parity else (0.13, 0.71)
+    m.frac = np.array([[0.0, 0.0, r3[0]], [0.31, 0.5, r3[0]], [0.5, 0.0, r3[1]], [0.77, 1.5, r3[1]]])
+    m.g0, m.count = (-7, -5, -6), (15, 11, 13)
+    return m
+
+
+@pytest.mark.parametrize("variant", ["0", "1", "2", "3"])
+@pytest.mark.parametrize("order,M,parity", [(8, 1, True), (5, 2, True), (3, 1, False), (6, 2, False),
+                                            (0, 2, True)])
+def test_every_recombination_form(monkeypatch, variant, order, M, parity):
+    """Variant 0: the default (folded where it applies), 1: the multi-configuration form,
+    2: the class form, 3: unfolded."""
+    monkeypatch.setenv("DSX_RECOMBINE_VARIANT", variant)
+    m = _half_r2_model(700 + order, order, M, parity)
+    say(f"recombination form variant={variant} order={order} M={M} parity={parity}")
+    I = gpu_intensity(m)
+    ref = O.intensity(m, O.grid_points(m.g0, m.count), order).reshape(m.count)
+    assert rel_l2(I, ref) <= TOL
