@@ -516,14 +516,21 @@ dsx_status tables_for(dsx_model m, const Box& bx, DeviceTables** out)
     return DSX_OK;
 }
 
-dsx_status plan_recombine(dsx_model m, const Box& bx, float* out, LaunchPlan& lp)
+// Memory layout of an output box: element (i1, i2, i3) at (i1 cnt1 + i2) pitch + i3 + off.
+struct Layout {
+    int pitch, off;
+};
+
+Layout dense_layout(const Box& b) { return Layout{b.cnt[2], 0}; }
+
+dsx_status plan_recombine(dsx_model m, const Box& bx, float* out, const Layout& lay, LaunchPlan& lp)
 {
     DeviceTables* tb = nullptr;
     dsx_status st = tables_for(m, bx, &tb);
     if (st != DSX_OK) return st;
     const int n1 = m->n[0], n2 = m->n[1], n3 = m->n[2];
     const bool mag = m->kind == DSX_MAGNETIC;
-    if ((unsigned long long)bx.cnt[1] * bx.cnt[2] * sizeof(float) >= (1ULL << 32))
+    if ((unsigned long long)bx.cnt[1] * lay.pitch * sizeof(float) >= (1ULL << 32))
         return fail(DSX_ERR_UNSUPPORTED, "one plane of the output box must stay below 4 GiB");
     RecombParams& p = lp.rp;
     std::memset(&p, 0, sizeof(p));
@@ -532,6 +539,7 @@ dsx_status plan_recombine(dsx_model m, const Box& bx, float* out, LaunchPlan& lp
     p.n1 = n1; p.n2 = n2; p.n3 = n3; p.nh = m->nh; p.S = m->S; p.SF = m->SF; p.F = m->F; p.M = m->M;
     p.first_mono = m->first_mono;
     for (int a = 0; a < 3; ++a) { p.g0[a] = bx.g0[a]; p.cnt[a] = bx.cnt[a]; }
+    p.opitch = lay.pitch; p.ooff = lay.off;
     p.H3min = tb->H3min; p.nH3span = tb->nH3span;
     p.nclass = m->nclass;
     p.work = tb->work; p.nwork = tb->nwork;
@@ -600,6 +608,7 @@ dsx_status plan_recombine(dsx_model m, const Box& bx, float* out, LaunchPlan& lp
     BraggParams& q = lp.bp;
     std::memset(&q, 0, sizeof(q));
     q.sums = m->d_sums; q.out = out;
+    q.opitch = lay.pitch; q.ooff = lay.off;
     for (int a = 0; a < 3; ++a) {
         q.g0[a] = bx.g0[a]; q.cnt[a] = bx.cnt[a]; q.n[a] = m->n[a];
         q.Hlo[a] = (int)ceildiv_l(bx.g0[a], m->n[a]);
@@ -675,10 +684,10 @@ dsx_status ensure_spectra(dsx_model m, hipStream_t st, bool force = false)
     return DSX_OK;
 }
 
-dsx_status run_box(dsx_model m, const Box& bx, float* dout, hipStream_t st)
+dsx_status run_box(dsx_model m, const Box& bx, float* dout, const Layout& lay, hipStream_t st)
 {
     LaunchPlan lp;
-    dsx_status s = plan_recombine(m, bx, dout, lp);
+    dsx_status s = plan_recombine(m, bx, dout, lay, lp);
     if (s != DSX_OK) return s;
     if (m->kind == DSX_MAGNETIC)
         HIPCHK(m, timed("recombine", st, [&] { return launch_recombine_magnetic(lp.rp, lp.hc, lp.block, lp.lds, st); }));
@@ -980,11 +989,23 @@ Box grown_box(const Box& b, int mm)
     return ext;
 }
 
+// The filter reads window points from eoff = 1 on: with `off` floats in front of
+// every row, the first window point of each 64-column output tile starts a 128-byte
+// line, so the filter's tiles read whole lines.
+constexpr int kExtEoff = 1;
+Layout ext_layout(const Box& ext)
+{
+    const int off = (32 - kExtEoff % 32) % 32;
+    return Layout{(off + ext.cnt[2] + 31) / 32 * 32, off};
+}
+
+size_t ext_elems(const Box& ext) { return (size_t)ext.cnt[0] * ext.cnt[1] * ext_layout(ext).pitch; }
+
 // Everything the filter needs that allocates or uploads (never inside a capture).
 dsx_status prepare_filter(dsx_model m, int mm, int sv)
 {
     const Box ext = grown_box(m->box, mm);
-    const size_t ext_vox = (size_t)ext.cnt[0] * ext.cnt[1] * ext.cnt[2];
+    const size_t ext_vox = ext_elems(ext);
     if (m->ext_cap < ext_vox) {
         if (m->pins) return fail(DSX_ERR_BUSY, "the grown box would outgrow a buffer a batch has recorded");
         dfree(m->d_ext);
@@ -1032,12 +1053,14 @@ dsx_status enqueue_filter(dsx_model m, int mm, int sv, float* dout, hipStream_t 
     dsx_status s;
     const Box ext = grown_box(m->box, mm);
     if ((s = ensure_spectra(m, st, force)) != DSX_OK) return s;
-    if ((s = run_box(m, ext, m->d_ext, st)) != DSX_OK) return s;
+    const Layout el = ext_layout(ext);
+    if ((s = run_box(m, ext, m->d_ext, el, st)) != DSX_OK) return s;
     LanczosParams lp{};
     lp.in = m->d_ext; lp.out = dout; lp.wn = m->lanczos_w[std::make_pair(mm, sv)];
+    lp.ipitch = el.pitch; lp.ioff = el.off;
     for (int a = 0; a < 3; ++a) { lp.e[a] = ext.cnt[a]; lp.o[a] = sv * m->box.cnt[a]; }
     lp.m = mm; lp.s = sv;
-    lp.eoff = 1;
+    lp.eoff = kExtEoff;
     lp.t3 = 64; lp.t1 = m->tune_lanczos_t1;
     lp.t2 = 32;
     while (lp.t2 > 1 && lanczos_lds_bytes(lp) > 150 * 1024) lp.t2 /= 2;
@@ -1053,7 +1076,7 @@ dsx_status enqueue_intensity(dsx_model m, float* dout, hipStream_t st, bool forc
 {
     dsx_status s;
     if ((s = ensure_spectra(m, st, force)) != DSX_OK) return s;
-    return run_box(m, m->box, dout, st);
+    return run_box(m, m->box, dout, dense_layout(m->box), st);
 }
 
 dsx_status check_filter_args(int32_t lanczos_m, int32_t oversample)
@@ -1201,7 +1224,8 @@ dsx_status dsx_autotune(dsx_model m, int32_t lanczos_m, void* hip_stream)
     for (int cand : {0, 2, 3}) {
         if (cand != 0 && m->kind != DSX_NUCLEAR) continue;
         m->tune_recomb_variant = cand;
-        const float t = time_min(st, 3, [&] { return run_box(m, b, dst, st); });
+        const Layout lay = filt ? ext_layout(b) : dense_layout(b);
+        const float t = time_min(st, 3, [&] { return run_box(m, b, dst, lay, st); });
         if (t >= 0.f && (best < 0.f || t < best)) { best = t; best_v = cand; }
     }
     m->tune_recomb_variant = best_v;
@@ -1478,7 +1502,7 @@ size_t request_workspace(dsx_model m, int lm, size_t* x_bytes)
 {
     *x_bytes = Arena::round(m->spectrum_bytes);
     size_t ws = *x_bytes + Arena::round(m->partial_bytes);
-    if (lm >= 2) ws += Arena::round(box_voxels(grown_box(m->box, lm)) * sizeof(float));
+    if (lm >= 2) ws += Arena::round(ext_elems(grown_box(m->box, lm)) * sizeof(float));
     return ws;
 }
 
@@ -1494,7 +1518,7 @@ dsx_status launch_request(dsx_server s, const Request& q, hipStream_t st, hipEve
     m->d_partial = reinterpret_cast<double*>(base + q.x_bytes);
     if (lm >= 2) {
         m->d_ext = reinterpret_cast<float*>(base + q.x_bytes + Arena::round(m->partial_bytes));
-        m->ext_cap = box_voxels(grown_box(m->box, lm));
+        m->ext_cap = ext_elems(grown_box(m->box, lm));
     }
     rs = follow(m, st);
     if (rs == DSX_OK && q.r.config >= 0) {

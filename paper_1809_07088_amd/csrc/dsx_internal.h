@@ -90,6 +90,7 @@ struct RecombParams {
     const float2* tabK2;
     int32_t n1, n2, n3, nh, S, SF, F, M, first_mono;
     int32_t g0[3], cnt[3];
+    int32_t opitch, ooff;   // output element (i1, i2, i3) at out[(i1 cnt1 + i2) opitch + i3 + ooff]
     int32_t H3min, nH3span;
     int32_t nclass;         // r3 classes (rows of tabH3)
     const int4* work;       // [nwork] (k1, k2, G1, h2a | h2b << 12 | mirror << 24), or k1 < 0
@@ -123,6 +124,7 @@ struct BraggParams {
     const double* sums;     // [M*S][T]
     float* out;             // output box
     int32_t g0[3], cnt[3];
+    int32_t opitch, ooff;   // output element (i1, i2, i3) at out[(i1 cnt1 + i2) opitch + i3 + ooff]
     int32_t n[3];
     int32_t Hlo[3], nH[3];  // H with n H inside the box
     int32_t S, T, M, kind;
@@ -135,7 +137,8 @@ struct BraggParams {
 
 // ---------------------------------------------------------------------------- Lanczos
 struct LanczosParams {
-    const float* in;        // I on the grown box [e1][e2][e3]
+    const float* in;        // I on the grown box [e1][e2][e3], rows of ipitch from ioff
+    int32_t ipitch, ioff;
     float* out;             // [o1][o2][o3]
     const float* wn;        // [s][2m] normalised weights (the same on every axis)
     int32_t e[3], o[3];

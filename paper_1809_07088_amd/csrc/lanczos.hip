@@ -16,11 +16,22 @@
 
 namespace dsx {
 
+// Tile of block b: blocks are dealt round-robin to the 8 XCDs, so XCD x is given
+// the x-th contiguous eighth of the tiles and neighbouring tiles (which share halo
+// rows and output cache lines) meet in one L2.  Returns -1 past the last tile.
+__device__ __forceinline__ int xcd_tile(int b, int ntiles)
+{
+    const int per = (ntiles + 7) / 8;
+    const int t = (b % 8) * per + b / 8;
+    return t < ntiles ? t : -1;
+}
+
 __global__ __launch_bounds__(256) void k_lanczos(LanczosParams P)
 {
     extern __shared__ float sm[];
     const int m2 = 2 * P.m, s = P.s;
-    int b = blockIdx.x;
+    int b = xcd_tile(blockIdx.x, P.nb1 * P.nb2 * P.nb3);
+    if (b < 0) return;
     const int b3 = b % P.nb3; b /= P.nb3;
     const int b2 = b % P.nb2;
     const int b1 = b / P.nb2;
@@ -41,10 +52,10 @@ __global__ __launch_bounds__(256) void k_lanczos(LanczosParams P)
     const int e1a = o1 / s + eo, e1b = (o1 + T1 - 1) / s + eo + m2 - 1;
     for (int e1 = e1a; e1 <= e1b; ++e1) {
         __syncthreads();
-        const float* src = P.in + ((size_t)e1 * P.e[1] + E2lo) * P.e[2] + E3lo;
+        const float* src = P.in + P.ioff + ((size_t)e1 * P.e[1] + E2lo) * P.ipitch + E3lo;
         for (int idx = threadIdx.x; idx < E2n * E3n; idx += blockDim.x) {
             const int r = idx / E3n, c = idx - r * E3n;
-            stg[idx] = src[(size_t)r * P.e[2] + c];
+            stg[idx] = src[(size_t)r * P.ipitch + c];
         }
         __syncthreads();
         // axis 3
@@ -104,7 +115,8 @@ __global__ __launch_bounds__(512, 2) void k_lanczos_ring(LanczosParams P)
     __shared__ float stg[L2 * L3];
     __shared__ float mid[L2 * kRT3];
     const int s = S1 ? 1 : P.s;              // S1: no oversampling, divisions by s vanish
-    int b = blockIdx.x;
+    int b = xcd_tile(blockIdx.x, P.nb1 * P.nb2 * P.nb3);
+    if (b < 0) return;
     const int b3 = b % P.nb3; b /= P.nb3;
     const int b2 = b % P.nb2;
     const int b1 = b / P.nb2;
@@ -123,10 +135,10 @@ __global__ __launch_bounds__(512, 2) void k_lanczos_ring(LanczosParams P)
         soff[k] = -1;
         if (idx < E2n * E3n) {
             const int r = idx / E3n, c = idx - r * E3n;
-            soff[k] = (E2lo + r) * P.e[2] + E3lo + c;
+            soff[k] = (E2lo + r) * P.ipitch + E3lo + c + P.ioff;
         }
     }
-    const size_t plane = (size_t)P.e[1] * P.e[2];
+    const size_t plane = (size_t)P.e[1] * P.ipitch;
     const int e1a = o1 / s + eo, e1b = (o1 + T1 - 1) / s + eo + M2 - 1;
     // two register buffers alternate: the load of plane e1 + 2 is issued right
     // after plane e1 is staged, so every load has two plane iterations to land
@@ -232,7 +244,7 @@ hipError_t launch_lanczos(const LanczosParams& p, hipStream_t st)
         q.t2 = kRT2; q.t3 = kRT3;
         q.nb2 = (p.o[1] + kRT2 - 1) / kRT2;
         q.nb3 = (p.o[2] + kRT3 - 1) / kRT3;
-        const dim3 grid(q.nb1 * q.nb2 * q.nb3);
+        const dim3 grid(8 * ((q.nb1 * q.nb2 * q.nb3 + 7) / 8));
         const bool s1 = p.s == 1;
         if (p.m == 2) {
             if (s1) hipLaunchKernelGGL((k_lanczos_ring<4, true>), grid, dim3(kRThreads), 0, st, q);
@@ -252,7 +264,7 @@ hipError_t launch_lanczos(const LanczosParams& p, hipStream_t st)
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_lanczos, dim3(p.nb1 * p.nb2 * p.nb3), dim3(256), lds, st, p);
+    hipLaunchKernelGGL(k_lanczos, dim3(8 * ((p.nb1 * p.nb2 * p.nb3 + 7) / 8)), dim3(256), lds, st, p);
     return hipGetLastError();
 }
 

@@ -162,11 +162,11 @@ struct RowOut {
 __device__ __forceinline__ RowOut row_out(const RecombParams& P, const BlockWork& w, int i2, int i3b)
 {
     RowOut r;
-    const size_t plane = (size_t)P.cnt[1] * P.cnt[2];
-    r.oplane = reinterpret_cast<char*>(P.out + (size_t)w.i1 * plane);
-    r.mplane = reinterpret_cast<char*>(P.out + (size_t)(P.cnt[0] - 1 - w.i1) * plane);
-    r.o0 = 4u * (uint32_t)(i2 * P.cnt[2] + i3b);
-    r.m0 = 4u * (uint32_t)((P.cnt[1] - 1 - i2) * P.cnt[2] + (P.cnt[2] - 1 - i3b));
+    const size_t plane = (size_t)P.cnt[1] * P.opitch;
+    r.oplane = reinterpret_cast<char*>(P.out + P.ooff + (size_t)w.i1 * plane);
+    r.mplane = reinterpret_cast<char*>(P.out + P.ooff + (size_t)(P.cnt[0] - 1 - w.i1) * plane);
+    r.o0 = 4u * (uint32_t)(i2 * P.opitch + i3b);
+    r.m0 = 4u * (uint32_t)((P.cnt[1] - 1 - i2) * P.opitch + (P.cnt[2] - 1 - i3b));
     r.step = 4u * (uint32_t)P.n3;
     return r;
 }
@@ -877,8 +877,8 @@ __global__ __launch_bounds__(512) void k_recombine_magnetic(RecombParams P)
         }
     }
     if (hcnt > 0) {
-        float* orow = P.out + ((size_t)w.i1 * P.cnt[1] + i2) * P.cnt[2];
-        float* mrow = P.out + ((size_t)(P.cnt[0] - 1 - w.i1) * P.cnt[1] + (P.cnt[1] - 1 - i2)) * P.cnt[2];
+        float* orow = P.out + P.ooff + ((size_t)w.i1 * P.cnt[1] + i2) * P.opitch;
+        float* mrow = P.out + P.ooff + ((size_t)(P.cnt[0] - 1 - w.i1) * P.cnt[1] + (P.cnt[1] - 1 - i2)) * P.opitch;
 #pragma unroll
         for (int h = 0; h < HC; ++h) {
             if (h < hcnt) {
@@ -1064,7 +1064,7 @@ __global__ __launch_bounds__(64) void k_bragg_nuclear(BraggParams P)
         mre /= P.M; mim /= P.M;
         const double I = (sq / P.M - (mre * mre + mim * mim)) * P.scale;
         const int G[3] = {P.n[0] * H[0], P.n[1] * H[1], P.n[2] * H[2]};
-        P.out[((size_t)(G[0] - P.g0[0]) * P.cnt[1] + (G[1] - P.g0[1])) * P.cnt[2] + (G[2] - P.g0[2])] = (float)I;
+        P.out[((size_t)(G[0] - P.g0[0]) * P.cnt[1] + (G[1] - P.g0[1])) * P.opitch + (G[2] - P.g0[2]) + P.ooff] = (float)I;
     }
 }
 
@@ -1080,7 +1080,7 @@ __global__ __launch_bounds__(256) void k_bragg_magnetic(BraggParams P)
     const int j3 = idx % P.nH[2], j2 = (idx / P.nH[2]) % P.nH[1], j1 = idx / (P.nH[2] * P.nH[1]);
     const int H[3] = {P.Hlo[0] + j1, P.Hlo[1] + j2, P.Hlo[2] + j3};
     const int G[3] = {P.n[0] * H[0], P.n[1] * H[1], P.n[2] * H[2]};
-    float* o = P.out + ((size_t)(G[0] - P.g0[0]) * P.cnt[1] + (G[1] - P.g0[1])) * P.cnt[2] + (G[2] - P.g0[2]);
+    float* o = P.out + ((size_t)(G[0] - P.g0[0]) * P.cnt[1] + (G[1] - P.g0[1])) * P.opitch + (G[2] - P.g0[2]) + P.ooff;
     double Q[3];
     for (int c = 0; c < 3; ++c) Q[c] = H[0] * P.recip[c] + H[1] * P.recip[3 + c] + H[2] * P.recip[6 + c];
     const double q2 = Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2];
