@@ -989,14 +989,14 @@ Box grown_box(const Box& b, int mm)
     return ext;
 }
 
-// The filter reads window points from eoff = 1 on: with `off` floats in front of
-// every row, the first window point of each 64-column output tile starts a 128-byte
-// line, so the filter's tiles read whole lines.
+// Rows of the grown box start on 128-byte lines (pitch a multiple of 32 floats):
+// the recombination writes each H3 step of a row as whole lines, and the filter,
+// whose window points start at eoff = 1, cuts its column tiles at multiples of 64
+// in window (input) coordinates, so its tiles read whole lines too.
 constexpr int kExtEoff = 1;
 Layout ext_layout(const Box& ext)
 {
-    const int off = (32 - kExtEoff % 32) % 32;
-    return Layout{(off + ext.cnt[2] + 31) / 32 * 32, off};
+    return Layout{(ext.cnt[2] + 31) / 32 * 32, 0};
 }
 
 size_t ext_elems(const Box& ext) { return (size_t)ext.cnt[0] * ext.cnt[1] * ext_layout(ext).pitch; }

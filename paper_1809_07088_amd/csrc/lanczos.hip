@@ -100,120 +100,128 @@ __global__ __launch_bounds__(256) void k_lanczos(LanczosParams P)
     }
 }
 
-// Register-ring variant for m = M2/2 in {2, 3, 4} and a 32 x 64 output tile:
-// each thread owns 8 fixed output positions of the tile, keeps the last 2m
-// axis-2-filtered values of each in registers, and prefetches the next input plane
-// into registers while the current one is filtered.  Two block barriers per plane.
-constexpr int kRT2 = 32, kRT3 = 64, kRThreads = 512, kRPPT = kRT2 * kRT3 / kRThreads;
+// Register-ring variant for m = M2/2 in {2, 3, 4} and a 32 x 64 output tile.
+// Per input plane: the plane's tile (with halo) is staged in LDS; the axis-3 pass
+// gives each thread a run of four consecutive columns of one row (it reads the
+// M2 + 3 inputs of the run once); the axis-2 pass gives each thread four
+// consecutive rows of one column, whose filtered values join a register ring of
+// the last M2 planes; the axis-1 pass then emits the thread's four outputs of the
+// plane whose window is complete.  The next two input planes are in flight in
+// registers while a plane is filtered.  Three block barriers per plane.
+constexpr int kRT2 = 32, kRT3 = 64, kRThreads = 512, kRRun = 4;
 
 template <int M2, bool S1>
 __global__ __launch_bounds__(512, 2) void k_lanczos_ring(LanczosParams P)
 {
-    constexpr int L2 = kRT2 + M2, L3 = kRT3 + M2;          // staging extent for s = 1
+    constexpr int L2 = kRT2 + M2 - 1;                     // staged rows (s = 1)
+    constexpr int L3 = (kRT3 + M2 - 1 + 3) & ~3;          // staged row pitch (s = 1), 16-byte rows
     constexpr int NSTG = (L2 * L3 + kRThreads - 1) / kRThreads;
     __shared__ float wn_s[16 * M2];
-    __shared__ float stg[L2 * L3];
-    __shared__ float mid[L2 * kRT3];
-    const int s = S1 ? 1 : P.s;              // S1: no oversampling, divisions by s vanish
+    __shared__ __align__(16) float stg[(S1 ? L2 * L3 : 1)];
+    __shared__ __align__(16) float mid[(S1 ? L2 * kRT3 : 1)];
+    static_assert(S1, "the oversampled filter takes the generic kernel");
     int b = xcd_tile(blockIdx.x, P.nb1 * P.nb2 * P.nb3);
     if (b < 0) return;
     const int b3 = b % P.nb3; b /= P.nb3;
     const int b2 = b % P.nb2;
     const int b1 = b / P.nb2;
-    const int o1 = b1 * P.t1, o2 = b2 * kRT2, o3 = b3 * kRT3;
-    const int T1 = min(P.t1, P.o[0] - o1), T2 = min(kRT2, P.o[1] - o2), T3 = min(kRT3, P.o[2] - o3);
     const int eo = P.eoff;
-    const int E2lo = o2 / s + eo, E2n = (o2 + T2 - 1) / s + eo - E2lo + M2;
-    const int E3lo = o3 / s + eo, E3n = (o3 + T3 - 1) / s + eo - E3lo + M2;
-    for (int i = threadIdx.x; i < s * M2; i += blockDim.x) wn_s[i] = P.wn[i];
+    // column tiles are cut at multiples of 64 in input coordinates (o3 + eo)
+    const int o1 = b1 * P.t1, o2 = b2 * kRT2, o3 = max(0, b3 * kRT3 - eo);
+    const int T1 = min(P.t1, P.o[0] - o1), T2 = min(kRT2, P.o[1] - o2);
+    const int T3 = min((b3 + 1) * kRT3 - eo, P.o[2]) - o3;
+    const int E2lo = o2 + eo, E2n = T2 + M2 - 1;
+    const int E3lo = o3 + eo, E3n = T3 + M2 - 1;
+    for (int i = threadIdx.x; i < M2; i += blockDim.x) wn_s[i] = P.wn[i];
 
-    // prefetch addresses: this thread's staging elements
+    // this thread's staging elements (row-major, pitch L3)
     int soff[NSTG];
 #pragma unroll
     for (int k = 0; k < NSTG; ++k) {
         const int idx = threadIdx.x + kRThreads * k;
-        soff[k] = -1;
-        if (idx < E2n * E3n) {
-            const int r = idx / E3n, c = idx - r * E3n;
-            soff[k] = (E2lo + r) * P.ipitch + E3lo + c + P.ioff;
-        }
+        const int r = idx / L3, c = idx - r * L3;
+        soff[k] = (idx < L2 * L3 && r < E2n && c < E3n) ? (E2lo + r) * P.ipitch + E3lo + c + P.ioff : -1;
     }
     const size_t plane = (size_t)P.e[1] * P.ipitch;
-    const int e1a = o1 / s + eo, e1b = (o1 + T1 - 1) / s + eo + M2 - 1;
-    // two register buffers alternate: the load of plane e1 + 2 is issued right
-    // after plane e1 is staged, so every load has two plane iterations to land
+    const int e1a = o1 + eo, e1b = o1 + T1 - 1 + eo + M2 - 1;
     float pa[NSTG], pb[NSTG];
 #pragma unroll
     for (int k = 0; k < NSTG; ++k) {
         pa[k] = soff[k] >= 0 ? P.in[(size_t)e1a * plane + soff[k]] : 0.f;
         pb[k] = (soff[k] >= 0 && e1a + 1 <= e1b) ? P.in[(size_t)(e1a + 1) * plane + soff[k]] : 0.f;
     }
-
-    float ring[M2][kRPPT];
+    // axis-2 / axis-1 ownership: column j3, rows 4 g .. 4 g + 3
+    const int j3 = threadIdx.x & 63;
+    const int g = threadIdx.x >> 6;
+    float ring[M2][kRRun];
 #pragma unroll
     for (int d = 0; d < M2; ++d)
 #pragma unroll
-        for (int k = 0; k < kRPPT; ++k) ring[d][k] = 0.f;
-    const int j3 = threadIdx.x & 63;
-    const int j2b = threadIdx.x >> 6;       // rows j2b + 8 k
+        for (int k = 0; k < kRRun; ++k) ring[d][k] = 0.f;
+    float w[M2];
 
     auto plane_step = [&](int e1, float (&buf)[NSTG]) {
-        __syncthreads();
+        __syncthreads();                      // the previous plane's staging is consumed
 #pragma unroll
-        for (int k = 0; k < NSTG; ++k)
-            if (soff[k] >= 0) stg[threadIdx.x + kRThreads * k] = buf[k];
+        for (int k = 0; k < NSTG; ++k) {
+            const int idx = threadIdx.x + kRThreads * k;
+            if (idx < L2 * L3) stg[idx] = buf[k];
+        }
         if (e1 + 2 <= e1b) {
 #pragma unroll
             for (int k = 0; k < NSTG; ++k)
                 if (soff[k] >= 0) buf[k] = P.in[(size_t)(e1 + 2) * plane + soff[k]];
         }
         __syncthreads();
-        // axis 3: mid[r][j3] for every staged row
-        for (int idx = threadIdx.x; idx < E2n * kRT3; idx += kRThreads) {
-            const int r = idx >> 6, jj = idx & 63;
-            if (jj < T3) {
-                const int i3 = o3 + jj;
-                const float* w = wn_s + (S1 ? 0 : (i3 % s) * M2);
-                const float* x = stg + r * E3n + ((S1 ? i3 : i3 / s) + eo - E3lo);
+#pragma unroll
+        for (int d = 0; d < M2; ++d) w[d] = wn_s[d];
+        // axis 3: runs of four columns
+        for (int t = threadIdx.x; t < E2n * (kRT3 / kRRun); t += kRThreads) {
+            const int r = t / (kRT3 / kRRun), c0 = (t - r * (kRT3 / kRRun)) * kRRun;
+            const float* x = stg + r * L3 + c0;
+            float xv[kRRun + M2 - 1];
+#pragma unroll
+            for (int i = 0; i < kRRun + M2 - 1; ++i) xv[i] = x[i];
+            float4 o;
+            float* op = reinterpret_cast<float*>(&o);
+#pragma unroll
+            for (int q = 0; q < kRRun; ++q) {
                 float acc = 0.f;
 #pragma unroll
-                for (int d = 0; d < M2; ++d) acc += w[d] * x[d];
-                mid[idx] = acc;
+                for (int d = 0; d < M2; ++d) acc += w[d] * xv[q + d];
+                op[q] = acc;
             }
+            *reinterpret_cast<float4*>(mid + r * kRT3 + c0) = o;
         }
         __syncthreads();
-        // axis 2 into the register ring (shift by one plane)
+        // axis 2: four consecutive rows of column j3 into the ring (shift by one plane)
+        float xv[kRRun + M2 - 1];
 #pragma unroll
-        for (int k = 0; k < kRPPT; ++k) {
-            const int j2 = j2b + 8 * k;
-            float v = 0.f;
-            if (j2 < T2 && j3 < T3) {
-                const int i2 = o2 + j2;
-                const float* w = wn_s + (S1 ? 0 : (i2 % s) * M2);
-                const float* x = mid + ((S1 ? i2 : i2 / s) + eo - E2lo) * kRT3 + j3;
-#pragma unroll
-                for (int d = 0; d < M2; ++d) v += w[d] * x[d * kRT3];
-            }
-#pragma unroll
-            for (int d = 0; d < M2 - 1; ++d) ring[d][k] = ring[d + 1][k];
-            ring[M2 - 1][k] = v;
+        for (int i = 0; i < kRRun + M2 - 1; ++i) {
+            const int r = g * kRRun + i;
+            xv[i] = r < E2n ? mid[r * kRT3 + j3] : 0.f;
         }
-        // axis 1: outputs whose window ends at plane e1
-        const int fl = e1 - M2 + 1;       // first input plane of the window
-        if (fl >= e1a) {
-            const int ia = max(o1, (fl - eo) * s), ib = min(o1 + T1, (fl - eo) * s + s);
-            for (int i1 = ia; i1 < ib; ++i1) {
-                const float* w = wn_s + (i1 % s) * M2;
-                float* orow = P.out + ((size_t)i1 * P.o[1] + o2) * P.o[2] + o3;
 #pragma unroll
-                for (int k = 0; k < kRPPT; ++k) {
-                    const int j2 = j2b + 8 * k;
-                    if (j2 < T2 && j3 < T3) {
-                        float acc = 0.f;
+        for (int q = 0; q < kRRun; ++q) {
+            float v = 0.f;
 #pragma unroll
-                        for (int d = 0; d < M2; ++d) acc += w[d] * ring[d][k];
-                        orow[(size_t)j2 * P.o[2] + j3] = acc;
-                    }
+            for (int d = 0; d < M2; ++d) v += w[d] * xv[q + d];
+#pragma unroll
+            for (int d = 0; d < M2 - 1; ++d) ring[d][q] = ring[d + 1][q];
+            ring[M2 - 1][q] = v;
+        }
+        // axis 1: the output plane whose window ends at input plane e1
+        const int i1 = e1 - M2 + 1 - eo;
+        if (i1 >= o1 && j3 < T3) {
+            float* orow = P.out + ((size_t)i1 * P.o[1] + o2) * P.o[2] + o3 + j3;
+#pragma unroll
+            for (int q = 0; q < kRRun; ++q) {
+                const int j2 = g * kRRun + q;
+                if (j2 < T2) {
+                    float acc = 0.f;
+#pragma unroll
+                    for (int d = 0; d < M2; ++d) acc += w[d] * ring[d][q];
+                    orow[(size_t)j2 * P.o[2]] = acc;
                 }
             }
         }
@@ -234,7 +242,7 @@ size_t lanczos_lds_bytes(const LanczosParams& p)
 
 bool lanczos_ring_supported(const LanczosParams& p)
 {
-    return p.s <= 16 && (p.m == 2 || p.m == 3 || p.m == 4);
+    return p.s == 1 && (p.m == 2 || p.m == 3 || p.m == 4);
 }
 
 hipError_t launch_lanczos(const LanczosParams& p, hipStream_t st)
@@ -243,19 +251,11 @@ hipError_t launch_lanczos(const LanczosParams& p, hipStream_t st)
         LanczosParams q = p;
         q.t2 = kRT2; q.t3 = kRT3;
         q.nb2 = (p.o[1] + kRT2 - 1) / kRT2;
-        q.nb3 = (p.o[2] + kRT3 - 1) / kRT3;
+        q.nb3 = (p.o[2] + p.eoff + kRT3 - 1) / kRT3;
         const dim3 grid(8 * ((q.nb1 * q.nb2 * q.nb3 + 7) / 8));
-        const bool s1 = p.s == 1;
-        if (p.m == 2) {
-            if (s1) hipLaunchKernelGGL((k_lanczos_ring<4, true>), grid, dim3(kRThreads), 0, st, q);
-            else hipLaunchKernelGGL((k_lanczos_ring<4, false>), grid, dim3(kRThreads), 0, st, q);
-        } else if (p.m == 3) {
-            if (s1) hipLaunchKernelGGL((k_lanczos_ring<6, true>), grid, dim3(kRThreads), 0, st, q);
-            else hipLaunchKernelGGL((k_lanczos_ring<6, false>), grid, dim3(kRThreads), 0, st, q);
-        } else {
-            if (s1) hipLaunchKernelGGL((k_lanczos_ring<8, true>), grid, dim3(kRThreads), 0, st, q);
-            else hipLaunchKernelGGL((k_lanczos_ring<8, false>), grid, dim3(kRThreads), 0, st, q);
-        }
+        if (p.m == 2) hipLaunchKernelGGL((k_lanczos_ring<4, true>), grid, dim3(kRThreads), 0, st, q);
+        else if (p.m == 3) hipLaunchKernelGGL((k_lanczos_ring<6, true>), grid, dim3(kRThreads), 0, st, q);
+        else hipLaunchKernelGGL((k_lanczos_ring<8, true>), grid, dim3(kRThreads), 0, st, q);
         return hipGetLastError();
     }
     const size_t lds = lanczos_lds_bytes(p);

@@ -151,11 +151,13 @@ struct RowOut {
     char* oplane;
     char* mplane;
     uint32_t o0, m0, step;
+    // streaming stores: the output is not read again here, and keeping it out of
+    // L2 keeps the spectra columns there
     __device__ __forceinline__ void put(int h, float v) const {
-        *reinterpret_cast<float*>(oplane + (o0 + step * (uint32_t)h)) = v;
+        __builtin_nontemporal_store(v, reinterpret_cast<float*>(oplane + (o0 + step * (uint32_t)h)));
     }
     __device__ __forceinline__ void put_mirror(int h, float v) const {
-        *reinterpret_cast<float*>(mplane + (m0 - step * (uint32_t)h)) = v;
+        __builtin_nontemporal_store(v, reinterpret_cast<float*>(mplane + (m0 - step * (uint32_t)h)));
     }
 };
 
