@@ -429,6 +429,205 @@ __global__ __launch_bounds__(256) void k_fft_planes(PlaneParams P)
     }
 }
 
+// ---------------------------------------------------------------------------- register FFTs
+// Power-of-two lengths L <= 32 are transformed by one thread in registers
+// (radix-2 decimation in time, input in bit-reversed order), so a line needs no
+// LDS passes and no barriers.
+__host__ __device__ constexpr int bit_reverse(int i, int L)
+{
+    int r = 0;
+    for (int b = 1; b < L; b <<= 1) { r = (r << 1) | (i & 1); i >>= 1; }
+    return r;
+}
+
+template <int L>
+__device__ __forceinline__ void fft_reg(float2 (&z)[L], const float2* __restrict__ tw)   // tw[t] = e^{+2 pi i t / L}
+{
+#pragma unroll
+    for (int st = 0; (1 << st) < L; ++st) {
+        const int half = 1 << st;
+        const int step = L / (2 * half);
+#pragma unroll
+        for (int k = 0; k < L; k += 2 * half) {
+#pragma unroll
+            for (int j = 0; j < half; ++j) {
+                const float2 a = z[k + j];
+                float2 b = z[k + j + half];
+                if (j * step == L / 4) b = cmuli(b);          // e^{+i pi / 2} = i
+                else if (j != 0) b = cmul(b, tw[j * step]);
+                z[k + j] = cadd(a, b);
+                z[k + j + half] = csub(a, b);
+            }
+        }
+    }
+}
+
+// Axis 1 in place: one thread per column (k2, c), the L1 values of the column in
+// registers.  Columns are contiguous in memory, so every load and store of a wave
+// is one contiguous run.
+template <int L1>
+__global__ __launch_bounds__(256) void k_fft_axis1_reg(Axis1Params P)
+{
+    __shared__ float2 tw[L1];
+    for (int i = threadIdx.x; i < L1; i += blockDim.x) tw[i] = P.tw1[i];
+    __syncthreads();
+    const unsigned per_m = (unsigned)P.n2 * (unsigned)P.cols;
+    const unsigned g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= per_m * (unsigned)P.M) return;
+    const unsigned m = g / per_m, rem = g - m * per_m;
+    float2* base = P.X + (size_t)m * L1 * per_m + rem;
+    float2 z[L1];
+#pragma unroll
+    for (int i = 0; i < L1; ++i) z[i] = base[(size_t)bit_reverse(i, L1) * per_m];
+    fft_reg<L1>(z, tw);
+#pragma unroll
+    for (int k = 0; k < L1; ++k) base[(size_t)k * per_m] = z[k];
+}
+
+// One lattice plane R1 of one site, a chunk of kRegFC fields, for power-of-two
+// n2 = L2, n3 = L3 <= 32:
+//  1. every thread generates the chunk's fields of a few cells (the powers of a
+//     p-run are stepped by one factor u1 each), centred by the FP64 mean, into LDS;
+//  2. one thread per (field, row pair) packs two real rows into one complex line and
+//     transforms it along axis 3 in registers, then separates the two half spectra;
+//  3. one thread per (field, k3) transforms the column along axis 2 in registers and
+//     writes it to the spectra (k3 fastest across the wave: contiguous runs).
+constexpr int kRegFC = 8, kRegThreads = 128;
+
+template <int L2, int L3>
+__global__ __launch_bounds__(kRegThreads) void k_fft_planes_reg(PlaneParams P)
+{
+    constexpr int NH = L3 / 2 + 1;
+    constexpr int RP = L3 + 1;                         // real row pitch (floats)
+    constexpr int FS = ((L2 * RP + 31) / 32) * 32 + 1; // real field stride: lanes of two fields hit other banks
+    constexpr int CP = L2 + 1;                         // complex column pitch
+    constexpr int CS = NH * CP;                        // complex field stride
+    constexpr int UN = (kRegFC * FS > 2 * kRegFC * CS) ? kRegFC * FS : 2 * kRegFC * CS;   // floats
+    __shared__ float2 tw2[L2], tw3[L3];
+    __shared__ float buf[UN];
+    __shared__ float meanf[kRegFC];
+    __shared__ int expo[kRegFC][4];                    // p, q, r, p-run continues the previous field
+
+    int b = blockIdx.x;
+    const int fc = b % P.nfchunk; b /= P.nfchunk;
+    const int R1 = b % P.n1; b /= P.n1;
+    const int mu = b % P.S;
+    const int m = b / P.S;
+    const int ncell = P.n1 * L2 * L3;
+    const int fa = fc * kRegFC;
+    const int nfb = min(P.F, fa + kRegFC) - fa;
+    for (int i = threadIdx.x; i < L2; i += blockDim.x) tw2[i] = P.tw2[i];
+    for (int i = threadIdx.x; i < L3; i += blockDim.x) tw3[i] = P.tw3[i];
+    if (threadIdx.x < nfb) {
+        const int f = fa + threadIdx.x;
+        const int ep = P.mono[3 * f], eq = P.mono[3 * f + 1], er = P.mono[3 * f + 2];
+        const int t = P.kind == 1 ? f : mono_index(ep, eq, er);
+        meanf[threadIdx.x] = (float)(P.sums[(size_t)(m * P.S + mu) * P.T + t] / (double)ncell);
+        expo[threadIdx.x][0] = ep; expo[threadIdx.x][1] = eq; expo[threadIdx.x][2] = er;
+        int cont = 0;
+        if (threadIdx.x > 0 && P.kind != 1) {
+            const int f0 = f - 1;
+            cont = (P.mono[3 * f0] + 1 == ep && P.mono[3 * f0 + 1] == eq && P.mono[3 * f0 + 2] == er) ? 1 : 0;
+        }
+        expo[threadIdx.x][3] = cont;
+    }
+    __syncthreads();
+
+    // 1. generation
+    const size_t plane0 = ((size_t)(m * P.S + mu)) * ncell + (size_t)R1 * L2 * L3;
+    for (int c = threadIdx.x; c < L2 * L3; c += blockDim.x) {
+        const int r2 = c / L3, r3 = c - r2 * L3;
+        const float d = P.occ ? P.occ[plane0 + c] : 1.f;
+        float u0 = 0.f, u1 = 0.f, u2 = 0.f;
+        if (P.vec) {
+            const float* u = P.vec + 3 * (plane0 + c);
+            u0 = u[0]; u1 = u[1]; u2 = u[2];
+        }
+        float v = 1.f;
+        for (int fb = 0; fb < nfb; ++fb) {
+            float x;
+            if (P.kind == 1) {
+                const int comp = fa + fb;
+                x = (comp == 0 ? u0 : comp == 1 ? u1 : u2) * d;
+            } else {
+                if (expo[fb][3]) {
+                    v *= u0;
+                } else {
+                    v = 1.f;
+                    for (int k = 0; k < expo[fb][0]; ++k) v *= u0;
+                    for (int k = 0; k < expo[fb][1]; ++k) v *= u1;
+                    for (int k = 0; k < expo[fb][2]; ++k) v *= u2;
+                }
+                x = v * d;
+            }
+            buf[fb * FS + r2 * RP + r3] = x - meanf[fb];
+        }
+    }
+    __syncthreads();
+
+    // 2. axis 3: two real rows per complex line, then the two half spectra
+    constexpr int NP = L2 / 2;
+    const int t = threadIdx.x;
+    const int fb3 = t / NP, j = t - fb3 * NP;
+    const bool act3 = t < kRegFC * NP && fb3 < nfb;
+    float2 z[L3];
+    if (act3) {
+        const float* r0 = buf + fb3 * FS + (2 * j) * RP;
+#pragma unroll
+        for (int i = 0; i < L3; ++i) z[i] = make_float2(r0[bit_reverse(i, L3)], r0[RP + bit_reverse(i, L3)]);
+        fft_reg<L3>(z, tw3);
+    }
+    __syncthreads();                      // the real rows are no longer needed
+    float2* cb = reinterpret_cast<float2*>(buf);
+    if (act3) {
+        float2* col = cb + fb3 * CS + 2 * j;
+#pragma unroll
+        for (int k = 0; k < NH; ++k) {
+            const float2 zk = z[k], zm = z[(L3 - k) % L3];
+            col[k * CP] = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+            col[k * CP + 1] = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
+        }
+    }
+    __syncthreads();
+
+    // 3. axis 2, written to the spectra
+    const int SF = P.S * P.F;
+    float2* out = P.X + ((size_t)(m * P.n1 + R1) * L2) * SF * NH + (size_t)(mu * P.F + fa) * NH;
+    for (int it = threadIdx.x; it < nfb * NH; it += blockDim.x) {
+        const int fb = it / NH, k = it - fb * NH;
+        const float2* col = cb + fb * CS + k * CP;
+        float2 y[L2];
+#pragma unroll
+        for (int i = 0; i < L2; ++i) y[i] = col[bit_reverse(i, L2)];
+        fft_reg<L2>(y, tw2);
+#pragma unroll
+        for (int k2 = 0; k2 < L2; ++k2) out[(size_t)k2 * SF * NH + it] = y[k2];
+    }
+}
+
+bool fft_reg_supported(int n) { return n == 8 || n == 16 || n == 32; }
+
+template <int L2, int L3>
+static hipError_t launch_planes_reg(const PlaneParams& p, hipStream_t st)
+{
+    PlaneParams q = p;
+    q.fchunk = kRegFC;
+    q.nfchunk = (p.F + kRegFC - 1) / kRegFC;
+    hipLaunchKernelGGL((k_fft_planes_reg<L2, L3>), dim3(q.M * q.S * q.n1 * q.nfchunk), dim3(kRegThreads), 0, st, q);
+    return hipGetLastError();
+}
+
+template <int L2>
+static hipError_t launch_planes_reg2(const PlaneParams& p, hipStream_t st)
+{
+    switch (p.n3) {
+        case 8: return launch_planes_reg<L2, 8>(p, st);
+        case 16: return launch_planes_reg<L2, 16>(p, st);
+        case 32: return launch_planes_reg<L2, 32>(p, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 size_t planes_lds_bytes(const PlaneParams& p)
 {
     return sizeof(float2) * (size_t)(p.n2 + p.n3 + 2 * p.fchunk * p.buf_elems);
@@ -436,6 +635,13 @@ size_t planes_lds_bytes(const PlaneParams& p)
 
 hipError_t launch_fft_planes(const PlaneParams& p, hipStream_t st)
 {
+    if (fft_reg_supported(p.n2) && fft_reg_supported(p.n3)) {
+        switch (p.n2) {
+            case 8: return launch_planes_reg2<8>(p, st);
+            case 16: return launch_planes_reg2<16>(p, st);
+            default: return launch_planes_reg2<32>(p, st);
+        }
+    }
     const size_t lds = planes_lds_bytes(p);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)k_fft_planes,
@@ -491,6 +697,14 @@ size_t axis1_lds_bytes(const Axis1Params& p)
 
 hipError_t launch_fft_axis1(const Axis1Params& p, hipStream_t st)
 {
+    if (fft_reg_supported(p.n1)) {
+        const unsigned total = (unsigned)p.M * p.n2 * p.cols;
+        const dim3 grid((total + 255) / 256);
+        if (p.n1 == 8) hipLaunchKernelGGL(k_fft_axis1_reg<8>, grid, dim3(256), 0, st, p);
+        else if (p.n1 == 16) hipLaunchKernelGGL(k_fft_axis1_reg<16>, grid, dim3(256), 0, st, p);
+        else hipLaunchKernelGGL(k_fft_axis1_reg<32>, grid, dim3(256), 0, st, p);
+        return hipGetLastError();
+    }
     const size_t lds = axis1_lds_bytes(p);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)k_fft_axis1,

@@ -211,3 +211,18 @@ def test_every_recombination_form(monkeypatch, variant, order, M, parity):
     I = gpu_intensity(m)
     ref = O.intensity(m, O.grid_points(m.g0, m.count), order).reshape(m.count)
     assert rel_l2(I, ref) <= TOL
+
+
+@pytest.mark.parametrize("n,kind,order", [((16, 8, 32), synth.NUCLEAR, 3), ((8, 32, 16), synth.NUCLEAR, 0),
+                                          ((8, 16, 8), synth.MAGNETIC, 0), ((32, 32, 8), synth.NUCLEAR, 5)])
+def test_power_of_two_edges_register_transforms(n, kind, order):
+    """Edges 8, 16, 32 take the register-resident transforms (occupancy, Taylor
+    p-runs and spin components all pass through them)."""
+    m = synth.random_model(800 + sum(n), n=n, S=2, M=2, order=order, kind=kind,
+                           cell=None if kind == synth.NUCLEAR else [6.0, 7.0, 8.0, 90.0, 90.0, 90.0])
+    m.g0 = tuple(-(v // 2) - 1 for v in n)      # every residue k, ragged at both ends
+    m.count = tuple(v + 3 for v in n)
+    say(f"register transforms n={n} kind={kind} order={order}")
+    I = gpu_intensity(m)
+    ref = O.intensity(m, O.grid_points(m.g0, m.count), order if kind == synth.NUCLEAR else None).reshape(m.count)
+    assert rel_l2(I, ref) <= TOL
