@@ -138,7 +138,7 @@ def bench_ensemble(dsx, torch, dev, steps, warmup, lm=2):
     """Batched ensemble (8 models x 8 configurations, edges from {16,20,24,32,40}, 1-4
     sites, Taylor order 6, |h|,|k|,|l| <= 4, Lanczos filter): one graph replay against the
     plain path that calls noise_filter model by model.  Both steps first upload every
-    configuration again (device-to-device set_sites), so both recompute all spectra."""
+    configuration again (stream-ordered device copies), so both recompute all spectra."""
     import synth
     models = synth.ensemble()
     hs, outs, sites = [], [], []
@@ -160,7 +160,7 @@ def bench_ensemble(dsx, torch, dev, steps, warmup, lm=2):
     def upload():
         for h, st in zip(hs, sites):
             for c, (occ, disp) in enumerate(st):
-                h.set_sites(c, occ, disp)
+                h.set_sites_async(c, occ, disp)
 
     def timed(fn):
         for _ in range(warmup):
@@ -387,7 +387,7 @@ def main():
     info = dsx.plan_query(cell=model.cell, n=n, frac=model.frac, b=model.b, taylor_order=N, n_configs=M)
 
     def step():
-        h.set_sites(0, None, disp_dev)
+        h.set_sites_async(0, None, disp_dev)     # stream-ordered device copy of the sites
         h.noise_filter(lm, 1, out)
 
     if args.copy_probe:
@@ -441,12 +441,12 @@ def main():
 
     # unfiltered path (compute_intensity) for context
     for _ in range(2):
-        h.set_sites(0, None, disp_dev)
+        h.set_sites_async(0, None, disp_dev)
         h.compute_intensity(out)
     torch.cuda.synchronize()
     u0 = time.perf_counter()
     for _ in range(args.steps):
-        h.set_sites(0, None, disp_dev)
+        h.set_sites_async(0, None, disp_dev)
         h.compute_intensity(out)
     torch.cuda.synchronize()
     unfiltered = voxels / ((time.perf_counter() - u0) / args.steps)
@@ -460,12 +460,12 @@ def main():
             hm.set_grid(model.g0, count)
             hm.set_sites(0, None, disp_dev)
             for _ in range(2):
-                hm.set_sites(0, None, disp_dev)
+                hm.set_sites_async(0, None, disp_dev)
                 hm.compute_intensity(out)
             torch.cuda.synchronize()
             s0 = time.perf_counter()
             for _ in range(args.steps):
-                hm.set_sites(0, None, disp_dev)
+                hm.set_sites_async(0, None, disp_dev)
                 hm.compute_intensity(out)
             torch.cuda.synchronize()
             sweep[str(NN)] = round(voxels / ((time.perf_counter() - s0) / args.steps), 1)

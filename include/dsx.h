@@ -119,6 +119,16 @@ dsx_status dsx_set_sites(dsx_model m, int32_t config, const float* occ, const fl
                          const float* spin, int32_t where);
 
 /*
+ * Stream-ordered form of dsx_set_sites for device arrays: the copies are enqueued
+ * on hip_stream after all earlier work of the model (on any stream), so a loop of
+ * set_sites_async + compute calls never waits on the host.  The caller keeps the
+ * source arrays unchanged until the copies have run on hip_stream.  Not for models
+ * owned by a server (DSX_ERR_STATE).
+ */
+dsx_status dsx_set_sites_async(dsx_model m, int32_t config, const float* occ, const float* disp,
+                               const float* spin, void* hip_stream);
+
+/*
  * Output box: the integer points G with g0[a] <= G_a < g0[a] + count[a], count >= 1.
  */
 dsx_status dsx_set_grid(dsx_model m, const int32_t g0[3], const int32_t count[3]);

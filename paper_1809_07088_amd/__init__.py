@@ -47,7 +47,7 @@ class KernelStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
 
 
-EXPORTS = ("dsx_plan_query", "dsx_create_model", "dsx_set_sites", "dsx_set_grid",
+EXPORTS = ("dsx_plan_query", "dsx_create_model", "dsx_set_sites", "dsx_set_sites_async", "dsx_set_grid",
            "dsx_compute_intensity", "dsx_noise_filter", "dsx_destroy_model", "dsx_last_error",
            "dsx_version", "dsx_profile_enable", "dsx_profile_read", "dsx_profile_reset",
            "dsx_batch_create", "dsx_batch_run", "dsx_batch_destroy", "dsx_autotune",
@@ -87,6 +87,8 @@ def lib():
         L.dsx_plan_query.argtypes = [ctypes.POINTER(ModelDesc), ctypes.POINTER(PlanInfo)]
         L.dsx_create_model.argtypes = [ctypes.POINTER(ModelDesc), ctypes.POINTER(P)]
         L.dsx_set_sites.argtypes = [P, i32, P, P, P, i32]
+        L.dsx_set_sites_async.argtypes = [P, i32, P, P, P, P]
+        L.dsx_set_sites_async.restype = i32
         L.dsx_set_grid.argtypes = [P, P, P]
         L.dsx_compute_intensity.argtypes = [P, P, i32, P]
         L.dsx_noise_filter.argtypes = [P, i32, i32, P, i32, P]
@@ -197,6 +199,15 @@ def set_sites(model, config, occ=None, disp=None, spin=None):
     _check(lib().dsx_set_sites(model, int(config), ptrs[0][0], ptrs[1][0], ptrs[2][0], where))
 
 
+def set_sites_async(model, config, occ=None, disp=None, spin=None, stream=None):
+    """Stream-ordered site upload from device tensors (kept unchanged until it has run)."""
+    ptrs = [_ptr_where(a) for a in (occ, disp, spin)]
+    if any(w == HOST for (_, w, _) in ptrs):
+        raise ValueError("set_sites_async takes device tensors")
+    _check(lib().dsx_set_sites_async(model, int(config), ptrs[0][0], ptrs[1][0], ptrs[2][0],
+                                     _stream_handle(stream)))
+
+
 def set_grid(model, g0, count):
     g = np.ascontiguousarray(g0, dtype=np.int32)
     c = np.ascontiguousarray(count, dtype=np.int32)
@@ -284,6 +295,9 @@ class Model:
 
     def set_sites(self, config, occ=None, disp=None, spin=None):
         set_sites(self.handle, config, occ, disp, spin)
+
+    def set_sites_async(self, config, occ=None, disp=None, spin=None, stream=None):
+        set_sites_async(self.handle, config, occ, disp, spin, stream)
 
     def set_grid(self, g0, count):
         self.g0, self.count = tuple(int(v) for v in g0), tuple(int(v) for v in count)

@@ -929,6 +929,30 @@ dsx_status dsx_set_sites(dsx_model m, int32_t config, const float* occ, const fl
     return DSX_OK;
 }
 
+dsx_status dsx_set_sites_async(dsx_model m, int32_t config, const float* occ, const float* disp,
+                               const float* spin, void* hip_stream)
+{
+    dsx_status s = check_model(m);
+    if (s != DSX_OK) return s;
+    if (config < 0 || config >= m->M) return fail(DSX_ERR_ARG, "config out of range");
+    if (m->has_occ && !occ) return fail(DSX_ERR_ARG, "occ is required (has_occ != 0)");
+    const float* vec = m->kind == DSX_MAGNETIC ? spin : disp;
+    const bool need_vec = m->kind == DSX_MAGNETIC || m->order > 0;
+    if (need_vec && !vec)
+        return fail(DSX_ERR_ARG, m->kind == DSX_MAGNETIC ? "spin is required" : "disp is required (taylor_order > 0)");
+    if (m->server) return fail(DSX_ERR_STATE, "the model belongs to a server: its requests carry the sites");
+    hipStream_t st = (hipStream_t)hip_stream;
+    if ((s = follow(m, st)) != DSX_OK) return s;     // after every earlier use of the inputs
+    const size_t per = (size_t)m->S * m->ncell;
+    if (m->has_occ)
+        HIPCHK(m, hipMemcpyAsync(m->d_occ + per * config, occ, per * sizeof(float), hipMemcpyDeviceToDevice, st));
+    if (need_vec)
+        HIPCHK(m, hipMemcpyAsync(m->d_vec + 3 * per * config, vec, 3 * per * sizeof(float), hipMemcpyDeviceToDevice, st));
+    m->set[config] = 1;
+    m->dirty = true;
+    return DSX_OK;
+}
+
 dsx_status dsx_set_grid(dsx_model m, const int32_t g0[3], const int32_t count[3])
 {
     dsx_status s = check_model(m);

@@ -226,3 +226,23 @@ def test_power_of_two_edges_register_transforms(n, kind, order):
     I = gpu_intensity(m)
     ref = O.intensity(m, O.grid_points(m.g0, m.count), order if kind == synth.NUCLEAR else None).reshape(m.count)
     assert rel_l2(I, ref) <= TOL
+
+
+def test_set_sites_async_matches_set_sites():
+    import torch
+    m = synth.random_model(900, n=(6, 8, 5), S=3, M=2, order=4)
+    m2 = synth.random_model(901, n=(6, 8, 5), S=3, M=2, order=4)
+    say("set_sites_async")
+    h = to_dsx(m)
+    out = torch.empty(tuple(m.count), device="cuda")
+    h.compute_intensity(out)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        for c in range(m.n_configs):
+            h.set_sites_async(c, torch.from_numpy(m2.occ[c]).cuda(), torch.from_numpy(m2.disp[c]).cuda(), stream=s)
+    h.compute_intensity(out)                       # the default stream: ordered after the copies
+    torch.cuda.synchronize()
+    m2.frac, m2.b = m.frac, m.b
+    ref = gpu_intensity(m2)
+    assert np.array_equal(out.cpu().numpy(), ref)
+    h.close()
