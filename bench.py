@@ -38,6 +38,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "diffuse-intensity voxels/s at ≤1e-5 rel L2 vs FP64; p50/p99 request latency"
 TRAFFIC_MD = os.path.join(ROOT, "profiles", "recombine_displacive32_order8_traffic.md")
+KTRACE_MD = os.path.join(ROOT, "profiles", "kernels_displacive32_order8.md")
 COPY_PROBE_BYTES = 256 << 20     # plain device copy of known size, read + write
 
 
@@ -87,6 +88,30 @@ def summarize_pmc(fetch_dir, write_dir, out_md, command):
         f.write("| WRITE_SIZE | %.0f | %.0f |\n\n" % (sum(kw[0]) / len(kw[0]), w_avg))
         f.write("```json\n%s\n```\n" % json.dumps(rec))
     return rec
+
+
+def summarize_ktrace(trace_dir, out_md, command):
+    """Kernel-time summary from a rocprofv3 --kernel-trace --stats folder: per kernel,
+    calls and average / min / max duration (the recombination's average must agree
+    with the benchmark's HIP-event launch time)."""
+    paths = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
+    if not paths:
+        raise SystemExit("summarize: no kernel_stats.csv under " + trace_dir)
+    rows = list(csv.DictReader(open(paths[0])))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    with open(out_md, "w") as f:
+        f.write("# Kernel time, displacive 32^3 fcc, Taylor order 8, 513^3 box, Lanczos m = 2\n\n")
+        f.write("rocprofv3 kernel trace of the benchmark's filtered steps only (`--only-steps`: "
+                "set_sites_async + noise_filter per step, plus the plain device copy used as the "
+                "PMC probe).  MI355X, one GPU.\n\nCommand (run from /tmp with TMPDIR=/tmp, "
+                "R = repository root):\n\n```\n%s\n```\n\n" % command)
+        f.write("| kernel | calls | average (us) | min (us) | max (us) | share of GPU time |\n"
+                "|---|---|---|---|---|---|\n")
+        for r in rows:
+            f.write("| `%s` | %s | %.1f | %.1f | %.1f | %.2f %% |\n" % (
+                r["Name"], r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
+                float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+    return len(rows)
 
 
 def stored_traffic():
@@ -346,6 +371,11 @@ def main():
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the traffic summary from two rocprofv3 --pmc output folders and exit")
     ap.add_argument("--pmc-command", default="", help="command line recorded in the traffic summary")
+    ap.add_argument("--summarize-ktrace", metavar="TRACE_DIR",
+                    help="write the kernel-time summary from a rocprofv3 --kernel-trace --stats folder and exit")
+    ap.add_argument("--only-steps", action="store_true",
+                    help="time the filtered steps only (no unfiltered pass, sweep, ensemble, serving or "
+                         "CPU baseline): the run the profiles are taken from")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble comparison")
     ap.add_argument("--ensemble-only", action="store_true",
                     help="time only the batched ensemble (for kernel traces of the graph path)")
@@ -353,6 +383,9 @@ def main():
                     help="length of the Poisson request trace of the serving comparison (0: skip)")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving comparison")
     args = ap.parse_args()
+    if args.summarize_ktrace:
+        print(summarize_ktrace(args.summarize_ktrace, KTRACE_MD, args.pmc_command))
+        return
     if args.summarize_pmc:
         print(json.dumps(summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], TRAFFIC_MD,
                                        args.pmc_command)))
@@ -439,18 +472,22 @@ def main():
                  "achieved_hbm_GBs": round(gbs, 1), "achieved_TFLOPs": round(tflops, 3)})
     kernels = {k: {"launches": v[0], "avg_ms": round(v[1] / max(v[0], 1), 4)} for k, v in kstats.items()}
 
+    if args.only_steps:
+        args.no_cpu_baseline, args.sweep, args.no_ensemble, args.serve_seconds = True, False, True, 0.0
     # unfiltered path (compute_intensity) for context
-    for _ in range(2):
+    unfiltered = None
+    for _ in range(0 if args.only_steps else 2):
         h.set_sites_async(0, None, disp_dev)
         h.compute_intensity(out)
     torch.cuda.synchronize()
-    u0 = time.perf_counter()
-    for _ in range(args.steps):
-        h.set_sites_async(0, None, disp_dev)
-        h.compute_intensity(out)
-    torch.cuda.synchronize()
-    unfiltered = voxels / ((time.perf_counter() - u0) / args.steps)
-    I_gpu = out.cpu().numpy()
+    if not args.only_steps:
+        u0 = time.perf_counter()
+        for _ in range(args.steps):
+            h.set_sites_async(0, None, disp_dev)
+            h.compute_intensity(out)
+        torch.cuda.synchronize()
+        unfiltered = voxels / ((time.perf_counter() - u0) / args.steps)
+        I_gpu = out.cpu().numpy()
 
     sweep = None
     if args.sweep:
@@ -514,7 +551,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "parity": parity,
-        "unfiltered_voxels_per_s": round(unfiltered, 1),
+        "unfiltered_voxels_per_s": None if unfiltered is None else round(unfiltered, 1),
         "kernels": kernels,
     }
     if sweep is not None:
