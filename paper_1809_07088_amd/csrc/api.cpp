@@ -86,14 +86,24 @@ hipError_t timed(const char* name, hipStream_t st, Fn fn)
 struct Box {
     int g0[3];
     int cnt[3];
+    int half = 0;   // symmetric box stored as its planes G1 <= 0 only (I(-G) = I(G))
     bool operator<(const Box& o) const {
         for (int a = 0; a < 3; ++a) {
             if (g0[a] != o.g0[a]) return g0[a] < o.g0[a];
             if (cnt[a] != o.cnt[a]) return cnt[a] < o.cnt[a];
         }
-        return false;
+        return half < o.half;
     }
 };
+
+bool symmetric_box(const Box& b)
+{
+    for (int a = 0; a < 3; ++a)
+        if (b.cnt[a] % 2 == 0 || b.g0[a] != -(b.cnt[a] - 1) / 2) return false;
+    return true;
+}
+
+int stored_planes(const Box& b) { return b.half ? (b.cnt[0] + 1) / 2 : b.cnt[0]; }
 
 long floordiv_l(long a, long b) { long q = a / b; if ((a % b) != 0 && a < 0) --q; return q; }
 long ceildiv_l(long a, long b) { return -floordiv_l(-a, b); }
@@ -422,9 +432,8 @@ dsx_status tables_for(dsx_model m, const Box& bx, DeviceTables** out)
     if ((size_t)m->nclass * t.nH3span * sizeof(float2) > 32 * 1024)
         return fail(DSX_ERR_UNSUPPORTED, "output box too long along axis 3 for this supercell");
     const int h2per = std::max(1, maxT / per_h2);
-    bool friedel = true;
-    for (int a = 0; a < 3; ++a)
-        if (bx.cnt[a] % 2 == 0 || bx.g0[a] != -(bx.cnt[a] - 1) / 2) friedel = false;
+    const bool friedel = symmetric_box(bx);
+    if (bx.half && !friedel) return fail(DSX_ERR_STATE, "half storage needs a symmetric box");
     std::vector<std::pair<long long, int4>> items, items2;
     int maxrows = 1;
     for (int k1 = 0; k1 < n1; ++k1) {
@@ -449,7 +458,7 @@ dsx_status tables_for(dsx_model m, const Box& bx, DeviceTables** out)
                         if (k2 > km2) continue;
                         mirror = k2 < km2 ? 1 : 0;
                     } else {
-                        mirror = 1;
+                        mirror = bx.half ? 0 : 1;   // half storage keeps the planes G1 <= 0 only
                     }
                 }
                 planes.push_back({j1, mirror});
@@ -615,6 +624,7 @@ dsx_status plan_recombine(dsx_model m, const Box& bx, float* out, const Layout& 
         const int hi = (int)floordiv_l((long)bx.g0[a] + bx.cnt[a] - 1, m->n[a]);
         q.nH[a] = std::max(0, hi - q.Hlo[a] + 1);
     }
+    if (bx.half) q.nH[0] = std::max(0, std::min(q.nH[0], 1 - q.Hlo[0]));   // planes G1 <= 0
     q.S = m->S; q.T = m->T; q.M = m->M; q.kind = m->kind;
     q.scale = C / m->normN;
     q.site = m->d_site;
@@ -1013,6 +1023,15 @@ Box grown_box(const Box& b, int mm)
     return ext;
 }
 
+// The box the filter reads: the output box grown by the window, stored as its half
+// G1 <= 0 when it is symmetric about G = 0.
+Box filter_box(const Box& b, int mm)
+{
+    Box e = grown_box(b, mm);
+    e.half = symmetric_box(e) ? 1 : 0;
+    return e;
+}
+
 // Rows of the grown box start on 128-byte lines (pitch a multiple of 32 floats):
 // the recombination writes each H3 step of a row as whole lines, and the filter,
 // whose window points start at eoff = 1, cuts its column tiles at multiples of 64
@@ -1023,12 +1042,12 @@ Layout ext_layout(const Box& ext)
     return Layout{(ext.cnt[2] + 31) / 32 * 32, 0};
 }
 
-size_t ext_elems(const Box& ext) { return (size_t)ext.cnt[0] * ext.cnt[1] * ext_layout(ext).pitch; }
+size_t ext_elems(const Box& ext) { return (size_t)stored_planes(ext) * ext.cnt[1] * ext_layout(ext).pitch; }
 
 // Everything the filter needs that allocates or uploads (never inside a capture).
 dsx_status prepare_filter(dsx_model m, int mm, int sv)
 {
-    const Box ext = grown_box(m->box, mm);
+    const Box ext = filter_box(m->box, mm);
     const size_t ext_vox = ext_elems(ext);
     if (m->ext_cap < ext_vox) {
         if (m->pins) return fail(DSX_ERR_BUSY, "the grown box would outgrow a buffer a batch has recorded");
@@ -1075,13 +1094,14 @@ dsx_status prepare_intensity(dsx_model m)
 dsx_status enqueue_filter(dsx_model m, int mm, int sv, float* dout, hipStream_t st, bool force)
 {
     dsx_status s;
-    const Box ext = grown_box(m->box, mm);
+    const Box ext = filter_box(m->box, mm);
     if ((s = ensure_spectra(m, st, force)) != DSX_OK) return s;
     const Layout el = ext_layout(ext);
     if ((s = run_box(m, ext, m->d_ext, el, st)) != DSX_OK) return s;
     LanczosParams lp{};
     lp.in = m->d_ext; lp.out = dout; lp.wn = m->lanczos_w[std::make_pair(mm, sv)];
     lp.ipitch = el.pitch; lp.ioff = el.off;
+    lp.ihalf = stored_planes(ext);
     for (int a = 0; a < 3; ++a) { lp.e[a] = ext.cnt[a]; lp.o[a] = sv * m->box.cnt[a]; }
     lp.m = mm; lp.s = sv;
     lp.eoff = kExtEoff;
@@ -1089,6 +1109,8 @@ dsx_status enqueue_filter(dsx_model m, int mm, int sv, float* dout, hipStream_t 
     lp.t2 = 32;
     while (lp.t2 > 1 && lanczos_lds_bytes(lp) > 150 * 1024) lp.t2 /= 2;
     while (lp.t3 > 8 && lanczos_lds_bytes(lp) > 150 * 1024) lp.t3 /= 2;
+    // s = 1 on a symmetric box: compute the planes G1 <= 0 and write each also at -G
+    lp.ohalf = (sv == 1 && symmetric_box(m->box)) ? (lp.o[0] + 1) / 2 : 0;
     lp.nb1 = (lp.o[0] + lp.t1 - 1) / lp.t1;
     lp.nb2 = (lp.o[1] + lp.t2 - 1) / lp.t2;
     lp.nb3 = (lp.o[2] + lp.t3 - 1) / lp.t3;
@@ -1243,7 +1265,7 @@ dsx_status dsx_autotune(dsx_model m, int32_t lanczos_m, void* hip_stream)
     // recombination form (the parity form only exists for nuclear models whose r3 are halves)
     best = -1.f;
     int best_v = 0;
-    const Box b = filt ? grown_box(m->box, lanczos_m) : m->box;
+    const Box b = filt ? filter_box(m->box, lanczos_m) : m->box;
     float* dst = filt ? m->d_ext : scratch;
     for (int cand : {0, 2, 3}) {
         if (cand != 0 && m->kind != DSX_NUCLEAR) continue;
@@ -1526,7 +1548,7 @@ size_t request_workspace(dsx_model m, int lm, size_t* x_bytes)
 {
     *x_bytes = Arena::round(m->spectrum_bytes);
     size_t ws = *x_bytes + Arena::round(m->partial_bytes);
-    if (lm >= 2) ws += Arena::round(ext_elems(grown_box(m->box, lm)) * sizeof(float));
+    if (lm >= 2) ws += Arena::round(ext_elems(filter_box(m->box, lm)) * sizeof(float));
     return ws;
 }
 
@@ -1542,7 +1564,7 @@ dsx_status launch_request(dsx_server s, const Request& q, hipStream_t st, hipEve
     m->d_partial = reinterpret_cast<double*>(base + q.x_bytes);
     if (lm >= 2) {
         m->d_ext = reinterpret_cast<float*>(base + q.x_bytes + Arena::round(m->partial_bytes));
-        m->ext_cap = ext_elems(grown_box(m->box, lm));
+        m->ext_cap = ext_elems(filter_box(m->box, lm));
     }
     rs = follow(m, st);
     if (rs == DSX_OK && q.r.config >= 0) {

@@ -139,6 +139,10 @@ struct BraggParams {
 struct LanczosParams {
     const float* in;        // I on the grown box [e1][e2][e3], rows of ipitch from ioff
     int32_t ipitch, ioff;
+    int32_t ihalf;          // planes stored; plane e1 >= ihalf is read as the mirror of plane
+                            // e[0] - 1 - e1 (I(-G) = I(G) on a symmetric box)
+    int32_t ohalf;          // 0, or the output planes computed on a symmetric output box: each
+                            // is also written mirrored (the filter commutes with G -> -G)
     float* out;             // [o1][o2][o3]
     const float* wn;        // [s][2m] normalised weights (the same on every axis)
     int32_t e[3], o[3];

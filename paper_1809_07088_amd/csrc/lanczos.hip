@@ -52,10 +52,13 @@ __global__ __launch_bounds__(256) void k_lanczos(LanczosParams P)
     const int e1a = o1 / s + eo, e1b = (o1 + T1 - 1) / s + eo + m2 - 1;
     for (int e1 = e1a; e1 <= e1b; ++e1) {
         __syncthreads();
-        const float* src = P.in + P.ioff + ((size_t)e1 * P.e[1] + E2lo) * P.ipitch + E3lo;
+        const bool mir = e1 >= P.ihalf;
+        const size_t pbase = (size_t)(mir ? P.e[0] - 1 - e1 : e1) * P.e[1];
         for (int idx = threadIdx.x; idx < E2n * E3n; idx += blockDim.x) {
             const int r = idx / E3n, c = idx - r * E3n;
-            stg[idx] = src[(size_t)r * P.ipitch + c];
+            int row = E2lo + r, colx = E3lo + c;
+            if (mir) { row = P.e[1] - 1 - row; colx = P.e[2] - 1 - colx; }
+            stg[idx] = P.in[P.ioff + (pbase + row) * P.ipitch + colx];
         }
         __syncthreads();
         // axis 3
@@ -128,28 +131,37 @@ __global__ __launch_bounds__(512, 2) void k_lanczos_ring(LanczosParams P)
     const int eo = P.eoff;
     // column tiles are cut at multiples of 64 in input coordinates (o3 + eo)
     const int o1 = b1 * P.t1, o2 = b2 * kRT2, o3 = max(0, b3 * kRT3 - eo);
-    const int T1 = min(P.t1, P.o[0] - o1), T2 = min(kRT2, P.o[1] - o2);
+    const int T1 = min(P.t1, (P.ohalf ? P.ohalf : P.o[0]) - o1), T2 = min(kRT2, P.o[1] - o2);
     const int T3 = min((b3 + 1) * kRT3 - eo, P.o[2]) - o3;
     const int E2lo = o2 + eo, E2n = T2 + M2 - 1;
     const int E3lo = o3 + eo, E3n = T3 + M2 - 1;
     for (int i = threadIdx.x; i < M2; i += blockDim.x) wn_s[i] = P.wn[i];
 
-    // this thread's staging elements (row-major, pitch L3)
-    int soff[NSTG];
+    // this thread's staging elements (row-major, pitch L3), as offsets within a stored
+    // plane and within the mirrored plane (rows and columns reversed)
+    int soff[NSTG], moff[NSTG];
 #pragma unroll
     for (int k = 0; k < NSTG; ++k) {
         const int idx = threadIdx.x + kRThreads * k;
         const int r = idx / L3, c = idx - r * L3;
-        soff[k] = (idx < L2 * L3 && r < E2n && c < E3n) ? (E2lo + r) * P.ipitch + E3lo + c + P.ioff : -1;
+        const bool in = idx < L2 * L3 && r < E2n && c < E3n;
+        soff[k] = in ? (E2lo + r) * P.ipitch + E3lo + c + P.ioff : -1;
+        moff[k] = in ? (P.e[1] - 1 - E2lo - r) * P.ipitch + (P.e[2] - 1 - E3lo - c) + P.ioff : -1;
     }
     const size_t plane = (size_t)P.e[1] * P.ipitch;
     const int e1a = o1 + eo, e1b = o1 + T1 - 1 + eo + M2 - 1;
+    auto fetch = [&](int e1, float (&buf)[NSTG]) {
+        const bool mir = e1 >= P.ihalf;
+        const float* src = P.in + (size_t)(mir ? P.e[0] - 1 - e1 : e1) * plane;
+#pragma unroll
+        for (int k = 0; k < NSTG; ++k)
+            if (soff[k] >= 0) buf[k] = src[mir ? moff[k] : soff[k]];
+    };
     float pa[NSTG], pb[NSTG];
 #pragma unroll
-    for (int k = 0; k < NSTG; ++k) {
-        pa[k] = soff[k] >= 0 ? P.in[(size_t)e1a * plane + soff[k]] : 0.f;
-        pb[k] = (soff[k] >= 0 && e1a + 1 <= e1b) ? P.in[(size_t)(e1a + 1) * plane + soff[k]] : 0.f;
-    }
+    for (int k = 0; k < NSTG; ++k) pa[k] = pb[k] = 0.f;
+    fetch(e1a, pa);
+    if (e1a + 1 <= e1b) fetch(e1a + 1, pb);
     // axis-2 / axis-1 ownership: column j3, rows 4 g .. 4 g + 3
     const int j3 = threadIdx.x & 63;
     const int g = threadIdx.x >> 6;
@@ -167,11 +179,7 @@ __global__ __launch_bounds__(512, 2) void k_lanczos_ring(LanczosParams P)
             const int idx = threadIdx.x + kRThreads * k;
             if (idx < L2 * L3) stg[idx] = buf[k];
         }
-        if (e1 + 2 <= e1b) {
-#pragma unroll
-            for (int k = 0; k < NSTG; ++k)
-                if (soff[k] >= 0) buf[k] = P.in[(size_t)(e1 + 2) * plane + soff[k]];
-        }
+        if (e1 + 2 <= e1b) fetch(e1 + 2, buf);
         __syncthreads();
 #pragma unroll
         for (int d = 0; d < M2; ++d) w[d] = wn_s[d];
@@ -214,6 +222,10 @@ __global__ __launch_bounds__(512, 2) void k_lanczos_ring(LanczosParams P)
         const int i1 = e1 - M2 + 1 - eo;
         if (i1 >= o1 && j3 < T3) {
             float* orow = P.out + ((size_t)i1 * P.o[1] + o2) * P.o[2] + o3 + j3;
+            // the mirrored output (-G): plane o0 - 1 - i1, rows and columns reversed
+            const bool mirror = P.ohalf && i1 != P.o[0] - 1 - i1;
+            float* mrow = P.out + ((size_t)(P.o[0] - 1 - i1) * P.o[1] + (P.o[1] - 1 - o2)) * P.o[2]
+                        + (P.o[2] - 1 - o3 - j3);
 #pragma unroll
             for (int q = 0; q < kRRun; ++q) {
                 const int j2 = g * kRRun + q;
@@ -222,6 +234,7 @@ __global__ __launch_bounds__(512, 2) void k_lanczos_ring(LanczosParams P)
 #pragma unroll
                     for (int d = 0; d < M2; ++d) acc += w[d] * ring[d][q];
                     orow[(size_t)j2 * P.o[2]] = acc;
+                    if (mirror) mrow[-(ptrdiff_t)j2 * P.o[2]] = acc;
                 }
             }
         }
@@ -252,6 +265,7 @@ hipError_t launch_lanczos(const LanczosParams& p, hipStream_t st)
         q.t2 = kRT2; q.t3 = kRT3;
         q.nb2 = (p.o[1] + kRT2 - 1) / kRT2;
         q.nb3 = (p.o[2] + p.eoff + kRT3 - 1) / kRT3;
+        if (p.ohalf) q.nb1 = (p.ohalf + p.t1 - 1) / p.t1;
         const dim3 grid(8 * ((q.nb1 * q.nb2 * q.nb3 + 7) / 8));
         if (p.m == 2) hipLaunchKernelGGL((k_lanczos_ring<4, true>), grid, dim3(kRThreads), 0, st, q);
         else if (p.m == 3) hipLaunchKernelGGL((k_lanczos_ring<6, true>), grid, dim3(kRThreads), 0, st, q);

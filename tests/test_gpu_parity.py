@@ -246,3 +246,15 @@ def test_set_sites_async_matches_set_sites():
     ref = gpu_intensity(m2)
     assert np.array_equal(out.cpu().numpy(), ref)
     h.close()
+
+
+@pytest.mark.parametrize("lm,s", [(2, 1), (3, 1), (4, 1), (2, 2)])
+def test_lanczos_symmetric_box_half_storage(lm, s):
+    """On a box symmetric about G = 0 the grown box is stored as its half G1 <= 0 and
+    (s = 1) the filter computes half the planes and writes their mirrors."""
+    m = synth.random_model(950 + lm + s, n=(6, 4, 8), S=3, M=2, order=3)
+    m.g0, m.count = (-7, -6, -9), (15, 13, 19)
+    say(f"lanczos symmetric box m={lm} s={s}")
+    out = gpu_filtered(m, lm, s)
+    ref = O.filtered_intensity(m, lm, s, order=3)
+    assert rel_l2(out, ref) <= TOL
