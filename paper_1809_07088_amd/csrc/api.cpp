@@ -549,6 +549,7 @@ dsx_status plan_recombine(dsx_model m, const Box& bx, float* out, const Layout& 
     p.first_mono = m->first_mono;
     for (int a = 0; a < 3; ++a) { p.g0[a] = bx.g0[a]; p.cnt[a] = bx.cnt[a]; }
     p.opitch = lay.pitch; p.ooff = lay.off;
+    p.ostream = (lay.pitch % 32 == 0 && lay.off % 32 == 0 && ((uintptr_t)out & 127) == 0) ? 1 : 0;
     p.H3min = tb->H3min; p.nH3span = tb->nH3span;
     p.nclass = m->nclass;
     p.work = tb->work; p.nwork = tb->nwork;

@@ -91,6 +91,7 @@ struct RecombParams {
     int32_t n1, n2, n3, nh, S, SF, F, M, first_mono;
     int32_t g0[3], cnt[3];
     int32_t opitch, ooff;   // output element (i1, i2, i3) at out[(i1 cnt1 + i2) opitch + i3 + ooff]
+    int32_t ostream;        // rows start 128-byte lines: direct writes are streaming stores
     int32_t H3min, nH3span;
     int32_t nclass;         // r3 classes (rows of tabH3)
     const int4* work;       // [nwork] (k1, k2, G1, h2a | h2b << 12 | mirror << 24), or k1 < 0

@@ -151,13 +151,19 @@ struct RowOut {
     char* oplane;
     char* mplane;
     uint32_t o0, m0, step;
-    // streaming stores: the output is not read again here, and keeping it out of
-    // L2 keeps the spectra columns there
+    bool nt;
+    // On line-aligned rows every H3 step of a row is whole lines: streaming stores
+    // keep the output (not read again here) out of L2, where the spectra columns stay.
+    // Unaligned rows go through L2, which merges the partial lines.
     __device__ __forceinline__ void put(int h, float v) const {
-        __builtin_nontemporal_store(v, reinterpret_cast<float*>(oplane + (o0 + step * (uint32_t)h)));
+        float* a = reinterpret_cast<float*>(oplane + (o0 + step * (uint32_t)h));
+        if (nt) __builtin_nontemporal_store(v, a);
+        else *a = v;
     }
     __device__ __forceinline__ void put_mirror(int h, float v) const {
-        __builtin_nontemporal_store(v, reinterpret_cast<float*>(mplane + (m0 - step * (uint32_t)h)));
+        float* a = reinterpret_cast<float*>(mplane + (m0 - step * (uint32_t)h));
+        if (nt) __builtin_nontemporal_store(v, a);
+        else *a = v;
     }
 };
 
@@ -170,6 +176,7 @@ __device__ __forceinline__ RowOut row_out(const RecombParams& P, const BlockWork
     r.o0 = 4u * (uint32_t)(i2 * P.opitch + i3b);
     r.m0 = 4u * (uint32_t)((P.cnt[1] - 1 - i2) * P.opitch + (P.cnt[2] - 1 - i3b));
     r.step = 4u * (uint32_t)P.n3;
+    r.nt = P.ostream != 0;
     return r;
 }
 
@@ -481,8 +488,9 @@ __global__ __launch_bounds__(1024) void k_recombine_folded(RecombParams P)
     float2* tHs = smem + 2 * (size_t)P.bs_elems;
     __shared__ int jtab[2][QR];              // terms N - e + 1, field of p = 0 of pair j
     __shared__ float jfr[QR];                // 1/r! of pair j
-    // per plane and site: b e^{2 pi i (g1 r1 + k2 r2 / n2)} (i tau1)^p / p!
-    __shared__ float2 wtab[2][kMaxSites][N + 1];
+    // per plane and site: b e^{2 pi i (g1 r1 + k2 r2 / n2)} (i tau1)^p / p!, and its
+    // conjugate for the mirrored half (sum w conj(x) = conj(sum conj(w) x))
+    __shared__ float2 wtab[2][2][kMaxSites][N + 1];
     const int n1 = P.n1, n2 = P.n2, n3 = P.n3, nh = P.nh;
     const int SFnh = P.SF * nh;
     for (int j = threadIdx.x; j < QR; j += blockDim.x) {
@@ -509,7 +517,9 @@ __global__ __launch_bounds__(1024) void k_recombine_folded(RecombParams P)
         const int p4 = p & 3;
         const float2 ip = p4 == 0 ? make_float2(mag, 0.f) : p4 == 1 ? make_float2(0.f, mag)
                         : p4 == 2 ? make_float2(-mag, 0.f) : make_float2(0.f, -mag);
-        wtab[pl][sl][p] = cmulf(wb, ip);
+        const float2 wv = cmulf(wb, ip);
+        wtab[0][pl][sl][p] = wv;
+        wtab[1][pl][sl][p] = make_float2(wv.x, -wv.y);
     }
     const float2* tH0 = PAR ? nullptr : stage_class_phases(P, tHs);
 
@@ -584,10 +594,13 @@ __global__ __launch_bounds__(1024) void k_recombine_folded(RecombParams P)
                     }
                 }
             };
-            // ... and sum_p w_p X (X = x, or conj x on the mirrored half) for both planes
+            // ... and sum_p w_p X (X = x, or conj x on the mirrored half) for both planes:
+            // the mirrored half forms sum conj(w) x with the conjugated weights and
+            // conjugates the sum
+            const int hw = half ? 1 : 0;
             auto contract = [&](int sl, const float2 (&x)[N + 1], float2& acc0, float2& acc1) {
-                const float2* w0 = wtab[0][sl];
-                const float2* w1 = wtab[1][sl];
+                const float2* w0 = wtab[hw][0][sl];
+                const float2* w1 = wtab[hw][1][sl];
                 acc0 = make_float2(0.f, 0.f);
                 acc1 = make_float2(0.f, 0.f);
 #pragma unroll
@@ -596,14 +609,15 @@ __global__ __launch_bounds__(1024) void k_recombine_folded(RecombParams P)
                         float2 v = x[p];
                         if (p == 0) v = f0 >= 0 ? v : make_float2(0.f, 0.f);   // absent constant monomial
                         if (p >= pmin) v = p < pc ? v : make_float2(0.f, 0.f);
-                        v.y = __uint_as_float(__float_as_uint(v.y) ^ cj);
                         const float2 wp = w0[p], wq = w1[p];
-                        acc0.x += wp.x * v.x - wp.y * v.y;
-                        acc0.y += wp.x * v.y + wp.y * v.x;
-                        acc1.x += wq.x * v.x - wq.y * v.y;
-                        acc1.y += wq.x * v.y + wq.y * v.x;
+                        acc0.x = fmaf(wp.x, v.x, acc0.x); acc0.x = fmaf(-wp.y, v.y, acc0.x);
+                        acc0.y = fmaf(wp.x, v.y, acc0.y); acc0.y = fmaf(wp.y, v.x, acc0.y);
+                        acc1.x = fmaf(wq.x, v.x, acc1.x); acc1.x = fmaf(-wq.y, v.y, acc1.x);
+                        acc1.y = fmaf(wq.x, v.y, acc1.y); acc1.y = fmaf(wq.y, v.x, acc1.y);
                     }
                 }
+                acc0.y = __uint_as_float(__float_as_uint(acc0.y) ^ cj);
+                acc1.y = __uint_as_float(__float_as_uint(acc1.y) ^ cj);
             };
             // sites in class order; the loads of the next site are in flight while the
             // current one is contracted
