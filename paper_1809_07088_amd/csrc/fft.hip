@@ -487,7 +487,7 @@ __global__ __launch_bounds__(256) void k_fft_axis1_reg(Axis1Params P)
 // One lattice plane R1 of one site, a chunk of kRegFC fields, for power-of-two
 // n2 = L2, n3 = L3 <= 32:
 //  1. every thread generates the chunk's fields of a few cells (the powers of a
-//     p-run are stepped by one factor u1 each), centred by the FP64 mean, into LDS;
+//     p-run are stepped by one factor u_1 each), centred by the FP64 mean, into LDS;
 //  2. one thread per (field, row pair) packs two real rows into one complex line and
 //     transforms it along axis 3 in registers, then separates the two half spectra;
 //  3. one thread per (field, k3) transforms the column along axis 2 in registers and
@@ -506,7 +506,6 @@ __global__ __launch_bounds__(kRegThreads) void k_fft_planes_reg(PlaneParams P)
     __shared__ float2 tw2[L2], tw3[L3];
     __shared__ float buf[UN];
     __shared__ float meanf[kRegFC];
-    __shared__ int expo[kRegFC][4];                    // p, q, r, p-run continues the previous field
 
     int b = blockIdx.x;
     const int fc = b % P.nfchunk; b /= P.nfchunk;
@@ -523,45 +522,61 @@ __global__ __launch_bounds__(kRegThreads) void k_fft_planes_reg(PlaneParams P)
         const int ep = P.mono[3 * f], eq = P.mono[3 * f + 1], er = P.mono[3 * f + 2];
         const int t = P.kind == 1 ? f : mono_index(ep, eq, er);
         meanf[threadIdx.x] = (float)(P.sums[(size_t)(m * P.S + mu) * P.T + t] / (double)ncell);
-        expo[threadIdx.x][0] = ep; expo[threadIdx.x][1] = eq; expo[threadIdx.x][2] = er;
-        int cont = 0;
-        if (threadIdx.x > 0 && P.kind != 1) {
-            const int f0 = f - 1;
-            cont = (P.mono[3 * f0] + 1 == ep && P.mono[3 * f0 + 1] == eq && P.mono[3 * f0 + 2] == er) ? 1 : 0;
-        }
-        expo[threadIdx.x][3] = cont;
     }
     __syncthreads();
 
-    // 1. generation
+    // 1. generation.  The thread's cells are loaded together (one memory latency);
+    //    the loop over the chunk's fields is uniform, so exponents are scalars and a
+    //    field continuing the p-run of the previous one costs one product per cell.
     const size_t plane0 = ((size_t)(m * P.S + mu)) * ncell + (size_t)R1 * L2 * L3;
-    for (int c = threadIdx.x; c < L2 * L3; c += blockDim.x) {
-        const int r2 = c / L3, r3 = c - r2 * L3;
-        const float d = P.occ ? P.occ[plane0 + c] : 1.f;
-        float u0 = 0.f, u1 = 0.f, u2 = 0.f;
-        if (P.vec) {
-            const float* u = P.vec + 3 * (plane0 + c);
-            u0 = u[0]; u1 = u[1]; u2 = u[2];
+    static_assert(kRegThreads % L3 == 0, "a thread's cells share r3");
+    constexpr int CPT = (L2 * L3 + kRegThreads - 1) / kRegThreads;   // cells per thread
+    constexpr int RSTEP = kRegThreads / L3;            // rows between a thread's cells
+    const bool gen = threadIdx.x < L2 * L3;           // false only on planes under kRegThreads cells
+    float cd[CPT], cu0[CPT], cu1[CPT], cu2[CPT], v[CPT];
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+        const size_t c = plane0 + threadIdx.x + k * kRegThreads;
+        cd[k] = (gen && P.occ) ? P.occ[c] : 1.f;
+        cu0[k] = cu1[k] = cu2[k] = 0.f;
+        if (gen && P.vec) {
+            const float* u = P.vec + 3 * c;
+            cu0[k] = u[0]; cu1[k] = u[1]; cu2[k] = u[2];
         }
-        float v = 1.f;
-        for (int fb = 0; fb < nfb; ++fb) {
-            float x;
-            if (P.kind == 1) {
-                const int comp = fa + fb;
-                x = (comp == 0 ? u0 : comp == 1 ? u1 : u2) * d;
-            } else {
-                if (expo[fb][3]) {
-                    v *= u0;
-                } else {
-                    v = 1.f;
-                    for (int k = 0; k < expo[fb][0]; ++k) v *= u0;
-                    for (int k = 0; k < expo[fb][1]; ++k) v *= u1;
-                    for (int k = 0; k < expo[fb][2]; ++k) v *= u2;
-                }
-                x = v * d;
-            }
-            buf[fb * FS + r2 * RP + r3] = x - meanf[fb];
+        v[k] = 1.f;
+    }
+    float* const dst0 = buf + (threadIdx.x / L3) * RP + threadIdx.x % L3;
+    int pe = -1, qe = -1, re = -1;                     // exponents of the previous field
+    for (int fb = 0; fb < (gen ? nfb : 0); ++fb) {
+        const int f = fa + fb;
+        const float mf = meanf[fb];
+        float* const dst = dst0 + fb * FS;
+        if (P.kind == 1) {
+#pragma unroll
+            for (int k = 0; k < CPT; ++k)
+                dst[k * RSTEP * RP] = (f == 0 ? cu0[k] : f == 1 ? cu1[k] : cu2[k]) * cd[k] - mf;
+            continue;
         }
+        const int ep = P.mono[3 * f], eq = P.mono[3 * f + 1], er = P.mono[3 * f + 2];
+        if (ep == pe + 1 && eq == qe && er == re) {
+#pragma unroll
+            for (int k = 0; k < CPT; ++k) v[k] *= cu0[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < CPT; ++k) v[k] = 1.f;
+            for (int e = 0; e < ep; ++e)
+#pragma unroll
+                for (int k = 0; k < CPT; ++k) v[k] *= cu0[k];
+            for (int e = 0; e < eq; ++e)
+#pragma unroll
+                for (int k = 0; k < CPT; ++k) v[k] *= cu1[k];
+            for (int e = 0; e < er; ++e)
+#pragma unroll
+                for (int k = 0; k < CPT; ++k) v[k] *= cu2[k];
+        }
+        pe = ep; qe = eq; re = er;
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) dst[k * RSTEP * RP] = v[k] * cd[k] - mf;
     }
     __syncthreads();
 
