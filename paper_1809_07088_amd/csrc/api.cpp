@@ -179,8 +179,10 @@ struct DeviceTables {
     float2* tabH3 = nullptr;
     int4* work = nullptr;
     int4* work2 = nullptr;     // the same blocks with two G1 planes of one column each
+    int4* work3 = nullptr;     // work2 with each block cut into k3 slices (null: no slicing)
     int H3min = 0, nH3span = 0;
-    int nwork = 0, nwork2 = 0, hc = 0, nchunk3 = 0, block = 0;
+    int nwork = 0, nwork2 = 0, nwork3 = 0, hc = 0, nchunk3 = 0, block = 0;
+    int n3s = 0, block3 = 0;   // k3 per slice, threads per plane of a sliced block
 };
 
 struct LaunchPlan {
@@ -223,7 +225,7 @@ struct dsx_model_s {
     std::map<std::pair<int, int>, float*> lanczos_w;
     int sum_chunk = 256, sum_chunks = 0;   // cells per sums block, blocks per (config, site)
     // plan knobs (defaults, or chosen by the autotuner for this model's key)
-    int tune_recomb_variant = 0;   // 0 default form, 2 class form
+    int tune_recomb_variant = 0;   // 0 default form, 2 class form, 3 unfolded, 4 unsliced
     int tune_fchunk = 0;           // fields per FFT plane block (0 = heuristic)
     int tune_lanczos_t1 = 32;      // planes per filter block
     bool tuned = false;
@@ -378,7 +380,7 @@ dsx_status tables_for(dsx_model m, const Box& bx, DeviceTables** out)
         if (se != hipSuccess) { m->failed = true; return fail(DSX_ERR_DEVICE, hipGetErrorString(se)); }
         for (auto& kv : m->tables) {
             dfree(kv.second.tab1); dfree(kv.second.tab2); dfree(kv.second.tabK3); dfree(kv.second.tabH3);
-            dfree(kv.second.tabK2); dfree(kv.second.work); dfree(kv.second.work2);
+            dfree(kv.second.tabK2); dfree(kv.second.work); dfree(kv.second.work2); dfree(kv.second.work3);
         }
         m->tables.clear();
     }
@@ -434,8 +436,12 @@ dsx_status tables_for(dsx_model m, const Box& bx, DeviceTables** out)
     const int h2per = std::max(1, maxT / per_h2);
     const bool friedel = symmetric_box(bx);
     if (bx.half && !friedel) return fail(DSX_ERR_STATE, "half storage needs a symmetric box");
-    std::vector<std::pair<long long, int4>> items, items2;
+    std::vector<std::pair<long long, int4>> items, items2, items3;
     int maxrows = 1;
+    // k3 slices of the two-plane blocks: halves of the k3 range when it is long enough
+    // that a slice still writes 64-byte runs of an output row
+    const int nsl = (n3 >= 16) ? 2 : 1;
+    t.n3s = (n3 + nsl - 1) / nsl;
     for (int k1 = 0; k1 < n1; ++k1) {
         const int nH1 = hcount(k1, n1, bx.g0[0], bx.cnt[0]);
         const int H1lo = (int)ceildiv_l((long)bx.g0[0] - k1, n1);
@@ -478,8 +484,12 @@ dsx_status tables_for(dsx_model m, const Box& bx, DeviceTables** out)
                     const int G1 = k1 + n1 * (H1lo + j1);
                     const int hasb = i + 1 < planes.size() ? 1 : 0;
                     const int mb = hasb ? planes[i + 1].second : 0;
-                    items2.push_back({key * 4096 + j1, make_int4(k1, k2, G1, h2a | (h2b << 12) | (planes[i].second << 24) |
-                                                                          (hasb << 25) | (mb << 26))});
+                    const int wv = h2a | (h2b << 12) | (planes[i].second << 24) | (hasb << 25) | (mb << 26);
+                    items2.push_back({key * 4096 + j1, make_int4(k1, k2, G1, wv)});
+                    // the slices of one block are adjacent: they share the column's spectra
+                    // and the cache lines of the output rows
+                    for (int sl = 0; sl < nsl && nsl > 1; ++sl)
+                        items3.push_back({key * 4096 + j1, make_int4(k1, k2, G1, wv | (sl << 27))});
                 }
             }
         }
@@ -497,10 +507,12 @@ dsx_status tables_for(dsx_model m, const Box& bx, DeviceTables** out)
         }
         return wl;
     };
-    const std::vector<int4> work = xcd_order(items), work2 = xcd_order(items2);
+    const std::vector<int4> work = xcd_order(items), work2 = xcd_order(items2), work3 = xcd_order(items3);
     t.nwork = (int)work.size();
     t.nwork2 = (int)work2.size();
+    t.nwork3 = (int)work3.size();
     t.block = ((std::min(maxT, maxrows * per_h2) + 63) / 64) * 64;
+    t.block3 = ((std::min(maxT, maxrows * t.n3s * t.nchunk3) + 63) / 64) * 64;
 
     auto up = [&](float2** dst, const std::vector<float2>& src) -> hipError_t {
         hipError_t e = hipMalloc(dst, sizeof(float2) * std::max<size_t>(1, src.size()));
@@ -514,8 +526,12 @@ dsx_status tables_for(dsx_model m, const Box& bx, DeviceTables** out)
         (e = hipMalloc(&t.work, sizeof(int4) * std::max<size_t>(1, work.size()))) != hipSuccess ||
         (e = hipMemcpy(t.work, work.data(), sizeof(int4) * work.size(), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMalloc(&t.work2, sizeof(int4) * std::max<size_t>(1, work2.size()))) != hipSuccess ||
-        (e = hipMemcpy(t.work2, work2.data(), sizeof(int4) * work2.size(), hipMemcpyHostToDevice)) != hipSuccess) {
+        (e = hipMemcpy(t.work2, work2.data(), sizeof(int4) * work2.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+        (!work3.empty() &&
+         ((e = hipMalloc(&t.work3, sizeof(int4) * work3.size())) != hipSuccess ||
+          (e = hipMemcpy(t.work3, work3.data(), sizeof(int4) * work3.size(), hipMemcpyHostToDevice)) != hipSuccess))) {
         dfree(t.tab1); dfree(t.tab2); dfree(t.tabK3); dfree(t.tabH3); dfree(t.tabK2); dfree(t.work); dfree(t.work2);
+        dfree(t.work3);
         if (e == hipErrorOutOfMemory) return fail(DSX_ERR_NOMEM, "out of device memory for phase tables");
         m->failed = true;
         return fail(DSX_ERR_DEVICE, std::string("phase tables: ") + hipGetErrorString(e));
@@ -599,19 +615,27 @@ dsx_status plan_recombine(dsx_model m, const Box& bx, float* out, const Layout& 
             p.sgn2[i] = ((long long)std::floor(t2) % 2 == 0) ? 1 : -1;
         }
         const int L2 = whole ? 1 : 2;
-        const size_t bs = (size_t)m->nclass * L2 * n3 * n_pairs(m->order);
-        // two planes per block: level A buffers of both, then the class phases
+        // k3 slices (variant 4: none): smaller blocks, two of them resident per CU
+        const bool sliced = tb->work3 != nullptr && p.variant != 4;
+        const int n3s = sliced ? tb->n3s : n3;
+        const size_t bs = (size_t)m->nclass * L2 * n3s * n_pairs(m->order);
+        // two planes per block: level A buffers of both, the weights of level A, then
+        // the class phases
         const bool par = p.parity && p.variant != 2;
-        const size_t lds = sizeof(float2) * (2 * bs + (par ? 0 : (size_t)m->nclass * tb->nH3span));
+        const size_t lds = sizeof(float2) * (2 * bs + (size_t)4 * m->S * (m->order + 1) +
+                                             (par ? 0 : (size_t)m->nclass * tb->nH3span));
         if (halves && lds <= 140 * 1024) {
             p.fold = 1;
             p.fold_l2 = L2;
+            p.n3s = n3s;
             p.bs_elems = (int)bs;
             p.xs_elems = 0;
-            p.work = tb->work2;
-            p.nwork = tb->nwork2;
-            lp.block = 2 * tb->block;
+            p.work = sliced ? tb->work3 : tb->work2;
+            p.nwork = sliced ? tb->nwork3 : tb->nwork2;
+            lp.block = 2 * (sliced ? tb->block3 : tb->block);
             lp.lds = lds;
+            // a slice covers part of each 128-byte line of a row: cached stores only
+            if (sliced) p.ostream = 0;
         }
     }
 
@@ -1268,7 +1292,7 @@ dsx_status dsx_autotune(dsx_model m, int32_t lanczos_m, void* hip_stream)
     int best_v = 0;
     const Box b = filt ? filter_box(m->box, lanczos_m) : m->box;
     float* dst = filt ? m->d_ext : scratch;
-    for (int cand : {0, 2, 3}) {
+    for (int cand : {0, 2, 3, 4}) {
         if (cand != 0 && m->kind != DSX_NUCLEAR) continue;
         m->tune_recomb_variant = cand;
         const Layout lay = filt ? ext_layout(b) : dense_layout(b);

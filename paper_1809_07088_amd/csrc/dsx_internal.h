@@ -94,16 +94,19 @@ struct RecombParams {
     int32_t ostream;        // rows start 128-byte lines: direct writes are streaming stores
     int32_t H3min, nH3span;
     int32_t nclass;         // r3 classes (rows of tabH3)
-    const int4* work;       // [nwork] (k1, k2, G1, h2a | h2b << 12 | mirror << 24), or k1 < 0
+    const int4* work;       // [nwork] (k1, k2, G1, h2a | h2b << 12 | mirror << 24), or k1 < 0;
+                            // the folded form adds hasb << 25 | mirror_b << 26 | slice << 27
     int32_t nwork;
     int32_t nchunk3;        // H3 chunks per (H2, k3)
     int32_t variant;        // kernel variant (0: default for the problem, 1: multi-configuration
                             // form, 2: class form even when the parity form applies,
-                            // 3: unfolded even when the folded form applies)
+                            // 3: unfolded even when the folded form applies, 4: folded
+                            // without k3 slices)
     int32_t fold;           // folded form: every r_mu2 is a multiple of 1/2, so the g2 phase of a
                             // site is e^{2 pi i k2 r_mu2 / n2} times +-1 by the parity of H2, and
                             // level A sums the sites of each r3 class (per H2 residue)
     int32_t fold_l2;        // H2 residues of the folded form: 1 (every r_mu2 whole) or 2
+    int32_t n3s;            // folded form: k3 per slice; block slice s covers k3 in [s n3s, (s + 1) n3s)
     int32_t sgn2[kMaxSites];         // per sorted position: e^{2 pi i r_mu2} = +-1
     int32_t parity;         // every r_mu3 is a multiple of 1/2 (the parity form applies)
     int32_t class_sign[kMaxSites];   // per class: e^{2 pi i r_c3} = +-1 in the parity form

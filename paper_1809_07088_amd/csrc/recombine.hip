@@ -452,11 +452,14 @@ __global__ __launch_bounds__(512, 4) void k_recombine_nuclear(RecombParams P)
 }
 
 // Folded form (every r_mu2 a multiple of 1/2; see the top of the file).  A block
-// takes two planes G1 and G1 + n1 of one spectra column (the second may be absent):
-// level A reads every spectrum once for both, and each half of the block then runs
-// levels B and C of one plane.  LDS:
-//   Bs   [2][nclass][L2][n3][QR]  level A summed over the sites of each r3 class,
+// takes two planes G1 and G1 + n1 of one spectra column (the second may be absent)
+// and one slice of n3s k3 values: level A reads every spectrum of the slice once for
+// both planes, and each half of the block then runs levels B and C of one plane.
+// Slicing k3 keeps the LDS of a block small enough for two blocks per CU, so the
+// load-bound level A of one overlaps the arithmetic and stores of the other.  LDS:
+//   Bs   [2][nclass][L2][n3s][QR] level A summed over the sites of each r3 class,
 //                                 with the site phase (but the H2-parity sign) and 1/r!
+//   wt   [2][2][S][N + 1]         level-A weights (conjugated copy, plane, site, p)
 //   tHs  [nclass][nH3span]        class phases e^{2 pi i H3 r_c3} (class form only)
 // Level A reads the spectra straight from the (L2-resident) column: every thread
 // owns (pair, k3) items and accumulates the sites of a class in registers, with the
@@ -469,6 +472,9 @@ __global__ __launch_bounds__(1024) void k_recombine_folded(RecombParams P)
     const int4 wi = P.work[blockIdx.x];
     if (wi.x < 0) return;
     const bool hasb = (wi.w >> 25) & 1;
+    const int n3s = P.n3s;
+    const int k3a = ((wi.w >> 27) & 7) * n3s;       // first k3 of the slice
+    const int k3n = min(n3s, P.n3 - k3a);          // k3 in the slice
     const int bh = blockDim.x >> 1;                 // threads per plane
     const int sel = (int)threadIdx.x >= bh ? 1 : 0; // the plane of this thread's B / C item
     BlockWork w;
@@ -485,12 +491,13 @@ __global__ __launch_bounds__(1024) void k_recombine_folded(RecombParams P)
     w.i1 = w.G1 - P.g0[0];
     const int L2 = P.fold_l2;
     float2* Bs = smem + (size_t)sel * P.bs_elems;
-    float2* tHs = smem + 2 * (size_t)P.bs_elems;
-    __shared__ int jtab[2][QR];              // terms N - e + 1, field of p = 0 of pair j
-    __shared__ float jfr[QR];                // 1/r! of pair j
     // per plane and site: b e^{2 pi i (g1 r1 + k2 r2 / n2)} (i tau1)^p / p!, and its
     // conjugate for the mirrored half (sum w conj(x) = conj(sum conj(w) x))
-    __shared__ float2 wtab[2][2][kMaxSites][N + 1];
+    float2* wt = smem + 2 * (size_t)P.bs_elems;
+    auto wtab = [&](int hw, int pl, int sl) { return wt + ((hw * 2 + pl) * P.S + sl) * (N + 1); };
+    float2* tHs = wt + 4 * P.S * (N + 1);
+    __shared__ int jtab[2][QR];              // terms N - e + 1, field of p = 0 of pair j
+    __shared__ float jfr[QR];                // 1/r! of pair j
     const int n1 = P.n1, n2 = P.n2, n3 = P.n3, nh = P.nh;
     const int SFnh = P.SF * nh;
     for (int j = threadIdx.x; j < QR; j += blockDim.x) {
@@ -518,19 +525,19 @@ __global__ __launch_bounds__(1024) void k_recombine_folded(RecombParams P)
         const float2 ip = p4 == 0 ? make_float2(mag, 0.f) : p4 == 1 ? make_float2(0.f, mag)
                         : p4 == 2 ? make_float2(-mag, 0.f) : make_float2(0.f, -mag);
         const float2 wv = cmulf(wb, ip);
-        wtab[0][pl][sl][p] = wv;
-        wtab[1][pl][sl][p] = make_float2(wv.x, -wv.y);
+        wtab(0, pl, sl)[p] = wv;
+        wtab(1, pl, sl)[p] = make_float2(wv.x, -wv.y);
     }
     const float2* tH0 = PAR ? nullptr : stage_class_phases(P, tHs);
 
-    // this thread's item: (H2, H3 chunk, k3) with k3 fastest, in its plane
-    const int nitems = (w.h2b - w.h2a) * n3 * P.nchunk3;
+    // this thread's item: (H2, H3 chunk, k3 of the slice) with k3 fastest, in its plane
+    const int nitems = (w.h2b - w.h2a) * k3n * P.nchunk3;
     const int item = threadIdx.x - sel * bh;
     const bool active = item < nitems && (sel == 0 || hasb);
-    int k3 = 0, ch = 0, h2 = w.h2a;
+    int k3 = k3a, ch = 0, h2 = w.h2a;
     if (active) {
-        k3 = item % n3;
-        const int r = item / n3;
+        k3 = k3a + item % k3n;
+        const int r = item / k3n;
         ch = r % P.nchunk3;
         h2 = w.h2a + r / P.nchunk3;
     }
@@ -553,8 +560,8 @@ __global__ __launch_bounds__(1024) void k_recombine_folded(RecombParams P)
 
     const size_t col = ((size_t)w.k1 * n2 + w.k2) * SFnh;
     const size_t colm = ((size_t)((n1 - w.k1) % n1) * n2 + (n2 - w.k2) % n2) * SFnh;
-    const int nitemA = QR * n3;
-    const float rn3 = 1.f / (float)n3;
+    const int nitemA = QR * k3n;
+    const float rn3 = 1.f / (float)k3n;
     const size_t fstride = (size_t)P.F * nh;   // between the sites of a column
 
     constexpr int NF = PAR ? 1 : HC;
@@ -570,37 +577,40 @@ __global__ __launch_bounds__(1024) void k_recombine_folded(RecombParams P)
             const int gw0 = __builtin_amdgcn_readfirstlane(base + (int)(threadIdx.x & ~63u));
             if (gw0 >= nitemA) continue;
             const int gw1 = min(gw0 + 63, nitemA - 1);
-            const int pmax = __builtin_amdgcn_readfirstlane(jtab[0][qdiv_r(gw0, n3, rn3)]);
-            const int pmin = __builtin_amdgcn_readfirstlane(jtab[0][qdiv_r(gw1, n3, rn3)]);
+            const int pmax = __builtin_amdgcn_readfirstlane(jtab[0][qdiv_r(gw0, k3n, rn3)]);
+            const int pmin = __builtin_amdgcn_readfirstlane(jtab[0][qdiv_r(gw1, k3n, rn3)]);
             const int g = base + threadIdx.x;
             const bool ok = g < nitemA;
             const int gg = ok ? g : nitemA - 1;
-            const int j = qdiv_r(gg, n3, rn3);
-            const int kk = gg - j * n3;
+            const int j = qdiv_r(gg, k3n, rn3);
+            const int kl = gg - j * k3n;                  // k3 within the slice
+            const int kk = k3a + kl;
             const int pc = jtab[0][j], f0 = jtab[1][j];
             const float fr = jfr[j];
             const bool half = kk >= nh;                   // conj X(-k) from the mirrored column
             const float2* xl = Xm + (half ? colm : col) + (half ? n3 - kk : kk);
             const unsigned cj = half ? 0x80000000u : 0u;
-            // the p terms of site sl: loads (clamped in-bounds, masked later) ...
-            auto load = [&](int sl, float2 (&x)[N + 1]) {
-                const float2* xb = xl + (size_t)P.site_of[sl] * fstride;
+            // the p terms of site sl and its k3 phase.  Every lane issues the same N + 2
+            // loads whatever its run length (terms past the run reread the first field and
+            // are masked in the contraction): with a fixed count in flight, the wait for
+            // one site leaves the loads of the next one outstanding.
+            int fo[N + 1];
 #pragma unroll
-                for (int p = 0; p <= N; ++p) {
-                    if (p < pmax) {
-                        const int f = f0 + p;
-                        if (p < pmin) x[p] = xb[(size_t)(p == 0 ? max(f, 0) : f) * nh];
-                        else x[p] = xb[(size_t)min(f, P.F - 1) * nh];
-                    }
-                }
+            for (int p = 0; p <= N; ++p) fo[p] = (p < pc ? max(f0 + p, 0) : max(f0, 0)) * nh;
+            auto load = [&](int sl, float2 (&x)[N + 2]) {
+                const int mu = P.site_of[sl];
+                const float2* xb = xl + (size_t)mu * fstride;
+#pragma unroll
+                for (int p = 0; p <= N; ++p) x[p] = xb[fo[p]];
+                x[N + 1] = P.tabK3[(size_t)mu * n3 + kk];
             };
             // ... and sum_p w_p X (X = x, or conj x on the mirrored half) for both planes:
             // the mirrored half forms sum conj(w) x with the conjugated weights and
             // conjugates the sum
             const int hw = half ? 1 : 0;
-            auto contract = [&](int sl, const float2 (&x)[N + 1], float2& acc0, float2& acc1) {
-                const float2* w0 = wtab[hw][0][sl];
-                const float2* w1 = wtab[hw][1][sl];
+            auto contract = [&](int sl, const float2 (&x)[N + 2], float2& acc0, float2& acc1) {
+                const float2* w0 = wtab(hw, 0, sl);
+                const float2* w1 = wtab(hw, 1, sl);
                 acc0 = make_float2(0.f, 0.f);
                 acc1 = make_float2(0.f, 0.f);
 #pragma unroll
@@ -621,11 +631,10 @@ __global__ __launch_bounds__(1024) void k_recombine_folded(RecombParams P)
             };
             // sites in class order; the loads of the next site are in flight while the
             // current one is contracted
-            float2 xa[N + 1], xb2[N + 1];
+            float2 xa[N + 2], xb2[N + 2];
             float2 aE0 = make_float2(0.f, 0.f), aO0 = aE0, aE1 = aE0, aO1 = aE0;
-            auto finish = [&](int sl, const float2& acc0, const float2& acc1) {
-                const int mu = P.site_of[sl];
-                const float2 k3p = P.tabK3[(size_t)mu * n3 + kk];
+            auto finish = [&](int sl, const float2 (&x)[N + 2], const float2& acc0, const float2& acc1) {
+                const float2 k3p = x[N + 1];
                 const float2 kf = make_float2(k3p.x * fr, k3p.y * fr);
                 const float2 v0 = cmulf(kf, acc0), v1 = cmulf(kf, acc1);
                 const float s2 = (float)P.sgn2[sl];
@@ -636,28 +645,30 @@ __global__ __launch_bounds__(1024) void k_recombine_folded(RecombParams P)
                 const int c = P.class_of[sl];
                 if (sl + 1 == P.S || P.class_of[sl + 1] != c) {   // last site of class c
                     if (ok) {
-                        float2* b0 = smem + ((size_t)(c * L2) * n3 + kk) * QR + j;
+                        float2* b0 = smem + ((size_t)(c * L2) * n3s + kl) * QR + j;
                         float2* b1 = b0 + P.bs_elems;
                         b0[0] = aE0;
                         b1[0] = aE1;
                         if (L2 == 2) {
-                            b0[(size_t)n3 * QR] = aO0;
-                            b1[(size_t)n3 * QR] = aO1;
+                            b0[(size_t)n3s * QR] = aO0;
+                            b1[(size_t)n3s * QR] = aO1;
                         }
                     }
                     aE0 = aO0 = aE1 = aO1 = make_float2(0.f, 0.f);
                 }
             };
+            // (the loads are unconditional: a site past the last repeats the last one)
             float2 c0, c1;
+            const int slast = P.S - 1;
             load(0, xa);
             for (int sl = 0; sl < P.S; sl += 2) {
-                if (sl + 1 < P.S) load(sl + 1, xb2);
+                load(min(sl + 1, slast), xb2);
                 contract(sl, xa, c0, c1);
-                finish(sl, c0, c1);
+                finish(sl, xa, c0, c1);
+                load(min(sl + 2, slast), xa);
                 if (sl + 1 < P.S) {
-                    if (sl + 2 < P.S) load(sl + 2, xa);
                     contract(sl + 1, xb2, c0, c1);
-                    finish(sl + 1, c0, c1);
+                    finish(sl + 1, xb2, c0, c1);
                 }
             }
         }
@@ -674,7 +685,7 @@ __global__ __launch_bounds__(1024) void k_recombine_folded(RecombParams P)
         for (int r = 0; r <= N; ++r) { DE[r] = make_float2(0.f, 0.f); DO[r] = make_float2(0.f, 0.f); }
         if (active) {
             for (int c = 0; c < P.nclass; ++c) {
-                const float2* Bp = Bs + ((size_t)(c * L2 + rho) * n3 + k3) * QR;
+                const float2* Bp = Bs + ((size_t)(c * L2 + rho) * n3s + (k3 - k3a)) * QR;
                 const float sgn = PAR ? (float)P.class_sign[c] : 1.f;
                 float2 D[PAR ? 1 : N + 1];
 #pragma unroll

@@ -213,6 +213,44 @@ def test_every_recombination_form(monkeypatch, variant, order, M, parity):
     assert rel_l2(I, ref) <= TOL
 
 
+def _half_r2_long_k3(seed, n3, order, M, parity):
+    m = _half_r2_model(seed, order, M, parity)
+    small = synth.random_model(seed, n=(4, 4, n3), S=4, M=M, order=order)
+    small.frac = m.frac
+    return small
+
+
+@pytest.mark.parametrize("variant", ["0", "1", "2", "4"])
+@pytest.mark.parametrize("n3,order,M,parity", [(16, 8, 1, True), (17, 5, 2, True), (20, 3, 1, False),
+                                               (33, 4, 2, False)])
+def test_folded_k3_slices(monkeypatch, variant, n3, order, M, parity):
+    """Supercells with n3 >= 16 cut the folded blocks into two k3 slices (odd n3: of
+    unequal length); variant 4 keeps whole blocks.  The box is ragged at both ends."""
+    monkeypatch.setenv("DSX_RECOMBINE_VARIANT", variant)
+    m = _half_r2_long_k3(1000 + n3, n3, order, M, parity)
+    m.g0, m.count = (-5, -4, -(n3 + 3)), (9, 9, 2 * n3 + 7)
+    say(f"folded k3 slices variant={variant} n3={n3} order={order} M={M} parity={parity}")
+    I = gpu_intensity(m)
+    ref = O.intensity(m, O.grid_points(m.g0, m.count), order).reshape(m.count)
+    assert rel_l2(I, ref) <= TOL
+
+
+@pytest.mark.parametrize("lm", [0, 2])
+def test_folded_k3_slices_symmetric_box(lm):
+    """Sliced folded blocks on a box symmetric about G = 0 (Friedel mirror writes) and,
+    through the filter, on its half-stored grown box."""
+    m = _half_r2_long_k3(1100 + lm, 16, 4, 2, True)
+    m.g0, m.count = (-9, -8, -21), (19, 17, 43)
+    say(f"folded k3 slices symmetric box lanczos m={lm}")
+    if lm == 0:
+        out = gpu_intensity(m)
+        ref = O.intensity(m, O.grid_points(m.g0, m.count), 4).reshape(m.count)
+    else:
+        out = gpu_filtered(m, lm, 1)
+        ref = O.filtered_intensity(m, lm, 1, order=4)
+    assert rel_l2(out, ref) <= TOL
+
+
 @pytest.mark.parametrize("n,kind,order", [((16, 8, 32), synth.NUCLEAR, 3), ((8, 32, 16), synth.NUCLEAR, 0),
                                           ((8, 16, 8), synth.MAGNETIC, 0), ((32, 32, 8), synth.NUCLEAR, 5)])
 def test_power_of_two_edges_register_transforms(n, kind, order):
