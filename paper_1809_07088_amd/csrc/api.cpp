@@ -563,7 +563,10 @@ dsx_status plan_recombine(dsx_model m, const Box& bx, float* out, const Layout& 
     p.tab1 = tb->tab1; p.tab2 = tb->tab2; p.tabK3 = tb->tabK3; p.tabH3 = tb->tabH3; p.tabK2 = tb->tabK2;
     p.n1 = n1; p.n2 = n2; p.n3 = n3; p.nh = m->nh; p.S = m->S; p.SF = m->SF; p.F = m->F; p.M = m->M;
     p.first_mono = m->first_mono;
-    for (int a = 0; a < 3; ++a) { p.g0[a] = bx.g0[a]; p.cnt[a] = bx.cnt[a]; }
+    for (int a = 0; a < 3; ++a) {
+        p.g0[a] = bx.g0[a]; p.cnt[a] = bx.cnt[a];
+        p.tw[a] = 2.0 * M_PI / m->n[a];
+    }
     p.opitch = lay.pitch; p.ooff = lay.off;
     p.ostream = (lay.pitch % 32 == 0 && lay.off % 32 == 0 && ((uintptr_t)out & 127) == 0) ? 1 : 0;
     p.H3min = tb->H3min; p.nH3span = tb->nH3span;
@@ -605,7 +608,9 @@ dsx_status plan_recombine(dsx_model m, const Box& bx, float* out, const Layout& 
     if (lp.lds > 160 * 1024) return fail(DSX_ERR_UNSUPPORTED, "recombination does not fit the LDS for this box");
     // folded form: every r_mu2 a multiple of 1/2 (exactly, as given), fewer r3 classes
     // than sites, and the class buffers fit the LDS
-    if (!mag && p.variant != 3 && m->nclass < m->S) {
+    // (the folded kernel addresses the spectra of one configuration with 32-bit offsets)
+    const bool small_spectra = (unsigned long long)n1 * n2 * m->SF * m->nh * sizeof(float2) < (1ULL << 32);
+    if (!mag && p.variant != 3 && m->nclass < m->S && small_spectra) {
         bool halves = true, whole = true;
         for (int i = 0; i < m->S; ++i) {
             const double r2 = m->frac[3 * m->site_of[i] + 1];

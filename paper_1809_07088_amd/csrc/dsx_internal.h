@@ -116,6 +116,7 @@ struct RecombParams {
     int32_t sc_start[kMaxSites + 1];   // site chunk boundaries in the sorted site list
     int32_t site_of[kMaxSites];        // sorted position -> site index
     int32_t class_of[kMaxSites];       // sorted position -> class index
+    double tw[3];           // 2 pi / n_a
     float scale;            // 1/(N M)  (magnetic: C/(N M))
     // magnetic only
     float recip[9];         // rows a*, b*, c* (inverse Angstrom)

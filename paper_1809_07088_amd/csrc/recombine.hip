@@ -137,6 +137,11 @@ __device__ __forceinline__ const float2* stage_class_phases(const RecombParams& 
     return dst - P.H3min;
 }
 
+// Word 3 of a raw buffer resource on gfx9-class targets: 32-bit data format (a zero
+// format would read zeros); no swizzle, stride 0, so offsets are plain byte offsets
+// checked against the record count.
+constexpr int kBufferFlags = 0x00020000;
+
 // ---------------------------------------------------------------------------- nuclear
 __device__ __forceinline__ int wave_min_uniform(int v)
 {
@@ -475,8 +480,9 @@ __global__ __launch_bounds__(1024) void k_recombine_folded(RecombParams P)
     const int n3s = P.n3s;
     const int k3a = ((wi.w >> 27) & 7) * n3s;       // first k3 of the slice
     const int k3n = min(n3s, P.n3 - k3a);          // k3 in the slice
-    const int bh = blockDim.x >> 1;                 // threads per plane
-    const int sel = (int)threadIdx.x >= bh ? 1 : 0; // the plane of this thread's B / C item
+    const int bh = blockDim.x >> 1;                 // threads per plane (a multiple of 64)
+    // the plane of this thread's B / C item (wave-uniform: its output bases are scalars)
+    const int sel = __builtin_amdgcn_readfirstlane((int)threadIdx.x >= bh ? 1 : 0);
     BlockWork w;
     w.k1 = wi.x;
     w.k2 = wi.y;
@@ -517,10 +523,11 @@ __global__ __launch_bounds__(1024) void k_recombine_folded(RecombParams P)
         const int sl = u / (N + 1), p = u - sl * (N + 1);
         const int mu = P.site_of[sl];
         const int G1 = wi.z + (pl && hasb ? n1 : 0);      // (an absent plane repeats the first)
-        const float tau1 = (float)(6.283185307179586 * (double)G1 / (double)n1);
+        const float tau1 = (float)((double)G1 * P.tw[0]);
         const float2 wb = cmulf(P.tab1[(size_t)mu * P.cnt[0] + (G1 - P.g0[0])], P.tabK2[(size_t)mu * n2 + w.k2]);
-        float mag = 1.f;
-        for (int v = 1; v <= p; ++v) mag *= tau1 / (float)v;
+        // sqrt(scale) here scales every |F|^2 by the output scale at no cost per voxel
+        float mag = inv_factorial_rt(p) * sqrtf(P.scale);
+        for (int v = 1; v <= p; ++v) mag *= tau1;
         const int p4 = p & 3;
         const float2 ip = p4 == 0 ? make_float2(mag, 0.f) : p4 == 1 ? make_float2(0.f, mag)
                         : p4 == 2 ? make_float2(-mag, 0.f) : make_float2(0.f, -mag);
@@ -550,8 +557,8 @@ __global__ __launch_bounds__(1024) void k_recombine_folded(RecombParams P)
     const int hbeg = ch * HC;
     const int hcnt = active ? max(0, min(HC, nH3 - hbeg)) : 0;
     const int hmin = wave_min_uniform(active ? hcnt : HC);   // iterations every lane needs
-    const float tau2 = (float)(6.283185307179586 * (double)G2 / (double)n2);
-    const float c3 = (float)(6.283185307179586 / (double)n3);
+    const float tau2 = (float)((double)G2 * P.tw[1]);
+    const float c3 = (float)P.tw[2];
     const float t3base = (float)(k3 + n3 * (H3lo + hbeg)) * c3;   // tau3 of h = 0
     const float dt3 = 6.283185307179586f;                          // tau3 step per H3
     float I[MULTI ? HC : 1];
@@ -568,8 +575,14 @@ __global__ __launch_bounds__(1024) void k_recombine_folded(RecombParams P)
     float2 F[NF];
     float2 DE[N + 1], DO[N + 1];
     __syncthreads();
+    // buffer resources: the spectra of one configuration, the k3 phase table
+    const uint32_t xbytes = (uint32_t)((size_t)n1 * n2 * SFnh * sizeof(float2));
+    const __amdgpu_buffer_rsrc_t rk = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float2*>(P.tabK3), (short)0, (int)(P.S * n3 * sizeof(float2)), kBufferFlags);
     for (int m = 0; m < P.M; ++m) {
         const float2* Xm = P.X + (size_t)m * n1 * n2 * SFnh;
+        const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float2*>(Xm), (short)0, (int)xbytes, kBufferFlags);
         // level A: items (pair j, k3) with k3 fastest; pairs run in order of e = q + r,
         // so the number of p terms N - e + 1 only falls along a wave: its first and
         // last lanes give the wave-uniform bounds
@@ -588,21 +601,27 @@ __global__ __launch_bounds__(1024) void k_recombine_folded(RecombParams P)
             const int pc = jtab[0][j], f0 = jtab[1][j];
             const float fr = jfr[j];
             const bool half = kk >= nh;                   // conj X(-k) from the mirrored column
-            const float2* xl = Xm + (half ? colm : col) + (half ? n3 - kk : kk);
             const unsigned cj = half ? 0x80000000u : 0u;
-            // the p terms of site sl and its k3 phase.  Every lane issues the same N + 2
-            // loads whatever its run length (terms past the run reread the first field and
-            // are masked in the contraction): with a fixed count in flight, the wait for
-            // one site leaves the loads of the next one outstanding.
-            int fo[N + 1];
+            // the p terms of site sl and the k3 phase of its class.  Every lane issues the
+            // same N + 2 loads whatever its run length (terms past the run reread the first
+            // field and are masked in the contraction): with a fixed count in flight, the
+            // wait for one site leaves the loads of the next one outstanding.  They are
+            // buffer loads: per-item 32-bit byte offsets (the spectra of one configuration
+            // are below 4 GiB) plus the site's offset in a scalar, so a load costs no
+            // address arithmetic.
+            const uint32_t o0 = (uint32_t)((half ? colm : col) + (size_t)(half ? n3 - kk : kk));
+            uint32_t vo[N + 1];
 #pragma unroll
-            for (int p = 0; p <= N; ++p) fo[p] = (p < pc ? max(f0 + p, 0) : max(f0, 0)) * nh;
+            for (int p = 0; p <= N; ++p)
+                vo[p] = 8u * (o0 + (uint32_t)((p < pc ? max(f0 + p, 0) : max(f0, 0)) * nh));
+            const uint32_t ko = 8u * (uint32_t)kk;
             auto load = [&](int sl, float2 (&x)[N + 2]) {
-                const int mu = P.site_of[sl];
-                const float2* xb = xl + (size_t)mu * fstride;
+                const uint32_t mu = (uint32_t)P.site_of[sl];
+                const uint32_t so = mu * (uint32_t)(8 * fstride);
 #pragma unroll
-                for (int p = 0; p <= N; ++p) x[p] = xb[fo[p]];
-                x[N + 1] = P.tabK3[(size_t)mu * n3 + kk];
+                for (int p = 0; p <= N; ++p)
+                    x[p] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rx, vo[p], so, 0));
+                x[N + 1] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rk, ko, mu * (uint32_t)(8 * n3), 0));
             };
             // ... and sum_p w_p X (X = x, or conj x on the mirrored half) for both planes:
             // the mirrored half forms sum conj(w) x with the conjugated weights and
@@ -634,24 +653,23 @@ __global__ __launch_bounds__(1024) void k_recombine_folded(RecombParams P)
             float2 xa[N + 2], xb2[N + 2];
             float2 aE0 = make_float2(0.f, 0.f), aO0 = aE0, aE1 = aE0, aO1 = aE0;
             auto finish = [&](int sl, const float2 (&x)[N + 2], const float2& acc0, const float2& acc1) {
-                const float2 k3p = x[N + 1];
-                const float2 kf = make_float2(k3p.x * fr, k3p.y * fr);
-                const float2 v0 = cmulf(kf, acc0), v1 = cmulf(kf, acc1);
                 const float s2 = (float)P.sgn2[sl];
-                aE0.x += v0.x; aE0.y += v0.y;
-                aO0.x += s2 * v0.x; aO0.y += s2 * v0.y;
-                aE1.x += v1.x; aE1.y += v1.y;
-                aO1.x += s2 * v1.x; aO1.y += s2 * v1.y;
+                aE0.x += acc0.x; aE0.y += acc0.y;
+                aO0.x = fmaf(s2, acc0.x, aO0.x); aO0.y = fmaf(s2, acc0.y, aO0.y);
+                aE1.x += acc1.x; aE1.y += acc1.y;
+                aO1.x = fmaf(s2, acc1.x, aO1.x); aO1.y = fmaf(s2, acc1.y, aO1.y);
                 const int c = P.class_of[sl];
                 if (sl + 1 == P.S || P.class_of[sl + 1] != c) {   // last site of class c
+                    // the sites of a class share r3, hence the k3 phase: applied once, with 1/r!
+                    const float2 kf = make_float2(x[N + 1].x * fr, x[N + 1].y * fr);
                     if (ok) {
                         float2* b0 = smem + ((size_t)(c * L2) * n3s + kl) * QR + j;
                         float2* b1 = b0 + P.bs_elems;
-                        b0[0] = aE0;
-                        b1[0] = aE1;
+                        b0[0] = cmulf(kf, aE0);
+                        b1[0] = cmulf(kf, aE1);
                         if (L2 == 2) {
-                            b0[(size_t)n3s * QR] = aO0;
-                            b1[(size_t)n3s * QR] = aO1;
+                            b0[(size_t)n3s * QR] = cmulf(kf, aO0);
+                            b1[(size_t)n3s * QR] = cmulf(kf, aO1);
                         }
                     }
                     aE0 = aO0 = aE1 = aO1 = make_float2(0.f, 0.f);
@@ -678,7 +696,7 @@ __global__ __launch_bounds__(1024) void k_recombine_folded(RecombParams P)
         float a2[N + 1];   // tau2^q / q!
         a2[0] = 1.f;
 #pragma unroll
-        for (int q = 1; q <= N; ++q) a2[q] = a2[q - 1] * tau2 / (float)q;
+        for (int q = 1; q <= N; ++q) a2[q] = a2[q - 1] * tau2 * (1.f / (float)q);
 #pragma unroll
         for (int h = 0; h < NF; ++h) F[h] = make_float2(0.f, 0.f);
 #pragma unroll
@@ -749,8 +767,8 @@ __global__ __launch_bounds__(1024) void k_recombine_folded(RecombParams P)
         else if constexpr (PAR) return parity_eval<N>((h & 1) ? DO : DE, t3base + (float)h * dt3);
         else return F[h].x * F[h].x + F[h].y * F[h].y;
     };
-    if (w.mirror) write_row<HC, true>(ro, full, active, hmin, hcnt, P.scale, val);
-    else write_row<HC, false>(ro, full, active, hmin, hcnt, P.scale, val);
+    if (w.mirror) write_row<HC, true>(ro, full, active, hmin, hcnt, 1.f, val);
+    else write_row<HC, false>(ro, full, active, hmin, hcnt, 1.f, val);
 }
 
 // ---------------------------------------------------------------------------- magnetic
