@@ -376,6 +376,7 @@ def main():
     ap.add_argument("--only-steps", action="store_true",
                     help="time the filtered steps only (no unfiltered pass, sweep, ensemble, serving or "
                          "CPU baseline): the run the profiles are taken from")
+    ap.add_argument("--no-tune", action="store_true", help="run with the default plan instead of tuning it")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble comparison")
     ap.add_argument("--ensemble-only", action="store_true",
                     help="time only the batched ensemble (for kernel traces of the graph path)")
@@ -422,6 +423,12 @@ def main():
     def step():
         h.set_sites_async(0, None, disp_dev)     # stream-ordered device copy of the sites
         h.noise_filter(lm, 1, out)
+
+    # plan tuning happens once per model, before any timed step
+    h.set_sites_async(0, None, disp_dev)
+    if not args.no_tune:
+        h.autotune(lm)
+    plan = h.tune_query()
 
     if args.copy_probe:
         src = torch.empty(COPY_PROBE_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
@@ -548,6 +555,7 @@ def main():
                                f"|h|,|k|,|l|<=8 step 1/32 ({count[0]}^3 voxels), Lanczos m={lm}",
                    "voxels_per_step": voxels, "taylor_order": N, "lanczos_m": lm,
                    "fft_fields": info.total_fields},
+        "plan": plan,
         "roofline": roof,
         "cpu_baseline": cpu,
         "parity": parity,

@@ -203,6 +203,16 @@ dsx_status dsx_batch_destroy(dsx_batch b);
 dsx_status dsx_autotune(dsx_model m, int32_t lanczos_m, void* hip_stream);
 
 /*
+ * The plan choices a model runs with (tuned by dsx_autotune, else the defaults):
+ *   choice[0]  recombination form (0 default for the problem, 2 class form, 3 without
+ *              the folded form, 4 folded without k3 slices)
+ *   choice[1]  FFT fields per plane block (0 = chosen from the problem size)
+ *   choice[2]  filter output planes per block
+ * *tuned = 1 when they come from dsx_autotune.  Host memory, owned by the caller.
+ */
+dsx_status dsx_tune_query(dsx_model m, int32_t choice[3], int32_t* tuned);
+
+/*
  * Serving (an execution pattern; the arithmetic is that of dsx_compute_intensity /
  * dsx_noise_filter).  Refinement recomputes the intensity of a model again and
  * again as its variables change (Sec. I; Sec. VI), so a server keeps models

@@ -50,7 +50,7 @@ class KernelStat(ctypes.Structure):
 EXPORTS = ("dsx_plan_query", "dsx_create_model", "dsx_set_sites", "dsx_set_sites_async", "dsx_set_grid",
            "dsx_compute_intensity", "dsx_noise_filter", "dsx_destroy_model", "dsx_last_error",
            "dsx_version", "dsx_profile_enable", "dsx_profile_read", "dsx_profile_reset",
-           "dsx_batch_create", "dsx_batch_run", "dsx_batch_destroy", "dsx_autotune",
+           "dsx_batch_create", "dsx_batch_run", "dsx_batch_destroy", "dsx_autotune", "dsx_tune_query",
            "dsx_server_create", "dsx_server_add_model", "dsx_server_submit", "dsx_server_wait",
            "dsx_server_stats_read", "dsx_server_destroy")
 
@@ -106,13 +106,14 @@ def lib():
         L.dsx_batch_run.argtypes = [P, P]
         L.dsx_batch_destroy.argtypes = [P]
         L.dsx_autotune.argtypes = [P, i32, P]
+        L.dsx_tune_query.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.dsx_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(P)]
         L.dsx_server_add_model.argtypes = [P, ctypes.POINTER(ModelDesc), ctypes.POINTER(P)]
         L.dsx_server_submit.argtypes = [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_int64)]
         L.dsx_server_wait.argtypes = [P, ctypes.c_int64, i32, ctypes.POINTER(i32)]
         L.dsx_server_stats_read.argtypes = [P, i32, ctypes.POINTER(ServerStats)]
         L.dsx_server_destroy.argtypes = [P]
-        for f in ("dsx_batch_create", "dsx_batch_run", "dsx_batch_destroy", "dsx_autotune",
+        for f in ("dsx_batch_create", "dsx_batch_run", "dsx_batch_destroy", "dsx_autotune", "dsx_tune_query",
                   "dsx_server_create", "dsx_server_add_model", "dsx_server_submit", "dsx_server_wait",
                   "dsx_server_stats_read", "dsx_server_destroy"):
             getattr(L, f).restype = i32
@@ -256,6 +257,16 @@ def autotune(model, lanczos_m=0, stream=None):
     _check(lib().dsx_autotune(model, int(lanczos_m), _stream_handle(stream)))
 
 
+def tune_query(model):
+    """The plan choices of a model (dsx_tune_query): recombination form, FFT fields
+    per plane block, filter planes per block, and whether they were tuned."""
+    c = (ctypes.c_int32 * 3)()
+    t = ctypes.c_int32(0)
+    _check(lib().dsx_tune_query(model, c, ctypes.byref(t)))
+    return {"recombine_form": int(c[0]), "fft_fields_per_block": int(c[1]),
+            "filter_planes_per_block": int(c[2]), "tuned": bool(t.value)}
+
+
 class Batch:
     """A recorded launch sequence over several models (dsx_batch_*): run() replays it."""
 
@@ -311,6 +322,9 @@ class Model:
 
     def autotune(self, lanczos_m=0, stream=None):
         autotune(self.handle, lanczos_m, stream)
+
+    def tune_query(self):
+        return tune_query(self.handle)
 
     def close(self):
         if self.handle:

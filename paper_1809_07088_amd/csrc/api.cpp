@@ -227,7 +227,7 @@ struct dsx_model_s {
     // plan knobs (defaults, or chosen by the autotuner for this model's key)
     int tune_recomb_variant = 0;   // 0 default form, 2 class form, 3 unfolded, 4 unsliced
     int tune_fchunk = 0;           // fields per FFT plane block (0 = heuristic)
-    int tune_lanczos_t1 = 32;      // planes per filter block
+    int tune_lanczos_t1 = 16;      // planes per filter block
     bool tuned = false;
     // state
     std::vector<char> set;
@@ -1269,7 +1269,7 @@ dsx_status dsx_autotune(dsx_model m, int32_t lanczos_m, void* hip_stream)
     if (lanczos_m != 0 && (s = check_filter_args(lanczos_m, 1)) != DSX_OK) return s;
     hipStream_t st = (hipStream_t)hip_stream;
     const std::string key = tune_key(m, lanczos_m);
-    int v = 0, fc = 0, t1 = 32;
+    int v = 0, fc = 0, t1 = 16;
     if (tune_lookup(key, &v, &fc, &t1)) {
         m->tune_recomb_variant = v; m->tune_fchunk = fc; m->tune_lanczos_t1 = t1;
         m->tuned = true;
@@ -1306,7 +1306,7 @@ dsx_status dsx_autotune(dsx_model m, int32_t lanczos_m, void* hip_stream)
     }
     m->tune_recomb_variant = best_v;
     // filter: planes per block
-    int best_t1 = 32;
+    int best_t1 = 16;
     if (filt) {
         best = -1.f;
         for (int cand : {16, 32, 64}) {
@@ -1320,6 +1320,17 @@ dsx_status dsx_autotune(dsx_model m, int32_t lanczos_m, void* hip_stream)
     if (m->failed) return fail(DSX_ERR_DEVICE, "device error during tuning");
     m->tuned = true;
     tune_store(key, best_v, best_fc, best_t1);
+    return DSX_OK;
+}
+
+dsx_status dsx_tune_query(dsx_model m, int32_t choice[3], int32_t* tuned)
+{
+    if (!m) return fail(DSX_ERR_ARG, "null model");
+    if (!choice || !tuned) return fail(DSX_ERR_ARG, "null output");
+    choice[0] = m->tune_recomb_variant;
+    choice[1] = m->tune_fchunk;
+    choice[2] = m->tune_lanczos_t1;
+    *tuned = m->tuned ? 1 : 0;
     return DSX_OK;
 }
 
