@@ -180,6 +180,9 @@ struct DeviceTables {
     int4* work = nullptr;
     int4* work2 = nullptr;     // the same blocks with two G1 planes of one column each
     int4* work3 = nullptr;     // work2 with each block cut into k3 slices (null: no slicing)
+    int2* k3tab = nullptr;     // [n3] (H3lo, count) of residue k3 in the box
+    int hmin_all = 0;          // fewest H3 values of any (k3, chunk) item ...
+    int hmin_slice[8] = {};    // ... and of any item of one k3 slice
     int H3min = 0, nH3span = 0;
     int nwork = 0, nwork2 = 0, nwork3 = 0, hc = 0, nchunk3 = 0, block = 0;
     int n3s = 0, block3 = 0;   // k3 per slice, threads per plane of a sliced block
@@ -381,6 +384,7 @@ dsx_status tables_for(dsx_model m, const Box& bx, DeviceTables** out)
         for (auto& kv : m->tables) {
             dfree(kv.second.tab1); dfree(kv.second.tab2); dfree(kv.second.tabK3); dfree(kv.second.tabH3);
             dfree(kv.second.tabK2); dfree(kv.second.work); dfree(kv.second.work2); dfree(kv.second.work3);
+            dfree(kv.second.k3tab);
         }
         m->tables.clear();
     }
@@ -513,6 +517,17 @@ dsx_status tables_for(dsx_model m, const Box& bx, DeviceTables** out)
     t.nwork3 = (int)work3.size();
     t.block = ((std::min(maxT, maxrows * per_h2) + 63) / 64) * 64;
     t.block3 = ((std::min(maxT, maxrows * t.n3s * t.nchunk3) + 63) / 64) * 64;
+    std::vector<int2> k3t(n3);
+    t.hmin_all = t.hc;
+    for (int s = 0; s < 8; ++s) t.hmin_slice[s] = t.hc;
+    for (int k = 0; k < n3; ++k) {
+        k3t[k] = make_int2((int)ceildiv_l((long)bx.g0[2] - k, n3), hcount(k, n3, bx.g0[2], bx.cnt[2]));
+        for (int c = 0; c < t.nchunk3; ++c) {
+            const int h = std::max(0, std::min(t.hc, k3t[k].y - c * t.hc));
+            t.hmin_all = std::min(t.hmin_all, h);
+            t.hmin_slice[k / t.n3s] = std::min(t.hmin_slice[k / t.n3s], h);
+        }
+    }
 
     auto up = [&](float2** dst, const std::vector<float2>& src) -> hipError_t {
         hipError_t e = hipMalloc(dst, sizeof(float2) * std::max<size_t>(1, src.size()));
@@ -529,9 +544,11 @@ dsx_status tables_for(dsx_model m, const Box& bx, DeviceTables** out)
         (e = hipMemcpy(t.work2, work2.data(), sizeof(int4) * work2.size(), hipMemcpyHostToDevice)) != hipSuccess ||
         (!work3.empty() &&
          ((e = hipMalloc(&t.work3, sizeof(int4) * work3.size())) != hipSuccess ||
-          (e = hipMemcpy(t.work3, work3.data(), sizeof(int4) * work3.size(), hipMemcpyHostToDevice)) != hipSuccess))) {
+          (e = hipMemcpy(t.work3, work3.data(), sizeof(int4) * work3.size(), hipMemcpyHostToDevice)) != hipSuccess)) ||
+        (e = hipMalloc(&t.k3tab, sizeof(int2) * k3t.size())) != hipSuccess ||
+        (e = hipMemcpy(t.k3tab, k3t.data(), sizeof(int2) * k3t.size(), hipMemcpyHostToDevice)) != hipSuccess) {
         dfree(t.tab1); dfree(t.tab2); dfree(t.tabK3); dfree(t.tabH3); dfree(t.tabK2); dfree(t.work); dfree(t.work2);
-        dfree(t.work3);
+        dfree(t.work3); dfree(t.k3tab);
         if (e == hipErrorOutOfMemory) return fail(DSX_ERR_NOMEM, "out of device memory for phase tables");
         m->failed = true;
         return fail(DSX_ERR_DEVICE, std::string("phase tables: ") + hipGetErrorString(e));
@@ -608,8 +625,8 @@ dsx_status plan_recombine(dsx_model m, const Box& bx, float* out, const Layout& 
     if (lp.lds > 160 * 1024) return fail(DSX_ERR_UNSUPPORTED, "recombination does not fit the LDS for this box");
     // folded form: every r_mu2 a multiple of 1/2 (exactly, as given), fewer r3 classes
     // than sites, and the class buffers fit the LDS
-    // (the folded kernel addresses the spectra of one configuration with 32-bit offsets)
-    const bool small_spectra = (unsigned long long)n1 * n2 * m->SF * m->nh * sizeof(float2) < (1ULL << 32);
+    // (the folded kernel addresses the spectra of one configuration with 31-bit offsets)
+    const bool small_spectra = (unsigned long long)n1 * n2 * m->SF * m->nh * sizeof(float2) < (1ULL << 31);
     if (!mag && p.variant != 3 && m->nclass < m->S && small_spectra) {
         bool halves = true, whole = true;
         for (int i = 0; i < m->S; ++i) {
@@ -637,6 +654,8 @@ dsx_status plan_recombine(dsx_model m, const Box& bx, float* out, const Layout& 
             p.xs_elems = 0;
             p.work = sliced ? tb->work3 : tb->work2;
             p.nwork = sliced ? tb->nwork3 : tb->nwork2;
+            p.k3tab = tb->k3tab;
+            for (int s = 0; s < 8; ++s) p.hmin_s[s] = sliced ? tb->hmin_slice[s] : tb->hmin_all;
             lp.block = 2 * (sliced ? tb->block3 : tb->block);
             lp.lds = lds;
             // a slice covers part of each 128-byte line of a row: cached stores only

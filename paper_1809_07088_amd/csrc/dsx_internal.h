@@ -107,6 +107,8 @@ struct RecombParams {
                             // level A sums the sites of each r3 class (per H2 residue)
     int32_t fold_l2;        // H2 residues of the folded form: 1 (every r_mu2 whole) or 2
     int32_t n3s;            // folded form: k3 per slice; block slice s covers k3 in [s n3s, (s + 1) n3s)
+    const int2* k3tab;      // folded form: [n3] (H3lo, count) of the H3 with k3 + n3 H3 in the box
+    int32_t hmin_s[8];      // folded form, per slice: the fewest H3 values any item of a full wave has
     int32_t sgn2[kMaxSites];         // per sorted position: e^{2 pi i r_mu2} = +-1
     int32_t parity;         // every r_mu3 is a multiple of 1/2 (the parity form applies)
     int32_t class_sign[kMaxSites];   // per class: e^{2 pi i r_c3} = +-1 in the parity form

@@ -141,6 +141,7 @@ __device__ __forceinline__ const float2* stage_class_phases(const RecombParams& 
 // format would read zeros); no swizzle, stride 0, so offsets are plain byte offsets
 // checked against the record count.
 constexpr int kBufferFlags = 0x00020000;
+constexpr uint32_t kNoRecord = 0x80000000u;   // an offset past every record count used here
 
 // ---------------------------------------------------------------------------- nuclear
 __device__ __forceinline__ int wave_min_uniform(int v)
@@ -543,20 +544,21 @@ __global__ __launch_bounds__(1024) void k_recombine_folded(RecombParams P)
     const bool active = item < nitems && (sel == 0 || hasb);
     int k3 = k3a, ch = 0, h2 = w.h2a;
     if (active) {
-        k3 = k3a + item % k3n;
-        const int r = item / k3n;
-        ch = r % P.nchunk3;
-        h2 = w.h2a + r / P.nchunk3;
+        const int r = qdiv_r(item, k3n, 1.f / (float)k3n);
+        k3 = k3a + (item - r * k3n);
+        const int rc = P.nchunk3 == 1 ? r : qdiv_r(r, P.nchunk3, 1.f / (float)P.nchunk3);
+        ch = r - rc * P.nchunk3;
+        h2 = w.h2a + rc;
     }
     const int H2 = w.H2lo + h2;
     const int rho = (L2 == 2) ? (H2 & 1) : 0;
     const int G2 = w.k2 + n2 * H2;
     const int i2 = G2 - P.g0[1];
-    int H3lo, nH3;
-    hrange(k3, n3, P.g0[2], P.cnt[2], H3lo, nH3);
+    const int2 h3 = P.k3tab[k3];                   // H3 range of residue k3 in the box
+    const int H3lo = h3.x, nH3 = h3.y;
     const int hbeg = ch * HC;
     const int hcnt = active ? max(0, min(HC, nH3 - hbeg)) : 0;
-    const int hmin = wave_min_uniform(active ? hcnt : HC);   // iterations every lane needs
+    const int hmin = P.hmin_s[(wi.w >> 27) & 7];   // iterations every lane of a full wave needs
     const float tau2 = (float)((double)G2 * P.tw[1]);
     const float c3 = (float)P.tw[2];
     const float t3base = (float)(k3 + n3 * (H3lo + hbeg)) * c3;   // tau3 of h = 0
@@ -589,9 +591,7 @@ __global__ __launch_bounds__(1024) void k_recombine_folded(RecombParams P)
         for (int base = 0; base < nitemA; base += blockDim.x) {
             const int gw0 = __builtin_amdgcn_readfirstlane(base + (int)(threadIdx.x & ~63u));
             if (gw0 >= nitemA) continue;
-            const int gw1 = min(gw0 + 63, nitemA - 1);
             const int pmax = __builtin_amdgcn_readfirstlane(jtab[0][qdiv_r(gw0, k3n, rn3)]);
-            const int pmin = __builtin_amdgcn_readfirstlane(jtab[0][qdiv_r(gw1, k3n, rn3)]);
             const int g = base + threadIdx.x;
             const bool ok = g < nitemA;
             const int gg = ok ? g : nitemA - 1;
@@ -603,17 +603,17 @@ __global__ __launch_bounds__(1024) void k_recombine_folded(RecombParams P)
             const bool half = kk >= nh;                   // conj X(-k) from the mirrored column
             const unsigned cj = half ? 0x80000000u : 0u;
             // the p terms of site sl and the k3 phase of its class.  Every lane issues the
-            // same N + 2 loads whatever its run length (terms past the run reread the first
-            // field and are masked in the contraction): with a fixed count in flight, the
+            // same N + 2 loads whatever its run length: with a fixed count in flight, the
             // wait for one site leaves the loads of the next one outstanding.  They are
             // buffer loads: per-item 32-bit byte offsets (the spectra of one configuration
-            // are below 4 GiB) plus the site's offset in a scalar, so a load costs no
-            // address arithmetic.
+            // are below 2 GiB) plus the site's offset in a scalar, so a load costs no
+            // address arithmetic, and a term past the pair's run (or the absent constant
+            // monomial) takes an offset past the record count and reads 0.
             const uint32_t o0 = (uint32_t)((half ? colm : col) + (size_t)(half ? n3 - kk : kk));
             uint32_t vo[N + 1];
 #pragma unroll
             for (int p = 0; p <= N; ++p)
-                vo[p] = 8u * (o0 + (uint32_t)((p < pc ? max(f0 + p, 0) : max(f0, 0)) * nh));
+                vo[p] = (p < pc && f0 + p >= 0) ? 8u * (o0 + (uint32_t)((f0 + p) * nh)) : kNoRecord;
             const uint32_t ko = 8u * (uint32_t)kk;
             auto load = [&](int sl, float2 (&x)[N + 2]) {
                 const uint32_t mu = (uint32_t)P.site_of[sl];
@@ -635,9 +635,7 @@ __global__ __launch_bounds__(1024) void k_recombine_folded(RecombParams P)
 #pragma unroll
                 for (int p = 0; p <= N; ++p) {
                     if (p < pmax) {
-                        float2 v = x[p];
-                        if (p == 0) v = f0 >= 0 ? v : make_float2(0.f, 0.f);   // absent constant monomial
-                        if (p >= pmin) v = p < pc ? v : make_float2(0.f, 0.f);
+                        const float2 v = x[p];
                         const float2 wp = w0[p], wq = w1[p];
                         acc0.x = fmaf(wp.x, v.x, acc0.x); acc0.x = fmaf(-wp.y, v.y, acc0.x);
                         acc0.y = fmaf(wp.x, v.y, acc0.y); acc0.y = fmaf(wp.y, v.x, acc0.y);
@@ -760,7 +758,7 @@ __global__ __launch_bounds__(1024) void k_recombine_folded(RecombParams P)
     }
     const int i3b = k3 + n3 * (H3lo + hbeg) - P.g0[2];       // output index of h = 0
     const RowOut ro = row_out(P, w, i2, i3b);
-    const bool full = wave_min_uniform(active ? 1 : 0) != 0;
+    const bool full = __ballot(active) == ~0ull;
     if constexpr (PAR && !MULTI) parity_order<N>(DE, DO, H3lo + hbeg);
     auto val = [&](int h) -> float {
         if constexpr (MULTI) return I[h];
