@@ -48,6 +48,14 @@ def kernel_source_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
+def _after_probe(rows):
+    """The dispatches issued after the copy probe's fill kernel: the timed steps and
+    their warmup, not the plan tuning that comes before the probe."""
+    marks = [int(r["Dispatch_Id"]) for r in rows if "FillFunctor" in r["Kernel_Name"]]
+    first = max(marks) if marks else -1
+    return [r for r in rows if int(r["Dispatch_Id"]) > first]
+
+
 def summarize_pmc(fetch_dir, write_dir, out_md, command):
     """Turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) into the
     traffic summary: per-launch HBM bytes of the recombination, scaled by the ratio of
@@ -55,63 +63,74 @@ def summarize_pmc(fetch_dir, write_dir, out_md, command):
     def per_kernel(d, counter):
         vals = {}
         for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
-            for r in csv.DictReader(open(path)):
-                if r["Counter_Name"] == counter:
-                    vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
+            rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+            for r in _after_probe(rows):
+                vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
         return vals
     fetch, write = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
 
     def probe(vals):
         cands = [max(v) for k, v in vals.items() if "copyBuffer" in k]
         return max(cands) if cands else None
+
+    def step_kernel(vals):
+        ks = [k for k in vals if "k_recombine" in k]
+        return max(ks, key=lambda k: len(vals[k])) if ks else None
     pf, pw = probe(fetch), probe(write)
-    kf = [v for k, v in fetch.items() if "k_recombine" in k]
-    kw = [v for k, v in write.items() if "k_recombine" in k]
-    if not kf or not kw or not pf or not pw:
+    nf, nw = step_kernel(fetch), step_kernel(write)
+    if not nf or not nw or not pf or not pw:
         raise SystemExit("summarize: recombination or copy probe missing in the counter files")
+    kf, kw = fetch[nf], write[nw]
     sf, sw = COPY_PROBE_BYTES / pf, COPY_PROBE_BYTES / pw
-    f_avg = sum(kf[0]) / len(kf[0]) * sf
-    w_avg = sum(kw[0]) / len(kw[0]) * sw
-    rec = {"kernel": "recombine", "source_hash": kernel_source_hash(), "fetch_bytes": f_avg,
-           "write_bytes": w_avg, "traffic_bytes": f_avg + w_avg, "copy_probe_bytes": COPY_PROBE_BYTES,
-           "fetch_scale": sf, "write_scale": sw}
+    f_avg = sum(kf) / len(kf) * sf
+    w_avg = sum(kw) / len(kw) * sw
+    rec = {"kernel": "recombine", "kernel_name": nf, "source_hash": kernel_source_hash(),
+           "fetch_bytes": f_avg, "write_bytes": w_avg, "traffic_bytes": f_avg + w_avg,
+           "copy_probe_bytes": COPY_PROBE_BYTES, "fetch_scale": sf, "write_scale": sw}
     with open(out_md, "w") as f:
         f.write("# HBM traffic of the recombination kernel (displacive 32^3, Taylor order 8, "
                 "513^3 box grown by the Lanczos window)\n\n")
         f.write("Two rocprofv3 PMC runs of the benchmark (`FETCH_SIZE`, then `WRITE_SIZE`, KiB per "
                 "dispatch), each scaled by copy-probe bytes / counter reading of the plain device "
-                "copy of %d MiB issued by the benchmark (fetch scale %.4f, write scale %.4f).\n\n"
-                % (COPY_PROBE_BYTES >> 20, sf, sw))
+                "copy of %d MiB issued by the benchmark (fetch scale %.4f, write scale %.4f).  Only "
+                "the dispatches after the probe count (the plan tuning runs before it).  Kernel: "
+                "`%s`, %d launches.\n\n" % (COPY_PROBE_BYTES >> 20, sf, sw, nf, len(kf)))
         f.write("Command:\n\n```\n%s\n```\n\n" % command)
         f.write("| counter | raw per launch (bytes) | scaled (bytes) |\n|---|---|---|\n")
-        f.write("| FETCH_SIZE | %.0f | %.0f |\n" % (sum(kf[0]) / len(kf[0]), f_avg))
-        f.write("| WRITE_SIZE | %.0f | %.0f |\n\n" % (sum(kw[0]) / len(kw[0]), w_avg))
+        f.write("| FETCH_SIZE | %.0f | %.0f |\n" % (sum(kf) / len(kf), f_avg))
+        f.write("| WRITE_SIZE | %.0f | %.0f |\n\n" % (sum(kw) / len(kw), w_avg))
         f.write("```json\n%s\n```\n" % json.dumps(rec))
     return rec
 
 
 def summarize_ktrace(trace_dir, out_md, command):
-    """Kernel-time summary from a rocprofv3 --kernel-trace --stats folder: per kernel,
-    calls and average / min / max duration (the recombination's average must agree
-    with the benchmark's HIP-event launch time)."""
-    paths = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
+    """Kernel-time summary from a rocprofv3 --kernel-trace folder: per kernel, calls and
+    average / min / max duration of the dispatches after the copy probe (the timed
+    steps and their warmup; the recombination's average must agree with the
+    benchmark's HIP-event launch time)."""
+    paths = glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)
     if not paths:
-        raise SystemExit("summarize: no kernel_stats.csv under " + trace_dir)
-    rows = list(csv.DictReader(open(paths[0])))
-    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+        raise SystemExit("summarize: no kernel_trace.csv under " + trace_dir)
+    rows = _after_probe(list(csv.DictReader(open(paths[0]))))
+    per = {}
+    for r in rows:
+        per.setdefault(r["Kernel_Name"], []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    total = sum(sum(v) for v in per.values())
+    order = sorted(per, key=lambda k: -sum(per[k]))
     with open(out_md, "w") as f:
         f.write("# Kernel time, displacive 32^3 fcc, Taylor order 8, 513^3 box, Lanczos m = 2\n\n")
-        f.write("rocprofv3 kernel trace of the benchmark's filtered steps only (`--only-steps`: "
-                "set_sites_async + noise_filter per step, plus the plain device copy used as the "
-                "PMC probe).  MI355X, one GPU.\n\nCommand (run from /tmp with TMPDIR=/tmp, "
-                "R = repository root):\n\n```\n%s\n```\n\n" % command)
+        f.write("rocprofv3 kernel trace of the benchmark's filtered steps (`--only-steps`: "
+                "set_sites_async + noise_filter per step, warmup and timed steps), i.e. the "
+                "dispatches after the plain device copy used as the PMC probe; the plan tuning "
+                "before it is left out.  MI355X, one GPU.\n\nCommand (run from /tmp with "
+                "TMPDIR=/tmp, R = repository root):\n\n```\n%s\n```\n\n" % command)
         f.write("| kernel | calls | average (us) | min (us) | max (us) | share of GPU time |\n"
                 "|---|---|---|---|---|---|\n")
-        for r in rows:
-            f.write("| `%s` | %s | %.1f | %.1f | %.1f | %.2f %% |\n" % (
-                r["Name"], r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
-                float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
-    return len(rows)
+        for k in order:
+            v = per[k]
+            f.write("| `%s` | %d | %.1f | %.1f | %.1f | %.2f %% |\n" % (
+                k, len(v), sum(v) / len(v) / 1e3, min(v) / 1e3, max(v) / 1e3, 100.0 * sum(v) / total))
+    return len(order)
 
 
 def stored_traffic():
