@@ -470,8 +470,12 @@ __global__ __launch_bounds__(512, 4) void k_recombine_nuclear(RecombParams P)
 // Level A reads the spectra straight from the (L2-resident) column: every thread
 // owns (pair, k3) items and accumulates the sites of a class in registers, with the
 // loads of the next site in flight, so the level needs no staging and no barrier.
+// One configuration in the parity form: at most 80 VGPRs, so that three 512-thread sliced
+// blocks share a CU (their LDS fits too); the multi-configuration form keeps its |F|^2
+// accumulators and the class form its per-H3 structure factors in registers.
 template <int N, int HC, bool MULTI, bool PAR>
-__global__ __launch_bounds__(1024) void k_recombine_folded(RecombParams P)
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu((!MULTI && PAR) ? 6 : 4)))
+void k_recombine_folded(RecombParams P)
 {
     extern __shared__ float2 smem[];
     constexpr int QR = n_pairs(N);
@@ -581,7 +585,9 @@ __global__ __launch_bounds__(1024) void k_recombine_folded(RecombParams P)
     const uint32_t xbytes = (uint32_t)((size_t)n1 * n2 * SFnh * sizeof(float2));
     const __amdgpu_buffer_rsrc_t rk = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<float2*>(P.tabK3), (short)0, (int)(P.S * n3 * sizeof(float2)), kBufferFlags);
-    for (int m = 0; m < P.M; ++m) {
+    // (one configuration: a constant trip count, so the coefficient sets leave no loop)
+    const int nconf = MULTI ? P.M : 1;
+    for (int m = 0; m < nconf; ++m) {
         const float2* Xm = P.X + (size_t)m * n1 * n2 * SFnh;
         const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<float2*>(Xm), (short)0, (int)xbytes, kBufferFlags);
@@ -699,16 +705,18 @@ __global__ __launch_bounds__(1024) void k_recombine_folded(RecombParams P)
         for (int h = 0; h < NF; ++h) F[h] = make_float2(0.f, 0.f);
 #pragma unroll
         for (int r = 0; r <= N; ++r) { DE[r] = make_float2(0.f, 0.f); DO[r] = make_float2(0.f, 0.f); }
-        if (active) {
+        // (every lane: an inactive one evaluates a valid item of its block whose values are
+        // never written, which keeps the wave free of merges)
+        {
             for (int c = 0; c < P.nclass; ++c) {
                 const float2* Bp = Bs + ((size_t)(c * L2 + rho) * n3s + (k3 - k3a)) * QR;
                 const float sgn = PAR ? (float)P.class_sign[c] : 1.f;
                 float2 D[PAR ? 1 : N + 1];
 #pragma unroll
                 for (int r = 0; r <= N; ++r) {
-                    float2 C = make_float2(0.f, 0.f);
+                    float2 C = Bp[pair_index(0, r)];          // q = 0: a2[0] = 1
 #pragma unroll
-                    for (int q = 0; q + r <= N; ++q) {
+                    for (int q = 1; q + r <= N; ++q) {
                         const float2 v = Bp[pair_index(q, r)];
                         const float a = a2[q];
                         // C += i^q a v
