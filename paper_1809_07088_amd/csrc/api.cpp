@@ -230,7 +230,7 @@ struct dsx_model_s {
     // plan knobs (defaults, or chosen by the autotuner for this model's key)
     int tune_recomb_variant = 0;   // 0 default form, 2 class form, 3 unfolded, 4 unsliced
     int tune_fchunk = 0;           // fields per FFT plane block (0 = heuristic)
-    int tune_lanczos_t1 = 16;      // planes per filter block
+    int tune_lanczos_t1 = 12;      // planes per filter block
     bool tuned = false;
     // state
     std::vector<char> set;
@@ -1288,7 +1288,7 @@ dsx_status dsx_autotune(dsx_model m, int32_t lanczos_m, void* hip_stream)
     if (lanczos_m != 0 && (s = check_filter_args(lanczos_m, 1)) != DSX_OK) return s;
     hipStream_t st = (hipStream_t)hip_stream;
     const std::string key = tune_key(m, lanczos_m);
-    int v = 0, fc = 0, t1 = 16;
+    int v = 0, fc = 0, t1 = 12;
     if (tune_lookup(key, &v, &fc, &t1)) {
         m->tune_recomb_variant = v; m->tune_fchunk = fc; m->tune_lanczos_t1 = t1;
         m->tuned = true;
@@ -1325,10 +1325,10 @@ dsx_status dsx_autotune(dsx_model m, int32_t lanczos_m, void* hip_stream)
     }
     m->tune_recomb_variant = best_v;
     // filter: planes per block
-    int best_t1 = 16;
+    int best_t1 = 12;
     if (filt) {
         best = -1.f;
-        for (int cand : {16, 32, 64}) {
+        for (int cand : {8, 12, 16, 20, 26, 32, 52, 64}) {
             m->tune_lanczos_t1 = cand;
             const float t = time_min(st, 3, [&] { return enqueue_filter(m, lanczos_m, 1, scratch, st, false); });
             if (t >= 0.f && (best < 0.f || t < best)) { best = t; best_t1 = cand; }
