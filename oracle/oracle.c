@@ -24,7 +24,10 @@
  *                    nearest-image convention (Sec. II, Eq. intensity_dble_sum).
  *   orc_lanczos      the windowed-sinc resampling of Sec. V.B (Eqs.
  *                    intensity_convol_finite, windowed_sinc, weight_sinc, lanczos)
- *                    summed directly over the (2m)^3 neighbourhood, NOT separably.
+ *                    summed directly over the (2m)^3 neighbourhood, NOT separably;
+ *                    orc_lanczos_cutoff the same with the cutoff of the m' modification
+ *                    (Sec. V.B, the second of the three modifications), and
+ *                    orc_lanczos_points at arbitrary Q (not on the s-grid).
  *
  * The lattice-point part of every phase is reduced exactly in integers first:
  * e^{2 pi i G_a R_a / n_a} = e^{2 pi i ((G_a R_a) mod n_a) / n_a}.  This is an
@@ -214,28 +217,55 @@ int orc_pair_sum(const int32_t* n, int32_t S, const double* frac, const double* 
 static double sinc(double x) { return x == 0.0 ? 1.0 : sin(x) / x; }
 
 /* One-axis factor of the windowed-sinc weight W = W_sinc * L:
- * 2 r_cut sinc(2 pi r_cut d) * [ |d| < m ] sinc(pi d / m), with r_cut = (1 - 1/m)/2. */
-static double lanczos_axis(double d, int m)
+ * 2 r_cut sinc(2 pi r_cut d) * [ |d| < w ] sinc(pi d / w).  The plain filter has
+ * r_cut = (1 - 1/m)/2 and w = m; the m' modification takes r_cut = (1 - 1/m)/m' and
+ * replaces m by w = m m'/2 in the window, so that m' = 2 is the plain filter. */
+static double lanczos_axis(double d, int m, int mp)
 {
-    const double rcut = 0.5 * (1.0 - 1.0 / m);
-    if (!(fabs(d) < (double)m)) return 0.0;
-    return 2.0 * rcut * sinc(TWO_PI * rcut * d) * sinc(M_PI * d / m);
+    const double rcut = (1.0 - 1.0 / m) / mp;
+    const double w = 0.5 * m * mp;
+    if (!(fabs(d) < w)) return 0.0;
+    return 2.0 * rcut * sinc(TWO_PI * rcut * d) * sinc(M_PI * d / w);
 }
 
-/* Windowed-sinc resampling, direct (2m)^3 sum.
+/* Windowed sum at one Q: G_a in [floor(Q_a) - w + 1, floor(Q_a) + w] with w = m m'/2.
+ * Returns -1 if a needed G lies outside the input box. */
+static int lanczos_at(const double* Q, int m, int mp, const int32_t* e0, const int32_t* ecount,
+                      const double* I, double* out)
+{
+    const long w = (long)m * mp / 2;
+    const long f[3] = {(long)floor(Q[0]), (long)floor(Q[1]), (long)floor(Q[2])};
+    double num = 0.0, den = 0.0;
+    for (long G1 = f[0] - w + 1; G1 <= f[0] + w; ++G1)
+    for (long G2 = f[1] - w + 1; G2 <= f[1] + w; ++G2)
+    for (long G3 = f[2] - w + 1; G3 <= f[2] + w; ++G3) {
+        const long j1 = G1 - e0[0], j2 = G2 - e0[1], j3 = G3 - e0[2];
+        if (j1 < 0 || j2 < 0 || j3 < 0 || j1 >= ecount[0] || j2 >= ecount[1] || j3 >= ecount[2]) return -1;
+        const double W = lanczos_axis(Q[0] - G1, m, mp) * lanczos_axis(Q[1] - G2, m, mp) *
+                         lanczos_axis(Q[2] - G3, m, mp);
+        num += W * I[(j1 * ecount[1] + j2) * ecount[2] + j3];
+        den += W;
+    }
+    *out = num / den;
+    return 0;
+}
+
+/* Windowed-sinc resampling, direct (2w)^3 sum, w = m m'/2 (mp = m' >= 2, m m' even).
  * Input I(G) on the box [e0, e0 + ecount) (last axis fastest).
  * Output I(Q) at Q_a = q0_a + i_a / s for i_a in [0, qcount_a) (last axis fastest):
  *   I(Q) = sum_G I(G) W(Q - G) / sum_G W(Q - G),
- *   G_a in [floor(Q_a) - m + 1, floor(Q_a) + m].
+ *   G_a in [floor(Q_a) - w + 1, floor(Q_a) + w].
  * Returns -1 if a needed G lies outside the input box. */
-int orc_lanczos(int32_t m, int32_t s, const int32_t* e0, const int32_t* ecount, const double* I,
-                const int32_t* q0, const int32_t* qcount, double* out)
+int orc_lanczos_cutoff(int32_t m, int32_t mp, int32_t s, const int32_t* e0, const int32_t* ecount,
+                       const double* I, const int32_t* q0, const int32_t* qcount, double* out)
 {
-    if (m < 2 || s < 1 || !e0 || !ecount || !I || !q0 || !qcount || !out) return -1;
+    if (m < 2 || mp < 2 || (m * mp) % 2 != 0 || s < 1 || !e0 || !ecount || !I || !q0 || !qcount || !out)
+        return -1;
+    const long w = (long)m * mp / 2;
     /* range check over the whole output first */
     for (int a = 0; a < 3; ++a) {
-        const long lo = (long)q0[a] - m + 1;
-        const long hi = (long)q0[a] + (qcount[a] - 1) / s + m;
+        const long lo = (long)q0[a] - w + 1;
+        const long hi = (long)q0[a] + (qcount[a] - 1) / s + w;
         if (lo < e0[a] || hi >= (long)e0[a] + ecount[a]) return -1;
     }
     const long total = (long)qcount[0] * qcount[1] * qcount[2];
@@ -244,19 +274,28 @@ int orc_lanczos(int32_t m, int32_t s, const int32_t* e0, const int32_t* ecount, 
     for (long idx = 0; idx < total; ++idx) {
         const long i3 = idx % qcount[2], i2 = (idx / qcount[2]) % qcount[1], i1 = idx / ((long)qcount[2] * qcount[1]);
         const double Q[3] = {q0[0] + (double)i1 / s, q0[1] + (double)i2 / s, q0[2] + (double)i3 / s};
-        const long f[3] = {(long)floor(Q[0]), (long)floor(Q[1]), (long)floor(Q[2])};
-        double num = 0.0, den = 0.0;
-        for (long G1 = f[0] - m + 1; G1 <= f[0] + m; ++G1)
-        for (long G2 = f[1] - m + 1; G2 <= f[1] + m; ++G2)
-        for (long G3 = f[2] - m + 1; G3 <= f[2] + m; ++G3) {
-            const double W = lanczos_axis(Q[0] - G1, m) * lanczos_axis(Q[1] - G2, m) * lanczos_axis(Q[2] - G3, m);
-            const long j1 = G1 - e0[0], j2 = G2 - e0[1], j3 = G3 - e0[2];
-            if (j1 < 0 || j2 < 0 || j3 < 0 || j1 >= ecount[0] || j2 >= ecount[1] || j3 >= ecount[2]) { bad = 1; continue; }
-            num += W * I[(j1 * ecount[1] + j2) * ecount[2] + j3];
-            den += W;
-        }
-        out[idx] = num / den;
+        if (lanczos_at(Q, m, mp, e0, ecount, I, &out[idx]) != 0) bad = 1;
     }
+    return bad ? -1 : 0;
+}
+
+int orc_lanczos(int32_t m, int32_t s, const int32_t* e0, const int32_t* ecount, const double* I,
+                const int32_t* q0, const int32_t* qcount, double* out)
+{
+    return orc_lanczos_cutoff(m, 2, s, e0, ecount, I, q0, qcount, out);
+}
+
+/* The same windowed sum at npts arbitrary points Q[npts][3] (reciprocal-lattice
+ * units, any direction, e.g. an off-axis plane).  Returns -1 if a needed G lies
+ * outside the input box. */
+int orc_lanczos_points(int32_t m, int32_t mp, const int32_t* e0, const int32_t* ecount, const double* I,
+                       int64_t npts, const double* Q, double* out)
+{
+    if (m < 2 || mp < 2 || (m * mp) % 2 != 0 || npts < 0 || !e0 || !ecount || !I || !Q || !out) return -1;
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(|:bad)
+    for (int64_t i = 0; i < npts; ++i)
+        if (lanczos_at(Q + 3 * i, m, mp, e0, ecount, I, &out[i]) != 0) bad = 1;
     return bad ? -1 : 0;
 }
 

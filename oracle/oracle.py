@@ -76,7 +76,10 @@ def lib():
         L.orc_sf_magnetic.argtypes = [P, i32, P, P, i32, P, P, i64, P, P]
         L.orc_pair_sum.argtypes = [P, i32, P, P, P, P, f64, i64, P, P]
         L.orc_lanczos.argtypes = [i32, i32, P, P, P, P, P, P]
-        for f in (L.orc_sf_nuclear, L.orc_sf_magnetic, L.orc_pair_sum, L.orc_lanczos):
+        L.orc_lanczos_cutoff.argtypes = [i32, i32, i32, P, P, P, P, P, P]
+        L.orc_lanczos_points.argtypes = [i32, i32, P, P, P, i64, P, P]
+        for f in (L.orc_sf_nuclear, L.orc_sf_magnetic, L.orc_pair_sum, L.orc_lanczos,
+                  L.orc_lanczos_cutoff, L.orc_lanczos_points):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -241,8 +244,9 @@ def pair_sum(model, member, G) -> np.ndarray:
     return out[:, 0] + 1j * out[:, 1]
 
 
-def lanczos(I_ext, e0, m, s, q0, qcount) -> np.ndarray:
-    """Windowed-sinc resampling by the direct (2m)^3 sum (Sec. V.B).
+def lanczos(I_ext, e0, m, s, q0, qcount, mprime=2) -> np.ndarray:
+    """Windowed-sinc resampling by the direct (2w)^3 sum (Sec. V.B), w = m m'/2; the
+    cutoff modification m' > 2 takes r_cut = (1 - 1/m)/m' (m' = 2: the plain filter).
     I_ext: float array [e1][e2][e3] on the box starting at e0; output on
     Q_a = q0_a + i_a / s, i_a < qcount_a, float64 [q1][q2][q3]."""
     I_ext = np.ascontiguousarray(I_ext, dtype=np.float64)
@@ -251,21 +255,61 @@ def lanczos(I_ext, e0, m, s, q0, qcount) -> np.ndarray:
     q0 = np.ascontiguousarray(q0, dtype=np.int32)
     qc = np.ascontiguousarray(qcount, dtype=np.int32)
     out = np.zeros(tuple(int(v) for v in qcount), dtype=np.float64)
-    rc = lib().orc_lanczos(int(m), int(s), _ptr(e0), _ptr(ec), _ptr(I_ext), _ptr(q0), _ptr(qc),
-                           _ptr(out))
+    if mprime == 2:
+        rc = lib().orc_lanczos(int(m), int(s), _ptr(e0), _ptr(ec), _ptr(I_ext), _ptr(q0), _ptr(qc),
+                               _ptr(out))
+    else:
+        rc = lib().orc_lanczos_cutoff(int(m), int(mprime), int(s), _ptr(e0), _ptr(ec), _ptr(I_ext),
+                                      _ptr(q0), _ptr(qc), _ptr(out))
     if rc != 0:
         raise ValueError("orc_lanczos: bad arguments or input box too small for the window")
     return out
 
 
-def filtered_intensity(model, m, s=1, order=None) -> np.ndarray:
-    """The model box filtered with Lanczos parameter m: I(G) is summed directly on the
-    box grown by m on every side, then resampled by the direct (2m)^3 sum."""
-    e0 = [model.g0[a] - m for a in range(3)]
-    ec = [model.count[a] + 2 * m for a in range(3)]
+def lanczos_points(I_ext, e0, m, Q, mprime=2) -> np.ndarray:
+    """The windowed-sinc sum of lanczos() at arbitrary points Q [npts][3] (reciprocal
+    lattice units of the supercell Bragg grid G, any direction).  float64 [npts]."""
+    I_ext = np.ascontiguousarray(I_ext, dtype=np.float64)
+    e0 = np.ascontiguousarray(e0, dtype=np.int32)
+    ec = np.ascontiguousarray(I_ext.shape, dtype=np.int32)
+    Q = np.ascontiguousarray(Q, dtype=np.float64).reshape(-1, 3)
+    out = np.zeros(Q.shape[0], dtype=np.float64)
+    rc = lib().orc_lanczos_points(int(m), int(mprime), _ptr(e0), _ptr(ec), _ptr(I_ext), Q.shape[0],
+                                  _ptr(Q), _ptr(out))
+    if rc != 0:
+        raise ValueError("orc_lanczos_points: bad arguments or input box too small for the window")
+    return out
+
+
+def window_halfwidth(m, mprime=2) -> int:
+    """w = m m'/2: the window spans G_a in [floor(Q_a) - w + 1, floor(Q_a) + w]."""
+    if m < 2 or mprime < 2 or (m * mprime) % 2:
+        raise ValueError("need m >= 2, m' >= 2 and m m' even")
+    return m * mprime // 2
+
+
+def filtered_intensity(model, m, s=1, order=None, mprime=2) -> np.ndarray:
+    """The model box filtered with Lanczos parameter m (and cutoff modification m'):
+    I(G) is summed directly on the box grown by w = m m'/2 on every side, then
+    resampled by the direct (2w)^3 sum."""
+    w = window_halfwidth(m, mprime)
+    e0 = [model.g0[a] - w for a in range(3)]
+    ec = [model.count[a] + 2 * w for a in range(3)]
     I_ext = intensity(model, grid_points(e0, ec), order).reshape(ec)
     qc = [s * model.count[a] for a in range(3)]
-    return lanczos(I_ext, e0, m, s, model.g0, qc)
+    return lanczos(I_ext, e0, m, s, model.g0, qc, mprime)
+
+
+def filtered_points(model, m, Q, order=None, mprime=2) -> np.ndarray:
+    """I(Q) at arbitrary points Q [npts][3]: I(G) summed directly on the smallest box
+    holding every window, then the direct windowed sum at each point."""
+    w = window_halfwidth(m, mprime)
+    Q = np.asarray(Q, dtype=np.float64).reshape(-1, 3)
+    f = np.floor(Q).astype(np.int64)
+    e0 = (f.min(axis=0) - w + 1).astype(np.int32)
+    ec = (f.max(axis=0) + w - e0 + 1).astype(np.int32)
+    I_ext = intensity(model, grid_points(e0, ec), order).reshape(ec)
+    return lanczos_points(I_ext, e0, m, Q, mprime)
 
 
 # ----------------------------------------------------------------------------- FFT route

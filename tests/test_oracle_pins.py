@@ -252,6 +252,61 @@ def test_lanczos_m2_weights_closed_form():
     assert abs(w1 - 0.405285) < 1e-6
 
 
+# ------------------------------------------------- P8' cutoff modification, arbitrary Q
+
+def _cosine_response(m, mp, dr):
+    """Filter I(G) = 1 + cos(2 pi G1 dr) (one real-space separation dr along axis 1)
+    and read the attenuation of the cosine at Q = 0."""
+    w = O.window_halfwidth(m, mp)
+    e0 = np.array([-w - 2, -w - 2, -w - 2])
+    cnt = 2 * w + 5
+    G1 = e0[0] + np.arange(cnt)
+    I = np.broadcast_to((1.0 + np.cos(2 * np.pi * G1 * dr))[:, None, None], (cnt, cnt, cnt))
+    out = O.lanczos(I, e0, m, 1, [0, 0, 0], [1, 1, 1], mp)
+    return float(out[0, 0, 0]) - 1.0
+
+
+@pytest.mark.parametrize("m,mp", [(2, 4), (3, 4), (2, 3), (4, 3)])
+def test_cutoff_variant_reaches_zero_at_one_over_mprime(m, mp):
+    """The m' modification (Sec. V.B): the real-space cutoff of the filter reaches 0
+    at |dr| = 1/m' instead of 1/2, and stays near 1 at short range."""
+    assert _cosine_response(m, mp, 0.02) > 0.95
+    for dr in (1 / mp + 0.06, 1 / mp + 0.12, 0.5):
+        assert abs(_cosine_response(m, mp, dr)) < 0.03
+    # the plain filter (m' = 2) still passes a large part of a separation 1/m' + 0.06
+    assert _cosine_response(m, 2, 1 / mp + 0.06) > 0.1
+
+
+def test_cutoff_variant_m2_is_close_to_the_triangle():
+    # m = 2: the idealized cutoff is the triangle 1 - m'|dr| for |dr| < 1/m'
+    for mp in (3, 4):
+        half = _cosine_response(2, mp, 0.5 / mp)
+        assert 0.4 < half < 0.7
+
+
+def test_points_match_the_grid_filter_and_are_mirror_symmetric():
+    rng = np.random.default_rng(5)
+    e0 = np.array([-9, -9, -9])
+    A = rng.random((19, 19, 19))
+    I = A + A[::-1, ::-1, ::-1]                 # I(G) = I(-G) on the box symmetric about 0
+    for m, mp, s in [(2, 2, 2), (2, 4, 1), (3, 2, 3)]:
+        w = O.window_halfwidth(m, mp)
+        q0 = [-9 + w, -9 + w, -9 + w]
+        qc = [max(1, (19 - 2 * w - 1) * s)] * 3
+        box = O.lanczos(I, e0, m, s, q0, qc, mp)
+        idx = np.stack(np.meshgrid(*[np.arange(c) for c in qc], indexing="ij"), -1).reshape(-1, 3)
+        Q = np.asarray(q0) + idx / s
+        assert np.allclose(O.lanczos_points(I, e0, m, Q, mp), box.reshape(-1), rtol=1e-13, atol=1e-14)
+    # off-axis points of an (h h l) plane, away from the grid: I(Q) = I(-Q), constants kept
+    h, l = np.meshgrid(np.linspace(-2.37, 2.41, 9), np.linspace(-1.93, 2.07, 7), indexing="ij")
+    Q = np.stack([h, h, l], -1).reshape(-1, 3)
+    for m, mp in [(2, 2), (2, 4)]:
+        a = O.lanczos_points(I, e0, m, Q, mp)
+        b = O.lanczos_points(I, e0, m, -Q, mp)
+        assert np.allclose(a, b, rtol=1e-12)
+        assert np.allclose(O.lanczos_points(np.full_like(I, 2.5), e0, m, Q, mp), 2.5, rtol=1e-13)
+
+
 # --------------------------------------------------------------------------- P9 brute force
 
 @pytest.mark.parametrize("seed", [11, 12])
