@@ -164,6 +164,37 @@ dsx_status dsx_noise_filter(dsx_model m, int32_t lanczos_m, int32_t oversample, 
                             int32_t where, void* hip_stream);
 
 /*
+ * The same resampling with the cutoff modification of Sec. V.B (the second of the
+ * three modifications listed after Eq. lanczos): r_cut = (1 - 1/m)/m' in Eq.
+ * weight_sinc and m replaced by m m'/2 in Eq. lanczos, so that the idealized
+ * real-space cutoff reaches 0 at |dr| = 1/m' (stronger noise suppression).  The
+ * window spans G_a in [floor(Q_a) - w + 1, floor(Q_a) + w], w = m m'/2, and I(G) is
+ * computed on the box grown by w.  mprime = 2 is dsx_noise_filter.
+ * Requires mprime >= 2, lanczos_m * mprime even (w whole) and w <= 16; output and
+ * `where` / stream rules as for dsx_noise_filter.
+ */
+dsx_status dsx_noise_filter_cutoff(dsx_model m, int32_t lanczos_m, int32_t mprime, int32_t oversample,
+                                   float* out, int32_t where, void* hip_stream);
+
+/*
+ * Lanczos resampling at arbitrary points Q (Sec. V.B; e.g. the off-axis (h h l)
+ * planes of Sec. V.B, which a grid along the reciprocal axes cannot hold):
+ * I(Q) = sum_G I(G) W(Q-G) / sum_G W(Q-G) over the (2w)^3 supercell Bragg points
+ * G_a in [floor(Q_a) - w + 1, floor(Q_a) + w], w = m m'/2, with the weight of
+ * dsx_noise_filter_cutoff (mprime = 2: the plain filter).  I(G) is computed on the
+ * smallest box holding every window.
+ *   q[npts][3]  host array, float64, Q in units of the supercell Bragg grid (the G
+ *               of dsx_set_grid: G_a = n_a times the reciprocal-lattice index);
+ *               finite, |Q_a| <= 1e6
+ *   out[npts]   float32, host (where = DSX_HOST) or device memory
+ * Returns when the result is complete (the call synchronises hip_stream).  Requires
+ * lanczos_m >= 2, mprime >= 2, lanczos_m * mprime even and w <= 8.  The model's grid
+ * itself is not used, but sites and a grid must be set (DSX_ERR_STATE otherwise).
+ */
+dsx_status dsx_filter_points(dsx_model m, int32_t lanczos_m, int32_t mprime, int64_t npts, const double* q,
+                             float* out, int32_t where, void* hip_stream);
+
+/*
  * Batched execution (an execution pattern; the arithmetic is that of
  * dsx_compute_intensity / dsx_noise_filter).  The paper prefers many small
  * supercells averaged as an ensemble (Sec. III.B) and notes that their intensity

@@ -50,6 +50,7 @@ class KernelStat(ctypes.Structure):
 EXPORTS = ("dsx_plan_query", "dsx_create_model", "dsx_set_sites", "dsx_set_sites_async", "dsx_set_grid",
            "dsx_compute_intensity", "dsx_noise_filter", "dsx_destroy_model", "dsx_last_error",
            "dsx_version", "dsx_profile_enable", "dsx_profile_read", "dsx_profile_reset",
+           "dsx_noise_filter_cutoff", "dsx_filter_points",
            "dsx_batch_create", "dsx_batch_run", "dsx_batch_destroy", "dsx_autotune", "dsx_tune_query",
            "dsx_server_create", "dsx_server_add_model", "dsx_server_submit", "dsx_server_wait",
            "dsx_server_stats_read", "dsx_server_destroy")
@@ -92,6 +93,10 @@ def lib():
         L.dsx_set_grid.argtypes = [P, P, P]
         L.dsx_compute_intensity.argtypes = [P, P, i32, P]
         L.dsx_noise_filter.argtypes = [P, i32, i32, P, i32, P]
+        L.dsx_noise_filter_cutoff.argtypes = [P, i32, i32, i32, P, i32, P]
+        L.dsx_noise_filter_cutoff.restype = i32
+        L.dsx_filter_points.argtypes = [P, i32, i32, ctypes.c_int64, P, P, i32, P]
+        L.dsx_filter_points.restype = i32
         L.dsx_destroy_model.argtypes = [P]
         L.dsx_last_error.argtypes = []
         L.dsx_last_error.restype = ctypes.c_char_p
@@ -229,6 +234,25 @@ def noise_filter(model, lanczos_m, oversample, out, stream=None):
     return out
 
 
+def noise_filter_cutoff(model, lanczos_m, mprime, oversample, out, stream=None):
+    """dsx_noise_filter_cutoff: the filter with the m' cutoff modification."""
+    p, where, _ = _ptr_where(out)
+    st = _stream_handle(stream) if where == DEVICE else None
+    _check(lib().dsx_noise_filter_cutoff(model, int(lanczos_m), int(mprime), int(oversample), p, where, st))
+    return out
+
+
+def filter_points(model, lanczos_m, q, out, mprime=2, stream=None):
+    """dsx_filter_points: the filter at arbitrary points q [npts][3] (float64 host
+    array, units of the supercell Bragg grid) into out [npts]."""
+    q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1, 3)
+    p, where, _ = _ptr_where(out)
+    st = _stream_handle(stream) if where == DEVICE else None
+    _check(lib().dsx_filter_points(model, int(lanczos_m), int(mprime), q.shape[0],
+                                   q.ctypes.data_as(ctypes.c_void_p), p, where, st))
+    return out
+
+
 def destroy_model(model):
     _check(lib().dsx_destroy_model(model))
 
@@ -319,6 +343,12 @@ class Model:
 
     def noise_filter(self, lanczos_m, oversample, out, stream=None):
         return noise_filter(self.handle, lanczos_m, oversample, out, stream)
+
+    def noise_filter_cutoff(self, lanczos_m, mprime, oversample, out, stream=None):
+        return noise_filter_cutoff(self.handle, lanczos_m, mprime, oversample, out, stream)
+
+    def filter_points(self, lanczos_m, q, out, mprime=2, stream=None):
+        return filter_points(self.handle, lanczos_m, q, out, mprime, stream)
 
     def autotune(self, lanczos_m=0, stream=None):
         autotune(self.handle, lanczos_m, stream)

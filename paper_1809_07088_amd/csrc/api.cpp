@@ -19,7 +19,9 @@
 #include <cstring>
 #include <fstream>
 #include <sstream>
+#include <climits>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <set>
 #include <string>
@@ -223,9 +225,11 @@ struct dsx_model_s {
     float2* d_X = nullptr;
     float2* d_tw[3] = {nullptr, nullptr, nullptr};
     float* d_ext = nullptr;   size_t ext_cap = 0;
+    float* d_pts = nullptr;   size_t pts_cap = 0;   // I(G) on the box of a point list's windows
+    double* d_q = nullptr;    size_t q_cap = 0;     // the point list
     float* d_stage = nullptr; size_t stage_cap = 0;
     std::map<Box, DeviceTables> tables;
-    std::map<std::pair<int, int>, float*> lanczos_w;
+    std::map<std::tuple<int, int, int>, float*> lanczos_w;   // (m, m', s) -> weights
     int sum_chunk = 256, sum_chunks = 0;   // cells per sums block, blocks per (config, site)
     // plan knobs (defaults, or chosen by the autotuner for this model's key)
     int tune_recomb_variant = 0;   // 0 default form, 2 class form, 3 unfolded, 4 unsliced
@@ -352,7 +356,7 @@ void free_model(dsx_model m)
     dfree(m->d_occ); dfree(m->d_vec); dfree(m->d_partial); dfree(m->d_sums); dfree(m->d_X);
     dfree(m->d_site);
     for (auto& t : m->d_tw) dfree(t);
-    dfree(m->d_ext); dfree(m->d_stage);
+    dfree(m->d_ext); dfree(m->d_stage); dfree(m->d_pts); dfree(m->d_q);
     for (auto& kv : m->tables) {
         dfree(kv.second.tab1); dfree(kv.second.tab2); dfree(kv.second.tabK3); dfree(kv.second.tabH3);
         dfree(kv.second.work);
@@ -1094,8 +1098,11 @@ Layout ext_layout(const Box& ext)
 size_t ext_elems(const Box& ext) { return (size_t)stored_planes(ext) * ext.cnt[1] * ext_layout(ext).pitch; }
 
 // Everything the filter needs that allocates or uploads (never inside a capture).
-dsx_status prepare_filter(dsx_model m, int mm, int sv)
+// lm = m of the filter, mp = m' of its cutoff modification (2: none); the window's
+// half-width is lm mp / 2.
+dsx_status prepare_filter(dsx_model m, int lm, int sv, int mp = 2)
 {
+    const int mm = lm * mp / 2;
     const Box ext = filter_box(m->box, mm);
     const size_t ext_vox = ext_elems(ext);
     if (m->ext_cap < ext_vox) {
@@ -1107,10 +1114,10 @@ dsx_status prepare_filter(dsx_model m, int mm, int sv)
         HIPCHK(m, e);
         m->ext_cap = ext_vox;
     }
-    // normalised weights [s][2m]
-    const auto key = std::make_pair(mm, sv);
+    // normalised weights [s][2 mm]; r_cut = (1 - 1/m)/m' (Sec. V.B; m' = 2: (1 - 1/m)/2)
+    const auto key = std::make_tuple(lm, mp, sv);
     if (!m->lanczos_w.count(key)) {
-        const double rcut = 0.5 * (1.0 - 1.0 / mm);
+        const double rcut = (1.0 - 1.0 / lm) / mp;
         auto sinc = [](double x) { return x == 0.0 ? 1.0 : std::sin(x) / x; };
         std::vector<float> w((size_t)sv * 2 * mm);
         for (int j = 0; j < sv; ++j) {
@@ -1140,15 +1147,16 @@ dsx_status prepare_intensity(dsx_model m)
 
 // Stream-ordered launches only: spectra (when stale or forced), recombination on
 // the grown box, Bragg points, filter.
-dsx_status enqueue_filter(dsx_model m, int mm, int sv, float* dout, hipStream_t st, bool force)
+dsx_status enqueue_filter(dsx_model m, int lm, int sv, float* dout, hipStream_t st, bool force, int mp = 2)
 {
     dsx_status s;
+    const int mm = lm * mp / 2;
     const Box ext = filter_box(m->box, mm);
     if ((s = ensure_spectra(m, st, force)) != DSX_OK) return s;
     const Layout el = ext_layout(ext);
     if ((s = run_box(m, ext, m->d_ext, el, st)) != DSX_OK) return s;
     LanczosParams lp{};
-    lp.in = m->d_ext; lp.out = dout; lp.wn = m->lanczos_w[std::make_pair(mm, sv)];
+    lp.in = m->d_ext; lp.out = dout; lp.wn = m->lanczos_w[std::make_tuple(lm, mp, sv)];
     lp.ipitch = el.pitch; lp.ioff = el.off;
     lp.ihalf = stored_planes(ext);
     for (int a = 0; a < 3; ++a) { lp.e[a] = ext.cnt[a]; lp.o[a] = sv * m->box.cnt[a]; }
@@ -1205,6 +1213,101 @@ dsx_status dsx_noise_filter(dsx_model m, int32_t lanczos_m, int32_t oversample, 
     if ((s = enqueue_filter(m, lanczos_m, oversample, dout, st, false)) != DSX_OK) return s;
     if (where == DSX_HOST) {
         HIPCHK(m, hipMemcpyAsync(out, dout, out_vox * sizeof(float), hipMemcpyDeviceToHost, st));
+        HIPCHK(m, hipStreamSynchronize(st));
+    }
+    return DSX_OK;
+}
+
+dsx_status dsx_noise_filter_cutoff(dsx_model m, int32_t lanczos_m, int32_t mprime, int32_t oversample,
+                                   float* out, int32_t where, void* hip_stream)
+{
+    dsx_status s = check_direct(m);
+    if (s != DSX_OK) return s;
+    if (!out) return fail(DSX_ERR_ARG, "out is NULL");
+    if (where != DSX_HOST && where != DSX_DEVICE) return fail(DSX_ERR_ARG, "bad 'where'");
+    if (mprime < 2 || (lanczos_m * mprime) % 2 != 0)
+        return fail(DSX_ERR_ARG, "mprime must be >= 2 with lanczos_m * mprime even");
+    if ((s = check_filter_args(lanczos_m, oversample)) != DSX_OK) return s;
+    if (lanczos_m * mprime / 2 > 16) return fail(DSX_ERR_UNSUPPORTED, "the window half-width m m'/2 is limited to 16");
+    if ((s = ready(m)) != DSX_OK) return s;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const size_t out_vox = (size_t)oversample * m->box.cnt[0] * oversample * m->box.cnt[1] *
+                           oversample * m->box.cnt[2];
+    if ((s = prepare_filter(m, lanczos_m, oversample, mprime)) != DSX_OK) return s;
+    float* dout = out;
+    if (where == DSX_HOST && (s = stage(m, out_vox, &dout)) != DSX_OK) return s;
+    if ((s = follow(m, st)) != DSX_OK) return s;
+    if ((s = enqueue_filter(m, lanczos_m, oversample, dout, st, false, mprime)) != DSX_OK) return s;
+    if (where == DSX_HOST) {
+        HIPCHK(m, hipMemcpyAsync(out, dout, out_vox * sizeof(float), hipMemcpyDeviceToHost, st));
+        HIPCHK(m, hipStreamSynchronize(st));
+    }
+    return DSX_OK;
+}
+
+dsx_status dsx_filter_points(dsx_model m, int32_t lanczos_m, int32_t mprime, int64_t npts, const double* q,
+                             float* out, int32_t where, void* hip_stream)
+{
+    dsx_status s = check_direct(m);
+    if (s != DSX_OK) return s;
+    if (npts < 0 || (npts > 0 && (!q || !out))) return fail(DSX_ERR_ARG, "bad point list");
+    if (where != DSX_HOST && where != DSX_DEVICE) return fail(DSX_ERR_ARG, "bad 'where'");
+    if (lanczos_m < 2 || mprime < 2 || (lanczos_m * mprime) % 2 != 0)
+        return fail(DSX_ERR_ARG, "need lanczos_m >= 2, mprime >= 2 and lanczos_m * mprime even");
+    const int w = lanczos_m * mprime / 2;
+    if (w > kPointsMaxHalfwidth) return fail(DSX_ERR_UNSUPPORTED, "the window half-width m m'/2 is limited to 8 here");
+    if ((s = ready(m)) != DSX_OK) return s;
+    if (npts == 0) return DSX_OK;
+    // the box of every window: floor(Q_a) - w + 1 .. floor(Q_a) + w
+    long lo[3] = {LONG_MAX, LONG_MAX, LONG_MAX}, hi[3] = {LONG_MIN, LONG_MIN, LONG_MIN};
+    for (int64_t i = 0; i < npts; ++i)
+        for (int a = 0; a < 3; ++a) {
+            const double v = q[3 * i + a];
+            if (!std::isfinite(v) || std::fabs(v) > 1e6) return fail(DSX_ERR_ARG, "points must be finite, |Q| <= 1e6");
+            const long f = (long)std::floor(v);
+            lo[a] = std::min(lo[a], f - w + 1);
+            hi[a] = std::max(hi[a], f + w);
+        }
+    Box bx;
+    for (int a = 0; a < 3; ++a) { bx.g0[a] = (int)lo[a]; bx.cnt[a] = (int)(hi[a] - lo[a] + 1); }
+    const size_t vox = (size_t)bx.cnt[0] * bx.cnt[1] * bx.cnt[2];
+    DeviceTables* tb = nullptr;
+    if ((s = tables_for(m, bx, &tb)) != DSX_OK) return s;
+    if (m->pts_cap < vox || m->q_cap < (size_t)npts) {
+        if (m->pins) return fail(DSX_ERR_BUSY, "a batch has recorded this model's buffers");
+    }
+    if (m->pts_cap < vox) {
+        dfree(m->d_pts); m->d_pts = nullptr; m->pts_cap = 0;
+        hipError_t e = hipMalloc(&m->d_pts, vox * sizeof(float));
+        if (e == hipErrorOutOfMemory) return fail(DSX_ERR_NOMEM, "out of device memory for the points' box");
+        HIPCHK(m, e);
+        m->pts_cap = vox;
+    }
+    if (m->q_cap < (size_t)npts) {
+        dfree(m->d_q); m->d_q = nullptr; m->q_cap = 0;
+        hipError_t e = hipMalloc(&m->d_q, (size_t)npts * 3 * sizeof(double));
+        if (e == hipErrorOutOfMemory) return fail(DSX_ERR_NOMEM, "out of device memory for the points");
+        HIPCHK(m, e);
+        m->q_cap = (size_t)npts;
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    float* dout = out;
+    if (where == DSX_HOST && (s = stage(m, (size_t)npts, &dout)) != DSX_OK) return s;
+    if ((s = follow(m, st)) != DSX_OK) return s;
+    HIPCHK(m, hipMemcpyAsync(m->d_q, q, (size_t)npts * 3 * sizeof(double), hipMemcpyHostToDevice, st));
+    if ((s = ensure_spectra(m, st, false)) != DSX_OK) return s;
+    if ((s = run_box(m, bx, m->d_pts, dense_layout(bx), st)) != DSX_OK) return s;
+    PointsParams pp{};
+    pp.in = m->d_pts; pp.q = m->d_q; pp.out = dout; pp.npts = npts;
+    for (int a = 0; a < 3; ++a) { pp.e0[a] = bx.g0[a]; pp.e[a] = bx.cnt[a]; }
+    pp.w = w;
+    pp.rcut = (float)((1.0 - 1.0 / lanczos_m) / mprime);
+    HIPCHK(m, timed("lanczos_points", st, [&] { return launch_lanczos_points(pp, st); }));
+    if (where == DSX_HOST) {
+        HIPCHK(m, hipMemcpyAsync(out, dout, (size_t)npts * sizeof(float), hipMemcpyDeviceToHost, st));
+        HIPCHK(m, hipStreamSynchronize(st));
+    } else {
+        // the point list is a host array read by the copy above: wait before returning
         HIPCHK(m, hipStreamSynchronize(st));
     }
     return DSX_OK;

@@ -159,6 +159,19 @@ struct LanczosParams {
     int32_t nb1, nb2, nb3;
 };
 
+// Windowed-sinc sum at arbitrary points Q (one thread per point): I(G) on the box
+// [e0, e0 + e) of every window, G_a in [floor(Q_a) - w + 1, floor(Q_a) + w].
+constexpr int kPointsMaxHalfwidth = 8;
+struct PointsParams {
+    const float* in;        // I(G) [e1][e2][e3], dense
+    const double* q;        // [npts][3] points in units of the supercell Bragg grid
+    float* out;             // [npts]
+    int64_t npts;
+    int32_t e0[3], e[3];
+    int32_t w;              // window half-width m m'/2 (<= kPointsMaxHalfwidth)
+    float rcut;             // (1 - 1/m)/m'
+};
+
 // ---------------------------------------------------------------------------- launchers
 hipError_t launch_sums(const SumsParams& p, int order, hipStream_t st);
 hipError_t launch_fft_planes(const PlaneParams& p, hipStream_t st);
@@ -169,6 +182,7 @@ hipError_t launch_recombine_magnetic(const RecombParams& p, int hc, int block, s
                                      hipStream_t st);
 hipError_t launch_bragg(const BraggParams& p, int order, hipStream_t st);
 hipError_t launch_lanczos(const LanczosParams& p, hipStream_t st);
+hipError_t launch_lanczos_points(const PointsParams& p, hipStream_t st);
 
 // Block sizes / LDS limits the host planner must respect.
 int recombine_max_threads(int hc, int magnetic);

@@ -282,4 +282,72 @@ hipError_t launch_lanczos(const LanczosParams& p, hipStream_t st)
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------- points
+// The windowed sum at arbitrary points (off-axis planes such as (h h l), any grid):
+// one thread per point forms the 2w one-axis weights of each axis (float, from the
+// float64 offsets Q_a - G_a), then sums the (2w)^3 neighbourhood from the dense box,
+// which the host sized to hold every window.  The normaliser is the product of the
+// three one-axis weight sums (the weight is separable).
+template <int W>
+__global__ __launch_bounds__(256) void k_lanczos_points(PointsParams P)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.npts) return;
+    float wt[3][2 * W];
+    int lo[3];
+    float norm = 1.f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double Q = P.q[3 * i + a];
+        const double f = floor(Q);
+        lo[a] = (int)f - W + 1 - P.e0[a];
+        float sum = 0.f;
+#pragma unroll
+        for (int t = 0; t < 2 * W; ++t) {
+            const float d = (float)(Q - (f - W + 1 + t));      // Q_a - G_a
+            float v = 0.f;
+            if (fabsf(d) < (float)W) {
+                const float x1 = 6.283185307179586f * P.rcut * d, x2 = 3.141592653589793f * d / (float)W;
+                v = (x1 == 0.f ? 1.f : sinf(x1) / x1) * (x2 == 0.f ? 1.f : sinf(x2) / x2);
+            }
+            wt[a][t] = v;
+            sum += v;
+        }
+        norm *= sum;
+    }
+    const size_t p2 = (size_t)P.e[2], p1 = (size_t)P.e[1] * P.e[2];
+    float acc = 0.f;
+    for (int t1 = 0; t1 < 2 * W; ++t1) {
+        const float* plane = P.in + (size_t)(lo[0] + t1) * p1;
+        float a1 = 0.f;
+#pragma unroll
+        for (int t2 = 0; t2 < 2 * W; ++t2) {
+            const float* row = plane + (size_t)(lo[1] + t2) * p2 + lo[2];
+            float a2 = 0.f;
+#pragma unroll
+            for (int t3 = 0; t3 < 2 * W; ++t3) a2 = fmaf(wt[2][t3], row[t3], a2);
+            a1 = fmaf(wt[1][t2], a2, a1);
+        }
+        acc = fmaf(wt[0][t1], a1, acc);
+    }
+    P.out[i] = acc / norm;
+}
+
+hipError_t launch_lanczos_points(const PointsParams& p, hipStream_t st)
+{
+    const dim3 grid((unsigned)((p.npts + 255) / 256));
+    switch (p.w) {
+        case 1: hipLaunchKernelGGL(k_lanczos_points<1>, grid, dim3(256), 0, st, p); break;
+        case 2: hipLaunchKernelGGL(k_lanczos_points<2>, grid, dim3(256), 0, st, p); break;
+        case 3: hipLaunchKernelGGL(k_lanczos_points<3>, grid, dim3(256), 0, st, p); break;
+        case 4: hipLaunchKernelGGL(k_lanczos_points<4>, grid, dim3(256), 0, st, p); break;
+        case 5: hipLaunchKernelGGL(k_lanczos_points<5>, grid, dim3(256), 0, st, p); break;
+        case 6: hipLaunchKernelGGL(k_lanczos_points<6>, grid, dim3(256), 0, st, p); break;
+        case 7: hipLaunchKernelGGL(k_lanczos_points<7>, grid, dim3(256), 0, st, p); break;
+        case 8: hipLaunchKernelGGL(k_lanczos_points<8>, grid, dim3(256), 0, st, p); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 }  // namespace dsx

@@ -44,11 +44,14 @@ def gpu_intensity(model, device=True):
     return res
 
 
-def gpu_filtered(model, m, s=1):
+def gpu_filtered(model, m, s=1, mprime=2):
     import torch
     h = to_dsx(model)
     out = torch.empty(tuple(s * c for c in model.count), dtype=torch.float32, device="cuda")
-    h.noise_filter(m, s, out)
+    if mprime == 2:
+        h.noise_filter(m, s, out)
+    else:
+        h.noise_filter_cutoff(m, mprime, s, out)
     torch.cuda.synchronize()
     res = out.cpu().numpy()
     h.close()

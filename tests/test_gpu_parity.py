@@ -296,3 +296,64 @@ def test_lanczos_symmetric_box_half_storage(lm, s):
     out = gpu_filtered(m, lm, s)
     ref = O.filtered_intensity(m, lm, s, order=3)
     assert rel_l2(out, ref) <= TOL
+
+
+# ------------------------------------------------------------------ cutoff variant, arbitrary Q
+
+@pytest.mark.parametrize("m,mp,s", [(2, 4, 1), (2, 3, 1), (3, 4, 1), (2, 4, 2), (4, 3, 1)])
+def test_noise_filter_cutoff_variant(m, mp, s):
+    """The m' cutoff modification (r_cut = (1 - 1/m)/m', window m m'/2): w = 3, 4 take
+    the register-ring filter, w = 6 and s > 1 the general one."""
+    model = synth.random_model(1200 + 10 * m + mp + s, n=(5, 6, 4), S=2, M=2, order=2)
+    say(f"noise_filter_cutoff m={m} m'={mp} s={s}")
+    out = gpu_filtered(model, m, s, mprime=mp)
+    ref = O.filtered_intensity(model, m, s, order=2, mprime=mp)
+    assert rel_l2(out, ref) <= TOL
+
+
+def test_noise_filter_cutoff_symmetric_box():
+    model = synth.random_model(1250, n=(6, 4, 8), S=3, M=2, order=3)
+    model.g0, model.count = (-7, -6, -9), (15, 13, 19)
+    say("noise_filter_cutoff symmetric box m=2 m'=4")
+    out = gpu_filtered(model, 2, 1, mprime=4)
+    ref = O.filtered_intensity(model, 2, 1, order=3, mprime=4)
+    assert rel_l2(out, ref) <= TOL
+
+
+def _hhl_points(n, hmax, npts):
+    """Q of an (h h l) plane in units of the supercell Bragg grid (G_a = n_a h_a)."""
+    h, l = np.meshgrid(np.linspace(-hmax, hmax, npts), np.linspace(-hmax, hmax, npts), indexing="ij")
+    hkl = np.stack([h, h, l], -1).reshape(-1, 3)
+    return hkl * np.asarray(n, dtype=np.float64)
+
+
+@pytest.mark.parametrize("m,mp", [(2, 2), (2, 4), (3, 2)])
+def test_filter_points_on_an_hhl_plane(m, mp):
+    import torch
+    import paper_1809_07088_amd as dsx
+    model = synth.random_model(1300 + 10 * m + mp, n=(5, 5, 4), S=2, M=2, order=3)
+    Q = _hhl_points(model.n, 1.3, 23)
+    say(f"filter_points (h h l) m={m} m'={mp}")
+    h = to_dsx(model)
+    dev = torch.empty(len(Q), dtype=torch.float32, device="cuda")
+    h.filter_points(m, Q, dev, mprime=mp)
+    host = np.empty(len(Q), dtype=np.float32)
+    h.filter_points(m, Q, host, mprime=mp)
+    assert np.array_equal(dev.cpu().numpy(), host)
+    ref = O.filtered_points(model, m, Q, order=3, mprime=mp)
+    assert rel_l2(host, ref) <= TOL
+    # grid points agree with the box filter of the same window
+    if mp == 2:
+        box = np.empty(tuple(model.count), dtype=np.float32)
+        h.noise_filter(m, 1, box)
+        G = O.grid_points(model.g0, model.count).astype(np.float64)
+        at = np.empty(len(G), dtype=np.float32)
+        h.filter_points(m, G, at)
+        assert rel_l2(at, box.reshape(-1)) <= TOL
+    with pytest.raises(dsx.DsxError) as e:
+        h.filter_points(m, np.array([[0.5, np.nan, 1.0]]), host[:1])
+    assert e.value.status == dsx.ERR_ARG
+    with pytest.raises(dsx.DsxError) as e:
+        h.filter_points(3, Q, host, mprime=3)       # m m' odd
+    assert e.value.status == dsx.ERR_ARG
+    h.close()
