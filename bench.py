@@ -515,6 +515,42 @@ def main():
         unfiltered = voxels / ((time.perf_counter() - u0) / args.steps)
         I_gpu = out.cpu().numpy()
 
+    # the widened filter: the m' cutoff modification on the same box, and an off-axis
+    # (h h l) plane of 401 x 401 points over |h|, |l| <= 8 (the paper's plane format)
+    widened = None
+    if not args.only_steps:
+        widened = {}
+        out2 = torch.empty(count, dtype=torch.float32, device=dev)
+        for _ in range(2):
+            h.set_sites_async(0, None, disp_dev)
+            h.noise_filter_cutoff(lm, 4, 1, out2)
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        reps = max(3, args.steps // 2)
+        for _ in range(reps):
+            h.set_sites_async(0, None, disp_dev)
+            h.noise_filter_cutoff(lm, 4, 1, out2)
+        torch.cuda.synchronize()
+        tc = (time.perf_counter() - c0) / reps
+        widened["cutoff_mprime4"] = {"ms_per_step": round(tc * 1e3, 4), "voxels_per_s": round(voxels / tc, 1),
+                                     "lanczos_m": lm, "mprime": 4}
+        hh, ll = np.meshgrid(np.linspace(-8, 8, 401), np.linspace(-8, 8, 401), indexing="ij")
+        Qp = np.stack([hh, hh, ll], -1).reshape(-1, 3) * np.asarray(n, dtype=np.float64)
+        pts = torch.empty(len(Qp), dtype=torch.float32, device=dev)
+        h.set_sites_async(0, None, disp_dev)
+        h.filter_points(lm, Qp, pts)
+        c0 = time.perf_counter()
+        for _ in range(3):
+            h.set_sites_async(0, None, disp_dev)
+            h.filter_points(lm, Qp, pts)
+        tp = (time.perf_counter() - c0) / 3
+        widened["hhl_plane_401x401"] = {"ms_per_call": round(tp * 1e3, 3), "points": int(len(Qp)),
+                                        "points_per_s": round(len(Qp) / tp, 1), "lanczos_m": lm,
+                                        "note": "I(G) on the 513^3 box holding every window, then "
+                                                "the windowed sum per point; host point list, "
+                                                "synchronous call"}
+        del out2, pts
+
     sweep = None
     if args.sweep:
         sweep = {}
@@ -583,6 +619,8 @@ def main():
     }
     if sweep is not None:
         line["compute_intensity_voxels_per_s_by_order"] = sweep
+    if widened is not None:
+        line["widened_filter"] = widened
     if ensemble is not None:
         line["ensemble"] = ensemble
     if serving is not None:
