@@ -100,6 +100,31 @@ typedef struct {
 dsx_status dsx_plan_query(const dsx_model_desc* d, dsx_plan_info* info);
 
 /*
+ * Host-only split-site mapping (Sec. III.B, after Eq. comp_ft): when the
+ * displacements of a site take only a few values, every displaced position becomes
+ * a site of its own and displacive disorder becomes occupational disorder, which the
+ * compositional path (taylor_order 0, has_occ 1) then evaluates exactly, with no
+ * Taylor truncation.  Site mu with distinct displacements u_1..u_K (in the order
+ * first met, scanning configurations, then cells) becomes K sites at r_mu + u_k with
+ * b_mu and occupancy delta_{R,mu} [u_{R,mu} = u_k] (two displacements are equal when
+ * every component differs by at most tol; the site's position uses the first one).
+ *   n[3], n_sites, frac[n_sites][3], b[n_sites], n_configs   as in dsx_model_desc
+ *   occ   [n_configs][n_sites][n1][n2][n3] or NULL (delta = 1)
+ *   disp  [n_configs][n_sites][n1][n2][n3][3] fractional unit-cell displacements
+ *   max_sites  capacity of the outputs (<= DSX_MAX_SITES)
+ * Outputs (host memory owned by the caller): *n_split sites, frac_out[max_sites][3],
+ * b_out[max_sites], parent_out[max_sites] (the original site; pass it, or the
+ * original pos_id of it, as pos_id so that N is unchanged), occ_out
+ * [n_configs][max_sites][n1][n2][n3] (the first *n_split site blocks of each
+ * configuration are written).  DSX_ERR_UNSUPPORTED when more than max_sites split
+ * sites arise; nothing is written then.
+ */
+dsx_status dsx_split_sites(const int32_t n[3], int32_t n_sites, const double* frac, const double* b,
+                           int32_t n_configs, const float* occ, const float* disp, double tol,
+                           int32_t max_sites, int32_t* n_split, double* frac_out, double* b_out,
+                           int32_t* parent_out, float* occ_out);
+
+/*
  * Create a model on the current HIP device and allocate its device state
  * (inputs, spectra, FP64 sums).  *out receives the handle.  DSX_ERR_NOMEM when
  * the device cannot hold it.

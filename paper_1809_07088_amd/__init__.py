@@ -50,7 +50,7 @@ class KernelStat(ctypes.Structure):
 EXPORTS = ("dsx_plan_query", "dsx_create_model", "dsx_set_sites", "dsx_set_sites_async", "dsx_set_grid",
            "dsx_compute_intensity", "dsx_noise_filter", "dsx_destroy_model", "dsx_last_error",
            "dsx_version", "dsx_profile_enable", "dsx_profile_read", "dsx_profile_reset",
-           "dsx_noise_filter_cutoff", "dsx_filter_points",
+           "dsx_noise_filter_cutoff", "dsx_filter_points", "dsx_split_sites",
            "dsx_batch_create", "dsx_batch_run", "dsx_batch_destroy", "dsx_autotune", "dsx_tune_query",
            "dsx_server_create", "dsx_server_add_model", "dsx_server_submit", "dsx_server_wait",
            "dsx_server_stats_read", "dsx_server_destroy")
@@ -97,6 +97,9 @@ def lib():
         L.dsx_noise_filter_cutoff.restype = i32
         L.dsx_filter_points.argtypes = [P, i32, i32, ctypes.c_int64, P, P, i32, P]
         L.dsx_filter_points.restype = i32
+        L.dsx_split_sites.argtypes = [P, i32, P, P, i32, P, P, ctypes.c_double, i32, ctypes.POINTER(i32),
+                                      P, P, P, P]
+        L.dsx_split_sites.restype = i32
         L.dsx_destroy_model.argtypes = [P]
         L.dsx_last_error.argtypes = []
         L.dsx_last_error.restype = ctypes.c_char_p
@@ -251,6 +254,27 @@ def filter_points(model, lanczos_m, q, out, mprime=2, stream=None):
     _check(lib().dsx_filter_points(model, int(lanczos_m), int(mprime), q.shape[0],
                                    q.ctypes.data_as(ctypes.c_void_p), p, where, st))
     return out
+
+
+def split_sites(n, frac, b, disp, occ=None, tol=0.0, max_sites=64):
+    """dsx_split_sites (host only): the split-site form of a model whose displacements
+    take few values.  disp [M][S][n1][n2][n3][3], occ [M][S][n1][n2][n3] or None.
+    Returns (frac [S'][3], b [S'], parent [S'], occ [M][S'][n1][n2][n3])."""
+    n = np.ascontiguousarray(n, dtype=np.int32)
+    frac = np.ascontiguousarray(frac, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    disp = np.ascontiguousarray(disp, dtype=np.float32)
+    M, S = disp.shape[0], disp.shape[1]
+    occ_in = None if occ is None else np.ascontiguousarray(occ, dtype=np.float32)
+    fo = np.zeros((max_sites, 3)); bo = np.zeros(max_sites)
+    po = np.zeros(max_sites, dtype=np.int32)
+    oo = np.zeros((M, max_sites) + tuple(int(v) for v in n), dtype=np.float32)
+    ns = ctypes.c_int32(0)
+    vp = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+    _check(lib().dsx_split_sites(vp(n), S, vp(frac), vp(b), M, vp(occ_in), vp(disp), float(tol), int(max_sites),
+                                 ctypes.byref(ns), vp(fo), vp(bo), vp(po), vp(oo)))
+    k = ns.value
+    return fo[:k].copy(), bo[:k].copy(), po[:k].copy(), np.ascontiguousarray(oo[:, :k])
 
 
 def destroy_model(model):

@@ -19,6 +19,7 @@
 #include <cstring>
 #include <fstream>
 #include <sstream>
+#include <array>
 #include <climits>
 #include <map>
 #include <tuple>
@@ -1215,6 +1216,67 @@ dsx_status dsx_noise_filter(dsx_model m, int32_t lanczos_m, int32_t oversample, 
         HIPCHK(m, hipMemcpyAsync(out, dout, out_vox * sizeof(float), hipMemcpyDeviceToHost, st));
         HIPCHK(m, hipStreamSynchronize(st));
     }
+    return DSX_OK;
+}
+
+dsx_status dsx_split_sites(const int32_t n[3], int32_t n_sites, const double* frac, const double* b,
+                           int32_t n_configs, const float* occ, const float* disp, double tol,
+                           int32_t max_sites, int32_t* n_split, double* frac_out, double* b_out,
+                           int32_t* parent_out, float* occ_out)
+{
+    if (!n || !frac || !b || !disp || !n_split || !frac_out || !b_out || !parent_out || !occ_out)
+        return fail(DSX_ERR_ARG, "null argument");
+    for (int a = 0; a < 3; ++a)
+        if (n[a] < 1 || n[a] > DSX_MAX_N) return fail(DSX_ERR_ARG, "n out of range");
+    if (n_sites < 1 || n_sites > DSX_MAX_SITES || n_configs < 1 || !(tol >= 0.0))
+        return fail(DSX_ERR_ARG, "bad n_sites, n_configs or tol");
+    if (max_sites < 1 || max_sites > DSX_MAX_SITES) return fail(DSX_ERR_ARG, "max_sites out of range");
+    const size_t ncell = (size_t)n[0] * n[1] * n[2];
+    // distinct displacements per site, in the order first met; cls[c][mu][cell] = index
+    std::vector<std::vector<std::array<float, 3>>> vals(n_sites);
+    std::vector<int32_t> cls((size_t)n_configs * n_sites * ncell);
+    int total = 0;
+    for (int c = 0; c < n_configs; ++c)
+        for (int mu = 0; mu < n_sites; ++mu) {
+            const float* u = disp + ((size_t)c * n_sites + mu) * ncell * 3;
+            auto& vs = vals[mu];
+            for (size_t r = 0; r < ncell; ++r) {
+                const float* ur = u + 3 * r;
+                int k = -1;
+                for (size_t j = 0; j < vs.size() && k < 0; ++j)
+                    if (std::fabs((double)ur[0] - vs[j][0]) <= tol && std::fabs((double)ur[1] - vs[j][1]) <= tol &&
+                        std::fabs((double)ur[2] - vs[j][2]) <= tol)
+                        k = (int)j;
+                if (k < 0) {
+                    if (++total > max_sites)
+                        return fail(DSX_ERR_UNSUPPORTED, "more split sites than max_sites");
+                    vs.push_back({ur[0], ur[1], ur[2]});
+                    k = (int)vs.size() - 1;
+                }
+                cls[((size_t)c * n_sites + mu) * ncell + r] = k;
+            }
+        }
+    // split sites: site mu's values in order, sites in order
+    std::vector<int> first(n_sites + 1, 0);
+    for (int mu = 0; mu < n_sites; ++mu) first[mu + 1] = first[mu] + (int)vals[mu].size();
+    for (int mu = 0; mu < n_sites; ++mu)
+        for (size_t k = 0; k < vals[mu].size(); ++k) {
+            const int sidx = first[mu] + (int)k;
+            for (int a = 0; a < 3; ++a) frac_out[3 * sidx + a] = frac[3 * mu + a] + (double)vals[mu][k][a];
+            b_out[sidx] = b[mu];
+            parent_out[sidx] = mu;
+        }
+    const int ns = first[n_sites];
+    for (int c = 0; c < n_configs; ++c)
+        for (int mu = 0; mu < n_sites; ++mu) {
+            const float* dl = occ ? occ + ((size_t)c * n_sites + mu) * ncell : nullptr;
+            const int32_t* kk = cls.data() + ((size_t)c * n_sites + mu) * ncell;
+            for (size_t k = 0; k < vals[mu].size(); ++k) {
+                float* o = occ_out + ((size_t)c * max_sites + first[mu] + k) * ncell;
+                for (size_t r = 0; r < ncell; ++r) o[r] = kk[r] == (int)k ? (dl ? dl[r] : 1.f) : 0.f;
+            }
+        }
+    *n_split = ns;
     return DSX_OK;
 }
 

@@ -62,3 +62,26 @@ def rel_l2(a, ref):
     a = np.asarray(a, dtype=np.float64).ravel()
     ref = np.asarray(ref, dtype=np.float64).ravel()
     return float(np.linalg.norm(a - ref) / np.linalg.norm(ref))
+
+
+def discrete_displacement_model(seed, n=(4, 3, 5), S=2, M=2, K=3, amp=0.03, with_occ=True):
+    """A nuclear model whose displacements take K values per site (a split-site case)."""
+    import synth
+    m = synth.random_model(seed, n=n, S=S, M=M, order=8, with_occ=with_occ)
+    r = np.random.default_rng([7, seed])
+    vals = r.uniform(-amp, amp, (S, K, 3)).astype(np.float32)
+    pick = r.integers(0, K, (M, S) + tuple(n))
+    m.disp = np.ascontiguousarray(vals[np.arange(S)[None, :, None, None, None], pick]).astype(np.float32)
+    return m
+
+
+def split_model(model, tol=0.0):
+    """The split-site form of `model` (dsx_split_sites), N kept from the original."""
+    import copy
+    from oracle import oracle as O
+    fr, b, parent, occ = dsx.split_sites(model.n, model.frac, model.b, model.disp, model.occ, tol)
+    s = copy.copy(model)
+    s.frac, s.b, s.occ, s.disp, s.order = fr, b, occ, None, 0
+    s.pos_id = (parent if model.pos_id is None else np.asarray(model.pos_id)[parent]).astype(np.int32)
+    s.norm_N = O.norm_N(model)
+    return s

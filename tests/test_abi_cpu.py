@@ -8,6 +8,7 @@ import pytest
 
 import paper_1809_07088_amd as dsx
 import synth
+from oracle import oracle as O
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -115,3 +116,44 @@ def test_binding_structs_match_header_layout():
     assert set(pairs) <= set(hs)
     for cname, py in pairs.items():
         assert [f for f, _ in py._fields_] == hs[cname], cname
+
+
+# ------------------------------------------------------------------ split sites (host only)
+
+def test_split_sites_partition_and_positions():
+    from tests.helpers import discrete_displacement_model, split_model
+    m = discrete_displacement_model(31, K=3)
+    s = split_model(m)
+    assert s.n_sites <= m.n_sites * 3
+    for mu in range(m.n_sites):
+        kids = np.flatnonzero(np.asarray(s.pos_id) == mu)
+        # the occupancies of the split sites partition the parent's
+        assert np.array_equal(s.occ[:, kids].sum(axis=1), m.occ[:, mu])
+        # each split site sits at r_mu + one of the parent's displacement values
+        for k in kids:
+            u = s.frac[k] - m.frac[mu]
+            hit = np.all(np.abs(m.disp[:, mu] - u.astype(np.float32)) <= 1e-7, axis=-1)
+            assert np.array_equal(hit & (m.occ[:, mu] > 0), s.occ[:, k] > 0)
+
+
+def test_split_sites_exact_against_the_exponential():
+    """The split-site model, evaluated compositionally, is the displacive model with
+    the exact exponential (no Taylor truncation)."""
+    from tests.helpers import discrete_displacement_model, split_model
+    for seed, occ in [(32, True), (33, False)]:
+        m = discrete_displacement_model(seed, K=2, with_occ=occ)
+        if not occ:
+            m.occ = None
+        s = split_model(m)
+        G = O.grid_points(m.g0, m.count)[::7]
+        a = O.intensity(s, G)
+        b = O.intensity(m, G, -1)
+        assert np.linalg.norm(a - b) <= 1e-10 * np.linalg.norm(b)
+
+
+def test_split_sites_limit():
+    from tests.helpers import discrete_displacement_model
+    m = discrete_displacement_model(34, K=3)
+    with pytest.raises(dsx.DsxError) as e:
+        dsx.split_sites(m.n, m.frac, m.b, m.disp, m.occ, 0.0, max_sites=4)
+    assert e.value.status == dsx.ERR_UNSUPPORTED

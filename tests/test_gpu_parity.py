@@ -357,3 +357,20 @@ def test_filter_points_on_an_hhl_plane(m, mp):
         h.filter_points(3, Q, host, mprime=3)       # m m' odd
     assert e.value.status == dsx.ERR_ARG
     h.close()
+
+
+# ------------------------------------------------------------------ split sites
+
+@pytest.mark.parametrize("seed,K,occ", [(40, 2, True), (41, 3, False), (42, 4, True)])
+def test_split_sites_on_the_compositional_path(seed, K, occ):
+    """Discrete displacements mapped to split sites (dsx_split_sites) and evaluated by
+    the compositional kernels equal the exact-exponential displacive intensity."""
+    from tests.helpers import discrete_displacement_model, split_model
+    m = discrete_displacement_model(seed, n=(4, 6, 5), S=2, M=2, K=K, with_occ=occ)
+    if not occ:
+        m.occ = None
+    s = split_model(m)
+    say(f"split sites seed={seed} K={K} occ={occ} -> {s.n_sites} sites")
+    I = gpu_intensity(s)
+    ref = O.intensity(m, O.grid_points(m.g0, m.count), -1).reshape(m.count)
+    assert rel_l2(I, ref) <= TOL
