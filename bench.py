@@ -550,6 +550,37 @@ def main():
                                                 "the windowed sum per point; host point list, "
                                                 "synchronous call"}
         del out2, pts
+        # split sites: the fcc model with 4 discrete displacements per site (16 split
+        # sites, compositional path, exact exponential), filtered on the same box
+        rs = np.random.default_rng(1234)
+        vals = rs.uniform(-0.02, 0.02, (S, 4, 3)).astype(np.float32)
+        pick = rs.integers(0, 4, (1, S) + tuple(n))
+        dd = np.ascontiguousarray(vals[np.arange(S)[None, :, None, None, None], pick])
+        c0 = time.perf_counter()
+        fr2, b2, par2, occ2 = dsx.split_sites(n, model.frac, model.b, dd)
+        t_map = time.perf_counter() - c0
+        hs = dsx.Model(cell=model.cell, n=n, frac=fr2, b=b2, taylor_order=0, n_configs=1, has_occ=True,
+                       pos_id=par2, norm_N=float(np.prod(n)) * S)
+        hs.set_grid(model.g0, count)
+        occ_dev = torch.from_numpy(np.ascontiguousarray(occ2[0])).to(dev)
+        out3 = torch.empty(count, dtype=torch.float32, device=dev)
+        hs.set_sites_async(0, occ_dev, None)
+        hs.autotune(lm)
+        for _ in range(2):
+            hs.set_sites_async(0, occ_dev, None)
+            hs.noise_filter(lm, 1, out3)
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        for _ in range(reps):
+            hs.set_sites_async(0, occ_dev, None)
+            hs.noise_filter(lm, 1, out3)
+        torch.cuda.synchronize()
+        ts = (time.perf_counter() - c0) / reps
+        widened["split_sites_fcc32_K4"] = {"ms_per_step": round(ts * 1e3, 4), "voxels_per_s": round(voxels / ts, 1),
+                                           "split_sites": int(len(b2)), "host_mapping_ms": round(t_map * 1e3, 1),
+                                           "lanczos_m": lm}
+        hs.close()
+        del out3, occ_dev
 
     sweep = None
     if args.sweep:
