@@ -27,7 +27,9 @@
  *                    summed directly over the (2m)^3 neighbourhood, NOT separably;
  *                    orc_lanczos_cutoff the same with the cutoff of the m' modification
  *                    (Sec. V.B, the second of the three modifications), and
- *                    orc_lanczos_points at arbitrary Q (not on the s-grid).
+ *                    orc_lanczos_points at arbitrary Q (not on the s-grid), and
+ *                    orc_lanczos_spherical with the spherically symmetric cutoff W_r
+ *                    (the third modification) in place of Eq. weight_sinc.
  *
  * The lattice-point part of every phase is reduced exactly in integers first:
  * e^{2 pi i G_a R_a / n_a} = e^{2 pi i ((G_a R_a) mod n_a) / n_a}.  This is an
@@ -297,6 +299,60 @@ int orc_lanczos_points(int32_t m, int32_t mp, const int32_t* e0, const int32_t* 
     for (int64_t i = 0; i < npts; ++i)
         if (lanczos_at(Q + 3 * i, m, mp, e0, ecount, I, &out[i]) != 0) bad = 1;
     return bad ? -1 : 0;
+}
+
+/* x^-3 (sin x - x cos x) = sin(x)/x^3 - cos(x)/x^2: the bracket of W_r (the Fourier
+ * transform of a ball of radius 1 divided by 4 pi).  Near 0 its series
+ * 1/3 - x^2/30 + x^4/840 avoids the cancellation. */
+double orc_ball_ft(double x)
+{
+    const double ax = fabs(x);
+    if (ax < 1e-2) return 1.0 / 3.0 - x * x / 30.0 + x * x * x * x / 840.0;
+    return (sin(ax) - ax * cos(ax)) / (ax * ax * ax);
+}
+
+/* Lanczos resampling with the spherical cutoff (Sec. V.B, the third modification):
+ * W = W_r(|Q - G|) * L(Q - G), W_r proportional to orc_ball_ft(|Q - G|_cart r_c)
+ * with r_c = (1 - 1/m) r_max, L the window of Eq. lanczos (unchanged, half-width m).
+ * recip[9] = rows a*, b*, c* (inverse Angstrom, 2 pi included); n[3] the supercell;
+ * Q - G in supercell-grid units is (Q_a - G_a)/n_a reciprocal-lattice units.
+ * Box and output conventions as orc_lanczos_cutoff (m' = 2).  The constant factor
+ * 4 pi r_c^3 / (n1 n2 n3 V) cancels in the normalised sum. */
+int orc_lanczos_spherical(int32_t m, int32_t s, const int32_t* e0, const int32_t* ecount, const double* I,
+                          const int32_t* q0, const int32_t* qcount, const double* recip, const int32_t* n,
+                          double rc, double* out)
+{
+    if (m < 2 || s < 1 || !e0 || !ecount || !I || !q0 || !qcount || !recip || !n || !out || !(rc > 0.0)) return -1;
+    for (int a = 0; a < 3; ++a) {
+        if (n[a] < 1) return -1;
+        const long lo = (long)q0[a] - m + 1;
+        const long hi = (long)q0[a] + (qcount[a] - 1) / s + m;
+        if (lo < e0[a] || hi >= (long)e0[a] + ecount[a]) return -1;
+    }
+    const long total = (long)qcount[0] * qcount[1] * qcount[2];
+#pragma omp parallel for schedule(dynamic, 64)
+    for (long idx = 0; idx < total; ++idx) {
+        const long i3 = idx % qcount[2], i2 = (idx / qcount[2]) % qcount[1], i1 = idx / ((long)qcount[2] * qcount[1]);
+        const double Q[3] = {q0[0] + (double)i1 / s, q0[1] + (double)i2 / s, q0[2] + (double)i3 / s};
+        const long f[3] = {(long)floor(Q[0]), (long)floor(Q[1]), (long)floor(Q[2])};
+        double num = 0.0, den = 0.0;
+        for (long G1 = f[0] - m + 1; G1 <= f[0] + m; ++G1)
+        for (long G2 = f[1] - m + 1; G2 <= f[1] + m; ++G2)
+        for (long G3 = f[2] - m + 1; G3 <= f[2] + m; ++G3) {
+            const double d[3] = {Q[0] - G1, Q[1] - G2, Q[2] - G3};
+            double L = 1.0;
+            for (int a = 0; a < 3; ++a) L *= fabs(d[a]) < m ? sinc(M_PI * d[a] / m) : 0.0;
+            double q[3] = {0.0, 0.0, 0.0};
+            for (int a = 0; a < 3; ++a)
+                for (int c = 0; c < 3; ++c) q[c] += d[a] / n[a] * recip[3 * a + c];
+            const double W = orc_ball_ft(sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]) * rc) * L;
+            const long j1 = G1 - e0[0], j2 = G2 - e0[1], j3 = G3 - e0[2];
+            num += W * I[(j1 * ecount[1] + j2) * ecount[2] + j3];
+            den += W;
+        }
+        out[idx] = num / den;
+    }
+    return 0;
 }
 
 int orc_version(void) { return 1; }

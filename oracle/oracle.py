@@ -78,8 +78,11 @@ def lib():
         L.orc_lanczos.argtypes = [i32, i32, P, P, P, P, P, P]
         L.orc_lanczos_cutoff.argtypes = [i32, i32, i32, P, P, P, P, P, P]
         L.orc_lanczos_points.argtypes = [i32, i32, P, P, P, i64, P, P]
+        L.orc_lanczos_spherical.argtypes = [i32, i32, P, P, P, P, P, P, P, f64, P]
+        L.orc_ball_ft.argtypes = [f64]
+        L.orc_ball_ft.restype = f64
         for f in (L.orc_sf_nuclear, L.orc_sf_magnetic, L.orc_pair_sum, L.orc_lanczos,
-                  L.orc_lanczos_cutoff, L.orc_lanczos_points):
+                  L.orc_lanczos_cutoff, L.orc_lanczos_points, L.orc_lanczos_spherical):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -298,6 +301,46 @@ def filtered_intensity(model, m, s=1, order=None, mprime=2) -> np.ndarray:
     I_ext = intensity(model, grid_points(e0, ec), order).reshape(ec)
     qc = [s * model.count[a] for a in range(3)]
     return lanczos(I_ext, e0, m, s, model.g0, qc, mprime)
+
+
+def ball_ft(x) -> float:
+    """sin(x)/x^3 - cos(x)/x^2, the bracket of the spherical cutoff W_r."""
+    return float(lib().orc_ball_ft(float(x)))
+
+
+def spherical_rc(cell, n, m) -> float:
+    """r_c = (1 - 1/m) r_max, r_max the radius of the largest sphere inscribed in the
+    supercell: half the smallest distance between opposite faces, n_a 2 pi / |a*_a| / 2."""
+    R = reciprocal_basis(cell)
+    r_max = min(n[a] * np.pi / np.linalg.norm(R[a]) for a in range(3))
+    return (1.0 - 1.0 / m) * r_max
+
+
+def lanczos_spherical(I_ext, e0, m, s, q0, qcount, cell, n) -> np.ndarray:
+    """Resampling with the spherical cutoff W_r(|Q - G|) times the window of Eq. lanczos
+    (Sec. V.B), by the direct (2m)^3 sum."""
+    I_ext = np.ascontiguousarray(I_ext, dtype=np.float64)
+    e0 = np.ascontiguousarray(e0, dtype=np.int32)
+    ec = np.ascontiguousarray(I_ext.shape, dtype=np.int32)
+    q0 = np.ascontiguousarray(q0, dtype=np.int32)
+    qc = np.ascontiguousarray(qcount, dtype=np.int32)
+    R = np.ascontiguousarray(reciprocal_basis(cell), dtype=np.float64)
+    nn = np.ascontiguousarray(n, dtype=np.int32)
+    out = np.zeros(tuple(int(v) for v in qcount), dtype=np.float64)
+    rc = lib().orc_lanczos_spherical(int(m), int(s), _ptr(e0), _ptr(ec), _ptr(I_ext), _ptr(q0), _ptr(qc),
+                                     _ptr(R), _ptr(nn), spherical_rc(cell, n, m), _ptr(out))
+    if rc != 0:
+        raise ValueError("orc_lanczos_spherical: bad arguments or input box too small")
+    return out
+
+
+def filtered_intensity_spherical(model, m, s=1, order=None) -> np.ndarray:
+    """The model box filtered with the spherical cutoff (window half-width m)."""
+    e0 = [model.g0[a] - m for a in range(3)]
+    ec = [model.count[a] + 2 * m for a in range(3)]
+    I_ext = intensity(model, grid_points(e0, ec), order).reshape(ec)
+    qc = [s * model.count[a] for a in range(3)]
+    return lanczos_spherical(I_ext, e0, m, s, model.g0, qc, model.cell, model.n)
 
 
 def filtered_points(model, m, Q, order=None, mprime=2) -> np.ndarray:

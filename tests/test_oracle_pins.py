@@ -334,3 +334,43 @@ def test_fft_route_compositional_equals_direct():
     m = synth.compositional(n=(4, 5, 6), M=2, hmax=1, frac=synth.FCC_BASIS[:3], b=synth.FCC_B[:3])
     G = O.grid_points(m.g0, m.count)
     assert np.allclose(O.intensity(m, G), O.fft_route_intensity(m, G), rtol=1e-11, atol=1e-13)
+
+
+# ----------------------------------------------------------- P8'' spherical cutoff W_r
+
+@pytest.mark.parametrize("x", [1e-5, 4e-3, 0.3, 2.0, 7.5, 20.0])
+def test_ball_transform_against_quadrature(x):
+    """The bracket of W_r is the Fourier transform of a unit ball over 4 pi:
+    int_0^1 r^2 sin(x r)/(x r) dr, by quadrature."""
+    from scipy.integrate import quad
+    v, _ = quad(lambda r: r * r * np.sinc(x * r / np.pi), 0.0, 1.0, epsabs=1e-14, epsrel=1e-12, limit=200)
+    assert abs(O.ball_ft(x) - v) <= 1e-10 * max(1.0, abs(v))
+
+
+def test_inscribed_sphere_radius_from_real_space():
+    """r_max = half the smallest distance between opposite faces of the supercell,
+    computed from the cell vectors (volume over face area)."""
+    for cell, n in [([3.1, 4.7, 5.2, 90, 90, 90], (4, 3, 2)), ([4.0, 4.0, 6.5, 90, 90, 120], (5, 5, 3)),
+                    ([3.3, 4.1, 4.9, 81, 97, 104], (3, 4, 3))]:
+        A = O.cell_vectors(cell) * np.asarray(n, float)[:, None]
+        V = abs(np.dot(A[0], np.cross(A[1], A[2])))
+        gaps = [V / np.linalg.norm(np.cross(A[(a + 1) % 3], A[(a + 2) % 3])) for a in range(3)]
+        for m in (2, 3):
+            assert abs(O.spherical_rc(cell, n, m) - (1 - 1 / m) * min(gaps) / 2) < 1e-12
+
+
+@pytest.mark.parametrize("m,s", [(2, 1), (2, 2), (3, 1)])
+def test_spherical_cutoff_is_isotropic_and_keeps_constants(m, s):
+    """On a cubic cell with n1 = n2 = n3 the weight depends on |Q - G| and the window,
+    both symmetric under exchanging axes: filtering commutes with transposing I(G)."""
+    rng = np.random.default_rng(50 + m + s)
+    e0 = np.array([-6, -6, -6])
+    I = rng.random((13, 13, 13))
+    cell, n = [4.0, 4.0, 4.0, 90, 90, 90], (5, 5, 5)
+    q0 = [-6 + m] * 3
+    qc = [max(1, (13 - 2 * m - 1) * s)] * 3
+    a = O.lanczos_spherical(I, e0, m, s, q0, qc, cell, n)
+    b = O.lanczos_spherical(I.transpose(2, 0, 1), e0, m, s, q0, qc, cell, n)
+    assert np.allclose(b, a.transpose(2, 0, 1), rtol=1e-12)
+    c = O.lanczos_spherical(np.full_like(I, 1.75), e0, m, s, q0, qc, cell, n)
+    assert np.allclose(c, 1.75, rtol=1e-13)
