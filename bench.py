@@ -550,6 +550,21 @@ def main():
                                                 "the windowed sum per point; host point list, "
                                                 "synchronous call"}
         del out2, pts
+        # the spherical cutoff (non-separable (2m)^3 stencil) on the same box
+        out4 = torch.empty(count, dtype=torch.float32, device=dev)
+        for _ in range(2):
+            h.set_sites_async(0, None, disp_dev)
+            h.noise_filter_spherical(lm, 1, out4)
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        for _ in range(reps):
+            h.set_sites_async(0, None, disp_dev)
+            h.noise_filter_spherical(lm, 1, out4)
+        torch.cuda.synchronize()
+        tsph = (time.perf_counter() - c0) / reps
+        widened["spherical_cutoff"] = {"ms_per_step": round(tsph * 1e3, 4), "voxels_per_s": round(voxels / tsph, 1),
+                                       "lanczos_m": lm}
+        del out4
         # split sites: the fcc model with 4 discrete displacements per site (16 split
         # sites, compositional path, exact exponential), filtered on the same box
         rs = np.random.default_rng(1234)

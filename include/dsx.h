@@ -202,6 +202,18 @@ dsx_status dsx_noise_filter_cutoff(dsx_model m, int32_t lanczos_m, int32_t mprim
                                    float* out, int32_t where, void* hip_stream);
 
 /*
+ * The same resampling with the spherically symmetric cutoff of Sec. V.B (the third
+ * modification): Eq. weight_sinc replaced by W_r(|Q - G|), proportional to
+ * sin(x)/x^3 - cos(x)/x^2 with x = |Q - G| r_c (Q - G Cartesian, inverse Angstrom),
+ * r_c = (1 - 1/m) r_max and r_max the radius of the largest sphere inscribed in the
+ * supercell; the window of Eq. lanczos is kept.  The weight is no longer separable:
+ * every output sums its (2m)^3 neighbourhood.  Requires 2 <= lanczos_m <= 4 and
+ * 1 <= oversample <= 4; output and `where` / stream rules as for dsx_noise_filter.
+ */
+dsx_status dsx_noise_filter_spherical(dsx_model m, int32_t lanczos_m, int32_t oversample, float* out,
+                                     int32_t where, void* hip_stream);
+
+/*
  * Lanczos resampling at arbitrary points Q (Sec. V.B; e.g. the off-axis (h h l)
  * planes of Sec. V.B, which a grid along the reciprocal axes cannot hold):
  * I(Q) = sum_G I(G) W(Q-G) / sum_G W(Q-G) over the (2w)^3 supercell Bragg points

@@ -50,7 +50,7 @@ class KernelStat(ctypes.Structure):
 EXPORTS = ("dsx_plan_query", "dsx_create_model", "dsx_set_sites", "dsx_set_sites_async", "dsx_set_grid",
            "dsx_compute_intensity", "dsx_noise_filter", "dsx_destroy_model", "dsx_last_error",
            "dsx_version", "dsx_profile_enable", "dsx_profile_read", "dsx_profile_reset",
-           "dsx_noise_filter_cutoff", "dsx_filter_points", "dsx_split_sites",
+           "dsx_noise_filter_cutoff", "dsx_filter_points", "dsx_split_sites", "dsx_noise_filter_spherical",
            "dsx_batch_create", "dsx_batch_run", "dsx_batch_destroy", "dsx_autotune", "dsx_tune_query",
            "dsx_server_create", "dsx_server_add_model", "dsx_server_submit", "dsx_server_wait",
            "dsx_server_stats_read", "dsx_server_destroy")
@@ -95,6 +95,8 @@ def lib():
         L.dsx_noise_filter.argtypes = [P, i32, i32, P, i32, P]
         L.dsx_noise_filter_cutoff.argtypes = [P, i32, i32, i32, P, i32, P]
         L.dsx_noise_filter_cutoff.restype = i32
+        L.dsx_noise_filter_spherical.argtypes = [P, i32, i32, P, i32, P]
+        L.dsx_noise_filter_spherical.restype = i32
         L.dsx_filter_points.argtypes = [P, i32, i32, ctypes.c_int64, P, P, i32, P]
         L.dsx_filter_points.restype = i32
         L.dsx_split_sites.argtypes = [P, i32, P, P, i32, P, P, ctypes.c_double, i32, ctypes.POINTER(i32),
@@ -245,6 +247,14 @@ def noise_filter_cutoff(model, lanczos_m, mprime, oversample, out, stream=None):
     return out
 
 
+def noise_filter_spherical(model, lanczos_m, oversample, out, stream=None):
+    """dsx_noise_filter_spherical: the filter with the spherical cutoff W_r."""
+    p, where, _ = _ptr_where(out)
+    st = _stream_handle(stream) if where == DEVICE else None
+    _check(lib().dsx_noise_filter_spherical(model, int(lanczos_m), int(oversample), p, where, st))
+    return out
+
+
 def filter_points(model, lanczos_m, q, out, mprime=2, stream=None):
     """dsx_filter_points: the filter at arbitrary points q [npts][3] (float64 host
     array, units of the supercell Bragg grid) into out [npts]."""
@@ -370,6 +380,9 @@ class Model:
 
     def noise_filter_cutoff(self, lanczos_m, mprime, oversample, out, stream=None):
         return noise_filter_cutoff(self.handle, lanczos_m, mprime, oversample, out, stream)
+
+    def noise_filter_spherical(self, lanczos_m, oversample, out, stream=None):
+        return noise_filter_spherical(self.handle, lanczos_m, oversample, out, stream)
 
     def filter_points(self, lanczos_m, q, out, mprime=2, stream=None):
         return filter_points(self.handle, lanczos_m, q, out, mprime, stream)

@@ -1280,6 +1280,91 @@ dsx_status dsx_split_sites(const int32_t n[3], int32_t n_sites, const double* fr
     return DSX_OK;
 }
 
+dsx_status dsx_noise_filter_spherical(dsx_model m, int32_t lanczos_m, int32_t oversample, float* out,
+                                     int32_t where, void* hip_stream)
+{
+    dsx_status s = check_direct(m);
+    if (s != DSX_OK) return s;
+    if (!out) return fail(DSX_ERR_ARG, "out is NULL");
+    if (where != DSX_HOST && where != DSX_DEVICE) return fail(DSX_ERR_ARG, "bad 'where'");
+    if ((s = check_filter_args(lanczos_m, oversample)) != DSX_OK) return s;
+    if (lanczos_m > 4 || oversample > 4)
+        return fail(DSX_ERR_UNSUPPORTED, "the spherical cutoff supports lanczos_m <= 4 and oversample <= 4");
+    if ((s = ready(m)) != DSX_OK) return s;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int lm = lanczos_m, sv = oversample;
+    const size_t out_vox = (size_t)sv * m->box.cnt[0] * sv * m->box.cnt[1] * sv * m->box.cnt[2];
+    // the grown box and its tables (as for the separable filter)
+    if ((s = prepare_filter(m, lm, sv)) != DSX_OK) return s;
+    // weights [s^3][(2m)^3]: W_r(|Q - G|) L(Q - G), normalised per output phase
+    const auto key = std::make_tuple(lm, 0, sv);
+    if (!m->lanczos_w.count(key)) {
+        double rmax = 1e300;
+        for (int a = 0; a < 3; ++a) {
+            const double len = std::sqrt(m->recip[3 * a] * m->recip[3 * a] + m->recip[3 * a + 1] * m->recip[3 * a + 1] +
+                                         m->recip[3 * a + 2] * m->recip[3 * a + 2]);
+            rmax = std::min(rmax, m->n[a] * M_PI / len);
+        }
+        const double rc = (1.0 - 1.0 / lm) * rmax;
+        auto sinc = [](double x) { return x == 0.0 ? 1.0 : std::sin(x) / x; };
+        auto ball = [](double x) {
+            const double ax = std::fabs(x);
+            if (ax < 1e-2) return 1.0 / 3.0 - x * x / 30.0 + x * x * x * x / 840.0;
+            return (std::sin(ax) - ax * std::cos(ax)) / (ax * ax * ax);
+        };
+        const int T = 2 * lm;
+        std::vector<float> w((size_t)sv * sv * sv * T * T * T);
+        std::vector<double> v((size_t)T * T * T);
+        for (int j1 = 0; j1 < sv; ++j1)
+        for (int j2 = 0; j2 < sv; ++j2)
+        for (int j3 = 0; j3 < sv; ++j3) {
+            double tot = 0.0;
+            const int jj[3] = {j1, j2, j3};
+            for (int t1 = 0; t1 < T; ++t1)
+            for (int t2 = 0; t2 < T; ++t2)
+            for (int t3 = 0; t3 < T; ++t3) {
+                const int tt[3] = {t1, t2, t3};
+                double d[3], L = 1.0, q[3] = {0.0, 0.0, 0.0};
+                for (int a = 0; a < 3; ++a) {
+                    d[a] = (double)jj[a] / sv + lm - 1 - tt[a];      // Q_a - G_a
+                    L *= std::fabs(d[a]) < lm ? sinc(M_PI * d[a] / lm) : 0.0;
+                    for (int c = 0; c < 3; ++c) q[c] += d[a] / m->n[a] * m->recip[3 * a + c];
+                }
+                const double x = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]) * rc;
+                const double wv = ball(x) * L;
+                v[((size_t)t1 * T + t2) * T + t3] = wv;
+                tot += wv;
+            }
+            const size_t ph = ((size_t)j1 * sv + j2) * sv + j3;
+            for (size_t t = 0; t < v.size(); ++t) w[ph * v.size() + t] = (float)(v[t] / tot);
+        }
+        float* dw = nullptr;
+        HIPCHK(m, hipMalloc(&dw, w.size() * sizeof(float)));
+        HIPCHK(m, hipMemcpy(dw, w.data(), w.size() * sizeof(float), hipMemcpyHostToDevice));
+        m->lanczos_w[key] = dw;
+    }
+    float* dout = out;
+    if (where == DSX_HOST && (s = stage(m, out_vox, &dout)) != DSX_OK) return s;
+    if ((s = follow(m, st)) != DSX_OK) return s;
+    const Box ext = filter_box(m->box, lm);
+    if ((s = ensure_spectra(m, st, false)) != DSX_OK) return s;
+    const Layout el = ext_layout(ext);
+    if ((s = run_box(m, ext, m->d_ext, el, st)) != DSX_OK) return s;
+    LanczosParams lp{};
+    lp.in = m->d_ext; lp.out = dout; lp.wn = m->lanczos_w[key];
+    lp.ipitch = el.pitch; lp.ioff = el.off;
+    lp.ihalf = stored_planes(ext);
+    for (int a = 0; a < 3; ++a) { lp.e[a] = ext.cnt[a]; lp.o[a] = sv * m->box.cnt[a]; }
+    lp.m = lm; lp.s = sv;
+    lp.eoff = kExtEoff;
+    HIPCHK(m, timed("lanczos_spherical", st, [&] { return launch_lanczos_stencil(lp, st); }));
+    if (where == DSX_HOST) {
+        HIPCHK(m, hipMemcpyAsync(out, dout, out_vox * sizeof(float), hipMemcpyDeviceToHost, st));
+        HIPCHK(m, hipStreamSynchronize(st));
+    }
+    return DSX_OK;
+}
+
 dsx_status dsx_noise_filter_cutoff(dsx_model m, int32_t lanczos_m, int32_t mprime, int32_t oversample,
                                    float* out, int32_t where, void* hip_stream)
 {

@@ -183,6 +183,8 @@ hipError_t launch_recombine_magnetic(const RecombParams& p, int hc, int block, s
 hipError_t launch_bragg(const BraggParams& p, int order, hipStream_t st);
 hipError_t launch_lanczos(const LanczosParams& p, hipStream_t st);
 hipError_t launch_lanczos_points(const PointsParams& p, hipStream_t st);
+// the spherical cutoff: p.wn holds [s^3][(2m)^3] normalised weights; m in {2, 3, 4}
+hipError_t launch_lanczos_stencil(const LanczosParams& p, hipStream_t st);
 
 // Block sizes / LDS limits the host planner must respect.
 int recombine_max_threads(int hc, int magnetic);

@@ -350,4 +350,57 @@ hipError_t launch_lanczos_points(const PointsParams& p, hipStream_t st)
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------- spherical
+// The spherical cutoff makes the weight non-separable, so each output takes the
+// whole (2m)^3 neighbourhood: one thread per output voxel, consecutive lanes on
+// consecutive i3 (every tap's loads are one contiguous run, served from L2).  The
+// normalised weights of the s^3 output phases come from a float64 host table
+// [s^3][(2m)^3]; the input is the grown box, mirrored planes read as in the ring
+// filter.
+template <int T>
+__global__ __launch_bounds__(256) void k_lanczos_stencil(LanczosParams P)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)P.o[0] * P.o[1] * P.o[2];
+    if (idx >= total) return;
+    const int i3 = (int)(idx % P.o[2]);
+    const int i2 = (int)((idx / P.o[2]) % P.o[1]);
+    const int i1 = (int)(idx / ((int64_t)P.o[2] * P.o[1]));
+    const int s = P.s;
+    const int phase = ((i1 % s) * s + (i2 % s)) * s + (i3 % s);
+    const float* w = P.wn + (size_t)phase * T * T * T;
+    const int b1 = i1 / s + P.eoff, b2 = i2 / s + P.eoff, b3 = i3 / s + P.eoff;
+    const size_t plane = (size_t)P.e[1] * P.ipitch;
+    float acc = 0.f;
+    for (int t1 = 0; t1 < T; ++t1) {
+        const int e1 = b1 + t1;
+        const bool mir = e1 >= P.ihalf;
+        const float* pl = P.in + (size_t)(mir ? P.e[0] - 1 - e1 : e1) * plane + P.ioff;
+#pragma unroll
+        for (int t2 = 0; t2 < T; ++t2) {
+            const int e2 = mir ? P.e[1] - 1 - (b2 + t2) : b2 + t2;
+            const float* row = pl + (size_t)e2 * P.ipitch;
+#pragma unroll
+            for (int t3 = 0; t3 < T; ++t3) {
+                const int e3 = mir ? P.e[2] - 1 - (b3 + t3) : b3 + t3;
+                acc = fmaf(w[(t1 * T + t2) * T + t3], row[e3], acc);
+            }
+        }
+    }
+    P.out[idx] = acc;
+}
+
+hipError_t launch_lanczos_stencil(const LanczosParams& p, hipStream_t st)
+{
+    const int64_t total = (int64_t)p.o[0] * p.o[1] * p.o[2];
+    const dim3 grid((unsigned)((total + 255) / 256));
+    switch (2 * p.m) {
+        case 4: hipLaunchKernelGGL(k_lanczos_stencil<4>, grid, dim3(256), 0, st, p); break;
+        case 6: hipLaunchKernelGGL(k_lanczos_stencil<6>, grid, dim3(256), 0, st, p); break;
+        case 8: hipLaunchKernelGGL(k_lanczos_stencil<8>, grid, dim3(256), 0, st, p); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 }  // namespace dsx

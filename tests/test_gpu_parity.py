@@ -374,3 +374,34 @@ def test_split_sites_on_the_compositional_path(seed, K, occ):
     I = gpu_intensity(s)
     ref = O.intensity(m, O.grid_points(m.g0, m.count), -1).reshape(m.count)
     assert rel_l2(I, ref) <= TOL
+
+
+# ------------------------------------------------------------------ spherical cutoff
+
+@pytest.mark.parametrize("m,s", [(2, 1), (3, 1), (2, 2), (4, 1)])
+def test_noise_filter_spherical_cutoff(m, s):
+    """The spherically symmetric cutoff W_r (non-separable: the (2m)^3 stencil), on a
+    non-cubic cell so that the metric enters."""
+    model = synth.random_model(1400 + 10 * m + s, n=(5, 6, 4), S=2, M=2, order=2,
+                               cell=[4.1, 5.3, 6.2, 84.0, 97.0, 101.0])
+    say(f"noise_filter_spherical m={m} s={s}")
+    h = to_dsx(model)
+    out = np.empty(tuple(s * c for c in model.count), dtype=np.float32)
+    h.noise_filter_spherical(m, s, out)
+    h.close()
+    ref = O.filtered_intensity_spherical(model, m, s, order=2)
+    assert rel_l2(out, ref) <= TOL
+
+
+def test_noise_filter_spherical_symmetric_box():
+    model = synth.random_model(1450, n=(6, 4, 8), S=3, M=2, order=3)
+    model.g0, model.count = (-7, -6, -9), (15, 13, 19)
+    say("noise_filter_spherical symmetric box (half-stored grown box)")
+    h = to_dsx(model)
+    import torch
+    out = torch.empty(tuple(model.count), dtype=torch.float32, device="cuda")
+    h.noise_filter_spherical(2, 1, out)
+    torch.cuda.synchronize()
+    h.close()
+    ref = O.filtered_intensity_spherical(model, 2, 1, order=3)
+    assert rel_l2(out.cpu().numpy(), ref) <= TOL
