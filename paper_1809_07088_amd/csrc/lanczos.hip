@@ -390,8 +390,84 @@ __global__ __launch_bounds__(256) void k_lanczos_stencil(LanczosParams P)
     P.out[idx] = acc;
 }
 
+// s = 1: every output has the same weights.  A block stages the input tile of a
+// 4 x 8 x 64 output tile (with its halo) in LDS, and each thread computes the eight
+// outputs (i1, i2 = 0..7, i3) of its column: every staged row feeds the outputs of
+// all the i2 it reaches, so an output costs about T (T + 7) / 8 LDS reads instead
+// of T^3 loads.
+constexpr int kSt1 = 4, kSt2 = 8, kSt3 = 64;
+template <int T>
+__global__ __launch_bounds__(256) void k_lanczos_stencil_tile(LanczosParams P)
+{
+    constexpr int A = kSt1 + T - 1, B = kSt2 + T - 1, C = kSt3 + T - 1;
+    constexpr int CP = C + 1;                                  // LDS row pitch
+    __shared__ float tile[A * B * CP];
+    const int nb3 = (P.o[2] + kSt3 - 1) / kSt3, nb2 = (P.o[1] + kSt2 - 1) / kSt2;
+    int b = blockIdx.x;
+    const int bx3 = b % nb3; b /= nb3;
+    const int bx2 = b % nb2;
+    const int bx1 = b / nb2;
+    const int o1 = bx1 * kSt1, o2 = bx2 * kSt2, o3 = bx3 * kSt3;
+    const size_t plane = (size_t)P.e[1] * P.ipitch;
+    // stage: element (a, y, c) is input (o1 + eoff + a, o2 + eoff + y, o3 + eoff + c)
+    for (int k = threadIdx.x; k < A * B * C; k += blockDim.x) {
+        const int c = k % C, r = k / C;
+        const int y = r % B, a = r / B;
+        const int e1 = o1 + P.eoff + a, e2 = o2 + P.eoff + y, e3 = o3 + P.eoff + c;
+        float v = 0.f;
+        if (e1 < P.e[0] && e2 < P.e[1] && e3 < P.e[2]) {
+            const bool mir = e1 >= P.ihalf;
+            const size_t off = mir ? (size_t)(P.e[0] - 1 - e1) * plane + (size_t)(P.e[1] - 1 - e2) * P.ipitch
+                                         + (P.e[2] - 1 - e3)
+                                   : (size_t)e1 * plane + (size_t)e2 * P.ipitch + e3;
+            v = P.in[off + P.ioff];
+        }
+        tile[(a * B + y) * CP + c] = v;
+    }
+    __syncthreads();
+    const int c3 = threadIdx.x & 63, g = threadIdx.x >> 6;      // i3 lane, i1 within the tile
+    float acc[kSt2] = {};
+#pragma unroll 1
+    for (int t1 = 0; t1 < T; ++t1) {
+        const float* pl = tile + (size_t)((g + t1) * B) * CP + c3;
+#pragma unroll
+        for (int y = 0; y < B; ++y) {
+            float x[T];
+#pragma unroll
+            for (int t3 = 0; t3 < T; ++t3) x[t3] = pl[y * CP + t3];
+#pragma unroll
+            for (int t2 = 0; t2 < T; ++t2) {
+                const int q = y - t2;                           // output i2 this row reaches
+                if (q >= 0 && q < kSt2) {
+                    const float* w = P.wn + (t1 * T + t2) * T;
+#pragma unroll
+                    for (int t3 = 0; t3 < T; ++t3) acc[q] = fmaf(w[t3], x[t3], acc[q]);
+                }
+            }
+        }
+    }
+    const int i1 = o1 + g, i3 = o3 + c3;
+    if (i1 < P.o[0] && i3 < P.o[2]) {
+        float* o = P.out + ((size_t)i1 * P.o[1] + o2) * P.o[2] + i3;
+#pragma unroll
+        for (int q = 0; q < kSt2; ++q)
+            if (o2 + q < P.o[1]) o[(size_t)q * P.o[2]] = acc[q];
+    }
+}
+
 hipError_t launch_lanczos_stencil(const LanczosParams& p, hipStream_t st)
 {
+    if (p.s == 1) {
+        const dim3 grid((unsigned)(((p.o[0] + kSt1 - 1) / kSt1) * ((p.o[1] + kSt2 - 1) / kSt2) *
+                                   ((p.o[2] + kSt3 - 1) / kSt3)));
+        switch (2 * p.m) {
+            case 4: hipLaunchKernelGGL(k_lanczos_stencil_tile<4>, grid, dim3(256), 0, st, p); break;
+            case 6: hipLaunchKernelGGL(k_lanczos_stencil_tile<6>, grid, dim3(256), 0, st, p); break;
+            case 8: hipLaunchKernelGGL(k_lanczos_stencil_tile<8>, grid, dim3(256), 0, st, p); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     const int64_t total = (int64_t)p.o[0] * p.o[1] * p.o[2];
     const dim3 grid((unsigned)((total + 255) / 256));
     switch (2 * p.m) {
