@@ -1415,6 +1415,18 @@ dsx_status dsx_filter_points(dsx_model m, int32_t lanczos_m, int32_t mprime, int
             lo[a] = std::min(lo[a], f - w + 1);
             hi[a] = std::max(hi[a], f + w);
         }
+    // a box nearly symmetric about G = 0 is made symmetric (at most ~10 % more volume):
+    // the recombination then evaluates half of it (I(-G) = I(G))
+    bool near_sym = true;
+    for (int a = 0; a < 3; ++a) {
+        const long r = std::max(std::labs(lo[a]), std::labs(hi[a]));
+        if ((double)(2 * r + 1) > 1.1 * (double)(hi[a] - lo[a] + 1) + 2.0) near_sym = false;
+    }
+    if (near_sym)
+        for (int a = 0; a < 3; ++a) {
+            const long r = std::max(std::labs(lo[a]), std::labs(hi[a]));
+            lo[a] = -r; hi[a] = r;
+        }
     Box bx;
     for (int a = 0; a < 3; ++a) { bx.g0[a] = (int)lo[a]; bx.cnt[a] = (int)(hi[a] - lo[a] + 1); }
     const size_t vox = (size_t)bx.cnt[0] * bx.cnt[1] * bx.cnt[2];
