@@ -78,6 +78,9 @@ typedef struct {
                             /*   disp_expansion), 0 = no displacements; magnetic: must be 0                  */
     int32_t n_configs;      /* ensemble size M >= 1 (<.> is the mean over configurations)                    */
     double  norm_N;         /* N of I = <|F|^2>/N (Eq. intensity_sf); 0 => n1 n2 n3 x distinct positions      */
+    const double* dw_b;     /* [n_sites] isotropic Debye-Waller B [Angstrom^2] of magnetic sites: the factor  */
+                            /*   T_mu(G) = exp(-B s^2), s = |Q|/(4 pi), of Eq. mag_sf; NULL => T = 1.          */
+                            /*   Ignored for nuclear models.                                                   */
 } dsx_model_desc;
 
 /*

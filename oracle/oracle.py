@@ -201,11 +201,16 @@ def bragg_diffuse(F, G, n, normN) -> np.ndarray:
 
 
 def magnetic_perp(model, G, F_sites) -> np.ndarray:
-    """F_perp = F - Ghat (Ghat . F) of F = sum_mu f_mu(|Q|) F_mu; zero at G = 0. [M][nG][3]."""
+    """F_perp = F - Ghat (Ghat . F) of F = sum_mu f_mu(|Q|) T_mu(G) F_mu (Eq. mag_sf; T = 1
+    unless the model gives Debye-Waller B values); zero at G = 0. [M][nG][3]."""
     Q = q_cartesian(model, G)
     qn = np.linalg.norm(Q, axis=-1)
     s = qn / (4.0 * np.pi)
     f = np.stack([magnetic_form_factor(model.ff[mu], s) for mu in range(model.n_sites)], axis=-1)
+    dw = getattr(model, "dw_b", None)
+    if dw is not None:
+        # Debye-Waller factor T_mu(G) = exp(-B_mu s^2) of Eq. mag_sf
+        f = f * np.exp(-np.outer(s * s, np.asarray(dw, dtype=np.float64)))
     F = np.einsum("gs,mgsc->mgc", f, F_sites)
     with np.errstate(invalid="ignore", divide="ignore"):
         ghat = np.where(qn[:, None] > 0, Q / qn[:, None], 0.0)

@@ -34,7 +34,8 @@ class ModelDesc(ctypes.Structure):
     _fields_ = [("cell", ctypes.c_double * 6), ("n", ctypes.c_int32 * 3), ("n_sites", ctypes.c_int32),
                 ("frac", ctypes.c_void_p), ("pos_id", ctypes.c_void_p), ("b", ctypes.c_void_p),
                 ("ff", ctypes.c_void_p), ("kind", ctypes.c_int32), ("has_occ", ctypes.c_int32),
-                ("taylor_order", ctypes.c_int32), ("n_configs", ctypes.c_int32), ("norm_N", ctypes.c_double)]
+                ("taylor_order", ctypes.c_int32), ("n_configs", ctypes.c_int32), ("norm_N", ctypes.c_double),
+                ("dw_b", ctypes.c_void_p)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -168,12 +169,13 @@ def _stream_handle(stream):
 
 
 def make_desc(cell, n, frac, b, kind=NUCLEAR, taylor_order=0, n_configs=1, has_occ=False,
-              ff=None, pos_id=None, norm_N=0.0):
+              ff=None, pos_id=None, norm_N=0.0, dw_b=None):
     """A dsx_model_desc plus the arrays it points to (kept alive by the caller)."""
     frac = np.ascontiguousarray(frac, dtype=np.float64).reshape(-1, 3)
     b = np.ascontiguousarray(b, dtype=np.float64).reshape(-1)
     ffa = None if ff is None else np.ascontiguousarray(ff, dtype=np.float64).reshape(-1, 7)
     pid = None if pos_id is None else np.ascontiguousarray(pos_id, dtype=np.int32)
+    dwb = None if dw_b is None else np.ascontiguousarray(dw_b, dtype=np.float64).reshape(-1)
     d = ModelDesc()
     d.cell[:] = [float(v) for v in cell]
     d.n[:] = [int(v) for v in n]
@@ -184,7 +186,8 @@ def make_desc(cell, n, frac, b, kind=NUCLEAR, taylor_order=0, n_configs=1, has_o
     d.pos_id = None if pid is None else pid.ctypes.data
     d.kind, d.has_occ, d.taylor_order = int(kind), int(bool(has_occ)), int(taylor_order)
     d.n_configs, d.norm_N = int(n_configs), float(norm_N)
-    return d, (frac, b, ffa, pid)
+    d.dw_b = None if dwb is None else dwb.ctypes.data
+    return d, (frac, b, ffa, pid, dwb)
 
 
 def plan_query(**kw) -> PlanInfo:

@@ -309,6 +309,7 @@ int count_classes(const dsx_model_desc* d, std::vector<int>* site_of, std::vecto
             bool same = d->frac[3 * i + 2] == d->frac[3 * j + 2];
             if (same && d->kind == DSX_MAGNETIC && d->ff)
                 for (int k = 0; k < 7; ++k) same = same && d->ff[7 * i + k] == d->ff[7 * j + k];
+            if (same && d->kind == DSX_MAGNETIC && d->dw_b) same = d->dw_b[i] == d->dw_b[j];
             if (same) cls[j] = nc;
         }
         ++nc;
@@ -619,9 +620,9 @@ dsx_status plan_recombine(dsx_model m, const Box& bx, float* out, const Layout& 
     p.ff_uniform = 1;
     for (int i = 0; i < m->S; ++i) {
         const int mu = m->site_of[i];
-        for (int k = 0; k < 7; ++k) {
-            p.ff[i][k] = m->has_ff ? (float)m->ff[7 * mu + k] : (k == 6 ? 1.f : 0.f);
-            if (m->has_ff && m->ff[7 * mu + k] != m->ff[k]) p.ff_uniform = 0;
+        for (int k = 0; k < 8; ++k) {
+            p.ff[i][k] = m->has_ff ? (float)m->ff[8 * mu + k] : (k == 6 ? 1.f : 0.f);
+            if (m->has_ff && m->ff[8 * mu + k] != m->ff[k]) p.ff_uniform = 0;
         }
     }
     lp.hc = tb->hc;
@@ -873,8 +874,16 @@ dsx_status create_model_impl(const dsx_model_desc* d, bool transient, dsx_model*
     m->M = d->n_configs;
     m->frac.assign(d->frac, d->frac + 3 * m->S);
     m->b.assign(d->b, d->b + m->S);
-    m->has_ff = d->kind == DSX_MAGNETIC && d->ff != nullptr;
-    if (m->has_ff) m->ff.assign(d->ff, d->ff + 7 * m->S);
+    // per site: the 7 form-factor parameters (f = 1 when none are given) and the
+    // Debye-Waller B (0 when none is given)
+    m->has_ff = d->kind == DSX_MAGNETIC && (d->ff != nullptr || d->dw_b != nullptr);
+    if (m->has_ff) {
+        m->ff.assign((size_t)8 * m->S, 0.0);
+        for (int mu = 0; mu < m->S; ++mu) {
+            for (int k = 0; k < 7; ++k) m->ff[8 * mu + k] = d->ff ? d->ff[7 * mu + k] : (k == 6 ? 1.0 : 0.0);
+            m->ff[8 * mu + 7] = d->dw_b ? d->dw_b[mu] : 0.0;
+        }
+    }
     reciprocal_basis(m->cell, m->recip);
     int npos = m->S;
     if (d->pos_id) {
@@ -923,11 +932,11 @@ dsx_status create_model_impl(const dsx_model_desc* d, bool transient, dsx_model*
     if (e == hipSuccess && !transient) e = alloc((void**)&m->d_X, (size_t)z.spectrum_bytes);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&m->order_ev, hipEventDisableTiming);
     if (e == hipSuccess) {
-        std::vector<double> site((size_t)m->S * 11, 0.0);
+        std::vector<double> site((size_t)m->S * 12, 0.0);
         for (int mu = 0; mu < m->S; ++mu) {
-            for (int a = 0; a < 3; ++a) site[11 * mu + a] = m->frac[3 * mu + a];
-            site[11 * mu + 3] = m->b[mu];
-            for (int k = 0; k < 7; ++k) site[11 * mu + 4 + k] = m->has_ff ? m->ff[7 * mu + k] : 0.0;
+            for (int a = 0; a < 3; ++a) site[12 * mu + a] = m->frac[3 * mu + a];
+            site[12 * mu + 3] = m->b[mu];
+            for (int k = 0; k < 8; ++k) site[12 * mu + 4 + k] = m->has_ff ? m->ff[8 * mu + k] : 0.0;
         }
         e = alloc((void**)&m->d_site, site.size() * sizeof(double));
         if (e == hipSuccess)

@@ -123,7 +123,7 @@ struct RecombParams {
     // magnetic only
     float recip[9];         // rows a*, b*, c* (inverse Angstrom)
     int32_t ff_uniform;     // 1 when every site has the same form factor
-    float ff[kMaxSites][7];  // per sorted position
+    float ff[kMaxSites][8];  // per sorted position: form factor (7), Debye-Waller B
 };
 
 // ---------------------------------------------------------------------------- Bragg (k = 0)
@@ -136,7 +136,7 @@ struct BraggParams {
     int32_t Hlo[3], nH[3];  // H with n H inside the box
     int32_t S, T, M, kind;
     double scale;           // 1/N  (magnetic: C/N); the means over configurations are explicit
-    const double* site;     // [S][11]: r_mu (3), b_mu, form factor (7)
+    const double* site;     // [S][12]: r_mu (3), b_mu, form factor (7), Debye-Waller B
     double recip[9];
     int32_t has_ff;
     int8_t mono[3 * kMaxMono];   // exponents (p, q, r) of monomial t

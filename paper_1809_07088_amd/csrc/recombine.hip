@@ -778,8 +778,11 @@ void k_recombine_folded(RecombParams P)
 }
 
 // ---------------------------------------------------------------------------- magnetic
+// f(s) T(s) of a site: the analytic form factor times the Debye-Waller factor
+// T = exp(-B s^2) of Eq. mag_sf (f[7] = B; 0 when none is given).
 __device__ __forceinline__ float mag_ff(const float* f, float s2) {
-    return f[0] * expf(-f[1] * s2) + f[2] * expf(-f[3] * s2) + f[4] * expf(-f[5] * s2) + f[6];
+    const float ff = f[0] * expf(-f[1] * s2) + f[2] * expf(-f[3] * s2) + f[4] * expf(-f[5] * s2) + f[6];
+    return f[7] == 0.f ? ff : ff * expf(-f[7] * s2);
 }
 
 template <int HC>
@@ -1099,7 +1102,7 @@ __global__ __launch_bounds__(64) void k_bragg_nuclear(BraggParams P)
                 si += __shfl_down(si, off, 64);
             }
             if (lane == 0) {
-                const double* sd = P.site + 11 * mu;
+                const double* sd = P.site + 12 * mu;
                 double x = H[0] * sd[0] + H[1] * sd[1] + H[2] * sd[2];
                 x -= floor(x);
                 double sn, cs;
@@ -1120,7 +1123,8 @@ __global__ __launch_bounds__(64) void k_bragg_nuclear(BraggParams P)
 }
 
 __device__ double mag_ff_d(const double* f, double s2) {
-    return f[0] * exp(-f[1] * s2) + f[2] * exp(-f[3] * s2) + f[4] * exp(-f[5] * s2) + f[6];
+    const double ff = f[0] * exp(-f[1] * s2) + f[2] * exp(-f[3] * s2) + f[4] * exp(-f[5] * s2) + f[6];
+    return f[7] == 0.0 ? ff : ff * exp(-f[7] * s2);
 }
 
 __global__ __launch_bounds__(256) void k_bragg_magnetic(BraggParams P)
@@ -1143,7 +1147,7 @@ __global__ __launch_bounds__(256) void k_bragg_magnetic(BraggParams P)
     for (int m = 0; m < P.M; ++m) {
         double fr[3] = {0, 0, 0}, fi[3] = {0, 0, 0};
         for (int mu = 0; mu < P.S; ++mu) {
-            const double* sd = P.site + 11 * mu;
+            const double* sd = P.site + 12 * mu;
             double x = H[0] * sd[0] + H[1] * sd[1] + H[2] * sd[2];
             x -= floor(x);
             double sn, cs;

@@ -54,6 +54,7 @@ class Model:
     ff: Optional[np.ndarray] = None   # (S, 7) magnetic form factor parameters
     pos_id: Optional[np.ndarray] = None  # (S,) position index for the normalisation
     norm_N: float = 0.0           # 0 => n1 n2 n3 x number of distinct positions
+    dw_b: Optional[np.ndarray] = None   # (S,) magnetic Debye-Waller B [Angstrom^2] or None (T = 1)
     occ: Optional[np.ndarray] = None
     disp: Optional[np.ndarray] = None
     spin: Optional[np.ndarray] = None

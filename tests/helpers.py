@@ -8,7 +8,7 @@ def desc_kwargs(model):
     return dict(cell=model.cell, n=model.n, frac=model.frac, b=model.b, kind=model.kind,
                 taylor_order=model.order if model.kind == dsx.NUCLEAR else 0,
                 n_configs=model.n_configs, has_occ=model.occ is not None, ff=model.ff,
-                pos_id=model.pos_id, norm_N=model.norm_N)
+                pos_id=model.pos_id, norm_N=model.norm_N, dw_b=getattr(model, "dw_b", None))
 
 
 def to_dsx(model, device=True):

@@ -374,3 +374,21 @@ def test_spherical_cutoff_is_isotropic_and_keeps_constants(m, s):
     assert np.allclose(b, a.transpose(2, 0, 1), rtol=1e-12)
     c = O.lanczos_spherical(np.full_like(I, 1.75), e0, m, s, q0, qc, cell, n)
     assert np.allclose(c, 1.75, rtol=1e-13)
+
+
+# ------------------------------------------------- magnetic Debye-Waller factor T_mu(G)
+
+def test_debye_waller_scales_a_single_site_by_exp_minus_2Bs2():
+    """One magnetic site: T = exp(-B s^2) multiplies F, so I scales by exp(-2 B s^2),
+    with s = |Q|/(4 pi) taken here from the real-space metric (|Q|^2 = 4 pi^2 g.Gi.g)."""
+    m = synth.random_model(60, n=(3, 4, 3), S=1, M=2, kind=synth.MAGNETIC,
+                           cell=[4.2, 5.1, 6.3, 86.0, 95.0, 104.0])
+    G = O.grid_points(m.g0, m.count)[::5]
+    I0 = O.intensity(m, G)
+    m.dw_b = np.array([0.8])
+    I1 = O.intensity(m, G)
+    A = O.cell_vectors(m.cell)
+    Gi = np.linalg.inv(A @ A.T)                          # inverse real-space metric
+    g = G / np.asarray(m.n, float)
+    s2 = np.einsum("gi,ij,gj->g", g, Gi, g) * 4 * np.pi ** 2 / (16 * np.pi ** 2)
+    assert np.allclose(I1, I0 * np.exp(-2 * 0.8 * s2), rtol=1e-12, atol=1e-15)
