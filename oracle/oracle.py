@@ -150,6 +150,22 @@ def structure_factor(model, G, order=None) -> np.ndarray:
     occ = None if model.occ is None else np.ascontiguousarray(model.occ, dtype=np.float32)
     disp = None if model.disp is None else np.ascontiguousarray(model.disp, dtype=np.float32)
     M = model.n_configs
+    if getattr(model, "ff", None) is not None:
+        # a |Q|-dependent scattering factor per site (X-ray f_j(|Q|)): b_mu f_mu(s) with
+        # s = |Q|/(4 pi), the sum taken site by site
+        s_q = np.linalg.norm(q_cartesian(model, G), axis=-1) / (4.0 * np.pi)
+        F = np.zeros((M, G.shape[0]), dtype=np.complex128)
+        for mu in range(model.n_sites):
+            out = np.zeros((M, G.shape[0], 2), dtype=np.float64)
+            o1 = None if occ is None else np.ascontiguousarray(occ[:, mu:mu + 1])
+            d1 = None if disp is None else np.ascontiguousarray(disp[:, mu:mu + 1])
+            rc = lib().orc_sf_nuclear(_ptr(n), 1, _ptr(np.ascontiguousarray(frac[mu:mu + 1])),
+                                      _ptr(np.ascontiguousarray(b[mu:mu + 1])), M, _ptr(o1), _ptr(d1),
+                                      int(order), G.shape[0], _ptr(G), _ptr(out))
+            if rc != 0:
+                raise ValueError("orc_sf_nuclear rejected its arguments")
+            F += magnetic_form_factor(model.ff[mu], s_q)[None, :] * (out[..., 0] + 1j * out[..., 1])
+        return F
     out = np.zeros((M, G.shape[0], 2), dtype=np.float64)
     rc = lib().orc_sf_nuclear(_ptr(n), model.n_sites, _ptr(frac), _ptr(b), M, _ptr(occ),
                               _ptr(disp), int(order), G.shape[0], _ptr(G), _ptr(out))

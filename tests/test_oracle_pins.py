@@ -392,3 +392,20 @@ def test_debye_waller_scales_a_single_site_by_exp_minus_2Bs2():
     g = G / np.asarray(m.n, float)
     s2 = np.einsum("gi,ij,gj->g", g, Gi, g) * 4 * np.pi ** 2 / (16 * np.pi ** 2)
     assert np.allclose(I1, I0 * np.exp(-2 * 0.8 * s2), rtol=1e-12, atol=1e-15)
+
+
+def test_nuclear_form_factor_scales_a_single_site_by_f_squared():
+    """A |Q|-dependent scattering factor (X-ray f(|Q|)) on one site: I scales by f(s)^2,
+    s = |Q|/(4 pi) from the real-space metric."""
+    m = synth.random_model(61, n=(3, 4, 3), S=1, M=2, order=3, cell=[4.2, 5.1, 6.3, 86.0, 95.0, 104.0])
+    G = O.grid_points(m.g0, m.count)[::5]
+    I0 = O.intensity(m, G)
+    ff = np.array([2.1, 3.0, 1.2, 0.7, 0.4, 9.0, 0.3])
+    m.ff = ff[None, :]
+    I1 = O.intensity(m, G)
+    A = O.cell_vectors(m.cell)
+    Gi = np.linalg.inv(A @ A.T)
+    g = G / np.asarray(m.n, float)
+    s2 = np.einsum("gi,ij,gj->g", g, Gi, g) / 4
+    f = ff[0] * np.exp(-ff[1] * s2) + ff[2] * np.exp(-ff[3] * s2) + ff[4] * np.exp(-ff[5] * s2) + ff[6]
+    assert np.allclose(I1, I0 * f * f, rtol=1e-11, atol=1e-14)
