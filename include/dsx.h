@@ -69,9 +69,11 @@ typedef struct {
     const double* frac;     /* [n_sites][3] average fractional positions r_mu (Eq. r_vec)                     */
     const int32_t* pos_id;  /* [n_sites] position index used for the normalisation N, or NULL (= identity)   */
     const double* b;        /* [n_sites] scattering length b_mu (nuclear) or moment scale (magnetic)         */
-    const double* ff;       /* [n_sites][7] magnetic form factor (A,a,B,b,C,c,D):                             */
+    const double* ff;       /* [n_sites][7] form factor (A,a,B,b,C,c,D):                                      */
                             /*   f(s) = A e^{-a s^2} + B e^{-b s^2} + C e^{-c s^2} + D, s = |Q|/(4 pi);        */
-                            /*   NULL => f = 1.  Ignored for nuclear models.                                   */
+                            /*   magnetic: f_mag of Eq. mag_sf; nuclear: a |Q|-dependent factor multiplying  */
+                            /*   b_mu (X-ray f_j(|Q|), Sec. II), which takes the class form of the           */
+                            /*   recombination (sites grouped by r_mu3 and f).  NULL => f = 1.               */
     int32_t kind;           /* DSX_NUCLEAR or DSX_MAGNETIC                                                    */
     int32_t has_occ;        /* 0: delta == 1 everywhere (no occupancy array is read)                         */
     int32_t taylor_order;   /* nuclear: order N of the expansion of exp(i G.u) (Sec. III.C, Eq.              */

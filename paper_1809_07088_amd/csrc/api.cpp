@@ -307,7 +307,7 @@ int count_classes(const dsx_model_desc* d, std::vector<int>* site_of, std::vecto
         for (int j = i + 1; j < d->n_sites; ++j) {
             if (cls[j] >= 0) continue;
             bool same = d->frac[3 * i + 2] == d->frac[3 * j + 2];
-            if (same && d->kind == DSX_MAGNETIC && d->ff)
+            if (same && d->ff)
                 for (int k = 0; k < 7; ++k) same = same && d->ff[7 * i + k] == d->ff[7 * j + k];
             if (same && d->kind == DSX_MAGNETIC && d->dw_b) same = d->dw_b[i] == d->dw_b[j];
             if (same) cls[j] = nc;
@@ -606,8 +606,10 @@ dsx_status plan_recombine(dsx_model m, const Box& bx, float* out, const Layout& 
     for (int i = 0; i < m->S; ++i) { p.site_of[i] = m->site_of[i]; p.class_of[i] = m->class_of[i]; }
     p.bs_elems = m->bs_elems;
     p.xs_elems = m->xs_elems;
-    // parity form: every r_mu3 a multiple of 1/2 (exactly, as given)
-    p.parity = m->kind == DSX_NUCLEAR ? 1 : 0;
+    // parity form: every r_mu3 a multiple of 1/2 (exactly, as given); a |Q|-dependent
+    // nuclear scattering factor needs the classes apart at level C (class form)
+    p.nuc_ff = (m->kind == DSX_NUCLEAR && m->has_ff) ? 1 : 0;
+    p.parity = (m->kind == DSX_NUCLEAR && !p.nuc_ff) ? 1 : 0;
     for (int i = 0; i < m->S; ++i) {
         const double t2 = 2.0 * m->frac[3 * m->site_of[i] + 2];
         if (t2 != std::floor(t2)) p.parity = 0;
@@ -633,7 +635,7 @@ dsx_status plan_recombine(dsx_model m, const Box& bx, float* out, const Layout& 
     // than sites, and the class buffers fit the LDS
     // (the folded kernel addresses the spectra of one configuration with 31-bit offsets)
     const bool small_spectra = (unsigned long long)n1 * n2 * m->SF * m->nh * sizeof(float2) < (1ULL << 31);
-    if (!mag && p.variant != 3 && m->nclass < m->S && small_spectra) {
+    if (!mag && !p.nuc_ff && p.variant != 3 && m->nclass < m->S && small_spectra) {
         bool halves = true, whole = true;
         for (int i = 0; i < m->S; ++i) {
             const double r2 = m->frac[3 * m->site_of[i] + 1];
@@ -876,12 +878,12 @@ dsx_status create_model_impl(const dsx_model_desc* d, bool transient, dsx_model*
     m->b.assign(d->b, d->b + m->S);
     // per site: the 7 form-factor parameters (f = 1 when none are given) and the
     // Debye-Waller B (0 when none is given)
-    m->has_ff = d->kind == DSX_MAGNETIC && (d->ff != nullptr || d->dw_b != nullptr);
+    m->has_ff = d->ff != nullptr || (d->kind == DSX_MAGNETIC && d->dw_b != nullptr);
     if (m->has_ff) {
         m->ff.assign((size_t)8 * m->S, 0.0);
         for (int mu = 0; mu < m->S; ++mu) {
             for (int k = 0; k < 7; ++k) m->ff[8 * mu + k] = d->ff ? d->ff[7 * mu + k] : (k == 6 ? 1.0 : 0.0);
-            m->ff[8 * mu + 7] = d->dw_b ? d->dw_b[mu] : 0.0;
+            m->ff[8 * mu + 7] = (d->kind == DSX_MAGNETIC && d->dw_b) ? d->dw_b[mu] : 0.0;
         }
     }
     reciprocal_basis(m->cell, m->recip);

@@ -111,6 +111,7 @@ struct RecombParams {
     int32_t hmin_s[8];      // folded form, per slice: the fewest H3 values any item of a full wave has
     int32_t sgn2[kMaxSites];         // per sorted position: e^{2 pi i r_mu2} = +-1
     int32_t parity;         // every r_mu3 is a multiple of 1/2 (the parity form applies)
+    int32_t nuc_ff;         // nuclear sites with |Q|-dependent scattering factors ff (class form)
     int32_t class_sign[kMaxSites];   // per class: e^{2 pi i r_c3} = +-1 in the parity form
     int32_t nsc;            // site chunks (each fits the LDS budget)
     int32_t bs_elems;       // float2 elements of the level-A buffer (the staging area follows)

@@ -143,6 +143,14 @@ __device__ __forceinline__ const float2* stage_class_phases(const RecombParams& 
 constexpr int kBufferFlags = 0x00020000;
 constexpr uint32_t kNoRecord = 0x80000000u;   // an offset past every record count used here
 
+// f(s) T(s) of a site: the analytic form factor (A e^{-a s^2} + B e^{-b s^2} +
+// C e^{-c s^2} + D) times the Debye-Waller factor T = exp(-B_dw s^2) (f[7] = B_dw, 0
+// when none is given).  Nuclear sites use it as a |Q|-dependent scattering factor.
+__device__ __forceinline__ float site_ff(const float* f, float s2) {
+    const float ff = f[0] * expf(-f[1] * s2) + f[2] * expf(-f[3] * s2) + f[4] * expf(-f[5] * s2) + f[6];
+    return f[7] == 0.f ? ff : ff * expf(-f[7] * s2);
+}
+
 // ---------------------------------------------------------------------------- nuclear
 __device__ __forceinline__ int wave_min_uniform(int v)
 {
@@ -287,6 +295,11 @@ __global__ __launch_bounds__(512, 4) void k_recombine_nuclear(RecombParams P)
     a2[0] = 1.f;
 #pragma unroll
     for (int q = 1; q <= N; ++q) a2[q] = a2[q - 1] * tau2 / (float)q;
+    // g1 a* + g2 b* of the thread's row (for |Q|-dependent scattering factors)
+    const float g1f = (float)w.G1 / (float)n1, g2f = (float)G2 / (float)n2;
+    const float q12x = g1f * P.recip[0] + g2f * P.recip[3];
+    const float q12y = g1f * P.recip[1] + g2f * P.recip[4];
+    const float q12z = g1f * P.recip[2] + g2f * P.recip[5];
 
     float I[MULTI ? HC : 1];
 #pragma unroll
@@ -424,7 +437,15 @@ __global__ __launch_bounds__(512, 4) void k_recombine_nuclear(RecombParams P)
 #pragma unroll
                                 for (int r = N - 1; r >= 0; --r)
                                     acc = make_float2(D[r].x - t3 * acc.y, D[r].y + t3 * acc.x);
-                                const float2 e3 = tH[h];
+                                float2 e3 = tH[h];
+                                if (P.nuc_ff) {
+                                    // the class's scattering factor f(|Q|), s = |Q|/(4 pi)
+                                    const float g3 = (float)(k3 + n3 * (H3lo + hbeg + h)) / (float)n3;
+                                    const float qx = q12x + g3 * P.recip[6], qy = q12y + g3 * P.recip[7],
+                                                qz = q12z + g3 * P.recip[8];
+                                    const float f = site_ff(P.ff[sp], (qx * qx + qy * qy + qz * qz) * 0.00633257397764611f);
+                                    e3 = make_float2(e3.x * f, e3.y * f);
+                                }
                                 F[h].x += e3.x * acc.x - e3.y * acc.y;
                                 F[h].y += e3.x * acc.y + e3.y * acc.x;
                             }
@@ -778,12 +799,8 @@ void k_recombine_folded(RecombParams P)
 }
 
 // ---------------------------------------------------------------------------- magnetic
-// f(s) T(s) of a site: the analytic form factor times the Debye-Waller factor
-// T = exp(-B s^2) of Eq. mag_sf (f[7] = B; 0 when none is given).
-__device__ __forceinline__ float mag_ff(const float* f, float s2) {
-    const float ff = f[0] * expf(-f[1] * s2) + f[2] * expf(-f[3] * s2) + f[4] * expf(-f[5] * s2) + f[6];
-    return f[7] == 0.f ? ff : ff * expf(-f[7] * s2);
-}
+// the form factor and Debye-Waller factor of Eq. mag_sf
+__device__ __forceinline__ float mag_ff(const float* f, float s2) { return site_ff(f, s2); }
 
 template <int HC>
 __global__ __launch_bounds__(512) void k_recombine_magnetic(RecombParams P)
@@ -1107,8 +1124,20 @@ __global__ __launch_bounds__(64) void k_bragg_nuclear(BraggParams P)
                 x -= floor(x);
                 double sn, cs;
                 sincos(6.283185307179586476925 * x, &sn, &cs);
-                fr += sd[3] * (cs * sr - sn * si);
-                fi += sd[3] * (cs * si + sn * sr);
+                double wgt = sd[3];
+                if (P.has_ff) {
+                    // |Q|-dependent scattering factor at Q = H (reciprocal-lattice units)
+                    double q[3] = {0.0, 0.0, 0.0};
+                    for (int a = 0; a < 3; ++a)
+                        for (int c = 0; c < 3; ++c) q[c] += H[a] * P.recip[3 * a + c];
+                    const double s2 = (q[0] * q[0] + q[1] * q[1] + q[2] * q[2]) / (16.0 * M_PI * M_PI);
+                    const double* f = sd + 4;
+                    double ffv = f[0] * exp(-f[1] * s2) + f[2] * exp(-f[3] * s2) + f[4] * exp(-f[5] * s2) + f[6];
+                    if (f[7] != 0.0) ffv *= exp(-f[7] * s2);
+                    wgt *= ffv;
+                }
+                fr += wgt * (cs * sr - sn * si);
+                fi += wgt * (cs * si + sn * sr);
             }
         }
         sq += fr * fr + fi * fi;

@@ -421,3 +421,23 @@ def test_magnetic_debye_waller_factor(same_b):
     I = gpu_intensity(m)
     ref = O.intensity(m, O.grid_points(m.g0, m.count)).reshape(m.count)
     assert rel_l2(I, ref) <= TOL
+
+
+# ------------------------------------------------------------------ X-ray scattering factors
+
+@pytest.mark.parametrize("order,M,share_r3", [(3, 2, False), (0, 2, True), (5, 1, True)])
+def test_nuclear_q_dependent_scattering_factors(order, M, share_r3):
+    """Nuclear sites with |Q|-dependent scattering factors (X-ray f_j(|Q|)): the class
+    form with the class's factor at level C, and the FP64 Bragg points; sites sharing
+    r3 but not f stay in different classes."""
+    m = synth.random_model(1600 + order, n=(4, 5, 6), S=3, M=M, order=order, with_disp=order > 0,
+                           cell=[4.3, 5.2, 6.1, 88.0, 93.0, 99.0])
+    if share_r3:
+        m.frac[:, 2] = [0.3, 0.3, 0.75]
+    m.ff = np.array([[2.1, 3.0, 1.2, 0.7, 0.4, 9.0, 0.3],
+                     [1.5, 1.1, 0.9, 4.0, 0.2, 0.5, 0.8],
+                     [0.6, 2.5, 1.8, 0.3, 0.9, 6.0, 0.1]])
+    say(f"nuclear scattering factors order={order} M={M} share_r3={share_r3}")
+    I = gpu_intensity(m)
+    ref = O.intensity(m, O.grid_points(m.g0, m.count), order if order > 0 else None).reshape(m.count)
+    assert rel_l2(I, ref) <= TOL
