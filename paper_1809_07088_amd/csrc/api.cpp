@@ -1601,7 +1601,7 @@ dsx_status dsx_autotune(dsx_model m, int32_t lanczos_m, void* hip_stream)
     int best_t1 = 12;
     if (filt) {
         best = -1.f;
-        for (int cand : {8, 12, 16, 20, 26, 32, 52, 64}) {
+        for (int cand : {4, 6, 8, 12, 16, 20, 26, 32, 52, 64}) {
             m->tune_lanczos_t1 = cand;
             const float t = time_min(st, 3, [&] { return enqueue_filter(m, lanczos_m, 1, scratch, st, false); });
             if (t >= 0.f && (best < 0.f || t < best)) { best = t; best_t1 = cand; }

@@ -94,7 +94,7 @@ def test_autotune_cache_is_deterministic(tmp_path, monkeypatch):
     # the cache line holds the choices in the order form, FFT fields per block, filter planes
     v, fc, t1 = (int(x) for x in lines[0].split("\t")[1].split())
     assert (q["recombine_form"], q["fft_fields_per_block"], q["filter_planes_per_block"]) == (v, fc, t1)
-    assert v in (0, 2, 3, 4) and fc in (0, 1, 2, 4) and t1 in (8, 12, 16, 20, 26, 32, 52, 64)
+    assert v in (0, 2, 3, 4) and fc in (0, 1, 2, 4) and t1 in (4, 6, 8, 12, 16, 20, 26, 32, 52, 64)
     a = torch.empty(tuple(m.count), device="cuda")
     b = torch.empty(tuple(m.count), device="cuda")
     h.compute_intensity(a)
