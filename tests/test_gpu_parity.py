@@ -441,3 +441,22 @@ def test_nuclear_q_dependent_scattering_factors(order, M, share_r3):
     I = gpu_intensity(m)
     ref = O.intensity(m, O.grid_points(m.g0, m.count), order if order > 0 else None).reshape(m.count)
     assert rel_l2(I, ref) <= TOL
+
+
+def test_filter_variant_argument_errors():
+    import paper_1809_07088_amd as dsx
+    model = synth.random_model(1700, n=(4, 4, 4), S=1, M=1, order=1)
+    say("filter variant argument errors")
+    h = to_dsx(model)
+    out = np.empty(tuple(model.count), dtype=np.float32)
+    for call, status in [(lambda: h.noise_filter_cutoff(3, 3, 1, out), dsx.ERR_ARG),        # m m' odd
+                         (lambda: h.noise_filter_cutoff(2, 1, 1, out), dsx.ERR_ARG),        # m' < 2
+                         (lambda: h.noise_filter_cutoff(8, 6, 1, out), dsx.ERR_UNSUPPORTED),  # w = 24
+                         (lambda: h.noise_filter_spherical(5, 1, out), dsx.ERR_UNSUPPORTED),
+                         (lambda: h.noise_filter_spherical(1, 1, out), dsx.ERR_ARG),
+                         (lambda: h.filter_points(2, np.zeros((1, 3)), out[:1, 0, 0].copy(), mprime=20),
+                          dsx.ERR_UNSUPPORTED)]:                                          # w = 20 > 8
+        with pytest.raises(dsx.DsxError) as e:
+            call()
+        assert e.value.status == status
+    h.close()
