@@ -373,8 +373,8 @@ const char* dsx_last_error(void);
 
 /*
  * Per-kernel timing (instrumentation; not part of the method).  While enabled,
- * every kernel the library launches is bracketed by two HIP events recorded on
- * the stream it runs on.  dsx_profile_read waits for the recorded events, folds
+ * every kernel the library launches (or each of the kind dsx_profile_select
+ * names) is bracketed by two HIP events recorded on the stream it runs on.  dsx_profile_read waits for the recorded events, folds
  * them into per-kernel totals and copies at most `max` entries into `out`,
  * returning the number of kernel kinds seen since the last reset.  Process-wide;
  * safe to call from any thread.
@@ -386,6 +386,11 @@ typedef struct {
 } dsx_kernel_stat;
 
 dsx_status dsx_profile_enable(int32_t on);
+/* Restrict the timing to one kernel kind (`kernel` one of the names above; the
+ * other launches get no events, so they run as they do unprofiled), or time every
+ * kind again with NULL or "".  DSX_ERR_ARG for a name longer than 31 bytes; a
+ * name no kernel has simply times nothing. */
+dsx_status dsx_profile_select(const char* kernel);
 int32_t    dsx_profile_read(dsx_kernel_stat* out, int32_t max);
 dsx_status dsx_profile_reset(void);
 

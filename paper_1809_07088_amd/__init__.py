@@ -50,7 +50,7 @@ class KernelStat(ctypes.Structure):
 
 EXPORTS = ("dsx_plan_query", "dsx_create_model", "dsx_set_sites", "dsx_set_sites_async", "dsx_set_grid",
            "dsx_compute_intensity", "dsx_noise_filter", "dsx_destroy_model", "dsx_last_error",
-           "dsx_version", "dsx_profile_enable", "dsx_profile_read", "dsx_profile_reset",
+           "dsx_version", "dsx_profile_enable", "dsx_profile_select", "dsx_profile_read", "dsx_profile_reset",
            "dsx_noise_filter_cutoff", "dsx_filter_points", "dsx_split_sites", "dsx_noise_filter_spherical",
            "dsx_batch_create", "dsx_batch_run", "dsx_batch_destroy", "dsx_autotune", "dsx_tune_query",
            "dsx_server_create", "dsx_server_add_model", "dsx_server_submit", "dsx_server_wait",
@@ -109,6 +109,8 @@ def lib():
         L.dsx_version.restype = i32
         L.dsx_profile_enable.argtypes = [i32]
         L.dsx_profile_enable.restype = i32
+        L.dsx_profile_select.argtypes = [ctypes.c_char_p]
+        L.dsx_profile_select.restype = i32
         L.dsx_profile_read.argtypes = [P, i32]
         L.dsx_profile_read.restype = i32
         L.dsx_profile_reset.argtypes = []
@@ -300,6 +302,11 @@ def version() -> int:
 
 def profile_enable(on=True):
     _check(lib().dsx_profile_enable(1 if on else 0))
+
+
+def profile_select(kernel=None):
+    """Time only `kernel` (a name as profile_read reports it), or every kernel for None."""
+    _check(lib().dsx_profile_select(None if kernel is None else kernel.encode()))
 
 
 def profile_reset():

@@ -50,6 +50,7 @@ dsx_status fail(dsx_status s, const std::string& msg)
 struct Prof {
     std::mutex mu;
     bool on = false;
+    std::string only;   // when not empty, the one kernel kind that is timed
     struct Pending { std::string name; hipEvent_t a, b; };
     std::vector<Pending> pending;
     std::vector<hipEvent_t> pool;
@@ -71,6 +72,7 @@ hipError_t timed(const char* name, hipStream_t st, Fn fn)
     hipEvent_t a, b;
     {
         std::lock_guard<std::mutex> lk(g_prof.mu);
+        if (!g_prof.only.empty() && g_prof.only != name) return fn();
         a = g_prof.get();
         b = g_prof.get();
     }
@@ -801,6 +803,15 @@ dsx_status dsx_profile_enable(int32_t on)
 {
     std::lock_guard<std::mutex> lk(g_prof.mu);
     g_prof.on = on != 0;
+    return DSX_OK;
+}
+
+dsx_status dsx_profile_select(const char* kernel)
+{
+    if (kernel && std::strlen(kernel) >= sizeof(dsx_kernel_stat{}.name))
+        return fail(DSX_ERR_ARG, "kernel name longer than a dsx_kernel_stat name");
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.only = kernel ? kernel : "";
     return DSX_OK;
 }
 

@@ -157,3 +157,15 @@ def test_split_sites_limit():
     with pytest.raises(dsx.DsxError) as e:
         dsx.split_sites(m.n, m.frac, m.b, m.disp, m.occ, 0.0, max_sites=4)
     assert e.value.status == dsx.ERR_UNSUPPORTED
+
+
+def test_profile_select_arguments():
+    # host-only: selecting a kernel kind touches no device state
+    dsx.profile_select("recombine")
+    dsx.profile_select("")
+    dsx.profile_select(None)
+    with pytest.raises(dsx.DsxError) as e:
+        dsx.profile_select("k" * 32)
+    assert e.value.status == dsx.ERR_ARG
+    dsx.profile_reset()
+    assert dsx.profile_read() == {}

@@ -120,3 +120,40 @@ def test_batch_rejects_bad_arguments():
         dsx.Batch([h], [out], lanczos_m=1)
     assert e.value.status == dsx.ERR_ARG
     h.close()
+
+
+def test_profile_select_times_one_kernel_kind():
+    import torch
+    import paper_1809_07088_amd as dsx
+    m = synth.random_model(44, n=(6, 5, 7), S=2, M=2, order=3)
+    say("profile_select")
+    h = to_dsx(m)
+    out = torch.empty(tuple(m.count), device="cuda")
+    h.compute_intensity(out)
+    ref = out.clone()
+    try:
+        dsx.profile_reset()
+        dsx.profile_select("recombine")
+        dsx.profile_enable(True)
+        for _ in range(3):
+            h.compute_intensity(out)
+        torch.cuda.synchronize()
+        dsx.profile_enable(False)
+        only = dsx.profile_read()
+        dsx.profile_reset()
+        dsx.profile_select(None)
+        dsx.profile_enable(True)
+        h.compute_intensity(out)
+        torch.cuda.synchronize()
+        dsx.profile_enable(False)
+        every = dsx.profile_read()
+    finally:
+        dsx.profile_enable(False)
+        dsx.profile_select(None)
+        dsx.profile_reset()
+    assert set(only) == {"recombine"}
+    assert only["recombine"][0] == 3 and only["recombine"][1] > 0
+    # unchanged sites keep their spectra: a repeated call runs recombination and Bragg points
+    assert {"recombine", "bragg"} <= set(every)
+    assert torch.equal(out, ref)
+    h.close()
