@@ -1062,14 +1062,19 @@ hipError_t launch_recombine_magnetic(const RecombParams& p, int hc, int block, s
 }
 
 // ---------------------------------------------------------------------------- Bragg, float64
-// One 64-lane wave per unit-cell Bragg point H: lanes split the monomials of each
-// site, the partial sums are reduced across the wave in a fixed order, and lane 0
-// forms F_m(H), the ensemble moments and I(H), all in float64.
+// One 64-lane wave per unit-cell Bragg point H.  Lanes first form, one site each, the
+// site factor b_mu f_mu(H) e^{2 pi i H.r_mu}; then they stride over the (site,
+// monomial) pairs of a configuration, each adding S^{pqr}_{m,mu} times the monomial's
+// (2 pi i)^{p+q+r} H1^p H2^q H3^r / (p! q! r!) times the site factor, so the whole sum
+// over sites and monomials is one wave reduction (fixed order) per configuration.
+// Lane 0 keeps the ensemble moments and writes I(H); all of it in float64.
 template <int N>
 __global__ __launch_bounds__(64) void k_bragg_nuclear(BraggParams P)
 {
     constexpr int T = n_monomials(N);
     __shared__ double Ar[3][N + 1], Ai[3][N + 1];
+    __shared__ double Wr[kMaxSites], Wi[kMaxSites];
+    __shared__ int mono_s[T];
     const int total = P.nH[0] * P.nH[1] * P.nH[2];
     const int idx = blockIdx.x;
     if (idx >= total) return;
@@ -1086,59 +1091,54 @@ __global__ __launch_bounds__(64) void k_bragg_nuclear(BraggParams P)
         Ar[a][k] = ph == 0 ? mag : (ph == 2 ? -mag : 0.0);
         Ai[a][k] = ph == 1 ? mag : (ph == 3 ? -mag : 0.0);
     }
-    __syncthreads();
-    // this lane's monomials
-    int mp[(T + 63) / 64], mq[(T + 63) / 64], mr[(T + 63) / 64];
-#pragma unroll
-    for (int u = 0; u < (T + 63) / 64; ++u) {
-        const int t = lane + 64 * u;
-        mp[u] = mq[u] = mr[u] = -1;
-        if (t < T) { mp[u] = P.mono[3 * t]; mq[u] = P.mono[3 * t + 1]; mr[u] = P.mono[3 * t + 2]; }
+    for (int t = lane; t < T; t += 64)
+        mono_s[t] = P.mono[3 * t] | (P.mono[3 * t + 1] << 8) | (P.mono[3 * t + 2] << 16);
+    double s2 = 0.0;
+    if (P.has_ff) {
+        // |Q|-dependent scattering factor at Q = H (reciprocal-lattice units)
+        double q[3] = {0.0, 0.0, 0.0};
+        for (int a = 0; a < 3; ++a)
+            for (int c = 0; c < 3; ++c) q[c] += H[a] * P.recip[3 * a + c];
+        s2 = (q[0] * q[0] + q[1] * q[1] + q[2] * q[2]) / (16.0 * M_PI * M_PI);
     }
+    for (int mu = lane; mu < P.S; mu += 64) {
+        const double* sd = P.site + 12 * mu;
+        double x = H[0] * sd[0] + H[1] * sd[1] + H[2] * sd[2];
+        x -= floor(x);
+        double sn, cs;
+        sincos(6.283185307179586476925 * x, &sn, &cs);
+        double wgt = sd[3];
+        if (P.has_ff) {
+            const double* f = sd + 4;
+            double ffv = f[0] * exp(-f[1] * s2) + f[2] * exp(-f[3] * s2) + f[4] * exp(-f[5] * s2) + f[6];
+            if (f[7] != 0.0) ffv *= exp(-f[7] * s2);
+            wgt *= ffv;
+        }
+        Wr[mu] = wgt * cs;
+        Wi[mu] = wgt * sn;
+    }
+    __syncthreads();
+    const int items = P.S * T;
     double sq = 0.0, mre = 0.0, mim = 0.0;
     for (int m = 0; m < P.M; ++m) {
+        const double* Sm = P.sums + (size_t)m * items;    // [site][monomial] of configuration m
         double fr = 0.0, fi = 0.0;
-        for (int mu = 0; mu < P.S; ++mu) {
-            const double* Sm = P.sums + ((size_t)m * P.S + mu) * T;
-            double sr = 0.0, si = 0.0;
-#pragma unroll
-            for (int u = 0; u < (T + 63) / 64; ++u) {
-                if (mp[u] >= 0) {
-                    const int p = mp[u], q = mq[u], r = mr[u];
-                    const double xr = Ar[0][p] * Ar[1][q] - Ai[0][p] * Ai[1][q];
-                    const double xi = Ar[0][p] * Ai[1][q] + Ai[0][p] * Ar[1][q];
-                    const double cr = xr * Ar[2][r] - xi * Ai[2][r];
-                    const double ci = xr * Ai[2][r] + xi * Ar[2][r];
-                    const double sv = Sm[lane + 64 * u];
-                    sr += cr * sv;
-                    si += ci * sv;
-                }
-            }
-            for (int off = 32; off > 0; off >>= 1) {
-                sr += __shfl_down(sr, off, 64);
-                si += __shfl_down(si, off, 64);
-            }
-            if (lane == 0) {
-                const double* sd = P.site + 12 * mu;
-                double x = H[0] * sd[0] + H[1] * sd[1] + H[2] * sd[2];
-                x -= floor(x);
-                double sn, cs;
-                sincos(6.283185307179586476925 * x, &sn, &cs);
-                double wgt = sd[3];
-                if (P.has_ff) {
-                    // |Q|-dependent scattering factor at Q = H (reciprocal-lattice units)
-                    double q[3] = {0.0, 0.0, 0.0};
-                    for (int a = 0; a < 3; ++a)
-                        for (int c = 0; c < 3; ++c) q[c] += H[a] * P.recip[3 * a + c];
-                    const double s2 = (q[0] * q[0] + q[1] * q[1] + q[2] * q[2]) / (16.0 * M_PI * M_PI);
-                    const double* f = sd + 4;
-                    double ffv = f[0] * exp(-f[1] * s2) + f[2] * exp(-f[3] * s2) + f[4] * exp(-f[5] * s2) + f[6];
-                    if (f[7] != 0.0) ffv *= exp(-f[7] * s2);
-                    wgt *= ffv;
-                }
-                fr += wgt * (cs * sr - sn * si);
-                fi += wgt * (cs * si + sn * sr);
-            }
+#pragma unroll 4
+        for (int it = lane; it < items; it += 64) {
+            const int mu = it / T, t = it - mu * T;
+            const int e = mono_s[t];
+            const int p = e & 0xff, q = (e >> 8) & 0xff, r = e >> 16;
+            const double xr = Ar[0][p] * Ar[1][q] - Ai[0][p] * Ai[1][q];
+            const double xi = Ar[0][p] * Ai[1][q] + Ai[0][p] * Ar[1][q];
+            const double sv = Sm[it];
+            const double cr = (xr * Ar[2][r] - xi * Ai[2][r]) * sv;
+            const double ci = (xr * Ai[2][r] + xi * Ar[2][r]) * sv;
+            fr += cr * Wr[mu] - ci * Wi[mu];
+            fi += cr * Wi[mu] + ci * Wr[mu];
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            fr += __shfl_down(fr, off, 64);
+            fi += __shfl_down(fi, off, 64);
         }
         sq += fr * fr + fi * fi;
         mre += fr; mim += fi;
