@@ -165,6 +165,7 @@ __device__ float2* lds_fft(float2* a, float2* b, int nlines, int lstride, int es
 // values need 32 exchanges instead of 32 x 6), then across the four waves through
 // LDS.  The order of every addition is fixed: the sums are reproducible.
 constexpr int kSumsGroup = 32;
+constexpr int kSumsMaxPer = 8;    // cells per thread at most (the host's chunk is <= 8 x 256 cells)
 
 template <int N>
 struct MonoTable {
@@ -223,22 +224,33 @@ __global__ __launch_bounds__(256) void k_sums_nuclear(SumsParams P)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int c0 = chunk * P.chunk + threadIdx.x;
     const int c1 = min(P.ncell, (chunk + 1) * P.chunk);
+    // this thread's cells (c0, c0 + 256, ...), loaded once for every monomial group;
+    // the count is the same for the whole block
+    const int ncl = (c1 - chunk * P.chunk + 255) / 256;
+    float dv[kSumsMaxPer], uv[kSumsMaxPer][3];
+#pragma unroll
+    for (int i = 0; i < kSumsMaxPer; ++i) {
+        const int c = c0 + 256 * i;
+        const bool in = i < ncl && c < c1;
+        const size_t at = (size_t)ms * P.ncell + (in ? c : 0);
+        dv[i] = in ? (P.occ ? P.occ[at] : 1.f) : 0.f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) uv[i][a] = (in && N > 0 && P.vec) ? P.vec[3 * at + a] : 0.f;
+    }
 #pragma unroll
     for (int g0 = 0; g0 < T; g0 += kSumsGroup) {
         double acc[kSumsGroup];
 #pragma unroll
         for (int t = 0; t < kSumsGroup; ++t) acc[t] = 0.0;
-        // the cells are re-read (from cache) for every group: one group's
-        // accumulators at a time stay in registers
-#pragma unroll 1
-        for (int c = c0; c < c1; c += 256) {
-            const size_t at = (size_t)ms * P.ncell + c;
-            const double d = P.occ ? (double)P.occ[at] : 1.0;
+#pragma unroll
+        for (int i = 0; i < kSumsMaxPer; ++i) {
+            if (i >= ncl) break;
+            const double d = (double)dv[i];
             double pw[3][N + 1];
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 pw[a][0] = 1.0;
-                const double u = (N > 0 && P.vec) ? (double)P.vec[3 * at + a] : 0.0;
+                const double u = (double)uv[i][a];
 #pragma unroll
                 for (int k = 1; k <= N; ++k) pw[a][k] = pw[a][k - 1] * u;
             }
