@@ -396,6 +396,9 @@ def main():
                     help="time the filtered steps only (no unfiltered pass, sweep, ensemble, serving or "
                          "CPU baseline): the run the profiles are taken from")
     ap.add_argument("--no-tune", action="store_true", help="run with the default plan instead of tuning it")
+    ap.add_argument("--plan", metavar="FORM,FFT,FILTER",
+                    help="run this plan instead of tuning (recombination form, FFT fields per plane block, "
+                         "filter planes per block, as the line's plan object reports them)")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble comparison")
     ap.add_argument("--ensemble-only", action="store_true",
                     help="time only the batched ensemble (for kernel traces of the graph path)")
@@ -445,7 +448,9 @@ def main():
 
     # plan tuning happens once per model, before any timed step
     h.set_sites_async(0, None, disp_dev)
-    if not args.no_tune:
+    if args.plan:
+        h.tune_set(*[int(v) for v in args.plan.split(",")])
+    elif not args.no_tune:
         h.autotune(lm)
     plan = h.tune_query()
 

@@ -286,6 +286,15 @@ dsx_status dsx_autotune(dsx_model m, int32_t lanczos_m, void* hip_stream);
 dsx_status dsx_tune_query(dsx_model m, int32_t choice[3], int32_t* tuned);
 
 /*
+ * Set the plan choices (same meaning as dsx_tune_query; the filter planes per block
+ * in 1..64, forms 2-4 on nuclear models only) without timing anything, e.g. to
+ * re-run a plan that dsx_autotune chose in another process.  The model then counts
+ * as tuned.  Affects later calls, not batches already recorded.  DSX_ERR_ARG for a
+ * value outside those sets; host memory, read only.
+ */
+dsx_status dsx_tune_set(dsx_model m, const int32_t choice[3]);
+
+/*
  * Serving (an execution pattern; the arithmetic is that of dsx_compute_intensity /
  * dsx_noise_filter).  Refinement recomputes the intensity of a model again and
  * again as its variables change (Sec. I; Sec. VI), so a server keeps models

@@ -53,7 +53,7 @@ EXPORTS = ("dsx_plan_query", "dsx_create_model", "dsx_set_sites", "dsx_set_sites
            "dsx_version", "dsx_profile_enable", "dsx_profile_select", "dsx_profile_read", "dsx_profile_reset",
            "dsx_noise_filter_cutoff", "dsx_filter_points", "dsx_split_sites", "dsx_noise_filter_spherical",
            "dsx_batch_create", "dsx_batch_run", "dsx_batch_destroy", "dsx_autotune", "dsx_tune_query",
-           "dsx_server_create", "dsx_server_add_model", "dsx_server_submit", "dsx_server_wait",
+           "dsx_tune_set", "dsx_server_create", "dsx_server_add_model", "dsx_server_submit", "dsx_server_wait",
            "dsx_server_stats_read", "dsx_server_destroy")
 
 class ServerConfig(ctypes.Structure):
@@ -120,6 +120,7 @@ def lib():
         L.dsx_batch_destroy.argtypes = [P]
         L.dsx_autotune.argtypes = [P, i32, P]
         L.dsx_tune_query.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.dsx_tune_set.argtypes = [P, ctypes.POINTER(i32)]
         L.dsx_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(P)]
         L.dsx_server_add_model.argtypes = [P, ctypes.POINTER(ModelDesc), ctypes.POINTER(P)]
         L.dsx_server_submit.argtypes = [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_int64)]
@@ -127,7 +128,7 @@ def lib():
         L.dsx_server_stats_read.argtypes = [P, i32, ctypes.POINTER(ServerStats)]
         L.dsx_server_destroy.argtypes = [P]
         for f in ("dsx_batch_create", "dsx_batch_run", "dsx_batch_destroy", "dsx_autotune", "dsx_tune_query",
-                  "dsx_server_create", "dsx_server_add_model", "dsx_server_submit", "dsx_server_wait",
+                  "dsx_tune_set", "dsx_server_create", "dsx_server_add_model", "dsx_server_submit", "dsx_server_wait",
                   "dsx_server_stats_read", "dsx_server_destroy"):
             getattr(L, f).restype = i32
         for f in ("dsx_plan_query", "dsx_create_model", "dsx_set_sites", "dsx_set_grid",
@@ -335,6 +336,13 @@ def tune_query(model):
             "filter_planes_per_block": int(c[2]), "tuned": bool(t.value)}
 
 
+
+def tune_set(model, recombine_form, fft_fields_per_block, filter_planes_per_block):
+    """Set the plan choices without timing (dsx_tune_set); the model counts as tuned."""
+    c = (ctypes.c_int32 * 3)(int(recombine_form), int(fft_fields_per_block), int(filter_planes_per_block))
+    _check(lib().dsx_tune_set(model, c))
+
+
 class Batch:
     """A recorded launch sequence over several models (dsx_batch_*): run() replays it."""
 
@@ -402,6 +410,9 @@ class Model:
 
     def tune_query(self):
         return tune_query(self.handle)
+
+    def tune_set(self, recombine_form, fft_fields_per_block, filter_planes_per_block):
+        tune_set(self.handle, recombine_form, fft_fields_per_block, filter_planes_per_block)
 
     def close(self):
         if self.handle:

@@ -1626,6 +1626,22 @@ dsx_status dsx_autotune(dsx_model m, int32_t lanczos_m, void* hip_stream)
     return DSX_OK;
 }
 
+dsx_status dsx_tune_set(dsx_model m, const int32_t choice[3])
+{
+    dsx_status s = check_direct(m);
+    if (s != DSX_OK) return s;
+    if (!choice) return fail(DSX_ERR_ARG, "null choice");
+    const int v = choice[0], fc = choice[1], t1 = choice[2];
+    if (!(v == 0 || v == 2 || v == 3 || v == 4) || (v != 0 && m->kind != DSX_NUCLEAR))
+        return fail(DSX_ERR_ARG, "recombination form must be 0, or 2, 3, 4 on a nuclear model");
+    if (!(fc == 0 || fc == 1 || fc == 2 || fc == 4))
+        return fail(DSX_ERR_ARG, "FFT fields per plane block must be 0, 1, 2 or 4");
+    if (t1 < 1 || t1 > 64) return fail(DSX_ERR_ARG, "filter planes per block must be in 1..64");
+    m->tune_recomb_variant = v; m->tune_fchunk = fc; m->tune_lanczos_t1 = t1;
+    m->tuned = true;
+    return DSX_OK;
+}
+
 dsx_status dsx_tune_query(dsx_model m, int32_t choice[3], int32_t* tuned)
 {
     if (!m) return fail(DSX_ERR_ARG, "null model");

@@ -157,3 +157,26 @@ def test_profile_select_times_one_kernel_kind():
     assert {"recombine", "bragg"} <= set(every)
     assert torch.equal(out, ref)
     h.close()
+
+
+def test_tune_set_plan_and_errors():
+    import torch
+    import paper_1809_07088_amd as dsx
+    m = synth.random_model(45, n=(6, 5, 7), S=2, M=2, order=3)
+    say("tune_set")
+    h = to_dsx(m)
+    out = torch.empty(tuple(m.count), device="cuda")
+    ref = O.intensity(m).reshape(m.count)
+    for plan in [(0, 0, 12), (0, 2, 8), (2, 1, 4), (3, 4, 64), (4, 2, 1)]:
+        h.tune_set(*plan)
+        q = h.tune_query()
+        assert (q["recombine_form"], q["fft_fields_per_block"], q["filter_planes_per_block"]) == plan
+        assert q["tuned"]
+        h.compute_intensity(out)
+        torch.cuda.synchronize()
+        assert rel_l2(out.cpu().numpy(), ref) <= TOL
+    for bad in [(1, 0, 12), (5, 0, 12), (0, 3, 12), (0, 0, 0), (0, 0, 65)]:
+        with pytest.raises(dsx.DsxError) as e:
+            h.tune_set(*bad)
+        assert e.value.status == dsx.ERR_ARG
+    h.close()
