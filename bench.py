@@ -93,7 +93,7 @@ def summarize_pmc(fetch_dir, write_dir, out_md, command):
         f.write("Two rocprofv3 PMC runs of the benchmark (`FETCH_SIZE`, then `WRITE_SIZE`, KiB per "
                 "dispatch), each scaled by copy-probe bytes / counter reading of the plain device "
                 "copy of %d MiB issued by the benchmark (fetch scale %.4f, write scale %.4f).  Only "
-                "the dispatches after the probe count (the plan tuning runs before it).  Kernel: "
+                "the dispatches after the probe count (the plan tuning and the warm-up run before it).  Kernel: "
                 "`%s`, %d launches.\n\n" % (COPY_PROBE_BYTES >> 20, sf, sw, nf, len(kf)))
         f.write("Command:\n\n```\n%s\n```\n\n" % command)
         f.write("| counter | raw per launch (bytes) | scaled (bytes) |\n|---|---|---|\n")
@@ -120,9 +120,9 @@ def summarize_ktrace(trace_dir, out_md, command):
     with open(out_md, "w") as f:
         f.write("# Kernel time, displacive 32^3 fcc, Taylor order 8, 513^3 box, Lanczos m = 2\n\n")
         f.write("rocprofv3 kernel trace of the benchmark's filtered steps (`--only-steps`: "
-                "set_sites_async + noise_filter per step, warmup and timed steps), i.e. the "
-                "dispatches after the plain device copy used as the PMC probe; the plan tuning "
-                "before it is left out.  MI355X, one GPU.\n\nCommand (run from /tmp with "
+                "set_sites_async + noise_filter per step: the timed steps and the untimed steps of the "
+                "per-kernel breakdown), i.e. the dispatches after the plain device copy used as the "
+                "PMC probe; the plan tuning and the warm-up before it are left out.  MI355X, one GPU.\n\nCommand (run from /tmp with "
                 "TMPDIR=/tmp, R = repository root):\n\n```\n%s\n```\n\n" % command)
         f.write("| kernel | calls | average (us) | min (us) | max (us) | share of GPU time |\n"
                 "|---|---|---|---|---|---|\n")
@@ -454,16 +454,18 @@ def main():
         h.autotune(lm)
     plan = h.tune_query()
 
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # the probe also marks where profiled dispatches start counting: after the tuning
+    # and the warm-up (the recombination needs some 20 steps to reach its steady time)
     if args.copy_probe:
         src = torch.empty(COPY_PROBE_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
     # HIP events bracket only the dominant kernel inside the timed region (events
     # around every launch add about 30 us to a step)
     dsx.profile_reset()
