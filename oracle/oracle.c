@@ -17,9 +17,12 @@
  *                    disp_expansion, with G.u = 2 pi sum_alpha g_alpha u^alpha,
  *                    Eq. gdotu_1).
  *   orc_sf_magnetic  vector F_m(G) = sum_{R,mu} b_mu delta M e^{2 pi i g.(R + r_mu)}
- *                    (Sec. III.D, Eq. mag_sf and Eq. mag_ft with T = 1); the form
- *                    factor, the perpendicular projection and the constant are
- *                    applied by the Python side.
+ *                    per site (Sec. III.D, Eqs. mag_sf, mag_ft); the form factor, the
+ *                    Debye-Waller factor, the perpendicular projection and the
+ *                    constant are applied by the Python side.
+ *   orc_dw_mean      the Debye-Waller factor T_mu(G) of Sec. III.A, Eq. dw: the mean of
+ *                    e^{i G.u} over the occupied atoms of a site, every cell and every
+ *                    configuration (exact or order-N Taylor polynomial).
  *   orc_pair_sum     (1/N) sum_{j,k} b_j b_k e^{i Q.(r_j - r_k)} with the
  *                    nearest-image convention (Sec. II, Eq. intensity_dble_sum).
  *   orc_lanczos      the windowed-sinc resampling of Sec. V.B (Eqs.
@@ -157,6 +160,58 @@ int orc_sf_magnetic(const int32_t* n, int32_t S, const double* frac, const doubl
                 double* o = F + 2 * 3 * (((int64_t)m * nG + gi) * S + mu);
                 for (int k = 0; k < 3; ++k) { o[2 * k] = acc[k][0]; o[2 * k + 1] = acc[k][1]; }
             }
+        }
+    }
+    return 0;
+}
+
+/* Debye-Waller factor of one site (Sec. III.A, Eq. dw):
+ *   T_mu(G) = (1/(n1 n2 n3)) sum_R < (1 + a_{R,mu}) e^{i G.u_{R,mu}} >
+ * with 1 + a = delta / c_mu, c_mu the mean occupancy of the site over every cell
+ * and configuration, and < > the mean over configurations; written out that is
+ *   T_mu(G) = sum_{m,R} delta e^{2 pi i g.u} / sum_{m,R} delta,
+ * a plain average over the occupied atoms of the site.  exact mode (order < 0)
+ * evaluates the exponential; order-N mode its Taylor polynomial
+ * sum_{k<=N} (i x)^k / k!, x = 2 pi g.u (Sec. III.C, Eq. disp_expansion).
+ * A site with no occupied atom gets T = 0.
+ * occ [M][S][n1][n2][n3] or NULL (= 1); disp [M][S][n1][n2][n3][3] fractional;
+ * T [nG][S][2] output (re, im). */
+int orc_dw_mean(const int32_t* n, int32_t S, int32_t M, const float* occ, const float* disp,
+                int32_t order, int64_t nG, const int32_t* G, double* T)
+{
+    if (bad_dims(n) || S < 1 || M < 1 || nG < 0 || !disp || !G || !T) return -1;
+    const long ncell = (long)n[0] * n[1] * n[2];
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t gi = 0; gi < nG; ++gi) {
+        const double g[3] = {(double)G[3 * gi] / n[0], (double)G[3 * gi + 1] / n[1], (double)G[3 * gi + 2] / n[2]};
+        for (int32_t mu = 0; mu < S; ++mu) {
+            double tr = 0.0, ti = 0.0, wsum = 0.0;
+            for (int32_t m = 0; m < M; ++m)
+                for (long cell = 0; cell < ncell; ++cell) {
+                    const long at = ((long)m * S + mu) * ncell + cell;
+                    const double delta = occ ? (double)occ[at] : 1.0;
+                    if (delta == 0.0) continue;
+                    const float* u = disp + 3 * at;
+                    const double x = TWO_PI * (g[0] * u[0] + g[1] * u[1] + g[2] * u[2]);
+                    double er, ei;
+                    if (order < 0) {
+                        er = cos(x); ei = sin(x);
+                    } else {
+                        double pr = 1.0, pi = 0.0;      /* (i x)^k / k! */
+                        er = 0.0; ei = 0.0;
+                        for (int k = 0; k <= order; ++k) {
+                            er += pr; ei += pi;
+                            const double nr = -pi * x / (k + 1), ni = pr * x / (k + 1);
+                            pr = nr; pi = ni;
+                        }
+                    }
+                    tr += delta * er;
+                    ti += delta * ei;
+                    wsum += delta;
+                }
+            double* o = T + 2 * (gi * S + mu);
+            o[0] = wsum != 0.0 ? tr / wsum : 0.0;
+            o[1] = wsum != 0.0 ? ti / wsum : 0.0;
         }
     }
     return 0;

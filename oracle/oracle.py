@@ -30,9 +30,13 @@ notes of the repository):
   bragg_sf_disp); odd Taylor orders are kept in that mean.
 * N in I = <|F|^2>/N is n1 n2 n3 times the number of distinct average atomic
   positions (Sec. II), unless overridden.
-* Magnetic: T = 1, spins Cartesian, s = |Q|/(4 pi), the constant
-  C = 0.07265 barn of Eq. mag_intensity included, the Bragg subtraction applied to
-  F_perp, and I(G = 0) := 0 because the direction of G is undefined there.
+* Magnetic: spins Cartesian, s = |Q|/(4 pi), the constant C = 0.07265 barn of
+  Eq. mag_intensity included, the Bragg subtraction applied to F_perp, and
+  I(G = 0) := 0 because the direction of G is undefined there.  Moments sit at the
+  average positions R + r_mu; displacements enter only through the Debye-Waller
+  factor T_mu(G) of Eq. dw (the mean of e^{i G.u} over the site's occupied atoms,
+  every cell and configuration; 1 + a = delta / c), as Eq. mag_sf states; T = 1
+  when the model has no displacements.
 """
 from __future__ import annotations
 
@@ -74,6 +78,7 @@ def lib():
         i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
         L.orc_sf_nuclear.argtypes = [P, i32, P, P, i32, P, P, i32, i64, P, P]
         L.orc_sf_magnetic.argtypes = [P, i32, P, P, i32, P, P, i64, P, P]
+        L.orc_dw_mean.argtypes = [P, i32, i32, P, P, i32, i64, P, P]
         L.orc_pair_sum.argtypes = [P, i32, P, P, P, P, f64, i64, P, P]
         L.orc_lanczos.argtypes = [i32, i32, P, P, P, P, P, P]
         L.orc_lanczos_cutoff.argtypes = [i32, i32, i32, P, P, P, P, P, P]
@@ -81,7 +86,7 @@ def lib():
         L.orc_lanczos_spherical.argtypes = [i32, i32, P, P, P, P, P, P, P, f64, P]
         L.orc_ball_ft.argtypes = [f64]
         L.orc_ball_ft.restype = f64
-        for f in (L.orc_sf_nuclear, L.orc_sf_magnetic, L.orc_pair_sum, L.orc_lanczos,
+        for f in (L.orc_sf_nuclear, L.orc_sf_magnetic, L.orc_dw_mean, L.orc_pair_sum, L.orc_lanczos,
                   L.orc_lanczos_cutoff, L.orc_lanczos_points, L.orc_lanczos_spherical):
             f.restype = ctypes.c_int
         _lib = L
@@ -216,17 +221,37 @@ def bragg_diffuse(F, G, n, normN) -> np.ndarray:
     return (mean_sq - np.where(is_unit_cell_bragg(G, n), sq_mean, 0.0)) / normN
 
 
-def magnetic_perp(model, G, F_sites) -> np.ndarray:
-    """F_perp = F - Ghat (Ghat . F) of F = sum_mu f_mu(|Q|) T_mu(G) F_mu (Eq. mag_sf; T = 1
-    unless the model gives Debye-Waller B values); zero at G = 0. [M][nG][3]."""
+def debye_waller(model, G, order=None) -> np.ndarray:
+    """Debye-Waller factor T_mu(G) of every site (Sec. III.A, Eq. dw), complex128 [nG][S]:
+    the mean of e^{i G.u} over the occupied atoms of the site in every cell and
+    configuration ((1 + a) = delta / c with c the mean occupancy).  order=None: the
+    model's Taylor order; order=-1: the exact exponential.  1 for a model without
+    displacements."""
+    G = np.ascontiguousarray(G, dtype=np.int32).reshape(-1, 3)
+    if model.disp is None:
+        return np.ones((G.shape[0], model.n_sites), dtype=np.complex128)
+    if order is None:
+        order = model.order
+    n = np.ascontiguousarray(model.n, dtype=np.int32)
+    occ = None if model.occ is None else np.ascontiguousarray(model.occ, dtype=np.float32)
+    disp = np.ascontiguousarray(model.disp, dtype=np.float32)
+    out = np.zeros((G.shape[0], model.n_sites, 2), dtype=np.float64)
+    rc = lib().orc_dw_mean(_ptr(n), model.n_sites, model.n_configs, _ptr(occ), _ptr(disp), int(order),
+                           G.shape[0], _ptr(G), _ptr(out))
+    if rc != 0:
+        raise ValueError("orc_dw_mean rejected its arguments")
+    return out[..., 0] + 1j * out[..., 1]
+
+
+def magnetic_perp(model, G, F_sites, order=None) -> np.ndarray:
+    """F_perp = F - Ghat (Ghat . F) of F = sum_mu f_mu(|Q|) T_mu(G) F_mu (Eq. mag_sf, with
+    T_mu(G) of Eq. dw from the model's displacements; T = 1 without them); zero at
+    G = 0.  [M][nG][3]."""
     Q = q_cartesian(model, G)
     qn = np.linalg.norm(Q, axis=-1)
     s = qn / (4.0 * np.pi)
     f = np.stack([magnetic_form_factor(model.ff[mu], s) for mu in range(model.n_sites)], axis=-1)
-    dw = getattr(model, "dw_b", None)
-    if dw is not None:
-        # Debye-Waller factor T_mu(G) = exp(-B_mu s^2) of Eq. mag_sf
-        f = f * np.exp(-np.outer(s * s, np.asarray(dw, dtype=np.float64)))
+    f = f * debye_waller(model, G, order)
     F = np.einsum("gs,mgsc->mgc", f, F_sites)
     with np.errstate(invalid="ignore", divide="ignore"):
         ghat = np.where(qn[:, None] > 0, Q / qn[:, None], 0.0)
@@ -246,7 +271,7 @@ def intensity(model, G=None, order=None) -> np.ndarray:
     N = norm_N(model)
     if model.kind == NUCLEAR:
         return bragg_diffuse(structure_factor(model, G, order), G, model.n, N)
-    Fp = magnetic_perp(model, G, structure_factor_magnetic_sites(model, G))
+    Fp = magnetic_perp(model, G, structure_factor_magnetic_sites(model, G), order)
     return MAG_CONSTANT_BARN * bragg_diffuse(Fp, G, model.n, N)
 
 

@@ -54,7 +54,6 @@ class Model:
     ff: Optional[np.ndarray] = None   # (S, 7) magnetic form factor parameters
     pos_id: Optional[np.ndarray] = None  # (S,) position index for the normalisation
     norm_N: float = 0.0           # 0 => n1 n2 n3 x number of distinct positions
-    dw_b: Optional[np.ndarray] = None   # (S,) magnetic Debye-Waller B [Angstrom^2] or None (T = 1)
     occ: Optional[np.ndarray] = None
     disp: Optional[np.ndarray] = None
     spin: Optional[np.ndarray] = None
@@ -259,9 +258,11 @@ def poisson_arrivals(workload=5, rate=200.0, duration=30.0):
 
 
 def random_model(seed, n=(3, 4, 5), S=2, M=2, order=3, kind=NUCLEAR, with_occ=True,
-                 with_disp=True, sigma=0.05, cell=None):
+                 with_disp=True, sigma=0.05, cell=None, mag_order=0):
     """Small general test model: non-centrosymmetric random site positions, random b,
-    optional occupancies and uncorrelated displacements, non-cubic cells allowed."""
+    optional occupancies and uncorrelated displacements, non-cubic cells allowed.
+    Magnetic models carry displacements (for the Debye-Waller factor) only when
+    mag_order > 0, which is then their Taylor order."""
     r = np.random.default_rng([99, seed])
     nn = tuple(int(v) for v in n)
     frac = r.random((S, 3))
@@ -274,11 +275,12 @@ def random_model(seed, n=(3, 4, 5), S=2, M=2, order=3, kind=NUCLEAR, with_occ=Tr
     if kind == MAGNETIC:
         v = r.normal(size=(M, S) + nn + (3,))
         spin = (v / np.linalg.norm(v, axis=-1, keepdims=True)).astype(np.float32)
-        disp = None
-        order = 0
+        order = int(mag_order)
+        if order == 0:
+            disp = None
         ff = np.tile(MAG_FF, (S, 1))
     g0 = tuple(-2 * v - 1 for v in nn)
     count = tuple(4 * v + 3 for v in nn)
     return Model(cell=cell, n=nn, frac=frac, b=b, kind=kind,
-                 order=order if with_disp else 0, ff=ff, occ=occ, disp=disp, spin=spin,
+                 order=order if disp is not None else 0, ff=ff, occ=occ, disp=disp, spin=spin,
                  g0=g0, count=count, name=f"random seed={seed}")

@@ -6,9 +6,9 @@ import paper_1809_07088_amd as dsx
 
 def desc_kwargs(model):
     return dict(cell=model.cell, n=model.n, frac=model.frac, b=model.b, kind=model.kind,
-                taylor_order=model.order if model.kind == dsx.NUCLEAR else 0,
+                taylor_order=model.order,
                 n_configs=model.n_configs, has_occ=model.occ is not None, ff=model.ff,
-                pos_id=model.pos_id, norm_N=model.norm_N, dw_b=getattr(model, "dw_b", None))
+                pos_id=model.pos_id, norm_N=model.norm_N)
 
 
 def to_dsx(model, device=True):

@@ -407,22 +407,6 @@ def test_noise_filter_spherical_symmetric_box():
     assert rel_l2(out.cpu().numpy(), ref) <= TOL
 
 
-# ------------------------------------------------------------------ magnetic Debye-Waller
-
-@pytest.mark.parametrize("same_b", [False, True])
-def test_magnetic_debye_waller_factor(same_b):
-    """T_mu(G) = exp(-B_mu s^2) of Eq. mag_sf per site (sites with one r3 but different B
-    fall in different classes), through the recombination and the FP64 Bragg points."""
-    m = synth.random_model(1500 + same_b, n=(4, 5, 6), S=3, M=2, kind=synth.MAGNETIC,
-                           cell=[5.0, 6.0, 7.0, 90.0, 90.0, 90.0])
-    m.frac[:, 2] = [0.25, 0.25, 0.6]                    # two sites share r3
-    m.dw_b = np.array([0.9, 0.9, 0.9]) if same_b else np.array([0.4, 1.3, 0.7])
-    say(f"magnetic Debye-Waller same_b={same_b}")
-    I = gpu_intensity(m)
-    ref = O.intensity(m, O.grid_points(m.g0, m.count)).reshape(m.count)
-    assert rel_l2(I, ref) <= TOL
-
-
 # ------------------------------------------------------------------ X-ray scattering factors
 
 @pytest.mark.parametrize("order,M,share_r3", [(3, 2, False), (0, 2, True), (5, 1, True)])

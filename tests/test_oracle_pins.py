@@ -5,6 +5,7 @@ closed forms, exact invariances, the Taylor remainder bound, an independent
 brute-force formula (pair double sum), or an independent algorithm (the paper's
 FFT route against the direct sum).  All run on the CPU.
 """
+import itertools
 import math
 import os
 
@@ -378,20 +379,78 @@ def test_spherical_cutoff_is_isotropic_and_keeps_constants(m, s):
 
 # ------------------------------------------------- magnetic Debye-Waller factor T_mu(G)
 
-def test_debye_waller_scales_a_single_site_by_exp_minus_2Bs2():
-    """One magnetic site: T = exp(-B s^2) multiplies F, so I scales by exp(-2 B s^2),
-    with s = |Q|/(4 pi) taken here from the real-space metric (|Q|^2 = 4 pi^2 g.Gi.g)."""
-    m = synth.random_model(60, n=(3, 4, 3), S=1, M=2, kind=synth.MAGNETIC,
-                           cell=[4.2, 5.1, 6.3, 86.0, 95.0, 104.0])
-    G = O.grid_points(m.g0, m.count)[::5]
-    I0 = O.intensity(m, G)
-    m.dw_b = np.array([0.8])
-    I1 = O.intensity(m, G)
-    A = O.cell_vectors(m.cell)
-    Gi = np.linalg.inv(A @ A.T)                          # inverse real-space metric
+def _mag_with_disp(seed, order=4, M=2, S=3, sigma=0.03, cell=(4.2, 5.1, 6.3, 86.0, 95.0, 104.0), occ=True):
+    return synth.random_model(seed, n=(3, 4, 3), S=S, M=M, kind=synth.MAGNETIC, cell=list(cell),
+                              mag_order=order, sigma=sigma, with_occ=occ)
+
+
+def test_debye_waller_of_a_rigid_displacement_is_a_site_shift():
+    """Eq. dw with the same displacement u0 on every atom of a site: T = e^{i G.u0}, so the
+    magnetic intensity is that of the model whose site sits at r_mu + u0 (Eq. mag_sf)."""
+    m = _mag_with_disp(62, order=0)
+    m.order = -1
+    u0 = np.array([[0.071, -0.043, 0.118], [0.0, 0.0, 0.0], [-0.09, 0.033, 0.02]])
+    m.disp = np.broadcast_to(u0[None, :, None, None, None, :],
+                             (m.n_configs, m.n_sites) + tuple(m.n) + (3,)).astype(np.float32).copy()
+    G = O.grid_points(m.g0, m.count)[::3]
+    shifted = _mag_with_disp(62, order=0)
+    shifted.frac = m.frac + m.disp[0, :, 0, 0, 0].astype(np.float64)
+    assert np.allclose(O.intensity(m, G, order=-1), O.intensity(shifted, G), rtol=1e-10, atol=1e-14)
+    T = O.debye_waller(m, G, order=-1)
     g = G / np.asarray(m.n, float)
-    s2 = np.einsum("gi,ij,gj->g", g, Gi, g) * 4 * np.pi ** 2 / (16 * np.pi ** 2)
-    assert np.allclose(I1, I0 * np.exp(-2 * 0.8 * s2), rtol=1e-12, atol=1e-15)
+    assert np.allclose(T, np.exp(2j * np.pi * g @ m.disp[0, :, 0, 0, 0].astype(np.float64).T), atol=1e-12)
+
+
+def test_debye_waller_averages_over_occupied_atoms_only():
+    """1 + a = delta / c: displacements on vacant cells carry no weight, and a site's T is
+    the plain mean over its occupied atoms of every configuration."""
+    m = _mag_with_disp(63)
+    G = O.grid_points(m.g0, m.count)[::5]
+    I0 = O.intensity(m, G, order=-1)
+    m2 = _mag_with_disp(63)
+    rng = np.random.default_rng(5)
+    vac = m2.occ == 0
+    m2.disp[vac] = rng.normal(0, 0.2, (int(vac.sum()), 3)).astype(np.float32)
+    assert np.allclose(O.intensity(m2, G, order=-1), I0, rtol=1e-12, atol=1e-15)
+    # a site mean by brute force over (configuration, cell)
+    g = G[7] / np.asarray(m.n, float)
+    for mu in range(m.n_sites):
+        sel = m.occ[:, mu] > 0
+        u = m.disp[:, mu][sel].astype(np.float64)
+        expect = np.mean(np.exp(2j * np.pi * (u @ g)))
+        assert abs(O.debye_waller(m, G[7:8], order=-1)[0, mu] - expect) < 1e-13
+
+
+def test_debye_waller_of_symmetric_displacements_is_real_and_at_most_one():
+    """Displacements that come in +-u pairs: <e^{iG.u}> = <cos G.u>, real and <= 1."""
+    m = _mag_with_disp(64, occ=False)
+    m.disp[1] = -m.disp[0]
+    G = O.grid_points(m.g0, m.count)[::2]
+    T = O.debye_waller(m, G, order=-1)
+    assert np.max(np.abs(T.imag)) < 1e-14
+    assert np.all(T.real <= 1 + 1e-15)
+    assert np.allclose(T[np.all(G == 0, axis=1)], 1.0)
+
+
+@pytest.mark.parametrize("N", [1, 3, 6])
+def test_debye_waller_taylor_remainder(N):
+    """Order-N T stays within the mean Taylor remainder |x|^{N+1}/(N+1)! of the exact one."""
+    m = _mag_with_disp(65, order=N, sigma=0.05)
+    G = O.grid_points(m.g0, m.count)[::4]
+    Tn = O.debye_waller(m, G)
+    Tx = O.debye_waller(m, G, order=-1)
+    g = G / np.asarray(m.n, float)
+    for mu in range(m.n_sites):
+        sel = m.occ[:, mu] > 0
+        x = 2 * np.pi * (m.disp[:, mu][sel].astype(np.float64) @ g.T)
+        bound = np.mean(np.abs(x) ** (N + 1), axis=0) / math.factorial(N + 1)
+        assert np.all(np.abs(Tn[:, mu] - Tx[:, mu]) <= bound * (1 + 1e-9) + 1e-14)
+
+
+def test_magnetic_with_displacements_keeps_friedel_symmetry():
+    m = _mag_with_disp(66, order=5)
+    G = O.grid_points(m.g0, m.count)[::7]
+    assert np.allclose(O.intensity(m, G), O.intensity(m, -G), rtol=1e-10, atol=1e-14)
 
 
 def test_nuclear_form_factor_scales_a_single_site_by_f_squared():
@@ -409,3 +468,146 @@ def test_nuclear_form_factor_scales_a_single_site_by_f_squared():
     s2 = np.einsum("gi,ij,gj->g", g, Gi, g) / 4
     f = ff[0] * np.exp(-ff[1] * s2) + ff[2] * np.exp(-ff[3] * s2) + ff[4] * np.exp(-ff[5] * s2) + ff[6]
     assert np.allclose(I1, I0 * f * f, rtol=1e-11, atol=1e-14)
+
+
+# ------------------------------------------------- the ensemble mean and the Bragg rule
+
+def test_identical_configurations_give_the_single_configuration_intensity():
+    """M copies of one configuration: (1/M) sum |F|^2 = |F|^2 and |<F>|^2 = |F|^2, so the
+    intensity equals the M = 1 intensity at every G, the unit-cell Bragg points included
+    (where it is 0).  A 1/M^2 in place of 1/M, or the subtraction applied off H, fails."""
+    base = synth.random_model(70, n=(3, 4, 3), S=2, M=1, order=3)
+    G = np.concatenate([O.grid_points(base.g0, base.count)[::5], np.array([[0, 0, 0], [3, -4, 6]])])
+    I1 = O.intensity(base, G)
+    for M in (2, 5):
+        rep = synth.random_model(70, n=(3, 4, 3), S=2, M=1, order=3)
+        rep.occ = np.repeat(base.occ, M, axis=0)
+        rep.disp = np.repeat(base.disp, M, axis=0)
+        IM = O.intensity(rep, G)
+        assert np.allclose(IM, I1, rtol=1e-12, atol=1e-13)
+    assert np.all(np.abs(I1[O.is_unit_cell_bragg(G, base.n)]) < 1e-10)
+    mag = synth.random_model(71, n=(3, 3, 4), S=2, M=1, kind=synth.MAGNETIC, mag_order=2)
+    magM = synth.random_model(71, n=(3, 3, 4), S=2, M=1, kind=synth.MAGNETIC, mag_order=2)
+    magM.spin, magM.occ, magM.disp = (np.repeat(a, 3, axis=0) for a in (mag.spin, mag.occ, mag.disp))
+    Gm = O.grid_points(mag.g0, mag.count)[::9]
+    assert np.allclose(O.intensity(magM, Gm), O.intensity(mag, Gm), rtol=1e-12, atol=1e-15)
+
+
+def test_bragg_points_carry_the_population_variance():
+    """At H (G = 0 mod n) the diffuse intensity is (1/N) times the population variance
+    (1/M) sum_m |F_m - mean F|^2, computed two-pass; elsewhere it is (1/N) mean |F_m|^2."""
+    m = synth.random_model(72, n=(3, 2, 4), S=3, M=6, order=2)
+    H = np.array([[0, 0, 0], [3, 2, 4], [-6, 2, 8], [3, -4, -4]])
+    off = np.array([[1, 0, 0], [2, 1, 3], [-4, 1, 5]])
+    G = np.concatenate([H, off])
+    F = O.structure_factor(m, G)
+    N = O.norm_N(m)
+    I = O.intensity(m, G)
+    mean = F.mean(axis=0)
+    var = np.mean(np.abs(F - mean[None]) ** 2, axis=0)
+    assert np.allclose(I[:len(H)], var[:len(H)] / N, rtol=1e-10, atol=1e-12)
+    assert np.allclose(I[len(H):], np.mean(np.abs(F[:, len(H):]) ** 2, axis=0) / N, rtol=1e-12)
+    # and the variance is not zero: the configurations differ
+    assert np.all(var[:len(H)] > 1e-6)
+
+
+# ------------------------------------------------- the windowed-sinc weights and support
+
+def test_lanczos_m4_weights_closed_form():
+    """Impulse response of the m = 4 filter on the G grid: the weights of Eq. lanczos with
+    r_cut = 0.375, sinc(2 pi r_cut d) sinc(pi d / 4) at d = 0, 1, 2, 3 (and 0 at |d| = 4),
+    normalised per axis."""
+    w = np.array([0.030021, -0.135095, 0.270190, 1.0, 0.270190, -0.135095, 0.030021])
+    e0 = np.array([-7, -7, -7])
+    I = np.zeros((15, 15, 15))
+    I[7, 7, 7] = 1.0
+    out = O.lanczos(I, e0, 4, 1, [-3, -3, -3], [7, 7, 7])
+    line = w / w.sum()
+    assert np.allclose(out, np.einsum("i,j,k->ijk", line, line, line), atol=3e-6 * line.max() ** 3)
+    # the weights themselves, to the 6 digits given
+    assert np.allclose(out[3, 3, :] / out[3, 3, 3], w, atol=5e-7)
+
+
+@pytest.mark.parametrize("m", [2, 4])
+def test_lanczos_support_and_nominal_cutoff_are_the_printed_ones(m):
+    """The sum at an off-grid Q reads exactly (2m)^3 supercell Bragg points (64 for m = 2,
+    512 for m = 4), and the weight of Eq. weight_sinc vanishes where 2 r_cut d is a
+    nonzero integer, r_cut = 0.5 (1 - 1/m) (0.25 and 0.375)."""
+    g = golden()
+    rng = np.random.default_rng(80 + m)
+    e0 = np.array([-8, -8, -8])
+    base = rng.random((17, 17, 17))
+    Q = np.array([[0.37, -0.81, 1.23]])
+    ref = O.lanczos_points(base, e0, m, Q)[0]
+    touched = 0
+    for idx in itertools.product(range(17), repeat=3):
+        if max(abs(idx[a] + e0[a] - Q[0, a]) for a in range(3)) > m + 1:
+            continue
+        pert = base.copy()
+        pert[idx] += 1.0
+        if O.lanczos_points(pert, e0, m, Q)[0] != ref:
+            touched += 1
+    assert touched == g[f"lanczos_support_m{m}"]
+    rcut = g[f"lanczos_rcut_m{m}"]
+    # impulse at G = 0 read at Q = (d, 0, 0): proportional to the axis weight at d
+    imp = np.zeros((17, 17, 17))
+    imp[8, 8, 8] = 1.0
+    for k in range(1, 4):
+        d = k / (2 * rcut)
+        if d < m:
+            v = O.lanczos_points(imp, e0, m, np.array([[d, 0.0, 0.0]]))[0]
+            assert abs(v) < 1e-15
+    v = O.lanczos_points(imp, e0, m, np.array([[0.5 / (2 * rcut), 0.0, 0.0]]))[0]
+    assert v > 1e-3
+
+
+def _cosine_response_mean(m, dr, s=8):
+    """The plain filter applied to I(G) = 1 + cos(2 pi G1 dr), averaged over s output
+    points Q1 = i/s in [0, 1): the cutoff function at the separation dr."""
+    w = O.window_halfwidth(m)
+    e0 = np.array([-w - 2, -w - 2, -w - 2])
+    cnt = 2 * w + 6
+    G1 = e0[0] + np.arange(cnt)
+    I = np.broadcast_to((1.0 + np.cos(2 * np.pi * G1 * dr))[:, None, None], (cnt, cnt, cnt))
+    return float(np.mean(O.lanczos(I, e0, m, s, [0, 0, 0], [s, 1, 1])[:, 0, 0])) - 1.0
+
+
+@pytest.mark.parametrize("m", [2, 3, 4])
+def test_plain_filter_cutoff_is_half_at_the_nominal_cutoff(m):
+    """Sec. V.B: the idealized cutoff function equals 0.5 at the nominal cutoff
+    r_cut = 0.5 (1 - 1/m) (0.25 at m = 2, 0.375 at m = 4), is flat near 0, and ends at
+    the periodic limit r_cut = 0.5 of Sec. II; the actual (finite-sum) cutoff read on
+    the G grid follows it."""
+    g = golden()
+    rc = g.get(f"lanczos_rcut_m{m}", 0.5 * (1 - 1 / m))
+    assert abs(_cosine_response(m, 2, rc) - 0.5) < 0.06
+    assert _cosine_response(m, 2, 0.05) > 0.95
+    assert abs(_cosine_response_mean(m, g["periodic_rcut"])) < 0.02
+    assert _cosine_response_mean(m, 0.5 * g["periodic_rcut"] * (1 - 2 / m)) > 0.6
+
+
+@pytest.mark.parametrize("m", [4, 6])
+def test_spherical_cutoff_radius_in_real_space(m):
+    """The spherical cutoff W_r(|Q - G|) with r_c = (1 - 1/m) r_max, r_max the radius of
+    the sphere inscribed in the supercell (Sec. V.B), read in real space on a non-cubic
+    cell along directions off the axes: I(G) = 1 + cos(Q(G).dr) with Q(G) Cartesian
+    (inverse Angstrom) and dr Cartesian (Angstrom); the response at Q = 0 is I(0) - 1.
+    A ball of radius r_c, blurred by the window, keeps half of a separation at |dr| = r_c,
+    all of a short one and none of one well beyond r_c: any slip in the argument
+    |Q - G| r_c (a lost 2 pi, n or unit) moves the half-way point."""
+    cell, n = [4.0, 4.6, 5.3, 84.0, 97.0, 101.0], (6, 6, 6)
+    R = O.reciprocal_basis(cell)
+    rc = O.spherical_rc(cell, n, m)
+    e0 = np.array([-m - 1] * 3)
+    cnt = 2 * m + 3
+    Qc = (O.grid_points(e0, (cnt, cnt, cnt)) / np.asarray(n, float)) @ R
+
+    def response(dr):
+        I = (1.0 + np.cos(Qc @ dr)).reshape(cnt, cnt, cnt)
+        return float(O.lanczos_spherical(I, e0, m, 1, [0, 0, 0], [1, 1, 1], cell, n)[0, 0, 0]) - 1.0
+
+    for direction in ([1.0, 0.4, -0.3], [-0.2, 1.0, 0.7], [0.5, -0.5, 1.0]):
+        u = np.asarray(direction) / np.linalg.norm(direction)
+        assert response(0.3 * rc * u) > 0.9
+        assert abs(response(rc * u) - 0.5) < 0.15
+        assert abs(response(1.4 * rc * u)) < 0.06
