@@ -76,13 +76,15 @@ typedef struct {
                             /*   recombination (sites grouped by r_mu3 and f).  NULL => f = 1.               */
     int32_t kind;           /* DSX_NUCLEAR or DSX_MAGNETIC                                                    */
     int32_t has_occ;        /* 0: delta == 1 everywhere (no occupancy array is read)                         */
-    int32_t taylor_order;   /* nuclear: order N of the expansion of exp(i G.u) (Sec. III.C, Eq.              */
-                            /*   disp_expansion), 0 = no displacements; magnetic: must be 0                  */
+    int32_t taylor_order;   /* order N of the Taylor expansion of exp(i G.u) (Sec. III.C, Eq.                */
+                            /*   disp_expansion), in [0, DSX_MAX_ORDER]; 0 = no displacements.  Nuclear:     */
+                            /*   the displacive structure factor (Eq. total_sf_taylor).  Magnetic: the        */
+                            /*   moments stay at R + r_mu and the displacements enter only through the        */
+                            /*   Debye-Waller factor T_mu(G) of Eq. mag_sf, per Sec. III.A Eq. dw the mean of  */
+                            /*   (1 + a) e^{i G.u} over cells and configurations (1 + a = delta / c_mu, c_mu   */
+                            /*   the site's mean occupancy), here its order-N expansion; 0 => T = 1           */
     int32_t n_configs;      /* ensemble size M >= 1 (<.> is the mean over configurations)                    */
     double  norm_N;         /* N of I = <|F|^2>/N (Eq. intensity_sf); 0 => n1 n2 n3 x distinct positions      */
-    const double* dw_b;     /* [n_sites] isotropic Debye-Waller B [Angstrom^2] of magnetic sites: the factor  */
-                            /*   T_mu(G) = exp(-B s^2), s = |Q|/(4 pi), of Eq. mag_sf; NULL => T = 1.          */
-                            /*   Ignored for nuclear models.                                                   */
 } dsx_model_desc;
 
 /*
@@ -140,7 +142,7 @@ dsx_status dsx_create_model(const dsx_model_desc* d, dsx_model* out);
  * Set the variables of configuration `config` (0 <= config < n_configs).
  *   occ  [n_sites][n1][n2][n3]     delta (read iff has_occ)
  *   disp [n_sites][n1][n2][n3][3]  u in fractional unit-cell coordinates (read iff
- *                                  nuclear and taylor_order > 0)
+ *                                  taylor_order > 0)
  *   spin [n_sites][n1][n2][n3][3]  Cartesian moment M (read iff magnetic)
  * Pointers not read may be NULL.  where = DSX_HOST or DSX_DEVICE for all three.
  * The data are copied before return (the caller may free them at once).
@@ -171,8 +173,11 @@ dsx_status dsx_set_grid(dsx_model m, const int32_t g0[3], const int32_t count[3]
  *             k = G mod n, X the +i FFT of delta u1^p u2^q u3^r (Sec. III.C, Eq.
  *             total_sf_taylor, regrouped by monomial; Sec. III.B for N = 0);
  *   magnetic  I = (C/N) [ (1/M) sum |F_perp|^2 - [G = 0 mod n] |(1/M) sum F_perp|^2 ],
- *             F = sum_mu f_mu(|Q|) b_mu e^{2 pi i g.r_mu} M_{k,mu}, F_perp = F -
- *             Ghat (Ghat . F), C = 0.07265 barn, I(0) = 0 (Sec. III.D).
+ *             F = sum_mu f_mu(|Q|) T_mu(G) b_mu e^{2 pi i g.r_mu} M_{k,mu}, F_perp = F -
+ *             Ghat (Ghat . F), C = 0.07265 barn, I(0) = 0 (Sec. III.D, Eq. mag_sf), with
+ *             T_mu(G) = sum_{p+q+r<=N} (2 pi i)^{p+q+r} g1^p g2^q g3^r / (p! q! r!)
+ *             <u1^p u2^q u3^r>_mu (Eq. dw at order N; <.>_mu the mean over the site's
+ *             occupied atoms and the configurations), T = 1 when taylor_order = 0.
  * The points G = 0 (mod n) are evaluated in float64 from float64 lattice sums.
  * out: device pointer (where = DSX_DEVICE; asynchronous on hip_stream, NULL = the
  * null stream) or host pointer (where = DSX_HOST; synchronous).

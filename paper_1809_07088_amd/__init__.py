@@ -34,8 +34,7 @@ class ModelDesc(ctypes.Structure):
     _fields_ = [("cell", ctypes.c_double * 6), ("n", ctypes.c_int32 * 3), ("n_sites", ctypes.c_int32),
                 ("frac", ctypes.c_void_p), ("pos_id", ctypes.c_void_p), ("b", ctypes.c_void_p),
                 ("ff", ctypes.c_void_p), ("kind", ctypes.c_int32), ("has_occ", ctypes.c_int32),
-                ("taylor_order", ctypes.c_int32), ("n_configs", ctypes.c_int32), ("norm_N", ctypes.c_double),
-                ("dw_b", ctypes.c_void_p)]
+                ("taylor_order", ctypes.c_int32), ("n_configs", ctypes.c_int32), ("norm_N", ctypes.c_double)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -147,19 +146,45 @@ def _check(status):
         raise DsxError(status, last_error())
 
 
-def _ptr_where(a):
-    """(pointer, where, keepalive) for a numpy array (host) or a torch tensor (device)."""
+def _ptr_where(a, nelem=None):
+    """(pointer, where, keepalive) of an input array: a numpy array (host memory,
+    converted to contiguous float32 if needed) or a contiguous float32 torch tensor.
+    nelem, when given, is the element count the library will read."""
     if a is None:
         return None, None, None
     if isinstance(a, np.ndarray):
         a = np.ascontiguousarray(a, dtype=np.float32)
-        return a.ctypes.data, HOST, a
-    import torch
-    if isinstance(a, torch.Tensor):
+        ptr, where, size = a.ctypes.data, HOST, a.size
+    else:
+        import torch
+        if not isinstance(a, torch.Tensor):
+            raise TypeError(f"unsupported array type {type(a)}")
         if a.dtype != torch.float32 or not a.is_contiguous():
             raise ValueError("device arrays must be contiguous float32 tensors")
-        return a.data_ptr(), (DEVICE if a.is_cuda else HOST), a
-    raise TypeError(f"unsupported array type {type(a)}")
+        ptr, where, size = a.data_ptr(), (DEVICE if a.is_cuda else HOST), a.numel()
+    if nelem is not None and size != nelem:
+        raise ValueError(f"input array has {size} elements, the model reads {nelem}")
+    return ptr, where, a
+
+
+def _ptr_out(a, nelem=None):
+    """(pointer, where) of an output array, written in place and never copied: a
+    writable C-contiguous float32 numpy array (host) or a contiguous float32 torch
+    tensor.  nelem, when given, is the element count the library will write."""
+    if isinstance(a, np.ndarray):
+        if a.dtype != np.float32 or not a.flags.c_contiguous or not a.flags.writeable:
+            raise ValueError("host outputs must be writable C-contiguous float32 numpy arrays")
+        ptr, where, size = a.ctypes.data, HOST, a.size
+    else:
+        import torch
+        if not isinstance(a, torch.Tensor):
+            raise TypeError(f"unsupported output type {type(a)}")
+        if a.dtype != torch.float32 or not a.is_contiguous():
+            raise ValueError("outputs must be contiguous float32 tensors")
+        ptr, where, size = a.data_ptr(), (DEVICE if a.is_cuda else HOST), a.numel()
+    if nelem is not None and size != nelem:
+        raise ValueError(f"output array has {size} elements, the call writes {nelem}")
+    return ptr, where
 
 
 def _stream_handle(stream):
@@ -172,13 +197,12 @@ def _stream_handle(stream):
 
 
 def make_desc(cell, n, frac, b, kind=NUCLEAR, taylor_order=0, n_configs=1, has_occ=False,
-              ff=None, pos_id=None, norm_N=0.0, dw_b=None):
+              ff=None, pos_id=None, norm_N=0.0):
     """A dsx_model_desc plus the arrays it points to (kept alive by the caller)."""
     frac = np.ascontiguousarray(frac, dtype=np.float64).reshape(-1, 3)
     b = np.ascontiguousarray(b, dtype=np.float64).reshape(-1)
     ffa = None if ff is None else np.ascontiguousarray(ff, dtype=np.float64).reshape(-1, 7)
     pid = None if pos_id is None else np.ascontiguousarray(pos_id, dtype=np.int32)
-    dwb = None if dw_b is None else np.ascontiguousarray(dw_b, dtype=np.float64).reshape(-1)
     d = ModelDesc()
     d.cell[:] = [float(v) for v in cell]
     d.n[:] = [int(v) for v in n]
@@ -189,8 +213,7 @@ def make_desc(cell, n, frac, b, kind=NUCLEAR, taylor_order=0, n_configs=1, has_o
     d.pos_id = None if pid is None else pid.ctypes.data
     d.kind, d.has_occ, d.taylor_order = int(kind), int(bool(has_occ)), int(taylor_order)
     d.n_configs, d.norm_N = int(n_configs), float(norm_N)
-    d.dw_b = None if dwb is None else dwb.ctypes.data
-    return d, (frac, b, ffa, pid, dwb)
+    return d, (frac, b, ffa, pid)
 
 
 def plan_query(**kw) -> PlanInfo:
@@ -207,8 +230,8 @@ def create_model(**kw) -> int:
     return h.value
 
 
-def set_sites(model, config, occ=None, disp=None, spin=None):
-    ptrs = [_ptr_where(a) for a in (occ, disp, spin)]
+def set_sites(model, config, occ=None, disp=None, spin=None, sizes=(None, None, None)):
+    ptrs = [_ptr_where(a, z) for a, z in zip((occ, disp, spin), sizes)]
     wheres = {w for (_, w, _) in ptrs if w is not None}
     if len(wheres) > 1:
         raise ValueError("occ, disp and spin must all be host or all device arrays")
@@ -216,9 +239,9 @@ def set_sites(model, config, occ=None, disp=None, spin=None):
     _check(lib().dsx_set_sites(model, int(config), ptrs[0][0], ptrs[1][0], ptrs[2][0], where))
 
 
-def set_sites_async(model, config, occ=None, disp=None, spin=None, stream=None):
+def set_sites_async(model, config, occ=None, disp=None, spin=None, stream=None, sizes=(None, None, None)):
     """Stream-ordered site upload from device tensors (kept unchanged until it has run)."""
-    ptrs = [_ptr_where(a) for a in (occ, disp, spin)]
+    ptrs = [_ptr_where(a, z) for a, z in zip((occ, disp, spin), sizes)]
     if any(w == HOST for (_, w, _) in ptrs):
         raise ValueError("set_sites_async takes device tensors")
     _check(lib().dsx_set_sites_async(model, int(config), ptrs[0][0], ptrs[1][0], ptrs[2][0],
@@ -231,31 +254,31 @@ def set_grid(model, g0, count):
     _check(lib().dsx_set_grid(model, g.ctypes.data, c.ctypes.data))
 
 
-def compute_intensity(model, out, stream=None):
-    p, where, _ = _ptr_where(out)
+def compute_intensity(model, out, stream=None, nelem=None):
+    p, where = _ptr_out(out, nelem)
     st = _stream_handle(stream) if where == DEVICE else None
     _check(lib().dsx_compute_intensity(model, p, where, st))
     return out
 
 
-def noise_filter(model, lanczos_m, oversample, out, stream=None):
-    p, where, _ = _ptr_where(out)
+def noise_filter(model, lanczos_m, oversample, out, stream=None, nelem=None):
+    p, where = _ptr_out(out, nelem)
     st = _stream_handle(stream) if where == DEVICE else None
     _check(lib().dsx_noise_filter(model, int(lanczos_m), int(oversample), p, where, st))
     return out
 
 
-def noise_filter_cutoff(model, lanczos_m, mprime, oversample, out, stream=None):
+def noise_filter_cutoff(model, lanczos_m, mprime, oversample, out, stream=None, nelem=None):
     """dsx_noise_filter_cutoff: the filter with the m' cutoff modification."""
-    p, where, _ = _ptr_where(out)
+    p, where = _ptr_out(out, nelem)
     st = _stream_handle(stream) if where == DEVICE else None
     _check(lib().dsx_noise_filter_cutoff(model, int(lanczos_m), int(mprime), int(oversample), p, where, st))
     return out
 
 
-def noise_filter_spherical(model, lanczos_m, oversample, out, stream=None):
+def noise_filter_spherical(model, lanczos_m, oversample, out, stream=None, nelem=None):
     """dsx_noise_filter_spherical: the filter with the spherical cutoff W_r."""
-    p, where, _ = _ptr_where(out)
+    p, where = _ptr_out(out, nelem)
     st = _stream_handle(stream) if where == DEVICE else None
     _check(lib().dsx_noise_filter_spherical(model, int(lanczos_m), int(oversample), p, where, st))
     return out
@@ -265,7 +288,7 @@ def filter_points(model, lanczos_m, q, out, mprime=2, stream=None):
     """dsx_filter_points: the filter at arbitrary points q [npts][3] (float64 host
     array, units of the supercell Bragg grid) into out [npts]."""
     q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1, 3)
-    p, where, _ = _ptr_where(out)
+    p, where = _ptr_out(out, q.shape[0])
     st = _stream_handle(stream) if where == DEVICE else None
     _check(lib().dsx_filter_points(model, int(lanczos_m), int(mprime), q.shape[0],
                                    q.ctypes.data_as(ctypes.c_void_p), p, where, st))
@@ -374,33 +397,50 @@ class Batch:
 
 
 class Model:
-    """Convenience owner of one dsx model handle."""
+    """Convenience owner of one dsx model handle; checks array sizes against the model
+    before every call that reads or writes caller memory."""
 
     def __init__(self, **kw):
         self.desc_kw = dict(kw)
         self.handle = create_model(**kw)
+        self.g0 = self.count = None
+
+    def _site_sizes(self):
+        kw = self.desc_kw
+        n = [int(v) for v in kw["n"]]
+        S = np.asarray(kw["frac"]).reshape(-1, 3).shape[0]
+        per = S * n[0] * n[1] * n[2]
+        return (per, 3 * per, 3 * per)
+
+    def _box_voxels(self, s=1):
+        if self.count is None:
+            return None          # the library reports the missing grid
+        return int(np.prod([s * int(c) for c in self.count]))
 
     def set_sites(self, config, occ=None, disp=None, spin=None):
-        set_sites(self.handle, config, occ, disp, spin)
+        set_sites(self.handle, config, occ, disp, spin, sizes=self._site_sizes())
 
     def set_sites_async(self, config, occ=None, disp=None, spin=None, stream=None):
-        set_sites_async(self.handle, config, occ, disp, spin, stream)
+        set_sites_async(self.handle, config, occ, disp, spin, stream, sizes=self._site_sizes())
 
     def set_grid(self, g0, count):
-        self.g0, self.count = tuple(int(v) for v in g0), tuple(int(v) for v in count)
         set_grid(self.handle, g0, count)
+        self.g0, self.count = tuple(int(v) for v in g0), tuple(int(v) for v in count)
 
     def compute_intensity(self, out, stream=None):
-        return compute_intensity(self.handle, out, stream)
+        return compute_intensity(self.handle, out, stream, nelem=self._box_voxels())
 
     def noise_filter(self, lanczos_m, oversample, out, stream=None):
-        return noise_filter(self.handle, lanczos_m, oversample, out, stream)
+        return noise_filter(self.handle, lanczos_m, oversample, out, stream,
+                            nelem=self._box_voxels(int(oversample)))
 
     def noise_filter_cutoff(self, lanczos_m, mprime, oversample, out, stream=None):
-        return noise_filter_cutoff(self.handle, lanczos_m, mprime, oversample, out, stream)
+        return noise_filter_cutoff(self.handle, lanczos_m, mprime, oversample, out, stream,
+                                   nelem=self._box_voxels(int(oversample)))
 
     def noise_filter_spherical(self, lanczos_m, oversample, out, stream=None):
-        return noise_filter_spherical(self.handle, lanczos_m, oversample, out, stream)
+        return noise_filter_spherical(self.handle, lanczos_m, oversample, out, stream,
+                                      nelem=self._box_voxels(int(oversample)))
 
     def filter_points(self, lanczos_m, q, out, mprime=2, stream=None):
         return filter_points(self.handle, lanczos_m, q, out, mprime, stream)
@@ -436,6 +476,7 @@ class ServedModel(Model):
         _check(lib().dsx_server_add_model(server.handle, ctypes.byref(d), ctypes.byref(h)))
         self.handle = h.value
         self.server = server
+        self.g0 = self.count = None
 
     def close(self):
         self.handle = None
@@ -456,11 +497,12 @@ class Server:
 
     def submit(self, model, out, config=-1, occ=None, disp=None, spin=None, lanczos_m=0, oversample=1):
         """Queue a request; returns its ticket (DsxError ERR_BUSY when the queue is full)."""
-        ptrs = [_ptr_where(a) for a in (occ, disp, spin)]
+        ptrs = [_ptr_where(a, z) for a, z in zip((occ, disp, spin), model._site_sizes())]
         wheres = {w for (_, w, _) in ptrs if w is not None}
         if len(wheres) > 1:
             raise ValueError("occ, disp and spin must all be host or all device arrays")
-        p_out, w_out, _ = _ptr_where(out)
+        nelem = model._box_voxels(int(oversample) if lanczos_m else 1)
+        p_out, w_out = _ptr_out(out, nelem)
         if w_out != DEVICE:
             raise ValueError("out must be a device tensor")
         r = Request(model.handle, int(config), ptrs[0][0], ptrs[1][0], ptrs[2][0],

@@ -193,6 +193,14 @@ struct DeviceTables {
     int n3s = 0, block3 = 0;   // k3 per slice, threads per plane of a sliced block
 };
 
+// Releases every device buffer of one cached box.
+void free_tables(DeviceTables& t)
+{
+    dfree(t.tab1); dfree(t.tab2); dfree(t.tabK2); dfree(t.tabK3); dfree(t.tabH3);
+    dfree(t.work); dfree(t.work2); dfree(t.work3); dfree(t.k3tab);
+    t = DeviceTables{};
+}
+
 struct LaunchPlan {
     RecombParams rp;
     int hc = 0, block = 0;
@@ -222,6 +230,12 @@ struct dsx_model_s {
     int device = 0;
     float* d_occ = nullptr;
     float* d_vec = nullptr;
+    // magnetic models with displacements: the Debye-Waller factor of Eq. dw
+    int dw_order = 0;              // Taylor order of T_mu(G); 0 = no displacements (T = 1)
+    int dwT = 0;                   // monomials of that order
+    float* d_dsp = nullptr;        // [M][S][ncell][3] fractional displacements
+    double* d_dwsums = nullptr;    // [M*S][dwT] float64 lattice sums of the displacement monomials
+    double* d_dwc = nullptr;       // [S][dwT] their means over occupied atoms and configurations
     double* d_partial = nullptr;
     double* d_sums = nullptr;
     double* d_site = nullptr;   // [S][11]: r_mu, b_mu, form factor
@@ -278,8 +292,6 @@ dsx_status validate_desc(const dsx_model_desc* d)
     if (!d->frac || !d->b) return fail(DSX_ERR_ARG, "frac and b are required");
     if (d->kind != DSX_NUCLEAR && d->kind != DSX_MAGNETIC) return fail(DSX_ERR_ARG, "bad kind");
     if (d->taylor_order < 0) return fail(DSX_ERR_ARG, "taylor_order must be >= 0");
-    if (d->kind == DSX_MAGNETIC && d->taylor_order != 0)
-        return fail(DSX_ERR_UNSUPPORTED, "magnetic models take no Taylor order");
     if (d->taylor_order > DSX_MAX_ORDER) return fail(DSX_ERR_UNSUPPORTED, "taylor_order exceeds DSX_MAX_ORDER");
     if (d->n_configs < 1) return fail(DSX_ERR_ARG, "n_configs must be >= 1");
     if (!(d->norm_N >= 0.0)) return fail(DSX_ERR_ARG, "norm_N must be >= 0");
@@ -311,7 +323,6 @@ int count_classes(const dsx_model_desc* d, std::vector<int>* site_of, std::vecto
             bool same = d->frac[3 * i + 2] == d->frac[3 * j + 2];
             if (same && d->ff)
                 for (int k = 0; k < 7; ++k) same = same && d->ff[7 * i + k] == d->ff[7 * j + k];
-            if (same && d->kind == DSX_MAGNETIC && d->dw_b) same = d->dw_b[i] == d->dw_b[j];
             if (same) cls[j] = nc;
         }
         ++nc;
@@ -345,6 +356,12 @@ Sizes sizes_of(const dsx_model_desc* d)
     const long long sc = sums_chunk(z.ncell, M * S);
     const long long chunks = (z.ncell + sc - 1) / sc;
     z.device_bytes = z.spectrum_bytes + in + M * S * z.T * 8 * (chunks + 1);
+    if (d->kind == DSX_MAGNETIC && d->taylor_order > 0) {
+        // displacements, their lattice sums (partials shared with the spins') and means
+        const long long dwT = n_monomials(d->taylor_order);
+        z.device_bytes += M * S * z.ncell * 12 + M * S * dwT * 8 * (chunks > 1 ? chunks : 1)
+                        + M * S * dwT * 8 + S * dwT * 8;
+    }
     return z;
 }
 
@@ -358,13 +375,11 @@ dsx_status check_model(dsx_model m)
 void free_model(dsx_model m)
 {
     dfree(m->d_occ); dfree(m->d_vec); dfree(m->d_partial); dfree(m->d_sums); dfree(m->d_X);
+    dfree(m->d_dsp); dfree(m->d_dwsums); dfree(m->d_dwc);
     dfree(m->d_site);
     for (auto& t : m->d_tw) dfree(t);
     dfree(m->d_ext); dfree(m->d_stage); dfree(m->d_pts); dfree(m->d_q);
-    for (auto& kv : m->tables) {
-        dfree(kv.second.tab1); dfree(kv.second.tab2); dfree(kv.second.tabK3); dfree(kv.second.tabH3);
-        dfree(kv.second.work);
-    }
+    for (auto& kv : m->tables) free_tables(kv.second);
     for (auto& kv : m->lanczos_w) dfree(kv.second);
     if (m->order_ev) (void)hipEventDestroy(m->order_ev);
 }
@@ -389,11 +404,7 @@ dsx_status tables_for(dsx_model m, const Box& bx, DeviceTables** out)
         // (never while a recorded batch still points at a cached table)
         hipError_t se = hipStreamSynchronize(m->last_stream);
         if (se != hipSuccess) { m->failed = true; return fail(DSX_ERR_DEVICE, hipGetErrorString(se)); }
-        for (auto& kv : m->tables) {
-            dfree(kv.second.tab1); dfree(kv.second.tab2); dfree(kv.second.tabK3); dfree(kv.second.tabH3);
-            dfree(kv.second.tabK2); dfree(kv.second.work); dfree(kv.second.work2); dfree(kv.second.work3);
-            dfree(kv.second.k3tab);
-        }
+        for (auto& kv : m->tables) free_tables(kv.second);
         m->tables.clear();
     }
     DeviceTables t;
@@ -555,8 +566,7 @@ dsx_status tables_for(dsx_model m, const Box& bx, DeviceTables** out)
           (e = hipMemcpy(t.work3, work3.data(), sizeof(int4) * work3.size(), hipMemcpyHostToDevice)) != hipSuccess)) ||
         (e = hipMalloc(&t.k3tab, sizeof(int2) * k3t.size())) != hipSuccess ||
         (e = hipMemcpy(t.k3tab, k3t.data(), sizeof(int2) * k3t.size(), hipMemcpyHostToDevice)) != hipSuccess) {
-        dfree(t.tab1); dfree(t.tab2); dfree(t.tabK3); dfree(t.tabH3); dfree(t.tabK2); dfree(t.work); dfree(t.work2);
-        dfree(t.work3); dfree(t.k3tab);
+        free_tables(t);
         if (e == hipErrorOutOfMemory) return fail(DSX_ERR_NOMEM, "out of device memory for phase tables");
         m->failed = true;
         return fail(DSX_ERR_DEVICE, std::string("phase tables: ") + hipGetErrorString(e));
@@ -629,9 +639,15 @@ dsx_status plan_recombine(dsx_model m, const Box& bx, float* out, const Layout& 
             if (m->has_ff && m->ff[8 * mu + k] != m->ff[k]) p.ff_uniform = 0;
         }
     }
+    if (m->dw_order > 0) {
+        p.dwc = m->d_dwc;
+        p.dw_order = m->dw_order;
+        p.dwT = m->dwT;
+        p.dw_elems = m->S * n_pairs(m->dw_order);
+    }
     lp.hc = tb->hc;
     lp.block = tb->block;
-    lp.lds = m->chunk_lds + sizeof(float2) * (size_t)m->nclass * tb->nH3span;
+    lp.lds = m->chunk_lds + sizeof(float2) * ((size_t)m->nclass * tb->nH3span + p.dw_elems);
     if (lp.lds > 160 * 1024) return fail(DSX_ERR_UNSUPPORTED, "recombination does not fit the LDS for this box");
     // folded form: every r_mu2 a multiple of 1/2 (exactly, as given), fewer r3 classes
     // than sites, and the class buffers fit the LDS
@@ -696,6 +712,17 @@ dsx_status plan_recombine(dsx_model m, const Box& bx, float* out, const Layout& 
                     ++t;
                 }
     }
+    if (m->dw_order > 0) {
+        int t = 0;
+        for (int d = 0; d <= m->dw_order; ++d)
+            for (int pp = d; pp >= 0; --pp)
+                for (int qq = d - pp; qq >= 0; --qq) {
+                    q.mono[3 * t] = (int8_t)pp; q.mono[3 * t + 1] = (int8_t)qq; q.mono[3 * t + 2] = (int8_t)(d - pp - qq);
+                    ++t;
+                }
+        q.dwc = m->d_dwc;
+        q.dwT = m->dwT;
+    }
     for (int i = 0; i < 9; ++i) q.recip[i] = m->recip[i];
     q.has_ff = m->has_ff ? 1 : 0;
     return DSX_OK;
@@ -711,6 +738,14 @@ dsx_status ensure_spectra(dsx_model m, hipStream_t st, bool force = false)
     sp.M = m->M; sp.S = m->S; sp.ncell = m->ncell; sp.T = m->T; sp.kind = m->kind;
     sp.chunk = m->sum_chunk; sp.nchunk = m->sum_chunks;
     HIPCHK(m, timed("sums", st, [&] { return launch_sums(sp, m->order, st); }));
+    if (m->dw_order > 0) {
+        // the Debye-Waller factor of Eq. dw: float64 sums of the displacement monomials
+        // (the partials are free again: the spins' reduction ran before on this stream)
+        SumsParams dp = sp;
+        dp.vec = m->d_dsp; dp.sums = m->d_dwsums; dp.T = m->dwT; dp.kind = DSX_NUCLEAR;
+        HIPCHK(m, timed("sums", st, [&] { return launch_sums(dp, m->dw_order, st); }));
+        HIPCHK(m, timed("sums", st, [&] { return launch_dw_mean(m->d_dwsums, m->d_dwc, m->M, m->S, m->dwT, st); }));
+    }
 
     PlaneParams pp;
     std::memset(&pp, 0, sizeof(pp));
@@ -889,13 +924,15 @@ dsx_status create_model_impl(const dsx_model_desc* d, bool transient, dsx_model*
     m->b.assign(d->b, d->b + m->S);
     // per site: the 7 form-factor parameters (f = 1 when none are given) and the
     // Debye-Waller B (0 when none is given)
-    m->has_ff = d->ff != nullptr || (d->kind == DSX_MAGNETIC && d->dw_b != nullptr);
+    m->has_ff = d->ff != nullptr;
     if (m->has_ff) {
         m->ff.assign((size_t)8 * m->S, 0.0);
-        for (int mu = 0; mu < m->S; ++mu) {
-            for (int k = 0; k < 7; ++k) m->ff[8 * mu + k] = d->ff ? d->ff[7 * mu + k] : (k == 6 ? 1.0 : 0.0);
-            m->ff[8 * mu + 7] = (d->kind == DSX_MAGNETIC && d->dw_b) ? d->dw_b[mu] : 0.0;
-        }
+        for (int mu = 0; mu < m->S; ++mu)
+            for (int k = 0; k < 7; ++k) m->ff[8 * mu + k] = d->ff[7 * mu + k];
+    }
+    if (d->kind == DSX_MAGNETIC && d->taylor_order > 0) {
+        m->dw_order = d->taylor_order;
+        m->dwT = n_monomials(m->dw_order);
     }
     reciprocal_basis(m->cell, m->recip);
     int npos = m->S;
@@ -939,9 +976,15 @@ dsx_status create_model_impl(const dsx_model_desc* d, bool transient, dsx_model*
     if ((m->kind == DSX_MAGNETIC || m->order > 0) && e == hipSuccess)
         e = alloc((void**)&m->d_vec, M * S * nc * 3 * sizeof(float));
     m->spectrum_bytes = (size_t)z.spectrum_bytes;
-    m->partial_bytes = M * S * m->sum_chunks * m->T * sizeof(double);
+    // the partial sums serve the spins' and (after them, same stream) the displacements' sums
+    m->partial_bytes = M * S * m->sum_chunks * std::max(m->T, m->dwT) * sizeof(double);
     if (e == hipSuccess && !transient) e = alloc((void**)&m->d_partial, m->partial_bytes);
     if (e == hipSuccess) e = alloc((void**)&m->d_sums, M * S * m->T * sizeof(double));
+    if (m->dw_order > 0) {
+        if (e == hipSuccess) e = alloc((void**)&m->d_dsp, M * S * nc * 3 * sizeof(float));
+        if (e == hipSuccess) e = alloc((void**)&m->d_dwsums, M * S * m->dwT * sizeof(double));
+        if (e == hipSuccess) e = alloc((void**)&m->d_dwc, S * m->dwT * sizeof(double));
+    }
     if (e == hipSuccess && !transient) e = alloc((void**)&m->d_X, (size_t)z.spectrum_bytes);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&m->order_ev, hipEventDisableTiming);
     if (e == hipSuccess) {
@@ -1003,12 +1046,14 @@ dsx_status dsx_set_sites(dsx_model m, int32_t config, const float* occ, const fl
     const bool need_vec = m->kind == DSX_MAGNETIC || m->order > 0;
     if (need_vec && !vec)
         return fail(DSX_ERR_ARG, m->kind == DSX_MAGNETIC ? "spin is required" : "disp is required (taylor_order > 0)");
+    if (m->dw_order > 0 && !disp) return fail(DSX_ERR_ARG, "disp is required (taylor_order > 0)");
     if (m->queued.load() > 0) return fail(DSX_ERR_BUSY, "the model has requests queued at its server");
     HIPCHK(m, hipStreamSynchronize(m->last_stream));   // no pending work still reads the inputs
     const hipMemcpyKind kind = where == DSX_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
     const size_t per = (size_t)m->S * m->ncell;
     if (m->has_occ) HIPCHK(m, hipMemcpy(m->d_occ + per * config, occ, per * sizeof(float), kind));
     if (need_vec) HIPCHK(m, hipMemcpy(m->d_vec + 3 * per * config, vec, 3 * per * sizeof(float), kind));
+    if (m->dw_order > 0) HIPCHK(m, hipMemcpy(m->d_dsp + 3 * per * config, disp, 3 * per * sizeof(float), kind));
     if (where == DSX_DEVICE) HIPCHK(m, hipStreamSynchronize(nullptr));
     m->set[config] = 1;
     m->dirty = true;
@@ -1026,6 +1071,7 @@ dsx_status dsx_set_sites_async(dsx_model m, int32_t config, const float* occ, co
     const bool need_vec = m->kind == DSX_MAGNETIC || m->order > 0;
     if (need_vec && !vec)
         return fail(DSX_ERR_ARG, m->kind == DSX_MAGNETIC ? "spin is required" : "disp is required (taylor_order > 0)");
+    if (m->dw_order > 0 && !disp) return fail(DSX_ERR_ARG, "disp is required (taylor_order > 0)");
     if (m->server) return fail(DSX_ERR_STATE, "the model belongs to a server: its requests carry the sites");
     hipStream_t st = (hipStream_t)hip_stream;
     if ((s = follow(m, st)) != DSX_OK) return s;     // after every earlier use of the inputs
@@ -1034,6 +1080,8 @@ dsx_status dsx_set_sites_async(dsx_model m, int32_t config, const float* occ, co
         HIPCHK(m, hipMemcpyAsync(m->d_occ + per * config, occ, per * sizeof(float), hipMemcpyDeviceToDevice, st));
     if (need_vec)
         HIPCHK(m, hipMemcpyAsync(m->d_vec + 3 * per * config, vec, 3 * per * sizeof(float), hipMemcpyDeviceToDevice, st));
+    if (m->dw_order > 0)
+        HIPCHK(m, hipMemcpyAsync(m->d_dsp + 3 * per * config, disp, 3 * per * sizeof(float), hipMemcpyDeviceToDevice, st));
     m->set[config] = 1;
     m->dirty = true;
     return DSX_OK;
@@ -1935,6 +1983,8 @@ dsx_status launch_request(dsx_server s, const Request& q, hipStream_t st, hipEve
         if (m->has_occ) e = hipMemcpyAsync(m->d_occ + per * q.r.config, q.r.occ, per * sizeof(float), kind, st);
         if (e == hipSuccess && vec)
             e = hipMemcpyAsync(m->d_vec + 3 * per * q.r.config, vec, 3 * per * sizeof(float), kind, st);
+        if (e == hipSuccess && m->dw_order > 0)
+            e = hipMemcpyAsync(m->d_dsp + 3 * per * q.r.config, q.r.disp, 3 * per * sizeof(float), kind, st);
         if (e != hipSuccess) { m->failed = true; rs = fail(DSX_ERR_DEVICE, std::string("site upload: ") + hipGetErrorString(e)); }
         else m->set[q.r.config] = 1;
     }
@@ -2117,6 +2167,7 @@ dsx_status dsx_server_submit(dsx_server s, const dsx_request* r, int64_t* ticket
         const bool need_vec = m->kind == DSX_MAGNETIC || m->order > 0;
         if (need_vec && !(m->kind == DSX_MAGNETIC ? r->spin : r->disp))
             return fail(DSX_ERR_ARG, m->kind == DSX_MAGNETIC ? "spin is required" : "disp is required");
+        if (m->dw_order > 0 && !r->disp) return fail(DSX_ERR_ARG, "disp is required (taylor_order > 0)");
     }
     Request q;
     q.r = *r;

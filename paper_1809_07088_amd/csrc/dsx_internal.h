@@ -124,7 +124,13 @@ struct RecombParams {
     // magnetic only
     float recip[9];         // rows a*, b*, c* (inverse Angstrom)
     int32_t ff_uniform;     // 1 when every site has the same form factor
-    float ff[kMaxSites][8];  // per sorted position: form factor (7), Debye-Waller B
+    float ff[kMaxSites][8];  // per sorted position: form factor (7), unused
+    // Debye-Waller factor T_mu(G) of magnetic sites with displacements: dwc[mu][t] the
+    // mean over occupied atoms and configurations of u1^p u2^q u3^r (monomial t,
+    // mono_index order), float64; null or dw_order 0: T = 1.  The kernel contracts p per
+    // block into LDS (dw_elems float2 after the class phases), q per thread and r per voxel.
+    const double* dwc;
+    int32_t dw_order, dwT, dw_elems;
 };
 
 // ---------------------------------------------------------------------------- Bragg (k = 0)
@@ -137,10 +143,13 @@ struct BraggParams {
     int32_t Hlo[3], nH[3];  // H with n H inside the box
     int32_t S, T, M, kind;
     double scale;           // 1/N  (magnetic: C/N); the means over configurations are explicit
-    const double* site;     // [S][12]: r_mu (3), b_mu, form factor (7), Debye-Waller B
+    const double* site;     // [S][12]: r_mu (3), b_mu, form factor (7), unused
     double recip[9];
     int32_t has_ff;
-    int8_t mono[3 * kMaxMono];   // exponents (p, q, r) of monomial t
+    int8_t mono[3 * kMaxMono];   // exponents (p, q, r) of monomial t (nuclear sums, or the
+                                 // Debye-Waller means of a magnetic model)
+    const double* dwc;      // magnetic: [S][dwT] Debye-Waller means, or null (T = 1)
+    int32_t dwT;
 };
 
 // ---------------------------------------------------------------------------- Lanczos
@@ -182,6 +191,9 @@ hipError_t launch_recombine_nuclear(const RecombParams& p, int order, int hc, in
 hipError_t launch_recombine_magnetic(const RecombParams& p, int hc, int block, size_t lds,
                                      hipStream_t st);
 hipError_t launch_bragg(const BraggParams& p, int order, hipStream_t st);
+// dwc[mu][t] = sum_m sums[m][mu][t] / sum_m sums[m][mu][0] (0 for a site with no atom):
+// the Debye-Waller means of Eq. dw from the float64 lattice sums of the displacements.
+hipError_t launch_dw_mean(const double* sums, double* dwc, int M, int S, int T, hipStream_t st);
 hipError_t launch_lanczos(const LanczosParams& p, hipStream_t st);
 hipError_t launch_lanczos_points(const PointsParams& p, hipStream_t st);
 // the spherical cutoff: p.wn holds [s^3][(2m)^3] normalised weights; m in {2, 3, 4}

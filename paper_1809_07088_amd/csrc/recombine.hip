@@ -143,12 +143,11 @@ __device__ __forceinline__ const float2* stage_class_phases(const RecombParams& 
 constexpr int kBufferFlags = 0x00020000;
 constexpr uint32_t kNoRecord = 0x80000000u;   // an offset past every record count used here
 
-// f(s) T(s) of a site: the analytic form factor (A e^{-a s^2} + B e^{-b s^2} +
-// C e^{-c s^2} + D) times the Debye-Waller factor T = exp(-B_dw s^2) (f[7] = B_dw, 0
-// when none is given).  Nuclear sites use it as a |Q|-dependent scattering factor.
+// f(s) of a site: the analytic form factor A e^{-a s^2} + B e^{-b s^2} + C e^{-c s^2} + D.
+// Magnetic sites use it as f_mag of Eq. mag_sf, nuclear sites as a |Q|-dependent
+// scattering factor.
 __device__ __forceinline__ float site_ff(const float* f, float s2) {
-    const float ff = f[0] * expf(-f[1] * s2) + f[2] * expf(-f[3] * s2) + f[4] * expf(-f[5] * s2) + f[6];
-    return f[7] == 0.f ? ff : ff * expf(-f[7] * s2);
+    return f[0] * expf(-f[1] * s2) + f[2] * expf(-f[3] * s2) + f[4] * expf(-f[5] * s2) + f[6];
 }
 
 // ---------------------------------------------------------------------------- nuclear
@@ -799,10 +798,74 @@ void k_recombine_folded(RecombParams P)
 }
 
 // ---------------------------------------------------------------------------- magnetic
-// the form factor and Debye-Waller factor of Eq. mag_sf
+// the form factor f_mag of Eq. mag_sf
 __device__ __forceinline__ float mag_ff(const float* f, float s2) { return site_ff(f, s2); }
 
-template <int HC>
+// Debye-Waller factor T_mu(G) of Sec. III.A, Eq. dw, in its order-N Taylor form,
+//   T_mu(G) = sum_{p+q+r<=N} (i t1)^p/p! (i t2)^q/q! (i t3)^r/r! <u1^p u2^q u3^r>_mu,
+// t_a = 2 pi g_a, <.> the mean over the site's occupied atoms and the configurations
+// (dwc), sum-factorised like the nuclear recombination: p per block (this function, in
+// float64, into LDS A[mu][pair (q, r)]), q per thread (dw_level_b), r per voxel (Horner).
+__device__ void dw_level_a(const RecombParams& P, double tau1, float2* A)
+{
+    const int N = P.dw_order, QR = n_pairs(N);
+    for (int idx = threadIdx.x; idx < P.S * QR; idx += blockDim.x) {
+        const int mu = idx / QR, j = idx - mu * QR;
+        int e = 0;
+        while ((e + 1) * (e + 2) / 2 <= j) ++e;
+        const int r = j - e * (e + 1) / 2, q = e - r;
+        const double* c = P.dwc + (size_t)mu * P.dwT;
+        double ar = 0.0, ai = 0.0, mag = 1.0;     // (i t1)^p / p! = i^p mag
+        for (int p = 0; p + e <= N; ++p) {
+            const double v = mag * c[mono_index(p, q, r)];
+            switch (p & 3) {
+                case 0: ar += v; break;
+                case 1: ai += v; break;
+                case 2: ar -= v; break;
+                default: ai -= v; break;
+            }
+            mag *= tau1 / (p + 1);
+        }
+        A[idx] = make_float2((float)ar, (float)ai);
+    }
+}
+
+// B[r] = sum_q (i t2)^q/q! A[(q, r)] / r! for one site (the 1/r! folded in here).
+__device__ __forceinline__ void dw_level_b(const float2* A, int N, float tau2, float2 (&B)[kMaxOrder + 1])
+{
+#pragma unroll
+    for (int r = 0; r <= kMaxOrder; ++r) {
+        B[r] = make_float2(0.f, 0.f);
+        if (r > N) continue;
+        float mag = 1.f, rf = 1.f;
+        for (int k = 2; k <= r; ++k) rf *= (float)k;
+        for (int q = 0; q + r <= N; ++q) {
+            const float2 a = A[pair_index(q, r)];
+            float2 v = make_float2(a.x * mag, a.y * mag);
+            if (q & 1) v = make_float2(-v.y, v.x);          // times i
+            if (q & 2) v = make_float2(-v.x, -v.y);         // times -1
+            B[r].x += v.x; B[r].y += v.y;
+            mag *= tau2 / (float)(q + 1);
+        }
+        B[r].x /= rf; B[r].y /= rf;
+    }
+}
+
+// sum_r (i t3)^r B[r] (Horner).
+__device__ __forceinline__ float2 dw_level_c(const float2 (&B)[kMaxOrder + 1], int N, float tau3)
+{
+    float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int r = kMaxOrder; r >= 0; --r) {
+        if (r > N) continue;
+        acc = make_float2(B[r].x - tau3 * acc.y, B[r].y + tau3 * acc.x);
+    }
+    return acc;
+}
+
+// DW: the sites carry Debye-Waller factors T_mu(G) (Eq. dw); each site is then taken
+// on its own at level C instead of summed into its class first.
+template <int HC, bool DW>
 __global__ __launch_bounds__(512) void k_recombine_magnetic(RecombParams P)
 {
     extern __shared__ float2 smem[];
@@ -811,6 +874,7 @@ __global__ __launch_bounds__(512) void k_recombine_magnetic(RecombParams P)
     float2* Bs = smem;                    // [sites of the chunk][3][n3]
     float2* Xs = smem + P.bs_elems;       // [2][sites of the chunk][3][nh] staging
     float2* tHs = Xs + P.xs_elems;        // [nclass][nH3span]
+    float2* dwA = tHs + P.nclass * P.nH3span;   // DW: [S][pairs]
     const float2* tH0 = stage_class_phases(P, tHs);
     const int n1 = P.n1, n2 = P.n2, n3 = P.n3, nh = P.nh;
     const int SFnh = P.SF * nh;
@@ -837,6 +901,9 @@ __global__ __launch_bounds__(512) void k_recombine_magnetic(RecombParams P)
     const float q12y = g1 * P.recip[1] + g2 * P.recip[4];
     const float q12z = g1 * P.recip[2] + g2 * P.recip[5];
     const float inv16pi2 = 1.f / (16.f * 9.8696044010893586f);
+    const int Ndw = DW ? P.dw_order : 0;
+    const float tau2 = (float)(6.283185307179586 * (double)G2 / (double)n2);
+    if constexpr (DW) dw_level_a(P, 6.283185307179586 * (double)w.G1 / (double)n1, dwA);
 
     float I[HC];
 #pragma unroll
@@ -879,8 +946,9 @@ __global__ __launch_bounds__(512) void k_recombine_magnetic(RecombParams P)
                 int sp = s0;
                 while (sp < s1) {
                     const int c = P.class_of[sp];
+                    // a class at once, or (DW) one site at a time
                     int se = sp + 1;
-                    while (se < s1 && P.class_of[se] == c) ++se;
+                    while (!DW && se < s1 && P.class_of[se] == c) ++se;
                     float2 D[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
                     for (int sl = sp - s0; sl < se - s0; ++sl) {
                         const int mu = P.site_of[s0 + sl];
@@ -894,6 +962,8 @@ __global__ __launch_bounds__(512) void k_recombine_magnetic(RecombParams P)
                             D[comp].y += v.y;
                         }
                     }
+                    float2 Bdw[kMaxOrder + 1];
+                    if constexpr (DW) dw_level_b(dwA + (size_t)P.site_of[sp] * n_pairs(Ndw), Ndw, tau2, Bdw);
                     const float2* tH = tH0 + (size_t)c * P.nH3span;
                     const float* ffc = P.ff[sp];
 #pragma unroll
@@ -907,6 +977,10 @@ __global__ __launch_bounds__(512) void k_recombine_magnetic(RecombParams P)
                                             qz = q12z + g3 * P.recip[8];
                                 const float f = mag_ff(ffc, (qx * qx + qy * qy + qz * qz) * inv16pi2);
                                 e3.x *= f; e3.y *= f;
+                            }
+                            if constexpr (DW) {
+                                const float tau3 = 6.283185307f * ((float)(k3 + n3 * H3) / (float)n3);
+                                e3 = cmulf(e3, dw_level_c(Bdw, Ndw, tau3));
                             }
 #pragma unroll
                             for (int comp = 0; comp < 3; ++comp) {
@@ -1040,13 +1114,20 @@ hipError_t launch_recombine_nuclear(const RecombParams& p, int order, int hc, in
     }
 }
 
+template <int HC, bool DW>
+static hipError_t launch_mag_v(const RecombParams& p, int block, size_t lds, hipStream_t st)
+{
+    hipError_t e = set_lds(k_recombine_magnetic<HC, DW>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_recombine_magnetic<HC, DW>), dim3(p.nwork), dim3(block), lds, st, p);
+    return hipGetLastError();
+}
+
 template <int HC>
 static hipError_t launch_mag(const RecombParams& p, int block, size_t lds, hipStream_t st)
 {
-    hipError_t e = set_lds(k_recombine_magnetic<HC>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_recombine_magnetic<HC>), dim3(p.nwork), dim3(block), lds, st, p);
-    return hipGetLastError();
+    return (p.dwc && p.dw_order > 0) ? launch_mag_v<HC, true>(p, block, lds, st)
+                                     : launch_mag_v<HC, false>(p, block, lds, st);
 }
 
 hipError_t launch_recombine_magnetic(const RecombParams& p, int hc, int block, size_t lds,
@@ -1110,9 +1191,7 @@ __global__ __launch_bounds__(64) void k_bragg_nuclear(BraggParams P)
         double wgt = sd[3];
         if (P.has_ff) {
             const double* f = sd + 4;
-            double ffv = f[0] * exp(-f[1] * s2) + f[2] * exp(-f[3] * s2) + f[4] * exp(-f[5] * s2) + f[6];
-            if (f[7] != 0.0) ffv *= exp(-f[7] * s2);
-            wgt *= ffv;
+            wgt *= f[0] * exp(-f[1] * s2) + f[2] * exp(-f[3] * s2) + f[4] * exp(-f[5] * s2) + f[6];
         }
         Wr[mu] = wgt * cs;
         Wi[mu] = wgt * sn;
@@ -1152,8 +1231,26 @@ __global__ __launch_bounds__(64) void k_bragg_nuclear(BraggParams P)
 }
 
 __device__ double mag_ff_d(const double* f, double s2) {
-    const double ff = f[0] * exp(-f[1] * s2) + f[2] * exp(-f[3] * s2) + f[4] * exp(-f[5] * s2) + f[6];
-    return f[7] == 0.0 ? ff : ff * exp(-f[7] * s2);
+    return f[0] * exp(-f[1] * s2) + f[2] * exp(-f[3] * s2) + f[4] * exp(-f[5] * s2) + f[6];
+}
+
+// T_mu(H) of Eq. dw in float64: sum_t (2 pi i)^{p+q+r} H1^p H2^q H3^r / (p! q! r!) dwc[t].
+__device__ void dw_at_h(const BraggParams& P, const int H[3], int mu, double& tr, double& ti)
+{
+    const double* c = P.dwc + (size_t)mu * P.dwT;
+    tr = 0.0; ti = 0.0;
+    for (int t = 0; t < P.dwT; ++t) {
+        const int e[3] = {P.mono[3 * t], P.mono[3 * t + 1], P.mono[3 * t + 2]};
+        double mag = c[t];
+        for (int a = 0; a < 3; ++a)
+            for (int k = 1; k <= e[a]; ++k) mag *= 6.283185307179586476925 * H[a] / k;
+        switch ((e[0] + e[1] + e[2]) & 3) {
+            case 0: tr += mag; break;
+            case 1: ti += mag; break;
+            case 2: tr -= mag; break;
+            default: ti -= mag; break;
+        }
+    }
 }
 
 __global__ __launch_bounds__(256) void k_bragg_magnetic(BraggParams P)
@@ -1182,11 +1279,19 @@ __global__ __launch_bounds__(256) void k_bragg_magnetic(BraggParams P)
             double sn, cs;
             sincos(6.283185307179586476925 * x, &sn, &cs);
             const double f = P.has_ff ? mag_ff_d(sd + 4, s2) : 1.0;
+            // b f T e^{2 pi i H.r}
+            double wr = sd[3] * f * cs, wi = sd[3] * f * sn;
+            if (P.dwc) {
+                double tr, ti;
+                dw_at_h(P, H, mu, tr, ti);
+                const double xr = wr * tr - wi * ti;
+                wi = wr * ti + wi * tr;
+                wr = xr;
+            }
             const double* Sm = P.sums + ((size_t)m * P.S + mu) * 3;
             for (int c = 0; c < 3; ++c) {
-                const double w = sd[3] * f * Sm[c];
-                fr[c] += w * cs;
-                fi[c] += w * sn;
+                fr[c] += Sm[c] * wr;
+                fi[c] += Sm[c] * wi;
             }
         }
         const double pr = e[0] * fr[0] + e[1] * fr[1] + e[2] * fr[2];
@@ -1234,6 +1339,29 @@ hipError_t launch_bragg(const BraggParams& p, int order, hipStream_t st)
         case 8: return launch_bragg_t<8>(p, grid, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+// Debye-Waller means of Eq. dw: one thread per (site, monomial), configurations summed
+// in order.
+__global__ __launch_bounds__(256) void k_dw_mean(const double* sums, double* dwc, int M, int S, int T)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= S * T) return;
+    const int mu = idx / T, t = idx - mu * T;
+    double num = 0.0, den = 0.0;
+    for (int m = 0; m < M; ++m) {
+        const double* sm = sums + ((size_t)m * S + mu) * T;
+        num += sm[t];
+        den += sm[0];
+    }
+    dwc[idx] = den != 0.0 ? num / den : 0.0;
+}
+
+hipError_t launch_dw_mean(const double* sums, double* dwc, int M, int S, int T, hipStream_t st)
+{
+    const int tot = S * T;
+    hipLaunchKernelGGL(k_dw_mean, dim3((tot + 255) / 256), dim3(256), 0, st, sums, dwc, M, S, T);
+    return hipGetLastError();
 }
 
 }  // namespace dsx

@@ -64,6 +64,25 @@ def rel_l2(a, ref):
     return float(np.linalg.norm(a - ref) / np.linalg.norm(ref))
 
 
+def max_rel(a, ref):
+    """Worst voxel: max |a - ref| / max |ref|."""
+    a = np.asarray(a, dtype=np.float64).ravel()
+    ref = np.asarray(ref, dtype=np.float64).ravel()
+    return float(np.max(np.abs(a - ref)) / np.max(np.abs(ref)))
+
+
+# The parity bar: relative L2 over every compared voxel <= 1e-5 (float32 FFTs and
+# recombination against the float64 oracle), and the worst voxel within 1e-5 of the
+# largest reference value.
+TOL = 1e-5
+MAXTOL = 1e-5
+
+
+def assert_parity(a, ref, tol=TOL, maxtol=MAXTOL, what=""):
+    e, w = rel_l2(a, ref), max_rel(a, ref)
+    assert e <= tol and w <= maxtol, f"{what} rel L2 {e:.3e} (<= {tol:.0e}), worst voxel {w:.3e} (<= {maxtol:.0e})"
+
+
 def discrete_displacement_model(seed, n=(4, 3, 5), S=2, M=2, K=3, amp=0.03, with_occ=True):
     """A nuclear model whose displacements take K values per site (a split-site case)."""
     import synth

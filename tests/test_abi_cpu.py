@@ -57,6 +57,12 @@ def test_magnetic_plan_and_classes():
                           kind=dsx.MAGNETIC, ff=np.tile(synth.MAG_FF, (16, 1)))
     assert info.fields_per_site == 3
     assert info.n_classes == 4                       # r_mu3 in {0, 1/4, 1/2, 3/4}
+    # displacements of a magnetic model only feed its Debye-Waller factor (Eq. dw): still
+    # three transforms per site, plus the resident displacements and their lattice sums
+    dw = dsx.plan_query(cell=[10, 10, 10, 90, 90, 90], n=(24, 24, 24), frac=pyro, b=np.ones(16),
+                        kind=dsx.MAGNETIC, ff=np.tile(synth.MAG_FF, (16, 1)), taylor_order=4)
+    assert dw.fields_per_site == 3 and dw.spectrum_bytes == info.spectrum_bytes
+    assert dw.device_bytes >= info.device_bytes + 16 * 24 ** 3 * 12
 
 
 @pytest.mark.parametrize("kw,status", [
@@ -67,7 +73,6 @@ def test_magnetic_plan_and_classes():
     (dict(n_configs=0), dsx.ERR_ARG),
     (dict(cell=[1, 1, 1, 90, 90, 200]), dsx.ERR_ARG),
     (dict(cell=[0, 1, 1, 90, 90, 90]), dsx.ERR_ARG),
-    (dict(kind=dsx.MAGNETIC, taylor_order=2), dsx.ERR_UNSUPPORTED),
     (dict(kind=7), dsx.ERR_ARG),
     (dict(taylor_order=0, has_occ=False), dsx.ERR_ARG),
     (dict(norm_N=-1.0), dsx.ERR_ARG),
@@ -169,3 +174,34 @@ def test_profile_select_arguments():
     assert e.value.status == dsx.ERR_ARG
     dsx.profile_reset()
     assert dsx.profile_read() == {}
+
+
+# ------------------------------------------------------------------ binding argument checks
+
+def test_outputs_are_written_in_place_never_copied():
+    """An output the library could only fill through a temporary copy is refused."""
+    ok = np.zeros((3, 4), dtype=np.float32)
+    p, where = dsx._ptr_out(ok, 12)
+    assert p == ok.ctypes.data and where == dsx.HOST
+    for bad in (np.zeros((3, 4)), np.zeros((4, 3), dtype=np.float32).T, np.zeros(24, dtype=np.float32)[::2]):
+        with pytest.raises(ValueError):
+            dsx._ptr_out(bad)
+    ro = np.zeros(5, dtype=np.float32)
+    ro.flags.writeable = False
+    with pytest.raises(ValueError):
+        dsx._ptr_out(ro)
+
+
+def test_array_sizes_are_checked_before_the_call():
+    with pytest.raises(ValueError):
+        dsx._ptr_out(np.zeros(11, dtype=np.float32), 12)
+    with pytest.raises(ValueError):
+        dsx._ptr_where(np.zeros((2, 5)), 11)
+    p, where, keep = dsx._ptr_where(np.zeros((2, 5)), 10)    # inputs may be converted
+    assert keep.dtype == np.float32 and where == dsx.HOST
+
+
+def test_point_filter_output_must_hold_every_point():
+    # checked in the binding, before the library is called (no model is needed)
+    with pytest.raises(ValueError):
+        dsx.filter_points(0, 2, np.zeros((3, 3)), np.zeros(2, dtype=np.float32))

@@ -9,7 +9,7 @@ import pytest
 
 import synth
 from oracle import oracle as O
-from tests.helpers import rel_l2, to_dsx
+from tests.helpers import assert_parity, max_rel, MAXTOL, rel_l2, to_dsx
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
@@ -55,16 +55,15 @@ def test_displacive_fcc_32_full_box(order):
     assert np.all(np.isfinite(I))
     G = sample_points(m, 768, order)
     ref = O.intensity(m, G, order)
-    err = rel_l2(at(I, m, G), ref)
-    print("sampled rel L2 vs same-order oracle", err)
-    assert err <= TOL
+    print("sampled rel L2 vs same-order oracle", rel_l2(at(I, m, G), ref), "worst voxel", max_rel(at(I, m, G), ref))
+    assert_parity(at(I, m, G), ref)
     # Friedel symmetry over the whole (symmetric) box
-    assert rel_l2(I, I[::-1, ::-1, ::-1]) <= TOL
+    assert_parity(I, I[::-1, ::-1, ::-1])
     # one configuration: no diffuse intensity at G = 0 (mod n)
     assert np.max(np.abs(I[::32, ::32, ::32])) <= 1e-6 * np.max(I)
     if order == 8:   # truncation below float32 resolution: matches the exact exponential too
         ex = O.intensity(m, G[:256], -1)
-        assert rel_l2(at(I, m, G[:256]), ex) <= TOL
+        assert_parity(at(I, m, G[:256]), ex)
 
 
 def test_magnetic_pyrochlore_24_full_box():
@@ -74,10 +73,9 @@ def test_magnetic_pyrochlore_24_full_box():
     assert np.all(np.isfinite(I)) and np.all(I >= -1e-6 * I.max())
     G = sample_points(m, 512, 3)
     ref = O.intensity(m, G)
-    err = rel_l2(at(I, m, G), ref)
-    print("sampled rel L2", err)
-    assert err <= TOL
-    assert rel_l2(I, I[::-1, ::-1, ::-1]) <= TOL
+    print("sampled rel L2", rel_l2(at(I, m, G), ref), "worst voxel", max_rel(at(I, m, G), ref))
+    assert_parity(at(I, m, G), ref)
+    assert_parity(I, I[::-1, ::-1, ::-1])
 
 
 @pytest.mark.parametrize("mi", [0, 1, 2, 3])
@@ -88,7 +86,7 @@ def test_ensemble_members(mi):
     I = run_full(m)
     G = sample_points(m, 256, 40 + mi)
     ref = O.intensity(m, G)
-    assert rel_l2(at(I, m, G), ref) <= TOL
+    assert_parity(at(I, m, G), ref)
 
 
 def test_compositional_filter_full_box():
@@ -100,5 +98,5 @@ def test_compositional_filter_full_box():
     h.noise_filter(2, 1, out)
     torch.cuda.synchronize()
     ref = O.filtered_intensity(m, 2, 1)
-    assert rel_l2(out.cpu().numpy(), ref) <= TOL
+    assert_parity(out.cpu().numpy(), ref)
     h.close()

@@ -8,7 +8,7 @@ import pytest
 
 import synth
 from oracle import oracle as O
-from tests.helpers import desc_kwargs, rel_l2, to_dsx
+from tests.helpers import assert_parity, max_rel, MAXTOL, desc_kwargs, rel_l2, to_dsx
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
@@ -111,7 +111,7 @@ def test_alone_equals_mix_and_oracle():
             continue
         m = with_sites(models[i], variant_sites(models[i], 10 * i + v))
         exp = O.filtered_intensity(m, lm, 1) if lm else O.intensity(m).reshape(m.count)
-        assert rel_l2(alone[(i, v, lm)].numpy(), exp) <= TOL, (i, v, lm)
+        assert_parity(alone[(i, v, lm)].numpy(), exp, what=str((i, v, lm)))
     srv.close()
 
 
