@@ -186,6 +186,29 @@ dsx_status dsx_set_grid(dsx_model m, const int32_t g0[3], const int32_t count[3]
 dsx_status dsx_compute_intensity(dsx_model m, float* out, int32_t where, void* hip_stream);
 
 /*
+ * dsx_compute_intensity for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving or refinement loops, harnesses that forbid it.
+ * Same result and output rules as dsx_compute_intensity with where = DSX_DEVICE
+ * (out: device pointer; asynchronous on hip_stream, NULL = the null stream), bit for
+ * bit.  The call allocates nothing: it uses the model's resident state and the box's
+ * phase tables, which dsx_set_grid prepares, and a device scratch array of
+ * DSX_NOALLOC_SCRATCH_BYTES bytes, one per device, held from the first call on that
+ * device until the process ends, for the spectra and partial lattice sums
+ * (spectrum_bytes + the partial sums, each rounded up to 256 bytes, of
+ * dsx_plan_query's model; every byte is written before it is read, so nothing is
+ * cleared).  Every call on a device shares that device's scratch: calls that overlap
+ * on one device (different streams, or threads) race and must be serialised by the
+ * caller.  The model's own spectra are left stale (the next dsx_compute_intensity
+ * recomputes them).  Errors: DSX_ERR_UNSUPPORTED when the spectra and partial sums
+ * exceed the scratch; DSX_ERR_STATE when sites or grid are missing or the grid's
+ * tables are not resident (dsx_compute_intensity then reports why); DSX_ERR_ARG when
+ * the current device is not the model's.  With dsx_profile_enable on, the
+ * instrumentation creates HIP events.
+ */
+#define DSX_NOALLOC_SCRATCH_BYTES (96 * 1024 * 1024)
+dsx_status dsx_compute_intensity_noalloc(dsx_model m, float* out, void* hip_stream);
+
+/*
  * Lanczos resampling of I on the box (Sec. V.B, Eqs. intensity_convol_finite,
  * windowed_sinc, lanczos): I(Q) = sum_G I(G) W(Q-G) / sum_G W(Q-G), W the product
  * over axes of sinc(2 pi r_cut d) sinc(pi d/m) for |d| < m, r_cut = (1 - 1/m)/2,

@@ -19,6 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdsx.so")
 
 NUCLEAR, MAGNETIC = 0, 1
+NOALLOC_SCRATCH_BYTES = 96 * 1024 * 1024
 HOST, DEVICE = 0, 1
 OK, ERR_ARG, ERR_STATE, ERR_NOMEM, ERR_DEVICE, ERR_UNSUPPORTED, ERR_BUSY = 0, -1, -2, -3, -4, -5, -6
 MAX_N, MAX_SITES, MAX_ORDER = 128, 64, 8
@@ -48,7 +49,7 @@ class KernelStat(ctypes.Structure):
 
 
 EXPORTS = ("dsx_plan_query", "dsx_create_model", "dsx_set_sites", "dsx_set_sites_async", "dsx_set_grid",
-           "dsx_compute_intensity", "dsx_noise_filter", "dsx_destroy_model", "dsx_last_error",
+           "dsx_compute_intensity", "dsx_compute_intensity_noalloc", "dsx_noise_filter", "dsx_destroy_model", "dsx_last_error",
            "dsx_version", "dsx_profile_enable", "dsx_profile_select", "dsx_profile_read", "dsx_profile_reset",
            "dsx_noise_filter_cutoff", "dsx_filter_points", "dsx_split_sites", "dsx_noise_filter_spherical",
            "dsx_batch_create", "dsx_batch_run", "dsx_batch_destroy", "dsx_autotune", "dsx_tune_query",
@@ -92,6 +93,8 @@ def lib():
         L.dsx_set_sites_async.restype = i32
         L.dsx_set_grid.argtypes = [P, P, P]
         L.dsx_compute_intensity.argtypes = [P, P, i32, P]
+        L.dsx_compute_intensity_noalloc.argtypes = [P, P, P]
+        L.dsx_compute_intensity_noalloc.restype = i32
         L.dsx_noise_filter.argtypes = [P, i32, i32, P, i32, P]
         L.dsx_noise_filter_cutoff.argtypes = [P, i32, i32, i32, P, i32, P]
         L.dsx_noise_filter_cutoff.restype = i32
@@ -131,7 +134,7 @@ def lib():
                   "dsx_server_stats_read", "dsx_server_destroy"):
             getattr(L, f).restype = i32
         for f in ("dsx_plan_query", "dsx_create_model", "dsx_set_sites", "dsx_set_grid",
-                  "dsx_compute_intensity", "dsx_noise_filter", "dsx_destroy_model"):
+                  "dsx_compute_intensity", "dsx_compute_intensity_noalloc", "dsx_noise_filter", "dsx_destroy_model"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -258,6 +261,16 @@ def compute_intensity(model, out, stream=None, nelem=None):
     p, where = _ptr_out(out, nelem)
     st = _stream_handle(stream) if where == DEVICE else None
     _check(lib().dsx_compute_intensity(model, p, where, st))
+    return out
+
+
+def compute_intensity_noalloc(model, out, stream=None, nelem=None):
+    """dsx_compute_intensity_noalloc: the same I(G) into a device tensor, allocating
+    nothing (device scratch shared by every such call on the device)."""
+    p, where = _ptr_out(out, nelem)
+    if where != DEVICE:
+        raise ValueError("compute_intensity_noalloc writes device memory only")
+    _check(lib().dsx_compute_intensity_noalloc(model, p, _stream_handle(stream)))
     return out
 
 
@@ -429,6 +442,9 @@ class Model:
 
     def compute_intensity(self, out, stream=None):
         return compute_intensity(self.handle, out, stream, nelem=self._box_voxels())
+
+    def compute_intensity_noalloc(self, out, stream=None):
+        return compute_intensity_noalloc(self.handle, out, stream, nelem=self._box_voxels())
 
     def noise_filter(self, lanczos_m, oversample, out, stream=None):
         return noise_filter(self.handle, lanczos_m, oversample, out, stream,

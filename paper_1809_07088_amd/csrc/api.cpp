@@ -401,11 +401,14 @@ dsx_status tables_for(dsx_model m, const Box& bx, DeviceTables** out)
     auto it = m->tables.find(bx);
     if (it != m->tables.end()) { *out = &it->second; return DSX_OK; }
     if (m->tables.size() >= 8 && m->pins == 0) {   // keep the cache small: drop every cached box
-        // (never while a recorded batch still points at a cached table)
+        // but the grid's own (never while a recorded batch still points at a cached table)
         hipError_t se = hipStreamSynchronize(m->last_stream);
         if (se != hipSuccess) { m->failed = true; return fail(DSX_ERR_DEVICE, hipGetErrorString(se)); }
-        for (auto& kv : m->tables) free_tables(kv.second);
-        m->tables.clear();
+        for (auto it = m->tables.begin(); it != m->tables.end();) {
+            if (m->grid_set && !(it->first < m->box) && !(m->box < it->first)) { ++it; continue; }
+            free_tables(it->second);
+            it = m->tables.erase(it);
+        }
     }
     DeviceTables t;
     const int S = m->S, n1 = m->n[0], n2 = m->n[1], n3 = m->n[2];
@@ -1106,6 +1109,14 @@ dsx_status dsx_set_grid(dsx_model m, const int32_t g0[3], const int32_t count[3]
     if (vox > (1LL << 34)) return fail(DSX_ERR_UNSUPPORTED, "box too large");
     m->box = bx;
     m->grid_set = true;
+    // prepare the box's phase tables now, so that a compute call that may not allocate
+    // finds them; a box the recombination cannot take is still reported by the compute
+    // calls, as before
+    DeviceTables* tb = nullptr;
+    if (tables_for(m, bx, &tb) != DSX_OK) {
+        if (m->failed) return DSX_ERR_DEVICE;
+        g_err.clear();
+    }
     return DSX_OK;
 }
 
@@ -1128,6 +1139,75 @@ dsx_status dsx_compute_intensity(dsx_model m, float* out, int32_t where, void* h
         HIPCHK(m, hipStreamSynchronize(st));
     }
     return DSX_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------- no allocation
+// Device scratch of dsx_compute_intensity_noalloc: the spectra and the partial lattice
+// sums of one call.  Every device the library runs on holds its own copy until the
+// process ends; host code reaches it only through the address hipGetSymbolAddress
+// returns for the current device (the array's name is a host-side stand-in there).
+static __device__ __align__(256) unsigned char scratch[DSX_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, unsigned char*> g_scratch_at;   // device -> its copy of `scratch`
+
+dsx_status scratch_on(int dev, unsigned char** out)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_at.find(dev);
+    if (it == g_scratch_at.end()) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(DSX_ERR_DEVICE, std::string("scratch address: ") + hipGetErrorString(e));
+        it = g_scratch_at.emplace(dev, static_cast<unsigned char*>(p)).first;
+    }
+    *out = it->second;
+    return DSX_OK;
+}
+
+size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+}  // namespace
+
+extern "C" {
+
+dsx_status dsx_compute_intensity_noalloc(dsx_model m, float* out, void* hip_stream)
+{
+    dsx_status s = check_direct(m);
+    if (s != DSX_OK) return s;
+    if (!out) return fail(DSX_ERR_ARG, "out is NULL");
+    if ((s = ready(m)) != DSX_OK) return s;
+    int dev = -1;
+    HIPCHK(m, hipGetDevice(&dev));
+    if (dev != m->device) return fail(DSX_ERR_ARG, "the current device is not the model's device");
+    const size_t xb = round256(m->spectrum_bytes), pb = round256(m->partial_bytes);
+    if (xb + pb > (size_t)DSX_NOALLOC_SCRATCH_BYTES)
+        return fail(DSX_ERR_UNSUPPORTED, "spectra and partial sums (" + std::to_string(xb + pb) +
+                                         " bytes) exceed the " + std::to_string(DSX_NOALLOC_SCRATCH_BYTES) +
+                                         "-byte scratch of dsx_compute_intensity_noalloc");
+    if (!m->tables.count(m->box))
+        return fail(DSX_ERR_STATE, "the grid's phase tables are not resident: dsx_set_grid prepares them "
+                                   "(dsx_compute_intensity reports why it could not)");
+    unsigned char* base = nullptr;
+    if ((s = scratch_on(dev, &base)) != DSX_OK) return s;
+    hipStream_t st = (hipStream_t)hip_stream;
+    if ((s = follow(m, st)) != DSX_OK) return s;
+    // the whole chain reads and writes the scratch in place of the model's own spectra
+    // and partial sums; every element is written before it is read
+    float2* own_x = m->d_X;
+    double* own_p = m->d_partial;
+    m->d_X = reinterpret_cast<float2*>(base);
+    m->d_partial = reinterpret_cast<double*>(base + xb);
+    s = enqueue_intensity(m, out, st, true);
+    m->d_X = own_x;
+    m->d_partial = own_p;
+    m->dirty = true;     // the model's own spectra were not refreshed
+    return s;
 }
 
 }  // extern "C"
