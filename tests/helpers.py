@@ -104,3 +104,59 @@ def split_model(model, tol=0.0):
     s.pos_id = (parent if model.pos_id is None else np.asarray(model.pos_id)[parent]).astype(np.int32)
     s.norm_N = O.norm_N(model)
     return s
+
+
+# ----------------------------------------------------------------- sampled filtered outputs
+
+def edge_sample_indices(count, k, seed, edges=None):
+    """k output indices (i1, i2, i3) of a box of `count` voxels, drawn so that most
+    coordinates sit on the places a tiled, half-stored filter treats specially: the
+    box faces, both sides of the mirror plane, and both sides of tile and segment
+    boundaries (multiples of 4, 8, 12, 16, 32, 64 and their mirrors), the rest uniform."""
+    rng = np.random.default_rng(seed)
+    out = np.empty((k, 3), dtype=np.int64)
+    for a in range(3):
+        c = int(count[a])
+        cand = {0, 1, c - 2, c - 1, c // 2 - 1, c // 2, c // 2 + 1}
+        for t in (4, 8, 12, 16, 32, 64):
+            for b in range(t, c, t):
+                cand.update({b - 1, b, c - 1 - b, c - b})
+        if edges:
+            cand.update(edges[a])
+        cand = np.array(sorted(v for v in cand if 0 <= v < c))
+        pick = rng.random(k) < 0.75
+        out[:, a] = np.where(pick, cand[rng.integers(0, len(cand), k)], rng.integers(0, c, k))
+    return out
+
+
+def oracle_windows(model, Q, w, order=None):
+    """I(G) by the oracle's direct sum on the (2w)^3 window [floor(Q_a) - w + 1,
+    floor(Q_a) + w] of every point Q [k][3]: (windows [k][2w][2w][2w], their origins
+    [k][3]).  Every G shared by several windows is summed once."""
+    from oracle import oracle as O
+    Q = np.asarray(Q, dtype=np.float64).reshape(-1, 3)
+    e0 = np.floor(Q).astype(np.int64) - w + 1
+    off = np.stack(np.meshgrid(*[np.arange(2 * w)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    allG = (e0[:, None, :] + off[None, :, :]).reshape(-1, 3)
+    Gu, inv = np.unique(allG, axis=0, return_inverse=True)
+    Iu = O.intensity(model, Gu.astype(np.int32), order)
+    return Iu[inv.ravel()].reshape(len(Q), 2 * w, 2 * w, 2 * w), e0.astype(np.int32)
+
+
+def oracle_filtered_at(model, Q, m, mprime=2, spherical=False, order=None):
+    """The oracle's filtered intensity at the points Q [k][3] (units of the supercell
+    Bragg grid): I(G) on each window by direct sum, then the oracle's windowed sum
+    (Sec. V.B) -- the separable weights with the m' cutoff, or the spherical W_r."""
+    from oracle import oracle as O
+    Q = np.asarray(Q, dtype=np.float64).reshape(-1, 3)
+    w = m if spherical else O.window_halfwidth(m, mprime)
+    win, e0 = oracle_windows(model, Q, w, order)
+    out = np.empty(len(Q))
+    for i in range(len(Q)):
+        if spherical:
+            q0 = np.floor(Q[i]).astype(np.int32)
+            assert np.all(q0 == Q[i]), "the spherical filter is sampled on the G grid"
+            out[i] = O.lanczos_spherical(win[i], e0[i], m, 1, q0, (1, 1, 1), model.cell, model.n)[0, 0, 0]
+        else:
+            out[i] = O.lanczos_points(win[i], e0[i], m, Q[i:i + 1], mprime)[0]
+    return out

@@ -8,7 +8,7 @@ import pytest
 
 import synth
 from oracle import oracle as O
-from tests.helpers import assert_parity, max_rel, MAXTOL, desc_kwargs, rel_l2, to_dsx
+from tests.helpers import edge_sample_indices, oracle_filtered_at, assert_parity, max_rel, MAXTOL, desc_kwargs, rel_l2, to_dsx
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
@@ -105,13 +105,18 @@ def test_alone_equals_mix_and_oracle():
     torch.cuda.synchronize()
     assert torch.equal(ref.cpu(), alone[(i, v, 0)])
     plain.close()
-    # FP64 oracle on the small models
+    # FP64 oracle: whole boxes of the small models, sampled voxels of the larger ones
     for (i, v, lm) in jobs:
-        if models[i].n[0] > 8:
-            continue
         m = with_sites(models[i], variant_sites(models[i], 10 * i + v))
-        exp = O.filtered_intensity(m, lm, 1) if lm else O.intensity(m).reshape(m.count)
-        assert_parity(alone[(i, v, lm)].numpy(), exp, what=str((i, v, lm)))
+        got = alone[(i, v, lm)].numpy()
+        if m.n[0] <= 8:
+            exp = O.filtered_intensity(m, lm, 1) if lm else O.intensity(m).reshape(m.count)
+            assert_parity(got, exp, what=str((i, v, lm)))
+            continue
+        idx = edge_sample_indices(m.count, 128, 7 * i + v)
+        Q = idx + np.asarray(m.g0)
+        exp = oracle_filtered_at(m, Q, lm) if lm else O.intensity(m, Q.astype(np.int32))
+        assert_parity(got[tuple(idx.T)], exp, what=str((i, v, lm)))
     srv.close()
 
 

@@ -611,3 +611,16 @@ def test_spherical_cutoff_radius_in_real_space(m):
         assert response(0.3 * rc * u) > 0.9
         assert abs(response(rc * u) - 0.5) < 0.15
         assert abs(response(1.4 * rc * u)) < 0.06
+
+
+def test_sampled_windows_match_the_box_filter():
+    """The sampled check used at full size (I(G) on each output's own window, then the
+    windowed sum at that output) equals the oracle's filter of the whole box."""
+    from tests.helpers import edge_sample_indices, oracle_filtered_at
+    m = synth.random_model(5, n=(3, 4, 3), S=2, M=2, order=3)
+    m.g0, m.count = (-4, -5, -4), (9, 11, 9)
+    for mp, sph in [(2, False), (4, False), (2, True)]:
+        ref = O.filtered_intensity_spherical(m, 2) if sph else O.filtered_intensity(m, 2, 1, mprime=mp)
+        idx = edge_sample_indices(m.count, 40, 1)
+        got = oracle_filtered_at(m, idx + np.asarray(m.g0), 2, mp, sph)
+        assert np.allclose(got, ref[tuple(idx.T)], rtol=1e-13, atol=1e-15)
