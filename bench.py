@@ -124,6 +124,7 @@ def summarize_ktrace(trace_dir, out_md, command):
                 "per-kernel breakdown), i.e. the dispatches after the plain device copy used as the "
                 "PMC probe; the plan tuning and the warm-up before it are left out.  MI355X, one GPU.\n\nCommand (run from /tmp with "
                 "TMPDIR=/tmp, R = repository root):\n\n```\n%s\n```\n\n" % command)
+        f.write("Kernel sources: recombine.hip %s.\n\n" % kernel_source_hash())
         f.write("| kernel | calls | average (us) | min (us) | max (us) | share of GPU time |\n"
                 "|---|---|---|---|---|---|\n")
         for k in order:
@@ -131,6 +132,21 @@ def summarize_ktrace(trace_dir, out_md, command):
             f.write("| `%s` | %d | %.1f | %.1f | %.1f | %.2f %% |\n" % (
                 k, len(v), sum(v) / len(v) / 1e3, min(v) / 1e3, max(v) / 1e3, 100.0 * sum(v) / total))
     return len(order)
+
+
+def stored_trace_avg(kernel_substr):
+    """Average launch time (s) of a kernel in the committed kernel-trace summary, while
+    the recombination source it was taken with is unchanged."""
+    try:
+        txt = open(KTRACE_MD).read()
+    except OSError:
+        return None
+    if ("recombine.hip %s." % kernel_source_hash()) not in txt:
+        return None
+    for line in txt.splitlines():
+        if line.startswith("| `") and kernel_substr in line:
+            return float(line.split("|")[3]) * 1e-6
+    return None
 
 
 def stored_traffic():
@@ -144,7 +160,71 @@ def stored_traffic():
     rec = json.loads(m.group(1))
     return rec if rec.get("source_hash") == kernel_source_hash() else None
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-FP32_PEAK_TFLOPS = 157.3       # MI355X published FP32 vector peak
+FP32_PUBLISHED_TFLOPS = 157.3  # MI355X published FP32 vector peak: counts packed FP32 (two per lane)
+# The reachable FP32 vector peak of this build, which compiles without packed FP32:
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
+FP32_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+
+def roofline(flops, bytes_, t_launch, kernel, trace_avg_s=None):
+    """The roofline object of one kernel: the binding roof is whichever of the reachable
+    FP32 vector rate and HBM takes longer for the algorithmic flops and bytes; achieved
+    = algorithmic work per launch / the launch's HIP-event time (and, when given, the
+    rocprofv3 trace's average launch time)."""
+    tflops, gbs = flops / t_launch / 1e12, bytes_ / t_launch / 1e9
+    alu = flops / (FP32_VALU_TFLOPS * 1e12) > bytes_ / (HBM_PEAK_GBS * 1e9)
+    if alu:
+        roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": round(FP32_VALU_TFLOPS, 1),
+                "unit": "TFLOP/s", "frac": round(tflops / FP32_VALU_TFLOPS, 4)}
+    else:
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    roof["traffic"] = None
+    roof.update({"kernel": kernel, "launch_ms": round(t_launch * 1e3, 4),
+                 "algorithmic_flops_per_launch": int(flops), "algorithmic_bytes_per_launch": int(bytes_),
+                 "achieved_TFLOPs": round(tflops, 3), "achieved_hbm_GBs": round(gbs, 1),
+                 "frac_fp32_valu": round(tflops / FP32_VALU_TFLOPS, 4),
+                 "frac_fp32_published": round(tflops / FP32_PUBLISHED_TFLOPS, 4),
+                 "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)})
+    if trace_avg_s:
+        rate = (flops / trace_avg_s / 1e12 / FP32_VALU_TFLOPS) if alu else (bytes_ / trace_avg_s / 1e9 / HBM_PEAK_GBS)
+        roof["trace_launch_ms"] = round(trace_avg_s * 1e3, 4)
+        roof["frac_from_trace"] = round(rate, 4)
+    return roof
+
+
+def c15_report(G, gpu, ref, n):
+    """Error of the GPU result against the FP64 oracle at the points G: relative L2,
+    max |dI| / max |I_ref|, relative L2 per |g| shell (g = G/n, reciprocal-lattice
+    units, shells 2 wide) and the worst voxel."""
+    gpu = np.asarray(gpu, np.float64)
+    ref = np.asarray(ref, np.float64)
+    d = gpu - ref
+    gn = np.linalg.norm(np.asarray(G, np.float64) / np.asarray(n, np.float64), axis=1)
+    shells = {}
+    for lo in range(0, int(np.ceil(gn.max())) + 2, 2):
+        sel = (gn >= lo) & (gn < lo + 2)
+        if sel.any() and np.linalg.norm(ref[sel]) > 0:
+            shells[f"{lo}-{lo + 2}"] = float(np.linalg.norm(d[sel]) / np.linalg.norm(ref[sel]))
+    w = int(np.argmax(np.abs(d)))
+    return {"rel_l2": float(np.linalg.norm(d) / np.linalg.norm(ref)),
+            "max_abs_err_over_max_ref": float(np.max(np.abs(d)) / np.max(np.abs(ref))),
+            "rel_l2_by_g_shell": shells,
+            "worst_voxel": {"G": [int(v) for v in G[w]], "gpu": float(gpu[w]), "oracle": float(ref[w])},
+            "voxels": int(len(G))}
+
+
+def oracle_filtered_points(O, model, Q, m, order):
+    """The oracle's filtered intensity at integer output points Q: I(G) by direct sum
+    on each point's (2m)^3 window, then the oracle's windowed sum."""
+    Q = np.asarray(Q, np.int64)
+    off = np.stack(np.meshgrid(*[np.arange(2 * m)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    e0 = Q - m + 1
+    allG = (e0[:, None, :] + off[None]).reshape(-1, 3)
+    Gu, inv = np.unique(allG, axis=0, return_inverse=True)
+    win = O.intensity(model, Gu.astype(np.int32), order)[inv.ravel()].reshape(len(Q), 2 * m, 2 * m, 2 * m)
+    return np.array([O.lanczos_points(win[i], e0[i].astype(np.int32), m, Q[i:i + 1].astype(np.float64))[0]
+                     for i in range(len(Q))])
 
 
 def hcount(k, n, g0, cnt):
@@ -176,6 +256,171 @@ def recombine_work(n, S, nclass3, N, M, g0, cnt, nh, F, friedel=False):
     flops = M * (fl_a + fl_b + fl_c) * (0.5 if friedel else 1.0)
     bytes_ = 4 * V + M * n[0] * n[1] * S * F * nh * 8
     return flops, bytes_
+
+
+def magnetic_work(n, S, nclass3, M, g0, cnt, nh, friedel):
+    """Algorithmic flops and bytes of one magnetic recombination launch (spin spectra, one
+    form factor for every site):
+      level C  per voxel and r3 class: 3 complex multiply-adds (24); per voxel Q, its
+               direction, the perpendicular projection, |F_perp|^2 and f(|Q|)^2 (40)
+      level B  per (G1, G2, k3) and site: phase product (6) + 3 complex multiply-adds (24)
+      level A  per (G1, k2) column, site, component and k3: b e^{2 pi i g1 r1} times X (6)
+    bytes: float32 output written once + every half spin spectrum read once; halved
+    flops on a box symmetric about G = 0."""
+    V = int(np.prod(cnt))
+    items = sum(1 for k3 in range(n[2]) if hcount(k3, n[2], g0[2], cnt[2]) > 0) * cnt[0] * cnt[1]
+    cols = cnt[0] * sum(1 for k2 in range(n[1]) if hcount(k2, n[1], g0[1], cnt[1]) > 0)
+    flops = M * (V * (24 * nclass3 + 40) + items * S * 30 + cols * S * 3 * n[2] * 6) * (0.5 if friedel else 1.0)
+    bytes_ = 4 * V + M * n[0] * n[1] * S * 3 * nh * 8
+    return flops, bytes_
+
+
+def bench_magnetic(dsx, torch, dev, steps, warmup, O=None):
+    """The magnetic workload: pyrochlore, 16 sites, 24^3 supercell, unit spins with a
+    nearest-neighbour correlated component, magnetic form factor, perpendicular
+    projection, |h|,|k|,|l| <= 6 (289^3 voxels).  One step = set_sites_async (device copy)
+    + compute_intensity; the recombination is timed with HIP events on its stream."""
+    import synth
+    m = synth.magnetic(n=24, M=1, hmax=6)
+    count = tuple(m.count)
+    spin = torch.from_numpy(m.spin[0]).to(dev)
+    h = dsx.Model(cell=m.cell, n=m.n, frac=m.frac, b=m.b, kind=dsx.MAGNETIC, ff=m.ff, n_configs=1)
+    h.set_grid(m.g0, count)
+    h.set_sites_async(0, None, None, spin)
+    h.autotune(0)
+    out = torch.empty(count, dtype=torch.float32, device=dev)
+
+    def step():
+        h.set_sites_async(0, None, None, spin)
+        h.compute_intensity(out)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    dsx.profile_reset()
+    dsx.profile_select("recombine")
+    dsx.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    dsx.profile_enable(False)
+    ks = dsx.profile_read()
+    dsx.profile_reset()
+    dsx.profile_select(None)
+    launches, tot = ks.get("recombine", (0, float("nan")))
+    t_launch = tot / max(launches, 1) / 1e3
+    nclass3 = len(np.unique(m.frac[:, 2]))
+    flops, bytes_ = magnetic_work(m.n, m.n_sites, nclass3, 1, m.g0, count, m.n[2] // 2 + 1, friedel=True)
+    vox = int(np.prod(count))
+    res = {"workload": "magnetic pyrochlore 16 sites/cell, 24^3 supercell, unit spins (nearest-neighbour "
+                       "correlated), form factor (0.4,20,0.5,7,0.1,2,0), |h|,|k|,|l|<=6 (289^3 voxels)",
+           "voxels_per_step": vox, "ms_per_step": round(sec * 1e3, 4), "voxels_per_s": round(vox / sec, 1),
+           "roofline": roofline(flops, bytes_, t_launch, "recombine_magnetic", stored_trace_avg("k_recombine_magnetic"))}
+    if O is not None:
+        rng = np.random.default_rng([3, 0, 777])
+        G = np.stack([rng.integers(m.g0[a], m.g0[a] + count[a], 512) for a in range(3)], -1)
+        H = np.stack(np.meshgrid(*[np.arange(-6, 7, 3)] * 3, indexing="ij"), -1).reshape(-1, 3) * 24
+        G = np.concatenate([G, H]).astype(np.int32)
+        t = torch.as_tensor(G - np.asarray(m.g0), device=dev)
+        g = out[t[:, 0], t[:, 1], t[:, 2]].cpu().numpy()
+        res["parity"] = c15_report(G, g, O.intensity(m, G), m.n)
+    h.close()
+    return res
+
+
+def bench_compositional(dsx, torch, dev, steps, O=None, seeds=1024):
+    """The compositional workload: simple cubic, one site, 12^3 supercell, Bernoulli(0.5)
+    occupancies, 48^3 voxels (|h|,|k|,|l| < 2).  Single-instance latency of one
+    synchronous set_sites_async + compute_intensity, and throughput over `seeds`
+    configurations: (a) one model holding them as its ensemble (one FFT batch, one
+    recombination over configurations), (b) `seeds` independent models in one batch."""
+    import synth
+    base = synth.compositional(n=12, M=1, hmax=2)
+    count = tuple(base.count)
+    vox = int(np.prod(count))
+    occs = [torch.from_numpy((synth.rng_for(1, 0, s).random((1, 12, 12, 12)) < 0.5).astype(np.float32)).to(dev)
+            for s in range(seeds)]
+    desc = dict(cell=base.cell, n=base.n, frac=base.frac, b=base.b, taylor_order=0, has_occ=True)
+    # single instance
+    h = dsx.Model(**desc, n_configs=1)
+    h.set_grid(base.g0, count)
+    h.set_sites(0, occs[0])
+    out = torch.empty(count, dtype=torch.float32, device=dev)
+    lat = []
+    for i in range(steps + 10):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h.set_sites_async(0, occs[i % seeds])
+        h.compute_intensity(out)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+    lat = np.sort(np.array(lat[10:]))
+    res = {"workload": "compositional simple cubic, 12^3 supercell, Bernoulli(0.5), 48^3 voxels",
+           "voxels": vox,
+           "single_instance": {"p50_ms": round(float(np.median(lat)) * 1e3, 4),
+                               "p99_ms": round(float(lat[int(0.99 * (len(lat) - 1))]) * 1e3, 4),
+                               "voxels_per_s": round(vox / float(np.median(lat)), 1)}}
+    if O is not None:
+        m0 = synth.compositional(n=12, M=1, hmax=2)
+        m0.occ = occs[(steps + 9) % seeds].cpu().numpy()[None]
+        res["single_instance"]["parity"] = c15_report(O.grid_points(m0.g0, m0.count), out.cpu().numpy().ravel(),
+                                                      O.intensity(m0), m0.n)
+    h.close()
+    # (a) the seeds as one model's ensemble
+    he = dsx.Model(**desc, n_configs=seeds)
+    he.set_grid(base.g0, count)
+    for c in range(seeds):
+        he.set_sites(c, occs[c])
+    he.autotune(0)
+
+    def ens_step():
+        for c in range(seeds):
+            he.set_sites_async(c, occs[c])
+        he.compute_intensity(out)
+
+    ens_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(max(3, steps // 4)):
+        ens_step()
+    torch.cuda.synchronize()
+    te = (time.perf_counter() - t0) / max(3, steps // 4)
+    he.close()
+    res["ensemble_one_model"] = {"configurations": seeds, "ms_per_step": round(te * 1e3, 3),
+                                 "config_voxels_per_s": round(seeds * vox / te, 1),
+                                 "note": "step includes the stream-ordered upload of every configuration"}
+    # (b) independent models in one batch
+    hs, outs = [], []
+    for c in range(seeds):
+        hm = dsx.Model(**desc, n_configs=1)
+        hm.set_grid(base.g0, count)
+        hm.set_sites(0, occs[c])
+        hm.tune_set(0, 0, 12)
+        hs.append(hm)
+        outs.append(torch.empty(count, dtype=torch.float32, device=dev))
+    c0 = time.perf_counter()
+    batch = dsx.Batch(hs, outs)
+    t_create = time.perf_counter() - c0
+    batch.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(max(3, steps // 4)):
+        batch.run()
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / max(3, steps // 4)
+    res["batch_of_models"] = {"models": seeds, "ms_per_step": round(tb * 1e3, 3),
+                              "voxels_per_s": round(seeds * vox / tb, 1), "create_s": round(t_create, 2)}
+    if O is not None:
+        m1 = synth.compositional(n=12, M=1, hmax=2)
+        m1.occ = occs[seeds - 1].cpu().numpy()[None]
+        res["batch_of_models"]["parity_last_model"] = c15_report(
+            O.grid_points(m1.g0, m1.count), outs[-1].cpu().numpy().ravel(), O.intensity(m1), m1.n)
+    batch.close()
+    for hm in hs:
+        hm.close()
+    return res
 
 
 def bench_ensemble(dsx, torch, dev, steps, warmup, lm=2):
@@ -250,32 +495,42 @@ def bench_ensemble(dsx, torch, dev, steps, warmup, lm=2):
             "batched_equals_plain": bool(same)}
 
 
-def serving_pool(n_models=32, variants=2):
-    """Resident models of the serving workload and, per model, device-ready site variants."""
+def serving_pool(n_models=64, variants=4, frac=0.01):
+    """Resident models of the serving workload and, per model, device-ready site variants:
+    the model's own sites, and refinement moves that each change 1 % of its sites (an
+    occupancy flipped, a displacement or a spin drawn anew)."""
     import synth
     pool = [synth.serving_request_model(workload=5, model=i) for i in range(n_models)]
     sites = []
     for i, m in enumerate(pool):
-        vs = [(None if m.occ is None else m.occ[0], None if m.disp is None else m.disp[0],
-               None if m.spin is None else m.spin[0])]
+        base = (None if m.occ is None else m.occ[0], None if m.disp is None else m.disp[0],
+                None if m.spin is None else m.spin[0])
+        vs = [base]
         r = np.random.default_rng([5, i, 40_000])
+        S, nn = m.n_sites, tuple(m.n)
         for _ in range(variants - 1):
-            S, nn = m.n_sites, tuple(m.n)
-            if m.occ is not None:
-                vs.append(((r.random((S,) + nn) < 0.5).astype(np.float32), None, None))
-            elif m.disp is not None:
-                vs.append((None, synth.correlated_displacements(r, 1, S, nn)[0], None))
+            occ, disp, spin = (None if a is None else a.copy() for a in base)
+            nsite = S * int(np.prod(nn))
+            pick = r.choice(nsite, max(1, int(round(frac * nsite))), replace=False)
+            if occ is not None:
+                flat = occ.reshape(-1)
+                flat[pick] = 1.0 - flat[pick]
+            elif disp is not None:
+                flat = disp.reshape(-1, 3)
+                flat[pick] = r.normal(0.0, 0.004, (len(pick), 3)).astype(np.float32)
             else:
-                v = r.normal(size=(S,) + nn + (3,))
-                vs.append((None, None, (v / np.linalg.norm(v, axis=-1, keepdims=True)).astype(np.float32)))
+                flat = spin.reshape(-1, 3)
+                v = r.normal(size=(len(pick), 3))
+                flat[pick] = (v / np.linalg.norm(v, axis=-1, keepdims=True)).astype(np.float32)
+            vs.append((occ, disp, spin))
         sites.append(vs)
     return pool, sites
 
 
 def bench_serving(dsx, torch, dev, seconds, slots=4):
-    """Open-loop Poisson requests (200/s) over 32 resident models of the serving workload
+    """Open-loop Poisson requests (200/s) over 64 resident models of the serving workload
     (edge 8..64, 1-16 random sites, compositional / displacive order 6 / magnetic,
-    |h|,|k|,|l| <= 2): the server (continuous batching over `slots` streams, arena
+    |h|,|k|,|l| <= 2), each request a refinement move of 1 % of its model's sites: the server (continuous batching over `slots` streams, arena
     admission) against the plain path serving the same trace first come first served
     with one synchronous call at a time.  A burst of every request at once gives the
     saturated throughput of both."""
@@ -283,7 +538,7 @@ def bench_serving(dsx, torch, dev, seconds, slots=4):
     pool, sites = serving_pool()
     arrivals = synth.poisson_arrivals(rate=200.0, duration=seconds)
     pick = np.random.default_rng([5, 0, 50_000])
-    reqs = [(int(pick.integers(0, len(pool))), int(pick.integers(0, 2))) for _ in arrivals]
+    reqs = [(int(pick.integers(0, len(pool))), int(pick.integers(0, len(sites[0])))) for _ in arrivals]
     dsites = [[tuple(None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in v)
                for v in vs] for vs in sites]
     outs = [torch.empty(tuple(m.count), dtype=torch.float32, device=dev) for m in pool]
@@ -358,9 +613,9 @@ def bench_serving(dsx, torch, dev, seconds, slots=4):
     total_vox = sum(vox[i] for (i, _) in reqs)
     lat = np.sort(np.array(lat))
     pct = lambda p: float(lat[max(0, int(np.ceil(p * len(lat))) - 1)])
-    return {"workload": f"Poisson 200 req/s for {seconds:g} s ({len(reqs)} requests) over 32 resident "
+    return {"workload": f"Poisson 200 req/s for {seconds:g} s ({len(reqs)} requests) over {len(pool)} resident "
                         "models: edge U{8..64}, 1-16 sites, compositional / displacive (order 6) / "
-                        "magnetic, |h|,|k|,|l|<=2, new sites per request",
+                        "magnetic, |h|,|k|,|l|<=2, each request a refinement move of 1 % of its model's sites",
             "server": {"slots": slots, "voxels_per_s": round(open_srv["voxels"] / max(open_srv["span_s"], 1e-9), 1),
                        "p50_ms": round(open_srv["p50_ms"], 3), "p99_ms": round(open_srv["p99_ms"], 3),
                        "max_ms": round(open_srv["max_ms"], 3), "completed": open_srv["completed"],
@@ -405,6 +660,9 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the Poisson request trace of the serving comparison (0: skip)")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving comparison")
+    ap.add_argument("--magnetic-only", action="store_true",
+                    help="time only the magnetic workload (for kernel traces of its recombination)")
+    ap.add_argument("--compositional-only", action="store_true", help="time only the compositional workload")
     args = ap.parse_args()
     if args.summarize_ktrace:
         print(summarize_ktrace(args.summarize_ktrace, KTRACE_MD, args.pmc_command))
@@ -430,6 +688,12 @@ def main():
         return
     if args.serving_only:
         print(json.dumps({"serving": bench_serving(dsx, torch, dev, args.serve_seconds)}))
+        return
+    if args.magnetic_only:
+        print(json.dumps({"magnetic": bench_magnetic(dsx, torch, dev, args.steps, args.warmup)}))
+        return
+    if args.compositional_only:
+        print(json.dumps({"compositional": bench_compositional(dsx, torch, dev, args.steps)}))
         return
     N, lm = args.order, args.lanczos_m
     model = synth.displacive(n=32, M=1, order=N, hmax=8)
@@ -489,6 +753,14 @@ def main():
     dsx.profile_enable(False)
     kall = dsx.profile_read()
     dsx.profile_reset()
+    # sampled filtered outputs for the parity check (faces, mirror plane, tile edges)
+    rs = np.random.default_rng([2, 0, 778])
+    edges = [np.array(sorted({0, 1, 255, 256, 257, 511, 512} | {b + d for b in range(0, c, 32) for d in (-1, 0)}))
+             for c in count]
+    fidx = np.stack([np.where(rs.random(64) < 0.75, e[rs.integers(0, len(e), 64)], rs.integers(0, c, 64))
+                     for e, c in zip(edges, count)], -1).clip(0, np.asarray(count) - 1)
+    tidx = torch.as_tensor(fidx, device=dev)
+    F_gpu = out[tidx[:, 0], tidx[:, 1], tidx[:, 2]].cpu().numpy()
     sec = (t1 - t0) / args.steps
     value = voxels / sec
 
@@ -501,21 +773,10 @@ def main():
                                    info.fields_per_site, friedel=sym)
     launches, tot_ms = kstats.get("recombine", (0, float("nan")))
     t_launch = tot_ms / max(launches, 1) / 1e3
-    tflops = flops / t_launch / 1e12
-    gbs = bytes_ / t_launch / 1e9
-    alu_bound = flops / (FP32_PEAK_TFLOPS * 1e12) > bytes_ / (HBM_PEAK_GBS * 1e9)
-    if alu_bound:
-        roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(tflops / FP32_PEAK_TFLOPS, 4), "traffic": None}
-    else:
-        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None}
+    roof = roofline(flops, bytes_, t_launch, "recombine", stored_trace_avg("k_recombine"))
     tr = stored_traffic()
     if tr is not None:
         roof["traffic"] = int(tr["traffic_bytes"])
-    roof.update({"kernel": "recombine", "launch_ms": round(t_launch * 1e3, 4),
-                 "algorithmic_flops_per_launch": int(flops), "algorithmic_bytes_per_launch": int(bytes_),
-                 "achieved_hbm_GBs": round(gbs, 1), "achieved_TFLOPs": round(tflops, 3)})
     kernels = {k: {"launches": v[0], "avg_ms": round(v[1] / max(v[0], 1), 4)} for k, v in kall.items()}
 
     if args.only_steps:
@@ -638,12 +899,13 @@ def main():
 
     cpu = None
     parity = None
+    order_rule = None
     if not args.no_cpu_baseline:
         from oracle import oracle as O
         rng = np.random.default_rng([2, 0, 777])
         G_all = lambda k: np.stack([rng.integers(model.g0[a], model.g0[a] + count[a], k)
                                     for a in range(3)], -1).astype(np.int32)
-        threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+        threads = O.max_threads()
         Gs = G_all(64)
         c0 = time.perf_counter()
         O.intensity(model, Gs, N)
@@ -653,17 +915,47 @@ def main():
         c0 = time.perf_counter()
         I_or = O.intensity(model, Gs, N)
         dt = time.perf_counter() - c0
+        # the same direct sum on one thread: the per-core rate
+        per_g_1thread = dt / len(Gs) * threads          # seconds per voxel on one core, about
+        G1 = Gs[:int(min(512, max(16, 2.0 / max(per_g_1thread, 1e-6))))]
+        O.set_threads(1)
+        c1 = time.perf_counter()
+        O.intensity(model, G1, N)
+        dt1 = time.perf_counter() - c1
+        O.set_threads(threads)
         cpu = {"value": round(len(Gs) / dt, 2), "unit": "voxels/s", "cores": threads, "kind": "oracle",
                "sample": f"{len(Gs)} seeded random G of the 513^3 box, FP64 direct sum over all "
-                         f"131072 atoms, Taylor order {N}, {dt:.1f} s"}
+                         f"131072 atoms, Taylor order {N}, {dt:.1f} s",
+               "per_core_value": round(len(G1) / dt1, 2),
+               "per_core_sample": f"{len(G1)} of those G on 1 thread, {dt1:.2f} s"}
         idx = tuple((Gs[:, a] - model.g0[a]) for a in range(3))
         g = I_gpu[idx].astype(np.float64)
-        parity = {"rel_l2_vs_fp64_order_N": float(np.linalg.norm(g - I_or) / np.linalg.norm(I_or)),
-                  "voxels": int(len(Gs))}
+        parity = {"unfiltered_vs_fp64_order_N": c15_report(Gs, g, I_or, n)}
         I_ex = O.intensity(model, Gs[:256], -1)
-        parity["rel_l2_vs_fp64_exact_256"] = float(np.linalg.norm(g[:256] - I_ex) / np.linalg.norm(I_ex))
+        parity["unfiltered_vs_fp64_exact_256"] = c15_report(Gs[:256], g[:256], I_ex, n)
+        Qf = fidx + np.asarray(model.g0)
+        F_or = oracle_filtered_points(O, model, Qf, lm, N)
+        parity["filtered_vs_fp64_order_N"] = c15_report(Qf, F_gpu, F_or, n)
+        # the order rule: the GPU at each Taylor order N against the exact exponential
+        order_rule = {"voxels": 256, "rel_l2_vs_exact": {}, "rel_l2_vs_same_order_oracle": {}}
+        for NN in range(1, 9):
+            hm = dsx.Model(cell=model.cell, n=n, frac=model.frac, b=model.b, taylor_order=NN, n_configs=M)
+            hm.set_grid(model.g0, count)
+            hm.set_sites(0, None, disp_dev)
+            hm.compute_intensity(out)
+            torch.cuda.synchronize()
+            gN = out[tuple(torch.as_tensor(v, device=dev) for v in idx)][:256].cpu().numpy().astype(np.float64)
+            order_rule["rel_l2_vs_exact"][str(NN)] = float(np.linalg.norm(gN - I_ex) / np.linalg.norm(I_ex))
+            IN = O.intensity(model, Gs[:256], NN)
+            order_rule["rel_l2_vs_same_order_oracle"][str(NN)] = float(np.linalg.norm(gN - IN) / np.linalg.norm(IN))
+            hm.close()
     h.close()
 
+    Ocheck = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as Ocheck
+    magnetic = None if args.only_steps else bench_magnetic(dsx, torch, dev, args.steps, args.warmup, Ocheck)
+    compositional = None if args.only_steps else bench_compositional(dsx, torch, dev, args.steps, Ocheck)
     ensemble = None if args.no_ensemble else bench_ensemble(dsx, torch, dev, max(3, args.steps // 4), 2)
     serving = bench_serving(dsx, torch, dev, args.serve_seconds) if args.serve_seconds > 0 else None
 
@@ -680,6 +972,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "parity": parity,
+        "order_rule": order_rule,
         "unfiltered_voxels_per_s": None if unfiltered is None else round(unfiltered, 1),
         "kernels": kernels,
     }
@@ -687,6 +980,10 @@ def main():
         line["compute_intensity_voxels_per_s_by_order"] = sweep
     if widened is not None:
         line["widened_filter"] = widened
+    if magnetic is not None:
+        line["magnetic"] = magnetic
+    if compositional is not None:
+        line["compositional"] = compositional
     if ensemble is not None:
         line["ensemble"] = ensemble
     if serving is not None:

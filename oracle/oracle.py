@@ -93,6 +93,17 @@ def lib():
     return _lib
 
 
+def set_threads(n: int) -> None:
+    """Number of OpenMP threads the C oracle uses from now on (in this process)."""
+    lib().omp_set_num_threads(int(n))
+
+
+def max_threads() -> int:
+    f = lib().omp_get_max_threads
+    f.restype = ctypes.c_int
+    return int(f())
+
+
 def _ptr(a):
     return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
 

@@ -191,18 +191,21 @@ struct DeviceTables {
     int H3min = 0, nH3span = 0;
     int nwork = 0, nwork2 = 0, nwork3 = 0, hc = 0, nchunk3 = 0, block = 0;
     int n3s = 0, block3 = 0;   // k3 per slice, threads per plane of a sliced block
+    int4* work_mr = nullptr;   // magnetic models: blocks of the row-staged form (null: not used)
+    int nwork_mr = 0, rows_mr = 0, csites_mr = 0, qmod_mr = 0;
 };
 
 // Releases every device buffer of one cached box.
 void free_tables(DeviceTables& t)
 {
     dfree(t.tab1); dfree(t.tab2); dfree(t.tabK2); dfree(t.tabK3); dfree(t.tabH3);
-    dfree(t.work); dfree(t.work2); dfree(t.work3); dfree(t.k3tab);
+    dfree(t.work); dfree(t.work2); dfree(t.work3); dfree(t.k3tab); dfree(t.work_mr);
     t = DeviceTables{};
 }
 
 struct LaunchPlan {
     RecombParams rp;
+    bool mag_rows = false;     // the row-staged magnetic form
     int hc = 0, block = 0;
     size_t lds = 0;
     BraggParams bp;
@@ -462,8 +465,36 @@ dsx_status tables_for(dsx_model m, const Box& bx, DeviceTables** out)
     const int h2per = std::max(1, maxT / per_h2);
     const bool friedel = symmetric_box(bx);
     if (bx.half && !friedel) return fail(DSX_ERR_STATE, "half storage needs a symmetric box");
-    std::vector<std::pair<long long, int4>> items, items2, items3;
+    std::vector<std::pair<long long, int4>> items, items2, items3, items_mr;
     int maxrows = 1;
+    // the row-staged magnetic form: one thread per G3 of the box (at most
+    // kMagRowsMaxThreads), rows per block from the LDS budget (about four blocks per CU),
+    // site chunks of the staging area, and the H3 residues the classes are summed over
+    if (mag && bx.cnt[2] <= kMagRowsMaxThreads) {
+        const int NC = m->nclass;
+        int q = 0;
+        bool uniform = true;
+        for (int i = 0; i < S && m->has_ff; ++i)
+            for (int k = 0; k < 7; ++k) uniform = uniform && m->ff[8 * m->site_of[i] + k] == m->ff[8 * m->site_of[0] + k];
+        if (uniform && NC <= kMagRowsMaxClasses)
+            for (int cand : {1, 2, 3, 4, 6, 8}) {
+                bool ok = true;
+                for (int i = 0; i < S && ok; ++i) {
+                    const double x = m->frac[3 * m->site_of[i] + 2] * cand;
+                    ok = std::fabs(x - std::round(x)) < 1e-9;
+                }
+                if (ok) { q = cand <= NC ? cand : 0; break; }
+            }
+        t.qmod_mr = q;
+        int cs = S;
+        while (cs > 1 && (size_t)cs * 3 * n3 * sizeof(float2) > 12 * 1024) cs = (cs + 1) / 2;
+        const size_t budget = 48 * 1024 / sizeof(float2);
+        const size_t fixed = magnetic_rows_lds_elems(0, cs, S, NC, n3, t.nH3span);
+        const size_t per_row = magnetic_rows_lds_elems(1, 0, S, NC, n3, 0) - (size_t)S * n3;
+        int rows = fixed < budget ? (int)((budget - fixed) / per_row) : 0;
+        rows = std::min(std::min(rows, kMagRowsMaxRows), maxH2);
+        if (rows >= 1) { t.rows_mr = rows; t.csites_mr = cs; }
+    }
     // k3 slices of the two-plane blocks: halves of the k3 range when it is long enough
     // that a slice still writes 64-byte runs of an output row
     const int nsl = (n3 >= 16) ? 2 : 1;
@@ -494,6 +525,19 @@ dsx_status tables_for(dsx_model m, const Box& bx, DeviceTables** out)
                     }
                 }
                 planes.push_back({j1, mirror});
+            }
+            if (t.rows_mr > 0) {
+                const int npm = (nH2 + t.rows_mr - 1) / t.rows_mr;
+                const int rpm = (nH2 + npm - 1) / npm;
+                for (int part = 0; part < npm; ++part) {
+                    const int h2a = part * rpm, h2b = std::min(nH2, h2a + rpm);
+                    if (h2a >= h2b) continue;
+                    for (size_t i = 0; i < planes.size(); ++i) {
+                        const int G1 = k1 + n1 * (H1lo + planes[i].first);
+                        items_mr.push_back({key * 4096 + planes[i].first,
+                                            make_int4(k1, k2, G1, h2a | (h2b << 12) | (planes[i].second << 24))});
+                    }
+                }
             }
             for (int part = 0; part < np; ++part) {
                 const int h2a = part * rpp, h2b = std::min(nH2, h2a + rpp);
@@ -534,6 +578,8 @@ dsx_status tables_for(dsx_model m, const Box& bx, DeviceTables** out)
         return wl;
     };
     const std::vector<int4> work = xcd_order(items), work2 = xcd_order(items2), work3 = xcd_order(items3);
+    const std::vector<int4> work_mr = xcd_order(items_mr);
+    t.nwork_mr = (int)work_mr.size();
     t.nwork = (int)work.size();
     t.nwork2 = (int)work2.size();
     t.nwork3 = (int)work3.size();
@@ -567,6 +613,9 @@ dsx_status tables_for(dsx_model m, const Box& bx, DeviceTables** out)
         (!work3.empty() &&
          ((e = hipMalloc(&t.work3, sizeof(int4) * work3.size())) != hipSuccess ||
           (e = hipMemcpy(t.work3, work3.data(), sizeof(int4) * work3.size(), hipMemcpyHostToDevice)) != hipSuccess)) ||
+        (!work_mr.empty() &&
+         ((e = hipMalloc(&t.work_mr, sizeof(int4) * work_mr.size())) != hipSuccess ||
+          (e = hipMemcpy(t.work_mr, work_mr.data(), sizeof(int4) * work_mr.size(), hipMemcpyHostToDevice)) != hipSuccess)) ||
         (e = hipMalloc(&t.k3tab, sizeof(int2) * k3t.size())) != hipSuccess ||
         (e = hipMemcpy(t.k3tab, k3t.data(), sizeof(int2) * k3t.size(), hipMemcpyHostToDevice)) != hipSuccess) {
         free_tables(t);
@@ -651,6 +700,22 @@ dsx_status plan_recombine(dsx_model m, const Box& bx, float* out, const Layout& 
     lp.hc = tb->hc;
     lp.block = tb->block;
     lp.lds = m->chunk_lds + sizeof(float2) * ((size_t)m->nclass * tb->nH3span + p.dw_elems);
+    {
+        int c = 0;
+        for (int i = 0; i < m->S; ++i)
+            while (c <= m->class_of[i]) p.class_start[c++] = i;
+        while (c <= m->nclass) p.class_start[c++] = m->S;
+    }
+    if (mag && m->dw_order == 0 && tb->work_mr) {
+        lp.mag_rows = true;
+        p.work = tb->work_mr;
+        p.nwork = tb->nwork_mr;
+        p.rows = tb->rows_mr;
+        p.csites = tb->csites_mr;
+        p.qmod = tb->qmod_mr;
+        lp.block = std::max(64, (bx.cnt[2] + 63) / 64 * 64);
+        lp.lds = sizeof(float2) * magnetic_rows_lds_elems(tb->rows_mr, tb->csites_mr, m->S, m->nclass, n3, tb->nH3span);
+    }
     if (lp.lds > 160 * 1024) return fail(DSX_ERR_UNSUPPORTED, "recombination does not fit the LDS for this box");
     // folded form: every r_mu2 a multiple of 1/2 (exactly, as given), fewer r3 classes
     // than sites, and the class buffers fit the LDS
@@ -796,7 +861,9 @@ dsx_status run_box(dsx_model m, const Box& bx, float* dout, const Layout& lay, h
     LaunchPlan lp;
     dsx_status s = plan_recombine(m, bx, dout, lay, lp);
     if (s != DSX_OK) return s;
-    if (m->kind == DSX_MAGNETIC)
+    if (lp.mag_rows)
+        HIPCHK(m, timed("recombine", st, [&] { return launch_recombine_magnetic_rows(lp.rp, lp.block, lp.lds, st); }));
+    else if (m->kind == DSX_MAGNETIC)
         HIPCHK(m, timed("recombine", st, [&] { return launch_recombine_magnetic(lp.rp, lp.hc, lp.block, lp.lds, st); }));
     else
         HIPCHK(m, timed("recombine", st, [&] { return launch_recombine_nuclear(lp.rp, m->order, lp.hc, lp.block, lp.lds, st); }));
@@ -2029,7 +2096,6 @@ struct dsx_server_s {
 
 namespace {
 
-size_t box_voxels(const Box& b) { return (size_t)b.cnt[0] * b.cnt[1] * b.cnt[2]; }
 
 // Workspace of one request: spectra, partial lattice sums and, filtered, the grown box.
 size_t request_workspace(dsx_model m, int lm, size_t* x_bytes)

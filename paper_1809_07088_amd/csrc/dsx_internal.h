@@ -131,6 +131,13 @@ struct RecombParams {
     // block into LDS (dw_elems float2 after the class phases), q per thread and r per voxel.
     const double* dwc;
     int32_t dw_order, dwT, dw_elems;
+    // row-staged magnetic form: class c holds the sorted positions
+    // [class_start[c], class_start[c + 1]); the work list's blocks take at most
+    // `rows` rows; site chunks of `csites` sites
+    int32_t class_start[kMaxSites + 1];
+    int32_t rows, csites;
+    int32_t qmod;           // > 0: every r_c3 a multiple of 1/qmod and one form factor for all
+                            // sites: the classes are summed per residue of H3 mod qmod
 };
 
 // ---------------------------------------------------------------------------- Bragg (k = 0)
@@ -190,6 +197,18 @@ hipError_t launch_recombine_nuclear(const RecombParams& p, int order, int hc, in
                                     size_t lds, hipStream_t st);
 hipError_t launch_recombine_magnetic(const RecombParams& p, int hc, int block, size_t lds,
                                      hipStream_t st);
+// the row-staged magnetic form (no Debye-Waller factor); p.work lists its blocks, and
+// the launch has one thread per G3 of the box (block >= cnt3)
+constexpr int kMagRowsMaxThreads = 512;
+constexpr int kMagRowsMaxRows = 16;
+constexpr int kMagRowsMaxClasses = 8;   // the per-residue class sums need q <= nclass <= this
+hipError_t launch_recombine_magnetic_rows(const RecombParams& p, int block, size_t lds, hipStream_t st);
+// float2 elements of its LDS for rows, site chunks of csites, S sites, nclass classes
+inline size_t magnetic_rows_lds_elems(int rows, int csites, int S, int nclass, int n3, int nH3span)
+{
+    return (size_t)rows * nclass * 3 * n3 + (size_t)S * n3 + (size_t)rows * S + (size_t)nclass * nH3span
+         + (size_t)csites * 3 * n3;
+}
 hipError_t launch_bragg(const BraggParams& p, int order, hipStream_t st);
 // dwc[mu][t] = sum_m sums[m][mu][t] / sum_m sums[m][mu][0] (0 for a site with no atom):
 // the Debye-Waller means of Eq. dw from the float64 lattice sums of the displacements.

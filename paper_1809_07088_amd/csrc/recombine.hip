@@ -1049,6 +1049,242 @@ static hipError_t set_lds(K kernel, size_t lds)
     return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
+// Row-staged form of the magnetic recombination (sites without a Debye-Waller factor).
+// A block takes rows h2a..h2b of column (k1, k2) in plane G1; its threads cover the
+// box's G3 (one output column each, so a row is written by consecutive threads):
+//   level A  Bs[site][comp][k3] = b_mu e^{2 pi i (g1 r_mu1 + k3 r_mu3 / n3)} M_comp(k1, k2, k3),
+//            one site chunk at a time, read straight from the spin spectra of the column
+//            (k3 <= n3/2) and of its mirror (the rest, through X(k) = conj X(-k));
+//   level B  D[row][class][comp][k3] += sum over the chunk's sites of the class of
+//            e^{2 pi i g2 r_mu2} Bs; then, when every r_c3 of the classes is a multiple
+//            of 1/q and the form factor is the same for every site, the classes are
+//            summed per residue of H3 mod q, in place (q <= nclass):
+//            E[row][j][comp][k3] = sum_c e^{2 pi i H3_j r_c3} D  (H3_j = j mod q);
+//   level C  per voxel of the thread's column: F_comp = E[row][H3 mod q][comp][k3], or
+//            sum_c e^{2 pi i H3 r_c3} f_c(|Q|) D, then F_perp = F - Qhat (Qhat . F),
+//            |F_perp|^2 and f(|Q|)^2 (Eqs. mag_sf, mag_projection).  One configuration:
+//            each value is stored as it is made; several: accumulated in registers.
+// The form factor uses the hardware exponential (relative error ~1e-6 at the arguments
+// a s^2 <= 30 met here).
+__device__ __forceinline__ float mag_ff_fast(const float* f, float s2) {
+    return f[0] * __expf(-f[1] * s2) + f[2] * __expf(-f[3] * s2) + f[4] * __expf(-f[5] * s2) + f[6];
+}
+
+__device__ __forceinline__ void cmac(float2& acc, float2 a, float2 b) {
+    acc.x = fmaf(a.x, b.x, acc.x);
+    acc.x = fmaf(-a.y, b.y, acc.x);
+    acc.y = fmaf(a.x, b.y, acc.y);
+    acc.y = fmaf(a.y, b.x, acc.y);
+}
+
+template <bool MULTI>
+__global__ __launch_bounds__(kMagRowsMaxThreads) void k_recombine_magnetic_rows(RecombParams P)
+{
+    extern __shared__ float2 smem[];
+    __shared__ int cls[kMaxSites + 1];
+    __shared__ float2 t1s[kMaxSites];
+    BlockWork w;
+    if (!decode_block(P, w)) return;
+    const int n1 = P.n1, n2 = P.n2, n3 = P.n3, nh = P.nh, S = P.S, NC = P.nclass, q = P.qmod;
+    const int rows = w.h2b - w.h2a, cnt3 = P.cnt[2];
+    float2* D = smem;                              // [rows][NC][3][n3]; then E [rows][q][3][n3]
+    float2* tK3 = D + rows * NC * 3 * n3;          // [S][n3]   (sorted positions)
+    float2* t2 = tK3 + S * n3;                     // [rows][S]
+    float2* tHs = t2 + rows * S;                   // [NC][nH3span]
+    float2* Bs = tHs + NC * P.nH3span;             // [csites][3][n3]
+    const float2* tH0 = stage_class_phases(P, tHs);
+    const float rn3 = 1.f / (float)n3, rS = 1.f / (float)S, rNC = 1.f / (float)NC;
+    for (int idx = threadIdx.x; idx < S * n3; idx += blockDim.x) {
+        const int i = qdiv_r(idx, n3, rn3), k = idx - i * n3;
+        tK3[idx] = P.tabK3[(size_t)P.site_of[i] * n3 + k];
+    }
+    for (int idx = threadIdx.x; idx < rows * S; idx += blockDim.x) {
+        const int r = qdiv_r(idx, S, rS), i = idx - r * S;
+        const int i2 = w.k2 + n2 * (w.H2lo + w.h2a + r) - P.g0[1];
+        t2[idx] = P.tab2[(size_t)P.site_of[i] * P.cnt[1] + i2];
+    }
+    for (int i = threadIdx.x; i <= NC; i += blockDim.x) cls[i] = P.class_start[i];
+    for (int i = threadIdx.x; i < S; i += blockDim.x) t1s[i] = P.tab1[(size_t)P.site_of[i] * P.cnt[0] + w.i1];
+    const int SFnh = P.SF * nh;
+    const size_t col = ((size_t)w.k1 * n2 + w.k2) * SFnh;
+    const size_t colm = ((size_t)((n1 - w.k1) % n1) * n2 + (n2 - w.k2) % n2) * SFnh;
+    // the thread's output column i3 (the launch has at least cnt3 threads)
+    const int i3 = threadIdx.x;
+    const bool active = i3 < cnt3;
+    const int G3 = P.g0[2] + i3;
+    const int H3 = floordiv(G3, n3);
+    const int k3 = G3 - n3 * H3;
+    const int jq = q > 0 ? H3 - q * floordiv(H3, q) : 0;
+    const float inv16pi2 = 1.f / (16.f * 9.8696044010893586f);
+    const float g1 = (float)((double)w.G1 / (double)n1);
+    const float g3 = (float)((double)G3 / (double)n3);
+    const float rn2f = (float)(1.0 / (double)n2);
+    const float q13x = g1 * P.recip[0] + g3 * P.recip[6];
+    const float q13y = g1 * P.recip[1] + g3 * P.recip[7];
+    const float q13z = g1 * P.recip[2] + g3 * P.recip[8];
+    const size_t plane = (size_t)P.cnt[1] * P.opitch;
+    float* const orow0 = P.out + P.ooff + (size_t)w.i1 * plane + i3;
+    float* const mrow0 = P.out + P.ooff + (size_t)(P.cnt[0] - 1 - w.i1) * plane + (P.cnt[2] - 1 - i3);
+    float I[MULTI ? kMagRowsMaxRows : 1];
+#pragma unroll
+    for (int r = 0; r < (MULTI ? kMagRowsMaxRows : 1); ++r) I[r] = 0.f;
+
+    for (int m = 0; m < P.M; ++m) {
+        const float2* Xm = P.X + (size_t)m * n1 * n2 * SFnh;
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < rows * NC * 3 * n3; idx += blockDim.x) D[idx] = make_float2(0.f, 0.f);
+        for (int s0 = 0; s0 < S; s0 += P.csites) {
+            const int ns = min(P.csites, S - s0);
+            __syncthreads();
+            // level A (with the k3 phase of the site)
+            for (int idx = threadIdx.x; idx < ns * 3 * n3; idx += blockDim.x) {
+                const int rj = qdiv_r(idx, n3, rn3);
+                const int kk = idx - rj * n3;
+                const int sl = rj / 3, comp = rj - 3 * sl;
+                const size_t f = ((size_t)P.site_of[s0 + sl] * 3 + comp) * nh;
+                float2 x;
+                if (kk < nh) x = Xm[col + f + kk];
+                else { x = Xm[colm + f + (n3 - kk)]; x.y = -x.y; }
+                Bs[idx] = cmulf(cmulf(t1s[s0 + sl], tK3[(s0 + sl) * n3 + kk]), x);
+            }
+            __syncthreads();
+            // level B: one (row, class, k3) per thread, the chunk's sites of the class
+            for (int idx = threadIdx.x; idx < rows * NC * n3; idx += blockDim.x) {
+                const int rc = qdiv_r(idx, n3, rn3);
+                const int kk = idx - rc * n3;
+                const int r = qdiv_r(rc, NC, rNC);
+                const int c = rc - r * NC;
+                const int i0 = max(cls[c], s0), i1 = min(cls[c + 1], s0 + ns);
+                if (i0 >= i1) continue;
+                float2 acc[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+                for (int i = i0; i < i1; ++i) {
+                    const float2 ph = t2[r * S + i];
+                    const float2* b = Bs + (size_t)(i - s0) * 3 * n3 + kk;
+#pragma unroll
+                    for (int comp = 0; comp < 3; ++comp) cmac(acc[comp], ph, b[comp * n3]);
+                }
+                float2* d = D + (size_t)rc * 3 * n3 + kk;
+#pragma unroll
+                for (int comp = 0; comp < 3; ++comp) {
+                    d[comp * n3].x += acc[comp].x;
+                    d[comp * n3].y += acc[comp].y;
+                }
+            }
+        }
+        __syncthreads();
+        // classes summed per residue of H3 mod q, in place: one (row, comp, k3) per
+        // thread reads its classes' D, then writes E over the first q of them
+        if (q > 0) {
+            for (int idx = threadIdx.x; idx < rows * 3 * n3; idx += blockDim.x) {
+                const int rc = qdiv_r(idx, n3, rn3);
+                const int kk = idx - rc * n3;
+                const int r = rc / 3, comp = rc - 3 * r;
+                float2* d = D + (size_t)r * NC * 3 * n3 + comp * n3 + kk;
+                float2 dv[kMagRowsMaxClasses];
+#pragma unroll
+                for (int c = 0; c < kMagRowsMaxClasses; ++c) dv[c] = c < NC ? d[c * 3 * n3] : make_float2(0.f, 0.f);
+#pragma unroll
+                for (int j = 0; j < kMagRowsMaxClasses; ++j) {
+                    if (j >= q) break;
+                    const int h = P.H3min + ((j - P.H3min) % q + q) % q;   // an H3 of residue j
+                    if (h - P.H3min >= P.nH3span) continue;
+                    float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+                    for (int c = 0; c < kMagRowsMaxClasses; ++c)
+                        if (c < NC) cmac(acc, tH0[c * P.nH3span + h], dv[c]);
+                    d[j * 3 * n3] = acc;
+                }
+            }
+            __syncthreads();
+        }
+        // level C: the thread's column, every row
+        if (active) {
+            for (int r = 0; r < rows; ++r) {
+                const int G2 = w.k2 + n2 * (w.H2lo + w.h2a + r);
+                const float g2 = (float)G2 * rn2f;
+                const float qx = q13x + g2 * P.recip[3];
+                const float qy = q13y + g2 * P.recip[4];
+                const float qz = q13z + g2 * P.recip[5];
+                const float q2 = qx * qx + qy * qy + qz * qz;
+                const float s2 = q2 * inv16pi2;
+                float2 F[3];
+                if (q > 0) {
+                    const float2* e = D + ((size_t)(r * NC + jq) * 3) * n3 + k3;
+#pragma unroll
+                    for (int comp = 0; comp < 3; ++comp) F[comp] = e[comp * n3];
+                } else {
+#pragma unroll
+                    for (int comp = 0; comp < 3; ++comp) F[comp] = make_float2(0.f, 0.f);
+                    const float2* d = D + (size_t)r * NC * 3 * n3 + k3;
+                    const float2* th = tH0 + H3;
+                    for (int c = 0; c < NC; ++c) {
+                        float2 e3 = th[c * P.nH3span];
+                        if (!P.ff_uniform) {
+                            const float f = mag_ff_fast(P.ff[cls[c]], s2);
+                            e3.x *= f; e3.y *= f;
+                        }
+#pragma unroll
+                        for (int comp = 0; comp < 3; ++comp) cmac(F[comp], e3, d[(c * 3 + comp) * n3]);
+                    }
+                }
+                float val = 0.f;
+                if (q2 > 0.f) {
+                    const float iq = rsqrtf(q2);
+                    const float ex = qx * iq, ey = qy * iq, ez = qz * iq;
+                    const float px = ex * F[0].x + ey * F[1].x + ez * F[2].x;
+                    const float py = ex * F[0].y + ey * F[1].y + ez * F[2].y;
+#pragma unroll
+                    for (int comp = 0; comp < 3; ++comp) val += F[comp].x * F[comp].x + F[comp].y * F[comp].y;
+                    val -= px * px + py * py;
+                    if (P.ff_uniform) {
+                        const float f = mag_ff_fast(P.ff[0], s2);
+                        val *= f * f;
+                    }
+                }
+                if constexpr (MULTI) {
+#pragma unroll
+                    for (int rr = 0; rr < kMagRowsMaxRows; ++rr)
+                        if (rr == r) I[rr] += val;
+                } else {
+                    const int i2 = G2 - P.g0[1];
+                    const float o = val * P.scale;
+                    orow0[(size_t)i2 * P.opitch] = o;
+                    if (w.mirror) mrow0[(size_t)(P.cnt[1] - 1 - i2) * P.opitch] = o;
+                }
+            }
+        }
+    }
+    if constexpr (MULTI) {
+        if (active) {
+#pragma unroll
+            for (int r = 0; r < kMagRowsMaxRows; ++r) {
+                if (r < rows) {
+                    const int i2 = w.k2 + n2 * (w.H2lo + w.h2a + r) - P.g0[1];
+                    const float o = I[r] * P.scale;
+                    orow0[(size_t)i2 * P.opitch] = o;
+                    if (w.mirror) mrow0[(size_t)(P.cnt[1] - 1 - i2) * P.opitch] = o;
+                }
+            }
+        }
+    }
+}
+
+hipError_t launch_recombine_magnetic_rows(const RecombParams& p, int block, size_t lds, hipStream_t st)
+{
+    if (p.nwork <= 0) return hipSuccess;
+    if (block < p.cnt[2] || block > kMagRowsMaxThreads || p.rows > kMagRowsMaxRows) return hipErrorInvalidValue;
+    if (p.M > 1) {
+        hipError_t e = set_lds(k_recombine_magnetic_rows<true>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_recombine_magnetic_rows<true>), dim3(p.nwork), dim3(block), lds, st, p);
+    } else {
+        hipError_t e = set_lds(k_recombine_magnetic_rows<false>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_recombine_magnetic_rows<false>), dim3(p.nwork), dim3(block), lds, st, p);
+    }
+    return hipGetLastError();
+}
+
 template <int N, int HC, bool MULTI, bool PAR>
 static hipError_t launch_nuc_v(const RecombParams& p, int block, size_t lds, hipStream_t st)
 {
@@ -1253,11 +1489,18 @@ __device__ void dw_at_h(const BraggParams& P, const int H[3], int mu, double& tr
     }
 }
 
+// One 64-lane wave per unit-cell Bragg point H: each lane forms, for its sites, the
+// factor b_mu f_mu(|Q|) T_mu(H) e^{2 pi i H.r_mu} once, then per configuration the
+// vector F = sum_mu factor S_mu (S the float64 lattice sums of the spins) is one wave
+// reduction (fixed order); lane 0 projects F perpendicular to Q and keeps the ensemble
+// moments.  All in float64.
 __global__ __launch_bounds__(256) void k_bragg_magnetic(BraggParams P)
 {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double Wr[4][kMaxSites], Wi[4][kMaxSites];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int idx = blockIdx.x * 4 + wave;
     const int total = P.nH[0] * P.nH[1] * P.nH[2];
-    if (idx >= total) return;
+    if (idx >= total) return;              // whole waves leave together; no block barrier follows
     const int j3 = idx % P.nH[2], j2 = (idx / P.nH[2]) % P.nH[1], j1 = idx / (P.nH[2] * P.nH[1]);
     const int H[3] = {P.Hlo[0] + j1, P.Hlo[1] + j2, P.Hlo[2] + j3};
     const int G[3] = {P.n[0] * H[0], P.n[1] * H[1], P.n[2] * H[2]};
@@ -1265,49 +1508,66 @@ __global__ __launch_bounds__(256) void k_bragg_magnetic(BraggParams P)
     double Q[3];
     for (int c = 0; c < 3; ++c) Q[c] = H[0] * P.recip[c] + H[1] * P.recip[3 + c] + H[2] * P.recip[6 + c];
     const double q2 = Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2];
-    if (!(q2 > 0.0)) { *o = 0.f; return; }
+    if (!(q2 > 0.0)) {
+        if (lane == 0) *o = 0.f;
+        return;
+    }
+    const double s2 = q2 / (16.0 * 9.869604401089358618834);
+    for (int mu = lane; mu < P.S; mu += 64) {
+        const double* sd = P.site + 12 * mu;
+        double x = H[0] * sd[0] + H[1] * sd[1] + H[2] * sd[2];
+        x -= floor(x);
+        double sn, cs;
+        sincos(6.283185307179586476925 * x, &sn, &cs);
+        const double f = P.has_ff ? mag_ff_d(sd + 4, s2) : 1.0;
+        double wr = sd[3] * f * cs, wi = sd[3] * f * sn;
+        if (P.dwc) {
+            double tr, ti;
+            dw_at_h(P, H, mu, tr, ti);
+            const double xr = wr * tr - wi * ti;
+            wi = wr * ti + wi * tr;
+            wr = xr;
+        }
+        Wr[wave][mu] = wr;
+        Wi[wave][mu] = wi;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     const double iq = 1.0 / sqrt(q2);
     const double e[3] = {Q[0] * iq, Q[1] * iq, Q[2] * iq};
-    const double s2 = q2 / (16.0 * 9.869604401089358618834);
     double sq = 0.0, mr[3] = {0, 0, 0}, mi[3] = {0, 0, 0};
     for (int m = 0; m < P.M; ++m) {
         double fr[3] = {0, 0, 0}, fi[3] = {0, 0, 0};
-        for (int mu = 0; mu < P.S; ++mu) {
-            const double* sd = P.site + 12 * mu;
-            double x = H[0] * sd[0] + H[1] * sd[1] + H[2] * sd[2];
-            x -= floor(x);
-            double sn, cs;
-            sincos(6.283185307179586476925 * x, &sn, &cs);
-            const double f = P.has_ff ? mag_ff_d(sd + 4, s2) : 1.0;
-            // b f T e^{2 pi i H.r}
-            double wr = sd[3] * f * cs, wi = sd[3] * f * sn;
-            if (P.dwc) {
-                double tr, ti;
-                dw_at_h(P, H, mu, tr, ti);
-                const double xr = wr * tr - wi * ti;
-                wi = wr * ti + wi * tr;
-                wr = xr;
-            }
+        for (int mu = lane; mu < P.S; mu += 64) {
             const double* Sm = P.sums + ((size_t)m * P.S + mu) * 3;
             for (int c = 0; c < 3; ++c) {
-                fr[c] += Sm[c] * wr;
-                fi[c] += Sm[c] * wi;
+                fr[c] += Sm[c] * Wr[wave][mu];
+                fi[c] += Sm[c] * Wi[wave][mu];
             }
         }
-        const double pr = e[0] * fr[0] + e[1] * fr[1] + e[2] * fr[2];
-        const double pi = e[0] * fi[0] + e[1] * fi[1] + e[2] * fi[2];
-        for (int c = 0; c < 3; ++c) {
-            const double ar = fr[c] - e[c] * pr, ai = fi[c] - e[c] * pi;
-            sq += ar * ar + ai * ai;
-            mr[c] += ar; mi[c] += ai;
+        for (int off = 32; off > 0; off >>= 1)
+            for (int c = 0; c < 3; ++c) {
+                fr[c] += __shfl_down(fr[c], off, 64);
+                fi[c] += __shfl_down(fi[c], off, 64);
+            }
+        if (lane == 0) {
+            const double pr = e[0] * fr[0] + e[1] * fr[1] + e[2] * fr[2];
+            const double pi = e[0] * fi[0] + e[1] * fi[1] + e[2] * fi[2];
+            for (int c = 0; c < 3; ++c) {
+                const double ar = fr[c] - e[c] * pr, ai = fi[c] - e[c] * pi;
+                sq += ar * ar + ai * ai;
+                mr[c] += ar; mi[c] += ai;
+            }
         }
     }
-    double mm = 0.0;
-    for (int c = 0; c < 3; ++c) {
-        mr[c] /= P.M; mi[c] /= P.M;
-        mm += mr[c] * mr[c] + mi[c] * mi[c];
+    if (lane == 0) {
+        double mm = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            mr[c] /= P.M; mi[c] /= P.M;
+            mm += mr[c] * mr[c] + mi[c] * mi[c];
+        }
+        *o = (float)((sq / P.M - mm) * P.scale);
     }
-    *o = (float)((sq / P.M - mm) * P.scale);
 }
 
 template <int N>
@@ -1324,7 +1584,7 @@ hipError_t launch_bragg(const BraggParams& p, int order, hipStream_t st)
     if (total <= 0) return hipSuccess;
     const int grid = (total + 255) / 256;
     if (p.kind == 1) {
-        hipLaunchKernelGGL(k_bragg_magnetic, dim3(grid), dim3(256), 0, st, p);
+        hipLaunchKernelGGL(k_bragg_magnetic, dim3((total + 3) / 4), dim3(256), 0, st, p);
         return hipGetLastError();
     }
     switch (order) {
