@@ -37,15 +37,33 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "diffuse-intensity voxels/s at ≤1e-5 rel L2 vs FP64; p50/p99 request latency"
-TRAFFIC_MD = os.path.join(ROOT, "profiles", "recombine_displacive32_order8_traffic.md")
-KTRACE_MD = os.path.join(ROOT, "profiles", "kernels_displacive32_order8.md")
+PROFILES = os.path.join(ROOT, "profiles")
+# rocprofv3 summaries per workload: (title, kernel-name fragment of the dominant kernel)
+WORKLOADS = {
+    "displacive32_order8": ("displacive 32^3 fcc, Taylor order 8, 513^3 box, Lanczos m = 2 (the filtered step)",
+                            "k_recombine"),
+    "magnetic24": ("magnetic pyrochlore 24^3, 16 sites, 289^3 box (set_sites_async + compute_intensity)",
+                   "k_recombine_magnetic"),
+    "ensemble8x8": ("batched ensemble, 8 models x 8 configurations, one graph replay per step", "k_recombine"),
+}
+
+
+def ktrace_md(name):
+    return os.path.join(PROFILES, f"kernels_{name}.md")
+
+
+def traffic_md(name):
+    return os.path.join(PROFILES, f"traffic_{name}.md")
 COPY_PROBE_BYTES = 256 << 20     # plain device copy of known size, read + write
 
 
 def kernel_source_hash():
-    """Hash of the recombination source: stored traffic is only used while it matches."""
-    with open(os.path.join(ROOT, "paper_1809_07088_amd", "csrc", "recombine.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the kernel sources: stored traces and traffic are only used while it matches."""
+    h = hashlib.sha256()
+    for src in ("recombine.hip", "fft.hip", "lanczos.hip"):
+        with open(os.path.join(ROOT, "paper_1809_07088_amd", "csrc", src), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def _after_probe(rows):
@@ -56,10 +74,13 @@ def _after_probe(rows):
     return [r for r in rows if int(r["Dispatch_Id"]) > first]
 
 
-def summarize_pmc(fetch_dir, write_dir, out_md, command):
+def summarize_pmc(fetch_dir, write_dir, name, command):
     """Turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) into the
-    traffic summary: per-launch HBM bytes of the recombination, scaled by the ratio of
-    the known size of the plain copy probe to what the same counter reads for it."""
+    traffic summary of a workload: per kernel, the HBM bytes per launch, each counter
+    scaled by the ratio of the known size of the plain copy probe to what the same
+    counter reads for it; the dominant kernel's record is kept as JSON for the bench."""
+    title, dominant = WORKLOADS[name]
+
     def per_kernel(d, counter):
         vals = {}
         for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
@@ -72,59 +93,60 @@ def summarize_pmc(fetch_dir, write_dir, out_md, command):
     def probe(vals):
         cands = [max(v) for k, v in vals.items() if "copyBuffer" in k]
         return max(cands) if cands else None
-
-    def step_kernel(vals):
-        ks = [k for k in vals if "k_recombine" in k]
-        return max(ks, key=lambda k: len(vals[k])) if ks else None
     pf, pw = probe(fetch), probe(write)
-    nf, nw = step_kernel(fetch), step_kernel(write)
-    if not nf or not nw or not pf or not pw:
-        raise SystemExit("summarize: recombination or copy probe missing in the counter files")
-    kf, kw = fetch[nf], write[nw]
+    if not pf or not pw:
+        raise SystemExit("summarize: copy probe missing in the counter files")
     sf, sw = COPY_PROBE_BYTES / pf, COPY_PROBE_BYTES / pw
-    f_avg = sum(kf) / len(kf) * sf
-    w_avg = sum(kw) / len(kw) * sw
-    rec = {"kernel": "recombine", "kernel_name": nf, "source_hash": kernel_source_hash(),
+    kernels = [k for k in fetch if "dsx::" in k and k in write]
+    kernels.sort(key=lambda k: -sum(fetch[k]) / len(fetch[k]) - sum(write[k]) / len(write[k]))
+    dom = [k for k in kernels if dominant in k]
+    if not dom:
+        raise SystemExit("summarize: dominant kernel missing in the counter files")
+    dk = max(dom, key=lambda k: len(fetch[k]))
+    f_avg = sum(fetch[dk]) / len(fetch[dk]) * sf
+    w_avg = sum(write[dk]) / len(write[dk]) * sw
+    rec = {"kernel": dominant, "kernel_name": dk, "source_hash": kernel_source_hash(),
            "fetch_bytes": f_avg, "write_bytes": w_avg, "traffic_bytes": f_avg + w_avg,
            "copy_probe_bytes": COPY_PROBE_BYTES, "fetch_scale": sf, "write_scale": sw}
-    with open(out_md, "w") as f:
-        f.write("# HBM traffic of the recombination kernel (displacive 32^3, Taylor order 8, "
-                "513^3 box grown by the Lanczos window)\n\n")
+    with open(traffic_md(name), "w") as f:
+        f.write("# HBM traffic per kernel launch, %s\n\n" % title)
         f.write("Two rocprofv3 PMC runs of the benchmark (`FETCH_SIZE`, then `WRITE_SIZE`, KiB per "
                 "dispatch), each scaled by copy-probe bytes / counter reading of the plain device "
-                "copy of %d MiB issued by the benchmark (fetch scale %.4f, write scale %.4f).  Only "
-                "the dispatches after the probe count (the plan tuning and the warm-up run before it).  Kernel: "
-                "`%s`, %d launches.\n\n" % (COPY_PROBE_BYTES >> 20, sf, sw, nf, len(kf)))
-        f.write("Command:\n\n```\n%s\n```\n\n" % command)
-        f.write("| counter | raw per launch (bytes) | scaled (bytes) |\n|---|---|---|\n")
-        f.write("| FETCH_SIZE | %.0f | %.0f |\n" % (sum(kf) / len(kf), f_avg))
-        f.write("| WRITE_SIZE | %.0f | %.0f |\n\n" % (sum(kw) / len(kw), w_avg))
-        f.write("```json\n%s\n```\n" % json.dumps(rec))
+                "copy of %d MiB issued by the benchmark after its warm-up (fetch scale %.4f, write scale %.4f).  "
+                "Only the dispatches after the probe count.  Kernel sources: %s.\n\n"
+                % (COPY_PROBE_BYTES >> 20, sf, sw, kernel_source_hash()))
+        f.write("Command (run from /tmp with TMPDIR=/tmp, R = repository root):\n\n```\n%s\n```\n\n" % command)
+        f.write("| kernel | launches | FETCH raw (MB) | WRITE raw (MB) | fetch scaled (MB) | write scaled (MB) |\n"
+                "|---|---|---|---|---|---|\n")
+        for k in kernels:
+            fr, wr = sum(fetch[k]) / len(fetch[k]), sum(write[k]) / len(write[k])
+            f.write("| `%s` | %d | %.2f | %.2f | %.2f | %.2f |\n" % (
+                k, len(fetch[k]), fr / 1e6, wr / 1e6, fr * sf / 1e6, wr * sw / 1e6))
+        f.write("\nDominant kernel record:\n\n```json\n%s\n```\n" % json.dumps(rec))
     return rec
 
 
-def summarize_ktrace(trace_dir, out_md, command):
-    """Kernel-time summary from a rocprofv3 --kernel-trace folder: per kernel, calls and
-    average / min / max duration of the dispatches after the copy probe (the timed
-    steps and their warmup; the recombination's average must agree with the
-    benchmark's HIP-event launch time)."""
+def summarize_ktrace(trace_dir, name, command):
+    """Kernel-time summary of a workload from a rocprofv3 --kernel-trace folder: per
+    kernel, calls and average / min / max duration of the dispatches after the copy probe
+    (the timed steps and their warm-up; the dominant kernel's average is compared with
+    the benchmark's HIP-event launch time)."""
+    title, _ = WORKLOADS[name]
     paths = glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)
     if not paths:
         raise SystemExit("summarize: no kernel_trace.csv under " + trace_dir)
-    rows = _after_probe(list(csv.DictReader(open(paths[0]))))
+    rows = [r for r in _after_probe(list(csv.DictReader(open(paths[0])))) if "dsx::" in r["Kernel_Name"]]
     per = {}
     for r in rows:
         per.setdefault(r["Kernel_Name"], []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
     total = sum(sum(v) for v in per.values())
     order = sorted(per, key=lambda k: -sum(per[k]))
-    with open(out_md, "w") as f:
-        f.write("# Kernel time, displacive 32^3 fcc, Taylor order 8, 513^3 box, Lanczos m = 2\n\n")
-        f.write("rocprofv3 kernel trace of the benchmark's filtered steps (`--only-steps`: "
-                "set_sites_async + noise_filter per step: the timed steps and the untimed steps of the "
-                "per-kernel breakdown), i.e. the dispatches after the plain device copy used as the "
-                "PMC probe; the plan tuning and the warm-up before it are left out.  MI355X, one GPU.\n\nCommand (run from /tmp with "
-                "TMPDIR=/tmp, R = repository root):\n\n```\n%s\n```\n\n" % command)
-        f.write("Kernel sources: recombine.hip %s.\n\n" % kernel_source_hash())
+    with open(ktrace_md(name), "w") as f:
+        f.write("# Kernel time, %s\n\n" % title)
+        f.write("rocprofv3 kernel trace of the benchmark: the library's dispatches after the plain device "
+                "copy issued after the warm-up (the same probe the PMC runs use).  MI355X, one GPU.\n\n"
+                "Command (run from /tmp with TMPDIR=/tmp, R = repository root):\n\n```\n%s\n```\n\n" % command)
+        f.write("Kernel sources: %s.\n\n" % kernel_source_hash())
         f.write("| kernel | calls | average (us) | min (us) | max (us) | share of GPU time |\n"
                 "|---|---|---|---|---|---|\n")
         for k in order:
@@ -134,14 +156,14 @@ def summarize_ktrace(trace_dir, out_md, command):
     return len(order)
 
 
-def stored_trace_avg(kernel_substr):
-    """Average launch time (s) of a kernel in the committed kernel-trace summary, while
-    the recombination source it was taken with is unchanged."""
+def stored_trace_avg(name, kernel_substr):
+    """Average launch time (s) of a kernel in the committed kernel-trace summary of a
+    workload, while the kernel sources it was taken with are unchanged."""
     try:
-        txt = open(KTRACE_MD).read()
+        txt = open(ktrace_md(name)).read()
     except OSError:
         return None
-    if ("recombine.hip %s." % kernel_source_hash()) not in txt:
+    if ("Kernel sources: %s." % kernel_source_hash()) not in txt:
         return None
     for line in txt.splitlines():
         if line.startswith("| `") and kernel_substr in line:
@@ -149,9 +171,11 @@ def stored_trace_avg(kernel_substr):
     return None
 
 
-def stored_traffic():
+def stored_traffic(name):
+    """The dominant kernel's HBM bytes per launch from the committed traffic summary of a
+    workload, while the kernel sources are unchanged."""
     try:
-        txt = open(TRAFFIC_MD).read()
+        txt = open(traffic_md(name)).read()
     except OSError:
         return None
     m = re.search(r"```json\n(.*?)\n```", txt, re.S)
@@ -159,6 +183,8 @@ def stored_traffic():
         return None
     rec = json.loads(m.group(1))
     return rec if rec.get("source_hash") == kernel_source_hash() else None
+
+
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP32_PUBLISHED_TFLOPS = 157.3  # MI355X published FP32 vector peak: counts packed FP32 (two per lane)
 # The reachable FP32 vector peak of this build, which compiles without packed FP32:
@@ -258,6 +284,16 @@ def recombine_work(n, S, nclass3, N, M, g0, cnt, nh, F, friedel=False):
     return flops, bytes_
 
 
+def copy_probe(torch, dev):
+    """One plain device copy of known size: the reference the PMC byte counters are
+    scaled by, and the mark after which profiled dispatches count."""
+    src = torch.empty(COPY_PROBE_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def magnetic_work(n, S, nclass3, M, g0, cnt, nh, friedel):
     """Algorithmic flops and bytes of one magnetic recombination launch (spin spectra, one
     form factor for every site):
@@ -275,7 +311,7 @@ def magnetic_work(n, S, nclass3, M, g0, cnt, nh, friedel):
     return flops, bytes_
 
 
-def bench_magnetic(dsx, torch, dev, steps, warmup, O=None):
+def bench_magnetic(dsx, torch, dev, steps, warmup, O=None, probe=False):
     """The magnetic workload: pyrochlore, 16 sites, 24^3 supercell, unit spins with a
     nearest-neighbour correlated component, magnetic form factor, perpendicular
     projection, |h|,|k|,|l| <= 6 (289^3 voxels).  One step = set_sites_async (device copy)
@@ -297,6 +333,8 @@ def bench_magnetic(dsx, torch, dev, steps, warmup, O=None):
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
+    if probe:
+        copy_probe(torch, dev)
     dsx.profile_reset()
     dsx.profile_select("recombine")
     dsx.profile_enable(True)
@@ -317,7 +355,11 @@ def bench_magnetic(dsx, torch, dev, steps, warmup, O=None):
     res = {"workload": "magnetic pyrochlore 16 sites/cell, 24^3 supercell, unit spins (nearest-neighbour "
                        "correlated), form factor (0.4,20,0.5,7,0.1,2,0), |h|,|k|,|l|<=6 (289^3 voxels)",
            "voxels_per_step": vox, "ms_per_step": round(sec * 1e3, 4), "voxels_per_s": round(vox / sec, 1),
-           "roofline": roofline(flops, bytes_, t_launch, "recombine_magnetic", stored_trace_avg("k_recombine_magnetic"))}
+           "roofline": roofline(flops, bytes_, t_launch, "recombine_magnetic",
+                                stored_trace_avg("magnetic24", "k_recombine_magnetic"))}
+    tr = stored_traffic("magnetic24")
+    if tr is not None:
+        res["roofline"]["traffic"] = int(tr["traffic_bytes"])
     if O is not None:
         rng = np.random.default_rng([3, 0, 777])
         G = np.stack([rng.integers(m.g0[a], m.g0[a] + count[a], 512) for a in range(3)], -1)
@@ -423,7 +465,7 @@ def bench_compositional(dsx, torch, dev, steps, O=None, seeds=1024):
     return res
 
 
-def bench_ensemble(dsx, torch, dev, steps, warmup, lm=2):
+def bench_ensemble(dsx, torch, dev, steps, warmup, lm=2, probe=False, batched_only=False):
     """Batched ensemble (8 models x 8 configurations, edges from {16,20,24,32,40}, 1-4
     sites, Taylor order 6, |h|,|k|,|l| <= 4, Lanczos filter): one graph replay against the
     plain path that calls noise_filter model by model.  Both steps first upload every
@@ -477,6 +519,10 @@ def bench_ensemble(dsx, torch, dev, steps, warmup, lm=2):
         upload()
         batch.run()
 
+    if probe:
+        for _ in range(warmup):
+            batched()
+        copy_probe(torch, dev)
     t_batch = timed(batched)
     same = all(torch.equal(a, b) for a, b in zip(ref, outs))
     batch.close()
@@ -644,9 +690,11 @@ def main():
                     help="issue one plain device copy of known size (reference for PMC byte counters)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the traffic summary from two rocprofv3 --pmc output folders and exit")
-    ap.add_argument("--pmc-command", default="", help="command line recorded in the traffic summary")
+    ap.add_argument("--pmc-command", default="", help="command line recorded in the summary")
     ap.add_argument("--summarize-ktrace", metavar="TRACE_DIR",
                     help="write the kernel-time summary from a rocprofv3 --kernel-trace --stats folder and exit")
+    ap.add_argument("--profile-name", default="displacive32_order8", choices=sorted(WORKLOADS),
+                    help="workload the summary covers (names the file under profiles/)")
     ap.add_argument("--only-steps", action="store_true",
                     help="time the filtered steps only (no unfiltered pass, sweep, ensemble, serving or "
                          "CPU baseline): the run the profiles are taken from")
@@ -665,10 +713,10 @@ def main():
     ap.add_argument("--compositional-only", action="store_true", help="time only the compositional workload")
     args = ap.parse_args()
     if args.summarize_ktrace:
-        print(summarize_ktrace(args.summarize_ktrace, KTRACE_MD, args.pmc_command))
+        print(summarize_ktrace(args.summarize_ktrace, args.profile_name, args.pmc_command))
         return
     if args.summarize_pmc:
-        print(json.dumps(summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], TRAFFIC_MD,
+        print(json.dumps(summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.profile_name,
                                        args.pmc_command)))
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -684,13 +732,15 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.ensemble_only:
-        print(json.dumps({"ensemble": bench_ensemble(dsx, torch, dev, args.steps, args.warmup)}))
+        print(json.dumps({"ensemble": bench_ensemble(dsx, torch, dev, args.steps, args.warmup,
+                                                     probe=args.copy_probe)}))
         return
     if args.serving_only:
         print(json.dumps({"serving": bench_serving(dsx, torch, dev, args.serve_seconds)}))
         return
     if args.magnetic_only:
-        print(json.dumps({"magnetic": bench_magnetic(dsx, torch, dev, args.steps, args.warmup)}))
+        print(json.dumps({"magnetic": bench_magnetic(dsx, torch, dev, args.steps, args.warmup,
+                                                     probe=args.copy_probe)}))
         return
     if args.compositional_only:
         print(json.dumps({"compositional": bench_compositional(dsx, torch, dev, args.steps)}))
@@ -725,11 +775,7 @@ def main():
     # the probe also marks where profiled dispatches start counting: after the tuning
     # and the warm-up (the recombination needs some 20 steps to reach its steady time)
     if args.copy_probe:
-        src = torch.empty(COPY_PROBE_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        copy_probe(torch, dev)
     # HIP events bracket only the dominant kernel inside the timed region (events
     # around every launch add about 30 us to a step)
     dsx.profile_reset()
@@ -773,8 +819,8 @@ def main():
                                    info.fields_per_site, friedel=sym)
     launches, tot_ms = kstats.get("recombine", (0, float("nan")))
     t_launch = tot_ms / max(launches, 1) / 1e3
-    roof = roofline(flops, bytes_, t_launch, "recombine", stored_trace_avg("k_recombine"))
-    tr = stored_traffic()
+    roof = roofline(flops, bytes_, t_launch, "recombine", stored_trace_avg("displacive32_order8", "k_recombine"))
+    tr = stored_traffic("displacive32_order8")
     if tr is not None:
         roof["traffic"] = int(tr["traffic_bytes"])
     kernels = {k: {"launches": v[0], "avg_ms": round(v[1] / max(v[0], 1), 4)} for k, v in kall.items()}
