@@ -23,6 +23,10 @@
  *   orc_dw_mean      the Debye-Waller factor T_mu(G) of Sec. III.A, Eq. dw: the mean of
  *                    e^{i G.u} over the occupied atoms of a site, every cell and every
  *                    configuration (exact or order-N Taylor polynomial).
+ *   orc_subbox       the method of sub-boxes of Sec. V.A: every lattice point the origin of
+ *                    an open-boundary sub-box, |F|^2 and F averaged over origins and
+ *                    configurations at arbitrary Q (the slow reference the Lanczos filter
+ *                    of Sec. V.B is compared with).
  *   orc_pair_sum     (1/N) sum_{j,k} b_j b_k e^{i Q.(r_j - r_k)} with the
  *                    nearest-image convention (Sec. II, Eq. intensity_dble_sum).
  *   orc_lanczos      the windowed-sinc resampling of Sec. V.B (Eqs.
@@ -213,6 +217,79 @@ int orc_dw_mean(const int32_t* n, int32_t S, int32_t M, const float* occ, const 
             o[0] = wsum != 0.0 ? tr / wsum : 0.0;
             o[1] = wsum != 0.0 ? ti / wsum : 0.0;
         }
+    }
+    return 0;
+}
+
+/* Method of sub-boxes (Sec. V.A): every lattice point R0 of the supercell is the origin
+ * of a sub-box of nsb[0] x nsb[1] x nsb[2] unit cells with open boundaries (its cells
+ * R0 + d, 0 <= d_a < nsb_a, taken from the periodic supercell, their positions
+ * R0 + d + r_mu + u not folded back), and
+ *   F_sb(Q) = sum_{d, mu} b_mu delta e^{2 pi i Q.(d + r_mu + u)}
+ * at arbitrary Q (reciprocal-lattice units: Q.x = sum_a Q_a x_a for x in unit-cell
+ * coordinates; the common phase e^{2 pi i Q.R0} drops out of |F|^2 and is left out).
+ * Outputs, averaged over every origin and configuration:
+ *   sq[nQ]        < |F_sb(Q)|^2 >
+ *   mean[nQ][2]   < F_sb(Q) >
+ * exact mode (order < 0) or the order-N Taylor polynomial of e^{2 pi i Q.u}.
+ * occ/disp as orc_sf_nuclear; nsb_a in [1, n_a]. */
+int orc_subbox(const int32_t* n, int32_t S, const double* frac, const double* b, int32_t M,
+               const float* occ, const float* disp, int32_t order, const int32_t* nsb,
+               int64_t nQ, const double* Q, double* sq, double* mean)
+{
+    if (bad_dims(n) || S < 1 || M < 1 || nQ < 0 || !frac || !b || !nsb || !Q || !sq || !mean) return -1;
+    for (int a = 0; a < 3; ++a)
+        if (nsb[a] < 1 || nsb[a] > n[a]) return -1;
+    const long n1 = n[0], n2 = n[1], n3 = n[2];
+    const long ncell = n1 * n2 * n3;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t qi = 0; qi < nQ; ++qi) {
+        const double* q = Q + 3 * qi;
+        double acc_sq = 0.0, acc_r = 0.0, acc_i = 0.0;
+        for (int32_t m = 0; m < M; ++m)
+        for (long R1 = 0; R1 < n1; ++R1)
+        for (long R2 = 0; R2 < n2; ++R2)
+        for (long R3 = 0; R3 < n3; ++R3) {
+            double fr = 0.0, fi = 0.0;
+            for (int32_t mu = 0; mu < S; ++mu)
+            for (long d1 = 0; d1 < nsb[0]; ++d1)
+            for (long d2 = 0; d2 < nsb[1]; ++d2)
+            for (long d3 = 0; d3 < nsb[2]; ++d3) {
+                const long cell = (((R1 + d1) % n1) * n2 + (R2 + d2) % n2) * n3 + (R3 + d3) % n3;
+                const long at = ((long)m * S + mu) * ncell + cell;
+                const double delta = occ ? (double)occ[at] : 1.0;
+                if (delta == 0.0) continue;
+                const double x = q[0] * (d1 + frac[3 * mu]) + q[1] * (d2 + frac[3 * mu + 1]) +
+                                 q[2] * (d3 + frac[3 * mu + 2]);
+                double gu = 0.0;
+                if (disp) {
+                    const float* u = disp + 3 * at;
+                    gu = q[0] * u[0] + q[1] * u[1] + q[2] * u[2];
+                }
+                double er, ei;
+                if (order < 0) {
+                    er = cos(TWO_PI * (x + gu)); ei = sin(TWO_PI * (x + gu));
+                } else {
+                    const double c = cos(TWO_PI * x), s = sin(TWO_PI * x), y = TWO_PI * gu;
+                    double pr = 1.0, pi = 0.0, tr = 0.0, ti = 0.0;
+                    for (int k = 0; k <= order; ++k) {
+                        tr += pr; ti += pi;
+                        const double nr = -pi * y / (k + 1), ni = pr * y / (k + 1);
+                        pr = nr; pi = ni;
+                    }
+                    er = c * tr - s * ti; ei = c * ti + s * tr;
+                }
+                fr += b[mu] * delta * er;
+                fi += b[mu] * delta * ei;
+            }
+            acc_sq += fr * fr + fi * fi;
+            acc_r += fr;
+            acc_i += fi;
+        }
+        const double cnt = (double)M * ncell;
+        sq[qi] = acc_sq / cnt;
+        mean[2 * qi] = acc_r / cnt;
+        mean[2 * qi + 1] = acc_i / cnt;
     }
     return 0;
 }

@@ -79,6 +79,7 @@ def lib():
         L.orc_sf_nuclear.argtypes = [P, i32, P, P, i32, P, P, i32, i64, P, P]
         L.orc_sf_magnetic.argtypes = [P, i32, P, P, i32, P, P, i64, P, P]
         L.orc_dw_mean.argtypes = [P, i32, i32, P, P, i32, i64, P, P]
+        L.orc_subbox.argtypes = [P, i32, P, P, i32, P, P, i32, P, i64, P, P, P]
         L.orc_pair_sum.argtypes = [P, i32, P, P, P, P, f64, i64, P, P]
         L.orc_lanczos.argtypes = [i32, i32, P, P, P, P, P, P]
         L.orc_lanczos_cutoff.argtypes = [i32, i32, i32, P, P, P, P, P, P]
@@ -86,7 +87,7 @@ def lib():
         L.orc_lanczos_spherical.argtypes = [i32, i32, P, P, P, P, P, P, P, f64, P]
         L.orc_ball_ft.argtypes = [f64]
         L.orc_ball_ft.restype = f64
-        for f in (L.orc_sf_nuclear, L.orc_sf_magnetic, L.orc_dw_mean, L.orc_pair_sum, L.orc_lanczos,
+        for f in (L.orc_sf_nuclear, L.orc_sf_magnetic, L.orc_dw_mean, L.orc_subbox, L.orc_pair_sum, L.orc_lanczos,
                   L.orc_lanczos_cutoff, L.orc_lanczos_points, L.orc_lanczos_spherical):
             f.restype = ctypes.c_int
         _lib = L
@@ -302,6 +303,39 @@ def pair_sum(model, member, G) -> np.ndarray:
     if rc != 0:
         raise ValueError("orc_pair_sum rejected its arguments")
     return out[:, 0] + 1j * out[:, 1]
+
+
+def subbox_moments(model, Q, nsb, order=None):
+    """Method of sub-boxes (Sec. V.A) for a nuclear model: every lattice point is the
+    origin of an open-boundary sub-box of nsb = (nsb1, nsb2, nsb3) unit cells; returns
+    (< |F_sb(Q)|^2 >, < F_sb(Q) >) averaged over origins and configurations at the points
+    Q [nQ][3] (reciprocal-lattice units, any values).  order=None: the model's Taylor
+    order when it has displacements; -1: exact."""
+    assert model.kind == NUCLEAR
+    if order is None:
+        order = model.order if model.disp is not None else -1
+    Q = np.ascontiguousarray(Q, dtype=np.float64).reshape(-1, 3)
+    n = np.ascontiguousarray(model.n, dtype=np.int32)
+    nsb = np.ascontiguousarray(nsb, dtype=np.int32).reshape(3)
+    occ = None if model.occ is None else np.ascontiguousarray(model.occ, dtype=np.float32)
+    disp = None if model.disp is None else np.ascontiguousarray(model.disp, dtype=np.float32)
+    sq = np.zeros(len(Q))
+    mean = np.zeros((len(Q), 2))
+    rc = lib().orc_subbox(_ptr(n), model.n_sites, _ptr(np.ascontiguousarray(model.frac, dtype=np.float64)),
+                          _ptr(np.ascontiguousarray(model.b, dtype=np.float64)), model.n_configs, _ptr(occ),
+                          _ptr(disp), int(order), _ptr(nsb), len(Q), _ptr(Q), _ptr(sq), _ptr(mean))
+    if rc != 0:
+        raise ValueError("orc_subbox rejected its arguments")
+    return sq, mean[:, 0] + 1j * mean[:, 1]
+
+
+def subbox_intensity(model, Q, nsb, order=None) -> np.ndarray:
+    """Diffuse intensity by the method of sub-boxes: (1/N_sb) [<|F_sb|^2> - |<F_sb>|^2],
+    N_sb = nsb1 nsb2 nsb3 x number of distinct positions (the mean structure of the
+    sub-boxes removed at every Q, since an open box spreads the Bragg peaks)."""
+    sq, mean = subbox_moments(model, Q, nsb, order)
+    npos = model.n_sites if model.pos_id is None else len(np.unique(model.pos_id))
+    return (sq - np.abs(mean) ** 2) / (float(np.prod(nsb)) * npos)
 
 
 def lanczos(I_ext, e0, m, s, q0, qcount, mprime=2) -> np.ndarray:

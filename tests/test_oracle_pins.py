@@ -624,3 +624,70 @@ def test_sampled_windows_match_the_box_filter():
         idx = edge_sample_indices(m.count, 40, 1)
         got = oracle_filtered_at(m, idx + np.asarray(m.g0), 2, mp, sph)
         assert np.allclose(got, ref[tuple(idx.T)], rtol=1e-13, atol=1e-15)
+
+
+# ------------------------------------------------- the method of sub-boxes (Sec. V.A)
+
+def _autocorrelation(occ):
+    """A(k) = mean over configurations of (1/N) sum_R delta(R) delta(R + k), periodic,
+    by brute force over every shift k."""
+    M, n = occ.shape[0], occ.shape[1:]
+    A = np.zeros(n)
+    for k in itertools.product(*[range(v) for v in n]):
+        A[k] = np.mean([np.mean(occ[m] * np.roll(occ[m], [-v for v in k], axis=(0, 1, 2))) for m in range(M)])
+    return A
+
+
+def test_subbox_applies_the_triangular_cutoff():
+    """Sec. V.A: with every lattice point a sub-box origin, the number of pairs at a
+    separation of k cells inside a box of nsb cells is nsb - |k| per axis, so
+    <|F_sb(Q)|^2> = b^2 sum_k prod_a (nsb_a - |k_a|) A(k) e^{2 pi i Q.k} -- the periodic
+    pair correlations under a triangular cutoff that reaches 0 at |k_a| = nsb_a -- and
+    <F_sb(Q)> = b c sum_d e^{2 pi i Q.(d + r)} with c the mean occupancy."""
+    n, nsb = (6, 5, 4), (3, 2, 3)
+    m = synth.compositional(n=n, M=2, hmax=1, frac=np.array([[0.13, 0.29, 0.41]]), b=np.array([0.8]))
+    Q = np.random.default_rng(9).uniform(-1.3, 1.7, (12, 3))
+    sq, mean = O.subbox_moments(m, Q, nsb)
+    A = _autocorrelation(m.occ[:, 0].astype(np.float64))
+    ks = list(itertools.product(*[range(-(v - 1), v) for v in nsb]))
+    tri = np.array([np.prod([nsb[a] - abs(k[a]) for a in range(3)]) for k in ks])
+    Ak = np.array([A[tuple(k[a] % n[a] for a in range(3))] for k in ks])
+    ph = np.exp(2j * np.pi * Q @ np.array(ks).T)
+    expect = 0.8 ** 2 * (ph * (tri * Ak)[None]).sum(axis=1)
+    assert np.allclose(sq, expect.real, rtol=1e-11, atol=1e-11) and np.max(np.abs(expect.imag)) < 1e-9
+    c = float(m.occ.astype(np.float64).mean())
+    d = np.array(list(itertools.product(*[range(v) for v in nsb])))
+    fm = 0.8 * c * np.exp(2j * np.pi * Q @ (d + m.frac[0]).T).sum(axis=1)
+    assert np.allclose(mean, fm, rtol=1e-11, atol=1e-12)
+
+
+def test_subbox_rigid_shift_moves_the_site():
+    """Exact mode: one displacement u0 for every atom of a site is the site at r + u0."""
+    m = synth.random_model(74, n=(3, 4, 3), S=2, M=2, order=0, with_disp=False)
+    m.disp = np.zeros((2, 2, 3, 4, 3, 3), np.float32)
+    m.disp[:, 1] = np.array([0.07, -0.11, 0.05], np.float32)
+    Q = np.random.default_rng(2).uniform(-1, 1, (9, 3))
+    a = O.subbox_intensity(m, Q, (2, 3, 2), order=-1)
+    s = synth.random_model(74, n=(3, 4, 3), S=2, M=2, order=0, with_disp=False)
+    s.frac = m.frac + np.array([[0, 0, 0], m.disp[0, 1, 0, 0, 0].astype(np.float64)])
+    assert np.allclose(a, O.subbox_intensity(s, Q, (2, 3, 2)), rtol=1e-11, atol=1e-13)
+
+
+def test_lanczos_m2_cutoff_is_close_to_the_subbox_triangle():
+    """Sec. V.B: the m = 2 filter's effective cutoff resembles a smoothed triangle -- the
+    sub-box cutoff 1 - |dr| n/nsb with nsb = n/2, i.e. 1 - 2|dr| -- and its intensities
+    resemble the sub-box ones far more than the unfiltered supercell Bragg points do."""
+    for dr in np.linspace(0.0, 0.5, 11):
+        assert abs(_cosine_response_mean(2, dr) - (1 - 2 * dr)) < 0.16
+    n = (12, 12, 12)
+    rng = np.random.default_rng(3)
+    occ = np.stack([(synth._periodic_gaussian_smooth(rng.normal(size=n), 1.0) > 0) for _ in range(2)])
+    mdl = synth.Model(cell=np.array([1.0, 1, 1, 90, 90, 90]), n=n, frac=np.zeros((1, 3)), b=np.ones(1),
+                      occ=occ[:, None].astype(np.float32))
+    h = np.linspace(0.05, 1.95, 39)
+    Q = np.stack([h, 0.5 * h, np.full_like(h, 0.3)], -1)
+    sb = O.subbox_intensity(mdl, Q, (6, 6, 6))
+    lz = O.filtered_points(mdl, 2, Q * np.asarray(n))
+    near = O.intensity(mdl, np.round(Q * np.asarray(n)).astype(np.int32))
+    rel = lambda a: np.linalg.norm(a - sb) / np.linalg.norm(sb)
+    assert rel(lz) < 0.3 and rel(lz) < 0.5 * rel(near)
