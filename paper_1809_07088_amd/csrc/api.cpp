@@ -31,6 +31,7 @@
 
 #include "dsx.h"
 #include "dsx_internal.h"
+#include "arena.h"
 
 using namespace dsx;
 
@@ -44,6 +45,23 @@ dsx_status fail(dsx_status s, const std::string& msg)
 {
     g_err = msg;
     return s;
+}
+
+// Host failures (allocation, thread creation) never cross the C-ABI as exceptions: every
+// entry point runs its body through guarded(), which turns them into DSX_ERR_NOMEM.
+template <typename F>
+dsx_status guarded(F&& f) noexcept
+{
+    try {
+        return f();
+    } catch (...) {
+        try {
+            g_err = "host allocation or resource failure";
+        } catch (...) {
+            g_err.clear();
+        }
+        return DSX_ERR_NOMEM;
+    }
 }
 
 // ---------------------------------------------------------------------------- instrumentation
@@ -623,8 +641,13 @@ dsx_status tables_for(dsx_model m, const Box& bx, DeviceTables** out)
         m->failed = true;
         return fail(DSX_ERR_DEVICE, std::string("phase tables: ") + hipGetErrorString(e));
     }
-    auto ins = m->tables.emplace(bx, t);
-    *out = &ins.first->second;
+    try {
+        auto ins = m->tables.emplace(bx, t);
+        *out = &ins.first->second;
+    } catch (...) {
+        free_tables(t);
+        throw;
+    }
     return DSX_OK;
 }
 
@@ -920,7 +943,18 @@ dsx_status dsx_profile_select(const char* kernel)
     return DSX_OK;
 }
 
+static int32_t profile_read_impl(dsx_kernel_stat* out, int32_t max);
+
 int32_t dsx_profile_read(dsx_kernel_stat* out, int32_t max)
+{
+    try {
+        return profile_read_impl(out, max);
+    } catch (...) {
+        return 0;
+    }
+}
+
+static int32_t profile_read_impl(dsx_kernel_stat* out, int32_t max)
 {
     std::lock_guard<std::mutex> lk(g_prof.mu);
     for (auto& p : g_prof.pending) {
@@ -959,22 +993,26 @@ const char* dsx_last_error(void) { return g_err.c_str(); }
 
 dsx_status dsx_plan_query(const dsx_model_desc* d, dsx_plan_info* info)
 {
-    dsx_status s = validate_desc(d);
-    if (s != DSX_OK) return s;
-    if (!info) return fail(DSX_ERR_ARG, "info is NULL");
-    const Sizes z = sizes_of(d);
-    info->fields_per_site = z.F;
-    info->total_fields = d->n_configs * d->n_sites * z.F;
-    info->n_classes = z.nclass;
-    info->reserved = 0;
-    info->spectrum_bytes = z.spectrum_bytes;
-    info->device_bytes = z.device_bytes;
-    return DSX_OK;
+    return guarded([&]() -> dsx_status {
+        dsx_status s = validate_desc(d);
+        if (s != DSX_OK) return s;
+        if (!info) return fail(DSX_ERR_ARG, "info is NULL");
+        const Sizes z = sizes_of(d);
+        info->fields_per_site = z.F;
+        info->total_fields = d->n_configs * d->n_sites * z.F;
+        info->n_classes = z.nclass;
+        info->reserved = 0;
+        info->spectrum_bytes = z.spectrum_bytes;
+        info->device_bytes = z.device_bytes;
+        return DSX_OK;
+    });
 }
 
 }  // extern "C"
 
 namespace {
+
+dsx_status create_model_body(const dsx_model_desc* d, bool transient, dsx_model m, dsx_model* out);
 
 // Builds a model; `transient` leaves the spectra and partial-sum buffers to a server.
 dsx_status create_model_impl(const dsx_model_desc* d, bool transient, dsx_model* out)
@@ -985,6 +1023,25 @@ dsx_status create_model_impl(const dsx_model_desc* d, bool transient, dsx_model*
     *out = nullptr;
     dsx_model m = new (std::nothrow) dsx_model_s();
     if (!m) return fail(DSX_ERR_NOMEM, "host allocation failed");
+    dsx_status st;
+    try {
+        st = create_model_body(d, transient, m, out);
+    } catch (...) {
+        free_model(m);
+        delete m;
+        throw;
+    }
+    if (st != DSX_OK) {
+        free_model(m);
+        delete m;
+    }
+    return st;
+}
+
+// The model's description, plan and device state; on failure create_model_impl
+// releases whatever it allocated.
+dsx_status create_model_body(const dsx_model_desc* d, bool transient, dsx_model m, dsx_model* out)
+{
     std::memcpy(m->cell, d->cell, sizeof(m->cell));
     for (int a = 0; a < 3; ++a) m->n[a] = d->n[a];
     m->S = d->n_sites; m->kind = d->kind; m->has_occ = d->has_occ ? 1 : 0;
@@ -1076,8 +1133,6 @@ dsx_status create_model_impl(const dsx_model_desc* d, bool transient, dsx_model*
         if (e == hipSuccess) e = hipMemcpy(m->d_tw[a], tw.data(), sizeof(float2) * n, hipMemcpyHostToDevice);
     }
     if (e != hipSuccess) {
-        free_model(m);
-        delete m;
         (void)hipGetLastError();
         if (e == hipErrorOutOfMemory) return fail(DSX_ERR_NOMEM, "out of device memory for the model");
         return fail(DSX_ERR_DEVICE, std::string("create_model: ") + hipGetErrorString(e));
@@ -1101,111 +1156,121 @@ extern "C" {
 
 dsx_status dsx_create_model(const dsx_model_desc* d, dsx_model* out)
 {
-    return create_model_impl(d, false, out);
+    return guarded([&]() -> dsx_status {
+        return create_model_impl(d, false, out);
+    });
 }
 
 dsx_status dsx_set_sites(dsx_model m, int32_t config, const float* occ, const float* disp,
                          const float* spin, int32_t where)
 {
-    dsx_status s = check_model(m);
-    if (s != DSX_OK) return s;
-    if (config < 0 || config >= m->M) return fail(DSX_ERR_ARG, "config out of range");
-    if (where != DSX_HOST && where != DSX_DEVICE) return fail(DSX_ERR_ARG, "bad 'where'");
-    if (m->has_occ && !occ) return fail(DSX_ERR_ARG, "occ is required (has_occ != 0)");
-    const float* vec = m->kind == DSX_MAGNETIC ? spin : disp;
-    const bool need_vec = m->kind == DSX_MAGNETIC || m->order > 0;
-    if (need_vec && !vec)
-        return fail(DSX_ERR_ARG, m->kind == DSX_MAGNETIC ? "spin is required" : "disp is required (taylor_order > 0)");
-    if (m->dw_order > 0 && !disp) return fail(DSX_ERR_ARG, "disp is required (taylor_order > 0)");
-    if (m->queued.load() > 0) return fail(DSX_ERR_BUSY, "the model has requests queued at its server");
-    HIPCHK(m, hipStreamSynchronize(m->last_stream));   // no pending work still reads the inputs
-    const hipMemcpyKind kind = where == DSX_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
-    const size_t per = (size_t)m->S * m->ncell;
-    if (m->has_occ) HIPCHK(m, hipMemcpy(m->d_occ + per * config, occ, per * sizeof(float), kind));
-    if (need_vec) HIPCHK(m, hipMemcpy(m->d_vec + 3 * per * config, vec, 3 * per * sizeof(float), kind));
-    if (m->dw_order > 0) HIPCHK(m, hipMemcpy(m->d_dsp + 3 * per * config, disp, 3 * per * sizeof(float), kind));
-    if (where == DSX_DEVICE) HIPCHK(m, hipStreamSynchronize(nullptr));
-    m->set[config] = 1;
-    m->dirty = true;
-    return DSX_OK;
+    return guarded([&]() -> dsx_status {
+        dsx_status s = check_model(m);
+        if (s != DSX_OK) return s;
+        if (config < 0 || config >= m->M) return fail(DSX_ERR_ARG, "config out of range");
+        if (where != DSX_HOST && where != DSX_DEVICE) return fail(DSX_ERR_ARG, "bad 'where'");
+        if (m->has_occ && !occ) return fail(DSX_ERR_ARG, "occ is required (has_occ != 0)");
+        const float* vec = m->kind == DSX_MAGNETIC ? spin : disp;
+        const bool need_vec = m->kind == DSX_MAGNETIC || m->order > 0;
+        if (need_vec && !vec)
+            return fail(DSX_ERR_ARG, m->kind == DSX_MAGNETIC ? "spin is required" : "disp is required (taylor_order > 0)");
+        if (m->dw_order > 0 && !disp) return fail(DSX_ERR_ARG, "disp is required (taylor_order > 0)");
+        if (m->queued.load() > 0) return fail(DSX_ERR_BUSY, "the model has requests queued at its server");
+        HIPCHK(m, hipStreamSynchronize(m->last_stream));   // no pending work still reads the inputs
+        const hipMemcpyKind kind = where == DSX_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+        const size_t per = (size_t)m->S * m->ncell;
+        if (m->has_occ) HIPCHK(m, hipMemcpy(m->d_occ + per * config, occ, per * sizeof(float), kind));
+        if (need_vec) HIPCHK(m, hipMemcpy(m->d_vec + 3 * per * config, vec, 3 * per * sizeof(float), kind));
+        if (m->dw_order > 0) HIPCHK(m, hipMemcpy(m->d_dsp + 3 * per * config, disp, 3 * per * sizeof(float), kind));
+        if (where == DSX_DEVICE) HIPCHK(m, hipStreamSynchronize(nullptr));
+        m->set[config] = 1;
+        m->dirty = true;
+        return DSX_OK;
+    });
 }
 
 dsx_status dsx_set_sites_async(dsx_model m, int32_t config, const float* occ, const float* disp,
                                const float* spin, void* hip_stream)
 {
-    dsx_status s = check_model(m);
-    if (s != DSX_OK) return s;
-    if (config < 0 || config >= m->M) return fail(DSX_ERR_ARG, "config out of range");
-    if (m->has_occ && !occ) return fail(DSX_ERR_ARG, "occ is required (has_occ != 0)");
-    const float* vec = m->kind == DSX_MAGNETIC ? spin : disp;
-    const bool need_vec = m->kind == DSX_MAGNETIC || m->order > 0;
-    if (need_vec && !vec)
-        return fail(DSX_ERR_ARG, m->kind == DSX_MAGNETIC ? "spin is required" : "disp is required (taylor_order > 0)");
-    if (m->dw_order > 0 && !disp) return fail(DSX_ERR_ARG, "disp is required (taylor_order > 0)");
-    if (m->server) return fail(DSX_ERR_STATE, "the model belongs to a server: its requests carry the sites");
-    hipStream_t st = (hipStream_t)hip_stream;
-    if ((s = follow(m, st)) != DSX_OK) return s;     // after every earlier use of the inputs
-    const size_t per = (size_t)m->S * m->ncell;
-    if (m->has_occ)
-        HIPCHK(m, hipMemcpyAsync(m->d_occ + per * config, occ, per * sizeof(float), hipMemcpyDeviceToDevice, st));
-    if (need_vec)
-        HIPCHK(m, hipMemcpyAsync(m->d_vec + 3 * per * config, vec, 3 * per * sizeof(float), hipMemcpyDeviceToDevice, st));
-    if (m->dw_order > 0)
-        HIPCHK(m, hipMemcpyAsync(m->d_dsp + 3 * per * config, disp, 3 * per * sizeof(float), hipMemcpyDeviceToDevice, st));
-    m->set[config] = 1;
-    m->dirty = true;
-    return DSX_OK;
+    return guarded([&]() -> dsx_status {
+        dsx_status s = check_model(m);
+        if (s != DSX_OK) return s;
+        if (config < 0 || config >= m->M) return fail(DSX_ERR_ARG, "config out of range");
+        if (m->has_occ && !occ) return fail(DSX_ERR_ARG, "occ is required (has_occ != 0)");
+        const float* vec = m->kind == DSX_MAGNETIC ? spin : disp;
+        const bool need_vec = m->kind == DSX_MAGNETIC || m->order > 0;
+        if (need_vec && !vec)
+            return fail(DSX_ERR_ARG, m->kind == DSX_MAGNETIC ? "spin is required" : "disp is required (taylor_order > 0)");
+        if (m->dw_order > 0 && !disp) return fail(DSX_ERR_ARG, "disp is required (taylor_order > 0)");
+        if (m->server) return fail(DSX_ERR_STATE, "the model belongs to a server: its requests carry the sites");
+        hipStream_t st = (hipStream_t)hip_stream;
+        if ((s = follow(m, st)) != DSX_OK) return s;     // after every earlier use of the inputs
+        const size_t per = (size_t)m->S * m->ncell;
+        if (m->has_occ)
+            HIPCHK(m, hipMemcpyAsync(m->d_occ + per * config, occ, per * sizeof(float), hipMemcpyDeviceToDevice, st));
+        if (need_vec)
+            HIPCHK(m, hipMemcpyAsync(m->d_vec + 3 * per * config, vec, 3 * per * sizeof(float), hipMemcpyDeviceToDevice, st));
+        if (m->dw_order > 0)
+            HIPCHK(m, hipMemcpyAsync(m->d_dsp + 3 * per * config, disp, 3 * per * sizeof(float), hipMemcpyDeviceToDevice, st));
+        m->set[config] = 1;
+        m->dirty = true;
+        return DSX_OK;
+    });
 }
 
 dsx_status dsx_set_grid(dsx_model m, const int32_t g0[3], const int32_t count[3])
 {
-    dsx_status s = check_model(m);
-    if (s != DSX_OK) return s;
-    if (!g0 || !count) return fail(DSX_ERR_ARG, "g0 and count are required");
-    if (m->pins) return fail(DSX_ERR_BUSY, "the model is recorded in a batch; destroy the batch first");
-    if (m->queued.load() > 0) return fail(DSX_ERR_BUSY, "the model has requests queued at its server");
-    Box bx;
-    long long vox = 1;
-    for (int a = 0; a < 3; ++a) {
-        if (count[a] < 1) return fail(DSX_ERR_ARG, "count must be >= 1 on every axis");
-        if (std::llabs((long long)g0[a]) > (1LL << 24) || count[a] > (1 << 24))
-            return fail(DSX_ERR_UNSUPPORTED, "box coordinates too large");
-        bx.g0[a] = g0[a]; bx.cnt[a] = count[a];
-        vox *= count[a];
-    }
-    if (vox > (1LL << 34)) return fail(DSX_ERR_UNSUPPORTED, "box too large");
-    m->box = bx;
-    m->grid_set = true;
-    // prepare the box's phase tables now, so that a compute call that may not allocate
-    // finds them; a box the recombination cannot take is still reported by the compute
-    // calls, as before
-    DeviceTables* tb = nullptr;
-    if (tables_for(m, bx, &tb) != DSX_OK) {
-        if (m->failed) return DSX_ERR_DEVICE;
-        g_err.clear();
-    }
-    return DSX_OK;
+    return guarded([&]() -> dsx_status {
+        dsx_status s = check_model(m);
+        if (s != DSX_OK) return s;
+        if (!g0 || !count) return fail(DSX_ERR_ARG, "g0 and count are required");
+        if (m->pins) return fail(DSX_ERR_BUSY, "the model is recorded in a batch; destroy the batch first");
+        if (m->queued.load() > 0) return fail(DSX_ERR_BUSY, "the model has requests queued at its server");
+        Box bx;
+        long long vox = 1;
+        for (int a = 0; a < 3; ++a) {
+            if (count[a] < 1) return fail(DSX_ERR_ARG, "count must be >= 1 on every axis");
+            if (std::llabs((long long)g0[a]) > (1LL << 24) || count[a] > (1 << 24))
+                return fail(DSX_ERR_UNSUPPORTED, "box coordinates too large");
+            bx.g0[a] = g0[a]; bx.cnt[a] = count[a];
+            vox *= count[a];
+        }
+        if (vox > (1LL << 34)) return fail(DSX_ERR_UNSUPPORTED, "box too large");
+        m->box = bx;
+        m->grid_set = true;
+        // prepare the box's phase tables now, so that a compute call that may not allocate
+        // finds them; a box the recombination cannot take is still reported by the compute
+        // calls, as before
+        DeviceTables* tb = nullptr;
+        if (tables_for(m, bx, &tb) != DSX_OK) {
+            if (m->failed) return DSX_ERR_DEVICE;
+            g_err.clear();
+        }
+        return DSX_OK;
+    });
 }
 
 dsx_status dsx_compute_intensity(dsx_model m, float* out, int32_t where, void* hip_stream)
 {
-    dsx_status s = check_direct(m);
-    if (s != DSX_OK) return s;
-    if (!out) return fail(DSX_ERR_ARG, "out is NULL");
-    if (where != DSX_HOST && where != DSX_DEVICE) return fail(DSX_ERR_ARG, "bad 'where'");
-    if ((s = ready(m)) != DSX_OK) return s;
-    hipStream_t st = (hipStream_t)hip_stream;
-    const size_t vox = (size_t)m->box.cnt[0] * m->box.cnt[1] * m->box.cnt[2];
-    float* dout = out;
-    if (where == DSX_HOST && (s = stage(m, vox, &dout)) != DSX_OK) return s;
-    if ((s = prepare_intensity(m)) != DSX_OK) return s;
-    if ((s = follow(m, st)) != DSX_OK) return s;
-    if ((s = enqueue_intensity(m, dout, st, false)) != DSX_OK) return s;
-    if (where == DSX_HOST) {
-        HIPCHK(m, hipMemcpyAsync(out, dout, vox * sizeof(float), hipMemcpyDeviceToHost, st));
-        HIPCHK(m, hipStreamSynchronize(st));
-    }
-    return DSX_OK;
+    return guarded([&]() -> dsx_status {
+        dsx_status s = check_direct(m);
+        if (s != DSX_OK) return s;
+        if (!out) return fail(DSX_ERR_ARG, "out is NULL");
+        if (where != DSX_HOST && where != DSX_DEVICE) return fail(DSX_ERR_ARG, "bad 'where'");
+        if ((s = ready(m)) != DSX_OK) return s;
+        hipStream_t st = (hipStream_t)hip_stream;
+        const size_t vox = (size_t)m->box.cnt[0] * m->box.cnt[1] * m->box.cnt[2];
+        float* dout = out;
+        if (where == DSX_HOST && (s = stage(m, vox, &dout)) != DSX_OK) return s;
+        if ((s = prepare_intensity(m)) != DSX_OK) return s;
+        if ((s = follow(m, st)) != DSX_OK) return s;
+        if ((s = enqueue_intensity(m, dout, st, false)) != DSX_OK) return s;
+        if (where == DSX_HOST) {
+            HIPCHK(m, hipMemcpyAsync(out, dout, vox * sizeof(float), hipMemcpyDeviceToHost, st));
+            HIPCHK(m, hipStreamSynchronize(st));
+        }
+        return DSX_OK;
+    });
 }
 
 }  // extern "C"
@@ -1245,36 +1310,38 @@ extern "C" {
 
 dsx_status dsx_compute_intensity_noalloc(dsx_model m, float* out, void* hip_stream)
 {
-    dsx_status s = check_direct(m);
-    if (s != DSX_OK) return s;
-    if (!out) return fail(DSX_ERR_ARG, "out is NULL");
-    if ((s = ready(m)) != DSX_OK) return s;
-    int dev = -1;
-    HIPCHK(m, hipGetDevice(&dev));
-    if (dev != m->device) return fail(DSX_ERR_ARG, "the current device is not the model's device");
-    const size_t xb = round256(m->spectrum_bytes), pb = round256(m->partial_bytes);
-    if (xb + pb > (size_t)DSX_NOALLOC_SCRATCH_BYTES)
-        return fail(DSX_ERR_UNSUPPORTED, "spectra and partial sums (" + std::to_string(xb + pb) +
-                                         " bytes) exceed the " + std::to_string(DSX_NOALLOC_SCRATCH_BYTES) +
-                                         "-byte scratch of dsx_compute_intensity_noalloc");
-    if (!m->tables.count(m->box))
-        return fail(DSX_ERR_STATE, "the grid's phase tables are not resident: dsx_set_grid prepares them "
-                                   "(dsx_compute_intensity reports why it could not)");
-    unsigned char* base = nullptr;
-    if ((s = scratch_on(dev, &base)) != DSX_OK) return s;
-    hipStream_t st = (hipStream_t)hip_stream;
-    if ((s = follow(m, st)) != DSX_OK) return s;
-    // the whole chain reads and writes the scratch in place of the model's own spectra
-    // and partial sums; every element is written before it is read
-    float2* own_x = m->d_X;
-    double* own_p = m->d_partial;
-    m->d_X = reinterpret_cast<float2*>(base);
-    m->d_partial = reinterpret_cast<double*>(base + xb);
-    s = enqueue_intensity(m, out, st, true);
-    m->d_X = own_x;
-    m->d_partial = own_p;
-    m->dirty = true;     // the model's own spectra were not refreshed
-    return s;
+    return guarded([&]() -> dsx_status {
+        dsx_status s = check_direct(m);
+        if (s != DSX_OK) return s;
+        if (!out) return fail(DSX_ERR_ARG, "out is NULL");
+        if ((s = ready(m)) != DSX_OK) return s;
+        int dev = -1;
+        HIPCHK(m, hipGetDevice(&dev));
+        if (dev != m->device) return fail(DSX_ERR_ARG, "the current device is not the model's device");
+        const size_t xb = round256(m->spectrum_bytes), pb = round256(m->partial_bytes);
+        if (xb + pb > (size_t)DSX_NOALLOC_SCRATCH_BYTES)
+            return fail(DSX_ERR_UNSUPPORTED, "spectra and partial sums (" + std::to_string(xb + pb) +
+                                             " bytes) exceed the " + std::to_string(DSX_NOALLOC_SCRATCH_BYTES) +
+                                             "-byte scratch of dsx_compute_intensity_noalloc");
+        if (!m->tables.count(m->box))
+            return fail(DSX_ERR_STATE, "the grid's phase tables are not resident: dsx_set_grid prepares them "
+                                       "(dsx_compute_intensity reports why it could not)");
+        unsigned char* base = nullptr;
+        if ((s = scratch_on(dev, &base)) != DSX_OK) return s;
+        hipStream_t st = (hipStream_t)hip_stream;
+        if ((s = follow(m, st)) != DSX_OK) return s;
+        // the whole chain reads and writes the scratch in place of the model's own spectra
+        // and partial sums; every element is written before it is read
+        float2* own_x = m->d_X;
+        double* own_p = m->d_partial;
+        m->d_X = reinterpret_cast<float2*>(base);
+        m->d_partial = reinterpret_cast<double*>(base + xb);
+        s = enqueue_intensity(m, out, st, true);
+        m->d_X = own_x;
+        m->d_partial = own_p;
+        m->dirty = true;     // the model's own spectra were not refreshed
+        return s;
+    });
 }
 
 }  // extern "C"
@@ -1351,7 +1418,12 @@ dsx_status prepare_filter(dsx_model m, int lm, int sv, int mp = 2)
         float* dw = nullptr;
         HIPCHK(m, hipMalloc(&dw, w.size() * sizeof(float)));
         HIPCHK(m, hipMemcpy(dw, w.data(), w.size() * sizeof(float), hipMemcpyHostToDevice));
-        m->lanczos_w[key] = dw;
+        try {
+            m->lanczos_w[key] = dw;
+        } catch (...) {
+            dfree(dw);
+            throw;
+        }
     }
     DeviceTables* tb = nullptr;
     return tables_for(m, ext, &tb);
@@ -1415,25 +1487,27 @@ extern "C" {
 dsx_status dsx_noise_filter(dsx_model m, int32_t lanczos_m, int32_t oversample, float* out,
                             int32_t where, void* hip_stream)
 {
-    dsx_status s = check_direct(m);
-    if (s != DSX_OK) return s;
-    if (!out) return fail(DSX_ERR_ARG, "out is NULL");
-    if (where != DSX_HOST && where != DSX_DEVICE) return fail(DSX_ERR_ARG, "bad 'where'");
-    if ((s = check_filter_args(lanczos_m, oversample)) != DSX_OK) return s;
-    if ((s = ready(m)) != DSX_OK) return s;
-    hipStream_t st = (hipStream_t)hip_stream;
-    const size_t out_vox = (size_t)oversample * m->box.cnt[0] * oversample * m->box.cnt[1] *
-                           oversample * m->box.cnt[2];
-    if ((s = prepare_filter(m, lanczos_m, oversample)) != DSX_OK) return s;
-    float* dout = out;
-    if (where == DSX_HOST && (s = stage(m, out_vox, &dout)) != DSX_OK) return s;
-    if ((s = follow(m, st)) != DSX_OK) return s;
-    if ((s = enqueue_filter(m, lanczos_m, oversample, dout, st, false)) != DSX_OK) return s;
-    if (where == DSX_HOST) {
-        HIPCHK(m, hipMemcpyAsync(out, dout, out_vox * sizeof(float), hipMemcpyDeviceToHost, st));
-        HIPCHK(m, hipStreamSynchronize(st));
-    }
-    return DSX_OK;
+    return guarded([&]() -> dsx_status {
+        dsx_status s = check_direct(m);
+        if (s != DSX_OK) return s;
+        if (!out) return fail(DSX_ERR_ARG, "out is NULL");
+        if (where != DSX_HOST && where != DSX_DEVICE) return fail(DSX_ERR_ARG, "bad 'where'");
+        if ((s = check_filter_args(lanczos_m, oversample)) != DSX_OK) return s;
+        if ((s = ready(m)) != DSX_OK) return s;
+        hipStream_t st = (hipStream_t)hip_stream;
+        const size_t out_vox = (size_t)oversample * m->box.cnt[0] * oversample * m->box.cnt[1] *
+                               oversample * m->box.cnt[2];
+        if ((s = prepare_filter(m, lanczos_m, oversample)) != DSX_OK) return s;
+        float* dout = out;
+        if (where == DSX_HOST && (s = stage(m, out_vox, &dout)) != DSX_OK) return s;
+        if ((s = follow(m, st)) != DSX_OK) return s;
+        if ((s = enqueue_filter(m, lanczos_m, oversample, dout, st, false)) != DSX_OK) return s;
+        if (where == DSX_HOST) {
+            HIPCHK(m, hipMemcpyAsync(out, dout, out_vox * sizeof(float), hipMemcpyDeviceToHost, st));
+            HIPCHK(m, hipStreamSynchronize(st));
+        }
+        return DSX_OK;
+    });
 }
 
 dsx_status dsx_split_sites(const int32_t n[3], int32_t n_sites, const double* frac, const double* b,
@@ -1441,252 +1515,265 @@ dsx_status dsx_split_sites(const int32_t n[3], int32_t n_sites, const double* fr
                            int32_t max_sites, int32_t* n_split, double* frac_out, double* b_out,
                            int32_t* parent_out, float* occ_out)
 {
-    if (!n || !frac || !b || !disp || !n_split || !frac_out || !b_out || !parent_out || !occ_out)
-        return fail(DSX_ERR_ARG, "null argument");
-    for (int a = 0; a < 3; ++a)
-        if (n[a] < 1 || n[a] > DSX_MAX_N) return fail(DSX_ERR_ARG, "n out of range");
-    if (n_sites < 1 || n_sites > DSX_MAX_SITES || n_configs < 1 || !(tol >= 0.0))
-        return fail(DSX_ERR_ARG, "bad n_sites, n_configs or tol");
-    if (max_sites < 1 || max_sites > DSX_MAX_SITES) return fail(DSX_ERR_ARG, "max_sites out of range");
-    const size_t ncell = (size_t)n[0] * n[1] * n[2];
-    // distinct displacements per site, in the order first met; cls[c][mu][cell] = index
-    std::vector<std::vector<std::array<float, 3>>> vals(n_sites);
-    std::vector<int32_t> cls((size_t)n_configs * n_sites * ncell);
-    int total = 0;
-    for (int c = 0; c < n_configs; ++c)
-        for (int mu = 0; mu < n_sites; ++mu) {
-            const float* u = disp + ((size_t)c * n_sites + mu) * ncell * 3;
-            auto& vs = vals[mu];
-            for (size_t r = 0; r < ncell; ++r) {
-                const float* ur = u + 3 * r;
-                int k = -1;
-                for (size_t j = 0; j < vs.size() && k < 0; ++j)
-                    if (std::fabs((double)ur[0] - vs[j][0]) <= tol && std::fabs((double)ur[1] - vs[j][1]) <= tol &&
-                        std::fabs((double)ur[2] - vs[j][2]) <= tol)
-                        k = (int)j;
-                if (k < 0) {
-                    if (++total > max_sites)
-                        return fail(DSX_ERR_UNSUPPORTED, "more split sites than max_sites");
-                    vs.push_back({ur[0], ur[1], ur[2]});
-                    k = (int)vs.size() - 1;
+    return guarded([&]() -> dsx_status {
+        if (!n || !frac || !b || !disp || !n_split || !frac_out || !b_out || !parent_out || !occ_out)
+            return fail(DSX_ERR_ARG, "null argument");
+        for (int a = 0; a < 3; ++a)
+            if (n[a] < 1 || n[a] > DSX_MAX_N) return fail(DSX_ERR_ARG, "n out of range");
+        if (n_sites < 1 || n_sites > DSX_MAX_SITES || n_configs < 1 || !(tol >= 0.0))
+            return fail(DSX_ERR_ARG, "bad n_sites, n_configs or tol");
+        if (max_sites < 1 || max_sites > DSX_MAX_SITES) return fail(DSX_ERR_ARG, "max_sites out of range");
+        const size_t ncell = (size_t)n[0] * n[1] * n[2];
+        // distinct displacements per site, in the order first met; cls[c][mu][cell] = index
+        std::vector<std::vector<std::array<float, 3>>> vals(n_sites);
+        std::vector<int32_t> cls((size_t)n_configs * n_sites * ncell);
+        int total = 0;
+        for (int c = 0; c < n_configs; ++c)
+            for (int mu = 0; mu < n_sites; ++mu) {
+                const float* u = disp + ((size_t)c * n_sites + mu) * ncell * 3;
+                auto& vs = vals[mu];
+                for (size_t r = 0; r < ncell; ++r) {
+                    const float* ur = u + 3 * r;
+                    int k = -1;
+                    for (size_t j = 0; j < vs.size() && k < 0; ++j)
+                        if (std::fabs((double)ur[0] - vs[j][0]) <= tol && std::fabs((double)ur[1] - vs[j][1]) <= tol &&
+                            std::fabs((double)ur[2] - vs[j][2]) <= tol)
+                            k = (int)j;
+                    if (k < 0) {
+                        if (++total > max_sites)
+                            return fail(DSX_ERR_UNSUPPORTED, "more split sites than max_sites");
+                        vs.push_back({ur[0], ur[1], ur[2]});
+                        k = (int)vs.size() - 1;
+                    }
+                    cls[((size_t)c * n_sites + mu) * ncell + r] = k;
                 }
-                cls[((size_t)c * n_sites + mu) * ncell + r] = k;
             }
-        }
-    // split sites: site mu's values in order, sites in order
-    std::vector<int> first(n_sites + 1, 0);
-    for (int mu = 0; mu < n_sites; ++mu) first[mu + 1] = first[mu] + (int)vals[mu].size();
-    for (int mu = 0; mu < n_sites; ++mu)
-        for (size_t k = 0; k < vals[mu].size(); ++k) {
-            const int sidx = first[mu] + (int)k;
-            for (int a = 0; a < 3; ++a) frac_out[3 * sidx + a] = frac[3 * mu + a] + (double)vals[mu][k][a];
-            b_out[sidx] = b[mu];
-            parent_out[sidx] = mu;
-        }
-    const int ns = first[n_sites];
-    for (int c = 0; c < n_configs; ++c)
-        for (int mu = 0; mu < n_sites; ++mu) {
-            const float* dl = occ ? occ + ((size_t)c * n_sites + mu) * ncell : nullptr;
-            const int32_t* kk = cls.data() + ((size_t)c * n_sites + mu) * ncell;
+        // split sites: site mu's values in order, sites in order
+        std::vector<int> first(n_sites + 1, 0);
+        for (int mu = 0; mu < n_sites; ++mu) first[mu + 1] = first[mu] + (int)vals[mu].size();
+        for (int mu = 0; mu < n_sites; ++mu)
             for (size_t k = 0; k < vals[mu].size(); ++k) {
-                float* o = occ_out + ((size_t)c * max_sites + first[mu] + k) * ncell;
-                for (size_t r = 0; r < ncell; ++r) o[r] = kk[r] == (int)k ? (dl ? dl[r] : 1.f) : 0.f;
+                const int sidx = first[mu] + (int)k;
+                for (int a = 0; a < 3; ++a) frac_out[3 * sidx + a] = frac[3 * mu + a] + (double)vals[mu][k][a];
+                b_out[sidx] = b[mu];
+                parent_out[sidx] = mu;
             }
-        }
-    *n_split = ns;
-    return DSX_OK;
+        const int ns = first[n_sites];
+        for (int c = 0; c < n_configs; ++c)
+            for (int mu = 0; mu < n_sites; ++mu) {
+                const float* dl = occ ? occ + ((size_t)c * n_sites + mu) * ncell : nullptr;
+                const int32_t* kk = cls.data() + ((size_t)c * n_sites + mu) * ncell;
+                for (size_t k = 0; k < vals[mu].size(); ++k) {
+                    float* o = occ_out + ((size_t)c * max_sites + first[mu] + k) * ncell;
+                    for (size_t r = 0; r < ncell; ++r) o[r] = kk[r] == (int)k ? (dl ? dl[r] : 1.f) : 0.f;
+                }
+            }
+        *n_split = ns;
+        return DSX_OK;
+    });
 }
 
 dsx_status dsx_noise_filter_spherical(dsx_model m, int32_t lanczos_m, int32_t oversample, float* out,
                                      int32_t where, void* hip_stream)
 {
-    dsx_status s = check_direct(m);
-    if (s != DSX_OK) return s;
-    if (!out) return fail(DSX_ERR_ARG, "out is NULL");
-    if (where != DSX_HOST && where != DSX_DEVICE) return fail(DSX_ERR_ARG, "bad 'where'");
-    if ((s = check_filter_args(lanczos_m, oversample)) != DSX_OK) return s;
-    if (lanczos_m > 4 || oversample > 4)
-        return fail(DSX_ERR_UNSUPPORTED, "the spherical cutoff supports lanczos_m <= 4 and oversample <= 4");
-    if ((s = ready(m)) != DSX_OK) return s;
-    hipStream_t st = (hipStream_t)hip_stream;
-    const int lm = lanczos_m, sv = oversample;
-    const size_t out_vox = (size_t)sv * m->box.cnt[0] * sv * m->box.cnt[1] * sv * m->box.cnt[2];
-    // the grown box and its tables (as for the separable filter)
-    if ((s = prepare_filter(m, lm, sv)) != DSX_OK) return s;
-    // weights [s^3][(2m)^3]: W_r(|Q - G|) L(Q - G), normalised per output phase
-    const auto key = std::make_tuple(lm, 0, sv);
-    if (!m->lanczos_w.count(key)) {
-        double rmax = 1e300;
-        for (int a = 0; a < 3; ++a) {
-            const double len = std::sqrt(m->recip[3 * a] * m->recip[3 * a] + m->recip[3 * a + 1] * m->recip[3 * a + 1] +
-                                         m->recip[3 * a + 2] * m->recip[3 * a + 2]);
-            rmax = std::min(rmax, m->n[a] * M_PI / len);
-        }
-        const double rc = (1.0 - 1.0 / lm) * rmax;
-        auto sinc = [](double x) { return x == 0.0 ? 1.0 : std::sin(x) / x; };
-        auto ball = [](double x) {
-            const double ax = std::fabs(x);
-            if (ax < 1e-2) return 1.0 / 3.0 - x * x / 30.0 + x * x * x * x / 840.0;
-            return (std::sin(ax) - ax * std::cos(ax)) / (ax * ax * ax);
-        };
-        const int T = 2 * lm;
-        std::vector<float> w((size_t)sv * sv * sv * T * T * T);
-        std::vector<double> v((size_t)T * T * T);
-        for (int j1 = 0; j1 < sv; ++j1)
-        for (int j2 = 0; j2 < sv; ++j2)
-        for (int j3 = 0; j3 < sv; ++j3) {
-            double tot = 0.0;
-            const int jj[3] = {j1, j2, j3};
-            for (int t1 = 0; t1 < T; ++t1)
-            for (int t2 = 0; t2 < T; ++t2)
-            for (int t3 = 0; t3 < T; ++t3) {
-                const int tt[3] = {t1, t2, t3};
-                double d[3], L = 1.0, q[3] = {0.0, 0.0, 0.0};
-                for (int a = 0; a < 3; ++a) {
-                    d[a] = (double)jj[a] / sv + lm - 1 - tt[a];      // Q_a - G_a
-                    L *= std::fabs(d[a]) < lm ? sinc(M_PI * d[a] / lm) : 0.0;
-                    for (int c = 0; c < 3; ++c) q[c] += d[a] / m->n[a] * m->recip[3 * a + c];
-                }
-                const double x = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]) * rc;
-                const double wv = ball(x) * L;
-                v[((size_t)t1 * T + t2) * T + t3] = wv;
-                tot += wv;
+    return guarded([&]() -> dsx_status {
+        dsx_status s = check_direct(m);
+        if (s != DSX_OK) return s;
+        if (!out) return fail(DSX_ERR_ARG, "out is NULL");
+        if (where != DSX_HOST && where != DSX_DEVICE) return fail(DSX_ERR_ARG, "bad 'where'");
+        if ((s = check_filter_args(lanczos_m, oversample)) != DSX_OK) return s;
+        if (lanczos_m > 4 || oversample > 4)
+            return fail(DSX_ERR_UNSUPPORTED, "the spherical cutoff supports lanczos_m <= 4 and oversample <= 4");
+        if ((s = ready(m)) != DSX_OK) return s;
+        hipStream_t st = (hipStream_t)hip_stream;
+        const int lm = lanczos_m, sv = oversample;
+        const size_t out_vox = (size_t)sv * m->box.cnt[0] * sv * m->box.cnt[1] * sv * m->box.cnt[2];
+        // the grown box and its tables (as for the separable filter)
+        if ((s = prepare_filter(m, lm, sv)) != DSX_OK) return s;
+        // weights [s^3][(2m)^3]: W_r(|Q - G|) L(Q - G), normalised per output phase
+        const auto key = std::make_tuple(lm, 0, sv);
+        if (!m->lanczos_w.count(key)) {
+            double rmax = 1e300;
+            for (int a = 0; a < 3; ++a) {
+                const double len = std::sqrt(m->recip[3 * a] * m->recip[3 * a] + m->recip[3 * a + 1] * m->recip[3 * a + 1] +
+                                             m->recip[3 * a + 2] * m->recip[3 * a + 2]);
+                rmax = std::min(rmax, m->n[a] * M_PI / len);
             }
-            const size_t ph = ((size_t)j1 * sv + j2) * sv + j3;
-            for (size_t t = 0; t < v.size(); ++t) w[ph * v.size() + t] = (float)(v[t] / tot);
+            const double rc = (1.0 - 1.0 / lm) * rmax;
+            auto sinc = [](double x) { return x == 0.0 ? 1.0 : std::sin(x) / x; };
+            auto ball = [](double x) {
+                const double ax = std::fabs(x);
+                if (ax < 1e-2) return 1.0 / 3.0 - x * x / 30.0 + x * x * x * x / 840.0;
+                return (std::sin(ax) - ax * std::cos(ax)) / (ax * ax * ax);
+            };
+            const int T = 2 * lm;
+            std::vector<float> w((size_t)sv * sv * sv * T * T * T);
+            std::vector<double> v((size_t)T * T * T);
+            for (int j1 = 0; j1 < sv; ++j1)
+            for (int j2 = 0; j2 < sv; ++j2)
+            for (int j3 = 0; j3 < sv; ++j3) {
+                double tot = 0.0;
+                const int jj[3] = {j1, j2, j3};
+                for (int t1 = 0; t1 < T; ++t1)
+                for (int t2 = 0; t2 < T; ++t2)
+                for (int t3 = 0; t3 < T; ++t3) {
+                    const int tt[3] = {t1, t2, t3};
+                    double d[3], L = 1.0, q[3] = {0.0, 0.0, 0.0};
+                    for (int a = 0; a < 3; ++a) {
+                        d[a] = (double)jj[a] / sv + lm - 1 - tt[a];      // Q_a - G_a
+                        L *= std::fabs(d[a]) < lm ? sinc(M_PI * d[a] / lm) : 0.0;
+                        for (int c = 0; c < 3; ++c) q[c] += d[a] / m->n[a] * m->recip[3 * a + c];
+                    }
+                    const double x = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]) * rc;
+                    const double wv = ball(x) * L;
+                    v[((size_t)t1 * T + t2) * T + t3] = wv;
+                    tot += wv;
+                }
+                const size_t ph = ((size_t)j1 * sv + j2) * sv + j3;
+                for (size_t t = 0; t < v.size(); ++t) w[ph * v.size() + t] = (float)(v[t] / tot);
+            }
+            float* dw = nullptr;
+            HIPCHK(m, hipMalloc(&dw, w.size() * sizeof(float)));
+            HIPCHK(m, hipMemcpy(dw, w.data(), w.size() * sizeof(float), hipMemcpyHostToDevice));
+            try {
+                m->lanczos_w[key] = dw;
+            } catch (...) {
+                dfree(dw);
+                throw;
+            }
         }
-        float* dw = nullptr;
-        HIPCHK(m, hipMalloc(&dw, w.size() * sizeof(float)));
-        HIPCHK(m, hipMemcpy(dw, w.data(), w.size() * sizeof(float), hipMemcpyHostToDevice));
-        m->lanczos_w[key] = dw;
-    }
-    float* dout = out;
-    if (where == DSX_HOST && (s = stage(m, out_vox, &dout)) != DSX_OK) return s;
-    if ((s = follow(m, st)) != DSX_OK) return s;
-    const Box ext = filter_box(m->box, lm);
-    if ((s = ensure_spectra(m, st, false)) != DSX_OK) return s;
-    const Layout el = ext_layout(ext);
-    if ((s = run_box(m, ext, m->d_ext, el, st)) != DSX_OK) return s;
-    LanczosParams lp{};
-    lp.in = m->d_ext; lp.out = dout; lp.wn = m->lanczos_w[key];
-    lp.ipitch = el.pitch; lp.ioff = el.off;
-    lp.ihalf = stored_planes(ext);
-    for (int a = 0; a < 3; ++a) { lp.e[a] = ext.cnt[a]; lp.o[a] = sv * m->box.cnt[a]; }
-    lp.m = lm; lp.s = sv;
-    lp.eoff = kExtEoff;
-    HIPCHK(m, timed("lanczos_spherical", st, [&] { return launch_lanczos_stencil(lp, st); }));
-    if (where == DSX_HOST) {
-        HIPCHK(m, hipMemcpyAsync(out, dout, out_vox * sizeof(float), hipMemcpyDeviceToHost, st));
-        HIPCHK(m, hipStreamSynchronize(st));
-    }
-    return DSX_OK;
+        float* dout = out;
+        if (where == DSX_HOST && (s = stage(m, out_vox, &dout)) != DSX_OK) return s;
+        if ((s = follow(m, st)) != DSX_OK) return s;
+        const Box ext = filter_box(m->box, lm);
+        if ((s = ensure_spectra(m, st, false)) != DSX_OK) return s;
+        const Layout el = ext_layout(ext);
+        if ((s = run_box(m, ext, m->d_ext, el, st)) != DSX_OK) return s;
+        LanczosParams lp{};
+        lp.in = m->d_ext; lp.out = dout; lp.wn = m->lanczos_w[key];
+        lp.ipitch = el.pitch; lp.ioff = el.off;
+        lp.ihalf = stored_planes(ext);
+        for (int a = 0; a < 3; ++a) { lp.e[a] = ext.cnt[a]; lp.o[a] = sv * m->box.cnt[a]; }
+        lp.m = lm; lp.s = sv;
+        lp.eoff = kExtEoff;
+        HIPCHK(m, timed("lanczos_spherical", st, [&] { return launch_lanczos_stencil(lp, st); }));
+        if (where == DSX_HOST) {
+            HIPCHK(m, hipMemcpyAsync(out, dout, out_vox * sizeof(float), hipMemcpyDeviceToHost, st));
+            HIPCHK(m, hipStreamSynchronize(st));
+        }
+        return DSX_OK;
+    });
 }
 
 dsx_status dsx_noise_filter_cutoff(dsx_model m, int32_t lanczos_m, int32_t mprime, int32_t oversample,
                                    float* out, int32_t where, void* hip_stream)
 {
-    dsx_status s = check_direct(m);
-    if (s != DSX_OK) return s;
-    if (!out) return fail(DSX_ERR_ARG, "out is NULL");
-    if (where != DSX_HOST && where != DSX_DEVICE) return fail(DSX_ERR_ARG, "bad 'where'");
-    if (mprime < 2 || (lanczos_m * mprime) % 2 != 0)
-        return fail(DSX_ERR_ARG, "mprime must be >= 2 with lanczos_m * mprime even");
-    if ((s = check_filter_args(lanczos_m, oversample)) != DSX_OK) return s;
-    if (lanczos_m * mprime / 2 > 16) return fail(DSX_ERR_UNSUPPORTED, "the window half-width m m'/2 is limited to 16");
-    if ((s = ready(m)) != DSX_OK) return s;
-    hipStream_t st = (hipStream_t)hip_stream;
-    const size_t out_vox = (size_t)oversample * m->box.cnt[0] * oversample * m->box.cnt[1] *
-                           oversample * m->box.cnt[2];
-    if ((s = prepare_filter(m, lanczos_m, oversample, mprime)) != DSX_OK) return s;
-    float* dout = out;
-    if (where == DSX_HOST && (s = stage(m, out_vox, &dout)) != DSX_OK) return s;
-    if ((s = follow(m, st)) != DSX_OK) return s;
-    if ((s = enqueue_filter(m, lanczos_m, oversample, dout, st, false, mprime)) != DSX_OK) return s;
-    if (where == DSX_HOST) {
-        HIPCHK(m, hipMemcpyAsync(out, dout, out_vox * sizeof(float), hipMemcpyDeviceToHost, st));
-        HIPCHK(m, hipStreamSynchronize(st));
-    }
-    return DSX_OK;
+    return guarded([&]() -> dsx_status {
+        dsx_status s = check_direct(m);
+        if (s != DSX_OK) return s;
+        if (!out) return fail(DSX_ERR_ARG, "out is NULL");
+        if (where != DSX_HOST && where != DSX_DEVICE) return fail(DSX_ERR_ARG, "bad 'where'");
+        if (mprime < 2 || (lanczos_m * mprime) % 2 != 0)
+            return fail(DSX_ERR_ARG, "mprime must be >= 2 with lanczos_m * mprime even");
+        if ((s = check_filter_args(lanczos_m, oversample)) != DSX_OK) return s;
+        if (lanczos_m * mprime / 2 > 16) return fail(DSX_ERR_UNSUPPORTED, "the window half-width m m'/2 is limited to 16");
+        if ((s = ready(m)) != DSX_OK) return s;
+        hipStream_t st = (hipStream_t)hip_stream;
+        const size_t out_vox = (size_t)oversample * m->box.cnt[0] * oversample * m->box.cnt[1] *
+                               oversample * m->box.cnt[2];
+        if ((s = prepare_filter(m, lanczos_m, oversample, mprime)) != DSX_OK) return s;
+        float* dout = out;
+        if (where == DSX_HOST && (s = stage(m, out_vox, &dout)) != DSX_OK) return s;
+        if ((s = follow(m, st)) != DSX_OK) return s;
+        if ((s = enqueue_filter(m, lanczos_m, oversample, dout, st, false, mprime)) != DSX_OK) return s;
+        if (where == DSX_HOST) {
+            HIPCHK(m, hipMemcpyAsync(out, dout, out_vox * sizeof(float), hipMemcpyDeviceToHost, st));
+            HIPCHK(m, hipStreamSynchronize(st));
+        }
+        return DSX_OK;
+    });
 }
 
 dsx_status dsx_filter_points(dsx_model m, int32_t lanczos_m, int32_t mprime, int64_t npts, const double* q,
                              float* out, int32_t where, void* hip_stream)
 {
-    dsx_status s = check_direct(m);
-    if (s != DSX_OK) return s;
-    if (npts < 0 || (npts > 0 && (!q || !out))) return fail(DSX_ERR_ARG, "bad point list");
-    if (where != DSX_HOST && where != DSX_DEVICE) return fail(DSX_ERR_ARG, "bad 'where'");
-    if (lanczos_m < 2 || mprime < 2 || (lanczos_m * mprime) % 2 != 0)
-        return fail(DSX_ERR_ARG, "need lanczos_m >= 2, mprime >= 2 and lanczos_m * mprime even");
-    const int w = lanczos_m * mprime / 2;
-    if (w > kPointsMaxHalfwidth) return fail(DSX_ERR_UNSUPPORTED, "the window half-width m m'/2 is limited to 8 here");
-    if ((s = ready(m)) != DSX_OK) return s;
-    if (npts == 0) return DSX_OK;
-    // the box of every window: floor(Q_a) - w + 1 .. floor(Q_a) + w
-    long lo[3] = {LONG_MAX, LONG_MAX, LONG_MAX}, hi[3] = {LONG_MIN, LONG_MIN, LONG_MIN};
-    for (int64_t i = 0; i < npts; ++i)
-        for (int a = 0; a < 3; ++a) {
-            const double v = q[3 * i + a];
-            if (!std::isfinite(v) || std::fabs(v) > 1e6) return fail(DSX_ERR_ARG, "points must be finite, |Q| <= 1e6");
-            const long f = (long)std::floor(v);
-            lo[a] = std::min(lo[a], f - w + 1);
-            hi[a] = std::max(hi[a], f + w);
-        }
-    // a box nearly symmetric about G = 0 is made symmetric (at most ~10 % more volume):
-    // the recombination then evaluates half of it (I(-G) = I(G))
-    bool near_sym = true;
-    for (int a = 0; a < 3; ++a) {
-        const long r = std::max(std::labs(lo[a]), std::labs(hi[a]));
-        if ((double)(2 * r + 1) > 1.1 * (double)(hi[a] - lo[a] + 1) + 2.0) near_sym = false;
-    }
-    if (near_sym)
+    return guarded([&]() -> dsx_status {
+        dsx_status s = check_direct(m);
+        if (s != DSX_OK) return s;
+        if (npts < 0 || (npts > 0 && (!q || !out))) return fail(DSX_ERR_ARG, "bad point list");
+        if (where != DSX_HOST && where != DSX_DEVICE) return fail(DSX_ERR_ARG, "bad 'where'");
+        if (lanczos_m < 2 || mprime < 2 || (lanczos_m * mprime) % 2 != 0)
+            return fail(DSX_ERR_ARG, "need lanczos_m >= 2, mprime >= 2 and lanczos_m * mprime even");
+        const int w = lanczos_m * mprime / 2;
+        if (w > kPointsMaxHalfwidth) return fail(DSX_ERR_UNSUPPORTED, "the window half-width m m'/2 is limited to 8 here");
+        if ((s = ready(m)) != DSX_OK) return s;
+        if (npts == 0) return DSX_OK;
+        // the box of every window: floor(Q_a) - w + 1 .. floor(Q_a) + w
+        long lo[3] = {LONG_MAX, LONG_MAX, LONG_MAX}, hi[3] = {LONG_MIN, LONG_MIN, LONG_MIN};
+        for (int64_t i = 0; i < npts; ++i)
+            for (int a = 0; a < 3; ++a) {
+                const double v = q[3 * i + a];
+                if (!std::isfinite(v) || std::fabs(v) > 1e6) return fail(DSX_ERR_ARG, "points must be finite, |Q| <= 1e6");
+                const long f = (long)std::floor(v);
+                lo[a] = std::min(lo[a], f - w + 1);
+                hi[a] = std::max(hi[a], f + w);
+            }
+        // a box nearly symmetric about G = 0 is made symmetric (at most ~10 % more volume):
+        // the recombination then evaluates half of it (I(-G) = I(G))
+        bool near_sym = true;
         for (int a = 0; a < 3; ++a) {
             const long r = std::max(std::labs(lo[a]), std::labs(hi[a]));
-            lo[a] = -r; hi[a] = r;
+            if ((double)(2 * r + 1) > 1.1 * (double)(hi[a] - lo[a] + 1) + 2.0) near_sym = false;
         }
-    Box bx;
-    for (int a = 0; a < 3; ++a) { bx.g0[a] = (int)lo[a]; bx.cnt[a] = (int)(hi[a] - lo[a] + 1); }
-    const size_t vox = (size_t)bx.cnt[0] * bx.cnt[1] * bx.cnt[2];
-    DeviceTables* tb = nullptr;
-    if ((s = tables_for(m, bx, &tb)) != DSX_OK) return s;
-    if (m->pts_cap < vox || m->q_cap < (size_t)npts) {
-        if (m->pins) return fail(DSX_ERR_BUSY, "a batch has recorded this model's buffers");
-    }
-    if (m->pts_cap < vox) {
-        dfree(m->d_pts); m->d_pts = nullptr; m->pts_cap = 0;
-        hipError_t e = hipMalloc(&m->d_pts, vox * sizeof(float));
-        if (e == hipErrorOutOfMemory) return fail(DSX_ERR_NOMEM, "out of device memory for the points' box");
-        HIPCHK(m, e);
-        m->pts_cap = vox;
-    }
-    if (m->q_cap < (size_t)npts) {
-        dfree(m->d_q); m->d_q = nullptr; m->q_cap = 0;
-        hipError_t e = hipMalloc(&m->d_q, (size_t)npts * 3 * sizeof(double));
-        if (e == hipErrorOutOfMemory) return fail(DSX_ERR_NOMEM, "out of device memory for the points");
-        HIPCHK(m, e);
-        m->q_cap = (size_t)npts;
-    }
-    hipStream_t st = (hipStream_t)hip_stream;
-    float* dout = out;
-    if (where == DSX_HOST && (s = stage(m, (size_t)npts, &dout)) != DSX_OK) return s;
-    if ((s = follow(m, st)) != DSX_OK) return s;
-    HIPCHK(m, hipMemcpyAsync(m->d_q, q, (size_t)npts * 3 * sizeof(double), hipMemcpyHostToDevice, st));
-    if ((s = ensure_spectra(m, st, false)) != DSX_OK) return s;
-    if ((s = run_box(m, bx, m->d_pts, dense_layout(bx), st)) != DSX_OK) return s;
-    PointsParams pp{};
-    pp.in = m->d_pts; pp.q = m->d_q; pp.out = dout; pp.npts = npts;
-    for (int a = 0; a < 3; ++a) { pp.e0[a] = bx.g0[a]; pp.e[a] = bx.cnt[a]; }
-    pp.w = w;
-    pp.rcut = (float)((1.0 - 1.0 / lanczos_m) / mprime);
-    HIPCHK(m, timed("lanczos_points", st, [&] { return launch_lanczos_points(pp, st); }));
-    if (where == DSX_HOST) {
-        HIPCHK(m, hipMemcpyAsync(out, dout, (size_t)npts * sizeof(float), hipMemcpyDeviceToHost, st));
-        HIPCHK(m, hipStreamSynchronize(st));
-    } else {
-        // the point list is a host array read by the copy above: wait before returning
-        HIPCHK(m, hipStreamSynchronize(st));
-    }
-    return DSX_OK;
+        if (near_sym)
+            for (int a = 0; a < 3; ++a) {
+                const long r = std::max(std::labs(lo[a]), std::labs(hi[a]));
+                lo[a] = -r; hi[a] = r;
+            }
+        Box bx;
+        for (int a = 0; a < 3; ++a) { bx.g0[a] = (int)lo[a]; bx.cnt[a] = (int)(hi[a] - lo[a] + 1); }
+        const size_t vox = (size_t)bx.cnt[0] * bx.cnt[1] * bx.cnt[2];
+        DeviceTables* tb = nullptr;
+        if ((s = tables_for(m, bx, &tb)) != DSX_OK) return s;
+        if (m->pts_cap < vox || m->q_cap < (size_t)npts) {
+            if (m->pins) return fail(DSX_ERR_BUSY, "a batch has recorded this model's buffers");
+        }
+        if (m->pts_cap < vox) {
+            dfree(m->d_pts); m->d_pts = nullptr; m->pts_cap = 0;
+            hipError_t e = hipMalloc(&m->d_pts, vox * sizeof(float));
+            if (e == hipErrorOutOfMemory) return fail(DSX_ERR_NOMEM, "out of device memory for the points' box");
+            HIPCHK(m, e);
+            m->pts_cap = vox;
+        }
+        if (m->q_cap < (size_t)npts) {
+            dfree(m->d_q); m->d_q = nullptr; m->q_cap = 0;
+            hipError_t e = hipMalloc(&m->d_q, (size_t)npts * 3 * sizeof(double));
+            if (e == hipErrorOutOfMemory) return fail(DSX_ERR_NOMEM, "out of device memory for the points");
+            HIPCHK(m, e);
+            m->q_cap = (size_t)npts;
+        }
+        hipStream_t st = (hipStream_t)hip_stream;
+        float* dout = out;
+        if (where == DSX_HOST && (s = stage(m, (size_t)npts, &dout)) != DSX_OK) return s;
+        if ((s = follow(m, st)) != DSX_OK) return s;
+        HIPCHK(m, hipMemcpyAsync(m->d_q, q, (size_t)npts * 3 * sizeof(double), hipMemcpyHostToDevice, st));
+        if ((s = ensure_spectra(m, st, false)) != DSX_OK) return s;
+        if ((s = run_box(m, bx, m->d_pts, dense_layout(bx), st)) != DSX_OK) return s;
+        PointsParams pp{};
+        pp.in = m->d_pts; pp.q = m->d_q; pp.out = dout; pp.npts = npts;
+        for (int a = 0; a < 3; ++a) { pp.e0[a] = bx.g0[a]; pp.e[a] = bx.cnt[a]; }
+        pp.w = w;
+        pp.rcut = (float)((1.0 - 1.0 / lanczos_m) / mprime);
+        HIPCHK(m, timed("lanczos_points", st, [&] { return launch_lanczos_points(pp, st); }));
+        if (where == DSX_HOST) {
+            HIPCHK(m, hipMemcpyAsync(out, dout, (size_t)npts * sizeof(float), hipMemcpyDeviceToHost, st));
+            HIPCHK(m, hipStreamSynchronize(st));
+        } else {
+            // the point list is a host array read by the copy above: wait before returning
+            HIPCHK(m, hipStreamSynchronize(st));
+        }
+        return DSX_OK;
+    });
 }
 
 }  // extern "C"
@@ -1760,81 +1847,85 @@ extern "C" {
 
 dsx_status dsx_autotune(dsx_model m, int32_t lanczos_m, void* hip_stream)
 {
-    dsx_status s = check_direct(m);
-    if (s != DSX_OK) return s;
-    if ((s = ready(m)) != DSX_OK) return s;
-    const bool filt = lanczos_m >= 2;
-    if (lanczos_m != 0 && (s = check_filter_args(lanczos_m, 1)) != DSX_OK) return s;
-    hipStream_t st = (hipStream_t)hip_stream;
-    const std::string key = tune_key(m, lanczos_m);
-    int v = 0, fc = 0, t1 = 12;
-    if (tune_lookup(key, &v, &fc, &t1)) {
-        m->tune_recomb_variant = v; m->tune_fchunk = fc; m->tune_lanczos_t1 = t1;
-        m->tuned = true;
-        return DSX_OK;
-    }
-    if ((s = prepare_intensity(m)) != DSX_OK) return s;
-    if (filt && (s = prepare_filter(m, lanczos_m, 1)) != DSX_OK) return s;
-    float* scratch = nullptr;
-    const size_t vox = (size_t)m->box.cnt[0] * m->box.cnt[1] * m->box.cnt[2];
-    if ((s = stage(m, vox, &scratch)) != DSX_OK) return s;
-    if ((s = follow(m, st)) != DSX_OK) return s;
-    const bool prof = g_prof.on;
-    g_prof.on = false;
-    // FFT: fields per plane block
-    float best = -1.f;
-    int best_fc = 0;
-    for (int cand : {0, 1, 2, 4}) {
-        m->tune_fchunk = cand;
-        const float t = time_min(st, 3, [&] { return ensure_spectra(m, st, true); });
-        if (t >= 0.f && (best < 0.f || t < best)) { best = t; best_fc = cand; }
-    }
-    m->tune_fchunk = best_fc;
-    // recombination form (the parity form only exists for nuclear models whose r3 are halves)
-    best = -1.f;
-    int best_v = 0;
-    const Box b = filt ? filter_box(m->box, lanczos_m) : m->box;
-    float* dst = filt ? m->d_ext : scratch;
-    for (int cand : {0, 2, 3, 4}) {
-        if (cand != 0 && m->kind != DSX_NUCLEAR) continue;
-        m->tune_recomb_variant = cand;
-        const Layout lay = filt ? ext_layout(b) : dense_layout(b);
-        const float t = time_min(st, 3, [&] { return run_box(m, b, dst, lay, st); });
-        if (t >= 0.f && (best < 0.f || t < best)) { best = t; best_v = cand; }
-    }
-    m->tune_recomb_variant = best_v;
-    // filter: planes per block
-    int best_t1 = 12;
-    if (filt) {
-        best = -1.f;
-        for (int cand : {4, 6, 8, 12, 16, 20, 26, 32, 52, 64}) {
-            m->tune_lanczos_t1 = cand;
-            const float t = time_min(st, 3, [&] { return enqueue_filter(m, lanczos_m, 1, scratch, st, false); });
-            if (t >= 0.f && (best < 0.f || t < best)) { best = t; best_t1 = cand; }
+    return guarded([&]() -> dsx_status {
+        dsx_status s = check_direct(m);
+        if (s != DSX_OK) return s;
+        if ((s = ready(m)) != DSX_OK) return s;
+        const bool filt = lanczos_m >= 2;
+        if (lanczos_m != 0 && (s = check_filter_args(lanczos_m, 1)) != DSX_OK) return s;
+        hipStream_t st = (hipStream_t)hip_stream;
+        const std::string key = tune_key(m, lanczos_m);
+        int v = 0, fc = 0, t1 = 12;
+        if (tune_lookup(key, &v, &fc, &t1)) {
+            m->tune_recomb_variant = v; m->tune_fchunk = fc; m->tune_lanczos_t1 = t1;
+            m->tuned = true;
+            return DSX_OK;
         }
-        m->tune_lanczos_t1 = best_t1;
-    }
-    g_prof.on = prof;
-    if (m->failed) return fail(DSX_ERR_DEVICE, "device error during tuning");
-    m->tuned = true;
-    tune_store(key, best_v, best_fc, best_t1);
-    return DSX_OK;
+        if ((s = prepare_intensity(m)) != DSX_OK) return s;
+        if (filt && (s = prepare_filter(m, lanczos_m, 1)) != DSX_OK) return s;
+        float* scratch = nullptr;
+        const size_t vox = (size_t)m->box.cnt[0] * m->box.cnt[1] * m->box.cnt[2];
+        if ((s = stage(m, vox, &scratch)) != DSX_OK) return s;
+        if ((s = follow(m, st)) != DSX_OK) return s;
+        const bool prof = g_prof.on;
+        g_prof.on = false;
+        // FFT: fields per plane block
+        float best = -1.f;
+        int best_fc = 0;
+        for (int cand : {0, 1, 2, 4}) {
+            m->tune_fchunk = cand;
+            const float t = time_min(st, 3, [&] { return ensure_spectra(m, st, true); });
+            if (t >= 0.f && (best < 0.f || t < best)) { best = t; best_fc = cand; }
+        }
+        m->tune_fchunk = best_fc;
+        // recombination form (the parity form only exists for nuclear models whose r3 are halves)
+        best = -1.f;
+        int best_v = 0;
+        const Box b = filt ? filter_box(m->box, lanczos_m) : m->box;
+        float* dst = filt ? m->d_ext : scratch;
+        for (int cand : {0, 2, 3, 4}) {
+            if (cand != 0 && m->kind != DSX_NUCLEAR) continue;
+            m->tune_recomb_variant = cand;
+            const Layout lay = filt ? ext_layout(b) : dense_layout(b);
+            const float t = time_min(st, 3, [&] { return run_box(m, b, dst, lay, st); });
+            if (t >= 0.f && (best < 0.f || t < best)) { best = t; best_v = cand; }
+        }
+        m->tune_recomb_variant = best_v;
+        // filter: planes per block
+        int best_t1 = 12;
+        if (filt) {
+            best = -1.f;
+            for (int cand : {4, 6, 8, 12, 16, 20, 26, 32, 52, 64}) {
+                m->tune_lanczos_t1 = cand;
+                const float t = time_min(st, 3, [&] { return enqueue_filter(m, lanczos_m, 1, scratch, st, false); });
+                if (t >= 0.f && (best < 0.f || t < best)) { best = t; best_t1 = cand; }
+            }
+            m->tune_lanczos_t1 = best_t1;
+        }
+        g_prof.on = prof;
+        if (m->failed) return fail(DSX_ERR_DEVICE, "device error during tuning");
+        m->tuned = true;
+        tune_store(key, best_v, best_fc, best_t1);
+        return DSX_OK;
+    });
 }
 
 dsx_status dsx_tune_set(dsx_model m, const int32_t choice[3])
 {
-    dsx_status s = check_direct(m);
-    if (s != DSX_OK) return s;
-    if (!choice) return fail(DSX_ERR_ARG, "null choice");
-    const int v = choice[0], fc = choice[1], t1 = choice[2];
-    if (!(v == 0 || v == 2 || v == 3 || v == 4) || (v != 0 && m->kind != DSX_NUCLEAR))
-        return fail(DSX_ERR_ARG, "recombination form must be 0, or 2, 3, 4 on a nuclear model");
-    if (!(fc == 0 || fc == 1 || fc == 2 || fc == 4))
-        return fail(DSX_ERR_ARG, "FFT fields per plane block must be 0, 1, 2 or 4");
-    if (t1 < 1 || t1 > 64) return fail(DSX_ERR_ARG, "filter planes per block must be in 1..64");
-    m->tune_recomb_variant = v; m->tune_fchunk = fc; m->tune_lanczos_t1 = t1;
-    m->tuned = true;
-    return DSX_OK;
+    return guarded([&]() -> dsx_status {
+        dsx_status s = check_direct(m);
+        if (s != DSX_OK) return s;
+        if (!choice) return fail(DSX_ERR_ARG, "null choice");
+        const int v = choice[0], fc = choice[1], t1 = choice[2];
+        if (!(v == 0 || v == 2 || v == 3 || v == 4) || (v != 0 && m->kind != DSX_NUCLEAR))
+            return fail(DSX_ERR_ARG, "recombination form must be 0, or 2, 3, 4 on a nuclear model");
+        if (!(fc == 0 || fc == 1 || fc == 2 || fc == 4))
+            return fail(DSX_ERR_ARG, "FFT fields per plane block must be 0, 1, 2 or 4");
+        if (t1 < 1 || t1 > 64) return fail(DSX_ERR_ARG, "filter planes per block must be in 1..64");
+        m->tune_recomb_variant = v; m->tune_fchunk = fc; m->tune_lanczos_t1 = t1;
+        m->tuned = true;
+        return DSX_OK;
+    });
 }
 
 dsx_status dsx_tune_query(dsx_model m, int32_t choice[3], int32_t* tuned)
@@ -1882,115 +1973,123 @@ extern "C" {
 dsx_status dsx_batch_create(const dsx_model* models, int32_t n, int32_t lanczos_m, int32_t oversample,
                             float* const* outs, dsx_batch* out)
 {
-    if (!models || !outs || !out || n < 1) return fail(DSX_ERR_ARG, "models, outs and out are required, n >= 1");
-    *out = nullptr;
-    dsx_status s;
-    if (lanczos_m != 0 && (s = check_filter_args(lanczos_m, oversample)) != DSX_OK) return s;
-    for (int i = 0; i < n; ++i) {
-        if ((s = check_direct(models[i])) != DSX_OK) return s;
-        if ((s = ready(models[i])) != DSX_OK) return s;
-        if (!outs[i]) return fail(DSX_ERR_ARG, "outs[" + std::to_string(i) + "] is NULL");
-        for (int j = 0; j < i; ++j)
-            if (models[j] == models[i]) return fail(DSX_ERR_ARG, "a model appears twice in the batch");
-    }
-    dsx_batch b = new (std::nothrow) dsx_batch_s();
-    if (!b) return fail(DSX_ERR_NOMEM, "host allocation failed");
-    b->models.assign(models, models + n);
-    b->outs.assign(outs, outs + n);
-    b->lanczos_m = lanczos_m;
-    b->oversample = lanczos_m ? oversample : 1;
-    auto bail = [&](dsx_status st) { free_batch(b); delete b; return st; };
-    hipError_t e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
-    if (e != hipSuccess) return bail(fail(DSX_ERR_DEVICE, hipGetErrorString(e)));
-    // plan and tune (allocations and uploads happen here, never during capture)
-    for (int i = 0; i < n; ++i) {
-        dsx_model m = b->models[i];
-        if (!m->tuned && (s = dsx_autotune(m, lanczos_m, b->cap)) != DSX_OK) return bail(s);
-        if ((s = prepare_intensity(m)) != DSX_OK) return bail(s);
-        if (lanczos_m && (s = prepare_filter(m, lanczos_m, b->oversample)) != DSX_OK) return bail(s);
-    }
-    if ((e = hipStreamSynchronize(b->cap)) != hipSuccess) return bail(fail(DSX_ERR_DEVICE, hipGetErrorString(e)));
-    b->streams.assign(n, nullptr);
-    b->joins.assign(n, nullptr);
-    if ((e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming)) != hipSuccess)
-        return bail(fail(DSX_ERR_DEVICE, hipGetErrorString(e)));
-    for (int i = 0; i < n; ++i) {
-        if ((e = hipStreamCreateWithFlags(&b->streams[i], hipStreamNonBlocking)) != hipSuccess ||
-            (e = hipEventCreateWithFlags(&b->joins[i], hipEventDisableTiming)) != hipSuccess)
+    return guarded([&]() -> dsx_status {
+        if (!models || !outs || !out || n < 1) return fail(DSX_ERR_ARG, "models, outs and out are required, n >= 1");
+        *out = nullptr;
+        dsx_status s;
+        if (lanczos_m != 0 && (s = check_filter_args(lanczos_m, oversample)) != DSX_OK) return s;
+        for (int i = 0; i < n; ++i) {
+            if ((s = check_direct(models[i])) != DSX_OK) return s;
+            if ((s = ready(models[i])) != DSX_OK) return s;
+            if (!outs[i]) return fail(DSX_ERR_ARG, "outs[" + std::to_string(i) + "] is NULL");
+            for (int j = 0; j < i; ++j)
+                if (models[j] == models[i]) return fail(DSX_ERR_ARG, "a model appears twice in the batch");
+        }
+        dsx_batch b = new (std::nothrow) dsx_batch_s();
+        if (!b) return fail(DSX_ERR_NOMEM, "host allocation failed");
+        b->models.assign(models, models + n);
+        b->outs.assign(outs, outs + n);
+        b->lanczos_m = lanczos_m;
+        b->oversample = lanczos_m ? oversample : 1;
+        auto bail = [&](dsx_status st) { free_batch(b); delete b; return st; };
+        hipError_t e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+        if (e != hipSuccess) return bail(fail(DSX_ERR_DEVICE, hipGetErrorString(e)));
+        // plan and tune (allocations and uploads happen here, never during capture)
+        for (int i = 0; i < n; ++i) {
+            dsx_model m = b->models[i];
+            if (!m->tuned && (s = dsx_autotune(m, lanczos_m, b->cap)) != DSX_OK) return bail(s);
+            if ((s = prepare_intensity(m)) != DSX_OK) return bail(s);
+            if (lanczos_m && (s = prepare_filter(m, lanczos_m, b->oversample)) != DSX_OK) return bail(s);
+        }
+        if ((e = hipStreamSynchronize(b->cap)) != hipSuccess) return bail(fail(DSX_ERR_DEVICE, hipGetErrorString(e)));
+        b->streams.assign(n, nullptr);
+        b->joins.assign(n, nullptr);
+        if ((e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming)) != hipSuccess)
             return bail(fail(DSX_ERR_DEVICE, hipGetErrorString(e)));
-    }
-    // record every model's launch sequence into one graph
-    const bool prof = g_prof.on;
-    g_prof.on = false;
-    dsx_status cs = DSX_OK;
-    if ((e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed)) != hipSuccess) {
+        for (int i = 0; i < n; ++i) {
+            if ((e = hipStreamCreateWithFlags(&b->streams[i], hipStreamNonBlocking)) != hipSuccess ||
+                (e = hipEventCreateWithFlags(&b->joins[i], hipEventDisableTiming)) != hipSuccess)
+                return bail(fail(DSX_ERR_DEVICE, hipGetErrorString(e)));
+        }
+        // record every model's launch sequence into one graph
+        const bool prof = g_prof.on;
+        g_prof.on = false;
+        dsx_status cs = DSX_OK;
+        if ((e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed)) != hipSuccess) {
+            g_prof.on = prof;
+            return bail(fail(DSX_ERR_DEVICE, hipGetErrorString(e)));
+        }
+        e = hipEventRecord(b->fork, b->cap);
+        for (int i = 0; i < n && e == hipSuccess && cs == DSX_OK; ++i) {
+            dsx_model m = b->models[i];
+            hipStream_t si = b->streams[i];
+            if ((e = hipStreamWaitEvent(si, b->fork, 0)) != hipSuccess) break;
+            cs = lanczos_m ? enqueue_filter(m, lanczos_m, b->oversample, b->outs[i], si, true)
+                           : enqueue_intensity(m, b->outs[i], si, true);
+            if (cs != DSX_OK) break;
+            if ((e = hipEventRecord(b->joins[i], si)) != hipSuccess) break;
+            e = hipStreamWaitEvent(b->cap, b->joins[i], 0);
+        }
+        hipGraph_t g = nullptr;
+        const hipError_t ee = hipStreamEndCapture(b->cap, &g);
         g_prof.on = prof;
-        return bail(fail(DSX_ERR_DEVICE, hipGetErrorString(e)));
-    }
-    e = hipEventRecord(b->fork, b->cap);
-    for (int i = 0; i < n && e == hipSuccess && cs == DSX_OK; ++i) {
-        dsx_model m = b->models[i];
-        hipStream_t si = b->streams[i];
-        if ((e = hipStreamWaitEvent(si, b->fork, 0)) != hipSuccess) break;
-        cs = lanczos_m ? enqueue_filter(m, lanczos_m, b->oversample, b->outs[i], si, true)
-                       : enqueue_intensity(m, b->outs[i], si, true);
-        if (cs != DSX_OK) break;
-        if ((e = hipEventRecord(b->joins[i], si)) != hipSuccess) break;
-        e = hipStreamWaitEvent(b->cap, b->joins[i], 0);
-    }
-    hipGraph_t g = nullptr;
-    const hipError_t ee = hipStreamEndCapture(b->cap, &g);
-    g_prof.on = prof;
-    b->graph = g;
-    if (cs != DSX_OK) return bail(cs);
-    if (e != hipSuccess || ee != hipSuccess)
-        return bail(fail(DSX_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : ee)));
-    if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess)
-        return bail(fail(DSX_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e)));
-    for (dsx_model m : b->models) ++m->pins;
-    *out = b;
-    return DSX_OK;
+        b->graph = g;
+        if (cs != DSX_OK) return bail(cs);
+        if (e != hipSuccess || ee != hipSuccess)
+            return bail(fail(DSX_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : ee)));
+        if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess)
+            return bail(fail(DSX_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e)));
+        for (dsx_model m : b->models) ++m->pins;
+        *out = b;
+        return DSX_OK;
+    });
 }
 
 dsx_status dsx_batch_run(dsx_batch b, void* hip_stream)
 {
-    if (!b) return fail(DSX_ERR_ARG, "batch is NULL");
-    for (dsx_model m : b->models) {
-        dsx_status s = check_model(m);
-        if (s != DSX_OK) return s;
-    }
-    hipStream_t st = (hipStream_t)hip_stream;
-    for (dsx_model m : b->models) {
-        dsx_status s = follow(m, st);
-        if (s != DSX_OK) return s;
-    }
-    const hipError_t e = hipGraphLaunch(b->exec, st);
-    if (e != hipSuccess) {
-        for (dsx_model m : b->models) m->failed = true;
-        return fail(DSX_ERR_DEVICE, std::string("graph launch: ") + hipGetErrorString(e));
-    }
-    for (dsx_model m : b->models) m->dirty = false;
-    return DSX_OK;
+    return guarded([&]() -> dsx_status {
+        if (!b) return fail(DSX_ERR_ARG, "batch is NULL");
+        for (dsx_model m : b->models) {
+            dsx_status s = check_model(m);
+            if (s != DSX_OK) return s;
+        }
+        hipStream_t st = (hipStream_t)hip_stream;
+        for (dsx_model m : b->models) {
+            dsx_status s = follow(m, st);
+            if (s != DSX_OK) return s;
+        }
+        const hipError_t e = hipGraphLaunch(b->exec, st);
+        if (e != hipSuccess) {
+            for (dsx_model m : b->models) m->failed = true;
+            return fail(DSX_ERR_DEVICE, std::string("graph launch: ") + hipGetErrorString(e));
+        }
+        for (dsx_model m : b->models) m->dirty = false;
+        return DSX_OK;
+    });
 }
 
 dsx_status dsx_batch_destroy(dsx_batch b)
 {
-    if (!b) return fail(DSX_ERR_ARG, "batch is NULL");
-    for (dsx_model m : b->models) { (void)hipStreamSynchronize(m->last_stream); --m->pins; }
-    free_batch(b);
-    delete b;
-    return DSX_OK;
+    return guarded([&]() -> dsx_status {
+        if (!b) return fail(DSX_ERR_ARG, "batch is NULL");
+        for (dsx_model m : b->models) { (void)hipStreamSynchronize(m->last_stream); --m->pins; }
+        free_batch(b);
+        delete b;
+        return DSX_OK;
+    });
 }
 
 dsx_status dsx_destroy_model(dsx_model m)
 {
-    if (!m) return fail(DSX_ERR_ARG, "model is NULL");
-    if (m->server) return fail(DSX_ERR_ARG, "the model belongs to a server: dsx_server_destroy releases it");
-    if (m->pins) return fail(DSX_ERR_BUSY, "the model is recorded in a batch; destroy the batch first");
-    (void)hipStreamSynchronize(m->last_stream);
-    free_model(m);
-    delete m;
-    return DSX_OK;
+    return guarded([&]() -> dsx_status {
+        if (!m) return fail(DSX_ERR_ARG, "model is NULL");
+        if (m->server) return fail(DSX_ERR_ARG, "the model belongs to a server: dsx_server_destroy releases it");
+        if (m->pins) return fail(DSX_ERR_BUSY, "the model is recorded in a batch; destroy the batch first");
+        (void)hipStreamSynchronize(m->last_stream);
+        free_model(m);
+        delete m;
+        return DSX_OK;
+    });
 }
 
 }  // extern "C"
@@ -2001,51 +2100,7 @@ namespace {
 using Clock = std::chrono::steady_clock;
 
 // First-fit sub-allocator over the server's device arena, in 256-byte granules.
-class Arena {
-public:
-    static size_t round(size_t n) { return (n + 255) & ~size_t(255); }
-    void init(size_t n) { size_ = n; used_ = peak_ = 0; free_.clear(); free_[0] = n; }
-    bool alloc(size_t n, size_t* off)
-    {
-        n = round(n);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second < n) continue;
-            *off = it->first;
-            const size_t rest = it->second - n, next = it->first + n;
-            free_.erase(it);
-            if (rest) free_[next] = rest;
-            used_ += n;
-            peak_ = std::max(peak_, used_);
-            return true;
-        }
-        return false;
-    }
-    void release(size_t off, size_t n)
-    {
-        n = round(n);
-        used_ -= n;
-        auto it = free_.emplace(off, n).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-    size_t size() const { return size_; }
-    size_t peak() const { return peak_; }
-    void reset_peak() { peak_ = used_; }
 
-private:
-    size_t size_ = 0, used_ = 0, peak_ = 0;
-    std::map<size_t, size_t> free_;   // offset -> length of each free range
-};
 
 struct Request {
     int64_t ticket = 0;
@@ -2251,164 +2306,176 @@ extern "C" {
 
 dsx_status dsx_server_create(const dsx_server_config* c, dsx_server* out)
 {
-    if (!c || !out) return fail(DSX_ERR_ARG, "config and out are required");
-    *out = nullptr;
-    if (c->slots < 1 || c->slots > 16) return fail(DSX_ERR_ARG, "slots must be in 1..16");
-    if (c->queue_capacity < 1) return fail(DSX_ERR_ARG, "queue_capacity must be >= 1");
-    if (c->arena_bytes < 1) return fail(DSX_ERR_ARG, "arena_bytes must be >= 1");
-    dsx_server s = new (std::nothrow) dsx_server_s();
-    if (!s) return fail(DSX_ERR_NOMEM, "host allocation failed");
-    auto bail = [&](dsx_status st) { free_server(s); delete s; return st; };
-    (void)hipGetDevice(&s->device);
-    s->nslots = c->slots;
-    s->capacity = c->queue_capacity;
-    const size_t bytes = Arena::round((size_t)c->arena_bytes);
-    hipError_t e = hipMalloc(&s->arena_mem, bytes);
-    if (e == hipErrorOutOfMemory) { (void)hipGetLastError(); return bail(fail(DSX_ERR_NOMEM, "out of device memory for the arena")); }
-    if (e != hipSuccess) return bail(fail(DSX_ERR_DEVICE, hipGetErrorString(e)));
-    s->arena.init(bytes);
-    s->streams.assign(s->nslots, nullptr);
-    s->events.assign(s->nslots, nullptr);
-    s->busy.assign(s->nslots, 0);
-    s->running.resize(s->nslots);
-    for (int i = 0; i < s->nslots; ++i) {
-        if ((e = hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking)) != hipSuccess ||
-            (e = hipEventCreateWithFlags(&s->events[i], hipEventDisableTiming)) != hipSuccess)
-            return bail(fail(DSX_ERR_DEVICE, hipGetErrorString(e)));
-    }
-    try {
-        s->worker = std::thread(serve, s);
-    } catch (...) {
-        return bail(fail(DSX_ERR_NOMEM, "cannot start the dispatcher thread"));
-    }
-    *out = s;
-    return DSX_OK;
+    return guarded([&]() -> dsx_status {
+        if (!c || !out) return fail(DSX_ERR_ARG, "config and out are required");
+        *out = nullptr;
+        if (c->slots < 1 || c->slots > 16) return fail(DSX_ERR_ARG, "slots must be in 1..16");
+        if (c->queue_capacity < 1) return fail(DSX_ERR_ARG, "queue_capacity must be >= 1");
+        if (c->arena_bytes < 1) return fail(DSX_ERR_ARG, "arena_bytes must be >= 1");
+        dsx_server s = new (std::nothrow) dsx_server_s();
+        if (!s) return fail(DSX_ERR_NOMEM, "host allocation failed");
+        auto bail = [&](dsx_status st) { free_server(s); delete s; return st; };
+        (void)hipGetDevice(&s->device);
+        s->nslots = c->slots;
+        s->capacity = c->queue_capacity;
+        const size_t bytes = Arena::round((size_t)c->arena_bytes);
+        hipError_t e = hipMalloc(&s->arena_mem, bytes);
+        if (e == hipErrorOutOfMemory) { (void)hipGetLastError(); return bail(fail(DSX_ERR_NOMEM, "out of device memory for the arena")); }
+        if (e != hipSuccess) return bail(fail(DSX_ERR_DEVICE, hipGetErrorString(e)));
+        s->arena.init(bytes);
+        s->streams.assign(s->nslots, nullptr);
+        s->events.assign(s->nslots, nullptr);
+        s->busy.assign(s->nslots, 0);
+        s->running.resize(s->nslots);
+        for (int i = 0; i < s->nslots; ++i) {
+            if ((e = hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking)) != hipSuccess ||
+                (e = hipEventCreateWithFlags(&s->events[i], hipEventDisableTiming)) != hipSuccess)
+                return bail(fail(DSX_ERR_DEVICE, hipGetErrorString(e)));
+        }
+        try {
+            s->worker = std::thread(serve, s);
+        } catch (...) {
+            return bail(fail(DSX_ERR_NOMEM, "cannot start the dispatcher thread"));
+        }
+        *out = s;
+        return DSX_OK;
+    });
 }
 
 dsx_status dsx_server_add_model(dsx_server s, const dsx_model_desc* d, dsx_model* out)
 {
-    if (!s) return fail(DSX_ERR_ARG, "server is NULL");
-    dsx_status st = create_model_impl(d, true, out);
-    if (st != DSX_OK) return st;
-    (*out)->server = s;
-    std::lock_guard<std::mutex> lk(s->mu);
-    s->models.push_back(*out);
-    return DSX_OK;
+    return guarded([&]() -> dsx_status {
+        if (!s) return fail(DSX_ERR_ARG, "server is NULL");
+        dsx_status st = create_model_impl(d, true, out);
+        if (st != DSX_OK) return st;
+        (*out)->server = s;
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->models.push_back(*out);
+        return DSX_OK;
+    });
 }
 
 dsx_status dsx_server_submit(dsx_server s, const dsx_request* r, int64_t* ticket)
 {
-    if (!s || !r || !ticket) return fail(DSX_ERR_ARG, "server, request and ticket are required");
-    dsx_model m = r->model;
-    dsx_status st = check_model(m);
-    if (st != DSX_OK) return st;
-    if (m->server != s) return fail(DSX_ERR_ARG, "the model does not belong to this server");
-    if (!r->out) return fail(DSX_ERR_ARG, "out is NULL");
-    if (r->lanczos_m != 0 && (st = check_filter_args(r->lanczos_m, r->oversample)) != DSX_OK) return st;
-    if (!m->grid_set) return fail(DSX_ERR_STATE, "no output grid set");
-    if (r->config >= m->M || r->config < -1) return fail(DSX_ERR_ARG, "config out of range");
-    if (r->config >= 0) {
-        if (r->where != DSX_HOST && r->where != DSX_DEVICE) return fail(DSX_ERR_ARG, "bad 'where'");
-        if (m->has_occ && !r->occ) return fail(DSX_ERR_ARG, "occ is required (has_occ != 0)");
-        const bool need_vec = m->kind == DSX_MAGNETIC || m->order > 0;
-        if (need_vec && !(m->kind == DSX_MAGNETIC ? r->spin : r->disp))
-            return fail(DSX_ERR_ARG, m->kind == DSX_MAGNETIC ? "spin is required" : "disp is required");
-        if (m->dw_order > 0 && !r->disp) return fail(DSX_ERR_ARG, "disp is required (taylor_order > 0)");
-    }
-    Request q;
-    q.r = *r;
-    q.ws = request_workspace(m, r->lanczos_m, &q.x_bytes);
-    if (q.ws > s->arena.size())
-        return fail(DSX_ERR_NOMEM, "the request's workspace (" + std::to_string(q.ws) +
-                                   " bytes) exceeds the server's arena");
-    const int64_t sv = r->lanczos_m >= 2 ? r->oversample : 1;
-    q.voxels = sv * m->box.cnt[0] * sv * m->box.cnt[1] * sv * (int64_t)m->box.cnt[2];
-    std::lock_guard<std::mutex> lk(s->mu);
-    if (s->stop) return fail(DSX_ERR_STATE, "the server is shutting down");
-    if ((int)s->queue.size() >= s->capacity) {
-        ++s->rejected;
-        return fail(DSX_ERR_BUSY, "request queue full");
-    }
-    q.ticket = s->next_ticket++;
-    q.t_submit = Clock::now();
-    if (!s->have_first) { s->first_submit = q.t_submit; s->have_first = true; }
-    ++m->queued;
-    ++s->submitted;
-    s->pending.insert(q.ticket);
-    *ticket = q.ticket;
-    s->queue.push_back(std::move(q));
-    s->wake.notify_one();
-    return DSX_OK;
+    return guarded([&]() -> dsx_status {
+        if (!s || !r || !ticket) return fail(DSX_ERR_ARG, "server, request and ticket are required");
+        dsx_model m = r->model;
+        dsx_status st = check_model(m);
+        if (st != DSX_OK) return st;
+        if (m->server != s) return fail(DSX_ERR_ARG, "the model does not belong to this server");
+        if (!r->out) return fail(DSX_ERR_ARG, "out is NULL");
+        if (r->lanczos_m != 0 && (st = check_filter_args(r->lanczos_m, r->oversample)) != DSX_OK) return st;
+        if (!m->grid_set) return fail(DSX_ERR_STATE, "no output grid set");
+        if (r->config >= m->M || r->config < -1) return fail(DSX_ERR_ARG, "config out of range");
+        if (r->config >= 0) {
+            if (r->where != DSX_HOST && r->where != DSX_DEVICE) return fail(DSX_ERR_ARG, "bad 'where'");
+            if (m->has_occ && !r->occ) return fail(DSX_ERR_ARG, "occ is required (has_occ != 0)");
+            const bool need_vec = m->kind == DSX_MAGNETIC || m->order > 0;
+            if (need_vec && !(m->kind == DSX_MAGNETIC ? r->spin : r->disp))
+                return fail(DSX_ERR_ARG, m->kind == DSX_MAGNETIC ? "spin is required" : "disp is required");
+            if (m->dw_order > 0 && !r->disp) return fail(DSX_ERR_ARG, "disp is required (taylor_order > 0)");
+        }
+        Request q;
+        q.r = *r;
+        q.ws = request_workspace(m, r->lanczos_m, &q.x_bytes);
+        if (q.ws > s->arena.size())
+            return fail(DSX_ERR_NOMEM, "the request's workspace (" + std::to_string(q.ws) +
+                                       " bytes) exceeds the server's arena");
+        const int64_t sv = r->lanczos_m >= 2 ? r->oversample : 1;
+        q.voxels = sv * m->box.cnt[0] * sv * m->box.cnt[1] * sv * (int64_t)m->box.cnt[2];
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->stop) return fail(DSX_ERR_STATE, "the server is shutting down");
+        if ((int)s->queue.size() >= s->capacity) {
+            ++s->rejected;
+            return fail(DSX_ERR_BUSY, "request queue full");
+        }
+        q.ticket = s->next_ticket++;
+        q.t_submit = Clock::now();
+        if (!s->have_first) { s->first_submit = q.t_submit; s->have_first = true; }
+        ++m->queued;
+        ++s->submitted;
+        s->pending.insert(q.ticket);
+        *ticket = q.ticket;
+        s->queue.push_back(std::move(q));
+        s->wake.notify_one();
+        return DSX_OK;
+    });
 }
 
 dsx_status dsx_server_wait(dsx_server s, int64_t ticket, int32_t timeout_ms, dsx_status* result)
 {
-    if (!s || !result) return fail(DSX_ERR_ARG, "server and result are required");
-    std::unique_lock<std::mutex> lk(s->mu);
-    auto ready_ = [&] { return s->finished.count(ticket) > 0 || !s->pending.count(ticket); };
-    if (timeout_ms < 0) s->done.wait(lk, ready_);
-    else s->done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready_);
-    auto it = s->finished.find(ticket);
-    if (it == s->finished.end()) {
-        if (!s->pending.count(ticket)) return fail(DSX_ERR_ARG, "unknown or already retired ticket");
-        return fail(DSX_ERR_BUSY, "the request has not finished");
-    }
-    *result = it->second.status;
-    g_err = it->second.msg;
-    s->finished.erase(it);
-    return DSX_OK;
+    return guarded([&]() -> dsx_status {
+        if (!s || !result) return fail(DSX_ERR_ARG, "server and result are required");
+        std::unique_lock<std::mutex> lk(s->mu);
+        auto ready_ = [&] { return s->finished.count(ticket) > 0 || !s->pending.count(ticket); };
+        if (timeout_ms < 0) s->done.wait(lk, ready_);
+        else s->done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready_);
+        auto it = s->finished.find(ticket);
+        if (it == s->finished.end()) {
+            if (!s->pending.count(ticket)) return fail(DSX_ERR_ARG, "unknown or already retired ticket");
+            return fail(DSX_ERR_BUSY, "the request has not finished");
+        }
+        *result = it->second.status;
+        g_err = it->second.msg;
+        s->finished.erase(it);
+        return DSX_OK;
+    });
 }
 
 dsx_status dsx_server_stats_read(dsx_server s, int32_t reset, dsx_server_stats* out)
 {
-    if (!s || !out) return fail(DSX_ERR_ARG, "server and out are required");
-    std::lock_guard<std::mutex> lk(s->mu);
-    dsx_server_stats z{};
-    z.submitted = s->submitted; z.completed = s->completed; z.failed = s->failed; z.rejected = s->rejected;
-    z.voxels = s->voxels;
-    std::vector<double> l = s->lat_ms;
-    if (!l.empty()) {
-        std::sort(l.begin(), l.end());
-        auto q = [&](double p) {   // nearest-rank percentile
-            size_t k = (size_t)std::ceil(p * l.size());
-            return l[std::min(l.size(), std::max<size_t>(k, 1)) - 1];
-        };
-        z.p50_ms = q(0.50);
-        z.p99_ms = q(0.99);
-        double t = 0;
-        for (double v : l) t += v;
-        z.mean_ms = t / l.size();
-        z.max_ms = l.back();
-        z.span_s = std::chrono::duration<double>(s->last_done - s->first_submit).count();
-    }
-    z.arena_bytes = (int64_t)s->arena.size();
-    z.arena_peak_bytes = (int64_t)s->arena.peak();
-    z.slots = s->nslots;
-    z.peak_in_flight = s->peak_in_flight;
-    *out = z;
-    if (reset) {
-        s->submitted = s->completed = s->failed = s->rejected = s->voxels = 0;
-        s->lat_ms.clear();
-        s->have_first = false;
-        s->peak_in_flight = s->in_flight;
-        s->arena.reset_peak();
-    }
-    return DSX_OK;
+    return guarded([&]() -> dsx_status {
+        if (!s || !out) return fail(DSX_ERR_ARG, "server and out are required");
+        std::lock_guard<std::mutex> lk(s->mu);
+        dsx_server_stats z{};
+        z.submitted = s->submitted; z.completed = s->completed; z.failed = s->failed; z.rejected = s->rejected;
+        z.voxels = s->voxels;
+        std::vector<double> l = s->lat_ms;
+        if (!l.empty()) {
+            std::sort(l.begin(), l.end());
+            auto q = [&](double p) {   // nearest-rank percentile
+                size_t k = (size_t)std::ceil(p * l.size());
+                return l[std::min(l.size(), std::max<size_t>(k, 1)) - 1];
+            };
+            z.p50_ms = q(0.50);
+            z.p99_ms = q(0.99);
+            double t = 0;
+            for (double v : l) t += v;
+            z.mean_ms = t / l.size();
+            z.max_ms = l.back();
+            z.span_s = std::chrono::duration<double>(s->last_done - s->first_submit).count();
+        }
+        z.arena_bytes = (int64_t)s->arena.size();
+        z.arena_peak_bytes = (int64_t)s->arena.peak();
+        z.slots = s->nslots;
+        z.peak_in_flight = s->peak_in_flight;
+        *out = z;
+        if (reset) {
+            s->submitted = s->completed = s->failed = s->rejected = s->voxels = 0;
+            s->lat_ms.clear();
+            s->have_first = false;
+            s->peak_in_flight = s->in_flight;
+            s->arena.reset_peak();
+        }
+        return DSX_OK;
+    });
 }
 
 dsx_status dsx_server_destroy(dsx_server s)
 {
-    if (!s) return fail(DSX_ERR_ARG, "server is NULL");
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        s->stop = true;
-    }
-    s->wake.notify_all();
-    if (s->worker.joinable()) s->worker.join();
-    for (auto st : s->streams) if (st) (void)hipStreamSynchronize(st);
-    free_server(s);
-    delete s;
-    return DSX_OK;
+    return guarded([&]() -> dsx_status {
+        if (!s) return fail(DSX_ERR_ARG, "server is NULL");
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->stop = true;
+        }
+        s->wake.notify_all();
+        if (s->worker.joinable()) s->worker.join();
+        for (auto st : s->streams) if (st) (void)hipStreamSynchronize(st);
+        free_server(s);
+        delete s;
+        return DSX_OK;
+    });
 }
 
 }  // extern "C"
