@@ -55,7 +55,9 @@ enum { DSX_HOST = 0, DSX_DEVICE = 1 };
 /* Largest supported values (DSX_ERR_UNSUPPORTED beyond them). */
 #define DSX_MAX_N        128   /* supercell edge n_alpha                         */
 #define DSX_MAX_SITES    64    /* species-sites per unit cell                    */
-#define DSX_MAX_ORDER    8     /* Taylor order of exp(i G.u)                     */
+#define DSX_MAX_ORDER    16    /* Taylor order of exp(i G.u); above 8 the C(N+3,3)   */
+                               /* fields of one site (n3/2 + 1 complex values     */
+                               /* each) must fit the recombination's LDS          */
 
 /*
  * Model description (Sec. II; Sec. III Eq. r_vec).  An atom of site mu at lattice

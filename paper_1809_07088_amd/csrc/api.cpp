@@ -470,7 +470,8 @@ dsx_status tables_for(dsx_model m, const Box& bx, DeviceTables** out)
     const int hcs_nuc[4] = {4, 8, 17, 32};
     const int hcs_mag[3] = {4, 8, 17};
     const int* hcs = mag ? hcs_mag : hcs_nuc;
-    const int nhcs = mag ? 3 : 4;
+    // orders above kMaxOrderFast have runs of at most 8 H3 per thread
+    const int nhcs = mag ? 3 : (m->order > kMaxOrderFast ? 2 : 4);
     t.hc = hcs[nhcs - 1];
     for (int i = 0; i < nhcs; ++i) if (hcs[i] >= maxH3) { t.hc = hcs[i]; break; }
     t.nchunk3 = (maxH3 + t.hc - 1) / t.hc;
@@ -696,7 +697,7 @@ dsx_status plan_recombine(dsx_model m, const Box& bx, float* out, const Layout& 
     // parity form: every r_mu3 a multiple of 1/2 (exactly, as given); a |Q|-dependent
     // nuclear scattering factor needs the classes apart at level C (class form)
     p.nuc_ff = (m->kind == DSX_NUCLEAR && m->has_ff) ? 1 : 0;
-    p.parity = (m->kind == DSX_NUCLEAR && !p.nuc_ff) ? 1 : 0;
+    p.parity = (m->kind == DSX_NUCLEAR && !p.nuc_ff && m->order <= kMaxOrderFast) ? 1 : 0;
     for (int i = 0; i < m->S; ++i) {
         const double t2 = 2.0 * m->frac[3 * m->site_of[i] + 2];
         if (t2 != std::floor(t2)) p.parity = 0;
@@ -744,7 +745,7 @@ dsx_status plan_recombine(dsx_model m, const Box& bx, float* out, const Layout& 
     // than sites, and the class buffers fit the LDS
     // (the folded kernel addresses the spectra of one configuration with 31-bit offsets)
     const bool small_spectra = (unsigned long long)n1 * n2 * m->SF * m->nh * sizeof(float2) < (1ULL << 31);
-    if (!mag && !p.nuc_ff && p.variant != 3 && m->nclass < m->S && small_spectra) {
+    if (!mag && !p.nuc_ff && p.variant != 3 && m->nclass < m->S && small_spectra && m->order <= kMaxOrderFast) {
         bool halves = true, whole = true;
         for (int i = 0; i < m->S; ++i) {
             const double r2 = m->frac[3 * m->site_of[i] + 1];

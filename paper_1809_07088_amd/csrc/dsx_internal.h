@@ -9,8 +9,11 @@ namespace dsx {
 
 constexpr int kMaxN = 128;        // supercell edge
 constexpr int kMaxSites = 64;
-constexpr int kMaxOrder = 8;
-constexpr int kMaxMono = 165;     // monomials of total degree <= 8: C(11, 3)
+constexpr int kMaxOrder = 16;
+constexpr int kMaxMono = 969;     // monomials of total degree <= 16: C(19, 3)
+// Taylor orders above this take the class form of the recombination with at most 8 H3
+// per thread (the folded and parity forms and longer H3 runs are instantiated up to it)
+constexpr int kMaxOrderFast = 8;
 constexpr int kMaxRadices = 16;
 
 // Mixed-radix factorisation of one FFT axis.

@@ -237,7 +237,9 @@ __global__ __launch_bounds__(256) void k_sums_nuclear(SumsParams P)
 #pragma unroll
         for (int a = 0; a < 3; ++a) uv[i][a] = (in && N > 0 && P.vec) ? P.vec[3 * at + a] : 0.f;
     }
-#pragma unroll
+    // orders above kMaxOrderFast keep the group loop rolled (up to 31 groups of 32)
+    constexpr int kGroupUnroll = N <= kMaxOrderFast ? 8 : 1;
+#pragma unroll kGroupUnroll
     for (int g0 = 0; g0 < T; g0 += kSumsGroup) {
         double acc[kSumsGroup];
 #pragma unroll
@@ -338,6 +340,14 @@ hipError_t launch_sums(const SumsParams& p, int order, hipStream_t st)
             case 6: e = launch_sums_t<6>(p, st); break;
             case 7: e = launch_sums_t<7>(p, st); break;
             case 8: e = launch_sums_t<8>(p, st); break;
+            case 9: e = launch_sums_t<9>(p, st); break;
+            case 10: e = launch_sums_t<10>(p, st); break;
+            case 11: e = launch_sums_t<11>(p, st); break;
+            case 12: e = launch_sums_t<12>(p, st); break;
+            case 13: e = launch_sums_t<13>(p, st); break;
+            case 14: e = launch_sums_t<14>(p, st); break;
+            case 15: e = launch_sums_t<15>(p, st); break;
+            case 16: e = launch_sums_t<16>(p, st); break;
             default: return hipErrorInvalidValue;
         }
     }

@@ -67,12 +67,12 @@ __host__ __device__ constexpr float inv_factorial(int r) {
     return 1.f / f;
 }
 
-// 1/r! for a run-time r <= 8.
+// 1/r! for a run-time r <= kMaxOrder.
 __device__ __forceinline__ float inv_factorial_rt(int r)
 {
     float v = 1.f;
 #pragma unroll
-    for (int i = 2; i <= 8; ++i) v = (r == i) ? inv_factorial(i) : v;
+    for (int i = 2; i <= kMaxOrder; ++i) v = (r == i) ? inv_factorial(i) : v;
     return v;
 }
 
@@ -1332,11 +1332,34 @@ static hipError_t launch_nuc_hc(const RecombParams& p, int hc, int block, size_t
     }
 }
 
+// Orders above kMaxOrderFast: the class form (no folding, no parity sets), H3 runs of 4 or 8.
+template <int N>
+static hipError_t launch_nuc_hi(const RecombParams& p, int hc, int block, size_t lds, hipStream_t st)
+{
+    if (p.fold || p.parity) return hipErrorInvalidValue;
+    const bool multi = p.M > 1 || p.variant == 1;
+    switch (hc) {
+        case 4: return multi ? launch_nuc_v<N, 4, true, false>(p, block, lds, st)
+                             : launch_nuc_v<N, 4, false, false>(p, block, lds, st);
+        case 8: return multi ? launch_nuc_v<N, 8, true, false>(p, block, lds, st)
+                             : launch_nuc_v<N, 8, false, false>(p, block, lds, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_recombine_nuclear(const RecombParams& p, int order, int hc, int block,
                                     size_t lds, hipStream_t st)
 {
     if (p.nwork <= 0) return hipSuccess;
     switch (order) {
+        case 9: return launch_nuc_hi<9>(p, hc, block, lds, st);
+        case 10: return launch_nuc_hi<10>(p, hc, block, lds, st);
+        case 11: return launch_nuc_hi<11>(p, hc, block, lds, st);
+        case 12: return launch_nuc_hi<12>(p, hc, block, lds, st);
+        case 13: return launch_nuc_hi<13>(p, hc, block, lds, st);
+        case 14: return launch_nuc_hi<14>(p, hc, block, lds, st);
+        case 15: return launch_nuc_hi<15>(p, hc, block, lds, st);
+        case 16: return launch_nuc_hi<16>(p, hc, block, lds, st);
         case 0: return launch_nuc_hc<0>(p, hc, block, lds, st);
         case 1: return launch_nuc_hc<1>(p, hc, block, lds, st);
         case 2: return launch_nuc_hc<2>(p, hc, block, lds, st);
@@ -1597,6 +1620,14 @@ hipError_t launch_bragg(const BraggParams& p, int order, hipStream_t st)
         case 6: return launch_bragg_t<6>(p, grid, st);
         case 7: return launch_bragg_t<7>(p, grid, st);
         case 8: return launch_bragg_t<8>(p, grid, st);
+        case 9: return launch_bragg_t<9>(p, grid, st);
+        case 10: return launch_bragg_t<10>(p, grid, st);
+        case 11: return launch_bragg_t<11>(p, grid, st);
+        case 12: return launch_bragg_t<12>(p, grid, st);
+        case 13: return launch_bragg_t<13>(p, grid, st);
+        case 14: return launch_bragg_t<14>(p, grid, st);
+        case 15: return launch_bragg_t<15>(p, grid, st);
+        case 16: return launch_bragg_t<16>(p, grid, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -45,6 +45,8 @@ def test_field_counts_match_paper():
     for n in range(0, 9):
         full = dsx.plan_query(**fcc, taylor_order=n, has_occ=True).fields_per_site
         assert full == (n + 1) * (n + 2) * (n + 3) // 6
+    for n in (12, 16):          # C(N+3, 3) fields up to the largest order
+        assert dsx.plan_query(**fcc, taylor_order=n, has_occ=True).fields_per_site == (n + 1) * (n + 2) * (n + 3) // 6
     info = dsx.plan_query(**fcc, taylor_order=8, n_configs=3)
     assert info.fields_per_site == 164 and info.total_fields == 3 * 4 * 164
     assert info.n_classes == 2                       # r_mu3 in {0, 1/2}
@@ -68,7 +70,7 @@ def test_magnetic_plan_and_classes():
 @pytest.mark.parametrize("kw,status", [
     (dict(n=(0, 4, 4)), dsx.ERR_ARG),
     (dict(n=(4, 4, 129)), dsx.ERR_UNSUPPORTED),
-    (dict(taylor_order=9), dsx.ERR_UNSUPPORTED),
+    (dict(taylor_order=17), dsx.ERR_UNSUPPORTED),
     (dict(taylor_order=-1), dsx.ERR_ARG),
     (dict(n_configs=0), dsx.ERR_ARG),
     (dict(cell=[1, 1, 1, 90, 90, 200]), dsx.ERR_ARG),

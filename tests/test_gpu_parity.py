@@ -58,6 +58,26 @@ def test_random_model_every_order_full_box(order):
     assert_parity(I, ref)
 
 
+@pytest.mark.parametrize("order", [9, 12, 16])
+def test_high_taylor_orders_tiny_cell(order):
+    """Orders above 8 (class form, runs of at most 8 H3 per thread) up to the largest
+    supported, 16, on a tiny cell with occupancies and two configurations."""
+    m = synth.random_model(150 + order, n=(3, 4, 5), S=2, M=2, order=order, sigma=0.03)
+    m.g0, m.count = (-4, -5, -6), (9, 11, 13)
+    say(f"order {order} on n={m.n}")
+    I = gpu_intensity(m)
+    ref = O.intensity(m, O.grid_points(m.g0, m.count), order).reshape(m.count)
+    assert_parity(I, ref)
+
+
+def test_high_order_magnetic_debye_waller():
+    m = synth.random_model(170, n=(3, 4, 3), S=2, M=1, kind=synth.MAGNETIC, mag_order=12, sigma=0.03,
+                           cell=[5.0, 6.0, 7.0, 90.0, 97.0, 90.0])
+    say("magnetic Debye-Waller at order 12")
+    I = gpu_intensity(m)
+    assert_parity(I, O.intensity(m, O.grid_points(m.g0, m.count)).reshape(m.count))
+
+
 @pytest.mark.parametrize("n", [(7, 11, 9), (1, 4, 3), (5, 3, 1), (16, 2, 10),
                                (13, 26, 7), (49, 2, 7), (53, 1, 3), (2, 58, 3)])
 def test_odd_prime_and_degenerate_edges(n):
