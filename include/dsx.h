@@ -53,7 +53,7 @@ enum { DSX_NUCLEAR = 0, DSX_MAGNETIC = 1 };
 enum { DSX_HOST = 0, DSX_DEVICE = 1 };
 
 /* Largest supported values (DSX_ERR_UNSUPPORTED beyond them). */
-#define DSX_MAX_N        128   /* supercell edge n_alpha                         */
+#define DSX_MAX_N        256   /* supercell edge n_alpha                         */
 #define DSX_MAX_SITES    64    /* species-sites per unit cell                    */
 #define DSX_MAX_ORDER    16    /* Taylor order of exp(i G.u); above 8 the C(N+3,3)   */
                                /* fields of one site (n3/2 + 1 complex values     */

@@ -22,7 +22,7 @@ NUCLEAR, MAGNETIC = 0, 1
 NOALLOC_SCRATCH_BYTES = 96 * 1024 * 1024
 HOST, DEVICE = 0, 1
 OK, ERR_ARG, ERR_STATE, ERR_NOMEM, ERR_DEVICE, ERR_UNSUPPORTED, ERR_BUSY = 0, -1, -2, -3, -4, -5, -6
-MAX_N, MAX_SITES, MAX_ORDER = 128, 64, 16
+MAX_N, MAX_SITES, MAX_ORDER = 256, 64, 16
 
 
 class DsxError(RuntimeError):

@@ -857,6 +857,16 @@ dsx_status ensure_spectra(dsx_model m, hipStream_t st, bool force = false)
     if (m->tune_fchunk > 0) fb = m->tune_fchunk;
     pp.fchunk = std::min(fb, m->F);
     pp.nfchunk = (m->F + pp.fchunk - 1) / pp.fchunk;
+    // a plane too large for the LDS (edges up to 256): rows along axis 3 in blocks of a
+    // few row pairs, then axis 2 in place like axis 1
+    const bool by_rows = planes_lds_bytes(pp) > 150 * 1024;
+    if (by_rows) {
+        pp.row_pairs = std::max(1, std::min(npairs, 4096 / (m->n[2] + 2)));
+        pp.nrchunk = (npairs + pp.row_pairs - 1) / pp.row_pairs;
+        pp.buf_elems = std::max(pp.row_pairs * m->n[2], 2 * pp.row_pairs * m->nh);
+        pp.fchunk = 1;
+        pp.nfchunk = m->F;
+    }
     if (m->kind == DSX_NUCLEAR) {
         // spectra order: pairs (q, r) by e = q + r, q descending; p ascending within
         int f = 0;
@@ -869,6 +879,15 @@ dsx_status ensure_spectra(dsx_model m, hipStream_t st, bool force = false)
                 }
     }
     HIPCHK(m, timed("fft_planes", st, [&] { return launch_fft_planes(pp, st); }));
+    if (by_rows) {
+        // axis 2 in place: the spectra seen as [M n1][n2][1][S F nh]
+        Axis1Params a2{};
+        a2.X = m->d_X; a2.tw1 = m->d_tw[1]; a2.p1 = m->plan[1];
+        a2.n1 = m->n[1]; a2.n2 = 1; a2.cols = m->SF * m->nh; a2.M = m->M * m->n[0];
+        a2.tc = m->n[1] <= 64 ? 64 : 32;
+        a2.ncolblk = (a2.cols + a2.tc - 1) / a2.tc;
+        HIPCHK(m, timed("fft_axis2", st, [&] { return launch_fft_axis1(a2, st); }));
+    }
 
     Axis1Params ap{};
     ap.X = m->d_X; ap.tw1 = m->d_tw[0]; ap.p1 = m->plan[0];

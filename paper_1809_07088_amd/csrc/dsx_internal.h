@@ -7,7 +7,7 @@
 
 namespace dsx {
 
-constexpr int kMaxN = 128;        // supercell edge
+constexpr int kMaxN = 256;        // supercell edge
 constexpr int kMaxSites = 64;
 constexpr int kMaxOrder = 16;
 constexpr int kMaxMono = 969;     // monomials of total degree <= 16: C(19, 3)
@@ -66,6 +66,9 @@ struct PlaneParams {
     int32_t n1, n2, n3, nh, S, F, T, M, kind, first_mono;
     int32_t fchunk, nfchunk;
     int32_t buf_elems;    // complex elements per LDS ping-pong buffer
+    int32_t row_pairs;    // > 0: the plane does not fit the LDS; blocks take this many row pairs
+                          // and transform along axis 3 only (axis 2 follows in place)
+    int32_t nrchunk;      // row-pair chunks per plane
     int8_t mono[3 * kMaxMono];   // exponents (p, q, r) of field f (spectra order)
 };
 

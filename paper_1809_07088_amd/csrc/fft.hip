@@ -358,42 +358,25 @@ hipError_t launch_sums(const SumsParams& p, int order, hipStream_t st)
 }
 
 // ---------------------------------------------------------------------------- plane FFT
-__global__ __launch_bounds__(256) void k_fft_planes(PlaneParams P)
+// Generates the nfb fields fa.. of rows 2 j0 .. 2 (j0 + nj) - 1 of lattice plane R1 of
+// site mu, configuration m (centred by their float64 mean), packs two real rows per
+// complex line, transforms the lines along axis 3 in LDS and separates the two half
+// spectra.  Returns the LDS buffer holding row r (local) of field fb at
+// [fb * BE + r * nh + k3]; A and B are ping-pong buffers of nfb x BE elements.
+__device__ float2* planes_rows(const PlaneParams& P, float2* A, float2* B, const float2* tw3, int m, int mu,
+                               int R1, int j0, int nj, int fa, int nfb, int BE)
 {
-    extern __shared__ float2 smem[];
-    float2* tw2 = smem;
-    float2* tw3 = tw2 + P.n2;
-    float2* A = tw3 + P.n3;
-    float2* B = A + P.fchunk * P.buf_elems;
-
-    int b = blockIdx.x;
-    const int fc = b % P.nfchunk; b /= P.nfchunk;
-    const int R1 = b % P.n1; b /= P.n1;
-    const int mu = b % P.S;
-    const int m = b / P.S;
     const int n2 = P.n2, n3 = P.n3, nh = P.nh;
     const int ncell = P.n1 * n2 * n3;
-    const int SF = P.S * P.F;
-
-    for (int i = threadIdx.x; i < n2; i += blockDim.x) tw2[i] = P.tw2[i];
-    for (int i = threadIdx.x; i < n3; i += blockDim.x) tw3[i] = P.tw3[i];
-
     const size_t plane0 = ((size_t)(m * P.S + mu)) * ncell + (size_t)R1 * n2 * n3;
     const float* occ = P.occ ? P.occ + plane0 : nullptr;
     const float* vec = P.vec ? P.vec + 3 * plane0 : nullptr;
-    const int npairs = (n2 + 1) / 2;
-    const int fa = fc * P.fchunk;
-    const int nfb = min(P.F, fa + P.fchunk) - fa;     // fields of this block, batched
-    const int BE = P.buf_elems;
-
-    // generate two real rows per complex line: row 2j -> real, row 2j+1 -> imaginary
-    __syncthreads();   // twiddles visible
-    const float rpn3 = 1.f / (float)(npairs * n3), rn3 = 1.f / (float)n3, rnh = 1.f / (float)nh;
-    const float rpnh = 1.f / (float)(npairs * nh), rfnh = 1.f / (float)(nfb * nh);
-    for (int idx = threadIdx.x; idx < nfb * npairs * n3; idx += blockDim.x) {
-        const int fb = qdiv(idx, npairs * n3, rpn3);
-        const int rem = idx - fb * npairs * n3;
-        const int j = qdiv(rem, n3, rn3), R3 = rem - j * n3;
+    const float rpn3 = 1.f / (float)(nj * n3), rn3 = 1.f / (float)n3, rnh = 1.f / (float)nh;
+    const float rpnh = 1.f / (float)(nj * nh);
+    for (int idx = threadIdx.x; idx < nfb * nj * n3; idx += blockDim.x) {
+        const int fb = qdiv(idx, nj * n3, rpn3);
+        const int rem = idx - fb * nj * n3;
+        const int jj = qdiv(rem, n3, rn3), R3 = rem - jj * n3;
         const int f = fa + fb;
         const int ep = P.mono[3 * f], eq = P.mono[3 * f + 1], er = P.mono[3 * f + 2];
         const int t = P.kind == 1 ? f : mono_index(ep, eq, er);    // index of the field's lattice sum
@@ -401,7 +384,7 @@ __global__ __launch_bounds__(256) void k_fft_planes(PlaneParams P)
         float xv[2] = {0.f, 0.f};
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const int R2 = 2 * j + h;
+            const int R2 = 2 * (j0 + jj) + h;
             if (R2 < n2) {
                 const int c = R2 * n3 + R3;
                 float v;
@@ -420,34 +403,97 @@ __global__ __launch_bounds__(256) void k_fft_planes(PlaneParams P)
                 xv[h] = v - mean;
             }
         }
-        A[fb * BE + j * n3 + R3] = make_float2(xv[0], xv[1]);
+        A[fb * BE + jj * n3 + R3] = make_float2(xv[0], xv[1]);
     }
     __syncthreads();
-    float2* Z = lds_fft(A, B, npairs, n3, 1, P.p3, tw3, nfb, BE);
+    float2* Z = lds_fft(A, B, nj, n3, 1, P.p3, tw3, nfb, BE);
     float2* C = (Z == A) ? B : A;
     // unpack the packed real transforms: X_a = (Z_k + conj Z_-k)/2, X_b = -i (Z_k - conj Z_-k)/2
-    for (int idx = threadIdx.x; idx < nfb * npairs * nh; idx += blockDim.x) {
-        const int fb = qdiv(idx, npairs * nh, rpnh);
-        const int rem = idx - fb * npairs * nh;
-        const int j = qdiv(rem, nh, rnh), k = rem - j * nh;
-        const float2 zk = Z[fb * BE + j * n3 + k];
+    for (int idx = threadIdx.x; idx < nfb * nj * nh; idx += blockDim.x) {
+        const int fb = qdiv(idx, nj * nh, rpnh);
+        const int rem = idx - fb * nj * nh;
+        const int jj = qdiv(rem, nh, rnh), k = rem - jj * nh;
+        const float2 zk = Z[fb * BE + jj * n3 + k];
         const int km = (k == 0) ? 0 : n3 - k;
-        const float2 zm = Z[fb * BE + j * n3 + km];
+        const float2 zm = Z[fb * BE + jj * n3 + km];
         const float2 xa = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
         const float2 xb = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
-        C[fb * BE + (2 * j) * nh + k] = xa;
-        if (2 * j + 1 < n2) C[fb * BE + (2 * j + 1) * nh + k] = xb;
+        C[fb * BE + (2 * jj) * nh + k] = xa;
+        if (2 * (j0 + jj) + 1 < n2) C[fb * BE + (2 * jj + 1) * nh + k] = xb;
     }
     __syncthreads();
+    return C;
+}
+
+__global__ __launch_bounds__(256) void k_fft_planes(PlaneParams P)
+{
+    extern __shared__ float2 smem[];
+    float2* tw2 = smem;
+    float2* tw3 = tw2 + P.n2;
+    float2* A = tw3 + P.n3;
+    float2* B = A + P.fchunk * P.buf_elems;
+
+    int b = blockIdx.x;
+    const int fc = b % P.nfchunk; b /= P.nfchunk;
+    const int R1 = b % P.n1; b /= P.n1;
+    const int mu = b % P.S;
+    const int m = b / P.S;
+    const int n2 = P.n2, nh = P.nh;
+    const int SF = P.S * P.F;
+
+    for (int i = threadIdx.x; i < n2; i += blockDim.x) tw2[i] = P.tw2[i];
+    for (int i = threadIdx.x; i < P.n3; i += blockDim.x) tw3[i] = P.tw3[i];
+    const int fa = fc * P.fchunk;
+    const int nfb = min(P.F, fa + P.fchunk) - fa;     // fields of this block, batched
+    const int BE = P.buf_elems;
+    __syncthreads();   // twiddles visible
+    float2* C = planes_rows(P, A, B, tw3, m, mu, R1, 0, (n2 + 1) / 2, fa, nfb, BE);
     float2* D = (C == A) ? B : A;
     float2* Y = lds_fft(C, D, nh, 1, nh, P.p2, tw2, nfb, BE);
     // write: for each k2, the block's fields are contiguous runs of nh complex
+    const float rnh = 1.f / (float)nh, rfnh = 1.f / (float)(nfb * nh);
     float2* out = P.X + ((size_t)(m * P.n1 + R1) * n2) * SF * nh + (size_t)(mu * P.F + fa) * nh;
     for (int idx = threadIdx.x; idx < n2 * nfb * nh; idx += blockDim.x) {
         const int k2 = qdiv(idx, nfb * nh, rfnh);
         const int rem = idx - k2 * nfb * nh;
         const int fb = qdiv(rem, nh, rnh), k3 = rem - fb * nh;
         out[(size_t)k2 * SF * nh + rem] = Y[fb * BE + k2 * nh + k3];
+    }
+}
+
+// Planes that do not fit the LDS: rows 2 j0 .. of a plane (P.row_pairs pairs per block)
+// generated and transformed along axis 3 only, written with the row index R2 in place
+// of k2; the axis-2 transform then runs in place like the axis-1 one.
+__global__ __launch_bounds__(256) void k_fft_rows(PlaneParams P)
+{
+    extern __shared__ float2 smem[];
+    float2* tw3 = smem;
+    float2* A = tw3 + P.n3;
+    float2* B = A + P.fchunk * P.buf_elems;
+    int b = blockIdx.x;
+    const int fc = b % P.nfchunk; b /= P.nfchunk;
+    const int rc = b % P.nrchunk; b /= P.nrchunk;
+    const int R1 = b % P.n1; b /= P.n1;
+    const int mu = b % P.S;
+    const int m = b / P.S;
+    const int n2 = P.n2, nh = P.nh;
+    const int SF = P.S * P.F;
+    for (int i = threadIdx.x; i < P.n3; i += blockDim.x) tw3[i] = P.tw3[i];
+    const int fa = fc * P.fchunk;
+    const int nfb = min(P.F, fa + P.fchunk) - fa;
+    const int j0 = rc * P.row_pairs;
+    const int nj = min((n2 + 1) / 2, j0 + P.row_pairs) - j0;
+    const int BE = P.buf_elems;
+    __syncthreads();
+    const float2* C = planes_rows(P, A, B, tw3, m, mu, R1, j0, nj, fa, nfb, BE);
+    const int nrow = min(n2, 2 * (j0 + nj)) - 2 * j0;
+    const float rnh = 1.f / (float)nh, rfnh = 1.f / (float)(nfb * nh);
+    float2* out = P.X + ((size_t)(m * P.n1 + R1) * n2 + 2 * j0) * SF * nh + (size_t)(mu * P.F + fa) * nh;
+    for (int idx = threadIdx.x; idx < nrow * nfb * nh; idx += blockDim.x) {
+        const int r = qdiv(idx, nfb * nh, rfnh);
+        const int rem = idx - r * nfb * nh;
+        const int fb = qdiv(rem, nh, rnh), k3 = rem - fb * nh;
+        out[(size_t)r * SF * nh + rem] = C[fb * BE + r * nh + k3];
     }
 }
 
@@ -667,7 +713,7 @@ static hipError_t launch_planes_reg2(const PlaneParams& p, hipStream_t st)
 
 size_t planes_lds_bytes(const PlaneParams& p)
 {
-    return sizeof(float2) * (size_t)(p.n2 + p.n3 + 2 * p.fchunk * p.buf_elems);
+    return sizeof(float2) * (size_t)((p.row_pairs > 0 ? 0 : p.n2) + p.n3 + 2 * p.fchunk * p.buf_elems);
 }
 
 hipError_t launch_fft_planes(const PlaneParams& p, hipStream_t st)
@@ -680,6 +726,15 @@ hipError_t launch_fft_planes(const PlaneParams& p, hipStream_t st)
         }
     }
     const size_t lds = planes_lds_bytes(p);
+    if (p.row_pairs > 0) {
+        if (lds > 65536) {
+            hipError_t e = hipFuncSetAttribute((const void*)k_fft_rows,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(k_fft_rows, dim3(p.M * p.S * p.n1 * p.nrchunk * p.nfchunk), dim3(256), lds, st, p);
+        return hipGetLastError();
+    }
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)k_fft_planes,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -69,7 +69,7 @@ def test_magnetic_plan_and_classes():
 
 @pytest.mark.parametrize("kw,status", [
     (dict(n=(0, 4, 4)), dsx.ERR_ARG),
-    (dict(n=(4, 4, 129)), dsx.ERR_UNSUPPORTED),
+    (dict(n=(4, 4, 257)), dsx.ERR_UNSUPPORTED),
     (dict(taylor_order=17), dsx.ERR_UNSUPPORTED),
     (dict(taylor_order=-1), dsx.ERR_ARG),
     (dict(n_configs=0), dsx.ERR_ARG),

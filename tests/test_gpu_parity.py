@@ -58,6 +58,27 @@ def test_random_model_every_order_full_box(order):
     assert_parity(I, ref)
 
 
+@pytest.mark.parametrize("n,order", [((256, 2, 3), 3), ((3, 256, 2), 3), ((2, 3, 256), 3),
+                                     ((2, 256, 256), 0), ((3, 144, 250), 2)])
+def test_edges_up_to_256(n, order):
+    """Supercell edges up to 256 on every axis; planes of 256 x 256 and 144 x 250 exceed
+    the LDS and take the row route (axis 3 per row pair, then axis 2 in place)."""
+    m = synth.random_model(400 + sum(n), n=n, S=1 if order == 0 else 2, M=1, order=order,
+                           with_disp=order > 0, sigma=0.03)
+    m.g0 = tuple(-min(v + 1, 20) for v in n)
+    m.count = tuple(min(2 * v + 3, 41) for v in n)
+    say(f"edges n={n} order={order} box={m.count}")
+    I = gpu_intensity(m)
+    G = O.grid_points(m.g0, m.count)
+    if len(G) > 6000:
+        sel = np.random.default_rng(1).choice(len(G), 6000, replace=False)
+        G = G[sel]
+        got = I[tuple((G - np.asarray(m.g0)).T)]
+    else:
+        got = I.reshape(-1)
+    assert_parity(got, O.intensity(m, G, order if order > 0 else None))
+
+
 @pytest.mark.parametrize("order", [9, 12, 16])
 def test_high_taylor_orders_tiny_cell(order):
     """Orders above 8 (class form, runs of at most 8 H3 per thread) up to the largest
