@@ -453,7 +453,8 @@ def bench_compositional(dsx, torch, dev, steps, O=None, seeds=1024):
     torch.cuda.synchronize()
     tb = (time.perf_counter() - t0) / max(3, steps // 4)
     res["batch_of_models"] = {"models": seeds, "ms_per_step": round(tb * 1e3, 3),
-                              "voxels_per_s": round(seeds * vox / tb, 1), "create_s": round(t_create, 2)}
+                              "voxels_per_s": round(seeds * vox / tb, 1), "create_s": round(t_create, 2),
+                              "graph": batch_graph_report(dsx, batch.info())}
     if O is not None:
         m1 = synth.compositional(n=12, M=1, hmax=2)
         m1.occ = occs[seeds - 1].cpu().numpy()[None]
@@ -525,6 +526,7 @@ def bench_ensemble(dsx, torch, dev, steps, warmup, lm=2, probe=False, batched_on
         copy_probe(torch, dev)
     t_batch = timed(batched)
     same = all(torch.equal(a, b) for a, b in zip(ref, outs))
+    graph = batch.info()
     batch.close()
     for h in hs:
         h.close()
@@ -538,7 +540,19 @@ def bench_ensemble(dsx, torch, dev, steps, warmup, lm=2, probe=False, batched_on
             "batched_compute_ms": round((t_batch - t_upload) * 1e3, 3),
             "plain_compute_ms": round((t_plain - t_upload) * 1e3, 3),
             "create_and_tune_s": round(t_create, 2),
-            "batched_equals_plain": bool(same)}
+            "batched_equals_plain": bool(same),
+            "graph": batch_graph_report(dsx, graph)}
+
+
+def batch_graph_report(dsx, info):
+    """The batch's graph: the form it runs (chosen by timing both at creation), kernel
+    launches of the models against dispatches of the graph, and both forms' replay times."""
+    return {"form": "merged" if info["mode"] == dsx.BATCH_MERGED else "per_model",
+            "model_launches": info["launches"], "graph_dispatches": info["dispatches"],
+            "merged_dispatches": info["merged_nodes"], "kept_apart_for_spills": info["unmerged_spill"],
+            "merged_form_dispatches": info["merged_form_dispatches"] if info["merged_form_dispatches"] >= 0 else None,
+            "per_model_replay_ms": round(info["per_model_ms"], 4) if info["per_model_ms"] > 0 else None,
+            "merged_replay_ms": round(info["merged_ms"], 4) if info["merged_ms"] > 0 else None}
 
 
 def serving_pool(n_models=64, variants=4, frac=0.01):

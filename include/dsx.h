@@ -272,12 +272,18 @@ dsx_status dsx_filter_points(dsx_model m, int32_t lanczos_m, int32_t mprime, int
  * supercells averaged as an ensemble (Sec. III.B) and notes that their intensity
  * calculations can run in parallel (Sec. VI).  A batch fixes a set of ready models
  * (sites and grid set), one device output per model and the filter parameters.
- * dsx_batch_create tunes and plans every model (dsx_autotune), then records the
- * whole launch sequence -- per model its lattice sums, FFTs, recombination, Bragg
- * points and, when lanczos_m >= 2, the filter; each model on its own forked stream
- * -- into one hipGraph.  dsx_batch_run replays it on hip_stream: one graph launch
- * recomputes every model from its current sites (dsx_set_sites between runs is
- * allowed; grids and outputs are fixed).
+ * dsx_batch_create tunes and plans every model (dsx_autotune), then records each
+ * model's launch sequence -- its lattice sums, FFTs, recombination, Bragg points and,
+ * when lanczos_m >= 2, the filter -- and builds one hipGraph of kernel nodes from them.
+ * In the merged form, the launches of one step that run the same kernel (same
+ * template instance and block size) become one dispatch over a descriptor table:
+ * model d's blocks take a range of the merged grid (aligned to the 8 XCDs) and read
+ * their parameters from entry d, so models of uneven n share a dispatch wherever
+ * their kernels do; kernels whose merged form would spill registers are not merged.
+ * The per-model form gives every launch its own node.  A node waits only for the
+ * nodes that hold its models' previous launches.  dsx_batch_run replays the graph on
+ * hip_stream: one graph launch recomputes every model from its current sites
+ * (dsx_set_sites between runs is allowed; grids and outputs are fixed).
  *   models[n]  distinct models; n >= 1
  *   lanczos_m  0 = unfiltered I(G) (outs[i]: [count0][count1][count2] of model i),
  *              >= 2 = filtered with oversample s (outs[i]: [s count0][s count1][s count2])
@@ -292,6 +298,24 @@ typedef struct dsx_batch_s* dsx_batch;
 
 dsx_status dsx_batch_create(const dsx_model* models, int32_t n, int32_t lanczos_m, int32_t oversample,
                             float* const* outs, dsx_batch* out);
+/* mode of dsx_batch_create_mode: DSX_BATCH_AUTO builds both forms, times three
+ * replays of each on the device and keeps the faster (what dsx_batch_create does) */
+enum { DSX_BATCH_AUTO = 0, DSX_BATCH_PER_MODEL = 1, DSX_BATCH_MERGED = 2 };
+dsx_status dsx_batch_create_mode(const dsx_model* models, int32_t n, int32_t lanczos_m, int32_t oversample,
+                                 float* const* outs, int32_t mode, dsx_batch* out);
+typedef struct {
+    int32_t mode;              /* the form the batch runs: DSX_BATCH_PER_MODEL or DSX_BATCH_MERGED */
+    int32_t launches;          /* kernel launches of all models' sequences */
+    int32_t dispatches;        /* kernel nodes of the graph the batch replays */
+    int32_t merged_nodes;      /* nodes of that graph that serve more than one model */
+    int32_t unmerged_spill;    /* launches kept apart because their merged kernel spills */
+    int32_t merged_form_dispatches; /* kernel nodes of the merged form when it was built
+                                       (also when the batch runs the per-model form); else -1 */
+    float per_model_ms;        /* best of three replays of each form, when both were timed; else -1 */
+    float merged_ms;
+} dsx_batch_info;
+/* DSX_ERR_ARG for a NULL batch or info */
+dsx_status dsx_batch_query(dsx_batch b, dsx_batch_info* info);
 dsx_status dsx_batch_run(dsx_batch b, void* hip_stream);
 dsx_status dsx_batch_destroy(dsx_batch b);
 

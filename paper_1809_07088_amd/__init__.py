@@ -52,9 +52,20 @@ EXPORTS = ("dsx_plan_query", "dsx_create_model", "dsx_set_sites", "dsx_set_sites
            "dsx_compute_intensity", "dsx_compute_intensity_noalloc", "dsx_noise_filter", "dsx_destroy_model", "dsx_last_error",
            "dsx_version", "dsx_profile_enable", "dsx_profile_select", "dsx_profile_read", "dsx_profile_reset",
            "dsx_noise_filter_cutoff", "dsx_filter_points", "dsx_split_sites", "dsx_noise_filter_spherical",
-           "dsx_batch_create", "dsx_batch_run", "dsx_batch_destroy", "dsx_autotune", "dsx_tune_query",
+           "dsx_batch_create", "dsx_batch_create_mode", "dsx_batch_query", "dsx_batch_run", "dsx_batch_destroy",
+           "dsx_autotune", "dsx_tune_query",
            "dsx_tune_set", "dsx_server_create", "dsx_server_add_model", "dsx_server_submit", "dsx_server_wait",
            "dsx_server_stats_read", "dsx_server_destroy")
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("launches", ctypes.c_int32), ("dispatches", ctypes.c_int32),
+                ("merged_nodes", ctypes.c_int32), ("unmerged_spill", ctypes.c_int32),
+                ("merged_form_dispatches", ctypes.c_int32),
+                ("per_model_ms", ctypes.c_float), ("merged_ms", ctypes.c_float)]
+
+
+BATCH_AUTO, BATCH_PER_MODEL, BATCH_MERGED = 0, 1, 2
+
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("slots", ctypes.c_int32), ("queue_capacity", ctypes.c_int32), ("arena_bytes", ctypes.c_int64)]
@@ -118,6 +129,8 @@ def lib():
         L.dsx_profile_reset.argtypes = []
         L.dsx_profile_reset.restype = i32
         L.dsx_batch_create.argtypes = [P, i32, i32, i32, P, ctypes.POINTER(P)]
+        L.dsx_batch_create_mode.argtypes = [P, i32, i32, i32, P, i32, ctypes.POINTER(P)]
+        L.dsx_batch_query.argtypes = [P, ctypes.POINTER(BatchInfo)]
         L.dsx_batch_run.argtypes = [P, P]
         L.dsx_batch_destroy.argtypes = [P]
         L.dsx_autotune.argtypes = [P, i32, P]
@@ -129,7 +142,8 @@ def lib():
         L.dsx_server_wait.argtypes = [P, ctypes.c_int64, i32, ctypes.POINTER(i32)]
         L.dsx_server_stats_read.argtypes = [P, i32, ctypes.POINTER(ServerStats)]
         L.dsx_server_destroy.argtypes = [P]
-        for f in ("dsx_batch_create", "dsx_batch_run", "dsx_batch_destroy", "dsx_autotune", "dsx_tune_query",
+        for f in ("dsx_batch_create", "dsx_batch_create_mode", "dsx_batch_query", "dsx_batch_run",
+                  "dsx_batch_destroy", "dsx_autotune", "dsx_tune_query",
                   "dsx_tune_set", "dsx_server_create", "dsx_server_add_model", "dsx_server_submit", "dsx_server_wait",
                   "dsx_server_stats_read", "dsx_server_destroy"):
             getattr(L, f).restype = i32
@@ -380,9 +394,10 @@ def tune_set(model, recombine_form, fft_fields_per_block, filter_planes_per_bloc
 
 
 class Batch:
-    """A recorded launch sequence over several models (dsx_batch_*): run() replays it."""
+    """A recorded launch sequence over several models (dsx_batch_*): run() replays it.
+    mode: BATCH_AUTO (time both forms, keep the faster), BATCH_PER_MODEL or BATCH_MERGED."""
 
-    def __init__(self, models, outs, lanczos_m=0, oversample=1):
+    def __init__(self, models, outs, lanczos_m=0, oversample=1, mode=BATCH_AUTO):
         handles = [m.handle if isinstance(m, Model) else m for m in models]
         if len(handles) != len(outs) or not handles:
             raise ValueError("one output per model, at least one model")
@@ -390,9 +405,16 @@ class Batch:
         arr_m = (ctypes.c_void_p * len(handles))(*handles)
         arr_o = (ctypes.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
         h = ctypes.c_void_p()
-        _check(lib().dsx_batch_create(ctypes.cast(arr_m, ctypes.c_void_p), len(handles), int(lanczos_m),
-                                      int(oversample), ctypes.cast(arr_o, ctypes.c_void_p), ctypes.byref(h)))
+        _check(lib().dsx_batch_create_mode(ctypes.cast(arr_m, ctypes.c_void_p), len(handles), int(lanczos_m),
+                                           int(oversample), ctypes.cast(arr_o, ctypes.c_void_p), int(mode),
+                                           ctypes.byref(h)))
         self.handle = h.value
+
+    def info(self):
+        """The form the batch runs and its graph: dict of dsx_batch_info."""
+        i = BatchInfo()
+        _check(lib().dsx_batch_query(self.handle, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in BatchInfo._fields_}
 
     def run(self, stream=None):
         _check(lib().dsx_batch_run(self.handle, _stream_handle(stream)))

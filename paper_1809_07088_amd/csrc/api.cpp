@@ -86,6 +86,10 @@ Prof g_prof;
 template <typename Fn>
 hipError_t timed(const char* name, hipStream_t st, Fn fn)
 {
+    if (g_recorder) {            // a batch records its launches: label them with the step
+        g_recorder->stage = name;
+        return fn();
+    }
     if (!g_prof.on) return fn();
     hipEvent_t a, b;
     {
@@ -835,8 +839,9 @@ dsx_status ensure_spectra(dsx_model m, hipStream_t st, bool force = false)
         // (the partials are free again: the spins' reduction ran before on this stream)
         SumsParams dp = sp;
         dp.vec = m->d_dsp; dp.sums = m->d_dwsums; dp.T = m->dwT; dp.kind = DSX_NUCLEAR;
-        HIPCHK(m, timed("sums", st, [&] { return launch_sums(dp, m->dw_order, st); }));
-        HIPCHK(m, timed("sums", st, [&] { return launch_dw_mean(m->d_dwsums, m->d_dwc, m->M, m->S, m->dwT, st); }));
+        HIPCHK(m, timed("dw_sums", st, [&] { return launch_sums(dp, m->dw_order, st); }));
+        const DwParams dwp{m->d_dwsums, m->d_dwc, m->M, m->S, m->dwT};
+        HIPCHK(m, timed("dw_mean", st, [&] { return launch_dw_mean(dwp, st); }));
     }
 
     PlaneParams pp;
@@ -1962,39 +1967,252 @@ dsx_status dsx_tune_query(dsx_model m, int32_t choice[3], int32_t* tuned)
 }  // extern "C"
 
 // ---------------------------------------------------------------------------- batches
+namespace {
+
+// One kernel node of a batch graph: a model's launch, or the launches of several
+// models merged over a descriptor table.
+struct BatchNode {
+    const void* fn = nullptr;
+    unsigned grid = 0, block = 0, lds = 0;
+    bool merged = false;
+    std::vector<unsigned char> params;     // single launch: its parameter block
+    std::vector<int> members;              // merged: the models, in descriptor order
+    std::vector<unsigned> counts;          // merged: each model's own grid
+    std::vector<int> recs;                 // merged: each model's record index
+    size_t tab_off = 0, slot_off = 0;      // merged: its arrays in the graph's device block
+    std::vector<int> deps;                 // nodes holding the members' previous launches
+};
+
+struct BatchGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void* dmem = nullptr;                  // descriptor tables and slot maps
+    int dispatches = 0, merged_nodes = 0, spill_kept = 0;
+};
+
+void free_graph(BatchGraph& g)
+{
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    if (g.dmem) (void)hipFree(g.dmem);
+    g = BatchGraph{};
+}
+
+// Position of a step in the path: launches of one step are merged, a step's nodes of
+// different kernels run side by side.
+int stage_rank(const char* s)
+{
+    static const char* const order[] = {"sums", "dw_sums", "dw_mean", "fft_planes", "fft_axis2",
+                                        "fft_axis1", "recombine", "bragg", "lanczos"};
+    for (int i = 0; i < (int)(sizeof(order) / sizeof(order[0])); ++i)
+        if (std::strcmp(s, order[i]) == 0) return i;
+    return (int)(sizeof(order) / sizeof(order[0]));
+}
+
+// A merged kernel is used only where it keeps the single kernel's registers in
+// registers: no more private (spill) memory per lane than the single form.
+bool merge_keeps_registers(const void* one, const void* merged)
+{
+    hipFuncAttributes a{}, b{};
+    if (hipFuncGetAttributes(&a, one) != hipSuccess || hipFuncGetAttributes(&b, merged) != hipSuccess) return false;
+    return b.localSizeBytes <= a.localSizeBytes;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Build the graph of the recorded sequences: merged (launches of a step that share a
+// kernel and block size become one node) or one node per launch.
+dsx_status build_batch_graph(const std::vector<std::vector<LaunchRec>>& seq, bool merge, BatchGraph& out)
+{
+    const int n = (int)seq.size();
+    std::vector<size_t> head(n, 0);
+    std::vector<int> last(n, -1);
+    std::vector<BatchNode> nodes;
+    int spill_kept = 0;
+    for (;;) {
+        int best = INT_MAX;
+        for (int i = 0; i < n; ++i)
+            if (head[i] < seq[i].size()) best = std::min(best, stage_rank(seq[i][head[i]].stage));
+        if (best == INT_MAX) break;
+        // the heads of this step, grouped by kernel and block size (in model order)
+        std::vector<std::pair<std::pair<const void*, unsigned>, std::vector<int>>> groups;
+        for (int i = 0; i < n; ++i) {
+            if (head[i] >= seq[i].size()) continue;
+            const LaunchRec& r = seq[i][head[i]];
+            if (stage_rank(r.stage) != best) continue;
+            const auto key = std::make_pair(r.merged, r.block);
+            auto g = std::find_if(groups.begin(), groups.end(), [&](const auto& x) { return x.first == key; });
+            if (g == groups.end()) groups.push_back({key, {i}});
+            else g->second.push_back(i);
+        }
+        for (auto& g : groups) {
+            const std::vector<int>& mem = g.second;
+            const LaunchRec& r0 = seq[mem[0]][head[mem[0]]];
+            bool m = merge && mem.size() > 1;
+            if (m && !merge_keeps_registers(r0.one, r0.merged)) {
+                m = false;
+                spill_kept += (int)mem.size();
+            }
+            if (!m) {
+                for (int i : mem) {
+                    const LaunchRec& r = seq[i][head[i]];
+                    BatchNode nd;
+                    nd.fn = r.one; nd.grid = r.grid; nd.block = r.block; nd.lds = r.lds;
+                    nd.params = r.params;
+                    if (last[i] >= 0) nd.deps.push_back(last[i]);
+                    last[i] = (int)nodes.size();
+                    ++head[i];
+                    nodes.push_back(std::move(nd));
+                }
+                continue;
+            }
+            BatchNode nd;
+            nd.fn = r0.merged; nd.block = r0.block; nd.merged = true;
+            for (int i : mem) {
+                const LaunchRec& r = seq[i][head[i]];
+                if (r.params.size() != r0.params.size()) return fail(DSX_ERR_STATE, "batch: mismatched parameter blocks");
+                nd.members.push_back(i);
+                nd.counts.push_back(r.grid);
+                nd.recs.push_back((int)head[i]);
+                // every model's range starts at a multiple of 8 blocks: blocks keep their XCD
+                const unsigned long long g8 = (unsigned long long)nd.grid + ((r.grid + 7u) & ~7u);
+                if (g8 > 0x7fffffffULL) return fail(DSX_ERR_UNSUPPORTED, "batch: merged grid too large");
+                nd.grid = (unsigned)g8;
+                nd.lds = std::max(nd.lds, r.lds);
+                if (last[i] >= 0 && std::find(nd.deps.begin(), nd.deps.end(), last[i]) == nd.deps.end())
+                    nd.deps.push_back(last[i]);
+            }
+            for (int i : mem) { last[i] = (int)nodes.size(); ++head[i]; }
+            nodes.push_back(std::move(nd));
+        }
+    }
+    // device block: per merged node its descriptor array and its slot map
+    size_t bytes = 0;
+    for (BatchNode& nd : nodes) {
+        if (!nd.merged) continue;
+        nd.tab_off = bytes;
+        bytes = align256(bytes + nd.members.size() * seq[nd.members[0]][nd.recs[0]].params.size());
+        nd.slot_off = bytes;
+        bytes = align256(bytes + (size_t)(nd.grid / 8) * sizeof(Slot));
+    }
+    BatchGraph g;
+    auto bail = [&](dsx_status st) { free_graph(g); return st; };
+    hipError_t e = hipSuccess;
+    if (bytes) {
+        std::vector<unsigned char> host(bytes, 0);
+        for (BatchNode& nd : nodes) {
+            if (!nd.merged) continue;
+            const size_t ps = seq[nd.members[0]][nd.recs[0]].params.size();
+            Slot* sl = reinterpret_cast<Slot*>(host.data() + nd.slot_off);
+            int first = 0;
+            for (size_t d = 0; d < nd.members.size(); ++d) {
+                const LaunchRec& r = seq[nd.members[d]][nd.recs[d]];
+                std::memcpy(host.data() + nd.tab_off + d * ps, r.params.data(), ps);
+                const int span = (int)((nd.counts[d] + 7u) & ~7u);
+                for (int b = first; b < first + span; b += 8)
+                    sl[b / 8] = Slot{(int32_t)d, first, (int32_t)nd.counts[d], 0};
+                first += span;
+            }
+        }
+        if ((e = hipMalloc(&g.dmem, bytes)) != hipSuccess) return bail(fail(DSX_ERR_NOMEM, hipGetErrorString(e)));
+        if ((e = hipMemcpy(g.dmem, host.data(), bytes, hipMemcpyHostToDevice)) != hipSuccess)
+            return bail(fail(DSX_ERR_DEVICE, hipGetErrorString(e)));
+    }
+    if ((e = hipGraphCreate(&g.graph, 0)) != hipSuccess) return bail(fail(DSX_ERR_DEVICE, hipGetErrorString(e)));
+    std::vector<hipGraphNode_t> gn(nodes.size(), nullptr);
+    std::vector<hipGraphNode_t> deps;
+    for (size_t k = 0; k < nodes.size(); ++k) {
+        BatchNode& nd = nodes[k];
+        if (nd.lds > 65536 &&
+            (e = hipFuncSetAttribute(nd.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)nd.lds)) != hipSuccess)
+            return bail(fail(DSX_ERR_DEVICE, hipGetErrorString(e)));
+        void* tab = g.dmem ? (char*)g.dmem + nd.tab_off : nullptr;
+        void* slots = g.dmem ? (char*)g.dmem + nd.slot_off : nullptr;
+        void* margs[2] = {&tab, &slots};
+        void* sargs[1] = {nd.params.data()};
+        hipKernelNodeParams kp{};
+        kp.func = const_cast<void*>(nd.fn);
+        kp.gridDim = dim3(nd.grid);
+        kp.blockDim = dim3(nd.block);
+        kp.sharedMemBytes = nd.lds;
+        kp.kernelParams = nd.merged ? margs : sargs;
+        kp.extra = nullptr;
+        deps.clear();
+        for (int d : nd.deps) deps.push_back(gn[d]);
+        if ((e = hipGraphAddKernelNode(&gn[k], g.graph, deps.empty() ? nullptr : deps.data(), deps.size(), &kp)) != hipSuccess)
+            return bail(fail(DSX_ERR_DEVICE, std::string("graph node: ") + hipGetErrorString(e)));
+        ++g.dispatches;
+        if (nd.merged) ++g.merged_nodes;
+    }
+    if ((e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0)) != hipSuccess)
+        return bail(fail(DSX_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e)));
+    g.spill_kept = spill_kept;
+    out = g;
+    return DSX_OK;
+}
+
+}  // namespace
+
 struct dsx_batch_s {
     std::vector<dsx_model> models;
     std::vector<float*> outs;
     int lanczos_m = 0, oversample = 1;
+    int mode = DSX_BATCH_PER_MODEL, launches = 0, merged_form_dispatches = -1;
+    float per_model_ms = -1.f, merged_ms = -1.f;
     hipStream_t cap = nullptr;
-    std::vector<hipStream_t> streams;
-    hipEvent_t fork = nullptr;
-    std::vector<hipEvent_t> joins;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    BatchGraph g;
 };
 
 namespace {
 
 void free_batch(dsx_batch b)
 {
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
-    for (auto e : b->joins) if (e) (void)hipEventDestroy(e);
-    if (b->fork) (void)hipEventDestroy(b->fork);
-    for (auto st : b->streams) if (st) (void)hipStreamDestroy(st);
+    free_graph(b->g);
     if (b->cap) (void)hipStreamDestroy(b->cap);
+}
+
+// Each model's launch sequence, recorded (nothing runs).  The models' dirty flags are
+// kept: recording computes nothing.
+dsx_status record_batch(dsx_batch b, std::vector<std::vector<LaunchRec>>& seq)
+{
+    const int n = (int)b->models.size();
+    seq.assign(n, {});
+    for (int i = 0; i < n; ++i) {
+        dsx_model m = b->models[i];
+        const bool dirty = m->dirty;
+        Recorder r;
+        struct Reset { ~Reset() { g_recorder = nullptr; } } reset;
+        g_recorder = &r;
+        const dsx_status s = b->lanczos_m ? enqueue_filter(m, b->lanczos_m, b->oversample, b->outs[i], b->cap, true)
+                                          : enqueue_intensity(m, b->outs[i], b->cap, true);
+        g_recorder = nullptr;
+        m->dirty = dirty;
+        if (s != DSX_OK) return s;
+        seq[i] = std::move(r.recs);
+    }
+    return DSX_OK;
+}
+
+// Best of three replays of graph g on stream st (after one untimed replay), ms.
+float time_graph(const BatchGraph& g, hipStream_t st)
+{
+    if (hipGraphLaunch(g.exec, st) != hipSuccess) return -1.f;
+    return time_min(st, 3, [&]() -> dsx_status {
+        return hipGraphLaunch(g.exec, st) == hipSuccess ? DSX_OK : DSX_ERR_DEVICE;
+    });
 }
 
 }  // namespace
 
 extern "C" {
 
-dsx_status dsx_batch_create(const dsx_model* models, int32_t n, int32_t lanczos_m, int32_t oversample,
-                            float* const* outs, dsx_batch* out)
+dsx_status dsx_batch_create_mode(const dsx_model* models, int32_t n, int32_t lanczos_m, int32_t oversample,
+                                 float* const* outs, int32_t mode, dsx_batch* out)
 {
     return guarded([&]() -> dsx_status {
         if (!models || !outs || !out || n < 1) return fail(DSX_ERR_ARG, "models, outs and out are required, n >= 1");
+        if (mode != DSX_BATCH_AUTO && mode != DSX_BATCH_PER_MODEL && mode != DSX_BATCH_MERGED)
+            return fail(DSX_ERR_ARG, "unknown batch mode");
         *out = nullptr;
         dsx_status s;
         if (lanczos_m != 0 && (s = check_filter_args(lanczos_m, oversample)) != DSX_OK) return s;
@@ -2007,14 +2225,19 @@ dsx_status dsx_batch_create(const dsx_model* models, int32_t n, int32_t lanczos_
         }
         dsx_batch b = new (std::nothrow) dsx_batch_s();
         if (!b) return fail(DSX_ERR_NOMEM, "host allocation failed");
-        b->models.assign(models, models + n);
-        b->outs.assign(outs, outs + n);
+        auto bail = [&](dsx_status st) { free_batch(b); delete b; return st; };
+        try {
+            b->models.assign(models, models + n);
+            b->outs.assign(outs, outs + n);
+        } catch (...) {
+            delete b;
+            throw;
+        }
         b->lanczos_m = lanczos_m;
         b->oversample = lanczos_m ? oversample : 1;
-        auto bail = [&](dsx_status st) { free_batch(b); delete b; return st; };
         hipError_t e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
         if (e != hipSuccess) return bail(fail(DSX_ERR_DEVICE, hipGetErrorString(e)));
-        // plan and tune (allocations and uploads happen here, never during capture)
+        // plan and tune (allocations and uploads happen here, never in the graph)
         for (int i = 0; i < n; ++i) {
             dsx_model m = b->models[i];
             if (!m->tuned && (s = dsx_autotune(m, lanczos_m, b->cap)) != DSX_OK) return bail(s);
@@ -2022,45 +2245,54 @@ dsx_status dsx_batch_create(const dsx_model* models, int32_t n, int32_t lanczos_
             if (lanczos_m && (s = prepare_filter(m, lanczos_m, b->oversample)) != DSX_OK) return bail(s);
         }
         if ((e = hipStreamSynchronize(b->cap)) != hipSuccess) return bail(fail(DSX_ERR_DEVICE, hipGetErrorString(e)));
-        b->streams.assign(n, nullptr);
-        b->joins.assign(n, nullptr);
-        if ((e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming)) != hipSuccess)
-            return bail(fail(DSX_ERR_DEVICE, hipGetErrorString(e)));
-        for (int i = 0; i < n; ++i) {
-            if ((e = hipStreamCreateWithFlags(&b->streams[i], hipStreamNonBlocking)) != hipSuccess ||
-                (e = hipEventCreateWithFlags(&b->joins[i], hipEventDisableTiming)) != hipSuccess)
-                return bail(fail(DSX_ERR_DEVICE, hipGetErrorString(e)));
+        std::vector<std::vector<LaunchRec>> seq;
+        if ((s = record_batch(b, seq)) != DSX_OK) return bail(s);
+        for (const auto& q : seq) b->launches += (int)q.size();
+        if ((s = build_batch_graph(seq, mode != DSX_BATCH_PER_MODEL, b->g)) != DSX_OK) return bail(s);
+        // a graph without merged nodes is the per-model form
+        b->mode = b->g.merged_nodes > 0 ? DSX_BATCH_MERGED : DSX_BATCH_PER_MODEL;
+        if (mode != DSX_BATCH_PER_MODEL) b->merged_form_dispatches = b->g.dispatches;
+        if (mode == DSX_BATCH_AUTO && b->mode == DSX_BATCH_MERGED) {
+            // time both forms on the device and keep the faster
+            BatchGraph pm;
+            if ((s = build_batch_graph(seq, false, pm)) != DSX_OK) return bail(s);
+            for (dsx_model m : b->models) (void)hipStreamSynchronize(m->last_stream);
+            b->merged_ms = time_graph(b->g, b->cap);
+            b->per_model_ms = time_graph(pm, b->cap);
+            if ((e = hipStreamSynchronize(b->cap)) != hipSuccess || b->merged_ms < 0.f || b->per_model_ms < 0.f) {
+                free_graph(pm);
+                return bail(fail(DSX_ERR_DEVICE, "batch: timing the graphs failed"));
+            }
+            if (b->per_model_ms < b->merged_ms) {
+                std::swap(b->g, pm);
+                b->mode = DSX_BATCH_PER_MODEL;
+            }
+            free_graph(pm);
         }
-        // record every model's launch sequence into one graph
-        const bool prof = g_prof.on;
-        g_prof.on = false;
-        dsx_status cs = DSX_OK;
-        if ((e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed)) != hipSuccess) {
-            g_prof.on = prof;
-            return bail(fail(DSX_ERR_DEVICE, hipGetErrorString(e)));
-        }
-        e = hipEventRecord(b->fork, b->cap);
-        for (int i = 0; i < n && e == hipSuccess && cs == DSX_OK; ++i) {
-            dsx_model m = b->models[i];
-            hipStream_t si = b->streams[i];
-            if ((e = hipStreamWaitEvent(si, b->fork, 0)) != hipSuccess) break;
-            cs = lanczos_m ? enqueue_filter(m, lanczos_m, b->oversample, b->outs[i], si, true)
-                           : enqueue_intensity(m, b->outs[i], si, true);
-            if (cs != DSX_OK) break;
-            if ((e = hipEventRecord(b->joins[i], si)) != hipSuccess) break;
-            e = hipStreamWaitEvent(b->cap, b->joins[i], 0);
-        }
-        hipGraph_t g = nullptr;
-        const hipError_t ee = hipStreamEndCapture(b->cap, &g);
-        g_prof.on = prof;
-        b->graph = g;
-        if (cs != DSX_OK) return bail(cs);
-        if (e != hipSuccess || ee != hipSuccess)
-            return bail(fail(DSX_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : ee)));
-        if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess)
-            return bail(fail(DSX_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e)));
         for (dsx_model m : b->models) ++m->pins;
         *out = b;
+        return DSX_OK;
+    });
+}
+
+dsx_status dsx_batch_create(const dsx_model* models, int32_t n, int32_t lanczos_m, int32_t oversample,
+                            float* const* outs, dsx_batch* out)
+{
+    return dsx_batch_create_mode(models, n, lanczos_m, oversample, outs, DSX_BATCH_AUTO, out);
+}
+
+dsx_status dsx_batch_query(dsx_batch b, dsx_batch_info* info)
+{
+    return guarded([&]() -> dsx_status {
+        if (!b || !info) return fail(DSX_ERR_ARG, "batch and info are required");
+        info->mode = b->mode;
+        info->launches = b->launches;
+        info->dispatches = b->g.dispatches;
+        info->merged_nodes = b->g.merged_nodes;
+        info->unmerged_spill = b->g.spill_kept;
+        info->merged_form_dispatches = b->merged_form_dispatches;
+        info->per_model_ms = b->per_model_ms;
+        info->merged_ms = b->merged_ms;
         return DSX_OK;
     });
 }
@@ -2078,7 +2310,7 @@ dsx_status dsx_batch_run(dsx_batch b, void* hip_stream)
             dsx_status s = follow(m, st);
             if (s != DSX_OK) return s;
         }
-        const hipError_t e = hipGraphLaunch(b->exec, st);
+        const hipError_t e = hipGraphLaunch(b->g.exec, st);
         if (e != hipSuccess) {
             for (dsx_model m : b->models) m->failed = true;
             return fail(DSX_ERR_DEVICE, std::string("graph launch: ") + hipGetErrorString(e));

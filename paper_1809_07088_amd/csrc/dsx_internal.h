@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace dsx {
 
 constexpr int kMaxN = 256;        // supercell edge
@@ -195,6 +197,68 @@ struct PointsParams {
     float rcut;             // (1 - 1/m)/m'
 };
 
+// ---------------------------------------------------------------------------- merged launches
+// Several launches of one kernel (one per model of a batch) can run as one grid: the
+// launch of descriptor d, g_d blocks, takes the merged blocks [first_d, first_d + g_d),
+// first_d a multiple of 8, so a block sits on the XCD it would have in its own launch
+// (the dispatcher deals consecutive blocks round-robin to the 8 XCDs) and the kernels'
+// XCD-aware tile orders still hold.  Each group of 8 merged blocks has one slot.
+struct Slot {
+    int32_t d;              // descriptor: index into the kernel's parameter array
+    int32_t first;          // first merged block of the descriptor
+    int32_t count;          // blocks of the descriptor's own launch
+    int32_t pad;
+};
+
+// Descriptor and block index (within its own launch) of this block; false on the
+// padding blocks past the descriptor's own grid.
+__device__ __forceinline__ bool slot_of(const Slot* __restrict__ slots, int& d, int& bx)
+{
+    const Slot s = slots[blockIdx.x >> 3];
+    d = s.d;
+    bx = (int)blockIdx.x - s.first;
+    return bx < s.count;
+}
+
+// One launch as recorded for a merged batch: the merged form of its kernel, its grid,
+// block and dynamic LDS, and a copy of its parameter block.
+struct LaunchRec {
+    const void* one = nullptr;      // kernel (P params)
+    const void* merged = nullptr;   // kernel (const P* params, const Slot* slots)
+    uint32_t grid = 0, block = 0, lds = 0;
+    const char* stage = "";         // the step of the path it belongs to
+    std::vector<unsigned char> params;
+};
+
+// While a host thread's recorder is set, the launchers append their launches to it
+// instead of issuing them (the batch planner reads the sequence of each model).
+struct Recorder {
+    std::vector<LaunchRec> recs;
+    const char* stage = "";
+};
+inline thread_local Recorder* g_recorder = nullptr;
+
+// Issue a launch of `one` (or record it with its merged form `merged`).
+template <class P>
+hipError_t dispatch(void (*one)(P), void (*merged)(const P*, const Slot*), unsigned grid, unsigned block,
+                    size_t lds, hipStream_t st, const P& p)
+{
+    if (grid == 0) return hipSuccess;
+    if (Recorder* r = g_recorder) {
+        LaunchRec rec;
+        rec.one = reinterpret_cast<const void*>(one);
+        rec.merged = reinterpret_cast<const void*>(merged);
+        rec.grid = grid; rec.block = block; rec.lds = (uint32_t)lds;
+        rec.stage = r->stage;
+        rec.params.resize(sizeof(P));
+        __builtin_memcpy(rec.params.data(), &p, sizeof(P));
+        r->recs.push_back(std::move(rec));
+        return hipSuccess;
+    }
+    void* args[] = {const_cast<P*>(&p)};
+    return hipLaunchKernel(reinterpret_cast<const void*>(one), dim3(grid), dim3(block), args, lds, st);
+}
+
 // ---------------------------------------------------------------------------- launchers
 hipError_t launch_sums(const SumsParams& p, int order, hipStream_t st);
 hipError_t launch_fft_planes(const PlaneParams& p, hipStream_t st);
@@ -218,7 +282,12 @@ inline size_t magnetic_rows_lds_elems(int rows, int csites, int S, int nclass, i
 hipError_t launch_bragg(const BraggParams& p, int order, hipStream_t st);
 // dwc[mu][t] = sum_m sums[m][mu][t] / sum_m sums[m][mu][0] (0 for a site with no atom):
 // the Debye-Waller means of Eq. dw from the float64 lattice sums of the displacements.
-hipError_t launch_dw_mean(const double* sums, double* dwc, int M, int S, int T, hipStream_t st);
+struct DwParams {
+    const double* sums;     // [M][S][T]
+    double* dwc;            // [S][T]
+    int32_t M, S, T;
+};
+hipError_t launch_dw_mean(const DwParams& p, hipStream_t st);
 hipError_t launch_lanczos(const LanczosParams& p, hipStream_t st);
 hipError_t launch_lanczos_points(const PointsParams& p, hipStream_t st);
 // the spherical cutoff: p.wn holds [s^3][(2m)^3] normalised weights; m in {2, 3, 4}

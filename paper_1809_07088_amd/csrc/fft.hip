@@ -213,14 +213,14 @@ __device__ __forceinline__ double wave_transpose_sum(double (&acc)[kSumsGroup], 
     return acc[0] + __shfl_xor(acc[0], 1, 64);
 }
 
-template <int N>
-__global__ __launch_bounds__(256) void k_sums_nuclear(SumsParams P)
+template <int N, class PT>
+__device__ __forceinline__ void sums_nuclear_body(PT P, const int bx)
 {
     constexpr int T = n_monomials(N);
     constexpr MonoTable<N> mt = mono_table<N>();
     __shared__ double red[4][kSumsGroup];
-    const int chunk = blockIdx.x % P.nchunk;
-    const int ms = blockIdx.x / P.nchunk;
+    const int chunk = bx % P.nchunk;
+    const int ms = bx / P.nchunk;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int c0 = chunk * P.chunk + threadIdx.x;
     const int c1 = min(P.ncell, (chunk + 1) * P.chunk);
@@ -273,11 +273,21 @@ __global__ __launch_bounds__(256) void k_sums_nuclear(SumsParams P)
     }
 }
 
-__global__ __launch_bounds__(256) void k_sums_magnetic(SumsParams P)
+template <int N>
+__global__ __launch_bounds__(256) void k_sums_nuclear(SumsParams P) { sums_nuclear_body<N, SumsParams>(P, blockIdx.x); }
+template <int N>
+__global__ __launch_bounds__(256) void k_sums_nuclear_merged(const SumsParams* __restrict__ tab, const Slot* __restrict__ slots)
+{
+    int d, bx;
+    if (slot_of(slots, d, bx)) sums_nuclear_body<N, const SumsParams&>(tab[d], bx);
+}
+
+template <class PT>
+__device__ __forceinline__ void sums_magnetic_body(PT P, const int bx)
 {
     __shared__ double red[4][3];
-    const int chunk = blockIdx.x % P.nchunk;
-    const int ms = blockIdx.x / P.nchunk;
+    const int chunk = bx % P.nchunk;
+    const int ms = bx / P.nchunk;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double acc[3] = {0.0, 0.0, 0.0};
     const int c0 = chunk * P.chunk;
@@ -302,11 +312,19 @@ __global__ __launch_bounds__(256) void k_sums_magnetic(SumsParams P)
     }
 }
 
+__global__ __launch_bounds__(256) void k_sums_magnetic(SumsParams P) { sums_magnetic_body<SumsParams>(P, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_sums_magnetic_merged(const SumsParams* __restrict__ tab, const Slot* __restrict__ slots)
+{
+    int d, bx;
+    if (slot_of(slots, d, bx)) sums_magnetic_body<const SumsParams&>(tab[d], bx);
+}
+
 // One wave per output sum: lanes read the chunk partials, then a fixed-order
 // shuffle reduction (reproducible).
-__global__ __launch_bounds__(256) void k_sums_reduce(SumsParams P)
+template <class PT>
+__device__ __forceinline__ void sums_reduce_body(PT P, const int bx)
 {
-    const int idx = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int idx = bx * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (idx >= P.M * P.S * P.T) return;
     const int ms = idx / P.T, t = idx - ms * P.T;
@@ -316,19 +334,24 @@ __global__ __launch_bounds__(256) void k_sums_reduce(SumsParams P)
     if (lane == 0) P.sums[idx] = v;
 }
 
+__global__ __launch_bounds__(256) void k_sums_reduce(SumsParams P) { sums_reduce_body<SumsParams>(P, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_sums_reduce_merged(const SumsParams* __restrict__ tab, const Slot* __restrict__ slots)
+{
+    int d, bx;
+    if (slot_of(slots, d, bx)) sums_reduce_body<const SumsParams&>(tab[d], bx);
+}
+
 template <int N>
 static hipError_t launch_sums_t(const SumsParams& p, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_sums_nuclear<N>, dim3(p.M * p.S * p.nchunk), dim3(256), 0, st, p);
-    return hipGetLastError();
+    return dispatch(k_sums_nuclear<N>, k_sums_nuclear_merged<N>, p.M * p.S * p.nchunk, 256, 0, st, p);
 }
 
 hipError_t launch_sums(const SumsParams& p, int order, hipStream_t st)
 {
     hipError_t e = hipSuccess;
     if (p.kind == 1) {
-        hipLaunchKernelGGL(k_sums_magnetic, dim3(p.M * p.S * p.nchunk), dim3(256), 0, st, p);
-        e = hipGetLastError();
+        e = dispatch(k_sums_magnetic, k_sums_magnetic_merged, p.M * p.S * p.nchunk, 256, 0, st, p);
     } else {
         switch (order) {
             case 0: e = launch_sums_t<0>(p, st); break;
@@ -353,8 +376,7 @@ hipError_t launch_sums(const SumsParams& p, int order, hipStream_t st)
     }
     if (e != hipSuccess) return e;
     const int tot = p.M * p.S * p.T;
-    hipLaunchKernelGGL(k_sums_reduce, dim3((tot + 3) / 4), dim3(256), 0, st, p);
-    return hipGetLastError();
+    return dispatch(k_sums_reduce, k_sums_reduce_merged, (tot + 3) / 4, 256, 0, st, p);
 }
 
 // ---------------------------------------------------------------------------- plane FFT
@@ -363,7 +385,7 @@ hipError_t launch_sums(const SumsParams& p, int order, hipStream_t st)
 // complex line, transforms the lines along axis 3 in LDS and separates the two half
 // spectra.  Returns the LDS buffer holding row r (local) of field fb at
 // [fb * BE + r * nh + k3]; A and B are ping-pong buffers of nfb x BE elements.
-__device__ float2* planes_rows(const PlaneParams& P, float2* A, float2* B, const float2* tw3, int m, int mu,
+__device__ __forceinline__ float2* planes_rows(const PlaneParams& P, float2* A, float2* B, const float2* tw3, int m, int mu,
                                int R1, int j0, int nj, int fa, int nfb, int BE)
 {
     const int n2 = P.n2, n3 = P.n3, nh = P.nh;
@@ -425,7 +447,8 @@ __device__ float2* planes_rows(const PlaneParams& P, float2* A, float2* B, const
     return C;
 }
 
-__global__ __launch_bounds__(256) void k_fft_planes(PlaneParams P)
+template <class PT>
+__device__ __forceinline__ void fft_planes_body(PT P, const int bx)
 {
     extern __shared__ float2 smem[];
     float2* tw2 = smem;
@@ -433,7 +456,7 @@ __global__ __launch_bounds__(256) void k_fft_planes(PlaneParams P)
     float2* A = tw3 + P.n3;
     float2* B = A + P.fchunk * P.buf_elems;
 
-    int b = blockIdx.x;
+    int b = bx;
     const int fc = b % P.nfchunk; b /= P.nfchunk;
     const int R1 = b % P.n1; b /= P.n1;
     const int mu = b % P.S;
@@ -461,16 +484,24 @@ __global__ __launch_bounds__(256) void k_fft_planes(PlaneParams P)
     }
 }
 
+__global__ __launch_bounds__(256) void k_fft_planes(PlaneParams P) { fft_planes_body<PlaneParams>(P, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_fft_planes_merged(const PlaneParams* __restrict__ tab, const Slot* __restrict__ slots)
+{
+    int d, bx;
+    if (slot_of(slots, d, bx)) fft_planes_body<const PlaneParams&>(tab[d], bx);
+}
+
 // Planes that do not fit the LDS: rows 2 j0 .. of a plane (P.row_pairs pairs per block)
 // generated and transformed along axis 3 only, written with the row index R2 in place
 // of k2; the axis-2 transform then runs in place like the axis-1 one.
-__global__ __launch_bounds__(256) void k_fft_rows(PlaneParams P)
+template <class PT>
+__device__ __forceinline__ void fft_rows_body(PT P, const int bx)
 {
     extern __shared__ float2 smem[];
     float2* tw3 = smem;
     float2* A = tw3 + P.n3;
     float2* B = A + P.fchunk * P.buf_elems;
-    int b = blockIdx.x;
+    int b = bx;
     const int fc = b % P.nfchunk; b /= P.nfchunk;
     const int rc = b % P.nrchunk; b /= P.nrchunk;
     const int R1 = b % P.n1; b /= P.n1;
@@ -495,6 +526,13 @@ __global__ __launch_bounds__(256) void k_fft_rows(PlaneParams P)
         const int fb = qdiv(rem, nh, rnh), k3 = rem - fb * nh;
         out[(size_t)r * SF * nh + rem] = C[fb * BE + r * nh + k3];
     }
+}
+
+__global__ __launch_bounds__(256) void k_fft_rows(PlaneParams P) { fft_rows_body<PlaneParams>(P, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_fft_rows_merged(const PlaneParams* __restrict__ tab, const Slot* __restrict__ slots)
+{
+    int d, bx;
+    if (slot_of(slots, d, bx)) fft_rows_body<const PlaneParams&>(tab[d], bx);
 }
 
 // ---------------------------------------------------------------------------- register FFTs
@@ -533,14 +571,14 @@ __device__ __forceinline__ void fft_reg(float2 (&z)[L], const float2* __restrict
 // Axis 1 in place: one thread per column (k2, c), the L1 values of the column in
 // registers.  Columns are contiguous in memory, so every load and store of a wave
 // is one contiguous run.
-template <int L1>
-__global__ __launch_bounds__(256) void k_fft_axis1_reg(Axis1Params P)
+template <int L1, class PT>
+__device__ __forceinline__ void fft_axis1_reg_body(PT P, const int bx)
 {
     __shared__ float2 tw[L1];
     for (int i = threadIdx.x; i < L1; i += blockDim.x) tw[i] = P.tw1[i];
     __syncthreads();
     const unsigned per_m = (unsigned)P.n2 * (unsigned)P.cols;
-    const unsigned g = blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned g = bx * blockDim.x + threadIdx.x;
     if (g >= per_m * (unsigned)P.M) return;
     const unsigned m = g / per_m, rem = g - m * per_m;
     float2* base = P.X + (size_t)m * L1 * per_m + rem;
@@ -550,6 +588,15 @@ __global__ __launch_bounds__(256) void k_fft_axis1_reg(Axis1Params P)
     fft_reg<L1>(z, tw);
 #pragma unroll
     for (int k = 0; k < L1; ++k) base[(size_t)k * per_m] = z[k];
+}
+
+template <int L1>
+__global__ __launch_bounds__(256) void k_fft_axis1_reg(Axis1Params P) { fft_axis1_reg_body<L1, Axis1Params>(P, blockIdx.x); }
+template <int L1>
+__global__ __launch_bounds__(256) void k_fft_axis1_reg_merged(const Axis1Params* __restrict__ tab, const Slot* __restrict__ slots)
+{
+    int d, bx;
+    if (slot_of(slots, d, bx)) fft_axis1_reg_body<L1, const Axis1Params&>(tab[d], bx);
 }
 
 // One lattice plane R1 of one site, a chunk of kRegFC fields, for power-of-two
@@ -562,8 +609,8 @@ __global__ __launch_bounds__(256) void k_fft_axis1_reg(Axis1Params P)
 //     writes it to the spectra (k3 fastest across the wave: contiguous runs).
 constexpr int kRegFC = 8, kRegThreads = 128;
 
-template <int L2, int L3>
-__global__ __launch_bounds__(kRegThreads) void k_fft_planes_reg(PlaneParams P)
+template <int L2, int L3, class PT>
+__device__ __forceinline__ void fft_planes_reg_body(PT P, const int bx)
 {
     constexpr int NH = L3 / 2 + 1;
     constexpr int RP = L3 + 1;                         // real row pitch (floats)
@@ -575,7 +622,7 @@ __global__ __launch_bounds__(kRegThreads) void k_fft_planes_reg(PlaneParams P)
     __shared__ float buf[UN];
     __shared__ float meanf[kRegFC];
 
-    int b = blockIdx.x;
+    int b = bx;
     const int fc = b % P.nfchunk; b /= P.nfchunk;
     const int R1 = b % P.n1; b /= P.n1;
     const int mu = b % P.S;
@@ -688,6 +735,15 @@ __global__ __launch_bounds__(kRegThreads) void k_fft_planes_reg(PlaneParams P)
     }
 }
 
+template <int L2, int L3>
+__global__ __launch_bounds__(kRegThreads) void k_fft_planes_reg(PlaneParams P) { fft_planes_reg_body<L2, L3, PlaneParams>(P, blockIdx.x); }
+template <int L2, int L3>
+__global__ __launch_bounds__(kRegThreads) void k_fft_planes_reg_merged(const PlaneParams* __restrict__ tab, const Slot* __restrict__ slots)
+{
+    int d, bx;
+    if (slot_of(slots, d, bx)) fft_planes_reg_body<L2, L3, const PlaneParams&>(tab[d], bx);
+}
+
 bool fft_reg_supported(int n) { return n == 8 || n == 16 || n == 32; }
 
 template <int L2, int L3>
@@ -696,8 +752,8 @@ static hipError_t launch_planes_reg(const PlaneParams& p, hipStream_t st)
     PlaneParams q = p;
     q.fchunk = kRegFC;
     q.nfchunk = (p.F + kRegFC - 1) / kRegFC;
-    hipLaunchKernelGGL((k_fft_planes_reg<L2, L3>), dim3(q.M * q.S * q.n1 * q.nfchunk), dim3(kRegThreads), 0, st, q);
-    return hipGetLastError();
+    return dispatch(k_fft_planes_reg<L2, L3>, k_fft_planes_reg_merged<L2, L3>, q.M * q.S * q.n1 * q.nfchunk,
+                    kRegThreads, 0, st, q);
 }
 
 template <int L2>
@@ -732,26 +788,25 @@ hipError_t launch_fft_planes(const PlaneParams& p, hipStream_t st)
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
         }
-        hipLaunchKernelGGL(k_fft_rows, dim3(p.M * p.S * p.n1 * p.nrchunk * p.nfchunk), dim3(256), lds, st, p);
-        return hipGetLastError();
+        return dispatch(k_fft_rows, k_fft_rows_merged, p.M * p.S * p.n1 * p.nrchunk * p.nfchunk, 256, lds, st, p);
     }
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)k_fft_planes,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_fft_planes, dim3(p.M * p.S * p.n1 * p.nfchunk), dim3(256), lds, st, p);
-    return hipGetLastError();
+    return dispatch(k_fft_planes, k_fft_planes_merged, p.M * p.S * p.n1 * p.nfchunk, 256, lds, st, p);
 }
 
 // ---------------------------------------------------------------------------- axis-1 FFT
-__global__ __launch_bounds__(256) void k_fft_axis1(Axis1Params P)
+template <class PT>
+__device__ __forceinline__ void fft_axis1_body(PT P, const int bx)
 {
     extern __shared__ float2 smem[];
     float2* tw = smem;
     float2* A = tw + P.n1;
     float2* B = A + P.n1 * P.tc;
-    int b = blockIdx.x;
+    int b = bx;
     const int cb = b % P.ncolblk; b /= P.ncolblk;
     const int k2 = b % P.n2;
     const int m = b / P.n2;
@@ -782,6 +837,13 @@ __global__ __launch_bounds__(256) void k_fft_axis1(Axis1Params P)
     }
 }
 
+__global__ __launch_bounds__(256) void k_fft_axis1(Axis1Params P) { fft_axis1_body<Axis1Params>(P, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_fft_axis1_merged(const Axis1Params* __restrict__ tab, const Slot* __restrict__ slots)
+{
+    int d, bx;
+    if (slot_of(slots, d, bx)) fft_axis1_body<const Axis1Params&>(tab[d], bx);
+}
+
 size_t axis1_lds_bytes(const Axis1Params& p)
 {
     return sizeof(float2) * (size_t)(p.n1 + 2 * p.n1 * p.tc);
@@ -791,11 +853,10 @@ hipError_t launch_fft_axis1(const Axis1Params& p, hipStream_t st)
 {
     if (fft_reg_supported(p.n1)) {
         const unsigned total = (unsigned)p.M * p.n2 * p.cols;
-        const dim3 grid((total + 255) / 256);
-        if (p.n1 == 8) hipLaunchKernelGGL(k_fft_axis1_reg<8>, grid, dim3(256), 0, st, p);
-        else if (p.n1 == 16) hipLaunchKernelGGL(k_fft_axis1_reg<16>, grid, dim3(256), 0, st, p);
-        else hipLaunchKernelGGL(k_fft_axis1_reg<32>, grid, dim3(256), 0, st, p);
-        return hipGetLastError();
+        const unsigned grid = (total + 255) / 256;
+        if (p.n1 == 8) return dispatch(k_fft_axis1_reg<8>, k_fft_axis1_reg_merged<8>, grid, 256, 0, st, p);
+        if (p.n1 == 16) return dispatch(k_fft_axis1_reg<16>, k_fft_axis1_reg_merged<16>, grid, 256, 0, st, p);
+        return dispatch(k_fft_axis1_reg<32>, k_fft_axis1_reg_merged<32>, grid, 256, 0, st, p);
     }
     const size_t lds = axis1_lds_bytes(p);
     if (lds > 65536) {
@@ -803,8 +864,7 @@ hipError_t launch_fft_axis1(const Axis1Params& p, hipStream_t st)
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_fft_axis1, dim3(p.M * p.n2 * p.ncolblk), dim3(256), lds, st, p);
-    return hipGetLastError();
+    return dispatch(k_fft_axis1, k_fft_axis1_merged, p.M * p.n2 * p.ncolblk, 256, lds, st, p);
 }
 
 }  // namespace dsx

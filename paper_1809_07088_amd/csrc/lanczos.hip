@@ -26,11 +26,12 @@ __device__ __forceinline__ int xcd_tile(int b, int ntiles)
     return t < ntiles ? t : -1;
 }
 
-__global__ __launch_bounds__(256) void k_lanczos(LanczosParams P)
+template <class PT>
+__device__ __forceinline__ void lanczos_body(PT P, const int bx)
 {
     extern __shared__ float sm[];
     const int m2 = 2 * P.m, s = P.s;
-    int b = xcd_tile(blockIdx.x, P.nb1 * P.nb2 * P.nb3);
+    int b = xcd_tile(bx, P.nb1 * P.nb2 * P.nb3);
     if (b < 0) return;
     const int b3 = b % P.nb3; b /= P.nb3;
     const int b2 = b % P.nb2;
@@ -103,6 +104,13 @@ __global__ __launch_bounds__(256) void k_lanczos(LanczosParams P)
     }
 }
 
+__global__ __launch_bounds__(256) void k_lanczos(LanczosParams P) { lanczos_body<LanczosParams>(P, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_lanczos_merged(const LanczosParams* __restrict__ tab, const Slot* __restrict__ slots)
+{
+    int d, bx;
+    if (slot_of(slots, d, bx)) lanczos_body<const LanczosParams&>(tab[d], bx);
+}
+
 // Register-ring variant for m = M2/2 in {2, 3, 4} and a 32 x 64 output tile.
 // Per input plane: the plane's tile (with halo) is staged in LDS; the axis-3 pass
 // gives each thread a run of four consecutive columns of one row (it reads the
@@ -113,8 +121,8 @@ __global__ __launch_bounds__(256) void k_lanczos(LanczosParams P)
 // registers while a plane is filtered.  Three block barriers per plane.
 constexpr int kRT2 = 32, kRT3 = 64, kRThreads = 512, kRRun = 4;
 
-template <int M2, bool S1>
-__global__ __launch_bounds__(512, 2) void k_lanczos_ring(LanczosParams P)
+template <int M2, bool S1, class PT>
+__device__ __forceinline__ void lanczos_ring_body(PT P, const int bx)
 {
     constexpr int L2 = kRT2 + M2 - 1;                     // staged rows (s = 1)
     constexpr int L3 = (kRT3 + M2 - 1 + 3) & ~3;          // staged row pitch (s = 1), 16-byte rows
@@ -123,7 +131,7 @@ __global__ __launch_bounds__(512, 2) void k_lanczos_ring(LanczosParams P)
     __shared__ __align__(16) float stg[(S1 ? L2 * L3 : 1)];
     __shared__ __align__(16) float mid[(S1 ? L2 * kRT3 : 1)];
     static_assert(S1, "the oversampled filter takes the generic kernel");
-    int b = xcd_tile(blockIdx.x, P.nb1 * P.nb2 * P.nb3);
+    int b = xcd_tile(bx, P.nb1 * P.nb2 * P.nb3);
     if (b < 0) return;
     const int b3 = b % P.nb3; b /= P.nb3;
     const int b2 = b % P.nb2;
@@ -245,6 +253,15 @@ __global__ __launch_bounds__(512, 2) void k_lanczos_ring(LanczosParams P)
     }
 }
 
+template <int M2, bool S1>
+__global__ __launch_bounds__(512, 2) void k_lanczos_ring(LanczosParams P) { lanczos_ring_body<M2, S1, LanczosParams>(P, blockIdx.x); }
+template <int M2, bool S1>
+__global__ __launch_bounds__(512, 2) void k_lanczos_ring_merged(const LanczosParams* __restrict__ tab, const Slot* __restrict__ slots)
+{
+    int d, bx;
+    if (slot_of(slots, d, bx)) lanczos_ring_body<M2, S1, const LanczosParams&>(tab[d], bx);
+}
+
 size_t lanczos_lds_bytes(const LanczosParams& p)
 {
     const int m2 = 2 * p.m;
@@ -266,11 +283,10 @@ hipError_t launch_lanczos(const LanczosParams& p, hipStream_t st)
         q.nb2 = (p.o[1] + kRT2 - 1) / kRT2;
         q.nb3 = (p.o[2] + p.eoff + kRT3 - 1) / kRT3;
         if (p.ohalf) q.nb1 = (p.ohalf + p.t1 - 1) / p.t1;
-        const dim3 grid(8 * ((q.nb1 * q.nb2 * q.nb3 + 7) / 8));
-        if (p.m == 2) hipLaunchKernelGGL((k_lanczos_ring<4, true>), grid, dim3(kRThreads), 0, st, q);
-        else if (p.m == 3) hipLaunchKernelGGL((k_lanczos_ring<6, true>), grid, dim3(kRThreads), 0, st, q);
-        else hipLaunchKernelGGL((k_lanczos_ring<8, true>), grid, dim3(kRThreads), 0, st, q);
-        return hipGetLastError();
+        const unsigned grid = 8 * ((q.nb1 * q.nb2 * q.nb3 + 7) / 8);
+        if (p.m == 2) return dispatch(k_lanczos_ring<4, true>, k_lanczos_ring_merged<4, true>, grid, kRThreads, 0, st, q);
+        if (p.m == 3) return dispatch(k_lanczos_ring<6, true>, k_lanczos_ring_merged<6, true>, grid, kRThreads, 0, st, q);
+        return dispatch(k_lanczos_ring<8, true>, k_lanczos_ring_merged<8, true>, grid, kRThreads, 0, st, q);
     }
     const size_t lds = lanczos_lds_bytes(p);
     if (lds > 65536) {
@@ -278,8 +294,7 @@ hipError_t launch_lanczos(const LanczosParams& p, hipStream_t st)
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_lanczos, dim3(8 * ((p.nb1 * p.nb2 * p.nb3 + 7) / 8)), dim3(256), lds, st, p);
-    return hipGetLastError();
+    return dispatch(k_lanczos, k_lanczos_merged, 8 * ((p.nb1 * p.nb2 * p.nb3 + 7) / 8), 256, lds, st, p);
 }
 
 // ---------------------------------------------------------------------------- points
@@ -288,10 +303,10 @@ hipError_t launch_lanczos(const LanczosParams& p, hipStream_t st)
 // float64 offsets Q_a - G_a), then sums the (2w)^3 neighbourhood from the dense box,
 // which the host sized to hold every window.  The normaliser is the product of the
 // three one-axis weight sums (the weight is separable).
-template <int W>
-__global__ __launch_bounds__(256) void k_lanczos_points(PointsParams P)
+template <int W, class PT>
+__device__ __forceinline__ void lanczos_points_body(PT P, const int bx)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)bx * blockDim.x + threadIdx.x;
     if (i >= P.npts) return;
     float wt[3][2 * W];
     int lo[3];
@@ -333,21 +348,29 @@ __global__ __launch_bounds__(256) void k_lanczos_points(PointsParams P)
     P.out[i] = acc / norm;
 }
 
+template <int W>
+__global__ __launch_bounds__(256) void k_lanczos_points(PointsParams P) { lanczos_points_body<W, PointsParams>(P, blockIdx.x); }
+template <int W>
+__global__ __launch_bounds__(256) void k_lanczos_points_merged(const PointsParams* __restrict__ tab, const Slot* __restrict__ slots)
+{
+    int d, bx;
+    if (slot_of(slots, d, bx)) lanczos_points_body<W, const PointsParams&>(tab[d], bx);
+}
+
 hipError_t launch_lanczos_points(const PointsParams& p, hipStream_t st)
 {
-    const dim3 grid((unsigned)((p.npts + 255) / 256));
+    const unsigned grid = (unsigned)((p.npts + 255) / 256);
     switch (p.w) {
-        case 1: hipLaunchKernelGGL(k_lanczos_points<1>, grid, dim3(256), 0, st, p); break;
-        case 2: hipLaunchKernelGGL(k_lanczos_points<2>, grid, dim3(256), 0, st, p); break;
-        case 3: hipLaunchKernelGGL(k_lanczos_points<3>, grid, dim3(256), 0, st, p); break;
-        case 4: hipLaunchKernelGGL(k_lanczos_points<4>, grid, dim3(256), 0, st, p); break;
-        case 5: hipLaunchKernelGGL(k_lanczos_points<5>, grid, dim3(256), 0, st, p); break;
-        case 6: hipLaunchKernelGGL(k_lanczos_points<6>, grid, dim3(256), 0, st, p); break;
-        case 7: hipLaunchKernelGGL(k_lanczos_points<7>, grid, dim3(256), 0, st, p); break;
-        case 8: hipLaunchKernelGGL(k_lanczos_points<8>, grid, dim3(256), 0, st, p); break;
+        case 1: return dispatch(k_lanczos_points<1>, k_lanczos_points_merged<1>, grid, 256, 0, st, p);
+        case 2: return dispatch(k_lanczos_points<2>, k_lanczos_points_merged<2>, grid, 256, 0, st, p);
+        case 3: return dispatch(k_lanczos_points<3>, k_lanczos_points_merged<3>, grid, 256, 0, st, p);
+        case 4: return dispatch(k_lanczos_points<4>, k_lanczos_points_merged<4>, grid, 256, 0, st, p);
+        case 5: return dispatch(k_lanczos_points<5>, k_lanczos_points_merged<5>, grid, 256, 0, st, p);
+        case 6: return dispatch(k_lanczos_points<6>, k_lanczos_points_merged<6>, grid, 256, 0, st, p);
+        case 7: return dispatch(k_lanczos_points<7>, k_lanczos_points_merged<7>, grid, 256, 0, st, p);
+        case 8: return dispatch(k_lanczos_points<8>, k_lanczos_points_merged<8>, grid, 256, 0, st, p);
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------- spherical
@@ -357,10 +380,10 @@ hipError_t launch_lanczos_points(const PointsParams& p, hipStream_t st)
 // normalised weights of the s^3 output phases come from a float64 host table
 // [s^3][(2m)^3]; the input is the grown box, mirrored planes read as in the ring
 // filter.
-template <int T>
-__global__ __launch_bounds__(256) void k_lanczos_stencil(LanczosParams P)
+template <int T, class PT>
+__device__ __forceinline__ void lanczos_stencil_body(PT P, const int bx)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t idx = (int64_t)bx * blockDim.x + threadIdx.x;
     const int64_t total = (int64_t)P.o[0] * P.o[1] * P.o[2];
     if (idx >= total) return;
     const int i3 = (int)(idx % P.o[2]);
@@ -390,20 +413,29 @@ __global__ __launch_bounds__(256) void k_lanczos_stencil(LanczosParams P)
     P.out[idx] = acc;
 }
 
+template <int T>
+__global__ __launch_bounds__(256) void k_lanczos_stencil(LanczosParams P) { lanczos_stencil_body<T, LanczosParams>(P, blockIdx.x); }
+template <int T>
+__global__ __launch_bounds__(256) void k_lanczos_stencil_merged(const LanczosParams* __restrict__ tab, const Slot* __restrict__ slots)
+{
+    int d, bx;
+    if (slot_of(slots, d, bx)) lanczos_stencil_body<T, const LanczosParams&>(tab[d], bx);
+}
+
 // s = 1: every output has the same weights.  A block stages the input tile of a
 // 4 x 8 x 64 output tile (with its halo) in LDS, and each thread computes the eight
 // outputs (i1, i2 = 0..7, i3) of its column: every staged row feeds the outputs of
 // all the i2 it reaches, so an output costs about T (T + 7) / 8 LDS reads instead
 // of T^3 loads.
 constexpr int kSt1 = 4, kSt2 = 8, kSt3 = 64;
-template <int T>
-__global__ __launch_bounds__(256) void k_lanczos_stencil_tile(LanczosParams P)
+template <int T, class PT>
+__device__ __forceinline__ void lanczos_stencil_tile_body(PT P, const int bx)
 {
     constexpr int A = kSt1 + T - 1, B = kSt2 + T - 1, C = kSt3 + T - 1;
     constexpr int CP = C + 1;                                  // LDS row pitch
     __shared__ float tile[A * B * CP];
     const int nb3 = (P.o[2] + kSt3 - 1) / kSt3, nb2 = (P.o[1] + kSt2 - 1) / kSt2;
-    int b = blockIdx.x;
+    int b = bx;
     const int bx3 = b % nb3; b /= nb3;
     const int bx2 = b % nb2;
     const int bx1 = b / nb2;
@@ -455,28 +487,35 @@ __global__ __launch_bounds__(256) void k_lanczos_stencil_tile(LanczosParams P)
     }
 }
 
+template <int T>
+__global__ __launch_bounds__(256) void k_lanczos_stencil_tile(LanczosParams P) { lanczos_stencil_tile_body<T, LanczosParams>(P, blockIdx.x); }
+template <int T>
+__global__ __launch_bounds__(256) void k_lanczos_stencil_tile_merged(const LanczosParams* __restrict__ tab, const Slot* __restrict__ slots)
+{
+    int d, bx;
+    if (slot_of(slots, d, bx)) lanczos_stencil_tile_body<T, const LanczosParams&>(tab[d], bx);
+}
+
 hipError_t launch_lanczos_stencil(const LanczosParams& p, hipStream_t st)
 {
     if (p.s == 1) {
-        const dim3 grid((unsigned)(((p.o[0] + kSt1 - 1) / kSt1) * ((p.o[1] + kSt2 - 1) / kSt2) *
-                                   ((p.o[2] + kSt3 - 1) / kSt3)));
+        const unsigned grid = (unsigned)(((p.o[0] + kSt1 - 1) / kSt1) * ((p.o[1] + kSt2 - 1) / kSt2) *
+                                         ((p.o[2] + kSt3 - 1) / kSt3));
         switch (2 * p.m) {
-            case 4: hipLaunchKernelGGL(k_lanczos_stencil_tile<4>, grid, dim3(256), 0, st, p); break;
-            case 6: hipLaunchKernelGGL(k_lanczos_stencil_tile<6>, grid, dim3(256), 0, st, p); break;
-            case 8: hipLaunchKernelGGL(k_lanczos_stencil_tile<8>, grid, dim3(256), 0, st, p); break;
+            case 4: return dispatch(k_lanczos_stencil_tile<4>, k_lanczos_stencil_tile_merged<4>, grid, 256, 0, st, p);
+            case 6: return dispatch(k_lanczos_stencil_tile<6>, k_lanczos_stencil_tile_merged<6>, grid, 256, 0, st, p);
+            case 8: return dispatch(k_lanczos_stencil_tile<8>, k_lanczos_stencil_tile_merged<8>, grid, 256, 0, st, p);
             default: return hipErrorInvalidValue;
         }
-        return hipGetLastError();
     }
     const int64_t total = (int64_t)p.o[0] * p.o[1] * p.o[2];
-    const dim3 grid((unsigned)((total + 255) / 256));
+    const unsigned grid = (unsigned)((total + 255) / 256);
     switch (2 * p.m) {
-        case 4: hipLaunchKernelGGL(k_lanczos_stencil<4>, grid, dim3(256), 0, st, p); break;
-        case 6: hipLaunchKernelGGL(k_lanczos_stencil<6>, grid, dim3(256), 0, st, p); break;
-        case 8: hipLaunchKernelGGL(k_lanczos_stencil<8>, grid, dim3(256), 0, st, p); break;
+        case 4: return dispatch(k_lanczos_stencil<4>, k_lanczos_stencil_merged<4>, grid, 256, 0, st, p);
+        case 6: return dispatch(k_lanczos_stencil<6>, k_lanczos_stencil_merged<6>, grid, 256, 0, st, p);
+        case 8: return dispatch(k_lanczos_stencil<8>, k_lanczos_stencil_merged<8>, grid, 256, 0, st, p);
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 }  // namespace dsx

@@ -112,9 +112,9 @@ struct BlockWork {
     bool mirror;
 };
 
-__device__ __forceinline__ bool decode_block(const RecombParams& P, BlockWork& w)
+__device__ __forceinline__ bool decode_block(const RecombParams& P, BlockWork& w, const int bx)
 {
-    const int4 it = P.work[blockIdx.x];
+    const int4 it = P.work[bx];
     if (it.x < 0) return false;
     w.k1 = it.x;
     w.k2 = it.y;
@@ -243,13 +243,13 @@ __device__ __forceinline__ float parity_eval(const float2 (&S)[N + 1], float t3)
 // PAR: every r_mu3 is a multiple of 1/2, so e^{2 pi i H3 r_c3} = +-1 by the parity
 // of H3: level B folds the classes into two coefficient sets, one for even and one
 // for odd H3, and level C evaluates a single polynomial per voxel.
-template <int N, int HC, bool MULTI, bool PAR>
-__global__ __launch_bounds__(512, 4) void k_recombine_nuclear(RecombParams P)
+template <int N, int HC, bool MULTI, bool PAR, class PT>
+__device__ __forceinline__ void recombine_nuclear_body(PT P, const int bx)
 {
     extern __shared__ float2 smem[];
     constexpr int QR = n_pairs(N);
     BlockWork w;
-    if (!decode_block(P, w)) return;
+    if (!decode_block(P, w, bx)) return;
     float2* Bs = smem;                                  // [sites of the chunk][n3][QR]
     float2* Xs = smem + P.bs_elems;                     // [F][nh] staging
     float2* tHs = Xs + P.xs_elems;                      // [nclass][nH3span]
@@ -477,6 +477,15 @@ __global__ __launch_bounds__(512, 4) void k_recombine_nuclear(RecombParams P)
     else write_row<HC, false>(ro, full, active, hmin, hcnt, P.scale, val);
 }
 
+template <int N, int HC, bool MULTI, bool PAR>
+__global__ __launch_bounds__(512, 4) void k_recombine_nuclear(RecombParams P) { recombine_nuclear_body<N, HC, MULTI, PAR, RecombParams>(P, blockIdx.x); }
+template <int N, int HC, bool MULTI, bool PAR>
+__global__ __launch_bounds__(512, 4) void k_recombine_nuclear_merged(const RecombParams* __restrict__ tab, const Slot* __restrict__ slots)
+{
+    int d, bx;
+    if (slot_of(slots, d, bx)) recombine_nuclear_body<N, HC, MULTI, PAR, const RecombParams&>(tab[d], bx);
+}
+
 // Folded form (every r_mu2 a multiple of 1/2; see the top of the file).  A block
 // takes two planes G1 and G1 + n1 of one spectra column (the second may be absent)
 // and one slice of n3s k3 values: level A reads every spectrum of the slice once for
@@ -493,13 +502,12 @@ __global__ __launch_bounds__(512, 4) void k_recombine_nuclear(RecombParams P)
 // One configuration in the parity form: at most 80 VGPRs, so that three 512-thread sliced
 // blocks share a CU (their LDS fits too); the multi-configuration form keeps its |F|^2
 // accumulators and the class form its per-H3 structure factors in registers.
-template <int N, int HC, bool MULTI, bool PAR>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu((!MULTI && PAR) ? 6 : 4)))
-void k_recombine_folded(RecombParams P)
+template <int N, int HC, bool MULTI, bool PAR, class PT>
+__device__ __forceinline__ void recombine_folded_body(PT P, const int bx)
 {
     extern __shared__ float2 smem[];
     constexpr int QR = n_pairs(N);
-    const int4 wi = P.work[blockIdx.x];
+    const int4 wi = P.work[bx];
     if (wi.x < 0) return;
     const bool hasb = (wi.w >> 25) & 1;
     const int n3s = P.n3s;
@@ -797,6 +805,17 @@ void k_recombine_folded(RecombParams P)
     else write_row<HC, false>(ro, full, active, hmin, hcnt, 1.f, val);
 }
 
+template <int N, int HC, bool MULTI, bool PAR>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu((!MULTI && PAR) ? 6 : 4)))
+void k_recombine_folded(RecombParams P) { recombine_folded_body<N, HC, MULTI, PAR, RecombParams>(P, blockIdx.x); }
+template <int N, int HC, bool MULTI, bool PAR>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu((!MULTI && PAR) ? 6 : 4)))
+void k_recombine_folded_merged(const RecombParams* __restrict__ tab, const Slot* __restrict__ slots)
+{
+    int d, bx;
+    if (slot_of(slots, d, bx)) recombine_folded_body<N, HC, MULTI, PAR, const RecombParams&>(tab[d], bx);
+}
+
 // ---------------------------------------------------------------------------- magnetic
 // the form factor f_mag of Eq. mag_sf
 __device__ __forceinline__ float mag_ff(const float* f, float s2) { return site_ff(f, s2); }
@@ -865,12 +884,12 @@ __device__ __forceinline__ float2 dw_level_c(const float2 (&B)[kMaxOrder + 1], i
 
 // DW: the sites carry Debye-Waller factors T_mu(G) (Eq. dw); each site is then taken
 // on its own at level C instead of summed into its class first.
-template <int HC, bool DW>
-__global__ __launch_bounds__(512) void k_recombine_magnetic(RecombParams P)
+template <int HC, bool DW, class PT>
+__device__ __forceinline__ void recombine_magnetic_body(PT P, const int bx)
 {
     extern __shared__ float2 smem[];
     BlockWork w;
-    if (!decode_block(P, w)) return;
+    if (!decode_block(P, w, bx)) return;
     float2* Bs = smem;                    // [sites of the chunk][3][n3]
     float2* Xs = smem + P.bs_elems;       // [2][sites of the chunk][3][nh] staging
     float2* tHs = Xs + P.xs_elems;        // [nclass][nH3span]
@@ -1036,6 +1055,15 @@ __global__ __launch_bounds__(512) void k_recombine_magnetic(RecombParams P)
     }
 }
 
+template <int HC, bool DW>
+__global__ __launch_bounds__(512) void k_recombine_magnetic(RecombParams P) { recombine_magnetic_body<HC, DW, RecombParams>(P, blockIdx.x); }
+template <int HC, bool DW>
+__global__ __launch_bounds__(512) void k_recombine_magnetic_merged(const RecombParams* __restrict__ tab, const Slot* __restrict__ slots)
+{
+    int d, bx;
+    if (slot_of(slots, d, bx)) recombine_magnetic_body<HC, DW, const RecombParams&>(tab[d], bx);
+}
+
 int recombine_max_threads(int hc, int magnetic)
 {
     (void)hc; (void)magnetic;
@@ -1077,14 +1105,14 @@ __device__ __forceinline__ void cmac(float2& acc, float2 a, float2 b) {
     acc.y = fmaf(a.y, b.x, acc.y);
 }
 
-template <bool MULTI>
-__global__ __launch_bounds__(kMagRowsMaxThreads) void k_recombine_magnetic_rows(RecombParams P)
+template <bool MULTI, class PT>
+__device__ __forceinline__ void recombine_magnetic_rows_body(PT P, const int bx)
 {
     extern __shared__ float2 smem[];
     __shared__ int cls[kMaxSites + 1];
     __shared__ float2 t1s[kMaxSites];
     BlockWork w;
-    if (!decode_block(P, w)) return;
+    if (!decode_block(P, w, bx)) return;
     const int n1 = P.n1, n2 = P.n2, n3 = P.n3, nh = P.nh, S = P.S, NC = P.nclass, q = P.qmod;
     const int rows = w.h2b - w.h2a, cnt3 = P.cnt[2];
     float2* D = smem;                              // [rows][NC][3][n3]; then E [rows][q][3][n3]
@@ -1269,6 +1297,15 @@ __global__ __launch_bounds__(kMagRowsMaxThreads) void k_recombine_magnetic_rows(
     }
 }
 
+template <bool MULTI>
+__global__ __launch_bounds__(kMagRowsMaxThreads) void k_recombine_magnetic_rows(RecombParams P) { recombine_magnetic_rows_body<MULTI, RecombParams>(P, blockIdx.x); }
+template <bool MULTI>
+__global__ __launch_bounds__(kMagRowsMaxThreads) void k_recombine_magnetic_rows_merged(const RecombParams* __restrict__ tab, const Slot* __restrict__ slots)
+{
+    int d, bx;
+    if (slot_of(slots, d, bx)) recombine_magnetic_rows_body<MULTI, const RecombParams&>(tab[d], bx);
+}
+
 hipError_t launch_recombine_magnetic_rows(const RecombParams& p, int block, size_t lds, hipStream_t st)
 {
     if (p.nwork <= 0) return hipSuccess;
@@ -1276,13 +1313,11 @@ hipError_t launch_recombine_magnetic_rows(const RecombParams& p, int block, size
     if (p.M > 1) {
         hipError_t e = set_lds(k_recombine_magnetic_rows<true>, lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_recombine_magnetic_rows<true>), dim3(p.nwork), dim3(block), lds, st, p);
-    } else {
-        hipError_t e = set_lds(k_recombine_magnetic_rows<false>, lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_recombine_magnetic_rows<false>), dim3(p.nwork), dim3(block), lds, st, p);
+        return dispatch(k_recombine_magnetic_rows<true>, k_recombine_magnetic_rows_merged<true>, p.nwork, block, lds, st, p);
     }
-    return hipGetLastError();
+    hipError_t e = set_lds(k_recombine_magnetic_rows<false>, lds);
+    if (e != hipSuccess) return e;
+    return dispatch(k_recombine_magnetic_rows<false>, k_recombine_magnetic_rows_merged<false>, p.nwork, block, lds, st, p);
 }
 
 template <int N, int HC, bool MULTI, bool PAR>
@@ -1290,8 +1325,8 @@ static hipError_t launch_nuc_v(const RecombParams& p, int block, size_t lds, hip
 {
     hipError_t e = set_lds(k_recombine_nuclear<N, HC, MULTI, PAR>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_recombine_nuclear<N, HC, MULTI, PAR>), dim3(p.nwork), dim3(block), lds, st, p);
-    return hipGetLastError();
+    return dispatch(k_recombine_nuclear<N, HC, MULTI, PAR>, k_recombine_nuclear_merged<N, HC, MULTI, PAR>, p.nwork,
+                    block, lds, st, p);
 }
 
 template <int N, int HC, bool MULTI, bool PAR>
@@ -1299,8 +1334,8 @@ static hipError_t launch_fold_v(const RecombParams& p, int block, size_t lds, hi
 {
     hipError_t e = set_lds(k_recombine_folded<N, HC, MULTI, PAR>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_recombine_folded<N, HC, MULTI, PAR>), dim3(p.nwork), dim3(block), lds, st, p);
-    return hipGetLastError();
+    return dispatch(k_recombine_folded<N, HC, MULTI, PAR>, k_recombine_folded_merged<N, HC, MULTI, PAR>, p.nwork,
+                    block, lds, st, p);
 }
 
 template <int N, int HC>
@@ -1378,8 +1413,7 @@ static hipError_t launch_mag_v(const RecombParams& p, int block, size_t lds, hip
 {
     hipError_t e = set_lds(k_recombine_magnetic<HC, DW>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_recombine_magnetic<HC, DW>), dim3(p.nwork), dim3(block), lds, st, p);
-    return hipGetLastError();
+    return dispatch(k_recombine_magnetic<HC, DW>, k_recombine_magnetic_merged<HC, DW>, p.nwork, block, lds, st, p);
 }
 
 template <int HC>
@@ -1408,15 +1442,15 @@ hipError_t launch_recombine_magnetic(const RecombParams& p, int hc, int block, s
 // (2 pi i)^{p+q+r} H1^p H2^q H3^r / (p! q! r!) times the site factor, so the whole sum
 // over sites and monomials is one wave reduction (fixed order) per configuration.
 // Lane 0 keeps the ensemble moments and writes I(H); all of it in float64.
-template <int N>
-__global__ __launch_bounds__(64) void k_bragg_nuclear(BraggParams P)
+template <int N, class PT>
+__device__ __forceinline__ void bragg_nuclear_body(PT P, const int bx)
 {
     constexpr int T = n_monomials(N);
     __shared__ double Ar[3][N + 1], Ai[3][N + 1];
     __shared__ double Wr[kMaxSites], Wi[kMaxSites];
     __shared__ int mono_s[T];
     const int total = P.nH[0] * P.nH[1] * P.nH[2];
-    const int idx = blockIdx.x;
+    const int idx = bx;
     if (idx >= total) return;
     const int lane = threadIdx.x;
     const int j3 = idx % P.nH[2], j2 = (idx / P.nH[2]) % P.nH[1], j1 = idx / (P.nH[2] * P.nH[1]);
@@ -1489,6 +1523,15 @@ __global__ __launch_bounds__(64) void k_bragg_nuclear(BraggParams P)
     }
 }
 
+template <int N>
+__global__ __launch_bounds__(64) void k_bragg_nuclear(BraggParams P) { bragg_nuclear_body<N, BraggParams>(P, blockIdx.x); }
+template <int N>
+__global__ __launch_bounds__(64) void k_bragg_nuclear_merged(const BraggParams* __restrict__ tab, const Slot* __restrict__ slots)
+{
+    int d, bx;
+    if (slot_of(slots, d, bx)) bragg_nuclear_body<N, const BraggParams&>(tab[d], bx);
+}
+
 __device__ double mag_ff_d(const double* f, double s2) {
     return f[0] * exp(-f[1] * s2) + f[2] * exp(-f[3] * s2) + f[4] * exp(-f[5] * s2) + f[6];
 }
@@ -1517,11 +1560,12 @@ __device__ void dw_at_h(const BraggParams& P, const int H[3], int mu, double& tr
 // vector F = sum_mu factor S_mu (S the float64 lattice sums of the spins) is one wave
 // reduction (fixed order); lane 0 projects F perpendicular to Q and keeps the ensemble
 // moments.  All in float64.
-__global__ __launch_bounds__(256) void k_bragg_magnetic(BraggParams P)
+template <class PT>
+__device__ __forceinline__ void bragg_magnetic_body(PT P, const int bx)
 {
     __shared__ double Wr[4][kMaxSites], Wi[4][kMaxSites];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int idx = blockIdx.x * 4 + wave;
+    const int idx = bx * 4 + wave;
     const int total = P.nH[0] * P.nH[1] * P.nH[2];
     if (idx >= total) return;              // whole waves leave together; no block barrier follows
     const int j3 = idx % P.nH[2], j2 = (idx / P.nH[2]) % P.nH[1], j1 = idx / (P.nH[2] * P.nH[1]);
@@ -1593,12 +1637,18 @@ __global__ __launch_bounds__(256) void k_bragg_magnetic(BraggParams P)
     }
 }
 
+__global__ __launch_bounds__(256) void k_bragg_magnetic(BraggParams P) { bragg_magnetic_body<BraggParams>(P, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_bragg_magnetic_merged(const BraggParams* __restrict__ tab, const Slot* __restrict__ slots)
+{
+    int d, bx;
+    if (slot_of(slots, d, bx)) bragg_magnetic_body<const BraggParams&>(tab[d], bx);
+}
+
 template <int N>
 static hipError_t launch_bragg_t(const BraggParams& p, int grid, hipStream_t st)
 {
     (void)grid;
-    hipLaunchKernelGGL(k_bragg_nuclear<N>, dim3(p.nH[0] * p.nH[1] * p.nH[2]), dim3(64), 0, st, p);
-    return hipGetLastError();
+    return dispatch(k_bragg_nuclear<N>, k_bragg_nuclear_merged<N>, p.nH[0] * p.nH[1] * p.nH[2], 64, 0, st, p);
 }
 
 hipError_t launch_bragg(const BraggParams& p, int order, hipStream_t st)
@@ -1607,8 +1657,7 @@ hipError_t launch_bragg(const BraggParams& p, int order, hipStream_t st)
     if (total <= 0) return hipSuccess;
     const int grid = (total + 255) / 256;
     if (p.kind == 1) {
-        hipLaunchKernelGGL(k_bragg_magnetic, dim3((total + 3) / 4), dim3(256), 0, st, p);
-        return hipGetLastError();
+        return dispatch(k_bragg_magnetic, k_bragg_magnetic_merged, (total + 3) / 4, 256, 0, st, p);
     }
     switch (order) {
         case 0: return launch_bragg_t<0>(p, grid, st);
@@ -1634,25 +1683,31 @@ hipError_t launch_bragg(const BraggParams& p, int order, hipStream_t st)
 
 // Debye-Waller means of Eq. dw: one thread per (site, monomial), configurations summed
 // in order.
-__global__ __launch_bounds__(256) void k_dw_mean(const double* sums, double* dwc, int M, int S, int T)
+template <class PT>
+__device__ __forceinline__ void dw_mean_body(PT P, const int bx)
 {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= S * T) return;
-    const int mu = idx / T, t = idx - mu * T;
+    const int idx = bx * blockDim.x + threadIdx.x;
+    if (idx >= P.S * P.T) return;
+    const int mu = idx / P.T, t = idx - mu * P.T;
     double num = 0.0, den = 0.0;
-    for (int m = 0; m < M; ++m) {
-        const double* sm = sums + ((size_t)m * S + mu) * T;
+    for (int m = 0; m < P.M; ++m) {
+        const double* sm = P.sums + ((size_t)m * P.S + mu) * P.T;
         num += sm[t];
         den += sm[0];
     }
-    dwc[idx] = den != 0.0 ? num / den : 0.0;
+    P.dwc[idx] = den != 0.0 ? num / den : 0.0;
 }
 
-hipError_t launch_dw_mean(const double* sums, double* dwc, int M, int S, int T, hipStream_t st)
+__global__ __launch_bounds__(256) void k_dw_mean(DwParams P) { dw_mean_body<DwParams>(P, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_dw_mean_merged(const DwParams* __restrict__ tab, const Slot* __restrict__ slots)
 {
-    const int tot = S * T;
-    hipLaunchKernelGGL(k_dw_mean, dim3((tot + 255) / 256), dim3(256), 0, st, sums, dwc, M, S, T);
-    return hipGetLastError();
+    int d, bx;
+    if (slot_of(slots, d, bx)) dw_mean_body<const DwParams&>(tab[d], bx);
+}
+
+hipError_t launch_dw_mean(const DwParams& p, hipStream_t st)
+{
+    return dispatch(k_dw_mean, k_dw_mean_merged, (p.S * p.T + 255) / 256, 256, 0, st, p);
 }
 
 }  // namespace dsx

@@ -11,7 +11,7 @@ hipError_t launch_recombine_nuclear(const RecombParams&, int, int, int, size_t, 
 hipError_t launch_recombine_magnetic(const RecombParams&, int, int, size_t, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_recombine_magnetic_rows(const RecombParams&, int, size_t, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_bragg(const BraggParams&, int, hipStream_t) { return hipErrorNotSupported; }
-hipError_t launch_dw_mean(const double*, double*, int, int, int, hipStream_t) { return hipErrorNotSupported; }
+hipError_t launch_dw_mean(const DwParams&, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_lanczos(const LanczosParams&, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_lanczos_points(const PointsParams&, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_lanczos_stencil(const LanczosParams&, hipStream_t) { return hipErrorNotSupported; }

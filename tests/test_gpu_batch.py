@@ -30,15 +30,32 @@ def small_ensemble():
     return ms
 
 
+MODES = {"auto": 0, "per_model": 1, "merged": 2}
+
+
+@pytest.mark.parametrize("mode", sorted(MODES))
 @pytest.mark.parametrize("lm", [0, 2])
-def test_batch_equals_individual_and_oracle(lm):
+def test_batch_equals_individual_and_oracle(lm, mode):
     import torch
     import paper_1809_07088_amd as dsx
     models = small_ensemble()
-    say(f"batch of {len(models)} models, lanczos_m={lm}")
+    say(f"batch of {len(models)} models, lanczos_m={lm}, mode {mode}")
     hs = [to_dsx(m) for m in models]
     outs = [torch.full(tuple(m.count), -1.0, device="cuda") for m in models]
-    batch = dsx.Batch(hs, outs, lanczos_m=lm)
+    batch = dsx.Batch(hs, outs, lanczos_m=lm, mode=MODES[mode])
+    info = batch.info()
+    print("batch info", info)
+    if mode == "merged":
+        # uneven n, orders and kinds: the lattice-sum reduction and the generic-length FFTs
+        # are shared, so the graph has fewer dispatches than the models have launches
+        assert info["mode"] == dsx.BATCH_MERGED and info["merged_nodes"] >= 2
+        assert info["dispatches"] < info["launches"]
+    elif mode == "per_model":
+        assert info["mode"] == dsx.BATCH_PER_MODEL and info["merged_nodes"] == 0
+        assert info["dispatches"] == info["launches"]
+    else:
+        assert info["merged_ms"] > 0 and info["per_model_ms"] > 0
+        assert info["mode"] == (dsx.BATCH_MERGED if info["merged_ms"] <= info["per_model_ms"] else dsx.BATCH_PER_MODEL)
     batch.run()
     torch.cuda.synchronize()
     got = [o.cpu().numpy() for o in outs]
@@ -70,6 +87,70 @@ def test_batch_equals_individual_and_oracle(lm):
     assert e.value.status == dsx.ERR_BUSY
     batch.close()
     h0.set_grid(m0.g0, m0.count)
+    for h in hs:
+        h.close()
+
+
+def test_merged_batch_of_many_small_models():
+    """64 compositional models of one shape and 16 of another: one dispatch per step for
+    each shape; every output equals the model computed alone, bit for bit, and the oracle."""
+    import torch
+    import paper_1809_07088_amd as dsx
+    models = [synth.compositional(workload=46, model=i, n=6 if i < 64 else 5, M=1, hmax=1)
+              for i in range(80)]
+    say("merged batch of 80 small models (two shapes)")
+    hs = [to_dsx(m) for m in models]
+    for h in hs:
+        h.tune_set(0, 0, 12)
+    outs = [torch.full(tuple(m.count), -1.0, device="cuda") for m in models]
+    batch = dsx.Batch(hs, outs, mode=dsx.BATCH_MERGED)
+    info = batch.info()
+    print("batch info", info)
+    # about six launches a model (sums, their reduction, two FFT passes, recombination,
+    # Bragg points); the two shapes share a node wherever they run the same kernel with
+    # the same block size, so a step has at most two nodes
+    assert info["launches"] >= 5 * len(models)
+    assert info["dispatches"] <= 16 and info["merged_nodes"] >= 5
+    batch.run()
+    torch.cuda.synchronize()
+    for k in (0, 1, 37, 63, 64, 79):
+        alone = torch.empty(tuple(models[k].count), device="cuda")
+        hs[k].compute_intensity(alone)
+        torch.cuda.synchronize()
+        assert torch.equal(alone, outs[k]), k
+        assert_parity(outs[k].cpu().numpy(), O.intensity(models[k]).reshape(models[k].count))
+    # a second replay after new sites on some models
+    for k in (3, 70):
+        new = synth.compositional(workload=47, model=k, n=models[k].n[0], M=1, hmax=1)
+        hs[k].set_sites(0, torch.from_numpy(new.occ[0]).cuda())
+        models[k] = new
+    batch.run()
+    torch.cuda.synchronize()
+    for k in (3, 70):
+        assert_parity(outs[k].cpu().numpy(), O.intensity(models[k]).reshape(models[k].count))
+    batch.close()
+    for h in hs:
+        h.close()
+
+
+def test_merged_and_per_model_batches_agree_bitwise():
+    import torch
+    import paper_1809_07088_amd as dsx
+    models = small_ensemble()
+    say("merged vs per-model batch, bitwise")
+    hs = [to_dsx(m) for m in models]
+    res = {}
+    for mode in (dsx.BATCH_PER_MODEL, dsx.BATCH_MERGED):
+        outs = [torch.full(tuple(m.count), -1.0, device="cuda") for m in models]
+        b = dsx.Batch(hs, outs, lanczos_m=2, mode=mode)
+        for _ in range(3):      # replays with the program's own work between them
+            b.run()
+            torch.cuda.synchronize()
+            res.setdefault(mode, []).append([o.clone() for o in outs])
+        b.close()
+    for r in res[dsx.BATCH_PER_MODEL] + res[dsx.BATCH_MERGED]:
+        for a, b in zip(res[dsx.BATCH_PER_MODEL][0], r):
+            assert torch.equal(a, b)
     for h in hs:
         h.close()
 
