@@ -488,6 +488,8 @@ def bench_ensemble(dsx, torch, dev, steps, warmup, lm=2, probe=False, batched_on
         sites.append(st)
         outs.append(torch.empty(tuple(m.count), dtype=torch.float32, device=dev))
     voxels = sum(int(np.prod(m.count)) * m.n_configs for m in models)
+    for h in hs:              # the plain path and the batch run the same tuned plans
+        h.autotune(lm)
 
     def upload():
         for h, st in zip(hs, sites):

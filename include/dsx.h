@@ -340,6 +340,23 @@ dsx_status dsx_autotune(dsx_model m, int32_t lanczos_m, void* hip_stream);
 dsx_status dsx_tune_query(dsx_model m, int32_t choice[3], int32_t* tuned);
 
 /*
+ * FFT knobs of a model (Sec. IV: the supercell FFTs): the radix sequence of each axis's
+ * Stockham passes and the number of columns per block of the axis-1 transform in LDS.
+ * The autotuner times every order of every grouping of the edge's factor 2^a into 4s
+ * and 2s with its odd factors (at most 12 sequences per axis, the default first) on the
+ * axes the LDS kernels transform -- edges 8, 16 and 32 take register kernels of a
+ * fixed order -- and the tiles 16, 32 and 64; the choices join the tune cache line.
+ *   radices   [3][16] int32, per axis the radices in pass order, 0-terminated; each
+ *             2, 4 or odd (>= 3), product the edge n of the axis; NULL keeps the plans
+ *   col_tile  0 (by edge: 64 up to n1 = 64, else 32), 16, 32 or 64
+ * dsx_tune_set_fft marks the model tuned and its spectra stale.  DSX_ERR_ARG for an
+ * invalid sequence or a tile whose LDS (8 n1 (1 + 2 tile) bytes) exceeds 160 KiB.
+ * dsx_tune_query_fft writes the current sequences (0-padded) and tile.
+ */
+dsx_status dsx_tune_set_fft(dsx_model m, const int32_t* radices, int32_t col_tile);
+dsx_status dsx_tune_query_fft(dsx_model m, int32_t* radices, int32_t* col_tile);
+
+/*
  * Set the plan choices (same meaning as dsx_tune_query; the filter planes per block
  * in 1..64, forms 2-4 on nuclear models only) without timing anything, e.g. to
  * re-run a plan that dsx_autotune chose in another process.  The model then counts

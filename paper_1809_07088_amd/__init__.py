@@ -53,7 +53,7 @@ EXPORTS = ("dsx_plan_query", "dsx_create_model", "dsx_set_sites", "dsx_set_sites
            "dsx_version", "dsx_profile_enable", "dsx_profile_select", "dsx_profile_read", "dsx_profile_reset",
            "dsx_noise_filter_cutoff", "dsx_filter_points", "dsx_split_sites", "dsx_noise_filter_spherical",
            "dsx_batch_create", "dsx_batch_create_mode", "dsx_batch_query", "dsx_batch_run", "dsx_batch_destroy",
-           "dsx_autotune", "dsx_tune_query",
+           "dsx_autotune", "dsx_tune_query", "dsx_tune_set_fft", "dsx_tune_query_fft",
            "dsx_tune_set", "dsx_server_create", "dsx_server_add_model", "dsx_server_submit", "dsx_server_wait",
            "dsx_server_stats_read", "dsx_server_destroy")
 
@@ -136,6 +136,10 @@ def lib():
         L.dsx_autotune.argtypes = [P, i32, P]
         L.dsx_tune_query.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.dsx_tune_set.argtypes = [P, ctypes.POINTER(i32)]
+        L.dsx_tune_set_fft.argtypes = [P, P, i32]
+        L.dsx_tune_set_fft.restype = i32
+        L.dsx_tune_query_fft.argtypes = [P, P, ctypes.POINTER(i32)]
+        L.dsx_tune_query_fft.restype = i32
         L.dsx_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(P)]
         L.dsx_server_add_model.argtypes = [P, ctypes.POINTER(ModelDesc), ctypes.POINTER(P)]
         L.dsx_server_submit.argtypes = [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_int64)]
@@ -386,6 +390,29 @@ def tune_query(model):
             "filter_planes_per_block": int(c[2]), "tuned": bool(t.value)}
 
 
+def tune_query_fft(model):
+    """The FFT knobs of a model (dsx_tune_query_fft): per axis the radix sequence of its
+    passes, and the axis-1 column tile (0 = by edge)."""
+    r = (ctypes.c_int32 * 48)()
+    t = ctypes.c_int32(0)
+    _check(lib().dsx_tune_query_fft(model, r, ctypes.byref(t)))
+    return {"radices": [[int(x) for x in r[16 * a:16 * a + 16] if x] for a in range(3)],
+            "col_tile": int(t.value)}
+
+
+def tune_set_fft(model, radices=None, col_tile=0):
+    """Set the FFT knobs without timing (dsx_tune_set_fft): radices is None or three
+    sequences (each product = the axis's edge)."""
+    arr = None
+    if radices is not None:
+        if len(radices) != 3 or any(len(r) > 16 for r in radices):
+            raise ValueError("three radix sequences of at most 16 radices")
+        arr = (ctypes.c_int32 * 48)()
+        for a, rs in enumerate(radices):
+            for i, v in enumerate(rs):
+                arr[16 * a + i] = int(v)
+    _check(lib().dsx_tune_set_fft(model, arr, int(col_tile)))
+
 
 def tune_set(model, recombine_form, fft_fields_per_block, filter_planes_per_block):
     """Set the plan choices without timing (dsx_tune_set); the model counts as tuned."""
@@ -491,6 +518,12 @@ class Model:
 
     def tune_set(self, recombine_form, fft_fields_per_block, filter_planes_per_block):
         tune_set(self.handle, recombine_form, fft_fields_per_block, filter_planes_per_block)
+
+    def tune_query_fft(self):
+        return tune_query_fft(self.handle)
+
+    def tune_set_fft(self, radices=None, col_tile=0):
+        tune_set_fft(self.handle, radices, col_tile)
 
     def close(self):
         if self.handle:

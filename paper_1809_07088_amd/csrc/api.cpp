@@ -159,6 +159,74 @@ AxisPlan make_plan(int n)
     return p;
 }
 
+// Is `p` a valid radix sequence for its length: radices 2, 4 or odd (>= 3), product n.
+bool plan_valid(const AxisPlan& p)
+{
+    if (p.n < 1 || p.nrad < 0 || p.nrad > kMaxRadices) return false;
+    long prod = 1;
+    for (int i = 0; i < p.nrad; ++i) {
+        const int r = p.rad[i];
+        if (!(r == 2 || r == 4 || (r >= 3 && (r & 1)))) return false;
+        prod *= r;
+        if (prod > p.n) return false;
+    }
+    return prod == p.n;
+}
+
+// Radix sequences of length n for the autotuner: the default first, then every order of
+// every grouping of the factor 2^a into 4s and 2s with the odd primes, at most `cap`.
+std::vector<AxisPlan> plan_candidates(int n, int cap)
+{
+    std::vector<AxisPlan> out{make_plan(n)};
+    std::vector<int> odd;
+    int r = n, twos = 0;
+    while (r % 2 == 0) { ++twos; r /= 2; }
+    for (int f = 3; f <= r; f += 2)
+        while (r % f == 0) { odd.push_back(f); r /= f; }
+    for (int fours = twos / 2; fours >= 0 && (int)out.size() < cap; --fours) {
+        std::vector<int> rs(odd);
+        rs.insert(rs.end(), fours, 4);
+        rs.insert(rs.end(), twos - 2 * fours, 2);
+        if ((int)rs.size() > kMaxRadices) continue;
+        std::sort(rs.begin(), rs.end());
+        do {
+            AxisPlan p{};
+            p.n = n;
+            p.nrad = (int)rs.size();
+            for (size_t i = 0; i < rs.size(); ++i) p.rad[i] = rs[i];
+            bool dup = false;
+            for (const AxisPlan& q : out)
+                dup = dup || (q.nrad == p.nrad && std::equal(q.rad, q.rad + q.nrad, p.rad));
+            if (!dup) out.push_back(p);
+        } while ((int)out.size() < cap && std::next_permutation(rs.begin(), rs.end()));
+    }
+    return out;
+}
+
+std::string plan_string(const AxisPlan& p)
+{
+    std::string s;
+    for (int i = 0; i < p.nrad; ++i) s += (i ? "x" : "") + std::to_string(p.rad[i]);
+    return s.empty() ? "1" : s;
+}
+
+bool parse_plan(const std::string& s, int n, AxisPlan* out)
+{
+    AxisPlan p{};
+    p.n = n;
+    std::istringstream in(s);
+    std::string tok;
+    while (std::getline(in, tok, 'x')) {
+        if (tok.empty() || p.nrad >= kMaxRadices) return false;
+        const int v = std::atoi(tok.c_str());
+        if (v == 1 && s == "1") break;
+        p.rad[p.nrad++] = v;
+    }
+    if (!plan_valid(p)) return false;
+    *out = p;
+    return true;
+}
+
 // Rows a*, b*, c* of the reciprocal basis (a* = 2 pi b x c / V), a along x and b in
 // the xy plane.  Returns false for an invalid cell.
 bool reciprocal_basis(const double cell[6], double out[9])
@@ -277,6 +345,7 @@ struct dsx_model_s {
     int tune_recomb_variant = 0;   // 0 default form, 2 class form, 3 unfolded, 4 unsliced
     int tune_fchunk = 0;           // fields per FFT plane block (0 = heuristic)
     int tune_lanczos_t1 = 12;      // planes per filter block
+    int tune_tc = 0;               // columns per block of the LDS axis-1 FFT (0 = heuristic)
     bool tuned = false;
     // state
     std::vector<char> set;
@@ -897,7 +966,7 @@ dsx_status ensure_spectra(dsx_model m, hipStream_t st, bool force = false)
     Axis1Params ap{};
     ap.X = m->d_X; ap.tw1 = m->d_tw[0]; ap.p1 = m->plan[0];
     ap.n1 = m->n[0]; ap.n2 = m->n[1]; ap.cols = m->SF * m->nh; ap.M = m->M;
-    ap.tc = m->n[0] <= 64 ? 64 : 32;
+    ap.tc = m->tune_tc > 0 ? m->tune_tc : (m->n[0] <= 64 ? 64 : 32);
     ap.ncolblk = (ap.cols + ap.tc - 1) / ap.tc;
     HIPCHK(m, timed("fft_axis1", st, [&] { return launch_fft_axis1(ap, st); }));
     m->dirty = false;
@@ -1818,7 +1887,12 @@ std::string tune_key(dsx_model m, int lm)
 
 std::mutex g_tune_mu;
 
-bool tune_lookup(const std::string& key, int* v, int* fc, int* t1)
+struct FftChoice {
+    int tc = 0;
+    std::string plan[3];   // empty: default
+};
+
+bool tune_lookup(const std::string& key, int* v, int* fc, int* t1, FftChoice* fft)
 {
     const char* path = std::getenv("DSX_TUNE_CACHE");
     if (!path || !*path) return false;
@@ -1831,18 +1905,25 @@ bool tune_lookup(const std::string& key, int* v, int* fc, int* t1)
         if (tab == std::string::npos || line.substr(0, tab) != key) continue;
         std::istringstream in(line.substr(tab + 1));
         int a, b, c;
-        if (in >> a >> b >> c) { *v = a; *fc = b; *t1 = c; found = true; }
+        if (in >> a >> b >> c) {
+            *v = a; *fc = b; *t1 = c; found = true;
+            // optional: axis-1 column tile and the three radix sequences
+            FftChoice f;
+            if (in >> f.tc >> f.plan[0] >> f.plan[1] >> f.plan[2]) *fft = f;
+            else *fft = FftChoice{};
+        }
     }
     return found;
 }
 
-void tune_store(const std::string& key, int v, int fc, int t1)
+void tune_store(const std::string& key, int v, int fc, int t1, const FftChoice& fft)
 {
     const char* path = std::getenv("DSX_TUNE_CACHE");
     if (!path || !*path) return;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     std::ofstream f(path, std::ios::app);
-    f << key << "\t" << v << " " << fc << " " << t1 << "\n";
+    f << key << "\t" << v << " " << fc << " " << t1 << " " << fft.tc << " " << fft.plan[0] << " " << fft.plan[1]
+      << " " << fft.plan[2] << "\n";
 }
 
 // Minimum over `reps` timed runs of fn() on stream st (milliseconds), or < 0 on error.
@@ -1881,8 +1962,15 @@ dsx_status dsx_autotune(dsx_model m, int32_t lanczos_m, void* hip_stream)
         hipStream_t st = (hipStream_t)hip_stream;
         const std::string key = tune_key(m, lanczos_m);
         int v = 0, fc = 0, t1 = 12;
-        if (tune_lookup(key, &v, &fc, &t1)) {
+        FftChoice fch;
+        if (tune_lookup(key, &v, &fc, &t1, &fch)) {
             m->tune_recomb_variant = v; m->tune_fchunk = fc; m->tune_lanczos_t1 = t1;
+            if (fch.tc == 0 || fch.tc == 16 || fch.tc == 32 || fch.tc == 64) m->tune_tc = fch.tc;
+            for (int a = 0; a < 3; ++a) {
+                AxisPlan p{};
+                if (!fch.plan[a].empty() && parse_plan(fch.plan[a], m->n[a], &p)) m->plan[a] = p;
+            }
+            m->dirty = true;
             m->tuned = true;
             return DSX_OK;
         }
@@ -1903,6 +1991,35 @@ dsx_status dsx_autotune(dsx_model m, int32_t lanczos_m, void* hip_stream)
             if (t >= 0.f && (best < 0.f || t < best)) { best = t; best_fc = cand; }
         }
         m->tune_fchunk = best_fc;
+        // FFT radix orders of the axes the LDS kernels transform (the register kernels of
+        // edges 8, 16, 32 have a fixed order), one axis at a time
+        const auto reg = [](int n) { return n == 8 || n == 16 || n == 32; };
+        for (int a : {2, 1, 0}) {
+            const bool used = a == 0 ? !reg(m->n[0]) : !(reg(m->n[1]) && reg(m->n[2]));
+            if (!used) continue;
+            const std::vector<AxisPlan> cands = plan_candidates(m->n[a], 12);
+            if (cands.size() < 2) continue;
+            best = -1.f;
+            AxisPlan bestp = m->plan[a];
+            for (const AxisPlan& c : cands) {
+                m->plan[a] = c;
+                const float t = time_min(st, 3, [&] { return ensure_spectra(m, st, true); });
+                if (t >= 0.f && (best < 0.f || t < best)) { best = t; bestp = c; }
+            }
+            m->plan[a] = bestp;
+        }
+        // columns per block of the LDS axis-1 FFT
+        if (!reg(m->n[0])) {
+            best = -1.f;
+            int best_tc = 0;
+            for (int cand : {16, 32, 64}) {
+                if (sizeof(float2) * (size_t)m->n[0] * (1 + 2 * (size_t)cand) > 160 * 1024) continue;
+                m->tune_tc = cand;
+                const float t = time_min(st, 3, [&] { return ensure_spectra(m, st, true); });
+                if (t >= 0.f && (best < 0.f || t < best)) { best = t; best_tc = cand; }
+            }
+            m->tune_tc = best_tc;
+        }
         // recombination form (the parity form only exists for nuclear models whose r3 are halves)
         best = -1.f;
         int best_v = 0;
@@ -1930,7 +2047,11 @@ dsx_status dsx_autotune(dsx_model m, int32_t lanczos_m, void* hip_stream)
         g_prof.on = prof;
         if (m->failed) return fail(DSX_ERR_DEVICE, "device error during tuning");
         m->tuned = true;
-        tune_store(key, best_v, best_fc, best_t1);
+        m->dirty = true;      // the spectra of the last candidate: recomputed with the chosen plans
+        FftChoice chosen;
+        chosen.tc = m->tune_tc;
+        for (int a = 0; a < 3; ++a) chosen.plan[a] = plan_string(m->plan[a]);
+        tune_store(key, best_v, best_fc, best_t1, chosen);
         return DSX_OK;
     });
 }
@@ -1961,6 +2082,48 @@ dsx_status dsx_tune_query(dsx_model m, int32_t choice[3], int32_t* tuned)
     choice[1] = m->tune_fchunk;
     choice[2] = m->tune_lanczos_t1;
     *tuned = m->tuned ? 1 : 0;
+    return DSX_OK;
+}
+
+dsx_status dsx_tune_set_fft(dsx_model m, const int32_t* radices, int32_t col_tile)
+{
+    return guarded([&]() -> dsx_status {
+        dsx_status s = check_direct(m);
+        if (s != DSX_OK) return s;
+        if (!(col_tile == 0 || col_tile == 16 || col_tile == 32 || col_tile == 64))
+            return fail(DSX_ERR_ARG, "the axis-1 column tile must be 0, 16, 32 or 64");
+        if (col_tile && sizeof(float2) * (size_t)m->n[0] * (1 + 2 * (size_t)col_tile) > 160 * 1024)
+            return fail(DSX_ERR_ARG, "the axis-1 column tile does not fit the LDS at this edge");
+        AxisPlan np[3] = {m->plan[0], m->plan[1], m->plan[2]};
+        if (radices) {
+            for (int a = 0; a < 3; ++a) {
+                AxisPlan p{};
+                p.n = m->n[a];
+                for (int i = 0; i < kMaxRadices && radices[a * kMaxRadices + i] != 0; ++i)
+                    p.rad[p.nrad++] = radices[a * kMaxRadices + i];
+                if (m->n[a] == 1 && p.nrad == 0) { np[a] = p; continue; }
+                if (!plan_valid(p))
+                    return fail(DSX_ERR_ARG, "axis " + std::to_string(a + 1) +
+                                             ": radices must be 2, 4 or odd, with product n");
+                np[a] = p;
+            }
+        }
+        for (int a = 0; a < 3; ++a) m->plan[a] = np[a];
+        m->tune_tc = col_tile;
+        m->dirty = true;      // spectra are recomputed with the new plans
+        m->tuned = true;
+        return DSX_OK;
+    });
+}
+
+dsx_status dsx_tune_query_fft(dsx_model m, int32_t* radices, int32_t* col_tile)
+{
+    if (!m) return fail(DSX_ERR_ARG, "null model");
+    if (!radices || !col_tile) return fail(DSX_ERR_ARG, "null output");
+    for (int a = 0; a < 3; ++a)
+        for (int i = 0; i < kMaxRadices; ++i)
+            radices[a * kMaxRadices + i] = i < m->plan[a].nrad ? m->plan[a].rad[i] : 0;
+    *col_tile = m->tune_tc;
     return DSX_OK;
 }
 
@@ -2034,13 +2197,16 @@ dsx_status build_batch_graph(const std::vector<std::vector<LaunchRec>>& seq, boo
         for (int i = 0; i < n; ++i)
             if (head[i] < seq[i].size()) best = std::min(best, stage_rank(seq[i][head[i]].stage));
         if (best == INT_MAX) break;
-        // the heads of this step, grouped by kernel and block size (in model order)
-        std::vector<std::pair<std::pair<const void*, unsigned>, std::vector<int>>> groups;
+        // the heads of this step, grouped by kernel, block size and the number of blocks
+        // the LDS admits per CU (a node takes its members' largest LDS: members of one
+        // class keep their occupancy), in model order
+        std::vector<std::pair<std::tuple<const void*, unsigned, unsigned>, std::vector<int>>> groups;
         for (int i = 0; i < n; ++i) {
             if (head[i] >= seq[i].size()) continue;
             const LaunchRec& r = seq[i][head[i]];
             if (stage_rank(r.stage) != best) continue;
-            const auto key = std::make_pair(r.merged, r.block);
+            const unsigned per_cu = r.lds ? std::min(64u, (160u * 1024u) / r.lds) : 64u;
+            const auto key = std::make_tuple(r.merged, r.block, per_cu);
             auto g = std::find_if(groups.begin(), groups.end(), [&](const auto& x) { return x.first == key; });
             if (g == groups.end()) groups.push_back({key, {i}});
             else g->second.push_back(i);

@@ -172,9 +172,17 @@ def test_autotune_cache_is_deterministic(tmp_path, monkeypatch):
     assert cache.read_text().strip().splitlines() == lines
     q, q2 = h.tune_query(), h2.tune_query()
     assert q == q2 and q["tuned"]
-    # the cache line holds the choices in the order form, FFT fields per block, filter planes
-    v, fc, t1 = (int(x) for x in lines[0].split("\t")[1].split())
+    # the cache line holds the choices in the order form, FFT fields per block, filter
+    # planes, axis-1 column tile, then the radix sequence of each axis
+    f = lines[0].split("\t")[1].split()
+    assert len(f) == 7
+    v, fc, t1, tc = (int(x) for x in f[:4])
     assert (q["recombine_form"], q["fft_fields_per_block"], q["filter_planes_per_block"]) == (v, fc, t1)
+    qf = h.tune_query_fft()
+    assert qf == h2.tune_query_fft() and qf["col_tile"] == tc
+    for a in range(3):
+        assert "x".join(str(r) for r in qf["radices"][a]) == f[4 + a]
+        assert int(np.prod(qf["radices"][a])) == m.n[a]
     assert v in (0, 2, 3, 4) and fc in (0, 1, 2, 4) and t1 in (4, 6, 8, 12, 16, 20, 26, 32, 52, 64)
     a = torch.empty(tuple(m.count), device="cuda")
     b = torch.empty(tuple(m.count), device="cuda")
@@ -260,4 +268,58 @@ def test_tune_set_plan_and_errors():
         with pytest.raises(dsx.DsxError) as e:
             h.tune_set(*bad)
         assert e.value.status == dsx.ERR_ARG
+    h.close()
+
+
+def test_fft_radix_orders_and_column_tiles():
+    """Every radix order the tuner may pick computes the same intensities (to rounding):
+    forced sequences on edges 12, 20 and 18 (radices 2, 3, 4, 5 and the odd 9), and the
+    axis-1 column tiles."""
+    import torch
+    import paper_1809_07088_amd as dsx
+    m = synth.random_model(48, n=(12, 20, 18), S=2, M=2, order=4)
+    m.g0, m.count = (-13, -21, -19), (27, 43, 39)
+    say("forced FFT radix orders and column tiles")
+    h = to_dsx(m)
+    ref = O.intensity(m).reshape(m.count)
+    out = torch.empty(tuple(m.count), device="cuda")
+    plans = [None, ([3, 4], [5, 4], [2, 9]), ([4, 3], [4, 5], [9, 2]), ([2, 2, 3], [2, 5, 2], [3, 2, 3]),
+             ([3, 2, 2], [2, 2, 5], [3, 3, 2])]
+    for plan in plans:
+        for tile in (0, 16, 32, 64):
+            h.tune_set_fft(plan, tile)
+            q = h.tune_query_fft()
+            assert q["col_tile"] == tile
+            if plan is not None:
+                assert q["radices"] == [list(r) for r in plan]
+            h.compute_intensity(out)
+            torch.cuda.synchronize()
+            assert_parity(out.cpu().numpy(), ref, what=f"{plan} tile {tile}")
+    for bad in [([4, 4], [5, 4], [2, 9]), ([3, 4], [5, 4], [6, 3]), ([3, 4], [5, 4], [1, 18])]:
+        with pytest.raises(dsx.DsxError) as e:
+            h.tune_set_fft(bad, 0)
+        assert e.value.status == dsx.ERR_ARG
+    with pytest.raises(dsx.DsxError) as e:
+        h.tune_set_fft(None, 48)
+    assert e.value.status == dsx.ERR_ARG
+    h.close()
+
+
+def test_autotune_picks_valid_fft_plans():
+    import torch
+    import paper_1809_07088_amd as dsx
+    m = synth.random_model(49, n=(24, 20, 14), S=2, M=1, order=3)
+    m.g0, m.count = (-25, -21, -15), (51, 43, 31)
+    say("autotune over FFT radix orders")
+    h = to_dsx(m)
+    h.autotune(0)
+    q = h.tune_query_fft()
+    for a in range(3):
+        assert int(np.prod(q["radices"][a])) == m.n[a]
+        assert all(r in (2, 4) or (r % 2 == 1 and r >= 3) for r in q["radices"][a])
+    assert q["col_tile"] in (0, 16, 32, 64)
+    out = torch.empty(tuple(m.count), device="cuda")
+    h.compute_intensity(out)
+    torch.cuda.synchronize()
+    assert_parity(out.cpu().numpy(), O.intensity(m).reshape(m.count))
     h.close()
