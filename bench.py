@@ -45,7 +45,12 @@ WORKLOADS = {
     "magnetic24": ("magnetic pyrochlore 24^3, 16 sites, 289^3 box (set_sites_async + compute_intensity)",
                    "k_recombine_magnetic"),
     "ensemble8x8": ("batched ensemble, 8 models x 8 configurations, one graph replay per step", "k_recombine"),
+    "ensemble8x8_merged": ("batched ensemble, 8 models x 8 configurations, merged graph forced, one replay per step",
+                           "k_recombine"),
+    "compositional1024": ("1024 compositional models (12^3, 48^3 voxels each) in one batch, one graph replay "
+                          "per step", "k_recombine"),
 }
+BATCH_MODES = {"auto": 0, "per_model": 1, "merged": 2}
 
 
 def ktrace_md(name):
@@ -372,7 +377,7 @@ def bench_magnetic(dsx, torch, dev, steps, warmup, O=None, probe=False):
     return res
 
 
-def bench_compositional(dsx, torch, dev, steps, O=None, seeds=1024):
+def bench_compositional(dsx, torch, dev, steps, O=None, seeds=1024, probe=False, batch_mode="auto"):
     """The compositional workload: simple cubic, one site, 12^3 supercell, Bernoulli(0.5)
     occupancies, 48^3 voxels (|h|,|k|,|l| < 2).  Single-instance latency of one
     synchronous set_sites_async + compute_intensity, and throughput over `seeds`
@@ -443,10 +448,12 @@ def bench_compositional(dsx, torch, dev, steps, O=None, seeds=1024):
         hs.append(hm)
         outs.append(torch.empty(count, dtype=torch.float32, device=dev))
     c0 = time.perf_counter()
-    batch = dsx.Batch(hs, outs)
+    batch = dsx.Batch(hs, outs, mode=BATCH_MODES[batch_mode])
     t_create = time.perf_counter() - c0
     batch.run()
     torch.cuda.synchronize()
+    if probe:
+        copy_probe(torch, dev)
     t0 = time.perf_counter()
     for _ in range(max(3, steps // 4)):
         batch.run()
@@ -466,7 +473,7 @@ def bench_compositional(dsx, torch, dev, steps, O=None, seeds=1024):
     return res
 
 
-def bench_ensemble(dsx, torch, dev, steps, warmup, lm=2, probe=False, batched_only=False):
+def bench_ensemble(dsx, torch, dev, steps, warmup, lm=2, probe=False, batched_only=False, batch_mode="auto"):
     """Batched ensemble (8 models x 8 configurations, edges from {16,20,24,32,40}, 1-4
     sites, Taylor order 6, |h|,|k|,|l| <= 4, Lanczos filter): one graph replay against the
     plain path that calls noise_filter model by model.  Both steps first upload every
@@ -515,7 +522,7 @@ def bench_ensemble(dsx, torch, dev, steps, warmup, lm=2, probe=False, batched_on
     t_plain = timed(plain)
     ref = [o.clone() for o in outs]
     c0 = time.perf_counter()
-    batch = dsx.Batch(hs, outs, lanczos_m=lm)
+    batch = dsx.Batch(hs, outs, lanczos_m=lm, mode=BATCH_MODES[batch_mode])
     t_create = time.perf_counter() - c0
 
     def batched():
@@ -727,6 +734,8 @@ def main():
     ap.add_argument("--magnetic-only", action="store_true",
                     help="time only the magnetic workload (for kernel traces of its recombination)")
     ap.add_argument("--compositional-only", action="store_true", help="time only the compositional workload")
+    ap.add_argument("--batch-mode", default="auto", choices=sorted(BATCH_MODES),
+                    help="graph form of the batched legs (auto: the faster of the two, timed at creation)")
     args = ap.parse_args()
     if args.summarize_ktrace:
         print(summarize_ktrace(args.summarize_ktrace, args.profile_name, args.pmc_command))
@@ -749,7 +758,7 @@ def main():
     torch.cuda.set_device(dev)
     if args.ensemble_only:
         print(json.dumps({"ensemble": bench_ensemble(dsx, torch, dev, args.steps, args.warmup,
-                                                     probe=args.copy_probe)}))
+                                                     probe=args.copy_probe, batch_mode=args.batch_mode)}))
         return
     if args.serving_only:
         print(json.dumps({"serving": bench_serving(dsx, torch, dev, args.serve_seconds)}))
@@ -759,7 +768,8 @@ def main():
                                                      probe=args.copy_probe)}))
         return
     if args.compositional_only:
-        print(json.dumps({"compositional": bench_compositional(dsx, torch, dev, args.steps)}))
+        print(json.dumps({"compositional": bench_compositional(dsx, torch, dev, args.steps, probe=args.copy_probe,
+                                                               batch_mode=args.batch_mode)}))
         return
     N, lm = args.order, args.lanczos_m
     model = synth.displacive(n=32, M=1, order=N, hmax=8)

@@ -296,6 +296,7 @@ void free_tables(DeviceTables& t)
 struct LaunchPlan {
     RecombParams rp;
     bool mag_rows = false;     // the row-staged magnetic form
+    bool direct = false;       // the direct form (order 0)
     int hc = 0, block = 0;
     size_t lds = 0;
     BraggParams bp;
@@ -342,7 +343,7 @@ struct dsx_model_s {
     std::map<std::tuple<int, int, int>, float*> lanczos_w;   // (m, m', s) -> weights
     int sum_chunk = 256, sum_chunks = 0;   // cells per sums block, blocks per (config, site)
     // plan knobs (defaults, or chosen by the autotuner for this model's key)
-    int tune_recomb_variant = 0;   // 0 default form, 2 class form, 3 unfolded, 4 unsliced
+    int tune_recomb_variant = 0;   // 0 default form, 2 class form, 3 unfolded, 4 unsliced, 5 direct
     int tune_fchunk = 0;           // fields per FFT plane block (0 = heuristic)
     int tune_lanczos_t1 = 12;      // planes per filter block
     int tune_tc = 0;               // columns per block of the LDS axis-1 FFT (0 = heuristic)
@@ -732,6 +733,13 @@ struct Layout {
 
 Layout dense_layout(const Box& b) { return Layout{b.cnt[2], 0}; }
 
+// The direct form applies to nuclear models of Taylor order 0 with one field per site
+// and no |Q|-dependent scattering factor.
+bool direct_form_applies(dsx_model m)
+{
+    return m->kind == DSX_NUCLEAR && m->order == 0 && m->F == 1 && !m->has_ff;
+}
+
 dsx_status plan_recombine(dsx_model m, const Box& bx, float* out, const Layout& lay, LaunchPlan& lp)
 {
     DeviceTables* tb = nullptr;
@@ -813,12 +821,20 @@ dsx_status plan_recombine(dsx_model m, const Box& bx, float* out, const Layout& 
         lp.block = std::max(64, (bx.cnt[2] + 63) / 64 * 64);
         lp.lds = sizeof(float2) * magnetic_rows_lds_elems(tb->rows_mr, tb->csites_mr, m->S, m->nclass, n3, tb->nH3span);
     }
+    // direct form: asked for, or by default where the levelled forms would spend their
+    // blocks on set-up (one or two sites x configurations)
+    if (direct_form_applies(m) && (p.variant == 5 || (p.variant == 0 && m->S * m->M <= 2)) &&
+        (unsigned long long)bx.cnt[0] * bx.cnt[1] * bx.cnt[2] < (1ULL << 32) - 256) {
+        lp.direct = true;
+        lp.lds = 0;
+    }
     if (lp.lds > 160 * 1024) return fail(DSX_ERR_UNSUPPORTED, "recombination does not fit the LDS for this box");
     // folded form: every r_mu2 a multiple of 1/2 (exactly, as given), fewer r3 classes
     // than sites, and the class buffers fit the LDS
     // (the folded kernel addresses the spectra of one configuration with 31-bit offsets)
     const bool small_spectra = (unsigned long long)n1 * n2 * m->SF * m->nh * sizeof(float2) < (1ULL << 31);
-    if (!mag && !p.nuc_ff && p.variant != 3 && m->nclass < m->S && small_spectra && m->order <= kMaxOrderFast) {
+    if (!lp.direct && !mag && !p.nuc_ff && p.variant != 3 && m->nclass < m->S && small_spectra &&
+        m->order <= kMaxOrderFast) {
         bool halves = true, whole = true;
         for (int i = 0; i < m->S; ++i) {
             const double r2 = m->frac[3 * m->site_of[i] + 1];
@@ -978,7 +994,9 @@ dsx_status run_box(dsx_model m, const Box& bx, float* dout, const Layout& lay, h
     LaunchPlan lp;
     dsx_status s = plan_recombine(m, bx, dout, lay, lp);
     if (s != DSX_OK) return s;
-    if (lp.mag_rows)
+    if (lp.direct)
+        HIPCHK(m, timed("recombine", st, [&] { return launch_recombine_direct(lp.rp, st); }));
+    else if (lp.mag_rows)
         HIPCHK(m, timed("recombine", st, [&] { return launch_recombine_magnetic_rows(lp.rp, lp.block, lp.lds, st); }));
     else if (m->kind == DSX_MAGNETIC)
         HIPCHK(m, timed("recombine", st, [&] { return launch_recombine_magnetic(lp.rp, lp.hc, lp.block, lp.lds, st); }));
@@ -2025,8 +2043,9 @@ dsx_status dsx_autotune(dsx_model m, int32_t lanczos_m, void* hip_stream)
         int best_v = 0;
         const Box b = filt ? filter_box(m->box, lanczos_m) : m->box;
         float* dst = filt ? m->d_ext : scratch;
-        for (int cand : {0, 2, 3, 4}) {
+        for (int cand : {0, 2, 3, 4, 5}) {
             if (cand != 0 && m->kind != DSX_NUCLEAR) continue;
+            if (cand == 5 && !direct_form_applies(m)) continue;
             m->tune_recomb_variant = cand;
             const Layout lay = filt ? ext_layout(b) : dense_layout(b);
             const float t = time_min(st, 3, [&] { return run_box(m, b, dst, lay, st); });
@@ -2063,8 +2082,10 @@ dsx_status dsx_tune_set(dsx_model m, const int32_t choice[3])
         if (s != DSX_OK) return s;
         if (!choice) return fail(DSX_ERR_ARG, "null choice");
         const int v = choice[0], fc = choice[1], t1 = choice[2];
-        if (!(v == 0 || v == 2 || v == 3 || v == 4) || (v != 0 && m->kind != DSX_NUCLEAR))
-            return fail(DSX_ERR_ARG, "recombination form must be 0, or 2, 3, 4 on a nuclear model");
+        if (!(v == 0 || v == 2 || v == 3 || v == 4 || v == 5) || (v != 0 && m->kind != DSX_NUCLEAR))
+            return fail(DSX_ERR_ARG, "recombination form must be 0, or 2, 3, 4, 5 on a nuclear model");
+        if (v == 5 && !direct_form_applies(m))
+            return fail(DSX_ERR_ARG, "the direct form (5) needs Taylor order 0 and no |Q|-dependent scattering factor");
         if (!(fc == 0 || fc == 1 || fc == 2 || fc == 4))
             return fail(DSX_ERR_ARG, "FFT fields per plane block must be 0, 1, 2 or 4");
         if (t1 < 1 || t1 > 64) return fail(DSX_ERR_ARG, "filter planes per block must be in 1..64");

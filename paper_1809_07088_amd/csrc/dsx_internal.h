@@ -109,7 +109,7 @@ struct RecombParams {
     int32_t variant;        // kernel variant (0: default for the problem, 1: multi-configuration
                             // form, 2: class form even when the parity form applies,
                             // 3: unfolded even when the folded form applies, 4: folded
-                            // without k3 slices)
+                            // without k3 slices, 5: direct, order 0 only)
     int32_t fold;           // folded form: every r_mu2 is a multiple of 1/2, so the g2 phase of a
                             // site is e^{2 pi i k2 r_mu2 / n2} times +-1 by the parity of H2, and
                             // level A sums the sites of each r3 class (per H2 residue)
@@ -267,6 +267,8 @@ hipError_t launch_recombine_nuclear(const RecombParams& p, int order, int hc, in
                                     size_t lds, hipStream_t st);
 hipError_t launch_recombine_magnetic(const RecombParams& p, int hc, int block, size_t lds,
                                      hipStream_t st);
+// the direct form (Taylor order 0, one field per site): one thread per voxel of the box
+hipError_t launch_recombine_direct(const RecombParams& p, hipStream_t st);
 // the row-staged magnetic form (no Debye-Waller factor); p.work lists its blocks, and
 // the launch has one thread per G3 of the box (block >= cnt3)
 constexpr int kMagRowsMaxThreads = 512;

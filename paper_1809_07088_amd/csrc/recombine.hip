@@ -1382,6 +1382,72 @@ static hipError_t launch_nuc_hi(const RecombParams& p, int hc, int block, size_t
     }
 }
 
+// ---------------------------------------------------------------------------- direct form
+// Taylor order 0 (occupancies only, one field per site): every voxel is computed on its
+// own, F_m(G) = sum_mu b_mu e^{2 pi i g.r_mu} X_mu,m(k), I(G) = scale sum_m |F_m(G)|^2.
+// One thread per voxel in output order, so a wave writes 64 consecutive floats of a row;
+// the spectra of a row's k1, k2 sit in a few cache lines.  For one or two sites x
+// configurations this beats the levelled forms, whose blocks serve one column of the
+// grid each.  (One wave per row, with k3 and H3 stepped along it, ran slower on 48-long
+// rows: the row set-up then weighs on fewer voxels.)
+constexpr int kDirectThreads = 256;
+
+template <class PT>
+__device__ __forceinline__ void recombine_direct_body(PT P, const int bx)
+{
+    const uint32_t idx = (uint32_t)bx * kDirectThreads + threadIdx.x;
+    const uint32_t c2 = (uint32_t)P.cnt[2], c1 = (uint32_t)P.cnt[1];
+    if (idx >= (uint32_t)P.cnt[0] * c1 * c2) return;
+    const uint32_t r = idx / c2;
+    const int i3 = (int)(idx - r * c2);
+    const int i1 = (int)(r / c1), i2 = (int)(r - (uint32_t)i1 * c1);
+    const int n1 = P.n1, n2 = P.n2, n3 = P.n3, nh = P.nh;
+    const int G1 = P.g0[0] + i1, G2 = P.g0[1] + i2, G3 = P.g0[2] + i3;
+    const int k1 = ((G1 % n1) + n1) % n1, k2 = ((G2 % n2) + n2) % n2, k3 = ((G3 % n3) + n3) % n3;
+    const int h = (G3 - k3) / n3 - P.H3min;
+    // half spectra: k3 >= nh reads conj X(-k)
+    const bool half = k3 >= nh;
+    const int q1 = half ? (n1 - k1) % n1 : k1, q2 = half ? (n2 - k2) % n2 : k2, q3 = half ? n3 - k3 : k3;
+    const size_t SFnh = (size_t)P.SF * nh;
+    const size_t col = ((size_t)q1 * n2 + q2) * SFnh + q3;
+    const float cj = half ? -1.f : 1.f;
+    float I = 0.f;
+    for (int m = 0; m < P.M; ++m) {
+        const float2* Xm = P.X + (size_t)m * n1 * n2 * SFnh + col;
+        float2 F = make_float2(0.f, 0.f);
+        for (int s = 0; s < P.S; ++s) {
+            const int mu = P.site_of[s];
+            const float2 ph = cmulf(cmulf(P.tab1[(size_t)mu * P.cnt[0] + i1], P.tab2[(size_t)mu * P.cnt[1] + i2]),
+                                    cmulf(P.tabK3[(size_t)mu * n3 + k3], P.tabH3[(size_t)P.class_of[s] * P.nH3span + h]));
+            float2 x = Xm[(size_t)mu * P.F * nh];
+            x.y *= cj;
+            F.x += ph.x * x.x - ph.y * x.y;
+            F.y += ph.x * x.y + ph.y * x.x;
+        }
+        I += F.x * F.x + F.y * F.y;
+    }
+    P.out[(size_t)(i1 * P.cnt[1] + i2) * P.opitch + i3 + P.ooff] = I * P.scale;
+}
+
+__global__ __launch_bounds__(kDirectThreads) void k_recombine_direct(RecombParams P)
+{
+    recombine_direct_body<RecombParams>(P, blockIdx.x);
+}
+__global__ __launch_bounds__(kDirectThreads) void k_recombine_direct_merged(const RecombParams* __restrict__ tab, const Slot* __restrict__ slots)
+{
+    int d, bx;
+    if (slot_of(slots, d, bx)) recombine_direct_body<const RecombParams&>(tab[d], bx);
+}
+
+hipError_t launch_recombine_direct(const RecombParams& p, hipStream_t st)
+{
+    const unsigned long long vox = (unsigned long long)p.cnt[0] * p.cnt[1] * p.cnt[2];
+    if (vox == 0) return hipSuccess;
+    if (vox >= (1ULL << 32) - kDirectThreads) return hipErrorInvalidValue;
+    return dispatch(k_recombine_direct, k_recombine_direct_merged, (unsigned)((vox + kDirectThreads - 1) / kDirectThreads),
+                    kDirectThreads, 0, st, p);
+}
+
 hipError_t launch_recombine_nuclear(const RecombParams& p, int order, int hc, int block,
                                     size_t lds, hipStream_t st)
 {

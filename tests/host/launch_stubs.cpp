@@ -9,6 +9,7 @@ hipError_t launch_fft_planes(const PlaneParams&, hipStream_t) { return hipErrorN
 hipError_t launch_fft_axis1(const Axis1Params&, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_recombine_nuclear(const RecombParams&, int, int, int, size_t, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_recombine_magnetic(const RecombParams&, int, int, size_t, hipStream_t) { return hipErrorNotSupported; }
+hipError_t launch_recombine_direct(const RecombParams&, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_recombine_magnetic_rows(const RecombParams&, int, size_t, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_bragg(const BraggParams&, int, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_dw_mean(const DwParams&, hipStream_t) { return hipErrorNotSupported; }
