@@ -650,6 +650,22 @@ def bench_serving(dsx, torch, dev, seconds, slots=4):
     burst_srv = time.perf_counter() - tb
     burst_stats = srv.stats(reset=True)
     srv.close()
+    # the same burst on a server without merged rounds (one request per slot)
+    srv1 = dsx.Server(slots=slots, queue_capacity=4096, arena_bytes=24 << 30, max_round=1)
+    hs1 = []
+    for m, v in zip(pool, dsites):
+        h = srv1.add_model(**desc(m))
+        h.set_grid(m.g0, m.count)
+        h.set_sites(0, *v[0])
+        hs1.append(h)
+    for i in range(len(pool)):
+        srv1.wait(srv1.submit(hs1[i], outs[i], 0, *dsites[i][0]))
+    tb = time.perf_counter()
+    tickets = [srv1.submit(hs1[i], outs[i], 0, *dsites[i][v]) for (i, v) in reqs]
+    for t in tickets:
+        srv1.wait(t)
+    burst_srv1 = time.perf_counter() - tb
+    srv1.close()
 
     # ---- plain path: one synchronous call at a time, same trace
     plain = []
@@ -691,8 +707,11 @@ def bench_serving(dsx, torch, dev, seconds, slots=4):
                        "peak_in_flight": open_srv["peak_in_flight"],
                        "arena_peak_GB": round(open_srv["arena_peak_bytes"] / 1e9, 3),
                        "max_submit_lag_ms": round(lag * 1e3, 3),
+                       "mean_round": round(open_srv["round_requests"] / max(open_srv["rounds"], 1), 2),
                        "saturated_voxels_per_s": round(total_vox / burst_srv, 1),
-                       "saturated_p99_ms": round(burst_stats["p99_ms"], 3)},
+                       "saturated_p99_ms": round(burst_stats["p99_ms"], 3),
+                       "saturated_mean_round": round(burst_stats["round_requests"] / max(burst_stats["rounds"], 1), 2),
+                       "saturated_voxels_per_s_one_request_per_slot": round(total_vox / burst_srv1, 1)},
             "plain": {"voxels_per_s": round(total_vox / span_plain, 1), "p50_ms": round(pct(0.5), 3),
                       "p99_ms": round(pct(0.99), 3), "max_ms": round(float(lat[-1]), 3),
                       "saturated_voxels_per_s": round(total_vox / burst_plain, 1)},

@@ -379,11 +379,20 @@ dsx_status dsx_tune_set(dsx_model m, const int32_t choice[3]);
  * by HBM footprint), and requests of one model run one after another in
  * submission order.  Waiting requests are served first come first served, except
  * that a request that fits may start before an earlier one that does not yet fit
- * (at most 64 times for one waiting request).
- *   slots           1..16 requests on the device at once
+ * (at most 64 times for one waiting request).  When several small requests (up to
+ * 2^20 output voxels) can start at once, the dispatcher forms a round of up to
+ * max_round of them on one slot (a larger request runs alone on its slot): each
+ * request's site copy is issued as such, and the launches of all its steps run as
+ * merged kernels (the form of dsx_batch_create_mode's merged graph, one kernel per step
+ * and kernel instance over a descriptor table of the round's requests, issued directly
+ * on the slot's stream with the tables copied from host memory pinned at creation);
+ * the round's requests finish together.
+ *   slots           1..16 rounds (of one or more requests) on the device at once
  *   queue_capacity  >= 1 requests waiting for admission; beyond it submit returns
  *                   DSX_ERR_BUSY
  *   arena_bytes     device workspace shared by requests on the device
+ *   max_round       requests per round: 0 = 16, 1 = one request per slot (no merged
+ *                   launches), at most 64
  */
 typedef struct dsx_server_s* dsx_server;
 
@@ -391,6 +400,7 @@ typedef struct {
     int32_t slots;
     int32_t queue_capacity;
     int64_t arena_bytes;
+    int32_t max_round;
 } dsx_server_config;
 
 /*
@@ -421,6 +431,8 @@ typedef struct {
     double span_s;             /* first submission to last completion */
     int64_t arena_bytes, arena_peak_bytes;
     int32_t slots, peak_in_flight;
+    int64_t rounds;            /* rounds started (a round of one is a plain request) */
+    int64_t round_requests;    /* requests they held */
 } dsx_server_stats;
 
 dsx_status dsx_server_create(const dsx_server_config* c, dsx_server* out);

@@ -68,7 +68,8 @@ BATCH_AUTO, BATCH_PER_MODEL, BATCH_MERGED = 0, 1, 2
 
 
 class ServerConfig(ctypes.Structure):
-    _fields_ = [("slots", ctypes.c_int32), ("queue_capacity", ctypes.c_int32), ("arena_bytes", ctypes.c_int64)]
+    _fields_ = [("slots", ctypes.c_int32), ("queue_capacity", ctypes.c_int32), ("arena_bytes", ctypes.c_int64),
+                ("max_round", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -83,7 +84,8 @@ class ServerStats(ctypes.Structure):
                 ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
                 ("span_s", ctypes.c_double), ("arena_bytes", ctypes.c_int64),
                 ("arena_peak_bytes", ctypes.c_int64), ("slots", ctypes.c_int32),
-                ("peak_in_flight", ctypes.c_int32)]
+                ("peak_in_flight", ctypes.c_int32), ("rounds", ctypes.c_int64),
+                ("round_requests", ctypes.c_int64)]
 
 
 _lib = None
@@ -554,10 +556,11 @@ class ServedModel(Model):
 
 
 class Server:
-    """Continuous-batching request server over resident models (dsx_server_*)."""
+    """Continuous-batching request server over resident models (dsx_server_*).
+    max_round: requests merged into one round (0 = 16, 1 = one request per slot)."""
 
-    def __init__(self, slots=4, queue_capacity=1024, arena_bytes=8 << 30):
-        c = ServerConfig(int(slots), int(queue_capacity), int(arena_bytes))
+    def __init__(self, slots=4, queue_capacity=1024, arena_bytes=8 << 30, max_round=0):
+        c = ServerConfig(int(slots), int(queue_capacity), int(arena_bytes), int(max_round))
         h = ctypes.c_void_p()
         _check(lib().dsx_server_create(ctypes.byref(c), ctypes.byref(h)))
         self.handle = h.value

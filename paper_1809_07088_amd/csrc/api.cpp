@@ -827,6 +827,7 @@ dsx_status plan_recombine(dsx_model m, const Box& bx, float* out, const Layout& 
         (unsigned long long)bx.cnt[0] * bx.cnt[1] * bx.cnt[2] < (1ULL << 32) - 256) {
         lp.direct = true;
         lp.lds = 0;
+        p.planes = stored_planes(bx);   // a half-stored box: its planes G1 <= 0 only
     }
     if (lp.lds > 160 * 1024) return fail(DSX_ERR_UNSUPPORTED, "recombination does not fit the LDS for this box");
     // folded form: every r_mu2 a multiple of 1/2 (exactly, as given), fewer r3 classes
@@ -2204,14 +2205,17 @@ bool merge_keeps_registers(const void* one, const void* merged)
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Build the graph of the recorded sequences: merged (launches of a step that share a
-// kernel and block size become one node) or one node per launch.
-dsx_status build_batch_graph(const std::vector<std::vector<LaunchRec>>& seq, bool merge, BatchGraph& out)
+// Plan the kernel nodes of recorded sequences: merged (launches of a step that share a
+// kernel, block size and LDS class become one node) or one node per launch.  Nodes come
+// out in an order that respects every dependency, so issuing them in order on one stream
+// is also valid.
+dsx_status plan_nodes(const std::vector<std::vector<LaunchRec>>& seq, bool merge, std::vector<BatchNode>& nodes,
+                      int* spill_kept_out)
 {
     const int n = (int)seq.size();
     std::vector<size_t> head(n, 0);
     std::vector<int> last(n, -1);
-    std::vector<BatchNode> nodes;
+    nodes.clear();
     int spill_kept = 0;
     for (;;) {
         int best = INT_MAX;
@@ -2273,7 +2277,13 @@ dsx_status build_batch_graph(const std::vector<std::vector<LaunchRec>>& seq, boo
             nodes.push_back(std::move(nd));
         }
     }
-    // device block: per merged node its descriptor array and its slot map
+    *spill_kept_out = spill_kept;
+    return DSX_OK;
+}
+
+// Device bytes of the merged nodes' descriptor arrays and slot maps (sets their offsets).
+size_t layout_nodes(const std::vector<std::vector<LaunchRec>>& seq, std::vector<BatchNode>& nodes)
+{
     size_t bytes = 0;
     for (BatchNode& nd : nodes) {
         if (!nd.merged) continue;
@@ -2282,25 +2292,45 @@ dsx_status build_batch_graph(const std::vector<std::vector<LaunchRec>>& seq, boo
         nd.slot_off = bytes;
         bytes = align256(bytes + (size_t)(nd.grid / 8) * sizeof(Slot));
     }
+    return bytes;
+}
+
+// Write the descriptor arrays and slot maps of the merged nodes into host memory of the
+// size layout_nodes gave.
+void fill_nodes(const std::vector<std::vector<LaunchRec>>& seq, const std::vector<BatchNode>& nodes, unsigned char* host,
+                size_t bytes)
+{
+    std::memset(host, 0, bytes);
+    for (const BatchNode& nd : nodes) {
+        if (!nd.merged) continue;
+        const size_t ps = seq[nd.members[0]][nd.recs[0]].params.size();
+        Slot* sl = reinterpret_cast<Slot*>(host + nd.slot_off);
+        int first = 0;
+        for (size_t d = 0; d < nd.members.size(); ++d) {
+            const LaunchRec& r = seq[nd.members[d]][nd.recs[d]];
+            std::memcpy(host + nd.tab_off + d * ps, r.params.data(), ps);
+            const int span = (int)((nd.counts[d] + 7u) & ~7u);
+            for (int b = first; b < first + span; b += 8)
+                sl[b / 8] = Slot{(int32_t)d, first, (int32_t)nd.counts[d], 0};
+            first += span;
+        }
+    }
+}
+
+// Build the graph of the recorded sequences.
+dsx_status build_batch_graph(const std::vector<std::vector<LaunchRec>>& seq, bool merge, BatchGraph& out)
+{
+    std::vector<BatchNode> nodes;
+    int spill_kept = 0;
+    dsx_status ps = plan_nodes(seq, merge, nodes, &spill_kept);
+    if (ps != DSX_OK) return ps;
+    const size_t bytes = layout_nodes(seq, nodes);
     BatchGraph g;
     auto bail = [&](dsx_status st) { free_graph(g); return st; };
     hipError_t e = hipSuccess;
     if (bytes) {
         std::vector<unsigned char> host(bytes, 0);
-        for (BatchNode& nd : nodes) {
-            if (!nd.merged) continue;
-            const size_t ps = seq[nd.members[0]][nd.recs[0]].params.size();
-            Slot* sl = reinterpret_cast<Slot*>(host.data() + nd.slot_off);
-            int first = 0;
-            for (size_t d = 0; d < nd.members.size(); ++d) {
-                const LaunchRec& r = seq[nd.members[d]][nd.recs[d]];
-                std::memcpy(host.data() + nd.tab_off + d * ps, r.params.data(), ps);
-                const int span = (int)((nd.counts[d] + 7u) & ~7u);
-                for (int b = first; b < first + span; b += 8)
-                    sl[b / 8] = Slot{(int32_t)d, first, (int32_t)nd.counts[d], 0};
-                first += span;
-            }
-        }
+        fill_nodes(seq, nodes, host.data(), bytes);
         if ((e = hipMalloc(&g.dmem, bytes)) != hipSuccess) return bail(fail(DSX_ERR_NOMEM, hipGetErrorString(e)));
         if ((e = hipMemcpy(g.dmem, host.data(), bytes, hipMemcpyHostToDevice)) != hipSuccess)
             return bail(fail(DSX_ERR_DEVICE, hipGetErrorString(e)));
@@ -2557,6 +2587,10 @@ struct Finished {
 };
 
 constexpr int kMaxBypass = 64;
+// Requests up to this many output voxels may share a merged round (their launches are
+// short, so a round saves launch and tail time); larger ones run alone on their slot,
+// beside the other slots' work.
+constexpr int64_t kRoundMaxVoxels = 1 << 20;
 
 }  // namespace
 
@@ -2568,7 +2602,12 @@ struct dsx_server_s {
     std::vector<hipStream_t> streams;
     std::vector<hipEvent_t> events;
     std::vector<char> busy;
-    std::vector<Request> running;      // per slot
+    std::vector<std::vector<Request>> running;   // per slot: the requests of its round
+    int max_round = 16;
+    // per slot: pinned host and device staging of a round's descriptor tables
+    std::vector<unsigned char*> hstage;
+    std::vector<void*> dstage;
+    size_t stage_bytes = 0;
     std::deque<Request> queue;
     std::vector<dsx_model> models;
     std::set<dsx_model> active;        // models with a request on the device
@@ -2586,6 +2625,7 @@ struct dsx_server_s {
     bool have_first = false;
     Clock::time_point first_submit, last_done;
     int in_flight = 0, peak_in_flight = 0;
+    int64_t rounds = 0, round_requests = 0;
 };
 
 namespace {
@@ -2600,8 +2640,9 @@ size_t request_workspace(dsx_model m, int lm, size_t* x_bytes)
     return ws;
 }
 
-// Enqueues an admitted request on stream st and records ev after it (dispatcher thread).
-dsx_status launch_request(dsx_server s, const Request& q, hipStream_t st, hipEvent_t ev)
+// Enqueues an admitted request on stream st (its site copy, then its kernels; with a
+// recorder set the kernels are recorded instead) (dispatcher thread).
+dsx_status enqueue_request(dsx_server s, const Request& q, hipStream_t st)
 {
     dsx_model m = q.r.model;
     dsx_status rs = check_model(m);
@@ -2635,12 +2676,84 @@ dsx_status launch_request(dsx_server s, const Request& q, hipStream_t st, hipEve
     // the arena range belongs to the request, not the model
     m->d_X = nullptr; m->d_partial = nullptr; m->d_ext = nullptr; m->ext_cap = 0;
     m->dirty = true;
+    return rs;
+}
+
+// Enqueues an admitted request on stream st and records ev after it (dispatcher thread).
+dsx_status launch_request(dsx_server s, const Request& q, hipStream_t st, hipEvent_t ev)
+{
+    dsx_status rs = enqueue_request(s, q, st);
     if (rs == DSX_OK) {
         const hipError_t e = hipEventRecord(ev, st);
-        if (e != hipSuccess) { m->failed = true; rs = fail(DSX_ERR_DEVICE, hipGetErrorString(e)); }
+        if (e != hipSuccess) { q.r.model->failed = true; rs = fail(DSX_ERR_DEVICE, hipGetErrorString(e)); }
     }
     if (rs != DSX_OK) (void)hipStreamSynchronize(st);   // nothing may still use the range
     return rs;
+}
+
+// A round of several requests on one slot: every request's site copy is enqueued and its
+// kernels recorded, then the kernels of all of them run as merged launches on the slot's
+// stream, the descriptor tables copied from the slot's pinned staging.  status[i] is the
+// outcome of request i; the event is recorded after the round.  Returns DSX_OK when the
+// round was enqueued (some requests may have failed before any kernel of theirs).
+dsx_status launch_round(dsx_server s, int slot, std::vector<dsx_status>& status, std::vector<std::string>& msg)
+{
+    std::vector<Request>& reqs = s->running[slot];
+    const hipStream_t st = s->streams[slot];
+    const int n = (int)reqs.size();
+    status.assign(n, DSX_OK);
+    msg.assign(n, std::string());
+    std::vector<std::vector<LaunchRec>> seq;
+    std::vector<int> who;                       // request of each recorded sequence
+    for (int i = 0; i < n; ++i) {
+        Recorder r;
+        struct Reset { ~Reset() { g_recorder = nullptr; } } reset;
+        g_recorder = &r;
+        const dsx_status rs = enqueue_request(s, reqs[i], st);
+        g_recorder = nullptr;
+        if (rs != DSX_OK) { status[i] = rs; msg[i] = dsx_last_error(); continue; }
+        seq.push_back(std::move(r.recs));
+        who.push_back(i);
+    }
+    hipError_t e = hipSuccess;
+    dsx_status rs = DSX_OK;
+    if (!seq.empty()) {
+        std::vector<BatchNode> nodes;
+        int kept = 0;
+        rs = plan_nodes(seq, true, nodes, &kept);
+        size_t bytes = rs == DSX_OK ? layout_nodes(seq, nodes) : 0;
+        if (rs == DSX_OK && bytes > s->stage_bytes) {   // tables too large: the round runs unmerged
+            rs = plan_nodes(seq, false, nodes, &kept);
+            bytes = 0;
+        }
+        if (rs == DSX_OK && bytes) {
+            fill_nodes(seq, nodes, s->hstage[slot], bytes);
+            e = hipMemcpyAsync(s->dstage[slot], s->hstage[slot], bytes, hipMemcpyHostToDevice, st);
+        }
+        for (size_t k = 0; rs == DSX_OK && e == hipSuccess && k < nodes.size(); ++k) {
+            BatchNode& nd = nodes[k];
+            if (nd.lds > 65536 &&
+                (e = hipFuncSetAttribute(nd.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)nd.lds)) != hipSuccess)
+                break;
+            void* tab = (char*)s->dstage[slot] + nd.tab_off;
+            void* slots = (char*)s->dstage[slot] + nd.slot_off;
+            void* margs[2] = {&tab, &slots};
+            void* sargs[1] = {nd.params.data()};
+            e = hipLaunchKernel(nd.fn, dim3(nd.grid), dim3(nd.block), nd.merged ? margs : sargs, nd.lds, st);
+        }
+    }
+    if (e == hipSuccess && rs == DSX_OK) e = hipEventRecord(s->events[slot], st);
+    if (e != hipSuccess || rs != DSX_OK) {
+        const std::string m = e != hipSuccess ? std::string(hipGetErrorString(e)) : std::string(dsx_last_error());
+        for (int i : who) {
+            reqs[i].r.model->failed = e != hipSuccess;
+            status[i] = e != hipSuccess ? DSX_ERR_DEVICE : rs;
+            msg[i] = m;
+        }
+        (void)hipStreamSynchronize(st);   // nothing may still use the arena ranges
+        return status.empty() ? DSX_OK : status[0];
+    }
+    return DSX_OK;
 }
 
 // Bookkeeping of a request that left the device (lock held).
@@ -2677,48 +2790,75 @@ void serve(dsx_server s)
             if (e != hipSuccess) {
                 st = DSX_ERR_DEVICE;
                 msg = hipGetErrorString(e);
-                s->running[i].r.model->failed = true;
             }
-            finish_request(s, s->running[i], st, msg);
+            for (Request& q : s->running[i]) {
+                if (e != hipSuccess) q.r.model->failed = true;
+                finish_request(s, q, st, msg);
+                --s->in_flight;
+            }
+            s->running[i].clear();
             s->busy[i] = 0;
-            --s->in_flight;
             changed = true;
         }
         // admission: first come first served among requests whose workspace fits and
-        // whose model is idle; a request that fits may pass one that does not yet
+        // whose model is idle; a request that fits may pass one that does not yet.  A
+        // free slot takes a round of up to max_round such requests.
         for (;;) {
             int slot = -1;
             for (int i = 0; i < s->nslots && slot < 0; ++i)
                 if (!s->busy[i]) slot = i;
             if (slot < 0 || s->queue.empty()) break;
             std::set<dsx_model> waiting;   // models with an earlier request still queued
-            auto pick = s->queue.end();
-            for (auto it = s->queue.begin(); it != s->queue.end(); ++it) {
+            std::vector<Request>& round = s->running[slot];
+            round.clear();
+            bool closed = false;           // a large request runs alone
+            for (auto it = s->queue.begin(); it != s->queue.end() && (int)round.size() < s->max_round && !closed;) {
                 if (it != s->queue.begin() && s->queue.front().bypassed >= kMaxBypass) break;
                 dsx_model m = it->r.model;
-                if (s->active.count(m) || waiting.count(m)) { waiting.insert(m); continue; }
+                const bool large = it->voxels > kRoundMaxVoxels;
+                if (large && !round.empty()) {   // (its model's later requests wait behind it)
+                    waiting.insert(m);
+                    ++it;
+                    continue;
+                }
                 size_t off = 0;
-                if (!s->arena.alloc(it->ws, &off)) { waiting.insert(m); continue; }
+                if (s->active.count(m) || waiting.count(m) || !s->arena.alloc(it->ws, &off)) {
+                    waiting.insert(m);
+                    ++it;
+                    continue;
+                }
                 it->off = off;
-                pick = it;
-                break;
+                for (auto jt = s->queue.begin(); jt != it; ++jt) ++jt->bypassed;
+                s->active.insert(m);
+                round.push_back(std::move(*it));
+                it = s->queue.erase(it);
+                closed = large;
             }
-            if (pick == s->queue.end()) break;
-            for (auto it = s->queue.begin(); it != pick; ++it) ++it->bypassed;
-            s->running[slot] = std::move(*pick);
-            s->queue.erase(pick);
+            if (round.empty()) break;
             s->busy[slot] = 1;
-            s->active.insert(s->running[slot].r.model);
-            s->peak_in_flight = std::max(s->peak_in_flight, ++s->in_flight);
+            s->in_flight += (int)round.size();
+            s->peak_in_flight = std::max(s->peak_in_flight, s->in_flight);
+            ++s->rounds;
+            s->round_requests += (int64_t)round.size();
             lk.unlock();
-            const dsx_status st = launch_request(s, s->running[slot], s->streams[slot], s->events[slot]);
-            const std::string msg = st == DSX_OK ? std::string() : std::string(dsx_last_error());
+            std::vector<dsx_status> sts;
+            std::vector<std::string> msgs;
+            if (round.size() == 1) {
+                sts.assign(1, launch_request(s, round[0], s->streams[slot], s->events[slot]));
+                msgs.assign(1, sts[0] == DSX_OK ? std::string() : std::string(dsx_last_error()));
+            } else {
+                (void)launch_round(s, slot, sts, msgs);
+            }
             lk.lock();
-            if (st != DSX_OK) {
-                finish_request(s, s->running[slot], st, msg);
-                s->busy[slot] = 0;
+            // requests that failed before any of their kernels left the round now
+            std::vector<Request> keep;
+            for (size_t i = 0; i < round.size(); ++i) {
+                if (sts[i] == DSX_OK) { keep.push_back(std::move(round[i])); continue; }
+                finish_request(s, round[i], sts[i], msgs[i]);
                 --s->in_flight;
             }
+            round.swap(keep);
+            if (round.empty()) s->busy[slot] = 0;
             changed = true;
         }
         if (changed) s->done.notify_all();
@@ -2736,6 +2876,8 @@ void free_server(dsx_server s)
     for (dsx_model m : s->models) { free_model(m); delete m; }
     for (auto e : s->events) if (e) (void)hipEventDestroy(e);
     for (auto st : s->streams) if (st) (void)hipStreamDestroy(st);
+    for (auto h : s->hstage) if (h) (void)hipHostFree(h);
+    for (auto d : s->dstage) if (d) (void)hipFree(d);
     dfree(s->arena_mem);
 }
 
@@ -2751,6 +2893,7 @@ dsx_status dsx_server_create(const dsx_server_config* c, dsx_server* out)
         if (c->slots < 1 || c->slots > 16) return fail(DSX_ERR_ARG, "slots must be in 1..16");
         if (c->queue_capacity < 1) return fail(DSX_ERR_ARG, "queue_capacity must be >= 1");
         if (c->arena_bytes < 1) return fail(DSX_ERR_ARG, "arena_bytes must be >= 1");
+        if (c->max_round < 0 || c->max_round > 64) return fail(DSX_ERR_ARG, "max_round must be in 0..64");
         dsx_server s = new (std::nothrow) dsx_server_s();
         if (!s) return fail(DSX_ERR_NOMEM, "host allocation failed");
         auto bail = [&](dsx_status st) { free_server(s); delete s; return st; };
@@ -2766,10 +2909,18 @@ dsx_status dsx_server_create(const dsx_server_config* c, dsx_server* out)
         s->events.assign(s->nslots, nullptr);
         s->busy.assign(s->nslots, 0);
         s->running.resize(s->nslots);
+        s->max_round = c->max_round == 0 ? 16 : c->max_round;
+        s->stage_bytes = s->max_round > 1 ? (size_t)4 << 20 : 0;
+        s->hstage.assign(s->nslots, nullptr);
+        s->dstage.assign(s->nslots, nullptr);
         for (int i = 0; i < s->nslots; ++i) {
             if ((e = hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking)) != hipSuccess ||
                 (e = hipEventCreateWithFlags(&s->events[i], hipEventDisableTiming)) != hipSuccess)
                 return bail(fail(DSX_ERR_DEVICE, hipGetErrorString(e)));
+            if (s->stage_bytes &&
+                ((e = hipHostMalloc((void**)&s->hstage[i], s->stage_bytes, hipHostMallocDefault)) != hipSuccess ||
+                 (e = hipMalloc(&s->dstage[i], s->stage_bytes)) != hipSuccess))
+                return bail(fail(DSX_ERR_NOMEM, std::string("round staging: ") + hipGetErrorString(e)));
         }
         try {
             s->worker = std::thread(serve, s);
@@ -2888,9 +3039,12 @@ dsx_status dsx_server_stats_read(dsx_server s, int32_t reset, dsx_server_stats* 
         z.arena_peak_bytes = (int64_t)s->arena.peak();
         z.slots = s->nslots;
         z.peak_in_flight = s->peak_in_flight;
+        z.rounds = s->rounds;
+        z.round_requests = s->round_requests;
         *out = z;
         if (reset) {
             s->submitted = s->completed = s->failed = s->rejected = s->voxels = 0;
+            s->rounds = s->round_requests = 0;
             s->lat_ms.clear();
             s->have_first = false;
             s->peak_in_flight = s->in_flight;

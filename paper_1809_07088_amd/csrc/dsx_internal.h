@@ -146,6 +146,8 @@ struct RecombParams {
     int32_t rows, csites;
     int32_t qmod;           // > 0: every r_c3 a multiple of 1/qmod and one form factor for all
                             // sites: the classes are summed per residue of H3 mod qmod
+    int32_t planes;         // direct form: the planes i1 < planes are computed (a half-stored
+                            // box holds its planes G1 <= 0 only)
 };
 
 // ---------------------------------------------------------------------------- Bragg (k = 0)

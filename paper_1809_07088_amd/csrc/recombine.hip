@@ -1397,7 +1397,7 @@ __device__ __forceinline__ void recombine_direct_body(PT P, const int bx)
 {
     const uint32_t idx = (uint32_t)bx * kDirectThreads + threadIdx.x;
     const uint32_t c2 = (uint32_t)P.cnt[2], c1 = (uint32_t)P.cnt[1];
-    if (idx >= (uint32_t)P.cnt[0] * c1 * c2) return;
+    if (idx >= (uint32_t)P.planes * c1 * c2) return;
     const uint32_t r = idx / c2;
     const int i3 = (int)(idx - r * c2);
     const int i1 = (int)(r / c1), i2 = (int)(r - (uint32_t)i1 * c1);
@@ -1441,8 +1441,9 @@ __global__ __launch_bounds__(kDirectThreads) void k_recombine_direct_merged(cons
 
 hipError_t launch_recombine_direct(const RecombParams& p, hipStream_t st)
 {
-    const unsigned long long vox = (unsigned long long)p.cnt[0] * p.cnt[1] * p.cnt[2];
+    const unsigned long long vox = (unsigned long long)p.planes * p.cnt[1] * p.cnt[2];
     if (vox == 0) return hipSuccess;
+    if (p.planes < 0 || p.planes > p.cnt[0]) return hipErrorInvalidValue;
     if (vox >= (1ULL << 32) - kDirectThreads) return hipErrorInvalidValue;
     return dispatch(k_recombine_direct, k_recombine_direct_merged, (unsigned)((vox + kDirectThreads - 1) / kDirectThreads),
                     kDirectThreads, 0, st, p);
@@ -1511,6 +1512,10 @@ hipError_t launch_recombine_magnetic(const RecombParams& p, int hc, int block, s
 template <int N, class PT>
 __device__ __forceinline__ void bragg_nuclear_body(PT P, const int bx)
 {
+    // every product and sum rounded on its own (no contraction into FMAs): the kernel and
+    // its merged twin then compute the same bits, and the variance of one configuration
+    // cancels to exactly 0
+#pragma clang fp contract(off)
     constexpr int T = n_monomials(N);
     __shared__ double Ar[3][N + 1], Ai[3][N + 1];
     __shared__ double Wr[kMaxSites], Wi[kMaxSites];
@@ -1629,6 +1634,10 @@ __device__ void dw_at_h(const BraggParams& P, const int H[3], int mu, double& tr
 template <class PT>
 __device__ __forceinline__ void bragg_magnetic_body(PT P, const int bx)
 {
+    // every product and sum rounded on its own (no contraction into FMAs): the kernel and
+    // its merged twin then compute the same bits, and the variance of one configuration
+    // cancels to exactly 0
+#pragma clang fp contract(off)
     __shared__ double Wr[4][kMaxSites], Wi[4][kMaxSites];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int idx = bx * 4 + wave;

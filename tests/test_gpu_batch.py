@@ -323,3 +323,28 @@ def test_autotune_picks_valid_fft_plans():
     torch.cuda.synchronize()
     assert_parity(out.cpu().numpy(), O.intensity(m).reshape(m.count))
     h.close()
+
+
+def test_merged_magnetic_batch_bitwise():
+    """Magnetic models (row-staged recombination, FP64 Bragg points) merged and per model:
+    the same bits, and the oracle."""
+    import torch
+    import paper_1809_07088_amd as dsx
+    models = [synth.serving_request_model(workload=50, model=i, n=8, S=S, typ=2) for i, S in enumerate((4, 2, 3))]
+    say("magnetic batch, merged against per-model")
+    hs = [to_dsx(m) for m in models]
+    got = {}
+    for mode in (dsx.BATCH_PER_MODEL, dsx.BATCH_MERGED):
+        outs = [torch.full(tuple(m.count), -1.0, device="cuda") for m in models]
+        b = dsx.Batch(hs, outs, mode=mode)
+        b.run()
+        torch.cuda.synchronize()
+        got[mode] = [o.cpu() for o in outs]
+        if mode == dsx.BATCH_MERGED:
+            assert b.info()["merged_nodes"] >= 3
+        b.close()
+    for k, m in enumerate(models):
+        assert torch.equal(got[dsx.BATCH_PER_MODEL][k], got[dsx.BATCH_MERGED][k]), k
+        assert_parity(got[dsx.BATCH_MERGED][k].numpy(), O.intensity(m).reshape(m.count))
+    for h in hs:
+        h.close()

@@ -81,3 +81,37 @@ def test_direct_form_rejected_where_it_does_not_apply():
         h.tune_set(5, 0, 12)
     assert e.value.status == dsx.ERR_ARG
     h.close()
+
+
+def test_direct_form_filtered_on_half_stored_box():
+    """The filter's grown box of a symmetric output box is stored as its planes G1 <= 0:
+    the direct form computes exactly those (the filtered output matches the oracle and
+    the levelled form), and two models served side by side keep each other's results."""
+    import torch
+    import paper_1809_07088_amd as dsx
+    m = synth.compositional(workload=64, model=0, n=(8, 7, 9), M=1, hmax=1, closed=True)
+    say(f"direct form, filtered, symmetric box {m.count}")
+    h = to_dsx(m)
+    ref = O.filtered_intensity(m, 2, 1)
+    outs = {}
+    for v in (5, 2):
+        h.tune_set(v, 0, 12)
+        o = torch.full(tuple(m.count), -1.0, device="cuda")
+        h.noise_filter(2, 1, o)
+        torch.cuda.synchronize()
+        outs[v] = o.cpu().numpy()
+        assert_parity(outs[v], ref, what=f"form {v}")
+    h.close()
+    # adjacent workspaces in one server arena: a round of both models, filtered
+    other = synth.displacive(workload=64, model=1, n=8, M=1, order=3, hmax=1)
+    srv = dsx.Server(slots=1, queue_capacity=16, arena_bytes=1 << 30, max_round=16)
+    from tests.test_gpu_serving import served
+    hs = [served(srv, mm) for mm in (m, other)]
+    for _ in range(3):
+        o = [torch.full(tuple(mm.count), -1.0, device="cuda") for mm in (m, other)]
+        ts = [srv.submit(hh, oo, lanczos_m=2) for hh, oo in zip(hs, o)]
+        for t in ts:
+            assert srv.wait(t, 60000)
+        assert_parity(o[0].cpu().numpy(), ref)
+        assert_parity(o[1].cpu().numpy(), O.filtered_intensity(other, 2, 1))
+    srv.close()

@@ -209,3 +209,39 @@ def test_served_model_rules():
     st = srv.stats(reset=True)
     assert st["completed"] == 1 and st["failed"] == 1
     srv.close()
+
+
+def test_merged_rounds_equal_single_requests():
+    """A burst on a server that merges up to 16 requests per round gives, bit for bit, what
+    a server running one request per slot gives, and forms rounds of several requests."""
+    import torch
+    import paper_1809_07088_amd as dsx
+    models = [synth.serving_request_model(workload=54, model=i, n=n, S=S, typ=t, order=4)
+              for i, (n, S, t) in enumerate([(8, 2, 0), (8, 3, 1), (10, 2, 2), (12, 4, 1), (9, 1, 0), (8, 5, 2),
+                                             (11, 3, 1), (8, 1, 0)])]
+    jobs = [(i, v, lm) for i in range(len(models)) for v in range(2) for lm in (0, 2)]
+    variants = {(i, v): dev(variant_sites(m, 300 + 10 * i + v)) for i, m in enumerate(models) for v in range(2)}
+    res = {}
+    for mr in (1, 16):
+        say(f"burst on a server with max_round={mr}")
+        srv = dsx.Server(slots=2, queue_capacity=256, arena_bytes=2 << 30, max_round=mr)
+        hs = [served(srv, m) for m in models]
+        outs = {k: torch.full(tuple(models[k[0]].count), -3.0, device="cuda") for k in jobs}
+        srv.stats(reset=True)
+        ts = [srv.submit(hs[i], outs[(i, v, lm)], 0, *variants[(i, v)], lanczos_m=lm) for (i, v, lm) in jobs]
+        for t in ts:
+            assert srv.wait(t, 60000)
+        st = srv.stats()
+        assert st["completed"] == len(jobs) and st["failed"] == 0
+        if mr == 1:
+            assert st["round_requests"] == st["rounds"]
+        else:
+            assert st["round_requests"] > st["rounds"]       # some rounds held several requests
+        res[mr] = {k: o.cpu() for k, o in outs.items()}
+        srv.close()
+    for k in jobs:
+        assert torch.equal(res[1][k], res[16][k]), k
+    i, v, lm = jobs[5]
+    m = with_sites(models[i], variant_sites(models[i], 300 + 10 * i + v))
+    exp = O.filtered_intensity(m, lm, 1) if lm else O.intensity(m).reshape(m.count)
+    assert_parity(res[16][(i, v, lm)].numpy(), exp)
