@@ -431,8 +431,18 @@ class Batch:
         if len(handles) != len(outs) or not handles:
             raise ValueError("one output per model, at least one model")
         self._keep = (list(models), list(outs))
+        # device outputs: contiguous float32 tensors, large enough for their model's box
+        # (checked where the model is a Model, whose grid the binding knows)
+        sv = int(oversample) if lanczos_m else 1
+        ptrs = []
+        for mdl, o in zip(models, outs):
+            nelem = mdl._box_voxels(sv) if isinstance(mdl, Model) else None
+            p, w = _ptr_out(o, nelem)
+            if w != DEVICE:
+                raise ValueError("batch outputs must be device tensors")
+            ptrs.append(p)
         arr_m = (ctypes.c_void_p * len(handles))(*handles)
-        arr_o = (ctypes.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
+        arr_o = (ctypes.c_void_p * len(outs))(*ptrs)
         h = ctypes.c_void_p()
         _check(lib().dsx_batch_create_mode(ctypes.cast(arr_m, ctypes.c_void_p), len(handles), int(lanczos_m),
                                            int(oversample), ctypes.cast(arr_o, ctypes.c_void_p), int(mode),

@@ -208,6 +208,15 @@ def test_batch_rejects_bad_arguments():
     with pytest.raises(dsx.DsxError) as e:
         dsx.Batch([h], [out], lanczos_m=1)
     assert e.value.status == dsx.ERR_ARG
+    # outputs: the binding checks size, dtype, layout and device before the call
+    with pytest.raises(ValueError):
+        dsx.Batch([h], [torch.empty(out.numel() - 1, device="cuda")])
+    with pytest.raises(ValueError):
+        dsx.Batch([h], [out.double()])
+    with pytest.raises(ValueError):
+        dsx.Batch([h], [out.cpu()])
+    with pytest.raises(ValueError):
+        dsx.Batch([h], [out], lanczos_m=2, oversample=2)     # s = 2 needs 8 times the voxels
     h.close()
 
 
