@@ -824,7 +824,7 @@ dsx_status plan_recombine(dsx_model m, const Box& bx, float* out, const Layout& 
     // direct form: asked for, or by default where the levelled forms would spend their
     // blocks on set-up (one or two sites x configurations)
     if (direct_form_applies(m) && (p.variant == 5 || (p.variant == 0 && m->S * m->M <= 2)) &&
-        (unsigned long long)bx.cnt[0] * bx.cnt[1] * bx.cnt[2] < (1ULL << 32) - 256) {
+        (unsigned long long)bx.cnt[0] * bx.cnt[1] * bx.cnt[2] < (1ULL << 31)) {
         lp.direct = true;
         lp.lds = 0;
         p.planes = stored_planes(bx);   // a half-stored box: its planes G1 <= 0 only

@@ -1385,48 +1385,82 @@ static hipError_t launch_nuc_hi(const RecombParams& p, int hc, int block, size_t
 // ---------------------------------------------------------------------------- direct form
 // Taylor order 0 (occupancies only, one field per site): every voxel is computed on its
 // own, F_m(G) = sum_mu b_mu e^{2 pi i g.r_mu} X_mu,m(k), I(G) = scale sum_m |F_m(G)|^2.
-// One thread per voxel in output order, so a wave writes 64 consecutive floats of a row;
-// the spectra of a row's k1, k2 sit in a few cache lines.  For one or two sites x
-// configurations this beats the levelled forms, whose blocks serve one column of the
-// grid each.  (One wave per row, with k3 and H3 stepped along it, ran slower on 48-long
-// rows: the row set-up then weighs on fewer voxels.)
-constexpr int kDirectThreads = 256;
+// A thread takes kDirectVPT consecutive voxels in output order (the index arithmetic and
+// the chain of dependent parameter and table loads are paid once for all of them; k3 and
+// H3 step along the row, the row indices are redone only where a row ends), so a wave
+// writes 64 kDirectVPT consecutive floats.  For one or two sites x configurations this
+// beats the levelled forms, whose blocks serve one column of the grid each.
+constexpr int kDirectThreads = 256, kDirectVPT = 8;
 
 template <class PT>
 __device__ __forceinline__ void recombine_direct_body(PT P, const int bx)
 {
-    const uint32_t idx = (uint32_t)bx * kDirectThreads + threadIdx.x;
     const uint32_t c2 = (uint32_t)P.cnt[2], c1 = (uint32_t)P.cnt[1];
-    if (idx >= (uint32_t)P.planes * c1 * c2) return;
-    const uint32_t r = idx / c2;
-    const int i3 = (int)(idx - r * c2);
-    const int i1 = (int)(r / c1), i2 = (int)(r - (uint32_t)i1 * c1);
+    const uint32_t total = (uint32_t)P.planes * c1 * c2;
+    const uint32_t base = ((uint32_t)bx * kDirectThreads + threadIdx.x) * kDirectVPT;
+    if (base >= total) return;
     const int n1 = P.n1, n2 = P.n2, n3 = P.n3, nh = P.nh;
-    const int G1 = P.g0[0] + i1, G2 = P.g0[1] + i2, G3 = P.g0[2] + i3;
-    const int k1 = ((G1 % n1) + n1) % n1, k2 = ((G2 % n2) + n2) % n2, k3 = ((G3 % n3) + n3) % n3;
-    const int h = (G3 - k3) / n3 - P.H3min;
-    // half spectra: k3 >= nh reads conj X(-k)
-    const bool half = k3 >= nh;
-    const int q1 = half ? (n1 - k1) % n1 : k1, q2 = half ? (n2 - k2) % n2 : k2, q3 = half ? n3 - k3 : k3;
     const size_t SFnh = (size_t)P.SF * nh;
-    const size_t col = ((size_t)q1 * n2 + q2) * SFnh + q3;
-    const float cj = half ? -1.f : 1.f;
-    float I = 0.f;
-    for (int m = 0; m < P.M; ++m) {
-        const float2* Xm = P.X + (size_t)m * n1 * n2 * SFnh + col;
-        float2 F = make_float2(0.f, 0.f);
-        for (int s = 0; s < P.S; ++s) {
-            const int mu = P.site_of[s];
-            const float2 ph = cmulf(cmulf(P.tab1[(size_t)mu * P.cnt[0] + i1], P.tab2[(size_t)mu * P.cnt[1] + i2]),
-                                    cmulf(P.tabK3[(size_t)mu * n3 + k3], P.tabH3[(size_t)P.class_of[s] * P.nH3span + h]));
-            float2 x = Xm[(size_t)mu * P.F * nh];
-            x.y *= cj;
-            F.x += ph.x * x.x - ph.y * x.y;
-            F.y += ph.x * x.y + ph.y * x.x;
+    const size_t cstride = (size_t)n1 * n2 * SFnh;     // between configurations
+    const size_t fstride = (size_t)P.F * nh;           // between sites
+    uint32_t r = base / c2;
+    int i3 = (int)(base - r * c2);
+    int i1 = (int)(r / c1), i2 = (int)(r - (uint32_t)i1 * c1);
+    int k1 = 0, k2 = 0, k3 = 0, h = 0;
+    size_t colp = 0, colm = 0;
+    auto row = [&]() {     // the row (i1, i2) and the residue of its voxel i3
+        const int G1 = P.g0[0] + i1, G2 = P.g0[1] + i2, G3 = P.g0[2] + i3;
+        k1 = ((G1 % n1) + n1) % n1;
+        k2 = ((G2 % n2) + n2) % n2;
+        k3 = ((G3 % n3) + n3) % n3;
+        h = (G3 - k3) / n3 - P.H3min;
+        colp = ((size_t)k1 * n2 + k2) * SFnh;                              // X(k)
+        colm = ((size_t)((n1 - k1) % n1) * n2 + (n2 - k2) % n2) * SFnh;   // X(-k), conjugated
+    };
+    row();
+    const int nv = (int)min((uint32_t)kDirectVPT, total - base);
+    // one site: the phase has modulus b, so |F_m|^2 = b^2 |X_m(k)|^2 exactly
+    const bool one = P.S == 1;
+    const int mu0 = P.site_of[0];
+    const float2 t0 = P.tab1[(size_t)mu0 * P.cnt[0]];
+    const float b2s = (t0.x * t0.x + t0.y * t0.y) * P.scale;
+    for (int v = 0; v < nv; ++v) {
+        const bool half = k3 >= nh;                    // half spectra: k3 >= nh reads conj X(-k)
+        const size_t col = half ? colm + (size_t)(n3 - k3) : colp + (size_t)k3;
+        const float cj = half ? -1.f : 1.f;
+        float I = 0.f;
+        if (one) {
+            const float2* x = P.X + col + (size_t)mu0 * fstride;
+            for (int m = 0; m < P.M; ++m) {
+                const float2 xv = x[(size_t)m * cstride];
+                I += xv.x * xv.x + xv.y * xv.y;
+            }
+            P.out[(size_t)(i1 * P.cnt[1] + i2) * P.opitch + i3 + P.ooff] = I * b2s;
         }
-        I += F.x * F.x + F.y * F.y;
+        for (int m = 0; m < (one ? 0 : P.M); ++m) {
+            const float2* Xm = P.X + (size_t)m * cstride + col;
+            float2 F = make_float2(0.f, 0.f);
+            for (int s = 0; s < P.S; ++s) {
+                const int mu = P.site_of[s];
+                const float2 ph = cmulf(cmulf(P.tab1[(size_t)mu * P.cnt[0] + i1], P.tab2[(size_t)mu * c1 + i2]),
+                                        cmulf(P.tabK3[(size_t)mu * n3 + k3], P.tabH3[(size_t)P.class_of[s] * P.nH3span + h]));
+                float2 x = Xm[(size_t)mu * fstride];
+                x.y *= cj;
+                F.x += ph.x * x.x - ph.y * x.y;
+                F.y += ph.x * x.y + ph.y * x.x;
+            }
+            I += F.x * F.x + F.y * F.y;
+        }
+        if (!one) P.out[(size_t)(i1 * P.cnt[1] + i2) * P.opitch + i3 + P.ooff] = I * P.scale;
+        // next voxel: along the row, or the start of the next row
+        if (++i3 < (int)c2) {
+            if (++k3 == n3) { k3 = 0; ++h; }
+        } else {
+            i3 = 0;
+            if (++i2 == (int)c1) { i2 = 0; ++i1; }
+            if (v + 1 < nv) row();
+        }
     }
-    P.out[(size_t)(i1 * P.cnt[1] + i2) * P.opitch + i3 + P.ooff] = I * P.scale;
 }
 
 __global__ __launch_bounds__(kDirectThreads) void k_recombine_direct(RecombParams P)
@@ -1444,8 +1478,9 @@ hipError_t launch_recombine_direct(const RecombParams& p, hipStream_t st)
     const unsigned long long vox = (unsigned long long)p.planes * p.cnt[1] * p.cnt[2];
     if (vox == 0) return hipSuccess;
     if (p.planes < 0 || p.planes > p.cnt[0]) return hipErrorInvalidValue;
-    if (vox >= (1ULL << 32) - kDirectThreads) return hipErrorInvalidValue;
-    return dispatch(k_recombine_direct, k_recombine_direct_merged, (unsigned)((vox + kDirectThreads - 1) / kDirectThreads),
+    constexpr unsigned long long per = (unsigned long long)kDirectThreads * kDirectVPT;
+    if (vox >= (1ULL << 32) - per) return hipErrorInvalidValue;
+    return dispatch(k_recombine_direct, k_recombine_direct_merged, (unsigned)((vox + per - 1) / per),
                     kDirectThreads, 0, st, p);
 }
 
