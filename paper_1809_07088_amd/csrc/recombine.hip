@@ -1105,12 +1105,15 @@ __device__ __forceinline__ void cmac(float2& acc, float2 a, float2 b) {
     acc.y = fmaf(a.y, b.x, acc.y);
 }
 
-template <bool MULTI, class PT>
+// NCT: the number of r3 classes when the classes are summed per residue of H3 mod q
+// (then at most kMagRowsMaxClasses, and the residue sums unroll over it), else 0.
+template <bool MULTI, int NCT, class PT>
 __device__ __forceinline__ void recombine_magnetic_rows_body(PT P, const int bx)
 {
     extern __shared__ float2 smem[];
     __shared__ int cls[kMaxSites + 1];
     __shared__ float2 t1s[kMaxSites];
+    __shared__ float2 phq[NCT > 0 ? NCT * NCT : 1];   // [j][c]: e^{2 pi i H3_j r_c3}, H3_j of residue j
     BlockWork w;
     if (!decode_block(P, w, bx)) return;
     const int n1 = P.n1, n2 = P.n2, n3 = P.n3, nh = P.nh, S = P.S, NC = P.nclass, q = P.qmod;
@@ -1201,26 +1204,33 @@ __device__ __forceinline__ void recombine_magnetic_rows_body(PT P, const int bx)
         }
         __syncthreads();
         // classes summed per residue of H3 mod q, in place: one (row, comp, k3) per
-        // thread reads its classes' D, then writes E over the first q of them
-        if (q > 0) {
+        // thread reads its NCT classes' D, then writes E over the first q of them (the
+        // block's q x NCT phases staged once; a residue with no H3 in the box stays 0)
+        if constexpr (NCT > 0) {
+            if (m == 0) {
+                for (int t = threadIdx.x; t < NCT * NCT; t += blockDim.x) {
+                    const int j = t / NCT, c = t - j * NCT;
+                    const int h = P.H3min + ((j - P.H3min) % q + q) % q;   // an H3 of residue j
+                    phq[t] = (j < q && h - P.H3min < P.nH3span) ? tH0[c * P.nH3span + h] : make_float2(0.f, 0.f);
+                }
+                __syncthreads();
+            }
             for (int idx = threadIdx.x; idx < rows * 3 * n3; idx += blockDim.x) {
                 const int rc = qdiv_r(idx, n3, rn3);
                 const int kk = idx - rc * n3;
                 const int r = rc / 3, comp = rc - 3 * r;
-                float2* d = D + (size_t)r * NC * 3 * n3 + comp * n3 + kk;
-                float2 dv[kMagRowsMaxClasses];
+                float2* d = D + (size_t)r * NCT * 3 * n3 + comp * n3 + kk;
+                float2 dv[NCT];
 #pragma unroll
-                for (int c = 0; c < kMagRowsMaxClasses; ++c) dv[c] = c < NC ? d[c * 3 * n3] : make_float2(0.f, 0.f);
+                for (int c = 0; c < NCT; ++c) dv[c] = d[c * 3 * n3];
 #pragma unroll
-                for (int j = 0; j < kMagRowsMaxClasses; ++j) {
-                    if (j >= q) break;
-                    const int h = P.H3min + ((j - P.H3min) % q + q) % q;   // an H3 of residue j
-                    if (h - P.H3min >= P.nH3span) continue;
-                    float2 acc = make_float2(0.f, 0.f);
+                for (int j = 0; j < NCT; ++j) {
+                    if (j < q) {
+                        float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
-                    for (int c = 0; c < kMagRowsMaxClasses; ++c)
-                        if (c < NC) cmac(acc, tH0[c * P.nH3span + h], dv[c]);
-                    d[j * 3 * n3] = acc;
+                        for (int c = 0; c < NCT; ++c) cmac(acc, phq[j * NCT + c], dv[c]);
+                        d[j * 3 * n3] = acc;
+                    }
                 }
             }
             __syncthreads();
@@ -1236,7 +1246,7 @@ __device__ __forceinline__ void recombine_magnetic_rows_body(PT P, const int bx)
                 const float q2 = qx * qx + qy * qy + qz * qz;
                 const float s2 = q2 * inv16pi2;
                 float2 F[3];
-                if (q > 0) {
+                if (NCT > 0) {
                     const float2* e = D + ((size_t)(r * NC + jq) * 3) * n3 + k3;
 #pragma unroll
                     for (int comp = 0; comp < 3; ++comp) F[comp] = e[comp * n3];
@@ -1297,27 +1307,45 @@ __device__ __forceinline__ void recombine_magnetic_rows_body(PT P, const int bx)
     }
 }
 
-template <bool MULTI>
-__global__ __launch_bounds__(kMagRowsMaxThreads) void k_recombine_magnetic_rows(RecombParams P) { recombine_magnetic_rows_body<MULTI, RecombParams>(P, blockIdx.x); }
-template <bool MULTI>
+template <bool MULTI, int NCT>
+__global__ __launch_bounds__(kMagRowsMaxThreads) void k_recombine_magnetic_rows(RecombParams P) { recombine_magnetic_rows_body<MULTI, NCT, RecombParams>(P, blockIdx.x); }
+template <bool MULTI, int NCT>
 __global__ __launch_bounds__(kMagRowsMaxThreads) void k_recombine_magnetic_rows_merged(const RecombParams* __restrict__ tab, const Slot* __restrict__ slots)
 {
     int d, bx;
-    if (slot_of(slots, d, bx)) recombine_magnetic_rows_body<MULTI, const RecombParams&>(tab[d], bx);
+    if (slot_of(slots, d, bx)) recombine_magnetic_rows_body<MULTI, NCT, const RecombParams&>(tab[d], bx);
+}
+
+template <bool MULTI, int NCT>
+static hipError_t launch_mag_rows_v(const RecombParams& p, int block, size_t lds, hipStream_t st)
+{
+    hipError_t e = set_lds(k_recombine_magnetic_rows<MULTI, NCT>, lds);
+    if (e != hipSuccess) return e;
+    return dispatch(k_recombine_magnetic_rows<MULTI, NCT>, k_recombine_magnetic_rows_merged<MULTI, NCT>, p.nwork, block,
+                    lds, st, p);
+}
+
+template <bool MULTI>
+static hipError_t launch_mag_rows(const RecombParams& p, int block, size_t lds, hipStream_t st)
+{
+    // residue sums for up to four classes (the unrolled sums keep the block's q x NC
+    // phases in registers); more classes, or no residue grid, take level C per class,
+    // which is exact for any q
+    if (p.qmod <= 0 || p.nclass > 4) return launch_mag_rows_v<MULTI, 0>(p, block, lds, st);
+    switch (p.nclass) {
+        case 1: return launch_mag_rows_v<MULTI, 1>(p, block, lds, st);
+        case 2: return launch_mag_rows_v<MULTI, 2>(p, block, lds, st);
+        case 3: return launch_mag_rows_v<MULTI, 3>(p, block, lds, st);
+        default: return launch_mag_rows_v<MULTI, 4>(p, block, lds, st);
+    }
 }
 
 hipError_t launch_recombine_magnetic_rows(const RecombParams& p, int block, size_t lds, hipStream_t st)
 {
     if (p.nwork <= 0) return hipSuccess;
     if (block < p.cnt[2] || block > kMagRowsMaxThreads || p.rows > kMagRowsMaxRows) return hipErrorInvalidValue;
-    if (p.M > 1) {
-        hipError_t e = set_lds(k_recombine_magnetic_rows<true>, lds);
-        if (e != hipSuccess) return e;
-        return dispatch(k_recombine_magnetic_rows<true>, k_recombine_magnetic_rows_merged<true>, p.nwork, block, lds, st, p);
-    }
-    hipError_t e = set_lds(k_recombine_magnetic_rows<false>, lds);
-    if (e != hipSuccess) return e;
-    return dispatch(k_recombine_magnetic_rows<false>, k_recombine_magnetic_rows_merged<false>, p.nwork, block, lds, st, p);
+    if (p.qmod > 0 && (p.qmod > p.nclass || p.nclass > kMagRowsMaxClasses)) return hipErrorInvalidValue;
+    return p.M > 1 ? launch_mag_rows<true>(p, block, lds, st) : launch_mag_rows<false>(p, block, lds, st);
 }
 
 template <int N, int HC, bool MULTI, bool PAR>

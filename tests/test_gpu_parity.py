@@ -141,6 +141,22 @@ def test_magnetic_random_noncubic_full_box():
     assert_parity(I, ref)
 
 
+@pytest.mark.parametrize("r3s,M", [((0.0,), 1), ((0.0, 0.5), 2), ((0.0, 1 / 3, 2 / 3), 1), ((0.0, 0.25, 0.5, 0.75), 2),
+                                   ((0.0, 1 / 6, 1 / 3, 0.5, 2 / 3, 5 / 6), 1)])
+def test_magnetic_class_residue_sums(r3s, M):
+    """Sites whose r3 lie on a 1/q grid: the row-staged magnetic form sums the r3 classes per
+    residue of H3 mod q (unrolled up to four classes; six classes take level C per class)."""
+    S = 2 * len(r3s)
+    m = synth.random_model(410 + len(r3s), n=(6, 5, 6), S=S, M=M, kind=synth.MAGNETIC,
+                           cell=[6.0, 6.5, 7.0, 90.0, 90.0, 90.0])
+    m.frac[:, 2] = np.repeat(np.asarray(r3s), 2)      # two sites per class
+    m.g0, m.count = (-7, -6, -13), (15, 13, 27)
+    say(f"magnetic residue sums: {len(r3s)} classes, M={M}")
+    I = gpu_intensity(m)
+    ref = O.intensity(m, O.grid_points(m.g0, m.count)).reshape(m.count)
+    assert_parity(I, ref)
+
+
 def test_magnetic_per_site_form_factors():
     m = synth.random_model(401, n=(4, 4, 5), S=3, M=1, kind=synth.MAGNETIC,
                            cell=[6.0, 6.0, 6.0, 90.0, 90.0, 90.0])
