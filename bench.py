@@ -65,7 +65,8 @@ COPY_PROBE_BYTES = 256 << 20     # plain device copy of known size, read + write
 def kernel_source_hash():
     """Hash of the kernel sources: stored traces and traffic are only used while it matches."""
     h = hashlib.sha256()
-    for src in ("recombine.hip", "fft.hip", "lanczos.hip"):
+    for src in ("recombine.hip", "recombine_o0.hip", "recombine_o5.hip", "recombine_o7.hip", "recombine_o9.hip",
+                "fft.hip", "lanczos.hip"):
         with open(os.path.join(ROOT, "paper_1809_07088_amd", "csrc", src), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

@@ -20,7 +20,8 @@ ARCH = "gfx950"
 COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-Wall"]
-SOURCES = ["api.cpp", "fft.hip", "recombine.hip", "lanczos.hip"]
+SOURCES = ["api.cpp", "fft.hip", "recombine.hip", "recombine_o0.hip", "recombine_o5.hip", "recombine_o7.hip",
+           "recombine_o9.hip", "lanczos.hip"]
 
 
 def _compile(src):

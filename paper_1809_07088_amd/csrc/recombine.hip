@@ -816,6 +816,81 @@ void k_recombine_folded_merged(const RecombParams* __restrict__ tab, const Slot*
     if (slot_of(slots, d, bx)) recombine_folded_body<N, HC, MULTI, PAR, const RecombParams&>(tab[d], bx);
 }
 
+// ---------------------------------------------------------------------------- nuclear launchers
+// The nuclear and folded forms are instantiated per Taylor order in the recombine_o*.hip
+// units (explicit instantiations of launch_nuc_hc / launch_nuc_hi), which include this file
+// with DSX_RECOMBINE_PART defined and compile in parallel; this unit declares them extern.
+template <typename K>
+static hipError_t set_lds(K kernel, size_t lds)
+{
+    if (lds <= 65536) return hipSuccess;
+    return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <int N, int HC, bool MULTI, bool PAR>
+static hipError_t launch_nuc_v(const RecombParams& p, int block, size_t lds, hipStream_t st)
+{
+    hipError_t e = set_lds(k_recombine_nuclear<N, HC, MULTI, PAR>, lds);
+    if (e != hipSuccess) return e;
+    return dispatch(k_recombine_nuclear<N, HC, MULTI, PAR>, k_recombine_nuclear_merged<N, HC, MULTI, PAR>, p.nwork,
+                    block, lds, st, p);
+}
+
+template <int N, int HC, bool MULTI, bool PAR>
+static hipError_t launch_fold_v(const RecombParams& p, int block, size_t lds, hipStream_t st)
+{
+    hipError_t e = set_lds(k_recombine_folded<N, HC, MULTI, PAR>, lds);
+    if (e != hipSuccess) return e;
+    return dispatch(k_recombine_folded<N, HC, MULTI, PAR>, k_recombine_folded_merged<N, HC, MULTI, PAR>, p.nwork,
+                    block, lds, st, p);
+}
+
+template <int N, int HC>
+static hipError_t launch_nuc(const RecombParams& p, int block, size_t lds, hipStream_t st)
+{
+    const bool multi = p.M > 1 || p.variant == 1;
+    const bool par = p.parity != 0 && p.variant != 2;
+    if (p.fold) {
+        if (multi) return par ? launch_fold_v<N, HC, true, true>(p, block, lds, st)
+                              : launch_fold_v<N, HC, true, false>(p, block, lds, st);
+        return par ? launch_fold_v<N, HC, false, true>(p, block, lds, st)
+                   : launch_fold_v<N, HC, false, false>(p, block, lds, st);
+    }
+    if (multi) return par ? launch_nuc_v<N, HC, true, true>(p, block, lds, st)
+                          : launch_nuc_v<N, HC, true, false>(p, block, lds, st);
+    return par ? launch_nuc_v<N, HC, false, true>(p, block, lds, st)
+               : launch_nuc_v<N, HC, false, false>(p, block, lds, st);
+}
+
+template <int N>
+hipError_t launch_nuc_hc(const RecombParams& p, int hc, int block, size_t lds, hipStream_t st)
+{
+    switch (hc) {
+        case 4: return launch_nuc<N, 4>(p, block, lds, st);
+        case 8: return launch_nuc<N, 8>(p, block, lds, st);
+        case 17: return launch_nuc<N, 17>(p, block, lds, st);
+        case 32: return launch_nuc<N, 32>(p, block, lds, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// Orders above kMaxOrderFast: the class form (no folding, no parity sets), H3 runs of 4 or 8.
+template <int N>
+hipError_t launch_nuc_hi(const RecombParams& p, int hc, int block, size_t lds, hipStream_t st)
+{
+    if (p.fold || p.parity) return hipErrorInvalidValue;
+    const bool multi = p.M > 1 || p.variant == 1;
+    switch (hc) {
+        case 4: return multi ? launch_nuc_v<N, 4, true, false>(p, block, lds, st)
+                             : launch_nuc_v<N, 4, false, false>(p, block, lds, st);
+        case 8: return multi ? launch_nuc_v<N, 8, true, false>(p, block, lds, st)
+                             : launch_nuc_v<N, 8, false, false>(p, block, lds, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+#ifndef DSX_RECOMBINE_PART
+
 // ---------------------------------------------------------------------------- magnetic
 // the form factor f_mag of Eq. mag_sf
 __device__ __forceinline__ float mag_ff(const float* f, float s2) { return site_ff(f, s2); }
@@ -1070,12 +1145,6 @@ int recombine_max_threads(int hc, int magnetic)
     return 512;
 }
 
-template <typename K>
-static hipError_t set_lds(K kernel, size_t lds)
-{
-    if (lds <= 65536) return hipSuccess;
-    return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-}
 
 // Row-staged form of the magnetic recombination (sites without a Debye-Waller factor).
 // A block takes rows h2a..h2b of column (k1, k2) in plane G1; its threads cover the
@@ -1348,68 +1417,6 @@ hipError_t launch_recombine_magnetic_rows(const RecombParams& p, int block, size
     return p.M > 1 ? launch_mag_rows<true>(p, block, lds, st) : launch_mag_rows<false>(p, block, lds, st);
 }
 
-template <int N, int HC, bool MULTI, bool PAR>
-static hipError_t launch_nuc_v(const RecombParams& p, int block, size_t lds, hipStream_t st)
-{
-    hipError_t e = set_lds(k_recombine_nuclear<N, HC, MULTI, PAR>, lds);
-    if (e != hipSuccess) return e;
-    return dispatch(k_recombine_nuclear<N, HC, MULTI, PAR>, k_recombine_nuclear_merged<N, HC, MULTI, PAR>, p.nwork,
-                    block, lds, st, p);
-}
-
-template <int N, int HC, bool MULTI, bool PAR>
-static hipError_t launch_fold_v(const RecombParams& p, int block, size_t lds, hipStream_t st)
-{
-    hipError_t e = set_lds(k_recombine_folded<N, HC, MULTI, PAR>, lds);
-    if (e != hipSuccess) return e;
-    return dispatch(k_recombine_folded<N, HC, MULTI, PAR>, k_recombine_folded_merged<N, HC, MULTI, PAR>, p.nwork,
-                    block, lds, st, p);
-}
-
-template <int N, int HC>
-static hipError_t launch_nuc(const RecombParams& p, int block, size_t lds, hipStream_t st)
-{
-    const bool multi = p.M > 1 || p.variant == 1;
-    const bool par = p.parity != 0 && p.variant != 2;
-    if (p.fold) {
-        if (multi) return par ? launch_fold_v<N, HC, true, true>(p, block, lds, st)
-                              : launch_fold_v<N, HC, true, false>(p, block, lds, st);
-        return par ? launch_fold_v<N, HC, false, true>(p, block, lds, st)
-                   : launch_fold_v<N, HC, false, false>(p, block, lds, st);
-    }
-    if (multi) return par ? launch_nuc_v<N, HC, true, true>(p, block, lds, st)
-                          : launch_nuc_v<N, HC, true, false>(p, block, lds, st);
-    return par ? launch_nuc_v<N, HC, false, true>(p, block, lds, st)
-               : launch_nuc_v<N, HC, false, false>(p, block, lds, st);
-}
-
-template <int N>
-static hipError_t launch_nuc_hc(const RecombParams& p, int hc, int block, size_t lds, hipStream_t st)
-{
-    switch (hc) {
-        case 4: return launch_nuc<N, 4>(p, block, lds, st);
-        case 8: return launch_nuc<N, 8>(p, block, lds, st);
-        case 17: return launch_nuc<N, 17>(p, block, lds, st);
-        case 32: return launch_nuc<N, 32>(p, block, lds, st);
-        default: return hipErrorInvalidValue;
-    }
-}
-
-// Orders above kMaxOrderFast: the class form (no folding, no parity sets), H3 runs of 4 or 8.
-template <int N>
-static hipError_t launch_nuc_hi(const RecombParams& p, int hc, int block, size_t lds, hipStream_t st)
-{
-    if (p.fold || p.parity) return hipErrorInvalidValue;
-    const bool multi = p.M > 1 || p.variant == 1;
-    switch (hc) {
-        case 4: return multi ? launch_nuc_v<N, 4, true, false>(p, block, lds, st)
-                             : launch_nuc_v<N, 4, false, false>(p, block, lds, st);
-        case 8: return multi ? launch_nuc_v<N, 8, true, false>(p, block, lds, st)
-                             : launch_nuc_v<N, 8, false, false>(p, block, lds, st);
-        default: return hipErrorInvalidValue;
-    }
-}
-
 // ---------------------------------------------------------------------------- direct form
 // Taylor order 0 (occupancies only, one field per site): every voxel is computed on its
 // own, F_m(G) = sum_mu b_mu e^{2 pi i g.r_mu} X_mu,m(k), I(G) = scale sum_m |F_m(G)|^2.
@@ -1511,6 +1518,25 @@ hipError_t launch_recombine_direct(const RecombParams& p, hipStream_t st)
     return dispatch(k_recombine_direct, k_recombine_direct_merged, (unsigned)((vox + per - 1) / per),
                     kDirectThreads, 0, st, p);
 }
+
+// instantiated in recombine_o*.hip
+extern template hipError_t launch_nuc_hc<0>(const RecombParams&, int, int, size_t, hipStream_t);
+extern template hipError_t launch_nuc_hc<1>(const RecombParams&, int, int, size_t, hipStream_t);
+extern template hipError_t launch_nuc_hc<2>(const RecombParams&, int, int, size_t, hipStream_t);
+extern template hipError_t launch_nuc_hc<3>(const RecombParams&, int, int, size_t, hipStream_t);
+extern template hipError_t launch_nuc_hc<4>(const RecombParams&, int, int, size_t, hipStream_t);
+extern template hipError_t launch_nuc_hc<5>(const RecombParams&, int, int, size_t, hipStream_t);
+extern template hipError_t launch_nuc_hc<6>(const RecombParams&, int, int, size_t, hipStream_t);
+extern template hipError_t launch_nuc_hc<7>(const RecombParams&, int, int, size_t, hipStream_t);
+extern template hipError_t launch_nuc_hc<8>(const RecombParams&, int, int, size_t, hipStream_t);
+extern template hipError_t launch_nuc_hi<9>(const RecombParams&, int, int, size_t, hipStream_t);
+extern template hipError_t launch_nuc_hi<10>(const RecombParams&, int, int, size_t, hipStream_t);
+extern template hipError_t launch_nuc_hi<11>(const RecombParams&, int, int, size_t, hipStream_t);
+extern template hipError_t launch_nuc_hi<12>(const RecombParams&, int, int, size_t, hipStream_t);
+extern template hipError_t launch_nuc_hi<13>(const RecombParams&, int, int, size_t, hipStream_t);
+extern template hipError_t launch_nuc_hi<14>(const RecombParams&, int, int, size_t, hipStream_t);
+extern template hipError_t launch_nuc_hi<15>(const RecombParams&, int, int, size_t, hipStream_t);
+extern template hipError_t launch_nuc_hi<16>(const RecombParams&, int, int, size_t, hipStream_t);
 
 hipError_t launch_recombine_nuclear(const RecombParams& p, int order, int hc, int block,
                                     size_t lds, hipStream_t st)
@@ -1847,5 +1873,7 @@ hipError_t launch_dw_mean(const DwParams& p, hipStream_t st)
 {
     return dispatch(k_dw_mean, k_dw_mean_merged, (p.S * p.T + 255) / 256, 256, 0, st, p);
 }
+
+#endif  // DSX_RECOMBINE_PART
 
 }  // namespace dsx
