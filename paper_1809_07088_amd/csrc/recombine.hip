@@ -41,6 +41,8 @@
 // float64 lattice sums (k_bragg_*), where the Bragg subtraction |<F>|^2 cancels
 // most of |F|^2 (Sec. II, Eq. bragg_diffuse_sf; Sec. III.A, Eq. bragg_sf); the
 // ensemble mean <F> is the mean over the model's configurations.
+#include <type_traits>
+
 #include "dsx_internal.h"
 
 namespace dsx {
@@ -731,14 +733,19 @@ __device__ __forceinline__ void recombine_folded_body(PT P, const int bx)
         for (int q = 1; q <= N; ++q) a2[q] = a2[q - 1] * tau2 * (1.f / (float)q);
 #pragma unroll
         for (int h = 0; h < NF; ++h) F[h] = make_float2(0.f, 0.f);
-#pragma unroll
-        for (int r = 0; r <= N; ++r) { DE[r] = make_float2(0.f, 0.f); DO[r] = make_float2(0.f, 0.f); }
         // (every lane: an inactive one evaluates a valid item of its block whose values are
         // never written, which keeps the wave free of merges)
-        {
-            for (int c = 0; c < P.nclass; ++c) {
+        // Parity form: DE / DO are the coefficient sets of the even / odd h of the thread's
+        // run (H3 = H3lo + hbeg + h), so class c enters them with e^{2 pi i H3 r_c3} =
+        // sgn_c^H3 split as sgn_c^(H3lo + hbeg) (the weight wa) times sgn_c^h (wb = wa sgn_c
+        // for odd h); the first class initialises the sets.
+        const bool odd0 = ((H3lo + hbeg) & 1) != 0;
+        auto level_b = [&](int c, auto first_tag) {
+            constexpr bool FIRST = decltype(first_tag)::value;
+            {
                 const float2* Bp = Bs + ((size_t)(c * L2 + rho) * n3s + (k3 - k3a)) * QR;
                 const float sgn = PAR ? (float)P.class_sign[c] : 1.f;
+                const float wa = odd0 ? sgn : 1.f, wb = odd0 ? 1.f : sgn;
                 float2 D[PAR ? 1 : N + 1];
 #pragma unroll
                 for (int r = 0; r <= N; ++r) {
@@ -754,8 +761,13 @@ __device__ __forceinline__ void recombine_folded_body(PT P, const int bx)
                         else { C.x += a * v.y; C.y -= a * v.x; }
                     }
                     if constexpr (PAR) {
-                        DE[r].x += C.x; DE[r].y += C.y;
-                        DO[r].x += sgn * C.x; DO[r].y += sgn * C.y;
+                        if constexpr (FIRST) {
+                            DE[r] = make_float2(wa * C.x, wa * C.y);
+                            DO[r] = make_float2(wb * C.x, wb * C.y);
+                        } else {
+                            DE[r].x = fmaf(wa, C.x, DE[r].x); DE[r].y = fmaf(wa, C.y, DE[r].y);
+                            DO[r].x = fmaf(wb, C.x, DO[r].x); DO[r].y = fmaf(wb, C.y, DO[r].y);
+                        }
                     } else {
                         D[r] = C;
                     }
@@ -778,10 +790,15 @@ __device__ __forceinline__ void recombine_folded_body(PT P, const int bx)
                     }
                 }
             }
+        };
+        if constexpr (PAR) {
+            level_b(0, std::true_type{});
+            for (int c = 1; c < P.nclass; ++c) level_b(c, std::false_type{});
+        } else {
+            for (int c = 0; c < P.nclass; ++c) level_b(c, std::false_type{});
         }
         if constexpr (MULTI) {
             if constexpr (PAR) {
-                parity_order<N>(DE, DO, H3lo + hbeg);
 #pragma unroll
                 for (int h = 0; h < HC; ++h)
                     if (h < hmin || h < hcnt) I[h] += parity_eval<N>((h & 1) ? DO : DE, t3base + (float)h * dt3);
@@ -795,7 +812,6 @@ __device__ __forceinline__ void recombine_folded_body(PT P, const int bx)
     const int i3b = k3 + n3 * (H3lo + hbeg) - P.g0[2];       // output index of h = 0
     const RowOut ro = row_out(P, w, i2, i3b);
     const bool full = __ballot(active) == ~0ull;
-    if constexpr (PAR && !MULTI) parity_order<N>(DE, DO, H3lo + hbeg);
     auto val = [&](int h) -> float {
         if constexpr (MULTI) return I[h];
         else if constexpr (PAR) return parity_eval<N>((h & 1) ? DO : DE, t3base + (float)h * dt3);
