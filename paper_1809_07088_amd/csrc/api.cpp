@@ -282,7 +282,7 @@ struct DeviceTables {
     int nwork = 0, nwork2 = 0, nwork3 = 0, hc = 0, nchunk3 = 0, block = 0;
     int n3s = 0, block3 = 0;   // k3 per slice, threads per plane of a sliced block
     int4* work_mr = nullptr;   // magnetic models: blocks of the row-staged form (null: not used)
-    int nwork_mr = 0, rows_mr = 0, csites_mr = 0, qmod_mr = 0;
+    int nwork_mr = 0, rows_mr = 0, csites_mr = 0, qmod_mr = 0, qmod2_mr = 0, qmod1_mr = 0;
 };
 
 // Releases every device buffer of one cached box.
@@ -579,12 +579,34 @@ dsx_status tables_for(dsx_model m, const Box& bx, DeviceTables** out)
                 if (ok) { q = cand <= NC ? cand : 0; break; }
             }
         t.qmod_mr = q;
+        // rows whose H2 agree modulo q2 (every r_mu2 a multiple of 1/q2) share their site
+        // phases e^{2 pi i g2 r_mu2}, so a block stages min(rows, q2) of them only; planes
+        // whose H1 agree modulo q1 share e^{2 pi i g1 r_mu1}, and one block serves up to four
+        // of them (one configuration: the sums of several are accumulated per row)
+        auto grid_of = [&](int axis) {
+            for (int cand : {1, 2, 3, 4, 6, 8}) {
+                bool ok = true;
+                for (int i = 0; i < S && ok; ++i) {
+                    const double x = m->frac[3 * m->site_of[i] + axis] * cand;
+                    ok = std::fabs(x - std::round(x)) < 1e-9;
+                }
+                if (ok) return cand;
+            }
+            return 0;
+        };
+        const int q2 = grid_of(1);
+        t.qmod2_mr = q2;
+        t.qmod1_mr = m->M == 1 ? grid_of(0) : 0;
         int cs = S;
         while (cs > 1 && (size_t)cs * 3 * n3 * sizeof(float2) > 12 * 1024) cs = (cs + 1) / 2;
         const size_t budget = 48 * 1024 / sizeof(float2);
         const size_t fixed = magnetic_rows_lds_elems(0, cs, S, NC, n3, t.nH3span);
         const size_t per_row = magnetic_rows_lds_elems(1, 0, S, NC, n3, 0) - (size_t)S * n3;
-        int rows = fixed < budget ? (int)((budget - fixed) / per_row) : 0;
+        int rows;
+        if (q2 > 0)
+            rows = fixed + std::min(q2, kMagRowsMaxRows) * per_row <= budget ? kMagRowsMaxRows : 0;
+        else
+            rows = fixed < budget ? (int)((budget - fixed) / per_row) : 0;
         rows = std::min(std::min(rows, kMagRowsMaxRows), maxH2);
         if (rows >= 1) { t.rows_mr = rows; t.csites_mr = cs; }
     }
@@ -622,13 +644,34 @@ dsx_status tables_for(dsx_model m, const Box& bx, DeviceTables** out)
             if (t.rows_mr > 0) {
                 const int npm = (nH2 + t.rows_mr - 1) / t.rows_mr;
                 const int rpm = (nH2 + npm - 1) / npm;
+                // planes grouped by the residue of H1 mod q1, at most four a group, in H1 order
+                std::vector<std::vector<std::pair<int, int>>> groups;
+                if (t.qmod1_mr > 0) {
+                    const int q1 = t.qmod1_mr;
+                    for (int res = 0; res < q1; ++res) {
+                        std::vector<std::pair<int, int>> g;
+                        for (const auto& pl : planes)
+                            if (pl.first % q1 == res) {
+                                // a group's planes are j1, j1 + q1, ... (the kernel steps G1 by q1 n1)
+                                if (g.size() == 4 || (!g.empty() && pl.first != g.back().first + q1)) {
+                                    groups.push_back(g);
+                                    g.clear();
+                                }
+                                g.push_back(pl);
+                            }
+                        if (!g.empty()) groups.push_back(g);
+                    }
+                } else {
+                    for (const auto& pl : planes) groups.push_back({pl});
+                }
                 for (int part = 0; part < npm; ++part) {
                     const int h2a = part * rpm, h2b = std::min(nH2, h2a + rpm);
                     if (h2a >= h2b) continue;
-                    for (size_t i = 0; i < planes.size(); ++i) {
-                        const int G1 = k1 + n1 * (H1lo + planes[i].first);
-                        items_mr.push_back({key * 4096 + planes[i].first,
-                                            make_int4(k1, k2, G1, h2a | (h2b << 12) | (planes[i].second << 24))});
+                    for (const auto& g : groups) {
+                        const int G1 = k1 + n1 * (H1lo + g[0].first);
+                        int wv = h2a | (h2b << 12) | ((int)(g.size() - 1) << 28);
+                        for (size_t p = 0; p < g.size(); ++p) wv |= g[p].second << (24 + p);
+                        items_mr.push_back({key * 4096 + g[0].first, make_int4(k1, k2, G1, wv)});
                     }
                 }
             }
@@ -796,6 +839,13 @@ dsx_status plan_recombine(dsx_model m, const Box& bx, float* out, const Layout& 
             if (m->has_ff && m->ff[8 * mu + k] != m->ff[k]) p.ff_uniform = 0;
         }
     }
+    {
+        const double* R = m->recip;
+        auto dot = [R](int a, int b) { return R[3 * a] * R[3 * b] + R[3 * a + 1] * R[3 * b + 1] + R[3 * a + 2] * R[3 * b + 2]; };
+        const double tol = 1e-12 * dot(1, 1);
+        p.ff_sep = (p.ff_uniform && std::fabs(dot(0, 1)) <= tol * std::sqrt(dot(0, 0) / dot(1, 1)) &&
+                    std::fabs(dot(2, 1)) <= tol * std::sqrt(dot(2, 2) / dot(1, 1))) ? 1 : 0;
+    }
     if (m->dw_order > 0) {
         p.dwc = m->d_dwc;
         p.dw_order = m->dw_order;
@@ -818,8 +868,11 @@ dsx_status plan_recombine(dsx_model m, const Box& bx, float* out, const Layout& 
         p.rows = tb->rows_mr;
         p.csites = tb->csites_mr;
         p.qmod = tb->qmod_mr;
+        p.qmod2 = tb->qmod2_mr;
+        p.qmod1 = tb->qmod1_mr;
         lp.block = std::max(64, (bx.cnt[2] + 63) / 64 * 64);
-        lp.lds = sizeof(float2) * magnetic_rows_lds_elems(tb->rows_mr, tb->csites_mr, m->S, m->nclass, n3, tb->nH3span);
+        const int staged = tb->qmod2_mr > 0 ? std::min(tb->rows_mr, tb->qmod2_mr) : tb->rows_mr;
+        lp.lds = sizeof(float2) * magnetic_rows_lds_elems(staged, tb->csites_mr, m->S, m->nclass, n3, tb->nH3span);
     }
     // direct form: asked for, or by default where the levelled forms would spend their
     // blocks on set-up (one or two sites x configurations)

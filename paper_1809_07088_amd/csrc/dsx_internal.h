@@ -132,6 +132,9 @@ struct RecombParams {
     // magnetic only
     float recip[9];         // rows a*, b*, c* (inverse Angstrom)
     int32_t ff_uniform;     // 1 when every site has the same form factor
+    int32_t ff_sep;         // 1 when, besides, b* is orthogonal to a* and c*: |Q|^2 is then a
+                            // part of (g1, g3) plus a part of g2, and each Gaussian of the form
+                            // factor a product of the two parts' exponentials
     float ff[kMaxSites][8];  // per sorted position: form factor (7), unused
     // Debye-Waller factor T_mu(G) of magnetic sites with displacements: dwc[mu][t] the
     // mean over occupied atoms and configurations of u1^p u2^q u3^r (monomial t,
@@ -146,6 +149,13 @@ struct RecombParams {
     int32_t rows, csites;
     int32_t qmod;           // > 0: every r_c3 a multiple of 1/qmod and one form factor for all
                             // sites: the classes are summed per residue of H3 mod qmod
+    int32_t qmod2;          // > 0: every r_mu2 a multiple of 1/qmod2: rows whose H2 agree mod
+                            // qmod2 have the same site phases, so levels B and the residue sums
+                            // run on the first min(rows, qmod2) rows of a block only
+    int32_t qmod1;          // > 0: every r_mu1 a multiple of 1/qmod1: G1 planes of one column whose
+                            // H1 agree mod qmod1 have the same site phases; a work item then
+                            // covers 1 + ((w >> 28) & 3) planes G1 + p qmod1 n1, plane p mirrored
+                            // when bit 24 + p of w is set (one configuration only)
     int32_t planes;         // direct form: the planes i1 < planes are computed (a half-stored
                             // box holds its planes G1 <= 0 only)
 };
@@ -277,7 +287,8 @@ constexpr int kMagRowsMaxThreads = 512;
 constexpr int kMagRowsMaxRows = 16;
 constexpr int kMagRowsMaxClasses = 8;   // the per-residue class sums need q <= nclass <= this
 hipError_t launch_recombine_magnetic_rows(const RecombParams& p, int block, size_t lds, hipStream_t st);
-// float2 elements of its LDS for rows, site chunks of csites, S sites, nclass classes
+// float2 elements of its LDS for `rows` staged rows (a block's rows, or min(rows, qmod2)),
+// site chunks of csites, S sites, nclass classes
 inline size_t magnetic_rows_lds_elems(int rows, int csites, int S, int nclass, int n3, int nH3span)
 {
     return (size_t)rows * nclass * 3 * n3 + (size_t)S * n3 + (size_t)rows * S + (size_t)nclass * nH3span

@@ -1163,13 +1163,18 @@ int recombine_max_threads(int hc, int magnetic)
 
 
 // Row-staged form of the magnetic recombination (sites without a Debye-Waller factor).
-// A block takes rows h2a..h2b of column (k1, k2) in plane G1; its threads cover the
-// box's G3 (one output column each, so a row is written by consecutive threads):
+// A block takes rows h2a..h2b of column (k1, k2) in plane G1 (and, with one configuration
+// and every r_mu1 a multiple of 1/q1, in up to three more planes G1 + p q1 n1, whose site
+// phases e^{2 pi i g1 r_mu1} are plane G1's, so levels A and B serve all of them); its
+// threads cover the box's G3 (one output column each, so a row is written by consecutive
+// threads):
 //   level A  Bs[site][comp][k3] = b_mu e^{2 pi i (g1 r_mu1 + k3 r_mu3 / n3)} M_comp(k1, k2, k3),
 //            one site chunk at a time, read straight from the spin spectra of the column
 //            (k3 <= n3/2) and of its mirror (the rest, through X(k) = conj X(-k));
 //   level B  D[row][class][comp][k3] += sum over the chunk's sites of the class of
-//            e^{2 pi i g2 r_mu2} Bs; then, when every r_c3 of the classes is a multiple
+//            e^{2 pi i g2 r_mu2} Bs (when every r_mu2 is a multiple of 1/q2, rows whose
+//            H2 agree mod q2 have equal phases: the first q2 rows stand for all of
+//            them); then, when every r_c3 of the classes is a multiple
 //            of 1/q and the form factor is the same for every site, the classes are
 //            summed per residue of H3 mod q, in place (q <= nclass):
 //            E[row][j][comp][k3] = sum_c e^{2 pi i H3_j r_c3} D  (H3_j = j mod q);
@@ -1199,14 +1204,18 @@ __device__ __forceinline__ void recombine_magnetic_rows_body(PT P, const int bx)
     __shared__ int cls[kMaxSites + 1];
     __shared__ float2 t1s[kMaxSites];
     __shared__ float2 phq[NCT > 0 ? NCT * NCT : 1];   // [j][c]: e^{2 pi i H3_j r_c3}, H3_j of residue j
+    __shared__ float4 ffrow[kMagRowsMaxRows];         // separable form factor: the rows' g2 parts
     BlockWork w;
     if (!decode_block(P, w, bx)) return;
     const int n1 = P.n1, n2 = P.n2, n3 = P.n3, nh = P.nh, S = P.S, NC = P.nclass, q = P.qmod;
-    const int rows = w.h2b - w.h2a, cnt3 = P.cnt[2];
-    float2* D = smem;                              // [rows][NC][3][n3]; then E [rows][q][3][n3]
-    float2* tK3 = D + rows * NC * 3 * n3;          // [S][n3]   (sorted positions)
-    float2* t2 = tK3 + S * n3;                     // [rows][S]
-    float2* tHs = t2 + rows * S;                   // [NC][nH3span]
+    const int rows = w.h2b - w.h2a, cnt3 = P.cnt[2], q2 = P.qmod2;
+    // staged rows: with every r_mu2 a multiple of 1/q2, row r has the site phases of row
+    // r mod q2 (their H2 differ by a multiple of q2), so only the first q2 are staged
+    const int rowsB = q2 > 0 ? min(rows, q2) : rows;
+    float2* D = smem;                              // [rowsB][NC][3][n3]; then E [rowsB][q][3][n3]
+    float2* tK3 = D + rowsB * NC * 3 * n3;         // [S][n3]   (sorted positions)
+    float2* t2 = tK3 + S * n3;                     // [rowsB][S]
+    float2* tHs = t2 + rowsB * S;                  // [NC][nH3span]
     float2* Bs = tHs + NC * P.nH3span;             // [csites][3][n3]
     const float2* tH0 = stage_class_phases(P, tHs);
     const float rn3 = 1.f / (float)n3, rS = 1.f / (float)S, rNC = 1.f / (float)NC;
@@ -1214,7 +1223,7 @@ __device__ __forceinline__ void recombine_magnetic_rows_body(PT P, const int bx)
         const int i = qdiv_r(idx, n3, rn3), k = idx - i * n3;
         tK3[idx] = P.tabK3[(size_t)P.site_of[i] * n3 + k];
     }
-    for (int idx = threadIdx.x; idx < rows * S; idx += blockDim.x) {
+    for (int idx = threadIdx.x; idx < rowsB * S; idx += blockDim.x) {
         const int r = qdiv_r(idx, S, rS), i = idx - r * S;
         const int i2 = w.k2 + n2 * (w.H2lo + w.h2a + r) - P.g0[1];
         t2[idx] = P.tab2[(size_t)P.site_of[i] * P.cnt[1] + i2];
@@ -1232,15 +1241,24 @@ __device__ __forceinline__ void recombine_magnetic_rows_body(PT P, const int bx)
     const int k3 = G3 - n3 * H3;
     const int jq = q > 0 ? H3 - q * floordiv(H3, q) : 0;
     const float inv16pi2 = 1.f / (16.f * 9.8696044010893586f);
-    const float g1 = (float)((double)w.G1 / (double)n1);
     const float g3 = (float)((double)G3 / (double)n3);
     const float rn2f = (float)(1.0 / (double)n2);
-    const float q13x = g1 * P.recip[0] + g3 * P.recip[6];
-    const float q13y = g1 * P.recip[1] + g3 * P.recip[7];
-    const float q13z = g1 * P.recip[2] + g3 * P.recip[8];
+    // the block's G1 planes (H1 agreeing mod qmod1: their site phases are plane 0's)
+    const int wbits = P.work[bx].w;
+    const int npl = 1 + ((wbits >> 28) & 3);
+    // a separable form factor: e^{-a s^2} = e^{-a |q13|^2 / 16 pi^2} e^{-a g2^2 |b*|^2 / 16 pi^2}
+    // (b* orthogonal to a* and c*), the first factor per thread and plane, the second per row
+    const bool sep = P.ff_uniform && P.ff_sep;
+    if (sep) {
+        const float* f = P.ff[0];
+        const float b2sq = P.recip[3] * P.recip[3] + P.recip[4] * P.recip[4] + P.recip[5] * P.recip[5];
+        for (int r = threadIdx.x; r < rows; r += blockDim.x) {
+            const float g2 = (float)(w.k2 + n2 * (w.H2lo + w.h2a + r)) * rn2f;
+            const float t = g2 * g2 * b2sq * inv16pi2;
+            ffrow[r] = make_float4(__expf(-f[1] * t), __expf(-f[3] * t), __expf(-f[5] * t), 0.f);
+        }
+    }
     const size_t plane = (size_t)P.cnt[1] * P.opitch;
-    float* const orow0 = P.out + P.ooff + (size_t)w.i1 * plane + i3;
-    float* const mrow0 = P.out + P.ooff + (size_t)(P.cnt[0] - 1 - w.i1) * plane + (P.cnt[2] - 1 - i3);
     float I[MULTI ? kMagRowsMaxRows : 1];
 #pragma unroll
     for (int r = 0; r < (MULTI ? kMagRowsMaxRows : 1); ++r) I[r] = 0.f;
@@ -1248,7 +1266,7 @@ __device__ __forceinline__ void recombine_magnetic_rows_body(PT P, const int bx)
     for (int m = 0; m < P.M; ++m) {
         const float2* Xm = P.X + (size_t)m * n1 * n2 * SFnh;
         __syncthreads();
-        for (int idx = threadIdx.x; idx < rows * NC * 3 * n3; idx += blockDim.x) D[idx] = make_float2(0.f, 0.f);
+        for (int idx = threadIdx.x; idx < rowsB * NC * 3 * n3; idx += blockDim.x) D[idx] = make_float2(0.f, 0.f);
         for (int s0 = 0; s0 < S; s0 += P.csites) {
             const int ns = min(P.csites, S - s0);
             __syncthreads();
@@ -1265,7 +1283,7 @@ __device__ __forceinline__ void recombine_magnetic_rows_body(PT P, const int bx)
             }
             __syncthreads();
             // level B: one (row, class, k3) per thread, the chunk's sites of the class
-            for (int idx = threadIdx.x; idx < rows * NC * n3; idx += blockDim.x) {
+            for (int idx = threadIdx.x; idx < rowsB * NC * n3; idx += blockDim.x) {
                 const int rc = qdiv_r(idx, n3, rn3);
                 const int kk = idx - rc * n3;
                 const int r = qdiv_r(rc, NC, rNC);
@@ -1300,7 +1318,7 @@ __device__ __forceinline__ void recombine_magnetic_rows_body(PT P, const int bx)
                 }
                 __syncthreads();
             }
-            for (int idx = threadIdx.x; idx < rows * 3 * n3; idx += blockDim.x) {
+            for (int idx = threadIdx.x; idx < rowsB * 3 * n3; idx += blockDim.x) {
                 const int rc = qdiv_r(idx, n3, rn3);
                 const int kk = idx - rc * n3;
                 const int r = rc / 3, comp = rc - 3 * r;
@@ -1320,9 +1338,27 @@ __device__ __forceinline__ void recombine_magnetic_rows_body(PT P, const int bx)
             }
             __syncthreads();
         }
-        // level C: the thread's column, every row
-        if (active) {
-            for (int r = 0; r < rows; ++r) {
+        // level C: the thread's column, every row of every plane of the block
+        for (int pl = 0; pl < npl && active; ++pl) {
+            const int G1 = w.G1 + pl * P.qmod1 * n1;
+            const int i1 = G1 - P.g0[0];
+            const bool mirror = (wbits >> (24 + pl)) & 1;
+            const float g1 = (float)((double)G1 / (double)n1);
+            const float q13x = g1 * P.recip[0] + g3 * P.recip[6];
+            const float q13y = g1 * P.recip[1] + g3 * P.recip[7];
+            const float q13z = g1 * P.recip[2] + g3 * P.recip[8];
+            float e13a = 0.f, e13b = 0.f, e13c = 0.f;
+            if (sep) {
+                const float* f = P.ff[0];
+                const float s13 = (q13x * q13x + q13y * q13y + q13z * q13z) * inv16pi2;
+                e13a = f[0] * __expf(-f[1] * s13);
+                e13b = f[2] * __expf(-f[3] * s13);
+                e13c = f[4] * __expf(-f[5] * s13);
+            }
+            float* const orow0 = P.out + P.ooff + (size_t)i1 * plane + i3;
+            float* const mrow0 = P.out + P.ooff + (size_t)(P.cnt[0] - 1 - i1) * plane + (P.cnt[2] - 1 - i3);
+            int rd = 0;                            // the staged row holding row r's sums
+            for (int r = 0; r < rows; ++r, rd = (rd + 1 == rowsB) ? 0 : rd + 1) {
                 const int G2 = w.k2 + n2 * (w.H2lo + w.h2a + r);
                 const float g2 = (float)G2 * rn2f;
                 const float qx = q13x + g2 * P.recip[3];
@@ -1332,13 +1368,13 @@ __device__ __forceinline__ void recombine_magnetic_rows_body(PT P, const int bx)
                 const float s2 = q2 * inv16pi2;
                 float2 F[3];
                 if (NCT > 0) {
-                    const float2* e = D + ((size_t)(r * NC + jq) * 3) * n3 + k3;
+                    const float2* e = D + ((size_t)(rd * NC + jq) * 3) * n3 + k3;
 #pragma unroll
                     for (int comp = 0; comp < 3; ++comp) F[comp] = e[comp * n3];
                 } else {
 #pragma unroll
                     for (int comp = 0; comp < 3; ++comp) F[comp] = make_float2(0.f, 0.f);
-                    const float2* d = D + (size_t)r * NC * 3 * n3 + k3;
+                    const float2* d = D + (size_t)rd * NC * 3 * n3 + k3;
                     const float2* th = tH0 + H3;
                     for (int c = 0; c < NC; ++c) {
                         float2 e3 = th[c * P.nH3span];
@@ -1359,7 +1395,11 @@ __device__ __forceinline__ void recombine_magnetic_rows_body(PT P, const int bx)
 #pragma unroll
                     for (int comp = 0; comp < 3; ++comp) val += F[comp].x * F[comp].x + F[comp].y * F[comp].y;
                     val -= px * px + py * py;
-                    if (P.ff_uniform) {
+                    if (sep) {
+                        const float4 e2 = ffrow[r];
+                        const float f = fmaf(e13a, e2.x, fmaf(e13b, e2.y, fmaf(e13c, e2.z, P.ff[0][6])));
+                        val *= f * f;
+                    } else if (P.ff_uniform) {
                         const float f = mag_ff_fast(P.ff[0], s2);
                         val *= f * f;
                     }
@@ -1372,12 +1412,15 @@ __device__ __forceinline__ void recombine_magnetic_rows_body(PT P, const int bx)
                     const int i2 = G2 - P.g0[1];
                     const float o = val * P.scale;
                     orow0[(size_t)i2 * P.opitch] = o;
-                    if (w.mirror) mrow0[(size_t)(P.cnt[1] - 1 - i2) * P.opitch] = o;
+                    if (mirror) mrow0[(size_t)(P.cnt[1] - 1 - i2) * P.opitch] = o;
                 }
             }
         }
     }
     if constexpr (MULTI) {
+        // several configurations: one plane per block (the planner groups no planes)
+        float* const orow0 = P.out + P.ooff + (size_t)w.i1 * plane + i3;
+        float* const mrow0 = P.out + P.ooff + (size_t)(P.cnt[0] - 1 - w.i1) * plane + (P.cnt[2] - 1 - i3);
         if (active) {
 #pragma unroll
             for (int r = 0; r < kMagRowsMaxRows; ++r) {
@@ -1430,6 +1473,7 @@ hipError_t launch_recombine_magnetic_rows(const RecombParams& p, int block, size
     if (p.nwork <= 0) return hipSuccess;
     if (block < p.cnt[2] || block > kMagRowsMaxThreads || p.rows > kMagRowsMaxRows) return hipErrorInvalidValue;
     if (p.qmod > 0 && (p.qmod > p.nclass || p.nclass > kMagRowsMaxClasses)) return hipErrorInvalidValue;
+    if (p.M > 1 && p.qmod1 > 0) return hipErrorInvalidValue;   // grouped planes: one configuration
     return p.M > 1 ? launch_mag_rows<true>(p, block, lds, st) : launch_mag_rows<false>(p, block, lds, st);
 }
 

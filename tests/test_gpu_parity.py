@@ -157,6 +157,32 @@ def test_magnetic_class_residue_sums(r3s, M):
     assert_parity(I, ref)
 
 
+ORTHO = [6.0, 6.5, 7.0, 90.0, 90.0, 90.0]
+TRIC = [6.0, 6.5, 7.0, 84.0, 97.0, 103.0]
+
+
+@pytest.mark.parametrize("r2s,M,cell,q1", [((0.0,), 1, ORTHO, 1), ((0.0, 0.5), 2, ORTHO, 2),
+                                           ((0.0, 0.25, 0.5, 0.75), 1, ORTHO, 2), ((0.0, 1 / 3, 2 / 3), 2, TRIC, 0),
+                                           ((0.0, 0.25, 0.5, 0.75), 1, TRIC, 4)])
+def test_magnetic_row_residues(r2s, M, cell, q1):
+    """Sites whose r2 lie on a 1/q grid: rows of a block whose H2 agree mod q have the same
+    site phases, so the row-staged magnetic form stages q rows and maps the others onto
+    them (nine rows per column here).  With r1 on a 1/q1 grid and one configuration a block
+    serves up to four G1 planes of one H1 residue (q1 = 0: random r1, one plane a block).
+    On the orthogonal cell b* is orthogonal to a* and c* and the form factor is split into
+    a per-column and a per-row part."""
+    S = 2 * len(r2s)
+    m = synth.random_model(420 + 3 * len(r2s) + M, n=(2, 3, 5), S=S, M=M, kind=synth.MAGNETIC, cell=cell)
+    m.frac[:, 1] = np.repeat(np.asarray(r2s), 2)      # two sites per r2 value
+    if q1:
+        m.frac[:, 0] = (np.arange(S) % q1) / q1
+    m.g0, m.count = (-10, -13, -8), (21, 27, 17)
+    say(f"magnetic row residues: q2={len(r2s)}, q1={q1}, M={M}, cell angles {cell[3:]}")
+    I = gpu_intensity(m)
+    ref = O.intensity(m, O.grid_points(m.g0, m.count)).reshape(m.count)
+    assert_parity(I, ref)
+
+
 def test_magnetic_per_site_form_factors():
     m = synth.random_model(401, n=(4, 4, 5), S=3, M=1, kind=synth.MAGNETIC,
                            cell=[6.0, 6.0, 6.0, 90.0, 90.0, 90.0])
