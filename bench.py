@@ -970,6 +970,37 @@ def main():
         hs.close()
         del out3, occ_dev
 
+    # one GPU's share of Q-zone sharding over eight GPUs at its real shape: the centred
+    # slab |G1| <= 32 of the same box (65 x 513 x 513, Friedel-symmetric like the whole
+    # box), with its own tuned plan; the per-voxel rate against the whole box's rate
+    # says how far one shard's kernels keep the full-box efficiency
+    shard = None
+    if not args.only_steps:
+        hq = dsx.Model(cell=model.cell, n=n, frac=model.frac, b=model.b, taylor_order=N, n_configs=M)
+        g0q = (-32, model.g0[1], model.g0[2])
+        cntq = (65, count[1], count[2])
+        hq.set_grid(g0q, cntq)
+        outq = torch.empty(cntq, dtype=torch.float32, device=dev)
+        hq.set_sites_async(0, None, disp_dev)
+        hq.autotune(lm)
+        for _ in range(3):
+            hq.set_sites_async(0, None, disp_dev)
+            hq.noise_filter(lm, 1, outq)
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        for _ in range(args.steps):
+            hq.set_sites_async(0, None, disp_dev)
+            hq.noise_filter(lm, 1, outq)
+        torch.cuda.synchronize()
+        tq = (time.perf_counter() - c0) / args.steps
+        vq = int(np.prod(cntq)) * M
+        shard = {"slab": "G1 in [-32, 32] (1 of 8 Q zones), G2 and G3 as the whole box",
+                 "voxels_per_step": vq, "ms_per_step": round(tq * 1e3, 4),
+                 "voxels_per_s": round(vq / tq, 1), "rate_vs_whole_box": round(vq / tq / value, 3),
+                 "plan": hq.tune_query(), "lanczos_m": lm}
+        hq.close()
+        del outq
+
     sweep = None
     if args.sweep:
         sweep = {}
@@ -1072,6 +1103,8 @@ def main():
         line["compute_intensity_voxels_per_s_by_order"] = sweep
     if widened is not None:
         line["widened_filter"] = widened
+    if shard is not None:
+        line["q_zone_shard"] = shard
     if magnetic is not None:
         line["magnetic"] = magnetic
     if compositional is not None:

@@ -1240,6 +1240,8 @@ __device__ __forceinline__ void recombine_magnetic_rows_body(PT P, const int bx)
     const int H3 = floordiv(G3, n3);
     const int k3 = G3 - n3 * H3;
     const int jq = q > 0 ? H3 - q * floordiv(H3, q) : 0;
+    const int ebase = jq * 3 * n3 + k3;            // the thread's residue sums within a staged row
+    const int erow = NC * 3 * n3;                  // float2 per staged row
     const float inv16pi2 = 1.f / (16.f * 9.8696044010893586f);
     const float g3 = (float)((double)G3 / (double)n3);
     const float rn2f = (float)(1.0 / (double)n2);
@@ -1368,7 +1370,7 @@ __device__ __forceinline__ void recombine_magnetic_rows_body(PT P, const int bx)
                 const float s2 = q2 * inv16pi2;
                 float2 F[3];
                 if (NCT > 0) {
-                    const float2* e = D + ((size_t)(rd * NC + jq) * 3) * n3 + k3;
+                    const float2* e = D + rd * erow + ebase;
 #pragma unroll
                     for (int comp = 0; comp < 3; ++comp) F[comp] = e[comp * n3];
                 } else {
@@ -1386,24 +1388,22 @@ __device__ __forceinline__ void recombine_magnetic_rows_body(PT P, const int bx)
                         for (int comp = 0; comp < 3; ++comp) cmac(F[comp], e3, d[(c * 3 + comp) * n3]);
                     }
                 }
-                float val = 0.f;
-                if (q2 > 0.f) {
-                    const float iq = rsqrtf(q2);
-                    const float ex = qx * iq, ey = qy * iq, ez = qz * iq;
-                    const float px = ex * F[0].x + ey * F[1].x + ez * F[2].x;
-                    const float py = ex * F[0].y + ey * F[1].y + ez * F[2].y;
+                // |F_perp|^2 = |F|^2 - |Q.F|^2 / |Q|^2 (0 at Q = 0), times f(|Q|)^2
+                const float pr = qx * F[0].x + qy * F[1].x + qz * F[2].x;
+                const float pim = qx * F[0].y + qy * F[1].y + qz * F[2].y;
+                float f2 = 0.f;
 #pragma unroll
-                    for (int comp = 0; comp < 3; ++comp) val += F[comp].x * F[comp].x + F[comp].y * F[comp].y;
-                    val -= px * px + py * py;
-                    if (sep) {
-                        const float4 e2 = ffrow[r];
-                        const float f = fmaf(e13a, e2.x, fmaf(e13b, e2.y, fmaf(e13c, e2.z, P.ff[0][6])));
-                        val *= f * f;
-                    } else if (P.ff_uniform) {
-                        const float f = mag_ff_fast(P.ff[0], s2);
-                        val *= f * f;
-                    }
+                for (int comp = 0; comp < 3; ++comp) f2 += F[comp].x * F[comp].x + F[comp].y * F[comp].y;
+                float val = fmaf(-(pr * pr + pim * pim), __builtin_amdgcn_rcpf(q2), f2);
+                if (sep) {
+                    const float4 e2 = ffrow[r];
+                    const float f = fmaf(e13a, e2.x, fmaf(e13b, e2.y, fmaf(e13c, e2.z, P.ff[0][6])));
+                    val *= f * f;
+                } else if (P.ff_uniform) {
+                    const float f = mag_ff_fast(P.ff[0], s2);
+                    val *= f * f;
                 }
+                val = q2 > 0.f ? val : 0.f;
                 if constexpr (MULTI) {
 #pragma unroll
                     for (int rr = 0; rr < kMagRowsMaxRows; ++rr)
