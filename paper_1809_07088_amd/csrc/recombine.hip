@@ -1480,81 +1480,108 @@ hipError_t launch_recombine_magnetic_rows(const RecombParams& p, int block, size
 // ---------------------------------------------------------------------------- direct form
 // Taylor order 0 (occupancies only, one field per site): every voxel is computed on its
 // own, F_m(G) = sum_mu b_mu e^{2 pi i g.r_mu} X_mu,m(k), I(G) = scale sum_m |F_m(G)|^2.
-// A thread takes kDirectVPT consecutive voxels in output order (the index arithmetic and
-// the chain of dependent parameter and table loads are paid once for all of them; k3 and
-// H3 step along the row, the row indices are redone only where a row ends), so a wave
-// writes 64 kDirectVPT consecutive floats.  For one or two sites x configurations this
-// beats the levelled forms, whose blocks serve one column of the grid each.
+// A thread computes kDirectVPT consecutive voxels in output order (the index arithmetic
+// and the chain of dependent parameter and table loads are paid once for all of them; k3
+// and H3 step along the row, the row indices are redone only where a row ends) into LDS;
+// the block then writes its kDirectThreads kDirectVPT voxels with consecutive lanes on
+// consecutive voxels, so each store instruction of a wave covers whole cache lines.  For
+// one or two sites x configurations this beats the levelled forms, whose blocks serve one
+// column of the grid each.
 constexpr int kDirectThreads = 256, kDirectVPT = 8;
+constexpr int kDirectPitch = kDirectVPT + 1;   // staged floats per thread (odd: no bank conflicts)
 
 template <class PT>
 __device__ __forceinline__ void recombine_direct_body(PT P, const int bx)
 {
+    __shared__ float stage[kDirectThreads * kDirectPitch];
     const uint32_t c2 = (uint32_t)P.cnt[2], c1 = (uint32_t)P.cnt[1];
     const uint32_t total = (uint32_t)P.planes * c1 * c2;
-    const uint32_t base = ((uint32_t)bx * kDirectThreads + threadIdx.x) * kDirectVPT;
-    if (base >= total) return;
-    const int n1 = P.n1, n2 = P.n2, n3 = P.n3, nh = P.nh;
-    const size_t SFnh = (size_t)P.SF * nh;
-    const size_t cstride = (size_t)n1 * n2 * SFnh;     // between configurations
-    const size_t fstride = (size_t)P.F * nh;           // between sites
-    uint32_t r = base / c2;
-    int i3 = (int)(base - r * c2);
-    int i1 = (int)(r / c1), i2 = (int)(r - (uint32_t)i1 * c1);
-    int k1 = 0, k2 = 0, k3 = 0, h = 0;
-    size_t colp = 0, colm = 0;
-    auto row = [&]() {     // the row (i1, i2) and the residue of its voxel i3
-        const int G1 = P.g0[0] + i1, G2 = P.g0[1] + i2, G3 = P.g0[2] + i3;
-        k1 = ((G1 % n1) + n1) % n1;
-        k2 = ((G2 % n2) + n2) % n2;
-        k3 = ((G3 % n3) + n3) % n3;
-        h = (G3 - k3) / n3 - P.H3min;
-        colp = ((size_t)k1 * n2 + k2) * SFnh;                              // X(k)
-        colm = ((size_t)((n1 - k1) % n1) * n2 + (n2 - k2) % n2) * SFnh;   // X(-k), conjugated
-    };
-    row();
-    const int nv = (int)min((uint32_t)kDirectVPT, total - base);
-    // one site: the phase has modulus b, so |F_m|^2 = b^2 |X_m(k)|^2 exactly
-    const bool one = P.S == 1;
-    const int mu0 = P.site_of[0];
-    const float2 t0 = P.tab1[(size_t)mu0 * P.cnt[0]];
-    const float b2s = (t0.x * t0.x + t0.y * t0.y) * P.scale;
-    for (int v = 0; v < nv; ++v) {
-        const bool half = k3 >= nh;                    // half spectra: k3 >= nh reads conj X(-k)
-        const size_t col = half ? colm + (size_t)(n3 - k3) : colp + (size_t)k3;
-        const float cj = half ? -1.f : 1.f;
-        float I = 0.f;
-        if (one) {
-            const float2* x = P.X + col + (size_t)mu0 * fstride;
-            for (int m = 0; m < P.M; ++m) {
-                const float2 xv = x[(size_t)m * cstride];
-                I += xv.x * xv.x + xv.y * xv.y;
+    const uint32_t bbase = (uint32_t)bx * (kDirectThreads * kDirectVPT);   // the block's first voxel
+    const uint32_t base = bbase + threadIdx.x * kDirectVPT;
+    const int nv = base < total ? (int)min((uint32_t)kDirectVPT, total - base) : 0;
+    float* const mine = stage + threadIdx.x * kDirectPitch;
+    if (nv > 0) {
+        const int n1 = P.n1, n2 = P.n2, n3 = P.n3, nh = P.nh;
+        const size_t SFnh = (size_t)P.SF * nh;
+        const size_t cstride = (size_t)n1 * n2 * SFnh;     // between configurations
+        const size_t fstride = (size_t)P.F * nh;           // between sites
+        uint32_t r = base / c2;
+        int i3 = (int)(base - r * c2);
+        int i1 = (int)(r / c1), i2 = (int)(r - (uint32_t)i1 * c1);
+        int k1 = 0, k2 = 0, k3 = 0, h = 0;
+        size_t colp = 0, colm = 0;
+        auto row = [&]() {     // the row (i1, i2) and the residue of its voxel i3
+            const int G1 = P.g0[0] + i1, G2 = P.g0[1] + i2, G3 = P.g0[2] + i3;
+            k1 = ((G1 % n1) + n1) % n1;
+            k2 = ((G2 % n2) + n2) % n2;
+            k3 = ((G3 % n3) + n3) % n3;
+            h = (G3 - k3) / n3 - P.H3min;
+            colp = ((size_t)k1 * n2 + k2) * SFnh;                              // X(k)
+            colm = ((size_t)((n1 - k1) % n1) * n2 + (n2 - k2) % n2) * SFnh;   // X(-k), conjugated
+        };
+        row();
+        // one site: the phase has modulus b, so |F_m|^2 = b^2 |X_m(k)|^2 exactly
+        const bool one = P.S == 1;
+        const int mu0 = P.site_of[0];
+        const float2 t0 = P.tab1[(size_t)mu0 * P.cnt[0]];
+        const float b2s = (t0.x * t0.x + t0.y * t0.y) * P.scale;
+        for (int v = 0; v < nv; ++v) {
+            const bool half = k3 >= nh;                    // half spectra: k3 >= nh reads conj X(-k)
+            const size_t col = half ? colm + (size_t)(n3 - k3) : colp + (size_t)k3;
+            const float cj = half ? -1.f : 1.f;
+            float I = 0.f;
+            if (one) {
+                const float2* x = P.X + col + (size_t)mu0 * fstride;
+                for (int m = 0; m < P.M; ++m) {
+                    const float2 xv = x[(size_t)m * cstride];
+                    I += xv.x * xv.x + xv.y * xv.y;
+                }
+                I *= b2s;
+            } else {
+                for (int m = 0; m < P.M; ++m) {
+                    const float2* Xm = P.X + (size_t)m * cstride + col;
+                    float2 F = make_float2(0.f, 0.f);
+                    for (int s = 0; s < P.S; ++s) {
+                        const int mu = P.site_of[s];
+                        const float2 ph = cmulf(cmulf(P.tab1[(size_t)mu * P.cnt[0] + i1], P.tab2[(size_t)mu * c1 + i2]),
+                                                cmulf(P.tabK3[(size_t)mu * n3 + k3],
+                                                      P.tabH3[(size_t)P.class_of[s] * P.nH3span + h]));
+                        float2 x = Xm[(size_t)mu * fstride];
+                        x.y *= cj;
+                        F.x += ph.x * x.x - ph.y * x.y;
+                        F.y += ph.x * x.y + ph.y * x.x;
+                    }
+                    I += F.x * F.x + F.y * F.y;
+                }
+                I *= P.scale;
             }
-            P.out[(size_t)(i1 * P.cnt[1] + i2) * P.opitch + i3 + P.ooff] = I * b2s;
-        }
-        for (int m = 0; m < (one ? 0 : P.M); ++m) {
-            const float2* Xm = P.X + (size_t)m * cstride + col;
-            float2 F = make_float2(0.f, 0.f);
-            for (int s = 0; s < P.S; ++s) {
-                const int mu = P.site_of[s];
-                const float2 ph = cmulf(cmulf(P.tab1[(size_t)mu * P.cnt[0] + i1], P.tab2[(size_t)mu * c1 + i2]),
-                                        cmulf(P.tabK3[(size_t)mu * n3 + k3], P.tabH3[(size_t)P.class_of[s] * P.nH3span + h]));
-                float2 x = Xm[(size_t)mu * fstride];
-                x.y *= cj;
-                F.x += ph.x * x.x - ph.y * x.y;
-                F.y += ph.x * x.y + ph.y * x.x;
+            mine[v] = I;
+            // next voxel: along the row, or the start of the next row
+            if (++i3 < (int)c2) {
+                if (++k3 == n3) { k3 = 0; ++h; }
+            } else {
+                i3 = 0;
+                if (++i2 == (int)c1) { i2 = 0; ++i1; }
+                if (v + 1 < nv) row();
             }
-            I += F.x * F.x + F.y * F.y;
         }
-        if (!one) P.out[(size_t)(i1 * P.cnt[1] + i2) * P.opitch + i3 + P.ooff] = I * P.scale;
-        // next voxel: along the row, or the start of the next row
-        if (++i3 < (int)c2) {
-            if (++k3 == n3) { k3 = 0; ++h; }
-        } else {
-            i3 = 0;
-            if (++i2 == (int)c1) { i2 = 0; ++i1; }
-            if (v + 1 < nv) row();
-        }
+    }
+    __syncthreads();
+    // store: lane t of pass v writes the block's voxel j = v kDirectThreads + t (computed
+    // by thread j / kDirectVPT), row r = V / c2 of the box, V = bbase + j
+    uint32_t V = bbase + threadIdx.x;
+    if (V >= total) return;
+    uint32_t r = V / c2, i3 = V - r * c2;
+    const uint32_t dr = (uint32_t)kDirectThreads / c2, di = (uint32_t)kDirectThreads - dr * c2;
+#pragma unroll
+    for (int v = 0; v < kDirectVPT; ++v) {
+        const int j = v * kDirectThreads + (int)threadIdx.x;
+        P.out[(size_t)r * P.opitch + i3 + P.ooff] = stage[(j / kDirectVPT) * kDirectPitch + (j % kDirectVPT)];
+        V += kDirectThreads;
+        if (v + 1 == kDirectVPT || V >= total) break;
+        i3 += di;
+        r += dr;
+        if (i3 >= c2) { i3 -= c2; ++r; }
     }
 }
 
