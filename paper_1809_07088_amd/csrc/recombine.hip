@@ -1779,6 +1779,69 @@ __global__ __launch_bounds__(64) void k_bragg_nuclear_merged(const BraggParams* 
     if (slot_of(slots, d, bx)) bragg_nuclear_body<N, const BraggParams&>(tab[d], bx);
 }
 
+// Taylor order 0 with few sites (one field per site, the occupancy): one lane per H.  The
+// lane's site factors b_mu f(|H|) e^{2 pi i H.r_mu} are staged in its own LDS column, then
+// every configuration is summed over the sites serially, so a wave serves 64 H where the
+// form above, built for the many (site, monomial) pairs of a Taylor model, gives one H a wave.
+constexpr int kBraggLaneSites = 16;
+
+template <class PT>
+__device__ __forceinline__ void bragg_lanes_body(PT P, const int bx)
+{
+#pragma clang fp contract(off)
+    __shared__ double Wr[kBraggLaneSites][64], Wi[kBraggLaneSites][64];
+    const int total = P.nH[0] * P.nH[1] * P.nH[2];
+    const int lane = threadIdx.x;
+    const int idx = bx * 64 + lane;
+    if (idx >= total) return;                       // (no barrier below: each lane has its column)
+    const int j3 = idx % P.nH[2], j2 = (idx / P.nH[2]) % P.nH[1], j1 = idx / (P.nH[2] * P.nH[1]);
+    const int H[3] = {P.Hlo[0] + j1, P.Hlo[1] + j2, P.Hlo[2] + j3};
+    double s2 = 0.0;
+    if (P.has_ff) {
+        double q[3] = {0.0, 0.0, 0.0};
+        for (int a = 0; a < 3; ++a)
+            for (int c = 0; c < 3; ++c) q[c] += H[a] * P.recip[3 * a + c];
+        s2 = (q[0] * q[0] + q[1] * q[1] + q[2] * q[2]) / (16.0 * M_PI * M_PI);
+    }
+    for (int mu = 0; mu < P.S; ++mu) {
+        const double* sd = P.site + 12 * mu;
+        double x = H[0] * sd[0] + H[1] * sd[1] + H[2] * sd[2];
+        x -= floor(x);
+        double sn, cs;
+        sincos(6.283185307179586476925 * x, &sn, &cs);
+        double wgt = sd[3];
+        if (P.has_ff) {
+            const double* f = sd + 4;
+            wgt *= f[0] * exp(-f[1] * s2) + f[2] * exp(-f[3] * s2) + f[4] * exp(-f[5] * s2) + f[6];
+        }
+        Wr[mu][lane] = wgt * cs;
+        Wi[mu][lane] = wgt * sn;
+    }
+    double sq = 0.0, mre = 0.0, mim = 0.0;
+    for (int m = 0; m < P.M; ++m) {
+        const double* Sm = P.sums + (size_t)m * P.S * P.T;   // [site][monomial]; monomial 0: occupancy
+        double fr = 0.0, fi = 0.0;
+        for (int mu = 0; mu < P.S; ++mu) {
+            const double sv = Sm[(size_t)mu * P.T];
+            fr += sv * Wr[mu][lane];
+            fi += sv * Wi[mu][lane];
+        }
+        sq += fr * fr + fi * fi;
+        mre += fr; mim += fi;
+    }
+    mre /= P.M; mim /= P.M;
+    const double I = (sq / P.M - (mre * mre + mim * mim)) * P.scale;
+    const int G[3] = {P.n[0] * H[0], P.n[1] * H[1], P.n[2] * H[2]};
+    P.out[((size_t)(G[0] - P.g0[0]) * P.cnt[1] + (G[1] - P.g0[1])) * P.opitch + (G[2] - P.g0[2]) + P.ooff] = (float)I;
+}
+
+__global__ __launch_bounds__(64) void k_bragg_lanes(BraggParams P) { bragg_lanes_body<BraggParams>(P, blockIdx.x); }
+__global__ __launch_bounds__(64) void k_bragg_lanes_merged(const BraggParams* __restrict__ tab, const Slot* __restrict__ slots)
+{
+    int d, bx;
+    if (slot_of(slots, d, bx)) bragg_lanes_body<const BraggParams&>(tab[d], bx);
+}
+
 __device__ double mag_ff_d(const double* f, double s2) {
     return f[0] * exp(-f[1] * s2) + f[2] * exp(-f[3] * s2) + f[4] * exp(-f[5] * s2) + f[6];
 }
@@ -1910,6 +1973,8 @@ hipError_t launch_bragg(const BraggParams& p, int order, hipStream_t st)
     if (p.kind == 1) {
         return dispatch(k_bragg_magnetic, k_bragg_magnetic_merged, (total + 3) / 4, 256, 0, st, p);
     }
+    if (order == 0 && p.S <= kBraggLaneSites)
+        return dispatch(k_bragg_lanes, k_bragg_lanes_merged, (total + 63) / 64, 64, 0, st, p);
     switch (order) {
         case 0: return launch_bragg_t<0>(p, grid, st);
         case 1: return launch_bragg_t<1>(p, grid, st);

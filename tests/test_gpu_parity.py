@@ -45,6 +45,26 @@ def test_compositional_simple_cubic_full_grid(M):
         assert abs(I.astype(np.float64).mean() - c * (1 - c)) < 1e-6
 
 
+@pytest.mark.parametrize("S,M", [(3, 2), (16, 3), (17, 2), (24, 1)])
+def test_occupancy_bragg_points_across_site_counts(S, M):
+    """Order-0 (occupancy) models: up to 16 sites take the lane-per-H form of the float64
+    Bragg points, more sites the (site, monomial) form; both against the oracle on the whole
+    box and at its Bragg points G = n H (the variance over configurations; 0 for M = 1)."""
+    m = synth.random_model(440 + S, n=(3, 4, 3), S=S, M=M, order=0, with_disp=False)
+    m.g0, m.count = (-6, -8, -7), (13, 17, 15)
+    say(f"occupancy Bragg points S={S} M={M}")
+    I = gpu_intensity(m)
+    ref = O.intensity(m, O.grid_points(m.g0, m.count), 0).reshape(m.count)
+    assert_parity(I, ref)
+    G = O.grid_points(m.g0, m.count).reshape(m.count + (3,))
+    at_h = np.all(G % np.asarray(m.n) == 0, axis=-1)
+    assert at_h.sum() == 5 * 5 * 5
+    scale = np.abs(ref).max()
+    assert np.allclose(I[at_h], ref[at_h], rtol=1e-5, atol=1e-7 * scale)
+    if M == 1:
+        assert np.all(I[at_h] == 0.0)
+
+
 # ------------------------------------------------------------------ displacive, every order
 
 @pytest.mark.parametrize("order", list(range(0, 9)))
