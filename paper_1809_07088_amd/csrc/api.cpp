@@ -1033,9 +1033,12 @@ dsx_status ensure_spectra(dsx_model m, hipStream_t st, bool force = false)
         HIPCHK(m, timed("fft_axis2", st, [&] { return launch_fft_axis1(a2, st); }));
     }
 
+    // axis 1: for each k1 the (k2, field, k3) columns are contiguous, so they are tiled as
+    // one run of n2 S F nh columns (a small box fills whole tiles instead of one per k2)
     Axis1Params ap{};
     ap.X = m->d_X; ap.tw1 = m->d_tw[0]; ap.p1 = m->plan[0];
     ap.n1 = m->n[0]; ap.n2 = m->n[1]; ap.cols = m->SF * m->nh; ap.M = m->M;
+    if ((long long)ap.n2 * ap.cols <= (1LL << 30)) { ap.cols *= ap.n2; ap.n2 = 1; }
     ap.tc = m->tune_tc > 0 ? m->tune_tc : (m->n[0] <= 64 ? 64 : 32);
     ap.ncolblk = (ap.cols + ap.tc - 1) / ap.tc;
     HIPCHK(m, timed("fft_axis1", st, [&] { return launch_fft_axis1(ap, st); }));
