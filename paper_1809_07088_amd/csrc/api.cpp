@@ -990,6 +990,7 @@ dsx_status ensure_spectra(dsx_model m, hipStream_t st, bool force = false)
     pp.p2 = m->plan[1]; pp.p3 = m->plan[2];
     pp.n1 = m->n[0]; pp.n2 = m->n[1]; pp.n3 = m->n[2]; pp.nh = m->nh;
     pp.S = m->S; pp.F = m->F; pp.T = m->T; pp.M = m->M; pp.kind = m->kind; pp.first_mono = m->first_mono;
+    pp.npl = 1;
     const int npairs = (m->n[1] + 1) / 2;
     pp.buf_elems = std::max(npairs * m->n[2], m->n[1] * m->nh);
     // fields batched per block: more butterflies per pass, LDS <= 24 KB, and
@@ -1010,6 +1011,12 @@ dsx_status ensure_spectra(dsx_model m, hipStream_t st, bool force = false)
         pp.buf_elems = std::max(pp.row_pairs * m->n[2], 2 * pp.row_pairs * m->nh);
         pp.fchunk = 1;
         pp.nfchunk = m->F;
+    }
+    if (!by_rows) {
+        // small planes: several lattice planes per block (about 1024 cells), in <= 32 KB of LDS
+        int npl = std::max(1, 1024 / (m->n[1] * m->n[2] * pp.fchunk));
+        npl = std::min(npl, m->n[0]);
+        for (pp.npl = npl; pp.npl > 1 && planes_lds_bytes(pp) > 32 * 1024; --pp.npl) {}
     }
     if (m->kind == DSX_NUCLEAR) {
         // spectra order: pairs (q, r) by e = q + r, q descending; p ascending within

@@ -67,6 +67,7 @@ struct PlaneParams {
     AxisPlan p2, p3;
     int32_t n1, n2, n3, nh, S, F, T, M, kind, first_mono;
     int32_t fchunk, nfchunk;
+    int32_t npl;          // lattice planes per block (small planes; the rows kernel takes 1)
     int32_t buf_elems;    // complex elements per LDS ping-pong buffer
     int32_t row_pairs;    // > 0: the plane does not fit the LDS; blocks take this many row pairs
                           // and transform along axis 3 only (axis 2 follows in place)

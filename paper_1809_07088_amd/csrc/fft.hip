@@ -380,25 +380,30 @@ hipError_t launch_sums(const SumsParams& p, int order, hipStream_t st)
 }
 
 // ---------------------------------------------------------------------------- plane FFT
-// Generates the nfb fields fa.. of rows 2 j0 .. 2 (j0 + nj) - 1 of lattice plane R1 of
-// site mu, configuration m (centred by their float64 mean), packs two real rows per
-// complex line, transforms the lines along axis 3 in LDS and separates the two half
-// spectra.  Returns the LDS buffer holding row r (local) of field fb at
-// [fb * BE + r * nh + k3]; A and B are ping-pong buffers of nfb x BE elements.
+// Generates the nfb fields fa.. of rows 2 j0 .. 2 (j0 + nj) - 1 of the npl lattice planes
+// R1 .. R1 + npl - 1 of site mu, configuration m (centred by their float64 mean), packs two
+// real rows per complex line, transforms the lines along axis 3 in LDS and separates the
+// two half spectra.  Item b = pl nfb + fb is field fa + fb of plane R1 + pl.  Returns the
+// LDS buffer holding row r (local) of item b at [b * BE + r * nh + k3]; A and B are
+// ping-pong buffers of npl nfb x BE elements.
 __device__ __forceinline__ float2* planes_rows(const PlaneParams& P, float2* A, float2* B, const float2* tw3, int m, int mu,
-                               int R1, int j0, int nj, int fa, int nfb, int BE)
+                               int R1, int npl, int j0, int nj, int fa, int nfb, int BE)
 {
     const int n2 = P.n2, n3 = P.n3, nh = P.nh;
     const int ncell = P.n1 * n2 * n3;
     const size_t plane0 = ((size_t)(m * P.S + mu)) * ncell + (size_t)R1 * n2 * n3;
-    const float* occ = P.occ ? P.occ + plane0 : nullptr;
-    const float* vec = P.vec ? P.vec + 3 * plane0 : nullptr;
+    const float* occ0 = P.occ ? P.occ + plane0 : nullptr;
+    const float* vec0 = P.vec ? P.vec + 3 * plane0 : nullptr;
     const float rpn3 = 1.f / (float)(nj * n3), rn3 = 1.f / (float)n3, rnh = 1.f / (float)nh;
-    const float rpnh = 1.f / (float)(nj * nh);
-    for (int idx = threadIdx.x; idx < nfb * nj * n3; idx += blockDim.x) {
-        const int fb = qdiv(idx, nj * n3, rpn3);
-        const int rem = idx - fb * nj * n3;
+    const float rpnh = 1.f / (float)(nj * nh), rnfb = 1.f / (float)nfb;
+    const int nb = npl * nfb;
+    for (int idx = threadIdx.x; idx < nb * nj * n3; idx += blockDim.x) {
+        const int b = qdiv(idx, nj * n3, rpn3);
+        const int rem = idx - b * nj * n3;
         const int jj = qdiv(rem, n3, rn3), R3 = rem - jj * n3;
+        const int pl = qdiv(b, nfb, rnfb), fb = b - pl * nfb;
+        const float* occ = occ0 ? occ0 + (size_t)pl * n2 * n3 : nullptr;
+        const float* vec = vec0 ? vec0 + (size_t)3 * pl * n2 * n3 : nullptr;
         const int f = fa + fb;
         const int ep = P.mono[3 * f], eq = P.mono[3 * f + 1], er = P.mono[3 * f + 2];
         const int t = P.kind == 1 ? f : mono_index(ep, eq, er);    // index of the field's lattice sum
@@ -425,23 +430,23 @@ __device__ __forceinline__ float2* planes_rows(const PlaneParams& P, float2* A, 
                 xv[h] = v - mean;
             }
         }
-        A[fb * BE + jj * n3 + R3] = make_float2(xv[0], xv[1]);
+        A[b * BE + jj * n3 + R3] = make_float2(xv[0], xv[1]);
     }
     __syncthreads();
-    float2* Z = lds_fft(A, B, nj, n3, 1, P.p3, tw3, nfb, BE);
+    float2* Z = lds_fft(A, B, nj, n3, 1, P.p3, tw3, nb, BE);
     float2* C = (Z == A) ? B : A;
     // unpack the packed real transforms: X_a = (Z_k + conj Z_-k)/2, X_b = -i (Z_k - conj Z_-k)/2
-    for (int idx = threadIdx.x; idx < nfb * nj * nh; idx += blockDim.x) {
-        const int fb = qdiv(idx, nj * nh, rpnh);
-        const int rem = idx - fb * nj * nh;
+    for (int idx = threadIdx.x; idx < nb * nj * nh; idx += blockDim.x) {
+        const int b = qdiv(idx, nj * nh, rpnh);
+        const int rem = idx - b * nj * nh;
         const int jj = qdiv(rem, nh, rnh), k = rem - jj * nh;
-        const float2 zk = Z[fb * BE + jj * n3 + k];
+        const float2 zk = Z[b * BE + jj * n3 + k];
         const int km = (k == 0) ? 0 : n3 - k;
-        const float2 zm = Z[fb * BE + jj * n3 + km];
+        const float2 zm = Z[b * BE + jj * n3 + km];
         const float2 xa = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
         const float2 xb = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
-        C[fb * BE + (2 * jj) * nh + k] = xa;
-        if (2 * (j0 + jj) + 1 < n2) C[fb * BE + (2 * jj + 1) * nh + k] = xb;
+        C[b * BE + (2 * jj) * nh + k] = xa;
+        if (2 * (j0 + jj) + 1 < n2) C[b * BE + (2 * jj + 1) * nh + k] = xb;
     }
     __syncthreads();
     return C;
@@ -454,11 +459,12 @@ __device__ __forceinline__ void fft_planes_body(PT P, const int bx)
     float2* tw2 = smem;
     float2* tw3 = tw2 + P.n2;
     float2* A = tw3 + P.n3;
-    float2* B = A + P.fchunk * P.buf_elems;
+    float2* B = A + P.npl * P.fchunk * P.buf_elems;
 
     int b = bx;
     const int fc = b % P.nfchunk; b /= P.nfchunk;
-    const int R1 = b % P.n1; b /= P.n1;
+    const int nrb = (P.n1 + P.npl - 1) / P.npl;      // plane blocks per (site, configuration)
+    const int R1 = (b % nrb) * P.npl; b /= nrb;
     const int mu = b % P.S;
     const int m = b / P.S;
     const int n2 = P.n2, nh = P.nh;
@@ -468,19 +474,22 @@ __device__ __forceinline__ void fft_planes_body(PT P, const int bx)
     for (int i = threadIdx.x; i < P.n3; i += blockDim.x) tw3[i] = P.tw3[i];
     const int fa = fc * P.fchunk;
     const int nfb = min(P.F, fa + P.fchunk) - fa;     // fields of this block, batched
+    const int npl = min(P.npl, P.n1 - R1);            // and planes
     const int BE = P.buf_elems;
     __syncthreads();   // twiddles visible
-    float2* C = planes_rows(P, A, B, tw3, m, mu, R1, 0, (n2 + 1) / 2, fa, nfb, BE);
+    float2* C = planes_rows(P, A, B, tw3, m, mu, R1, npl, 0, (n2 + 1) / 2, fa, nfb, BE);
     float2* D = (C == A) ? B : A;
-    float2* Y = lds_fft(C, D, nh, 1, nh, P.p2, tw2, nfb, BE);
-    // write: for each k2, the block's fields are contiguous runs of nh complex
-    const float rnh = 1.f / (float)nh, rfnh = 1.f / (float)(nfb * nh);
+    float2* Y = lds_fft(C, D, nh, 1, nh, P.p2, tw2, npl * nfb, BE);
+    // write: for each plane and k2, the block's fields are contiguous runs of nh complex
+    const float rnh = 1.f / (float)nh, rfnh = 1.f / (float)(nfb * nh), rpl = 1.f / (float)(n2 * nfb * nh);
     float2* out = P.X + ((size_t)(m * P.n1 + R1) * n2) * SF * nh + (size_t)(mu * P.F + fa) * nh;
-    for (int idx = threadIdx.x; idx < n2 * nfb * nh; idx += blockDim.x) {
-        const int k2 = qdiv(idx, nfb * nh, rfnh);
-        const int rem = idx - k2 * nfb * nh;
+    for (int idx = threadIdx.x; idx < npl * n2 * nfb * nh; idx += blockDim.x) {
+        const int pl = qdiv(idx, n2 * nfb * nh, rpl);
+        const int r2 = idx - pl * n2 * nfb * nh;
+        const int k2 = qdiv(r2, nfb * nh, rfnh);
+        const int rem = r2 - k2 * nfb * nh;
         const int fb = qdiv(rem, nh, rnh), k3 = rem - fb * nh;
-        out[(size_t)k2 * SF * nh + rem] = Y[fb * BE + k2 * nh + k3];
+        out[((size_t)pl * n2 + k2) * SF * nh + rem] = Y[(pl * nfb + fb) * BE + k2 * nh + k3];
     }
 }
 
@@ -516,7 +525,7 @@ __device__ __forceinline__ void fft_rows_body(PT P, const int bx)
     const int nj = min((n2 + 1) / 2, j0 + P.row_pairs) - j0;
     const int BE = P.buf_elems;
     __syncthreads();
-    const float2* C = planes_rows(P, A, B, tw3, m, mu, R1, j0, nj, fa, nfb, BE);
+    const float2* C = planes_rows(P, A, B, tw3, m, mu, R1, 1, j0, nj, fa, nfb, BE);
     const int nrow = min(n2, 2 * (j0 + nj)) - 2 * j0;
     const float rnh = 1.f / (float)nh, rfnh = 1.f / (float)(nfb * nh);
     float2* out = P.X + ((size_t)(m * P.n1 + R1) * n2 + 2 * j0) * SF * nh + (size_t)(mu * P.F + fa) * nh;
@@ -769,7 +778,7 @@ static hipError_t launch_planes_reg2(const PlaneParams& p, hipStream_t st)
 
 size_t planes_lds_bytes(const PlaneParams& p)
 {
-    return sizeof(float2) * (size_t)((p.row_pairs > 0 ? 0 : p.n2) + p.n3 + 2 * p.fchunk * p.buf_elems);
+    return sizeof(float2) * (size_t)((p.row_pairs > 0 ? 0 : p.n2) + p.n3 + 2 * (p.npl > 1 ? p.npl : 1) * p.fchunk * p.buf_elems);
 }
 
 hipError_t launch_fft_planes(const PlaneParams& p, hipStream_t st)
@@ -795,7 +804,9 @@ hipError_t launch_fft_planes(const PlaneParams& p, hipStream_t st)
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    return dispatch(k_fft_planes, k_fft_planes_merged, p.M * p.S * p.n1 * p.nfchunk, 256, lds, st, p);
+    if (p.npl < 1) return hipErrorInvalidValue;
+    return dispatch(k_fft_planes, k_fft_planes_merged, p.M * p.S * ((p.n1 + p.npl - 1) / p.npl) * p.nfchunk, 256, lds,
+                    st, p);
 }
 
 // ---------------------------------------------------------------------------- axis-1 FFT

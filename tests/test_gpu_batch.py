@@ -46,9 +46,9 @@ def test_batch_equals_individual_and_oracle(lm, mode):
     info = batch.info()
     print("batch info", info)
     if mode == "merged":
-        # uneven n, orders and kinds: the lattice-sum reduction and the generic-length FFTs
-        # are shared, so the graph has fewer dispatches than the models have launches
-        assert info["mode"] == dsx.BATCH_MERGED and info["merged_nodes"] >= 2
+        # uneven n, orders and kinds: launches of one kernel and LDS class are shared (the
+        # lattice-sum reduction at least), so the graph has fewer dispatches than launches
+        assert info["mode"] == dsx.BATCH_MERGED and info["merged_nodes"] >= 1
         assert info["dispatches"] < info["launches"]
     elif mode == "per_model":
         assert info["mode"] == dsx.BATCH_PER_MODEL and info["merged_nodes"] == 0
