@@ -225,6 +225,21 @@ struct Slot {
 
 // Descriptor and block index (within its own launch) of this block; false on the
 // padding blocks past the descriptor's own grid.
+// A pointer taken from a descriptor table is generic to the compiler (flat memory
+// operations, which also hold the scalar-load counter); a kernel body reads and writes its
+// device buffers through this global-address-space view instead.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gptr(T* p)
+{
+    return (__attribute__((address_space(1))) T*)p;
+}
+
+// p[i] of a complex array through the global view (one 8-byte load)
+__device__ __forceinline__ float2 ldg2(const float2* p, size_t i)
+{
+    return __builtin_bit_cast(float2, ((const __attribute__((address_space(1))) unsigned long long*)p)[i]);
+}
+
 __device__ __forceinline__ bool slot_of(const Slot* __restrict__ slots, int& d, int& bx)
 {
     const Slot s = slots[blockIdx.x >> 3];

@@ -1480,108 +1480,153 @@ hipError_t launch_recombine_magnetic_rows(const RecombParams& p, int block, size
 // ---------------------------------------------------------------------------- direct form
 // Taylor order 0 (occupancies only, one field per site): every voxel is computed on its
 // own, F_m(G) = sum_mu b_mu e^{2 pi i g.r_mu} X_mu,m(k), I(G) = scale sum_m |F_m(G)|^2.
-// A thread computes kDirectVPT consecutive voxels in output order (the index arithmetic
-// and the chain of dependent parameter and table loads are paid once for all of them; k3
-// and H3 step along the row, the row indices are redone only where a row ends) into LDS;
-// the block then writes its kDirectThreads kDirectVPT voxels with consecutive lanes on
-// consecutive voxels, so each store instruction of a wave covers whole cache lines.  For
-// one or two sites x configurations this beats the levelled forms, whose blocks serve one
-// column of the grid each.
-constexpr int kDirectThreads = 256, kDirectVPT = 8;
-constexpr int kDirectPitch = kDirectVPT + 1;   // staged floats per thread (odd: no bank conflicts)
+// A wave takes 64 consecutive columns i3 of the box, one a lane, over kDirectRows
+// consecutive rows (i1, i2): a lane's column fixes k3, H3 and the half of the spectra it
+// reads, a row fixes k1, k2 and the spectra column for the whole wave (scalar registers,
+// stepped from row to row), so a voxel costs its loads, |F|^2 and one store, and every
+// load and store of a wave is one contiguous run.  For one or two sites x configurations
+// this beats the levelled forms, whose blocks serve one column of the grid each.
+constexpr int kDirectThreads = 256, kDirectRows = 16, kDirectGroup = 16;
+constexpr int kDirectWaves = kDirectThreads / 64;
+
+// a / b for a < 2^32 through the float64 reciprocal rb of b (relative error well below
+// 2^-40): the estimate is within one of the quotient, and one remainder check makes it exact
+__device__ __forceinline__ uint32_t udiv_exact(uint32_t a, uint32_t b, double rb)
+{
+    uint32_t q = (uint32_t)((double)a * rb);
+    const long long r = (long long)a - (long long)q * b;
+    q += (r >= (long long)b) ? 1u : 0u;
+    q -= (r < 0) ? 1u : 0u;
+    return q;
+}
+// 1/b in float64: the hardware reciprocal refined by two Newton steps
+__device__ __forceinline__ double rcp_refined(uint32_t b)
+{
+    const double d = (double)b;
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    r = fma(r, fma(-d, r, 1.0), r);
+    return r;
+}
+// floor(a / b) for |a| < 2^22, b > 0, through the float reciprocal rb of b (a few ulp at
+// most: the estimate is within one, then one remainder check)
+__device__ __forceinline__ int floordiv_exact(int a, int b, float rb)
+{
+    int q = (int)floorf((float)a * rb);
+    const int r = a - q * b;
+    q += (r >= b) ? 1 : 0;
+    q -= (r < 0) ? 1 : 0;
+    return q;
+}
 
 template <class PT>
 __device__ __forceinline__ void recombine_direct_body(PT P, const int bx)
 {
-    __shared__ float stage[kDirectThreads * kDirectPitch];
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
     const uint32_t c2 = (uint32_t)P.cnt[2], c1 = (uint32_t)P.cnt[1];
-    const uint32_t total = (uint32_t)P.planes * c1 * c2;
-    const uint32_t bbase = (uint32_t)bx * (kDirectThreads * kDirectVPT);   // the block's first voxel
-    const uint32_t base = bbase + threadIdx.x * kDirectVPT;
-    const int nv = base < total ? (int)min((uint32_t)kDirectVPT, total - base) : 0;
-    float* const mine = stage + threadIdx.x * kDirectPitch;
-    if (nv > 0) {
-        const int n1 = P.n1, n2 = P.n2, n3 = P.n3, nh = P.nh;
-        const size_t SFnh = (size_t)P.SF * nh;
-        const size_t cstride = (size_t)n1 * n2 * SFnh;     // between configurations
-        const size_t fstride = (size_t)P.F * nh;           // between sites
-        uint32_t r = base / c2;
-        int i3 = (int)(base - r * c2);
-        int i1 = (int)(r / c1), i2 = (int)(r - (uint32_t)i1 * c1);
-        int k1 = 0, k2 = 0, k3 = 0, h = 0;
-        size_t colp = 0, colm = 0;
-        auto row = [&]() {     // the row (i1, i2) and the residue of its voxel i3
-            const int G1 = P.g0[0] + i1, G2 = P.g0[1] + i2, G3 = P.g0[2] + i3;
-            k1 = ((G1 % n1) + n1) % n1;
-            k2 = ((G2 % n2) + n2) % n2;
-            k3 = ((G3 % n3) + n3) % n3;
-            h = (G3 - k3) / n3 - P.H3min;
-            colp = ((size_t)k1 * n2 + k2) * SFnh;                              // X(k)
-            colm = ((size_t)((n1 - k1) % n1) * n2 + (n2 - k2) % n2) * SFnh;   // X(-k), conjugated
-        };
-        row();
-        // one site: the phase has modulus b, so |F_m|^2 = b^2 |X_m(k)|^2 exactly
-        const bool one = P.S == 1;
-        const int mu0 = P.site_of[0];
-        const float2 t0 = P.tab1[(size_t)mu0 * P.cnt[0]];
-        const float b2s = (t0.x * t0.x + t0.y * t0.y) * P.scale;
-        for (int v = 0; v < nv; ++v) {
-            const bool half = k3 >= nh;                    // half spectra: k3 >= nh reads conj X(-k)
-            const size_t col = half ? colm + (size_t)(n3 - k3) : colp + (size_t)k3;
-            const float cj = half ? -1.f : 1.f;
-            float I = 0.f;
-            if (one) {
-                const float2* x = P.X + col + (size_t)mu0 * fstride;
-                for (int m = 0; m < P.M; ++m) {
-                    const float2 xv = x[(size_t)m * cstride];
-                    I += xv.x * xv.x + xv.y * xv.y;
-                }
-                I *= b2s;
-            } else {
-                for (int m = 0; m < P.M; ++m) {
-                    const float2* Xm = P.X + (size_t)m * cstride + col;
-                    float2 F = make_float2(0.f, 0.f);
-                    for (int s = 0; s < P.S; ++s) {
-                        const int mu = P.site_of[s];
-                        const float2 ph = cmulf(cmulf(P.tab1[(size_t)mu * P.cnt[0] + i1], P.tab2[(size_t)mu * c1 + i2]),
-                                                cmulf(P.tabK3[(size_t)mu * n3 + k3],
-                                                      P.tabH3[(size_t)P.class_of[s] * P.nH3span + h]));
-                        float2 x = Xm[(size_t)mu * fstride];
-                        x.y *= cj;
-                        F.x += ph.x * x.x - ph.y * x.y;
-                        F.y += ph.x * x.y + ph.y * x.x;
-                    }
-                    I += F.x * F.x + F.y * F.y;
-                }
-                I *= P.scale;
-            }
-            mine[v] = I;
-            // next voxel: along the row, or the start of the next row
-            if (++i3 < (int)c2) {
-                if (++k3 == n3) { k3 = 0; ++h; }
-            } else {
-                i3 = 0;
-                if (++i2 == (int)c1) { i2 = 0; ++i1; }
-                if (v + 1 < nv) row();
-            }
-        }
-    }
-    __syncthreads();
-    // store: lane t of pass v writes the block's voxel j = v kDirectThreads + t (computed
-    // by thread j / kDirectVPT), row r = V / c2 of the box, V = bbase + j
-    uint32_t V = bbase + threadIdx.x;
-    if (V >= total) return;
-    uint32_t r = V / c2, i3 = V - r * c2;
-    const uint32_t dr = (uint32_t)kDirectThreads / c2, di = (uint32_t)kDirectThreads - dr * c2;
+    const uint32_t rows = (uint32_t)P.planes * c1;
+    const uint32_t ncc = (c2 + 63) / 64;                                 // column chunks per row group
+    const uint32_t gw = (uint32_t)bx * kDirectWaves + wave;
+    const uint32_t rg = __builtin_amdgcn_readfirstlane(udiv_exact(gw, ncc, rcp_refined(ncc)));
+    const uint32_t r0 = rg * kDirectRows;
+    if ((uint64_t)r0 >= rows) return;
+    const int i3 = (int)(gw - rg * ncc) * 64 + lane;
+    if (i3 >= (int)c2) return;
+    const int nr = (int)min((uint32_t)kDirectRows, rows - r0);
+    const int n1 = P.n1, n2 = P.n2, n3 = P.n3, nh = P.nh;
+    const size_t SFnh = (size_t)P.SF * nh;
+    const size_t cstride = (size_t)n1 * n2 * SFnh;     // between configurations
+    const size_t fstride = (size_t)P.F * nh;           // between sites
+    // the lane's column: k3, H3 and the half of the spectra (k3 >= nh reads conj X(-k))
+    const int G3 = P.g0[2] + i3;
+    const int H3 = floordiv_exact(G3, n3, __builtin_amdgcn_rcpf((float)n3));
+    const int k3 = G3 - n3 * H3, h = H3 - P.H3min;
+    const bool half = k3 >= nh;
+    const int koff = half ? n3 - k3 : k3;
+    // the wave's first row: (i1, i2) and k1, k2
+    int i1 = __builtin_amdgcn_readfirstlane(udiv_exact(r0, c1, rcp_refined(c1)));
+    int i2 = (int)(r0 - (uint32_t)i1 * c1);
+    int k1 = __builtin_amdgcn_readfirstlane(P.g0[0] + i1 - n1 * floordiv_exact(P.g0[0] + i1, n1, __builtin_amdgcn_rcpf((float)n1)));
+    int k2 = __builtin_amdgcn_readfirstlane(P.g0[1] + i2 - n2 * floordiv_exact(P.g0[1] + i2, n2, __builtin_amdgcn_rcpf((float)n2)));
+    const int k20 = __builtin_amdgcn_readfirstlane(P.g0[1] - n2 * floordiv_exact(P.g0[1], n2, __builtin_amdgcn_rcpf((float)n2)));
+    auto* op = gptr(P.out) + P.ooff + (size_t)r0 * P.opitch + i3;
+    const bool one = P.S == 1;
+    const int mu0 = P.site_of[0];
+    const float2 t0 = ldg2(P.tab1, (size_t)mu0 * P.cnt[0]);
+    const float b2s = (t0.x * t0.x + t0.y * t0.y) * P.scale;
+    const float cj = half ? -1.f : 1.f;
+    if (one) {
+        // one site: the phase has modulus b, so |F_m|^2 = b^2 |X_m(k)|^2 exactly.  Rows go
+        // in groups: the group's spectra offsets first (a direct-form spectrum has fewer than
+        // 2^32 elements), then all its loads of a configuration in flight at once
+        const float2* __restrict__ X0 = P.X + (size_t)mu0 * fstride;
+        for (int g = 0; g < nr; g += kDirectGroup) {
+            uint32_t colr[kDirectGroup];
 #pragma unroll
-    for (int v = 0; v < kDirectVPT; ++v) {
-        const int j = v * kDirectThreads + (int)threadIdx.x;
-        P.out[(size_t)r * P.opitch + i3 + P.ooff] = stage[(j / kDirectVPT) * kDirectPitch + (j % kDirectVPT)];
-        V += kDirectThreads;
-        if (v + 1 == kDirectVPT || V >= total) break;
-        i3 += di;
-        r += dr;
-        if (i3 >= c2) { i3 -= c2; ++r; }
+            for (int r = 0; r < kDirectGroup; ++r) {
+                const uint32_t colp = (uint32_t)((k1 * n2 + k2) * SFnh);
+                const uint32_t colm = (uint32_t)(((k1 ? n1 - k1 : 0) * n2 + (k2 ? n2 - k2 : 0)) * SFnh);
+                colr[r] = (half ? colm : colp) + (uint32_t)koff;
+                if (++i2 == (int)c1) {
+                    i2 = 0;
+                    k2 = k20;
+                    k1 = (k1 + 1 == n1) ? 0 : k1 + 1;
+                } else {
+                    k2 = (k2 + 1 == n2) ? 0 : k2 + 1;
+                }
+            }
+            const int ng = min(kDirectGroup, nr - g);
+            float I[kDirectGroup];
+#pragma unroll
+            for (int r = 0; r < kDirectGroup; ++r) I[r] = 0.f;
+            for (int m = 0; m < P.M; ++m) {
+                const float2* __restrict__ Xm = X0 + (size_t)m * cstride;
+                float2 xv[kDirectGroup];
+#pragma unroll
+                for (int r = 0; r < kDirectGroup; ++r) xv[r] = r < ng ? ldg2(Xm, colr[r]) : make_float2(0.f, 0.f);
+#pragma unroll
+                for (int r = 0; r < kDirectGroup; ++r) I[r] += xv[r].x * xv[r].x + xv[r].y * xv[r].y;
+            }
+#pragma unroll
+            for (int r = 0; r < kDirectGroup; ++r)
+                if (r < ng) op[(size_t)r * P.opitch] = I[r] * b2s;
+            op += (size_t)kDirectGroup * P.opitch;
+        }
+        return;
+    }
+    for (int r = 0; r < nr; ++r) {
+        const size_t colp = ((size_t)k1 * n2 + k2) * SFnh;                                   // X(k)
+        const size_t colm = ((size_t)(k1 ? n1 - k1 : 0) * n2 + (k2 ? n2 - k2 : 0)) * SFnh;   // X(-k), conjugated
+        const size_t col = (half ? colm : colp) + (size_t)koff;
+        float I = 0.f;
+        for (int m = 0; m < P.M; ++m) {
+            const float2* Xm = P.X + (size_t)m * cstride + col;
+            float2 F = make_float2(0.f, 0.f);
+            for (int s = 0; s < P.S; ++s) {
+                const int mu = P.site_of[s];
+                const float2 ph = cmulf(cmulf(ldg2(P.tab1, (size_t)mu * P.cnt[0] + i1), ldg2(P.tab2, (size_t)mu * c1 + i2)),
+                                        cmulf(ldg2(P.tabK3, (size_t)mu * n3 + k3),
+                                              ldg2(P.tabH3, (size_t)P.class_of[s] * P.nH3span + h)));
+                float2 x = ldg2(Xm, (size_t)mu * fstride);
+                x.y *= cj;
+                F.x += ph.x * x.x - ph.y * x.y;
+                F.y += ph.x * x.y + ph.y * x.x;
+            }
+            I += F.x * F.x + F.y * F.y;
+        }
+        I *= P.scale;
+        *op = I;
+        op += P.opitch;
+        // next row: i2 (and k2) step by one, wrapping into the next plane
+        if (++i2 == (int)c1) {
+            i2 = 0;
+            ++i1;
+            k2 = k20;
+            k1 = (k1 + 1 == n1) ? 0 : k1 + 1;
+        } else {
+            k2 = (k2 + 1 == n2) ? 0 : k2 + 1;
+        }
     }
 }
 
@@ -1597,12 +1642,12 @@ __global__ __launch_bounds__(kDirectThreads) void k_recombine_direct_merged(cons
 
 hipError_t launch_recombine_direct(const RecombParams& p, hipStream_t st)
 {
-    const unsigned long long vox = (unsigned long long)p.planes * p.cnt[1] * p.cnt[2];
-    if (vox == 0) return hipSuccess;
     if (p.planes < 0 || p.planes > p.cnt[0]) return hipErrorInvalidValue;
-    constexpr unsigned long long per = (unsigned long long)kDirectThreads * kDirectVPT;
-    if (vox >= (1ULL << 32) - per) return hipErrorInvalidValue;
-    return dispatch(k_recombine_direct, k_recombine_direct_merged, (unsigned)((vox + per - 1) / per),
+    const unsigned long long rows = (unsigned long long)p.planes * p.cnt[1];
+    if (rows == 0 || p.cnt[2] == 0) return hipSuccess;
+    if (rows * (unsigned long long)p.cnt[2] >= (1ULL << 32)) return hipErrorInvalidValue;
+    const unsigned long long waves = (rows + kDirectRows - 1) / kDirectRows * ((p.cnt[2] + 63) / 64);
+    return dispatch(k_recombine_direct, k_recombine_direct_merged, (unsigned)((waves + kDirectWaves - 1) / kDirectWaves),
                     kDirectThreads, 0, st, p);
 }
 
