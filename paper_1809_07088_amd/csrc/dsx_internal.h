@@ -240,6 +240,12 @@ __device__ __forceinline__ float2 ldg2(const float2* p, size_t i)
     return __builtin_bit_cast(float2, ((const __attribute__((address_space(1))) unsigned long long*)p)[i]);
 }
 
+// p[i] = v for a complex array through the global view (one 8-byte store)
+__device__ __forceinline__ void stg2(float2* p, size_t i, float2 v)
+{
+    ((__attribute__((address_space(1))) unsigned long long*)p)[i] = __builtin_bit_cast(unsigned long long, v);
+}
+
 __device__ __forceinline__ bool slot_of(const Slot* __restrict__ slots, int& d, int& bx)
 {
     const Slot s = slots[blockIdx.x >> 3];

@@ -233,9 +233,9 @@ __device__ __forceinline__ void sums_nuclear_body(PT P, const int bx)
         const int c = c0 + 256 * i;
         const bool in = i < ncl && c < c1;
         const size_t at = (size_t)ms * P.ncell + (in ? c : 0);
-        dv[i] = in ? (P.occ ? P.occ[at] : 1.f) : 0.f;
+        dv[i] = in ? (P.occ ? gptr(P.occ)[at] : 1.f) : 0.f;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) uv[i][a] = (in && N > 0 && P.vec) ? P.vec[3 * at + a] : 0.f;
+        for (int a = 0; a < 3; ++a) uv[i][a] = (in && N > 0 && P.vec) ? gptr(P.vec)[3 * at + a] : 0.f;
     }
     // orders above kMaxOrderFast keep the group loop rolled (up to 31 groups of 32)
     constexpr int kGroupUnroll = N <= kMaxOrderFast ? 8 : 1;
@@ -294,9 +294,9 @@ __device__ __forceinline__ void sums_magnetic_body(PT P, const int bx)
     const int c1 = min(P.ncell, c0 + P.chunk);
     for (int c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
         const size_t at = (size_t)ms * P.ncell + c;
-        const double d = P.occ ? (double)P.occ[at] : 1.0;
+        const double d = P.occ ? (double)gptr(P.occ)[at] : 1.0;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) acc[a] += d * (double)P.vec[3 * at + a];
+        for (int a = 0; a < 3; ++a) acc[a] += d * (double)gptr(P.vec)[3 * at + a];
     }
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
@@ -331,7 +331,7 @@ __device__ __forceinline__ void sums_reduce_body(PT P, const int bx)
     double v = 0.0;
     for (int c = lane; c < P.nchunk; c += 64) v += P.partial[((size_t)ms * P.nchunk + c) * P.T + t];
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    if (lane == 0) P.sums[idx] = v;
+    if (lane == 0) gptr(P.sums)[idx] = v;
 }
 
 __global__ __launch_bounds__(256) void k_sums_reduce(SumsParams P) { sums_reduce_body<SumsParams>(P, blockIdx.x); }
@@ -392,8 +392,8 @@ __device__ __forceinline__ float2* planes_rows(const PlaneParams& P, float2* A, 
     const int n2 = P.n2, n3 = P.n3, nh = P.nh;
     const int ncell = P.n1 * n2 * n3;
     const size_t plane0 = ((size_t)(m * P.S + mu)) * ncell + (size_t)R1 * n2 * n3;
-    const float* occ0 = P.occ ? P.occ + plane0 : nullptr;
-    const float* vec0 = P.vec ? P.vec + 3 * plane0 : nullptr;
+    const auto* occ0 = P.occ ? gptr(P.occ) + plane0 : nullptr;
+    const auto* vec0 = P.vec ? gptr(P.vec) + 3 * plane0 : nullptr;
     const float rpn3 = 1.f / (float)(nj * n3), rn3 = 1.f / (float)n3, rnh = 1.f / (float)nh;
     const float rpnh = 1.f / (float)(nj * nh), rnfb = 1.f / (float)nfb;
     const int nb = npl * nfb;
@@ -402,12 +402,12 @@ __device__ __forceinline__ float2* planes_rows(const PlaneParams& P, float2* A, 
         const int rem = idx - b * nj * n3;
         const int jj = qdiv(rem, n3, rn3), R3 = rem - jj * n3;
         const int pl = qdiv(b, nfb, rnfb), fb = b - pl * nfb;
-        const float* occ = occ0 ? occ0 + (size_t)pl * n2 * n3 : nullptr;
-        const float* vec = vec0 ? vec0 + (size_t)3 * pl * n2 * n3 : nullptr;
+        const auto* occ = occ0 ? occ0 + (size_t)pl * n2 * n3 : nullptr;
+        const auto* vec = vec0 ? vec0 + (size_t)3 * pl * n2 * n3 : nullptr;
         const int f = fa + fb;
         const int ep = P.mono[3 * f], eq = P.mono[3 * f + 1], er = P.mono[3 * f + 2];
         const int t = P.kind == 1 ? f : mono_index(ep, eq, er);    // index of the field's lattice sum
-        const float mean = (float)(P.sums[(size_t)(m * P.S + mu) * P.T + t] / (double)ncell);
+        const float mean = (float)(gptr(P.sums)[(size_t)(m * P.S + mu) * P.T + t] / (double)ncell);
         float xv[2] = {0.f, 0.f};
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -470,8 +470,8 @@ __device__ __forceinline__ void fft_planes_body(PT P, const int bx)
     const int n2 = P.n2, nh = P.nh;
     const int SF = P.S * P.F;
 
-    for (int i = threadIdx.x; i < n2; i += blockDim.x) tw2[i] = P.tw2[i];
-    for (int i = threadIdx.x; i < P.n3; i += blockDim.x) tw3[i] = P.tw3[i];
+    for (int i = threadIdx.x; i < n2; i += blockDim.x) tw2[i] = ldg2(P.tw2, i);
+    for (int i = threadIdx.x; i < P.n3; i += blockDim.x) tw3[i] = ldg2(P.tw3, i);
     const int fa = fc * P.fchunk;
     const int nfb = min(P.F, fa + P.fchunk) - fa;     // fields of this block, batched
     const int npl = min(P.npl, P.n1 - R1);            // and planes
@@ -489,7 +489,7 @@ __device__ __forceinline__ void fft_planes_body(PT P, const int bx)
         const int k2 = qdiv(r2, nfb * nh, rfnh);
         const int rem = r2 - k2 * nfb * nh;
         const int fb = qdiv(rem, nh, rnh), k3 = rem - fb * nh;
-        out[((size_t)pl * n2 + k2) * SF * nh + rem] = Y[(pl * nfb + fb) * BE + k2 * nh + k3];
+        stg2(out, ((size_t)pl * n2 + k2) * SF * nh + rem, Y[(pl * nfb + fb) * BE + k2 * nh + k3]);
     }
 }
 
@@ -518,7 +518,7 @@ __device__ __forceinline__ void fft_rows_body(PT P, const int bx)
     const int m = b / P.S;
     const int n2 = P.n2, nh = P.nh;
     const int SF = P.S * P.F;
-    for (int i = threadIdx.x; i < P.n3; i += blockDim.x) tw3[i] = P.tw3[i];
+    for (int i = threadIdx.x; i < P.n3; i += blockDim.x) tw3[i] = ldg2(P.tw3, i);
     const int fa = fc * P.fchunk;
     const int nfb = min(P.F, fa + P.fchunk) - fa;
     const int j0 = rc * P.row_pairs;
@@ -533,7 +533,7 @@ __device__ __forceinline__ void fft_rows_body(PT P, const int bx)
         const int r = qdiv(idx, nfb * nh, rfnh);
         const int rem = idx - r * nfb * nh;
         const int fb = qdiv(rem, nh, rnh), k3 = rem - fb * nh;
-        out[(size_t)r * SF * nh + rem] = C[fb * BE + r * nh + k3];
+        stg2(out, (size_t)r * SF * nh + rem, C[fb * BE + r * nh + k3]);
     }
 }
 
@@ -584,7 +584,7 @@ template <int L1, class PT>
 __device__ __forceinline__ void fft_axis1_reg_body(PT P, const int bx)
 {
     __shared__ float2 tw[L1];
-    for (int i = threadIdx.x; i < L1; i += blockDim.x) tw[i] = P.tw1[i];
+    for (int i = threadIdx.x; i < L1; i += blockDim.x) tw[i] = ldg2(P.tw1, i);
     __syncthreads();
     const unsigned per_m = (unsigned)P.n2 * (unsigned)P.cols;
     const unsigned g = bx * blockDim.x + threadIdx.x;
@@ -593,10 +593,10 @@ __device__ __forceinline__ void fft_axis1_reg_body(PT P, const int bx)
     float2* base = P.X + (size_t)m * L1 * per_m + rem;
     float2 z[L1];
 #pragma unroll
-    for (int i = 0; i < L1; ++i) z[i] = base[(size_t)bit_reverse(i, L1) * per_m];
+    for (int i = 0; i < L1; ++i) z[i] = ldg2(base, (size_t)bit_reverse(i, L1) * per_m);
     fft_reg<L1>(z, tw);
 #pragma unroll
-    for (int k = 0; k < L1; ++k) base[(size_t)k * per_m] = z[k];
+    for (int k = 0; k < L1; ++k) stg2(base, (size_t)k * per_m, z[k]);
 }
 
 template <int L1>
@@ -639,13 +639,13 @@ __device__ __forceinline__ void fft_planes_reg_body(PT P, const int bx)
     const int ncell = P.n1 * L2 * L3;
     const int fa = fc * kRegFC;
     const int nfb = min(P.F, fa + kRegFC) - fa;
-    for (int i = threadIdx.x; i < L2; i += blockDim.x) tw2[i] = P.tw2[i];
-    for (int i = threadIdx.x; i < L3; i += blockDim.x) tw3[i] = P.tw3[i];
+    for (int i = threadIdx.x; i < L2; i += blockDim.x) tw2[i] = ldg2(P.tw2, i);
+    for (int i = threadIdx.x; i < L3; i += blockDim.x) tw3[i] = ldg2(P.tw3, i);
     if (threadIdx.x < nfb) {
         const int f = fa + threadIdx.x;
         const int ep = P.mono[3 * f], eq = P.mono[3 * f + 1], er = P.mono[3 * f + 2];
         const int t = P.kind == 1 ? f : mono_index(ep, eq, er);
-        meanf[threadIdx.x] = (float)(P.sums[(size_t)(m * P.S + mu) * P.T + t] / (double)ncell);
+        meanf[threadIdx.x] = (float)(gptr(P.sums)[(size_t)(m * P.S + mu) * P.T + t] / (double)ncell);
     }
     __syncthreads();
 
@@ -661,10 +661,10 @@ __device__ __forceinline__ void fft_planes_reg_body(PT P, const int bx)
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
         const size_t c = plane0 + threadIdx.x + k * kRegThreads;
-        cd[k] = (gen && P.occ) ? P.occ[c] : 1.f;
+        cd[k] = (gen && P.occ) ? gptr(P.occ)[c] : 1.f;
         cu0[k] = cu1[k] = cu2[k] = 0.f;
         if (gen && P.vec) {
-            const float* u = P.vec + 3 * c;
+            const auto* u = gptr(P.vec) + 3 * c;
             cu0[k] = u[0]; cu1[k] = u[1]; cu2[k] = u[2];
         }
         v[k] = 1.f;
@@ -740,7 +740,7 @@ __device__ __forceinline__ void fft_planes_reg_body(PT P, const int bx)
         for (int i = 0; i < L2; ++i) y[i] = col[bit_reverse(i, L2)];
         fft_reg<L2>(y, tw2);
 #pragma unroll
-        for (int k2 = 0; k2 < L2; ++k2) out[(size_t)k2 * SF * NH + it] = y[k2];
+        for (int k2 = 0; k2 < L2; ++k2) stg2(out, (size_t)k2 * SF * NH + it, y[k2]);
     }
 }
 
@@ -825,14 +825,14 @@ __device__ __forceinline__ void fft_axis1_body(PT P, const int bx)
     const int c0 = cb * tc;
     const size_t rowstride = (size_t)P.n2 * P.cols;
     float2* base = P.X + ((size_t)m * n1 * P.n2 + k2) * P.cols + c0;
-    for (int i = threadIdx.x; i < n1; i += blockDim.x) tw[i] = P.tw1[i];
+    for (int i = threadIdx.x; i < n1; i += blockDim.x) tw[i] = ldg2(P.tw1, i);
     for (int b0 = threadIdx.x; b0 < n1 * tc; b0 += 8 * blockDim.x) {
         float2 v[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int idx = b0 + u * blockDim.x;
             const int R1 = idx / tc, c = idx - R1 * tc;
-            v[u] = (idx < n1 * tc && c0 + c < P.cols) ? base[R1 * rowstride + c] : make_float2(0.f, 0.f);
+            v[u] = (idx < n1 * tc && c0 + c < P.cols) ? ldg2(base, R1 * rowstride + c) : make_float2(0.f, 0.f);
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -844,7 +844,7 @@ __device__ __forceinline__ void fft_axis1_body(PT P, const int bx)
     float2* Y = lds_fft(A, B, tc, 1, tc, P.p1, tw);
     for (int idx = threadIdx.x; idx < n1 * tc; idx += blockDim.x) {
         const int k1 = idx / tc, c = idx - k1 * tc;
-        if (c0 + c < P.cols) base[k1 * rowstride + c] = Y[idx];
+        if (c0 + c < P.cols) stg2(base, k1 * rowstride + c, Y[idx]);
     }
 }
 

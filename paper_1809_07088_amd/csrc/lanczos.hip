@@ -143,7 +143,7 @@ __device__ __forceinline__ void lanczos_ring_body(PT P, const int bx)
     const int T3 = min((b3 + 1) * kRT3 - eo, P.o[2]) - o3;
     const int E2lo = o2 + eo, E2n = T2 + M2 - 1;
     const int E3lo = o3 + eo, E3n = T3 + M2 - 1;
-    for (int i = threadIdx.x; i < M2; i += blockDim.x) wn_s[i] = P.wn[i];
+    for (int i = threadIdx.x; i < M2; i += blockDim.x) wn_s[i] = gptr(P.wn)[i];
 
     // this thread's staging elements (row-major, pitch L3), as offsets within a stored
     // plane and within the mirrored plane (rows and columns reversed)
@@ -160,7 +160,7 @@ __device__ __forceinline__ void lanczos_ring_body(PT P, const int bx)
     const int e1a = o1 + eo, e1b = o1 + T1 - 1 + eo + M2 - 1;
     auto fetch = [&](int e1, float (&buf)[NSTG]) {
         const bool mir = e1 >= P.ihalf;
-        const float* src = P.in + (size_t)(mir ? P.e[0] - 1 - e1 : e1) * plane;
+        const auto* src = gptr(P.in) + (size_t)(mir ? P.e[0] - 1 - e1 : e1) * plane;
 #pragma unroll
         for (int k = 0; k < NSTG; ++k)
             if (soff[k] >= 0) buf[k] = src[mir ? moff[k] : soff[k]];
@@ -229,10 +229,10 @@ __device__ __forceinline__ void lanczos_ring_body(PT P, const int bx)
         // axis 1: the output plane whose window ends at input plane e1
         const int i1 = e1 - M2 + 1 - eo;
         if (i1 >= o1 && j3 < T3) {
-            float* orow = P.out + ((size_t)i1 * P.o[1] + o2) * P.o[2] + o3 + j3;
+            auto* orow = gptr(P.out) + ((size_t)i1 * P.o[1] + o2) * P.o[2] + o3 + j3;
             // the mirrored output (-G): plane o0 - 1 - i1, rows and columns reversed
             const bool mirror = P.ohalf && i1 != P.o[0] - 1 - i1;
-            float* mrow = P.out + ((size_t)(P.o[0] - 1 - i1) * P.o[1] + (P.o[1] - 1 - o2)) * P.o[2]
+            auto* mrow = gptr(P.out) + ((size_t)(P.o[0] - 1 - i1) * P.o[1] + (P.o[1] - 1 - o2)) * P.o[2]
                         + (P.o[2] - 1 - o3 - j3);
 #pragma unroll
             for (int q = 0; q < kRRun; ++q) {

@@ -163,20 +163,20 @@ __device__ __forceinline__ int wave_min_uniform(int v)
 // boxes, their mirrors -G: byte offsets from block-uniform plane bases (a plane of
 // the box is below 4 GiB), so each store is one 32-bit add and a global store.
 struct RowOut {
-    char* oplane;
-    char* mplane;
+    __attribute__((address_space(1))) char* oplane;
+    __attribute__((address_space(1))) char* mplane;
     uint32_t o0, m0, step;
     bool nt;
     // On line-aligned rows every H3 step of a row is whole lines: streaming stores
     // keep the output (not read again here) out of L2, where the spectra columns stay.
     // Unaligned rows go through L2, which merges the partial lines.
     __device__ __forceinline__ void put(int h, float v) const {
-        float* a = reinterpret_cast<float*>(oplane + (o0 + step * (uint32_t)h));
+        auto* a = reinterpret_cast<__attribute__((address_space(1))) float*>(oplane + (o0 + step * (uint32_t)h));
         if (nt) __builtin_nontemporal_store(v, a);
         else *a = v;
     }
     __device__ __forceinline__ void put_mirror(int h, float v) const {
-        float* a = reinterpret_cast<float*>(mplane + (m0 - step * (uint32_t)h));
+        auto* a = reinterpret_cast<__attribute__((address_space(1))) float*>(mplane + (m0 - step * (uint32_t)h));
         if (nt) __builtin_nontemporal_store(v, a);
         else *a = v;
     }
@@ -186,8 +186,8 @@ __device__ __forceinline__ RowOut row_out(const RecombParams& P, const BlockWork
 {
     RowOut r;
     const size_t plane = (size_t)P.cnt[1] * P.opitch;
-    r.oplane = reinterpret_cast<char*>(P.out + P.ooff + (size_t)w.i1 * plane);
-    r.mplane = reinterpret_cast<char*>(P.out + P.ooff + (size_t)(P.cnt[0] - 1 - w.i1) * plane);
+    r.oplane = reinterpret_cast<__attribute__((address_space(1))) char*>(gptr(P.out) + P.ooff + (size_t)w.i1 * plane);
+    r.mplane = reinterpret_cast<__attribute__((address_space(1))) char*>(gptr(P.out) + P.ooff + (size_t)(P.cnt[0] - 1 - w.i1) * plane);
     r.o0 = 4u * (uint32_t)(i2 * P.opitch + i3b);
     r.m0 = 4u * (uint32_t)((P.cnt[1] - 1 - i2) * P.opitch + (P.cnt[2] - 1 - i3b));
     r.step = 4u * (uint32_t)P.n3;
@@ -1768,14 +1768,14 @@ __device__ __forceinline__ void bragg_nuclear_body(PT P, const int bx)
         s2 = (q[0] * q[0] + q[1] * q[1] + q[2] * q[2]) / (16.0 * M_PI * M_PI);
     }
     for (int mu = lane; mu < P.S; mu += 64) {
-        const double* sd = P.site + 12 * mu;
+        const auto* sd = gptr(P.site) + 12 * mu;
         double x = H[0] * sd[0] + H[1] * sd[1] + H[2] * sd[2];
         x -= floor(x);
         double sn, cs;
         sincos(6.283185307179586476925 * x, &sn, &cs);
         double wgt = sd[3];
         if (P.has_ff) {
-            const double* f = sd + 4;
+            const auto* f = sd + 4;
             wgt *= f[0] * exp(-f[1] * s2) + f[2] * exp(-f[3] * s2) + f[4] * exp(-f[5] * s2) + f[6];
         }
         Wr[mu] = wgt * cs;
@@ -1785,7 +1785,7 @@ __device__ __forceinline__ void bragg_nuclear_body(PT P, const int bx)
     const int items = P.S * T;
     double sq = 0.0, mre = 0.0, mim = 0.0;
     for (int m = 0; m < P.M; ++m) {
-        const double* Sm = P.sums + (size_t)m * items;    // [site][monomial] of configuration m
+        const auto* Sm = gptr(P.sums) + (size_t)m * items;    // [site][monomial] of configuration m
         double fr = 0.0, fi = 0.0;
 #pragma unroll 4
         for (int it = lane; it < items; it += 64) {
@@ -1811,7 +1811,7 @@ __device__ __forceinline__ void bragg_nuclear_body(PT P, const int bx)
         mre /= P.M; mim /= P.M;
         const double I = (sq / P.M - (mre * mre + mim * mim)) * P.scale;
         const int G[3] = {P.n[0] * H[0], P.n[1] * H[1], P.n[2] * H[2]};
-        P.out[((size_t)(G[0] - P.g0[0]) * P.cnt[1] + (G[1] - P.g0[1])) * P.opitch + (G[2] - P.g0[2]) + P.ooff] = (float)I;
+        gptr(P.out)[((size_t)(G[0] - P.g0[0]) * P.cnt[1] + (G[1] - P.g0[1])) * P.opitch + (G[2] - P.g0[2]) + P.ooff] = (float)I;
     }
 }
 
@@ -1849,14 +1849,14 @@ __device__ __forceinline__ void bragg_lanes_body(PT P, const int bx)
         s2 = (q[0] * q[0] + q[1] * q[1] + q[2] * q[2]) / (16.0 * M_PI * M_PI);
     }
     for (int mu = 0; mu < P.S; ++mu) {
-        const double* sd = P.site + 12 * mu;
+        const auto* sd = gptr(P.site) + 12 * mu;
         double x = H[0] * sd[0] + H[1] * sd[1] + H[2] * sd[2];
         x -= floor(x);
         double sn, cs;
         sincos(6.283185307179586476925 * x, &sn, &cs);
         double wgt = sd[3];
         if (P.has_ff) {
-            const double* f = sd + 4;
+            const auto* f = sd + 4;
             wgt *= f[0] * exp(-f[1] * s2) + f[2] * exp(-f[3] * s2) + f[4] * exp(-f[5] * s2) + f[6];
         }
         Wr[mu][lane] = wgt * cs;
@@ -1864,7 +1864,7 @@ __device__ __forceinline__ void bragg_lanes_body(PT P, const int bx)
     }
     double sq = 0.0, mre = 0.0, mim = 0.0;
     for (int m = 0; m < P.M; ++m) {
-        const double* Sm = P.sums + (size_t)m * P.S * P.T;   // [site][monomial]; monomial 0: occupancy
+        const auto* Sm = gptr(P.sums) + (size_t)m * P.S * P.T;   // [site][monomial]; monomial 0: occupancy
         double fr = 0.0, fi = 0.0;
         for (int mu = 0; mu < P.S; ++mu) {
             const double sv = Sm[(size_t)mu * P.T];
@@ -1877,7 +1877,7 @@ __device__ __forceinline__ void bragg_lanes_body(PT P, const int bx)
     mre /= P.M; mim /= P.M;
     const double I = (sq / P.M - (mre * mre + mim * mim)) * P.scale;
     const int G[3] = {P.n[0] * H[0], P.n[1] * H[1], P.n[2] * H[2]};
-    P.out[((size_t)(G[0] - P.g0[0]) * P.cnt[1] + (G[1] - P.g0[1])) * P.opitch + (G[2] - P.g0[2]) + P.ooff] = (float)I;
+    gptr(P.out)[((size_t)(G[0] - P.g0[0]) * P.cnt[1] + (G[1] - P.g0[1])) * P.opitch + (G[2] - P.g0[2]) + P.ooff] = (float)I;
 }
 
 __global__ __launch_bounds__(64) void k_bragg_lanes(BraggParams P) { bragg_lanes_body<BraggParams>(P, blockIdx.x); }
@@ -1887,7 +1887,8 @@ __global__ __launch_bounds__(64) void k_bragg_lanes_merged(const BraggParams* __
     if (slot_of(slots, d, bx)) bragg_lanes_body<const BraggParams&>(tab[d], bx);
 }
 
-__device__ double mag_ff_d(const double* f, double s2) {
+template <class FP>
+__device__ double mag_ff_d(FP f, double s2) {
     return f[0] * exp(-f[1] * s2) + f[2] * exp(-f[3] * s2) + f[4] * exp(-f[5] * s2) + f[6];
 }
 
@@ -1940,7 +1941,7 @@ __device__ __forceinline__ void bragg_magnetic_body(PT P, const int bx)
     }
     const double s2 = q2 / (16.0 * 9.869604401089358618834);
     for (int mu = lane; mu < P.S; mu += 64) {
-        const double* sd = P.site + 12 * mu;
+        const auto* sd = gptr(P.site) + 12 * mu;
         double x = H[0] * sd[0] + H[1] * sd[1] + H[2] * sd[2];
         x -= floor(x);
         double sn, cs;
@@ -1965,7 +1966,7 @@ __device__ __forceinline__ void bragg_magnetic_body(PT P, const int bx)
     for (int m = 0; m < P.M; ++m) {
         double fr[3] = {0, 0, 0}, fi[3] = {0, 0, 0};
         for (int mu = lane; mu < P.S; mu += 64) {
-            const double* Sm = P.sums + ((size_t)m * P.S + mu) * 3;
+            const auto* Sm = gptr(P.sums) + ((size_t)m * P.S + mu) * 3;
             for (int c = 0; c < 3; ++c) {
                 fr[c] += Sm[c] * Wr[wave][mu];
                 fi[c] += Sm[c] * Wi[wave][mu];
