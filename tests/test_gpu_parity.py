@@ -353,7 +353,9 @@ def test_folded_k3_slices_symmetric_box(lm):
 
 
 @pytest.mark.parametrize("n,kind,order", [((16, 8, 32), synth.NUCLEAR, 3), ((8, 32, 16), synth.NUCLEAR, 0),
-                                          ((8, 16, 8), synth.MAGNETIC, 0), ((32, 32, 8), synth.NUCLEAR, 5)])
+                                          ((8, 16, 8), synth.MAGNETIC, 0), ((32, 32, 8), synth.NUCLEAR, 5),
+                                          ((32, 16, 32), synth.NUCLEAR, 1), ((16, 32, 16), synth.MAGNETIC, 0),
+                                          ((8, 32, 32), synth.NUCLEAR, 0)])
 def test_power_of_two_edges_register_transforms(n, kind, order):
     """Edges 8, 16, 32 take the register-resident transforms (occupancy, Taylor
     p-runs and spin components all pass through them)."""
