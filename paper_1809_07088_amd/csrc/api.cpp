@@ -602,9 +602,12 @@ dsx_status tables_for(dsx_model m, const Box& bx, DeviceTables** out)
         const size_t budget = 48 * 1024 / sizeof(float2);
         const size_t fixed = magnetic_rows_lds_elems(0, cs, S, NC, n3, t.nH3span);
         const size_t per_row = magnetic_rows_lds_elems(1, 0, S, NC, n3, 0) - (size_t)S * n3;
+        // residue rows: every row of a column in one block when q2 staged rows fit; else the
+        // rows are staged one by one, as many as fit
+        if (q2 > 0 && fixed + std::min(q2, kMagRowsMaxRows) * per_row > budget) t.qmod2_mr = 0;
         int rows;
-        if (q2 > 0)
-            rows = fixed + std::min(q2, kMagRowsMaxRows) * per_row <= budget ? kMagRowsMaxRows : 0;
+        if (t.qmod2_mr > 0)
+            rows = kMagRowsMaxRows;
         else
             rows = fixed < budget ? (int)((budget - fixed) / per_row) : 0;
         rows = std::min(std::min(rows, kMagRowsMaxRows), maxH2);
