@@ -535,7 +535,6 @@ __device__ __forceinline__ void recombine_folded_body(PT P, const int bx)
     // per plane and site: b e^{2 pi i (g1 r1 + k2 r2 / n2)} (i tau1)^p / p!, and its
     // conjugate for the mirrored half (sum w conj(x) = conj(sum conj(w) x))
     float2* wt = smem + 2 * (size_t)P.bs_elems;
-    auto wtab = [&](int hw, int pl, int sl) { return wt + ((hw * 2 + pl) * P.S + sl) * (N + 1); };
     float2* tHs = wt + 4 * P.S * (N + 1);
     __shared__ int jtab[2][QR];              // terms N - e + 1, field of p = 0 of pair j
     __shared__ float jfr[QR];                // 1/r! of pair j
@@ -552,23 +551,26 @@ __device__ __forceinline__ void recombine_folded_body(PT P, const int bx)
         jtab[1][j] = cum - P.first_mono;
         jfr[j] = inv_factorial_rt(r);
     }
-    for (int t = threadIdx.x; t < 2 * P.S * (N + 1); t += blockDim.x) {
-        const int pl = t / (P.S * (N + 1));
-        const int u = t - pl * P.S * (N + 1);
-        const int sl = u / (N + 1), p = u - sl * (N + 1);
-        const int mu = P.site_of[sl];
+    // level-A weights w_p = b e^{2 pi i (g1 r1 + k2 r2 / n2)} (i tau1)^p / p!: per plane the real
+    // c_p = sqrt(scale) tau1^p / p! with the sign of i^p's nonzero part (+ for p mod 4 in {0, 1},
+    // - for {2, 3}), and per (plane, site) the phase wb, so that sum_p w_p x_p = wb (E + i O)
+    // with E, O the sums of c_p x_p over even and odd p
+    float* cm = reinterpret_cast<float*>(wt);                  // [2][N + 1]
+    float2* wbt = wt + (N + 1);                                 // [2][S]
+    for (int t = threadIdx.x; t < 2 * (N + 1); t += blockDim.x) {
+        const int pl = t / (N + 1), p = t - pl * (N + 1);
         const int G1 = wi.z + (pl && hasb ? n1 : 0);      // (an absent plane repeats the first)
         const float tau1 = (float)((double)G1 * P.tw[0]);
-        const float2 wb = cmulf(P.tab1[(size_t)mu * P.cnt[0] + (G1 - P.g0[0])], P.tabK2[(size_t)mu * n2 + w.k2]);
         // sqrt(scale) here scales every |F|^2 by the output scale at no cost per voxel
         float mag = inv_factorial_rt(p) * sqrtf(P.scale);
         for (int v = 1; v <= p; ++v) mag *= tau1;
-        const int p4 = p & 3;
-        const float2 ip = p4 == 0 ? make_float2(mag, 0.f) : p4 == 1 ? make_float2(0.f, mag)
-                        : p4 == 2 ? make_float2(-mag, 0.f) : make_float2(0.f, -mag);
-        const float2 wv = cmulf(wb, ip);
-        wtab(0, pl, sl)[p] = wv;
-        wtab(1, pl, sl)[p] = make_float2(wv.x, -wv.y);
+        cm[t] = ((p & 3) < 2) ? mag : -mag;
+    }
+    for (int t = threadIdx.x; t < 2 * P.S; t += blockDim.x) {
+        const int pl = t / P.S, sl = t - pl * P.S;
+        const int mu = P.site_of[sl];
+        const int G1 = wi.z + (pl && hasb ? n1 : 0);
+        wbt[t] = cmulf(P.tab1[(size_t)mu * P.cnt[0] + (G1 - P.g0[0])], P.tabK2[(size_t)mu * n2 + w.k2]);
     }
     const float2* tH0 = PAR ? nullptr : stage_class_phases(P, tHs);
 
@@ -660,25 +662,32 @@ __device__ __forceinline__ void recombine_folded_body(PT P, const int bx)
                 x[N + 1] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rk, ko, mu * (uint32_t)(8 * n3), 0));
             };
             // ... and sum_p w_p X (X = x, or conj x on the mirrored half) for both planes:
-            // the mirrored half forms sum conj(w) x with the conjugated weights and
-            // conjugates the sum
-            const int hw = half ? 1 : 0;
+            // wb (E + i O) from the real p-terms; the mirrored half forms sum conj(w) x =
+            // conj(wb) (E - i O) and conjugates it
+            const float sh = half ? -1.f : 1.f;
             auto contract = [&](int sl, const float2 (&x)[N + 2], float2& acc0, float2& acc1) {
-                const float2* w0 = wtab(hw, 0, sl);
-                const float2* w1 = wtab(hw, 1, sl);
-                acc0 = make_float2(0.f, 0.f);
-                acc1 = make_float2(0.f, 0.f);
+                float2 e0 = make_float2(0.f, 0.f), o0 = e0, e1 = e0, o1 = e0;
 #pragma unroll
                 for (int p = 0; p <= N; ++p) {
                     if (p < pmax) {
                         const float2 v = x[p];
-                        const float2 wp = w0[p], wq = w1[p];
-                        acc0.x = fmaf(wp.x, v.x, acc0.x); acc0.x = fmaf(-wp.y, v.y, acc0.x);
-                        acc0.y = fmaf(wp.x, v.y, acc0.y); acc0.y = fmaf(wp.y, v.x, acc0.y);
-                        acc1.x = fmaf(wq.x, v.x, acc1.x); acc1.x = fmaf(-wq.y, v.y, acc1.x);
-                        acc1.y = fmaf(wq.x, v.y, acc1.y); acc1.y = fmaf(wq.y, v.x, acc1.y);
+                        const float a = cm[p], b = cm[N + 1 + p];
+                        if (p & 1) {
+                            o0.x = fmaf(a, v.x, o0.x); o0.y = fmaf(a, v.y, o0.y);
+                            o1.x = fmaf(b, v.x, o1.x); o1.y = fmaf(b, v.y, o1.y);
+                        } else {
+                            e0.x = fmaf(a, v.x, e0.x); e0.y = fmaf(a, v.y, e0.y);
+                            e1.x = fmaf(b, v.x, e1.x); e1.y = fmaf(b, v.y, e1.y);
+                        }
                     }
                 }
+                const float2 in0 = make_float2(fmaf(-sh, o0.y, e0.x), fmaf(sh, o0.x, e0.y));
+                const float2 in1 = make_float2(fmaf(-sh, o1.y, e1.x), fmaf(sh, o1.x, e1.y));
+                float2 w0 = wbt[sl], w1 = wbt[P.S + sl];
+                w0.y *= sh;
+                w1.y *= sh;
+                acc0 = cmulf(w0, in0);
+                acc1 = cmulf(w1, in1);
                 acc0.y = __uint_as_float(__float_as_uint(acc0.y) ^ cj);
                 acc1.y = __uint_as_float(__float_as_uint(acc1.y) ^ cj);
             };
