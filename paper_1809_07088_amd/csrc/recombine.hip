@@ -363,23 +363,26 @@ __device__ __forceinline__ void recombine_nuclear_body(PT P, const int bx)
                     const int e = jtab[0][j];
                     const int f0 = jtab[1][j];           // field of p = 0 (may be -1)
                     const float2* xs = Xs + f0 * nh + (half ? n3 - kk : kk);
-                    float2 wgt = wbase;
-                    float2 acc = make_float2(0.f, 0.f);
+                    // sum_p wbase (i tau1)^p / p! x_p = wbase (E + i O): E, O sum the even and odd
+                    // p-terms with the real weights tau1^p / p! times the sign of i^p's nonzero
+                    // part; the mirror sign of x's imaginary part is applied to the sums
+                    float2 E = make_float2(0.f, 0.f), O = E;
+                    float mag = 1.f;
 #pragma unroll
                     for (int p = 0; p <= N; ++p) {
                         if (p <= N - e) {
                             if (f0 + p >= 0) {
-                                float2 x = xs[p * nh];
-                                x.y *= sg;
-                                acc.x += wgt.x * x.x - wgt.y * x.y;
-                                acc.y += wgt.x * x.y + wgt.y * x.x;
+                                const float2 x = xs[p * nh];
+                                const float c = ((p & 3) < 2) ? mag : -mag;
+                                if (p & 1) { O.x = fmaf(c, x.x, O.x); O.y = fmaf(c, x.y, O.y); }
+                                else { E.x = fmaf(c, x.x, E.x); E.y = fmaf(c, x.y, E.y); }
                             }
-                            // wgt <- wgt * (i tau1) / (p + 1)
-                            const float sc1 = tau1 * (1.f / (float)(p + 1));
-                            wgt = make_float2(-wgt.y * sc1, wgt.x * sc1);
+                            mag *= tau1 * (1.f / (float)(p + 1));
                         }
                     }
-                    Bs[((size_t)sl * n3 + kk) * QR + j] = acc;
+                    E.y *= sg;
+                    O.y *= sg;
+                    Bs[((size_t)sl * n3 + kk) * QR + j] = cmulf(wbase, make_float2(E.x - O.y, E.y + O.x));
                 }
             }
             __syncthreads();
